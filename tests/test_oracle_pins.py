@@ -1,0 +1,523 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks the oracle against a fact fixed by the paper or by
+mathematics: libm / Python ``math.frexp`` exponents, numpy's direct
+float64 -> float16 cast, exact rational arithmetic (``fractions.Fraction``),
+``math.fsum``, hand-derived worked examples (``tests/golden``), closed
+forms, and the paper's theorems read as inequalities.  No expected value
+here comes from the device library.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from collections import Counter
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
+
+
+def F(expr: str) -> Fraction:
+    """Evaluate an exact expression such as '1 + 2**-6' with Fractions."""
+    return eval(expr.replace("2**", "Fraction(2)**"), {"Fraction": Fraction})
+
+
+def exp_of_fraction(q: Fraction) -> int:
+    """floor(log2 |q|) for a nonzero rational, by integer arithmetic."""
+    q = abs(q)
+    e = q.numerator.bit_length() - q.denominator.bit_length()
+    if Fraction(2) ** e > q:
+        e -= 1
+    assert Fraction(2) ** e <= q < Fraction(2) ** (e + 1)
+    return e
+
+
+def py_split(v: float):
+    """Exponent / significand via Python's frexp (an independent libm path)."""
+    m, e = math.frexp(abs(v))
+    return e - 1, m * 2.0
+
+
+# --------------------------------------------------------------------------
+# Building blocks
+# --------------------------------------------------------------------------
+
+def test_split_every_exponent_code_and_subnormals():
+    vals = []
+    for code in range(1, 2047):
+        for frac in (0, 1, (1 << 51), (1 << 52) - 1, 0x5555555555555):
+            bits = (code << 52) | frac
+            vals.append(np.array([bits], dtype=np.uint64).view(np.float64)[0])
+    for frac in (1, 2, 3, 0x8000000000000, 0xFFFFFFFFFFFFF, 0x123456789):
+        vals.append(np.array([frac], dtype=np.uint64).view(np.float64)[0])
+    for v in vals:
+        for s in (1.0, -1.0):
+            E, m = oracle.split(s * float(v))
+            E2, m2 = py_split(s * float(v))
+            assert (E, m) == (E2, m2), v
+            assert 1.0 <= m < 2.0
+            assert Fraction(abs(s * float(v))) == Fraction(m) * Fraction(2) ** E
+
+
+def test_key_is_exponent_of_product():
+    g = workloads.rng(11)
+    xs = np.concatenate([
+        workloads.log_uniform_pair(3000, 3, -300, 300)[0],
+        np.ldexp(g.uniform(1, 2, 500), g.integers(-1074, -1030, 500)),  # subnormal
+        1.0 + g.integers(0, 1 << 20, 500) * 2.0 ** -52,                  # near 1
+        np.sqrt(2.0) * (1 + g.integers(-64, 64, 500) * 2.0 ** -52),      # m*m ~ 2
+    ])
+    ys = np.concatenate([
+        workloads.log_uniform_pair(3000, 4, -300, 300)[1],
+        np.ldexp(g.uniform(1, 2, 500), g.integers(-20, 20, 500)),
+        2.0 - g.integers(1, 1 << 20, 500) * 2.0 ** -52,
+        np.sqrt(2.0) * (1 + g.integers(-64, 64, 500) * 2.0 ** -52),
+    ])
+    corner = 0
+    for x, y in zip(xs.tolist(), ys.tolist()):
+        k = oracle.key(x, y, 0)
+        ex = exp_of_fraction(Fraction(x) * Fraction(y))
+        # the key is the exponent of the exact product, except where the
+        # significand product rounds up to exactly 2 (the key then follows
+        # the rounded product, one above)
+        if k != ex:
+            corner += 1
+            assert k == ex + 1
+            mx, my = py_split(x)[1], py_split(y)[1]
+            assert Fraction(mx) * Fraction(my) < 2 and mx * my == 2.0
+        # sum key: E(x) + E(y) from Python's frexp
+        assert oracle.key(x, y, 1) == py_split(x)[0] + py_split(y)[0]
+    assert corner < 10
+
+
+def test_key_follows_rounded_product_at_the_carry():
+    # Pairs whose significand product is just below 2 but rounds to 2.0: the
+    # product key is the IEEE exponent of fl64(x*y), one above the exact one.
+    found = 0
+    for i in range(1, 4000):
+        mx = 1.0 + i * 2.0 ** -12
+        my = np.float64(2.0 / mx)
+        while Fraction(mx) * Fraction(float(my)) >= 2:
+            my = np.nextafter(my, 0.0)
+        my = float(my)
+        if mx * my != 2.0:
+            continue
+        found += 1
+        for sx, sy, ex, ey in ((1, 1, 0, 0), (-1, 1, 5, -9), (1, -1, -300, 200)):
+            x, y = sx * math.ldexp(mx, ex), sy * math.ldexp(my, ey)
+            assert oracle.key(x, y, 0) == py_split(x * y)[0] == ex + ey + 1
+            assert exp_of_fraction(Fraction(x) * Fraction(y)) == ex + ey
+    assert found > 10
+    # in general, for normal products the key is the exponent of fl64(x*y)
+    x, y = workloads.log_uniform_pair(5000, 12, -100, 100)
+    for a, b in zip(x.tolist(), y.tolist()):
+        assert oracle.key(a, b, 0) == py_split(a * b)[0]
+
+
+def test_r16_matches_numpy_float16_cast():
+    g = workloads.rng(5)
+    base = np.arange(1 << 10, dtype=np.float64)
+    ms = [1.0 + base * 2.0 ** -10]                          # representable
+    ms.append(1.0 + (base + 0.5) * 2.0 ** -10)              # exact ties
+    ms.append(1.0 + (base + 0.5) * 2.0 ** -10 + 2.0 ** -40)  # tie + sticky
+    ms.append(1.0 + (base + 0.5) * 2.0 ** -10 - 2.0 ** -52)  # just below tie
+    ms.append(1.0 + g.integers(0, 1 << 52, 200000) * 2.0 ** -52)
+    ms.append(np.array([2.0 - 2.0 ** -52, 2.0 - 2.0 ** -12, 2.0 - 2.0 ** -11]))
+    m = np.concatenate(ms)
+    m = m[(m >= 1.0) & (m < 2.0)]
+    want = m.astype(np.float16).astype(np.float64) * 1024.0
+    got = np.array([oracle.r16(v) for v in m.tolist()])
+    np.testing.assert_array_equal(got, want)
+    assert oracle.r16(1.0 + 2.0 ** -11) == 1024.0                  # tie -> even
+    assert oracle.r16(1.0 + 2.0 ** -11 + 2.0 ** -40) == 1025.0     # above tie
+
+
+def test_t_exact_against_fractions():
+    g = workloads.rng(6)
+    cases = [(1, 1e-6), (4, 1e-6), (268, 1e-6), (269, 1e-6), (262, 1e-3),
+             (263, 1e-3), (343, 1e-8), (344, 1e-8), (219, 1e-10), (220, 1e-10),
+             (209, 1e-4), (210, 1e-4), (1, 5e-324), (4196, 5e-324),
+             (3, 2.2250738585072014e-308), (7, 1.7976931348623157e308),
+             (1, 1.0), (2, 1.0), (3, 1e3)]
+    for _ in range(3000):
+        cases.append((int(g.integers(1, 4197)),
+                      float(10.0 ** g.uniform(-320, 308))))
+    for nb, eps in cases:
+        if eps == 0.0:
+            continue
+        t = oracle.t_of(nb, eps)
+        e = Fraction(eps)
+        assert nb * Fraction(2) ** t <= e < nb * Fraction(2) ** (t + 1), (nb, eps)
+
+
+def test_ceil_log2():
+    for m in list(range(1, 5000)) + [2 ** 27, 2 ** 27 + 1, 2 ** 40 - 1]:
+        assert oracle.ceil_log2(m) == (m - 1).bit_length()
+
+
+def _min_precision(sigma: int, spare_bits: int) -> int:
+    """Lowest precision whose per-bin budget holds (proof of Thm 3.5):
+    2^(sigma + t) * eps(pi) <= 2^(t - spare_bits), i.e. sigma + spare <= m_pi,
+    searched over perforate (m = 0), half (10), single (23), double (52)."""
+    for cls, m in ((oracle.PERF, 0), (oracle.HALF, 10), (oracle.SINGLE, 23),
+                   (oracle.DOUBLE, 52)):
+        if sigma + spare_bits <= m:
+            return cls
+    return oracle.DOUBLE  # no precision meets it: stays at input precision
+
+
+def test_precision_is_the_lowest_one_meeting_the_budget():
+    # non-strict reading = lowest precision meeting the budget exactly;
+    # strict (printed half-open intervals) = lowest one with a spare bit
+    for sigma in range(-40, 80):
+        assert oracle.precision(sigma, 1) == _min_precision(sigma, 0), sigma
+        assert oracle.precision(sigma, 0) == _min_precision(sigma, 1), sigma
+
+
+def test_tree64_pairs_adjacent_leaves():
+    v = np.zeros(64, dtype=np.float32)
+    v[0], v[2], v[3] = 1.0, 2.0 ** -24, 2.0 ** -24
+    assert oracle.tree64(v) == 1.0 + 2.0 ** -23      # (1+0) + (2^-24+2^-24)
+    v = np.zeros(64, dtype=np.float32)
+    v[0], v[1], v[3] = 1.0, 2.0 ** -24, 2.0 ** -24
+    assert oracle.tree64(v) == 1.0                   # 1+2^-24 ties to 1, twice
+    v = np.zeros(64, dtype=np.float32)
+    v[0], v[32], v[33] = 1.0, 2.0 ** -24, 2.0 ** -24
+    assert oracle.tree64(v) == 1.0 + 2.0 ** -23      # halves meet at level 6
+    v = np.full(64, 3.0, dtype=np.float32)
+    assert oracle.tree64(v) == 192.0
+
+
+def test_exact_sum_matches_fsum_and_fractions():
+    g = workloads.rng(7)
+    for trial in range(200):
+        n = int(g.integers(1, 60))
+        v = np.ldexp(g.uniform(-1, 1, n), g.integers(-80, 80, n))
+        if trial % 3 == 0:  # heavy cancellation
+            v = np.concatenate([v, -v[: n // 2] * (1 + 2.0 ** -52)])
+        assert oracle.sum_exact(v) == math.fsum(v.tolist())
+        q = sum((Fraction(a) for a in v.tolist()), Fraction(0))
+        assert abs(Fraction(oracle.sum_exact(v)) - q) <= abs(
+            Fraction(math.fsum(v.tolist())) - q)
+    # halfway cases resolved by smaller partials
+    assert oracle.sum_exact([1e16, 1.0, 1e-16]) == 1e16 + 2.0
+    assert oracle.sum_exact([2.0 ** 53, 1.0, -2.0 ** -60]) == 2.0 ** 53
+    assert oracle.sum_exact([]) == 0.0
+
+
+def test_dot_exact_against_fractions():
+    for seed in range(20):
+        x, y = workloads.log_uniform_pair(50, 100 + seed, -30, 30)
+        q = sum((Fraction(a) * Fraction(b) for a, b in zip(x.tolist(), y.tolist())),
+                Fraction(0))
+        d = oracle.dot_exact(x, y)
+        # correctly rounded: no double is closer
+        lo, hi = np.nextafter(d, -np.inf), np.nextafter(d, np.inf)
+        assert abs(Fraction(d) - q) <= abs(Fraction(float(lo)) - q)
+        assert abs(Fraction(d) - q) <= abs(Fraction(float(hi)) - q)
+        qa = sum((abs(Fraction(a) * Fraction(b)) for a, b in zip(x.tolist(), y.tolist())),
+                 Fraction(0))
+        assert oracle.abs_dot(x, y) == float(qa)  # Fraction -> float rounds to nearest
+
+
+# --------------------------------------------------------------------------
+# Hand-derived worked examples
+# --------------------------------------------------------------------------
+
+def _golden_inputs(case):
+    if "x" in case:
+        x = np.array([float.fromhex(s) for s in case["x"]])
+        y = np.array([float.fromhex(s) for s in case["y"]])
+        return x, y, float(case["tol"])
+    if "ones" in case:
+        n = case["ones"]
+        return np.ones(n), np.ones(n), float(case["tol"])
+    n = 4160
+    x = np.zeros(n)
+    y = np.ones(n)
+    x[0] = 1.0
+    x[64:4158] = 2.0 ** -24
+    if case["name"] == "tile_tree_rounds":
+        x[1] = x[3] = 2.0 ** -24
+    else:
+        x[2] = x[3] = 2.0 ** -24
+    return x, y, 2.0 ** -20
+
+
+@pytest.mark.parametrize("name", [c["name"] for c in json.load(open(GOLDEN))["cases"]])
+def test_golden_worked_examples(name):
+    case = next(c for c in json.load(open(GOLDEN))["cases"] if c["name"] == name)
+    x, y, tol = _golden_inputs(case)
+    r = oracle.qdot(x, y, tol, want_classes=True, want_keys=True)
+    ex = case["expect"]
+    assert r["status"] == oracle.OK
+    for k in ("count", "n_bins", "e_max", "e_min", "t", "flags", "n_zero"):
+        if k in ex:
+            assert r[k] == ex[k], k
+    if "keys" in ex:
+        assert r["keys"].tolist() == ex["keys"]
+    if "classes" in ex:
+        assert r["classes"].tolist() == ex["classes"]
+    if "value" in ex:
+        v = ex["value"]
+        want = F(v) if isinstance(v, str) else Fraction(v)
+        assert Fraction(r["value"]) == want
+    if "bound_rel" in ex:
+        assert Fraction(r["bound_rel"]) == F(ex["bound_rel"])
+    if "exact" in ex:
+        assert Fraction(oracle.dot_exact(x, y)) == F(ex["exact"])
+
+
+# --------------------------------------------------------------------------
+# Histogram, partition, invariants
+# --------------------------------------------------------------------------
+
+def test_histogram_matches_counter_of_python_keys():
+    x, y = workloads.log_uniform_pair(20000, 21)
+    x[::97] = 0.0
+    r = oracle.qdot(x, y, 1e-6, want_hist=True, want_keys=True)
+    keys = []
+    for a, b in zip(x.tolist(), y.tolist()):
+        if a == 0.0 or b == 0.0:
+            continue
+        keys.append(exp_of_fraction(Fraction(a) * Fraction(b)))
+    cnt = Counter(keys)
+    h = r["hist"]
+    for k, c in cnt.items():
+        assert h[k - oracle.KMIN] == c
+    assert h.sum() == len(keys)
+    assert r["n_zero"] == len(x) - len(keys)
+    assert r["e_max"] == max(cnt) and r["e_min"] == min(cnt)
+    assert r["n_bins"] == len(cnt)
+    assert sum(r["count"]) == len(x)
+
+
+def _per_bin_budget_ok(r, hist):
+    """Every bin without the unattainable flag spends at most 2^t of the
+    relative budget: M_k 2^(k - e_max + 1) eps(class) <= 2^t (exact)."""
+    eps = {oracle.DOUBLE: Fraction(2) ** -52, oracle.SINGLE: Fraction(2) ** -23,
+           oracle.HALF: Fraction(2) ** -10, oracle.PERF: Fraction(1)}
+    cls_of_key = {}
+    for k, c in zip(r["keys"].tolist(), r["classes"].tolist()):
+        if k != np.iinfo(np.int32).min:
+            cls_of_key.setdefault(k, c)
+            assert cls_of_key[k] == c  # one precision per bin
+    for k, c in cls_of_key.items():
+        M = int(hist[k - oracle.KMIN])
+        spent = M * Fraction(2) ** (k - r["e_max"] + 1) * eps[c]
+        if not (r["flags"] & oracle.F_UNATTAINABLE):
+            assert spent <= Fraction(2) ** r["t"], (k, M, c)
+    return cls_of_key
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-10, 1e-16, 1e2])
+@pytest.mark.parametrize("law", ["c1", "distA", "distB"])
+def test_bounds_and_budget_on_random_data(tol, law):
+    if law == "c1":
+        x, y = workloads.log_uniform_pair(30000, 31)
+    elif law == "distA":
+        x, y = workloads.paper_dist_a(30000, 60, 32)
+    else:
+        x, y = workloads.paper_dist_b(30000, 14, 33)
+    r = oracle.qdot(x, y, tol, want_classes=True, want_keys=True, want_hist=True)
+    _per_bin_budget_ok(r, r["hist"])
+    exact = Fraction(oracle.dot_exact(x, y))  # correctly rounded; the rest is slack
+    err = abs(Fraction(r["value"]) - exact)
+    # rigorous bound: every rounding counted
+    assert err <= Fraction(r["bound_rig"]) + abs(exact) * Fraction(2) ** -52
+    # Thm 3.3 / 3.5 when the hypothesis e_max <= flexp(x.y) holds
+    E = exp_of_fraction(exact)
+    if r["e_max"] <= E and not (r["flags"] & oracle.F_UNATTAINABLE):
+        rel = err / abs(exact)
+        assert rel <= Fraction(r["bound_rel"]) * (1 + Fraction(1, 2 ** 20))
+        assert rel <= Fraction(tol)
+    # Thm 3.4 with the exact E always
+    if r["e_max"] > E:
+        b34 = Fraction(r["bound_rel"]) * Fraction(2) ** (r["e_max"] - E)
+        assert err / abs(exact) <= b34 * (1 + Fraction(1, 2 ** 20))
+
+
+def test_positive_data_satisfies_thm33_hypothesis():
+    # all products positive -> e_max <= flexp(x.y) (noted after Thm 3.3)
+    x, y = workloads.paper_dist_b(20000, 10, 41)
+    r = oracle.qdot(x, y, 1e-8)
+    E = exp_of_fraction(Fraction(oracle.dot_exact(x, y)))
+    assert r["e_max"] <= E
+
+
+def test_thm36_early_termination_means_all_double():
+    for seed in range(6):
+        x, y = workloads.log_uniform_pair(5000, 50 + seed, -1, 1)
+        for tol in (1e-16, 1e-14, 1e-12, 1e-9):
+            r = oracle.qdot(x, y, tol)
+            if r["flags"] & oracle.F_THM_ALL_DOUBLE:
+                assert r["count"][oracle.DOUBLE] == len(x)
+    r = oracle.qdot(*workloads.log_uniform_pair(5000, 57, -1, 1), 1e-16)
+    assert r["flags"] & oracle.F_THM_ALL_DOUBLE
+
+
+def test_invariants_scaling_sign_swap():
+    x, y = workloads.log_uniform_pair(9000, 61)
+    r0 = oracle.qdot(x, y, 1e-6, want_classes=True)
+    r1 = oracle.qdot(x * 2.0 ** 7, y * 2.0 ** -3, 1e-6, want_classes=True)
+    assert np.array_equal(r0["classes"], r1["classes"])
+    assert r1["value"] == r0["value"] * 2.0 ** 4
+    assert r1["e_max"] == r0["e_max"] + 4
+    r2 = oracle.qdot(-x, y, 1e-6, want_classes=True)
+    assert r2["value"] == -r0["value"]
+    r3 = oracle.qdot(y, x, 1e-6, want_classes=True)
+    assert r3["value"] == r0["value"] and np.array_equal(r3["classes"], r0["classes"])
+    # permutation: same bins, same classes per component, value moves only by
+    # FP32 tile rounding
+    p = workloads.rng(3).permutation(len(x))
+    r4 = oracle.qdot(x[p], y[p], 1e-6, want_classes=True)
+    assert r4["count"] == r0["count"]
+    assert np.array_equal(r4["classes"], r0["classes"][p])
+    assert abs(r4["value"] - r0["value"]) <= r0["bound_rig"]
+
+
+def test_raising_tol_never_raises_precision():
+    x, y = workloads.log_uniform_pair(8000, 71)
+    prev = None
+    for tol in [1e-16, 1e-12, 1e-9, 1e-6, 1e-3, 1e-1, 1e1, 1e3]:
+        r = oracle.qdot(x, y, tol, want_classes=True)
+        if prev is not None:
+            assert np.all(r["classes"] >= prev)  # DOUBLE=0 < ... < PERF=3
+        prev = r["classes"]
+
+
+def test_exact_products_all_double_equal_exact_dot():
+    # small-integer significands: every product and partial sum exact
+    g = workloads.rng(81)
+    x = np.ldexp(g.integers(1, 1 << 10, 3000).astype(float), g.integers(-30, 30, 3000))
+    y = np.ldexp(g.integers(1, 1 << 10, 3000).astype(float), g.integers(-30, 30, 3000))
+    r = oracle.qdot(x, y, 1e-300)
+    assert r["count"][oracle.DOUBLE] == 3000
+    assert r["value"] == oracle.dot_exact(x, y)
+
+
+def test_accum_modes_share_classes():
+    x, y = workloads.log_uniform_pair(20000, 91)
+    a = oracle.qdot(x, y, 1e-6, opt=[0, 0, 0, 0], want_classes=True)
+    b = oracle.qdot(x, y, 1e-6, opt=[0, 0, 0, 1], want_classes=True)
+    assert np.array_equal(a["classes"], b["classes"]) and a["count"] == b["count"]
+    assert abs(a["value"] - b["value"]) <= a["bound_rig"]
+
+
+def test_sum_key_and_raw_score_options():
+    x, y = workloads.log_uniform_pair(20000, 92)
+    ks = oracle.qdot(x, y, 1e-6, opt=[1, 0, 0, 0], want_keys=True)
+    for i in range(0, 20000, 37):
+        assert ks["keys"][i] == py_split(x[i])[0] + py_split(y[i])[0]
+    raw = oracle.qdot(x, y, 1e-6, opt=[0, 1, 0, 0])
+    assert raw["t"] == math.floor(math.log2(1e-6))
+    adj = oracle.qdot(x, y, 1e-6)
+    assert adj["t"] < raw["t"]
+    # a larger effective tolerance keeps fewer components at high precision
+    assert raw["count"][oracle.PERF] >= adj["count"][oracle.PERF]
+
+
+# --------------------------------------------------------------------------
+# Edge and error cases
+# --------------------------------------------------------------------------
+
+def test_edge_cases():
+    r = oracle.qdot(np.zeros(0), np.zeros(0), 1e-6)
+    assert r["status"] == oracle.OK and r["value"] == 0.0 and r["flags"] & oracle.F_ALL_PERF
+    r = oracle.qdot(np.zeros(100), np.ones(100), 1e-6)
+    assert r["value"] == 0.0 and r["count"] == [0, 0, 0, 100] and r["n_zero"] == 100
+    x = np.ones(10)
+    x[3] = np.nan
+    assert oracle.qdot(x, np.ones(10), 1e-6)["status"] == oracle.E_NONFINITE
+    x[3] = np.inf
+    assert oracle.qdot(x, np.ones(10), 1e-6)["status"] == oracle.E_NONFINITE
+    for bad in (0.0, -1.0, np.nan, np.inf):
+        assert oracle.qdot(np.ones(4), np.ones(4), bad)["status"] == oracle.E_INVAL
+    assert oracle.qdot(np.ones(4), np.ones(4), 1e-6, opt=[2, 0, 0, 0])["status"] == oracle.E_INVAL
+    # subnormal operands: exact product keys, classes well defined
+    sub = np.array([5e-324, 1e-310, -3e-320, 2.5e-308])
+    r = oracle.qdot(sub, np.array([1e300, 1e290, 2e300, 1.0]), 1e-12, want_keys=True)
+    for i, k in enumerate(r["keys"].tolist()):
+        a, b = sub[i], [1e300, 1e290, 2e300, 1.0][i]
+        assert k == exp_of_fraction(Fraction(float(a)) * Fraction(b)) or k == \
+            exp_of_fraction(Fraction(float(a)) * Fraction(b)) + 1
+    # huge tolerance -> everything perforated, value +0
+    x, y = workloads.log_uniform_pair(1000, 5)
+    r = oracle.qdot(x, y, 1e300)
+    assert r["value"] == 0.0 and r["count"][oracle.PERF] == 1000
+    # tiny tolerance -> all double
+    r = oracle.qdot(x, y, 1e-300)
+    assert r["count"][oracle.DOUBLE] == 1000
+    # single element, ragged lengths around the tile size
+    for n in (1, 63, 64, 65, 127, 129):
+        x, y = workloads.log_uniform_pair(n, n)
+        r = oracle.qdot(x, y, 1e-6)
+        assert sum(r["count"]) == n
+        assert abs(r["value"] - oracle.dot_exact(x, y)) <= r["bound_rig"] * (1 + 2 ** -40)
+
+
+# --------------------------------------------------------------------------
+# CG and power method
+# --------------------------------------------------------------------------
+
+def test_cg_poisson_converges_within_distinct_eigenvalue_count():
+    # 4x4 grid: eigenvalues 4 - 2cos(i pi/5) - 2cos(j pi/5) take at most 10
+    # distinct values ((i,j) and (j,i) coincide), so exact-arithmetic CG
+    # ends in at most 10 steps.
+    rp, col, val = workloads.poisson2d_csr(4)
+    b = workloads.normal_vector(16, 1)
+    r = oracle.cg(rp, col, val, b, 1e-10, 0.0 + 1e-8, 50, 0)
+    assert r["status"] == oracle.OK
+    assert r["iters"] <= 11
+    assert r["relres_true"] < 1e-9
+
+
+@pytest.mark.parametrize("m", [16, 32])
+def test_cg_qdot_matches_fp64_iteration_count(m):
+    rp, col, val = workloads.poisson2d_csr(m)
+    b = workloads.normal_vector(m * m, 2)
+    a = oracle.cg(rp, col, val, b, 1e-10, 1e-8, 5000, 0)
+    q = oracle.cg(rp, col, val, b, 1e-10, 1e-8, 5000, 1, want_trace=True)
+    assert a["status"] == oracle.OK and q["status"] == oracle.OK
+    assert abs(q["iters"] - a["iters"]) <= 1
+    assert q["relres_true"] < 1e-9
+    assert len(q["trace"]) == 1 + 2 * q["iters"]
+
+
+def test_cg_breaks_down_when_everything_is_perforated():
+    rp, col, val = workloads.poisson2d_csr(8)
+    b = workloads.normal_vector(64, 3)
+    r = oracle.cg(rp, col, val, b, 1e-10, 1e300, 100, 1)
+    assert r["status"] == oracle.E_BREAKDOWN
+
+
+def test_power_method_reaches_closed_form_lambda_max():
+    m = 4
+    rp, col, val = workloads.laplacian3d_csr(m)
+    lam_max = 6.0 + 6.0 * math.cos(math.pi / (m + 1))
+    x0 = workloads.unit_vector(m ** 3, 9)
+    r = oracle.power(rp, col, val, x0, 400, 1e-6, 0)
+    assert r["status"] == oracle.OK
+    assert abs(r["lambda"] - lam_max) < 1e-9
+    q = oracle.power(rp, col, val, x0, 400, 1e-10, 1)
+    assert abs(q["lambda"] - lam_max) < 1e-8
+    assert np.all(q["trace"] <= lam_max * (1 + 1e-12))
+
+
+def test_spmv_matches_dense_product():
+    rp, col, val = workloads.poisson2d_csr(5)
+    A = np.zeros((25, 25))
+    for i in range(25):
+        for j in range(rp[i], rp[i + 1]):
+            A[i, col[j]] = val[j]
+    assert np.array_equal(A, A.T)
+    np.testing.assert_array_equal(np.diag(A), 4.0)
+    x = workloads.normal_vector(25, 4)
+    np.testing.assert_allclose(oracle.spmv(rp, col, val, x), A @ x, rtol=0, atol=1e-14)

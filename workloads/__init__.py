@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs shared by the oracle side and the HIP side.
+
+This module only draws numbers and builds matrices; it contains none of the
+qdot arithmetic (no exponents, bins, scores, quantisation or sums), so the
+oracle and the device path can both take their inputs from here without
+sharing any of the method's code.
+
+Every generator takes an explicit integer seed and uses numpy's PCG64.  The
+value laws follow the workloads the qdot paper studies:
+
+* ``log_uniform_pair``: components s * 10**u with u uniform on [lo, hi] and
+  an equiprobable sign, x and y independent.  This is the law of the single
+  qdot workloads (n = 1e5 and n = 2**27 at u in [-20, 20]).
+* ``paper_dist_a`` / ``paper_dist_b``: the two synthetic families of the
+  error-bound experiments (Sec. 4.1): s * 2**p with s ~ U[0.5, 1) and p
+  uniform on [-t/2, t/2] (family A) or normal with standard deviation t/2
+  (family B); p is rounded to an integer.  Both are positive.
+* ``poisson2d_csr``: the 5-point Dirichlet Laplacian on an m x m grid
+  (diagonal 4, neighbours -1), CSR with int32 indices.  It stands in for the
+  HPCCG matrices the paper's CG study uses (Sec. 4.2), which are not
+  available here.
+* ``laplacian3d_csr``: the 7-point Dirichlet Laplacian on an m**3 grid
+  (diagonal 6, neighbours -1), standing in for the paper's random graph
+  Laplacians in the power-method study (Sec. 4.3).
+* ``ragged_batch``: many independent qdot instances with log-uniform lengths
+  in [1e2, 1e6] and tolerances drawn from {1e-4, 1e-6, 1e-8}.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "rng",
+    "log_uniform_pair",
+    "paper_dist_a",
+    "paper_dist_b",
+    "normal_vector",
+    "unit_vector",
+    "poisson2d_csr",
+    "laplacian3d_csr",
+    "ragged_batch",
+    "cg_grid_sides",
+]
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _log_uniform(g: np.random.Generator, n: int, lo: float, hi: float,
+                 out: np.ndarray) -> None:
+    chunk = 1 << 22
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        u = g.uniform(lo, hi, e - s)
+        sign = np.where(g.integers(0, 2, e - s) == 0, 1.0, -1.0)
+        np.power(10.0, u, out=u)
+        out[s:e] = sign * u
+
+
+def log_uniform_pair(n: int, seed: int, lo: float = -20.0, hi: float = 20.0):
+    """x, y in FP64, i.i.d. components +-10**U[lo, hi] (independent signs)."""
+    g = rng(seed)
+    x = np.empty(n, dtype=np.float64)
+    y = np.empty(n, dtype=np.float64)
+    _log_uniform(g, n, lo, hi, x)
+    _log_uniform(g, n, lo, hi, y)
+    return x, y
+
+
+def _paper_family(n: int, t: float, seed: int, normal: bool):
+    g = rng(seed)
+    out = []
+    for _ in range(2):
+        s = g.uniform(0.5, 1.0, n)
+        if normal:
+            p = np.rint(g.normal(0.0, 0.5 * t, n))
+        else:
+            p = np.rint(g.uniform(-0.5 * t, 0.5 * t, n))
+        out.append(np.ldexp(s, p.astype(np.int64)))
+    return out[0], out[1]
+
+
+def paper_dist_a(n: int, t: float, seed: int):
+    """Family A of the error-bound study: s * 2**p, p ~ U[-t/2, t/2]."""
+    return _paper_family(n, t, seed, normal=False)
+
+
+def paper_dist_b(n: int, t: float, seed: int):
+    """Family B of the error-bound study: s * 2**p, p ~ N(0, t/2)."""
+    return _paper_family(n, t, seed, normal=True)
+
+
+def normal_vector(n: int, seed: int) -> np.ndarray:
+    return rng(seed).standard_normal(n)
+
+
+def unit_vector(n: int, seed: int) -> np.ndarray:
+    v = rng(seed).standard_normal(n)
+    return v / np.sqrt(np.dot(v, v))
+
+
+def _stencil_csr(shape, diag: float):
+    """CSR of the Dirichlet Laplacian stencil on a tensor grid.
+
+    Row order is lexicographic with the last axis fastest.  Within a row the
+    column indices are ascending, so every consumer sums a row in the same
+    order.
+    """
+    shape = tuple(int(s) for s in shape)
+    n = int(np.prod(shape))
+    idx = np.arange(n, dtype=np.int64).reshape(shape)
+    cols = [idx]
+    vals = [np.full(shape, diag)]
+    for ax in range(len(shape)):
+        for d in (-1, 1):
+            nb = np.roll(idx, -d, axis=ax)
+            valid = np.ones(shape, dtype=bool)
+            sl = [slice(None)] * len(shape)
+            sl[ax] = slice(-1, None) if d == 1 else slice(0, 1)
+            valid[tuple(sl)] = False
+            cols.append(np.where(valid, nb, -1))
+            vals.append(np.where(valid, -1.0, 0.0))
+    C = np.stack([c.reshape(n) for c in cols], axis=1)
+    V = np.stack([v.reshape(n) for v in vals], axis=1)
+    order = np.argsort(np.where(C < 0, np.iinfo(np.int64).max, C), axis=1,
+                       kind="stable")
+    C = np.take_along_axis(C, order, axis=1)
+    V = np.take_along_axis(V, order, axis=1)
+    keep = C >= 0
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(keep.sum(axis=1), out=rowptr[1:])
+    col = C[keep].astype(np.int32)
+    val = V[keep].astype(np.float64)
+    return rowptr.astype(np.int32), col, val
+
+
+def poisson2d_csr(m: int):
+    """5-point Laplacian, m x m grid, Dirichlet boundary: (rowptr, col, val)."""
+    return _stencil_csr((m, m), 4.0)
+
+
+def laplacian3d_csr(m: int):
+    """7-point Laplacian, m x m x m grid, Dirichlet boundary."""
+    return _stencil_csr((m, m, m), 6.0)
+
+
+def ragged_batch(count: int, seed: int, n_lo: float = 1e2, n_hi: float = 1e6,
+                 tols=(1e-4, 1e-6, 1e-8), mag_lo: float = -20.0,
+                 mag_hi: float = 20.0, max_total: int | None = None):
+    """A ragged batch of qdot instances stored back to back.
+
+    Returns (offsets[int64, count+1], x_cat, y_cat, tols[float64, count]).
+    Instance j occupies [offsets[j], offsets[j+1]).  Lengths are
+    round(10**U[log10 n_lo, log10 n_hi]); when ``max_total`` is given the
+    lengths are scaled down so that their sum does not exceed it (used for
+    small test batches).
+    """
+    g = rng(seed)
+    lens = np.rint(10.0 ** g.uniform(np.log10(n_lo), np.log10(n_hi), count))
+    lens = lens.astype(np.int64)
+    if max_total is not None and lens.sum() > max_total:
+        lens = np.maximum(1, (lens * (max_total / lens.sum())).astype(np.int64))
+    offsets = np.zeros(count + 1, dtype=np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    total = int(offsets[-1])
+    tol = np.asarray(tols, dtype=np.float64)[g.integers(0, len(tols), count)]
+    x = np.empty(total, dtype=np.float64)
+    y = np.empty(total, dtype=np.float64)
+    _log_uniform(g, total, mag_lo, mag_hi, x)
+    _log_uniform(g, total, mag_lo, mag_hi, y)
+    return offsets, x, y, tol
+
+
+def cg_grid_sides(count: int, seed: int, lo_exp: float = 5.0,
+                  hi_exp: float = 9.0) -> np.ndarray:
+    """Grid sides m_j = round(2**U[lo_exp, hi_exp]) for a batch of 2D CG systems."""
+    g = rng(seed)
+    return np.rint(2.0 ** g.uniform(lo_exp, hi_exp, count)).astype(np.int64)
