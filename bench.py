@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""qdot benchmark on one MI355X.
+
+Workload (the single large qdot): x, y FP64 with n = 2**27 components
++-10**U[-20, 20] (independent random signs), tol = 1e-6.  One step is one
+full qdot: exponent scan, cutoff selection, quantised accumulation and FP64
+combine, result left in device memory.  Inputs are resident in HBM before
+the timed region; K steps are timed between two device synchronisations.
+
+Printed: one JSON line with Gelem/s, the roofline of the dominant kernel
+(HBM-bound: 16 algorithmic bytes per component per pass), the plain FP64 dot
+on the same buffers, the paper's approximation speedup and efficiency, the
+CG iteration counts (2D Poisson 1024^2) and power-method eigenvalue error
+(3D Laplacian 128^3), and the CPU oracle timed on a sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "qdot Gelem/s & % HBM peak vs FP64 dot at rel err<=1e-6; CG iteration count"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_acc_single_qdot_2p27_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    src = os.path.join(ROOT, "paper_2105_00115_amd", "csrc", "qdot_kernels.hip")
+    dev = os.path.join(ROOT, "paper_2105_00115_amd", "csrc", "qdot_device.hpp")
+    h = hashlib.sha256()
+    for p in (src, dev):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n):
+    """HBM bytes per launch of the accumulate kernel from the committed
+    rocprofv3 counter runs, if they were taken on the current kernel."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha") != kernel_source_sha() or t.get("n") != n:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(x_host, y_host, tol, budget_s=12.0):
+    """The oracle as it stands (single-threaded C), on a bounded sample."""
+    import oracle
+
+    n = len(x_host)
+    reps, t = 0, 0.0
+    while t < budget_s and reps < 20:
+        t0 = time.perf_counter()
+        oracle.qdot(x_host, y_host, tol)
+        t += time.perf_counter() - t0
+        reps += 1
+    return {"value": round(n * reps / t / 1e9, 6), "unit": "Gelem/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {n} components of the same x, y, qdot at tol={tol}, "
+                      f"{reps} repetitions, {t:.1f} s total, single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=2027)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 23)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); the sharded design is described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import __graft_entry__
+
+    __graft_entry__._ensure_built()
+    import paper_2105_00115_amd as q
+    import workloads
+
+    n, tol = 1 << 27, 1e-6
+    K, Wm = args.steps, args.warmup
+    dev = "cuda:0"
+    log(f"generating x, y n={n} seed={args.seed} on {dev}")
+    x, y = workloads.log_uniform_pair_torch(n, args.seed, dev)
+    torch.cuda.synchronize()
+
+    h = q.Qdot(0)
+    _, num_cus = h.device_info()
+    out = torch.zeros(q.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    d_out = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    # calibration copy of known size (256 MiB read + 256 MiB written), used to
+    # scale the HBM byte counters of the profiler runs
+    cal_src = x[: 1 << 25]
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    del cal_dst
+
+    log(f"qdot warmup {Wm}, timed {K}")
+    for _ in range(Wm):
+        h.qdot_async(x, y, tol, out)
+    torch.cuda.synchronize()
+    h.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        h.qdot_async(x, y, tol, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.timing_enable(False)
+    tq = h.timing_read()
+    res = q.parse_results(out)[0]
+    wall = t1 - t0
+
+    log("FP64 dot baselines")
+    for _ in range(Wm):
+        h.fp64_dot_async(x, y, d_out)
+    torch.cuda.synchronize()
+    h.timing_enable(True)
+    for _ in range(K):
+        h.fp64_dot_async(x, y, d_out)
+    torch.cuda.synchronize()
+    h.timing_enable(False)
+    td = h.timing_read()
+    dot64 = float(d_out.item())
+    for _ in range(Wm):
+        torch.dot(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(K):
+        tdot = torch.dot(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    torch_dot_ms = e0.elapsed_time(e1) / K
+
+    scan_ms = tq["scan_ms"] / tq["qdot_calls"]
+    cut_ms = tq["cut_ms"] / tq["qdot_calls"]
+    acc_ms = tq["acc_ms"] / tq["qdot_calls"]
+    d64_ms = td["dot64_ms"] / td["dot64_calls"]
+    dominant, dom_ms = ("k_acc", acc_ms) if acc_ms >= scan_ms else ("k_scan", scan_ms)
+    alg_bytes = 16.0 * n  # x_i and y_i once per pass
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(n)
+
+    # CG on the 2D Poisson matrix 1024^2 (qdot tol 1e-8 vs FP64 dot)
+    log("CG 2D Poisson 1024^2")
+    m = 1024
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val, device=dev)
+    b = torch.from_numpy(workloads.normal_vector(m * m, 3)).to(dev)
+    cg = {}
+    for name, use in (("qdot", 1), ("fp64", 0)):
+        xs = torch.zeros(m * m, dtype=torch.float64, device=dev)
+        c0 = time.perf_counter()
+        r = h.cg(A, b, xs, 1e-10, 1e-8, 20000, use)
+        cg[name] = {"iters": r["iters"], "status": r["status"],
+                    "relres_true": r["relres_true"],
+                    "seconds": round(time.perf_counter() - c0, 3)}
+    del A, b
+
+    # power method on the 3D Laplacian 128^3, 500 iterations, qdot tol 1e-6
+    log("power method 3D Laplacian 128^3")
+    m3 = 128
+    rp, col, val = workloads.laplacian3d_csr(m3)
+    A = q.Csr(rp, col, val, device=dev)
+    x0 = workloads.unit_vector(m3 ** 3, 4)
+    pm = {}
+    for name, use in (("qdot", 1), ("fp64", 0)):
+        xs = torch.from_numpy(x0).to(dev)
+        c0 = time.perf_counter()
+        r = h.power(A, xs, 500, 1e-6, use, trace=False)
+        pm[name] = {"lambda": r["lambda"], "status": r["status"],
+                    "seconds": round(time.perf_counter() - c0, 3)}
+    lam_max = 6.0 + 6.0 * float(np.cos(np.pi / (m3 + 1)))
+    del A
+
+    log(f"CPU oracle on a sample of {args.cpu_sample}")
+    xh = x[: args.cpu_sample].cpu().numpy()
+    yh = y[: args.cpu_sample].cpu().numpy()
+    cpu = cpu_baseline(xh, yh, tol)
+
+    value = n * K / wall / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gelem/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(wall / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single qdot, n=2^27 FP64 x and y, components "
+                               "+-10^U[-20,20], tol=1e-6",
+                   "n": n, "tol": tol, "seed": args.seed, "schedule": "two-pass"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "extra": {
+            "kernel_ms": {"k_scan": round(scan_ms, 4), "k_cut": round(cut_ms, 4),
+                          "k_acc": round(acc_ms, 4), "k_dot64": round(d64_ms, 4),
+                          "torch_dot": round(torch_dot_ms, 4)},
+            "scan_frac_hbm": round(alg_bytes / (scan_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "fp64_dot_gelem_s": round(n / (d64_ms * 1e-3) / 1e9, 3),
+            "torch_dot_gelem_s": round(n / (torch_dot_ms * 1e-3) / 1e9, 3),
+            "qdot_vs_fp64_dot": round(d64_ms / (wall / K * 1e3), 4),
+            "approx_speedup_t_dot_over_t_acc": round(d64_ms / acc_ms, 4),
+            "approx_efficiency": round(d64_ms / (scan_ms + cut_ms + d64_ms), 4),
+            "result": {"count": res["count"], "n_bins": res["n_bins"], "t": res["t"],
+                       "bound_rel": res["bound_rel"], "flags": res["flags"],
+                       "value": res["value"]},
+            "relerr_vs_fp64_dot": abs(res["value"] - dot64) / abs(dot64) if dot64 else None,
+            "torch_dot_value": float(tdot.item()),
+            "cg_poisson2d_1024": cg,
+            "power_laplacian3d_128": {**pm, "abs_lambda_diff":
+                                      abs(pm["qdot"]["lambda"] - pm["fp64"]["lambda"]),
+                                      "lambda_max_closed_form": lam_max},
+            "num_cus": num_cus,
+            "kernel_src_sha": kernel_source_sha(),
+        },
+    }
+    h.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * qdot.h -- C ABI of the MI355X (gfx950) qdot library.
+ *
+ * qdot is the error-bounded quantized dot product of Diffenderfer,
+ * Osei-Kuffuor and Menon ("Qdot: Quantized Dot Product Kernel for
+ * Approximate High Performance Computing", arXiv 2105.00115).  Given FP64
+ * vectors x, y and a relative tolerance eps it
+ *   1. bins the component products x_i y_i by their binary exponent
+ *      (Def. 3.1 with exact binning, Sec. 3.2; Alg. 2),
+ *   2. scores every non-empty bin (eq. bin-score-def) and gives it a
+ *      precision -- double, single, half or perforate -- (eq.
+ *      precision-def), so that the bound of Thm 3.3 / Thm 3.5 stays below
+ *      eps,
+ *   3. computes each kept product at its bin's precision after scaling the
+ *      operands to exponent 0 and sums the results (Alg. 1, Sec. 3.3).
+ *
+ * Conventions for every entry point:
+ *   - Vectors and matrices are device pointers (hipMalloc'd or any memory a
+ *     gfx950 kernel may read), 8-byte aligned, owned by the caller; the
+ *     library never frees or retains them past the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Entry points named *_async only enqueue work and return; their
+ *     results are written to device memory in stream order.  Others
+ *     synchronise `stream` before returning.
+ *   - Return value is a qdot_status.  Argument errors are detected on the
+ *     host before anything is enqueued.  Data-dependent errors of async
+ *     calls (non-finite input) land in the `status` field of the device
+ *     result.  Nothing aborts, nothing throws across the ABI.
+ *   - A handle is not thread-safe: use one handle per host thread/stream.
+ *     Calls on one handle must be ordered on one stream (they share the
+ *     handle's workspace).
+ */
+#ifndef QDOT_H
+#define QDOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define QDOT_API __attribute__((visibility("default")))
+#else
+#define QDOT_API
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define QDOT_OK 0
+#define QDOT_E_INVAL 1      /* bad argument: n < 0, NULL with n > 0, tol <= 0
+                               or not finite, unknown option value */
+#define QDOT_E_NONFINITE 2  /* an input component is Inf or NaN (value NaN) */
+#define QDOT_E_DEVICE 3     /* a HIP call failed; see qdot_last_error() */
+#define QDOT_E_NOMEM 4      /* workspace allocation failed */
+#define QDOT_E_BREAKDOWN 5  /* CG / power: a divisor was <= 0, not finite, or
+                               qdot perforated every component */
+#define QDOT_E_MAXIT 6      /* CG: iteration limit reached */
+
+/* ---- precision classes (eq. precision-def) ------------------------- */
+#define QDOT_DOUBLE 0
+#define QDOT_SINGLE 1
+#define QDOT_HALF 2
+#define QDOT_PERF 3 /* perforated: left out of the sum */
+
+/* ---- result flags ---------------------------------------------------- */
+#define QDOT_F_UNATTAINABLE 1  /* some bin scored >= m_double (52): no
+                                  precision row of eq. (precision-def)
+                                  applies; it stays double and the bound may
+                                  exceed eps */
+#define QDOT_F_THM_ALL_DOUBLE 2 /* Thm 3.6 condition e_max - e_min <= -t - 23
+                                  holds: every bin is double */
+#define QDOT_F_ALL_PERF 4      /* no component kept; value is +0 */
+#define QDOT_F_OVERFLOW 8      /* the final scaling by 2^e_max overflowed */
+
+/* ---- options --------------------------------------------------------- */
+/* Zero-initialised = defaults. */
+typedef struct qdot_options {
+    /* 0: key = exponent of the product x_i*y_i (Def. 3.1, the theorems);
+     * 1: key = E(x_i) + E(y_i) (Alg. 2, exponent preprocessing line). */
+    int32_t key_mode;
+    /* 0: score with eps / N_bins (experiments of Sec. 4.1), so that Thm 3.5
+     *    bounds the relative error by eps;  1: score with eps itself. */
+    int32_t score_mode;
+    /* 0: eq. (precision-def) as printed (half-open intervals);
+     * 1: the proof's wording (perforate when the score is <= 0, else the
+     *    narrowest precision whose mantissa width is >= the score). */
+    int32_t boundary_mode;
+    /* 0: FP32 leaves summed in FP32 inside 64-element tiles of the index
+     *    order (adjacent-pairwise tree), then at FP64;
+     * 1: reserved (exact per-bin accumulation); QDOT_E_INVAL for now. */
+    int32_t accum_mode;
+} qdot_options;
+
+/* ---- per-call result ------------------------------------------------- */
+typedef struct qdot_result {
+    double value;        /* the approximate dot product */
+    int64_t count[4];    /* components per class DOUBLE, SINGLE, HALF, PERF;
+                            PERF includes zero products */
+    int64_t n_zero;      /* components with x_i == 0 or y_i == 0 */
+    int32_t e_min, e_max;/* smallest / largest product exponent (keys) */
+    int32_t n_bins;      /* non-empty exponent bins */
+    int32_t t;           /* floor(log2(eps / N_bins)) (or of eps) */
+    double part[3];      /* class sums DOUBLE, SINGLE, HALF (absolute) */
+    double bound_rel;    /* sum_k M_k 2^(k - e_max + 1) eps(class_k)
+                            (Thm 3.3 relative bound) */
+    double bound_abs;    /* 2^e_max * bound_rel (Thm 3.2 absolute bound) */
+    int32_t flags;       /* QDOT_F_* */
+    int32_t status;      /* QDOT_OK or QDOT_E_NONFINITE */
+} qdot_result;
+
+/* ---- CSR matrix (device arrays, host struct) -------------------------- */
+typedef struct qdot_csr {
+    int64_t n;             /* rows == columns */
+    int64_t nnz;
+    const int32_t *rowptr; /* n + 1 */
+    const int32_t *col;    /* nnz, ascending within a row */
+    const double *val;     /* nnz */
+} qdot_csr;
+
+typedef struct qdot_cg_result {
+    int32_t iters;        /* iterations taken */
+    int32_t status;       /* QDOT_OK, QDOT_E_BREAKDOWN or QDOT_E_MAXIT */
+    double relres_est;    /* sqrt(c_k) / ||b|| at exit (c_k from the dot
+                             product in use) */
+    double relres_true;   /* ||b - A x|| / ||b|| recomputed at exit (FP64) */
+} qdot_cg_result;
+
+/* ---- launch configuration (autotuner) ---------------------------------- */
+typedef struct qdot_tune {
+    int32_t blocks_per_cu; /* persistent grid = blocks_per_cu * CUs (>= 1) */
+    int32_t unroll;        /* 1, 2 or 4 groups of 4 elements in flight per
+                              thread; never changes a result bit of the
+                              integer outputs or of any FP32 tile sum */
+} qdot_tune;
+
+typedef struct qdot_handle qdot_handle;
+
+/* Create a handle on `device` (HIP ordinal): allocates the workspace
+ * (histogram, class table, per-block partials) once.
+ * Returns QDOT_E_INVAL (h NULL or bad ordinal), QDOT_E_DEVICE, QDOT_E_NOMEM. */
+QDOT_API int32_t qdot_create(qdot_handle **h, int32_t device);
+
+/* Free the handle and its workspace.  NULL is a no-op. */
+QDOT_API int32_t qdot_destroy(qdot_handle *h);
+
+/* Text of the last error on this handle ("" if none).  Owned by the
+ * handle, valid until the next call on it. */
+QDOT_API const char *qdot_last_error(const qdot_handle *h);
+
+/* Device the handle was created on and its compute-unit count. */
+QDOT_API int32_t qdot_device_info(const qdot_handle *h, int32_t *device,
+                         int32_t *num_cus);
+
+/* Set / get the launch configuration (NULL cfg in set = defaults). */
+QDOT_API int32_t qdot_set_tune(qdot_handle *h, const qdot_tune *cfg);
+QDOT_API int32_t qdot_get_tune(const qdot_handle *h, qdot_tune *cfg);
+
+/* Kernel timing (diagnostics).  While enabled, every qdot and FP64-dot call
+ * on this handle records HIP events on its stream around each kernel it
+ * launches (not allowed while the stream is being captured into a graph).
+ * qdot_timing_read synchronises the recorded events and returns the summed
+ * durations in milliseconds of the scan, cutoff and accumulate kernels of
+ * qdot (ms[0..2]) and of the FP64 dot kernel (ms[3]), the number of qdot
+ * and FP64-dot calls timed (calls[0..1]), then clears the record. */
+QDOT_API int32_t qdot_timing_enable(qdot_handle *h, int32_t enable);
+QDOT_API int32_t qdot_timing_read(qdot_handle *h, double ms[4], int32_t calls[2]);
+
+/* qdot(x, y, eps) -- Alg. 3: parameter selection (Alg. 2) then the
+ * computation phase (Alg. 1).
+ *   x, y : device FP64[n]; n >= 0; tol = eps > 0, finite (any size:
+ *          eps > 1 is allowed, as in the CG study of Sec. 4.2).
+ *   opt  : NULL for defaults.
+ *   dev_out : device pointer to one qdot_result, written in stream order.
+ * n == 0 or all-zero products give value +0 with QDOT_F_ALL_PERF.
+ * Enqueues three kernels; performs no allocation and no host sync, so it
+ * may be captured in a HIP graph. */
+QDOT_API int32_t qdot_async(qdot_handle *h, const double *x, const double *y,
+                   int64_t n, double tol, const qdot_options *opt,
+                   void *stream, qdot_result *dev_out);
+
+/* Synchronous qdot: as qdot_async, then copies the result to host_out and
+ * synchronises the stream.  Returns the result's status (QDOT_OK or
+ * QDOT_E_NONFINITE) when the call itself succeeded. */
+QDOT_API int32_t qdot(qdot_handle *h, const double *x, const double *y, int64_t n,
+             double tol, const qdot_options *opt, void *stream,
+             qdot_result *host_out);
+
+/* Debug view of the parameter selection (Alg. 2): per-component class
+ * dev_cls[n] (uint8, QDOT_DOUBLE..QDOT_PERF) and, if dev_hist is not NULL,
+ * the exponent histogram dev_hist[4196] (int64, slot k + 2148 counts the
+ * products with exponent k).  Also writes the full result to dev_out.
+ * Async, same errors as qdot_async. */
+QDOT_API int32_t qdot_classes_async(qdot_handle *h, const double *x, const double *y,
+                           int64_t n, double tol, const qdot_options *opt,
+                           void *stream, uint8_t *dev_cls, int64_t *dev_hist,
+                           qdot_result *dev_out);
+
+/* Plain FP64 dot product sum_i x_i y_i (the full-precision kernel that
+ * qdot approximates; the comparison baseline of Sec. 4.1).  dev_out: one
+ * double in device memory.  Async. */
+QDOT_API int32_t qdot_fp64_dot_async(qdot_handle *h, const double *x, const double *y,
+                            int64_t n, void *stream, double *dev_out);
+
+/* y = A x for a CSR matrix (rows summed in stored order, each product and
+ * sum one FP64 rounding).  Async. */
+QDOT_API int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double *x,
+                        double *y, void *stream);
+
+/* Conjugate gradient, Alg. 4 (ACG): both inner products of every iteration
+ * (r.r and p.Ap) by qdot at tolerance qtol when use_qdot != 0, else by the
+ * plain FP64 dot.  x holds x0 on entry and the solution on exit.  Stops
+ * when sqrt(c_k) <= rtol * ||b||_2 (||b|| by the FP64 dot) or after maxit
+ * iterations.  trace: NULL or device qdot_result[2*maxit + 1] receiving
+ * every qdot result in call order.  Synchronous; out (host) receives the
+ * iteration count, status and residuals.  Returns out->status. */
+QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x,
+                double rtol, double qtol, int32_t maxit, int32_t use_qdot,
+                const qdot_options *opt, void *stream, qdot_cg_result *out,
+                qdot_result *trace);
+
+/* Power method (Alg. 5 with the Rayleigh quotient of the current unit
+ * iterate): per iteration w = A x, lambda = dot(x, w), c = dot(w, w),
+ * x = w / sqrt(c), with both dots by qdot at qtol when use_qdot != 0.
+ * x: device FP64[n], unit vector on entry, last iterate on exit.
+ * lambda (host): last lambda.  lambda_trace: NULL or device FP64[iters].
+ * Synchronous.  QDOT_E_BREAKDOWN if c <= 0 or not finite. */
+QDOT_API int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x,
+                   int32_t iters, double qtol, int32_t use_qdot,
+                   const qdot_options *opt, void *stream, double *lambda,
+                   double *lambda_trace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QDOT_H */

@@ -1,0 +1,317 @@
+"""qdot on MI355X: Python binding of ``libqdot.so``.
+
+The binding only marshals arguments: every step of qdot (exponent scan,
+cutoff selection, quantised accumulation, FP64 combine) and of the CG and
+power-method drivers runs in the library's HIP kernels.  PyTorch supplies
+device memory and streams.  If the library has not been built, loading
+fails loudly; there is no fallback.
+
+Two layers:
+
+* ``lib()`` -- the raw C ABI (names as in ``include/qdot.h``), taking
+  integer device addresses.
+* ``Qdot`` -- a handle wrapper taking torch tensors (float64, CUDA,
+  contiguous) and the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqdot.so")
+
+OK, E_INVAL, E_NONFINITE, E_DEVICE, E_NOMEM, E_BREAKDOWN, E_MAXIT = range(7)
+DOUBLE, SINGLE, HALF, PERF = 0, 1, 2, 3
+F_UNATTAINABLE, F_THM_ALL_DOUBLE, F_ALL_PERF, F_OVERFLOW = 1, 2, 4, 8
+KMIN, KMAX = -2148, 2047
+W = KMAX - KMIN + 1
+
+
+class QdotOptions(C.Structure):
+    _fields_ = [("key_mode", C.c_int32), ("score_mode", C.c_int32),
+                ("boundary_mode", C.c_int32), ("accum_mode", C.c_int32)]
+
+
+class QdotResult(C.Structure):
+    _fields_ = [
+        ("value", C.c_double),
+        ("count", C.c_int64 * 4),
+        ("n_zero", C.c_int64),
+        ("e_min", C.c_int32),
+        ("e_max", C.c_int32),
+        ("n_bins", C.c_int32),
+        ("t", C.c_int32),
+        ("part", C.c_double * 3),
+        ("bound_rel", C.c_double),
+        ("bound_abs", C.c_double),
+        ("flags", C.c_int32),
+        ("status", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "value": self.value, "count": list(self.count), "n_zero": self.n_zero,
+            "e_min": self.e_min, "e_max": self.e_max, "n_bins": self.n_bins,
+            "t": self.t, "part": list(self.part), "bound_rel": self.bound_rel,
+            "bound_abs": self.bound_abs, "flags": self.flags, "status": self.status,
+        }
+
+
+class QdotCsr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class QdotCgResult(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32),
+                ("relres_est", C.c_double), ("relres_true", C.c_double)]
+
+
+class QdotTune(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("unroll", C.c_int32)]
+
+
+RESULT_BYTES = C.sizeof(QdotResult)
+
+# (name, restype, argtypes) of every entry point in include/qdot.h
+_vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+_OPT = C.POINTER(QdotOptions)
+_CSR = C.POINTER(QdotCsr)
+SIGNATURES = [
+    ("qdot_create", _i32, [C.POINTER(_vp), _i32]),
+    ("qdot_destroy", _i32, [_vp]),
+    ("qdot_last_error", C.c_char_p, [_vp]),
+    ("qdot_device_info", _i32, [_vp, C.POINTER(_i32), C.POINTER(_i32)]),
+    ("qdot_set_tune", _i32, [_vp, C.POINTER(QdotTune)]),
+    ("qdot_get_tune", _i32, [_vp, C.POINTER(QdotTune)]),
+    ("qdot_timing_enable", _i32, [_vp, _i32]),
+    ("qdot_timing_read", _i32, [_vp, C.POINTER(_d), C.POINTER(_i32)]),
+    ("qdot_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp]),
+    ("qdot", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, C.POINTER(QdotResult)]),
+    ("qdot_classes_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp, _vp, _vp]),
+    ("qdot_fp64_dot_async", _i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    ("qdot_spmv_async", _i32, [_vp, _CSR, _vp, _vp, _vp]),
+    ("qdot_cg", _i32, [_vp, _CSR, _vp, _vp, _d, _d, _i32, _i32, _OPT, _vp,
+                       C.POINTER(QdotCgResult), _vp]),
+    ("qdot_power", _i32, [_vp, _CSR, _vp, _i32, _d, _i32, _OPT, _vp,
+                          C.POINTER(_d), _vp]),
+]
+
+_lib = None
+
+
+class QdotError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str = ""):
+        super().__init__(f"{where}: status {code} {msg}".strip())
+        self.code = code
+
+
+def lib():
+    """The loaded C library.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"qdot HIP library not found at {LIB_PATH}; build it first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES:
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _opts(opt):
+    if opt is None:
+        return None
+    if isinstance(opt, QdotOptions):
+        return C.byref(opt)
+    if isinstance(opt, dict):
+        return C.byref(QdotOptions(**opt))
+    return C.byref(QdotOptions(*[int(v) for v in opt]))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_vec(t, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == 1):
+        raise ValueError(f"{name} must be a contiguous 1-D float64 CUDA tensor")
+
+
+def parse_results(buf) -> list:
+    """Decode a uint8 tensor / bytes holding one or more qdot_result."""
+    raw = bytes(buf.cpu().numpy().tobytes()) if hasattr(buf, "cpu") else bytes(buf)
+    n = len(raw) // RESULT_BYTES
+    return [QdotResult.from_buffer_copy(raw, i * RESULT_BYTES).as_dict() for i in range(n)]
+
+
+class Csr:
+    """CSR matrix on the device (int32 indices, float64 values)."""
+
+    def __init__(self, rowptr, col, val, device="cuda"):
+        import torch
+        self.rowptr = torch.as_tensor(rowptr, dtype=torch.int32).to(device).contiguous()
+        self.col = torch.as_tensor(col, dtype=torch.int32).to(device).contiguous()
+        self.val = torch.as_tensor(val, dtype=torch.float64).to(device).contiguous()
+        self.n = self.rowptr.numel() - 1
+        self.c = QdotCsr(self.n, self.col.numel(), self.rowptr.data_ptr(),
+                         self.col.data_ptr(), self.val.data_ptr())
+
+
+class Qdot:
+    """A library handle bound to one device."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        st = lib().qdot_create(C.byref(self._h), int(device))
+        if st != OK:
+            raise QdotError(st, "qdot_create")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().qdot_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st, where):
+        raise QdotError(st, where, lib().qdot_last_error(self._h).decode())
+
+    # ---- configuration ----------------------------------------------------
+    def device_info(self):
+        d, c = C.c_int32(), C.c_int32()
+        lib().qdot_device_info(self._h, C.byref(d), C.byref(c))
+        return d.value, c.value
+
+    def set_tune(self, blocks_per_cu: int, unroll: int):
+        st = lib().qdot_set_tune(self._h, C.byref(QdotTune(blocks_per_cu, unroll)))
+        if st != OK:
+            self._raise(st, "qdot_set_tune")
+
+    def get_tune(self):
+        t = QdotTune()
+        lib().qdot_get_tune(self._h, C.byref(t))
+        return t.blocks_per_cu, t.unroll
+
+    def timing_enable(self, on: bool = True):
+        lib().qdot_timing_enable(self._h, 1 if on else 0)
+
+    def timing_read(self) -> dict:
+        ms = (C.c_double * 4)()
+        calls = (C.c_int32 * 2)()
+        st = lib().qdot_timing_read(self._h, ms, calls)
+        if st != OK:
+            self._raise(st, "qdot_timing_read")
+        return {"scan_ms": ms[0], "cut_ms": ms[1], "acc_ms": ms[2], "dot64_ms": ms[3],
+                "qdot_calls": calls[0], "dot64_calls": calls[1]}
+
+    # ---- qdot --------------------------------------------------------------
+    def qdot(self, x, y, tol, opt=None, stream=None) -> dict:
+        _check_vec(x, "x")
+        _check_vec(y, "y")
+        r = QdotResult()
+        st = lib().qdot(self._h, _ptr(x), _ptr(y), x.numel(), float(tol), _opts(opt),
+                        _stream(stream), C.byref(r))
+        if st not in (OK, E_NONFINITE):
+            self._raise(st, "qdot")
+        return r.as_dict()
+
+    def qdot_async(self, x, y, tol, out, opt=None, stream=None):
+        """out: CUDA uint8 tensor of RESULT_BYTES (or a slice address int)."""
+        _check_vec(x, "x")
+        _check_vec(y, "y")
+        dst = C.c_void_p(out if isinstance(out, int) else out.data_ptr())
+        st = lib().qdot_async(self._h, _ptr(x), _ptr(y), x.numel(), float(tol), _opts(opt),
+                              _stream(stream), dst)
+        if st != OK:
+            self._raise(st, "qdot_async")
+
+    def qdot_classes(self, x, y, tol, opt=None, stream=None):
+        """(classes uint8[n], histogram int64[W], result dict), synchronised."""
+        import torch
+        _check_vec(x, "x")
+        _check_vec(y, "y")
+        n = x.numel()
+        cls = torch.empty(max(n, 1), dtype=torch.uint8, device=x.device)
+        hist = torch.empty(W, dtype=torch.int64, device=x.device)
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=x.device)
+        st = lib().qdot_classes_async(self._h, _ptr(x), _ptr(y), n, float(tol), _opts(opt),
+                                      _stream(stream), _ptr(cls), _ptr(hist), _ptr(out))
+        if st != OK:
+            self._raise(st, "qdot_classes_async")
+        torch.cuda.current_stream().synchronize()
+        return cls[:n], hist, parse_results(out)[0]
+
+    def fp64_dot_async(self, x, y, out, stream=None):
+        _check_vec(x, "x")
+        _check_vec(y, "y")
+        st = lib().qdot_fp64_dot_async(self._h, _ptr(x), _ptr(y), x.numel(),
+                                       _stream(stream), _ptr(out))
+        if st != OK:
+            self._raise(st, "qdot_fp64_dot_async")
+
+    def fp64_dot(self, x, y) -> float:
+        import torch
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+        self.fp64_dot_async(x, y, out)
+        return float(out.item())
+
+    # ---- applications ------------------------------------------------------
+    def spmv(self, A: Csr, x, y, stream=None):
+        st = lib().qdot_spmv_async(self._h, C.byref(A.c), _ptr(x), _ptr(y), _stream(stream))
+        if st != OK:
+            self._raise(st, "qdot_spmv_async")
+
+    def cg(self, A: Csr, b, x, rtol, qtol, maxit, use_qdot, opt=None, trace=False,
+           stream=None) -> dict:
+        import torch
+        _check_vec(b, "b")
+        _check_vec(x, "x")
+        tr = (torch.zeros((2 * maxit + 1) * RESULT_BYTES, dtype=torch.uint8, device=b.device)
+              if trace else None)
+        r = QdotCgResult()
+        st = lib().qdot_cg(self._h, C.byref(A.c), _ptr(b), _ptr(x), float(rtol), float(qtol),
+                           int(maxit), int(use_qdot), _opts(opt), _stream(stream), C.byref(r),
+                           _ptr(tr))
+        if st not in (OK, E_BREAKDOWN, E_MAXIT):
+            self._raise(st, "qdot_cg")
+        d = {"status": r.status, "iters": r.iters, "relres_est": r.relres_est,
+             "relres_true": r.relres_true}
+        if trace:
+            d["trace"] = parse_results(tr[: (1 + 2 * r.iters) * RESULT_BYTES])
+        return d
+
+    def power(self, A: Csr, x, iters, qtol, use_qdot, opt=None, trace=True,
+              stream=None) -> dict:
+        import torch
+        _check_vec(x, "x")
+        tr = torch.zeros(max(iters, 1), dtype=torch.float64, device=x.device) if trace else None
+        lam = C.c_double()
+        st = lib().qdot_power(self._h, C.byref(A.c), _ptr(x), int(iters), float(qtol),
+                              int(use_qdot), _opts(opt), _stream(stream), C.byref(lam),
+                              _ptr(tr))
+        if st not in (OK, E_BREAKDOWN):
+            self._raise(st, "qdot_power")
+        d = {"status": st, "lambda": lam.value}
+        if trace:
+            d["trace"] = tr[:iters].cpu().numpy()
+        return d

@@ -1,0 +1,186 @@
+// Device-side building blocks shared by the qdot kernels (gfx950 only).
+//
+// Everything here is integer or exactly-rounded IEEE arithmetic; the whole
+// library is compiled with -ffp-contract=off so that no product is fused
+// with the sum that consumes it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qdot.h"
+
+namespace qd {
+
+// Product exponents (keys) span [KMIN, KMAX]: operand exponents are in
+// [-1074, 1023] once subnormals are normalised, and the product-mode carry
+// adds at most one.
+constexpr int KMIN = -2148;
+constexpr int KMAX = 2047;
+constexpr int W = KMAX - KMIN + 1;          // 4196 histogram slots
+constexpr int W_LUT = (W + 15) / 16 * 16;   // class table, padded
+
+constexpr int BLOCK = 256;                  // threads per block (4 waves)
+constexpr int EPT = 4;                      // consecutive elements per lane
+constexpr int CHUNK = BLOCK * EPT;          // 1024 elements per block group
+constexpr int TILE = 64;                    // FP32 accumulation tile
+constexpr int CUT_THREADS = 1024;
+
+constexpr uint64_t FRAC_MASK = 0x000fffffffffffffull;
+constexpr uint64_t ONE_BITS = 0x3ff0000000000000ull;
+
+// Control block in device memory, one per handle.
+struct Ws {
+    unsigned long long hist[W];  // pass-1 exponent histogram
+    unsigned long long n_zero;   // zero products seen by pass 1
+    unsigned int nonfinite;      // any Inf/NaN seen by pass 1
+    unsigned int ticket;         // last-block election of pass 2
+    // produced by the cutoff kernel for pass 2
+    int e_max;
+    int t;
+    int c32;                     // exponent offset of FP32 leaves
+    int skip;                    // nothing to accumulate (result final)
+    unsigned char lut[W_LUT];    // class of every key slot
+};
+
+// One operand split into unbiased exponent and 52-bit fraction of its
+// normalised significand m = 1.frac in [1, 2).
+struct Split {
+    int e;
+    uint64_t frac;
+};
+
+__device__ __forceinline__ Split split_bits(uint64_t b)
+{
+    Split s;
+    const uint32_t code = (uint32_t)(b >> 52) & 0x7ffu;
+    const uint64_t f = b & FRAC_MASK;
+    if (__builtin_expect(code != 0, 1)) {
+        s.e = (int)code - 1023;
+        s.frac = f;
+    } else {
+        // subnormal: leading one at bit p (0..51); value 2^(p-1074) * 1.xxx
+        const int p = 63 - __clzll(f | 1ull);
+        s.e = p - 1074;
+        s.frac = (f << (52 - p)) & FRAC_MASK;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double mant(uint64_t frac)
+{
+    return __longlong_as_double((long long)(frac | ONE_BITS));
+}
+
+// Everything the kernels need to know about one component.
+struct Comp {
+    int es;       // E(x) + E(y)
+    int slot;     // key - KMIN (0 for zero / non-finite components)
+    bool zero;    // x == 0 or y == 0
+    bool bad;     // x or y is Inf/NaN
+    bool neg;     // sign of x*y
+    uint64_t fx, fy;
+    double mp;    // fl64(m_x * m_y) in [1, 4)
+};
+
+__device__ __forceinline__ Comp component(double x, double y, int key_mode)
+{
+    Comp c;
+    const uint64_t bx = (uint64_t)__double_as_longlong(x);
+    const uint64_t by = (uint64_t)__double_as_longlong(y);
+    c.zero = ((bx << 1) == 0) | ((by << 1) == 0);
+    c.bad = (((bx >> 52) & 0x7ff) == 0x7ff) | (((by >> 52) & 0x7ff) == 0x7ff);
+    c.neg = ((bx ^ by) >> 63) != 0;
+    const Split sx = split_bits(bx);
+    const Split sy = split_bits(by);
+    c.fx = sx.frac;
+    c.fy = sy.frac;
+    c.es = sx.e + sy.e;
+    c.mp = mant(sx.frac) * mant(sy.frac);
+    const int carry = (key_mode == 0 && c.mp >= 2.0) ? 1 : 0;
+    const bool live = !(c.zero | c.bad);
+    c.slot = live ? (c.es + carry - KMIN) : 0;
+    return c;
+}
+
+// Binary16 significand of 1.frac, round to nearest even straight from the
+// 52-bit fraction: an integer in [1024, 2048].
+__device__ __forceinline__ uint32_t half_sig(uint64_t frac)
+{
+    const uint32_t q = (uint32_t)(frac >> 42);
+    const uint64_t rem = frac & ((1ull << 42) - 1);
+    const uint64_t mid = 1ull << 41;
+    const uint32_t up = (rem > mid) | ((rem == mid) & (q & 1u));
+    return 1024u + q + up;
+}
+
+// ---- cross-lane moves (DPP, within 16-lane rows) -------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141; // lane i <- 7 - i within 8
+constexpr int DPP_MIRROR = 0x140;      // lane i <- 15 - i within 16
+
+// Levels 3..6 of the adjacent-pairwise tree of a 64-element tile held as
+// 16 lanes x 4 consecutive leaves, each lane entering with the sum of its
+// own 4 leaves (levels 1..2).  After each level every lane of a group holds
+// the same group sum (IEEE addition is commutative), so any partner lane in
+// the neighbouring group supplies the same operand.
+__device__ __forceinline__ float tile_levels_3to6(float s)
+{
+    s = s + dpp_f<DPP_XOR1>(s);
+    s = s + dpp_f<DPP_XOR2>(s);
+    s = s + dpp_f<DPP_HALF_MIRROR>(s);
+    s = s + dpp_f<DPP_MIRROR>(s);
+    return s;
+}
+
+// ---- compensated FP64 accumulation ---------------------------------------
+struct Acc {
+    double s, c;
+};
+
+__device__ __forceinline__ void acc_add(Acc &a, double v)
+{
+    const double t = a.s + v;
+    const double bp = t - a.s;
+    const double err = (a.s - (t - bp)) + (v - bp);
+    a.s = t;
+    a.c = a.c + err;
+}
+
+__device__ __forceinline__ Acc acc_merge(Acc a, Acc b)
+{
+    Acc r = a;
+    acc_add(r, b.s);
+    r.c = r.c + b.c;
+    return r;
+}
+
+__device__ __forceinline__ Acc acc_shfl_xor(Acc a, int mask)
+{
+    Acc b;
+    b.s = __shfl_xor(a.s, mask, 64);
+    b.c = __shfl_xor(a.c, mask, 64);
+    return b;
+}
+
+__device__ __forceinline__ Acc wave_reduce(Acc a)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) a = acc_merge(a, acc_shfl_xor(a, m));
+    return a;
+}
+
+// ceil(log2 m), m >= 1
+__device__ __forceinline__ int ceil_log2_u64(unsigned long long m)
+{
+    return m <= 1 ? 0 : 64 - __clzll(m - 1);
+}
+
+}  // namespace qd

@@ -1,0 +1,61 @@
+// Host-side handle shared by the C ABI translation units.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "qdot_kernels.hpp"
+
+struct qdot_handle {
+    int device = 0;
+    int num_cus = 0;
+    qd::Ws *ws = nullptr;            // device control block
+    double *partials = nullptr;      // per-block partials
+    int partial_blocks = 0;          // capacity in blocks
+    qdot_result *dev_res = nullptr;  // device result slot for the sync API
+    qdot_result *host_res = nullptr; // pinned host mirror
+    qdot_tune tune = {4, 2};
+    std::string err;
+
+    // scratch for the solver drivers, grown on demand
+    double *vec = nullptr;           // 4 * vec_n doubles
+    int64_t vec_n = 0;
+    void *ctl = nullptr;             // solver control block
+    qdot_result *res_ring = nullptr; // solver result slots
+    double *dres = nullptr;          // FP64-dot result slots
+    void *host_ctl = nullptr;        // pinned mirror of ctl
+
+    // kernel timing (diagnostics)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool; // created events, reused after each read
+    std::vector<int> ev_kind;        // per timed call: 0 qdot (4 events), 1 dot (2)
+    size_t ev_used = 0;
+};
+
+namespace qd {
+
+// Make `h->device` current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int32_t fail(qdot_handle *h, int32_t code, const std::string &msg);
+int32_t hip_fail(qdot_handle *h, hipError_t e, const char *where);
+Launch make_launch(qdot_handle *h, hipStream_t s);
+// Events for one timed call of `kind` (0: qdot, 4 events; 1: FP64 dot, 2),
+// or NULL when timing is off or events cannot be created.
+hipEvent_t *take_events(qdot_handle *h, int kind);
+bool options_ok(const qdot_options &o);
+
+}  // namespace qd

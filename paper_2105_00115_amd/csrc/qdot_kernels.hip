@@ -1,0 +1,577 @@
+// qdot kernels for gfx950: exponent scan, cutoff selection, fused
+// quantize-and-accumulate, and the plain FP64 dot used as the baseline.
+//
+// Data layout: x and y are FP64 vectors read in groups of 4 consecutive
+// elements per lane (two 16-byte loads per operand when both are 16-byte
+// aligned).  A block of 256 lanes covers 1024 consecutive elements per
+// group; a wave covers 256, i.e. four 64-element FP32 accumulation tiles,
+// one per 16-lane DPP row.  Both passes use the same block -> chunk
+// mapping, so on inputs that fit in L2 / Infinity Cache the second pass
+// re-reads what the same XCD fetched in the first.
+#include "qdot_kernels.hpp"
+
+#include <climits>
+
+namespace qd {
+
+template <bool VEC>
+__device__ __forceinline__ void load4(const double *__restrict__ p, int64_t i0,
+                                      int64_t n, double v[4])
+{
+    if (i0 + 4 <= n) {
+        if (VEC) {
+            const double2 a = *reinterpret_cast<const double2 *>(p + i0);
+            const double2 b = *reinterpret_cast<const double2 *>(p + i0 + 2);
+            v[0] = a.x;
+            v[1] = a.y;
+            v[2] = b.x;
+            v[3] = b.y;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; e++) v[e] = p[i0 + e];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++) v[e] = (i0 + e < n) ? p[i0 + e] : 0.0;
+    }
+}
+
+__device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1 (Alg. 2, exponent preprocessing + counting): product exponents into
+// a block-private LDS histogram, merged into the global one at the end.
+// ---------------------------------------------------------------------------
+template <bool VEC, int U>
+__global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                int64_t n, int key_mode,
+                                                Ws *__restrict__ ws)
+{
+    __shared__ unsigned int h[W];
+    for (int i = threadIdx.x; i < W; i += BLOCK) h[i] = 0;
+    __syncthreads();
+
+    unsigned int nz = 0, bad = 0;
+    const int64_t step = (int64_t)gridDim.x * CHUNK * U;
+    for (int64_t base = (int64_t)blockIdx.x * CHUNK * U; base < n; base += step) {
+        double xv[U][4], yv[U][4];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            load4<VEC>(x, i0, n, xv[u]);
+            load4<VEC>(y, i0, n, yv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                if (i0 + e < n) {
+                    const Comp c = component(xv[u][e], yv[u][e], key_mode);
+                    nz += c.zero;
+                    bad |= c.bad;
+                    if (!(c.zero | c.bad)) atomicAdd(&h[c.slot], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < W; i += BLOCK) {
+        const unsigned int v = h[i];
+        if (v) atomicAdd(&ws->hist[i], (unsigned long long)v);
+    }
+    nz = wave_sum_u32(nz);
+    bad = wave_sum_u32(bad);
+    if ((threadIdx.x & 63) == 0) {
+        if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
+        if (bad) atomicOr(&ws->nonfinite, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cutoff selection (Alg. 2, bins -> scores -> precisions), one workgroup.
+// ---------------------------------------------------------------------------
+
+// t = floor(log2(eps / nb)): the largest integer tau with nb * 2^tau <= eps,
+// by integer comparison of 53-bit significands.  With eps = S * 2^(E - 52),
+// S in [2^52, 2^53), and nb scaled to N' = nb * 2^(53 - b) in the same
+// range (b = bit length of nb): nb * 2^tau = N' * 2^(tau - 53 + b), so
+// tau = E + 1 - b when N' <= S, else E - b.
+__device__ int floor_log2_ratio(double eps, unsigned long long nb)
+{
+    const uint64_t bits = (uint64_t)__double_as_longlong(eps);
+    const Split s = split_bits(bits);
+    const uint64_t S = s.frac | (1ull << 52);
+    const int b = 64 - __clzll(nb);
+    const uint64_t Np = nb << (53 - b);
+    return s.e + 1 - b - (Np > S ? 1 : 0);
+}
+
+__device__ __forceinline__ int class_of(int sigma, int nonstrict)
+{
+    // eq. (precision-def) with m_half = 10, m_single = 23; the non-strict
+    // reading moves every boundary up by one (score <= m qualifies).
+    const int o = nonstrict ? 1 : 0;
+    if (sigma < 0 + o) return QDOT_PERF;
+    if (sigma < 10 + o) return QDOT_HALF;
+    if (sigma < 23 + o) return QDOT_SINGLE;
+    return QDOT_DOUBLE;
+}
+
+__device__ __forceinline__ double eps_of_class(int c)
+{
+    return c == QDOT_DOUBLE ? 0x1p-52 : c == QDOT_SINGLE ? 0x1p-23
+         : c == QDOT_HALF ? 0x1p-10 : 1.0;
+}
+
+__global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double tol,
+                                                     int score_mode, int nonstrict,
+                                                     int64_t n, qdot_result *__restrict__ out,
+                                                     long long *__restrict__ hist_out)
+{
+    constexpr int R = (W + CUT_THREADS - 1) / CUT_THREADS;
+    constexpr int NW = CUT_THREADS / 64;
+    __shared__ int s_max[NW], s_min[NW], s_nb[NW], s_unatt[NW];
+    __shared__ unsigned long long s_cnt[NW][4];
+    __shared__ double s_bound[NW];
+    __shared__ int s_emax, s_t, s_go;
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    unsigned long long cnt[R];
+    int emax = INT_MIN, emin = INT_MAX, nb = 0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int j = tid + r * CUT_THREADS;
+        cnt[r] = j < W ? ws->hist[j] : 0ull;
+        if (cnt[r]) {
+            const int k = j + KMIN;
+            emax = max(emax, k);
+            emin = min(emin, k);
+            nb++;
+        }
+        if (hist_out && j < W) hist_out[j] = (long long)cnt[r];
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        emax = max(emax, __shfl_xor(emax, m, 64));
+        emin = min(emin, __shfl_xor(emin, m, 64));
+        nb += __shfl_xor(nb, m, 64);
+    }
+    if (lane == 0) {
+        s_max[wv] = emax;
+        s_min[wv] = emin;
+        s_nb[wv] = nb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int a = INT_MIN, b = INT_MAX, c = 0;
+        for (int w = 0; w < NW; w++) {
+            a = max(a, s_max[w]);
+            b = min(b, s_min[w]);
+            c += s_nb[w];
+        }
+        const unsigned long long nzero = ws->n_zero;
+        const unsigned int bad = ws->nonfinite;
+        out->n_zero = (long long)nzero;
+        out->n_bins = c;
+        out->e_max = c ? a : 0;
+        out->e_min = c ? b : 0;
+        for (int q = 0; q < 3; q++) out->part[q] = 0.0;
+        int go = 1, t = 0;
+        if (bad) {
+            go = 0;
+            out->value = __longlong_as_double(0x7ff8000000000000ll);
+            for (int q = 0; q < 4; q++) out->count[q] = 0;
+            out->status = QDOT_E_NONFINITE;
+            out->flags = 0;
+            out->t = 0;
+            out->bound_rel = out->bound_abs = 0.0;
+        } else if (c == 0) {
+            go = 0;
+            out->value = 0.0;
+            for (int q = 0; q < 3; q++) out->count[q] = 0;
+            out->count[QDOT_PERF] = n;
+            out->status = QDOT_OK;
+            out->flags = QDOT_F_ALL_PERF;
+            out->t = 0;
+            out->bound_rel = out->bound_abs = 0.0;
+        } else {
+            t = floor_log2_ratio(tol, score_mode == 0 ? (unsigned long long)c : 1ull);
+            out->t = t;
+            out->status = QDOT_OK;
+        }
+        s_emax = a;
+        s_t = t;
+        s_go = go;
+        ws->n_zero = 0;
+        ws->nonfinite = 0;
+    }
+    __syncthreads();
+    const int go = s_go;
+    const int e_max = s_emax, t = s_t;
+
+    unsigned long long cc[4] = {0, 0, 0, 0};
+    double bound = 0.0;
+    int unatt = 0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int j = tid + r * CUT_THREADS;
+        if (j >= W) break;
+        int cls = QDOT_PERF;
+        if (go && cnt[r]) {
+            const int k = j + KMIN;
+            // eq. (bin-score-def) with exact bins (u_k = k)
+            const int sigma = ceil_log2_u64(cnt[r]) + k - e_max - t + 1;
+            cls = class_of(sigma, nonstrict);
+            unatt |= sigma >= 52 + (nonstrict ? 1 : 0);
+            cc[cls] += cnt[r];
+            // Thm 3.3 term M_k 2^(k - e_max + 1) eps(class)
+            bound += ldexp((double)cnt[r] * eps_of_class(cls), k - e_max + 1);
+        }
+        ws->lut[j] = (unsigned char)cls;
+        ws->hist[j] = 0ull;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) cc[q] += __shfl_xor(cc[q], m, 64);
+        bound += __shfl_xor(bound, m, 64);
+        unatt |= __shfl_xor(unatt, m, 64);
+    }
+    if (lane == 0) {
+        for (int q = 0; q < 4; q++) s_cnt[wv][q] = cc[q];
+        s_bound[wv] = bound;
+        s_unatt[wv] = unatt;
+    }
+    __syncthreads();
+    if (tid == 0 && go) {
+        unsigned long long tc[4] = {0, 0, 0, 0};
+        double bsum = 0.0;
+        int ua = 0;
+        for (int w = 0; w < NW; w++) {
+            for (int q = 0; q < 4; q++) tc[q] += s_cnt[w][q];
+            bsum += s_bound[w];
+            ua |= s_unatt[w];
+        }
+        tc[QDOT_PERF] += (unsigned long long)out->n_zero;
+        for (int q = 0; q < 4; q++) out->count[q] = (long long)tc[q];
+        out->bound_rel = bsum;
+        out->bound_abs = ldexp(bsum, e_max);
+        int flags = ua ? QDOT_F_UNATTAINABLE : 0;
+        // Thm 3.6: e_max - e_min <= -t - m_single
+        if ((long long)e_max - out->e_min <= -(long long)t - 23) flags |= QDOT_F_THM_ALL_DOUBLE;
+        const bool none_kept = (tc[0] + tc[1] + tc[2]) == 0;
+        if (none_kept) {
+            flags |= QDOT_F_ALL_PERF;
+            out->value = 0.0;
+        }
+        out->flags = flags;
+        ws->e_max = e_max;
+        ws->t = t;
+        ws->c32 = e_max + t + 22;
+        ws->skip = none_kept ? 1 : 0;
+    } else if (tid == 0) {
+        ws->skip = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2 (Alg. 1): per component class -> quantised product (leaf) ->
+// 64-element FP32 tile trees (single and half separately) and compensated
+// FP64 sums -> per-block partials -> last block combines.
+//
+// Leaves (exact powers of two scale them; the FP64 result is multiplied by
+// 2^e_max once at the end):
+//   double: fl64(m_x m_y) * 2^(E_x + E_y - e_max)
+//   single: fl32(fl32(m_x) fl32(m_y)) * 2^(E_x + E_y - c32)
+//   half  : h16(m_x) h16(m_y) * 2^(E_x + E_y - c32)  (22-bit product, exact)
+// with c32 = e_max + t + 22, which keeps every FP32 leaf normal and < 4.
+// ---------------------------------------------------------------------------
+template <bool VEC, int U, bool CLS>
+__global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
+                                               const double *__restrict__ y,
+                                               int64_t n, int key_mode,
+                                               Ws *__restrict__ ws,
+                                               double *__restrict__ partials,
+                                               qdot_result *__restrict__ out,
+                                               unsigned char *__restrict__ cls_out)
+{
+    __shared__ unsigned char lut[W_LUT];
+    __shared__ Acc red[3][BLOCK / 64];
+    __shared__ int s_last;
+
+    const int skip = ws->skip;
+    if (skip && !CLS) return;
+    {
+        const unsigned int *src = reinterpret_cast<const unsigned int *>(ws->lut);
+        unsigned int *dst = reinterpret_cast<unsigned int *>(lut);
+        for (int i = threadIdx.x; i < W_LUT / 4; i += BLOCK) dst[i] = src[i];
+    }
+    const int e_max = ws->e_max;
+    const int c32 = ws->c32;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    Acc aD = {0.0, 0.0}, aS = {0.0, 0.0}, aH = {0.0, 0.0};
+    const int64_t step = (int64_t)gridDim.x * CHUNK * U;
+    for (int64_t base = (int64_t)blockIdx.x * CHUNK * U; base < n; base += step) {
+        double xv[U][4], yv[U][4];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            load4<VEC>(x, i0, n, xv[u]);
+            load4<VEC>(y, i0, n, yv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            float ls[4], lh[4];
+            double ld[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                ls[e] = 0.0f;
+                lh[e] = 0.0f;
+                ld[e] = 0.0;
+                const Comp c = component(xv[u][e], yv[u][e], key_mode);
+                const bool valid = i0 + e < n;
+                const int cls = (c.zero | c.bad | !valid) ? QDOT_PERF : (int)lut[c.slot];
+                if (CLS && valid) cls_out[i0 + e] = (unsigned char)cls;
+                if (cls == QDOT_DOUBLE) {
+                    ld[e] = ldexp(c.neg ? -c.mp : c.mp, c.es - e_max);
+                } else if (cls == QDOT_SINGLE) {
+                    const float a = (float)mant(c.fx);
+                    const float b = (float)mant(c.fy);
+                    const float p = a * b;
+                    ls[e] = ldexpf(c.neg ? -p : p, c.es - c32);
+                } else if (cls == QDOT_HALF) {
+                    const float p = (float)(half_sig(c.fx) * half_sig(c.fy));
+                    lh[e] = ldexpf(c.neg ? -p : p, c.es - c32 - 20);
+                }
+            }
+            if (!skip) {
+                // tile tree levels 1-2 in the lane, 3-6 across the row
+                const float s4 = (ls[0] + ls[1]) + (ls[2] + ls[3]);
+                const float h4 = (lh[0] + lh[1]) + (lh[2] + lh[3]);
+                const float ts = tile_levels_3to6(s4);
+                const float th = tile_levels_3to6(h4);
+                acc_add(aD, (ld[0] + ld[1]) + (ld[2] + ld[3]));
+                if ((lane & 15) == 0) {
+                    acc_add(aS, (double)ts);
+                    acc_add(aH, (double)th);
+                }
+            }
+        }
+    }
+    if (skip) return;
+
+    aD = wave_reduce(aD);
+    aS = wave_reduce(aS);
+    aH = wave_reduce(aH);
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = aD;
+        red[1][wv] = aS;
+        red[2][wv] = aH;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Acc b[3];
+        for (int q = 0; q < 3; q++) {
+            b[q] = red[q][0];
+            for (int w = 1; w < BLOCK / 64; w++) b[q] = acc_merge(b[q], red[q][w]);
+        }
+        double *p = partials + (size_t)blockIdx.x * 6;
+        for (int q = 0; q < 3; q++) {
+            p[2 * q] = b[q].s;
+            p[2 * q + 1] = b[q].c;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned int prev = __hip_atomic_fetch_add(&ws->ticket, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+
+    // Last block: combine every block's partials in a fixed order.
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    Acc c[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) {
+        const double *p = partials + (size_t)b * 6;
+        for (int q = 0; q < 3; q++) c[q] = acc_merge(c[q], Acc{p[2 * q], p[2 * q + 1]});
+    }
+    for (int q = 0; q < 3; q++) c[q] = wave_reduce(c[q]);
+    __syncthreads();
+    if (lane == 0)
+        for (int q = 0; q < 3; q++) red[q][wv] = c[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Acc f[3];
+        for (int q = 0; q < 3; q++) {
+            f[q] = red[q][0];
+            for (int w = 1; w < BLOCK / 64; w++) f[q] = acc_merge(f[q], red[q][w]);
+        }
+        const int t = ws->t;
+        // S = D + 2^(c32 - e_max) (S + H), with c32 - e_max = t + 22
+        Acc tot = f[0];
+        acc_add(tot, ldexp(f[1].s, t + 22));
+        acc_add(tot, ldexp(f[2].s, t + 22));
+        tot.c = tot.c + ldexp(f[1].c + f[2].c, t + 22);
+        const double S = tot.s + tot.c;
+        const double value = ldexp(S, e_max);
+        out->value = value;
+        out->part[QDOT_DOUBLE] = ldexp(f[0].s + f[0].c, e_max);
+        out->part[QDOT_SINGLE] = ldexp(f[1].s + f[1].c, c32);
+        out->part[QDOT_HALF] = ldexp(f[2].s + f[2].c, c32);
+        if (__builtin_isinf(value)) out->flags = out->flags | QDOT_F_OVERFLOW;
+        ws->ticket = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain FP64 dot (baseline): same skeleton, FP64 products and sums.
+// ---------------------------------------------------------------------------
+template <bool VEC, int U>
+__global__ __launch_bounds__(BLOCK) void k_dot64(const double *__restrict__ x,
+                                                 const double *__restrict__ y,
+                                                 int64_t n, Ws *__restrict__ ws,
+                                                 double *__restrict__ partials,
+                                                 double *__restrict__ out)
+{
+    __shared__ double red[BLOCK / 64];
+    __shared__ int s_last;
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+    const int64_t step = (int64_t)gridDim.x * CHUNK * U;
+    for (int64_t base = (int64_t)blockIdx.x * CHUNK * U; base < n; base += step) {
+        double xv[U][4], yv[U][4];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            load4<VEC>(x, i0, n, xv[u]);
+            load4<VEC>(y, i0, n, yv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc = fma(xv[u][e], yv[u][e], acc);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int w = 1; w < BLOCK / 64; w++) b += red[w];
+        partials[blockIdx.x] = b;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned int prev = __hip_atomic_fetch_add(&ws->ticket, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double c = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) c += partials[b];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, 64);
+    __syncthreads();
+    if (lane == 0) red[wv] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double f = red[0];
+        for (int w = 1; w < BLOCK / 64; w++) f += red[w];
+        *out = f;
+        ws->ticket = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+template <int U>
+static hipError_t launch_qdot_u(const Launch &L, const double *x, const double *y,
+                                int64_t n, double tol, const qdot_options &o,
+                                qdot_result *out, unsigned char *cls_out,
+                                long long *hist_out)
+{
+    const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
+    const int64_t groups = (n + (int64_t)CHUNK * U - 1) / ((int64_t)CHUNK * U);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.max_blocks, groups));
+    hipStream_t s = L.stream;
+    if (L.ev) (void)hipEventRecord(L.ev[0], s);
+    if (vec)
+        hipLaunchKernelGGL((k_scan<true, U>), dim3(grid), dim3(BLOCK), 0, s, x, y, n, o.key_mode, L.ws);
+    else
+        hipLaunchKernelGGL((k_scan<false, U>), dim3(grid), dim3(BLOCK), 0, s, x, y, n, o.key_mode, L.ws);
+    if (L.ev) (void)hipEventRecord(L.ev[1], s);
+    hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
+                       o.boundary_mode, n, out, hist_out);
+    if (L.ev) (void)hipEventRecord(L.ev[2], s);
+    if (cls_out) {
+        if (vec)
+            hipLaunchKernelGGL((k_acc<true, U, true>), dim3(grid), dim3(BLOCK), 0, s, x, y, n,
+                               o.key_mode, L.ws, L.partials, out, cls_out);
+        else
+            hipLaunchKernelGGL((k_acc<false, U, true>), dim3(grid), dim3(BLOCK), 0, s, x, y, n,
+                               o.key_mode, L.ws, L.partials, out, cls_out);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_acc<true, U, false>), dim3(grid), dim3(BLOCK), 0, s, x, y, n,
+                               o.key_mode, L.ws, L.partials, out, nullptr);
+        else
+            hipLaunchKernelGGL((k_acc<false, U, false>), dim3(grid), dim3(BLOCK), 0, s, x, y, n,
+                               o.key_mode, L.ws, L.partials, out, nullptr);
+    }
+    if (L.ev) (void)hipEventRecord(L.ev[3], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_t n,
+                       double tol, const qdot_options &o, qdot_result *out,
+                       unsigned char *cls_out, long long *hist_out)
+{
+    switch (L.unroll) {
+    case 1: return launch_qdot_u<1>(L, x, y, n, tol, o, out, cls_out, hist_out);
+    case 4: return launch_qdot_u<4>(L, x, y, n, tol, o, out, cls_out, hist_out);
+    default: return launch_qdot_u<2>(L, x, y, n, tol, o, out, cls_out, hist_out);
+    }
+}
+
+template <int U>
+static hipError_t launch_dot64_u(const Launch &L, const double *x, const double *y,
+                                 int64_t n, double *out)
+{
+    const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
+    const int64_t groups = (n + (int64_t)CHUNK * U - 1) / ((int64_t)CHUNK * U);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.max_blocks, groups));
+    if (L.ev) (void)hipEventRecord(L.ev[0], L.stream);
+    if (vec)
+        hipLaunchKernelGGL((k_dot64<true, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+                           L.ws, L.partials, out);
+    else
+        hipLaunchKernelGGL((k_dot64<false, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+                           L.ws, L.partials, out);
+    if (L.ev) (void)hipEventRecord(L.ev[1], L.stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot64(const Launch &L, const double *x, const double *y, int64_t n,
+                        double *out)
+{
+    switch (L.unroll) {
+    case 1: return launch_dot64_u<1>(L, x, y, n, out);
+    case 4: return launch_dot64_u<4>(L, x, y, n, out);
+    default: return launch_dot64_u<2>(L, x, y, n, out);
+    }
+}
+
+}  // namespace qd

@@ -1,0 +1,29 @@
+// Internal launch interface between the C ABI layer and the kernels.
+#pragma once
+
+#include <algorithm>
+
+#include "qdot_device.hpp"
+
+namespace qd {
+
+struct Launch {
+    hipStream_t stream;
+    Ws *ws;             // device control block of the handle
+    double *partials;   // >= 6 * max_blocks doubles
+    int max_blocks;     // persistent grid cap
+    int unroll;         // 1, 2 or 4 groups of 4 elements in flight per lane
+    hipEvent_t *ev;     // NULL, or events recorded around each kernel
+};
+
+// Enqueue scan -> cutoff -> accumulate for one qdot.  cls_out (n bytes) and
+// hist_out (W int64) are optional debug outputs.
+hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_t n,
+                       double tol, const qdot_options &o, qdot_result *out,
+                       unsigned char *cls_out, long long *hist_out);
+
+// Enqueue the plain FP64 dot; *out receives sum x_i y_i.
+hipError_t launch_dot64(const Launch &L, const double *x, const double *y, int64_t n,
+                        double *out);
+
+}  // namespace qd

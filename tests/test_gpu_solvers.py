@@ -1,0 +1,103 @@
+"""GPU CG / power method / SpMV against the oracle and against each other.
+
+SpMV rows are summed in the same order with the same roundings on both
+sides, so the product must match bit for bit.  CG with qdot must converge in
+the same number of iterations as CG with the FP64 dot (the target of the
+CG study) and as the oracle's CG, up to one iteration where rounding of the
+two inner products lands near the stopping threshold.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+import paper_2105_00115_amd as q  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    handle = q.Qdot(0)
+    yield handle
+    handle.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+@pytest.mark.parametrize("m", [7, 64])
+def test_spmv_bitwise(h, m):
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    x = workloads.normal_vector(m * m, 3)
+    y = torch.empty(m * m, dtype=torch.float64, device="cuda:0")
+    h.spmv(A, dev(x), y)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(y.cpu().numpy(), oracle.spmv(rp, col, val, x))
+
+
+@pytest.mark.parametrize("m", [32, 64, 128])
+def test_cg_iteration_parity(h, m):
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    b = workloads.normal_vector(m * m, 5)
+    bd = dev(b)
+    xq = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    xf = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    rq = h.cg(A, bd, xq, 1e-10, 1e-8, 20000, 1, trace=True)
+    rf = h.cg(A, bd, xf, 1e-10, 1e-8, 20000, 0)
+    assert rq["status"] == q.OK and rf["status"] == q.OK
+    assert abs(rq["iters"] - rf["iters"]) <= 1, (rq["iters"], rf["iters"])
+    assert rq["relres_true"] < 1e-9 and rf["relres_true"] < 1e-9
+    oq = oracle.cg(rp, col, val, b, 1e-10, 1e-8, 20000, 1, want_trace=True)
+    assert abs(oq["iters"] - rq["iters"]) <= 1, (oq["iters"], rq["iters"])
+    # the first qdot (r0 = b exactly) classifies identically
+    t0, o0 = rq["trace"][0], oq["trace"][0]
+    for k in ("count", "n_bins", "e_max", "e_min", "t", "flags"):
+        assert t0[k] == o0[k], k
+    assert abs(t0["value"] - o0["value"]) <= 1e-13 * float(np.dot(b, b))
+    # the solutions agree to the solver tolerance
+    np.testing.assert_allclose(xq.cpu().numpy(), oq["x"], rtol=0,
+                               atol=1e-7 * np.abs(oq["x"]).max())
+
+
+def test_cg_breakdown_when_all_perforated(h):
+    rp, col, val = workloads.poisson2d_csr(16)
+    A = q.Csr(rp, col, val)
+    b = dev(workloads.normal_vector(256, 6))
+    x = torch.zeros(256, dtype=torch.float64, device="cuda:0")
+    r = h.cg(A, b, x, 1e-10, 1e300, 100, 1)
+    assert r["status"] == q.E_BREAKDOWN
+
+
+def test_cg_maxit(h):
+    rp, col, val = workloads.poisson2d_csr(64)
+    A = q.Csr(rp, col, val)
+    b = dev(workloads.normal_vector(4096, 7))
+    x = torch.zeros(4096, dtype=torch.float64, device="cuda:0")
+    r = h.cg(A, b, x, 1e-14, 1e-8, 10, 1)
+    assert r["status"] == q.E_MAXIT and r["iters"] == 10
+
+
+@pytest.mark.parametrize("m", [6, 16])
+def test_power_method(h, m):
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, val)
+    x0 = workloads.unit_vector(m ** 3, 8)
+    iters = 200
+    lam_max = 6.0 + 6.0 * math.cos(math.pi / (m + 1))
+    for use_qdot in (1, 0):
+        xd = dev(x0)
+        r = h.power(A, xd, iters, 1e-6, use_qdot)
+        o = oracle.power(rp, col, val, x0, iters, 1e-6, use_qdot)
+        assert r["status"] == q.OK
+        np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
+        assert r["lambda"] <= lam_max * (1 + 1e-12)

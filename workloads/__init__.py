@@ -40,6 +40,7 @@ __all__ = [
     "laplacian3d_csr",
     "ragged_batch",
     "cg_grid_sides",
+    "log_uniform_pair_torch",
 ]
 
 
@@ -177,3 +178,24 @@ def cg_grid_sides(count: int, seed: int, lo_exp: float = 5.0,
     """Grid sides m_j = round(2**U[lo_exp, hi_exp]) for a batch of 2D CG systems."""
     g = rng(seed)
     return np.rint(2.0 ** g.uniform(lo_exp, hi_exp, count)).astype(np.int64)
+
+
+def log_uniform_pair_torch(n: int, seed: int, device="cuda:0"):
+    """Same law as ``log_uniform_pair`` drawn on the device with a seeded
+    torch generator (fast for n = 2**27; a different random stream from the
+    numpy generator)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    out = []
+    for _ in range(2):
+        u = torch.rand(n, generator=g, dtype=torch.float64, device=device)
+        u.mul_(40.0).sub_(20.0)
+        v = torch.pow(10.0, u)
+        del u
+        s = torch.randint(0, 2, (n,), generator=g, device=device, dtype=torch.int8)
+        v.mul_(1.0 - 2.0 * s.to(torch.float64))
+        del s
+        out.append(v)
+    return out[0], out[1]
