@@ -126,12 +126,20 @@ typedef struct qdot_cg_result {
 } qdot_cg_result;
 
 /* ---- launch configuration (autotuner) ---------------------------------- */
+/* Launch shape of the two streaming passes.  Grids are persistent:
+ * blocks_per_cu * CUs blocks of 256 threads, each thread keeping `unroll`
+ * groups of 4 consecutive components in flight (1, 2 or 4).  No setting
+ * changes a class, a count or an FP32 tile sum: the 64-element tiles are
+ * fixed by the index order. */
 typedef struct qdot_tune {
-    int32_t blocks_per_cu; /* persistent grid = blocks_per_cu * CUs (>= 1) */
-    int32_t unroll;        /* 1, 2 or 4 groups of 4 elements in flight per
-                              thread; never changes a result bit of the
-                              integer outputs or of any FP32 tile sum */
+    int32_t scan_blocks_per_cu; /* exponent scan, 1..16 */
+    int32_t scan_unroll;
+    int32_t acc_blocks_per_cu;  /* accumulate pass and FP64 dot, 1..16 */
+    int32_t acc_unroll;
 } qdot_tune;
+
+/* Tuning is kept per size bucket: n < 2^16, < 2^20, < 2^24, >= 2^24. */
+#define QDOT_TUNE_BUCKETS 4
 
 typedef struct qdot_handle qdot_handle;
 
@@ -151,19 +159,28 @@ QDOT_API const char *qdot_last_error(const qdot_handle *h);
 QDOT_API int32_t qdot_device_info(const qdot_handle *h, int32_t *device,
                          int32_t *num_cus);
 
-/* Set / get the launch configuration (NULL cfg in set = defaults). */
-QDOT_API int32_t qdot_set_tune(qdot_handle *h, const qdot_tune *cfg);
-QDOT_API int32_t qdot_get_tune(const qdot_handle *h, qdot_tune *cfg);
+/* Set / get the launch configuration of one size bucket (0..3, or -1 for
+ * all buckets in qdot_set_tune).  NULL cfg in set restores the defaults. */
+QDOT_API int32_t qdot_set_tune(qdot_handle *h, int32_t bucket, const qdot_tune *cfg);
+QDOT_API int32_t qdot_get_tune(const qdot_handle *h, int32_t bucket, qdot_tune *cfg);
+
+/* Load tuned configurations from a text file written by the autotuner: one
+ * line per bucket, "bucket scan_bpc scan_unroll acc_bpc acc_unroll", '#'
+ * starts a comment.  Invalid lines are rejected with QDOT_E_INVAL and leave
+ * the handle unchanged.  qdot_create also loads the file named by the
+ * environment variable QDOT_TUNE_FILE when it is set. */
+QDOT_API int32_t qdot_load_tune(qdot_handle *h, const char *path);
 
 /* Kernel timing (diagnostics).  While enabled, every qdot and FP64-dot call
  * on this handle records HIP events on its stream around each kernel it
  * launches (not allowed while the stream is being captured into a graph).
  * qdot_timing_read synchronises the recorded events and returns the summed
- * durations in milliseconds of the scan, cutoff and accumulate kernels of
- * qdot (ms[0..2]) and of the FP64 dot kernel (ms[3]), the number of qdot
- * and FP64-dot calls timed (calls[0..1]), then clears the record. */
+ * durations in milliseconds of the scan, cutoff, accumulate and finalize
+ * kernels of qdot (ms[0..3]) and of the FP64 dot (ms[4], both of its
+ * kernels), the number of qdot and FP64-dot calls timed (calls[0..1]), then
+ * clears the record. */
 QDOT_API int32_t qdot_timing_enable(qdot_handle *h, int32_t enable);
-QDOT_API int32_t qdot_timing_read(qdot_handle *h, double ms[4], int32_t calls[2]);
+QDOT_API int32_t qdot_timing_read(qdot_handle *h, double ms[5], int32_t calls[2]);
 
 /* qdot(x, y, eps) -- Alg. 3: parameter selection (Alg. 2) then the
  * computation phase (Alg. 1).

@@ -69,7 +69,15 @@ class QdotCgResult(C.Structure):
 
 
 class QdotTune(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int32), ("unroll", C.c_int32)]
+    _fields_ = [("scan_blocks_per_cu", C.c_int32), ("scan_unroll", C.c_int32),
+                ("acc_blocks_per_cu", C.c_int32), ("acc_unroll", C.c_int32)]
+
+
+TUNE_BUCKETS = 4  # n < 2^16, < 2^20, < 2^24, >= 2^24
+
+
+def tune_bucket(n: int) -> int:
+    return 0 if n < 1 << 16 else 1 if n < 1 << 20 else 2 if n < 1 << 24 else 3
 
 
 RESULT_BYTES = C.sizeof(QdotResult)
@@ -83,8 +91,9 @@ SIGNATURES = [
     ("qdot_destroy", _i32, [_vp]),
     ("qdot_last_error", C.c_char_p, [_vp]),
     ("qdot_device_info", _i32, [_vp, C.POINTER(_i32), C.POINTER(_i32)]),
-    ("qdot_set_tune", _i32, [_vp, C.POINTER(QdotTune)]),
-    ("qdot_get_tune", _i32, [_vp, C.POINTER(QdotTune)]),
+    ("qdot_set_tune", _i32, [_vp, _i32, C.POINTER(QdotTune)]),
+    ("qdot_get_tune", _i32, [_vp, _i32, C.POINTER(QdotTune)]),
+    ("qdot_load_tune", _i32, [_vp, C.c_char_p]),
     ("qdot_timing_enable", _i32, [_vp, _i32]),
     ("qdot_timing_read", _i32, [_vp, C.POINTER(_d), C.POINTER(_i32)]),
     ("qdot_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp]),
@@ -172,15 +181,30 @@ class Csr:
                          self.col.data_ptr(), self.val.data_ptr())
 
 
-class Qdot:
-    """A library handle bound to one device."""
+def tuned_file(device: int = 0):
+    """Autotuner output for this device model, if the tuner has been run."""
+    import torch
+    props = torch.cuda.get_device_properties(device)
+    arch = props.gcnArchName.split(":")[0]
+    return os.path.join(PKG, "tune", f"{arch}_{props.multi_processor_count}cu.txt")
 
-    def __init__(self, device: int = 0):
+
+class Qdot:
+    """A library handle bound to one device.  Loads the autotuned launch
+    shapes for the device when ``tune/<arch>_<cus>cu.txt`` exists."""
+
+    def __init__(self, device: int = 0, load_tuned: bool = True):
         self._h = C.c_void_p()
         st = lib().qdot_create(C.byref(self._h), int(device))
         if st != OK:
             raise QdotError(st, "qdot_create")
         self.device = device
+        self.tune_file = None
+        if load_tuned and not os.environ.get("QDOT_TUNE_FILE"):
+            path = tuned_file(device)
+            if path is not None and os.path.exists(path):
+                self.load_tune(path)
+                self.tune_file = path
 
     def close(self):
         if self._h:
@@ -202,27 +226,40 @@ class Qdot:
         lib().qdot_device_info(self._h, C.byref(d), C.byref(c))
         return d.value, c.value
 
-    def set_tune(self, blocks_per_cu: int, unroll: int):
-        st = lib().qdot_set_tune(self._h, C.byref(QdotTune(blocks_per_cu, unroll)))
+    def set_tune(self, bucket: int, scan_bpc: int, scan_unroll: int, acc_bpc: int,
+                 acc_unroll: int):
+        """bucket -1 sets all size buckets."""
+        cfg = QdotTune(scan_bpc, scan_unroll, acc_bpc, acc_unroll)
+        st = lib().qdot_set_tune(self._h, int(bucket), C.byref(cfg))
         if st != OK:
             self._raise(st, "qdot_set_tune")
 
-    def get_tune(self):
+    def reset_tune(self):
+        lib().qdot_set_tune(self._h, -1, None)
+
+    def get_tune(self, bucket: int):
         t = QdotTune()
-        lib().qdot_get_tune(self._h, C.byref(t))
-        return t.blocks_per_cu, t.unroll
+        st = lib().qdot_get_tune(self._h, int(bucket), C.byref(t))
+        if st != OK:
+            raise QdotError(st, "qdot_get_tune")
+        return (t.scan_blocks_per_cu, t.scan_unroll, t.acc_blocks_per_cu, t.acc_unroll)
+
+    def load_tune(self, path: str):
+        st = lib().qdot_load_tune(self._h, os.fsencode(path))
+        if st != OK:
+            self._raise(st, "qdot_load_tune")
 
     def timing_enable(self, on: bool = True):
         lib().qdot_timing_enable(self._h, 1 if on else 0)
 
     def timing_read(self) -> dict:
-        ms = (C.c_double * 4)()
+        ms = (C.c_double * 5)()
         calls = (C.c_int32 * 2)()
         st = lib().qdot_timing_read(self._h, ms, calls)
         if st != OK:
             self._raise(st, "qdot_timing_read")
-        return {"scan_ms": ms[0], "cut_ms": ms[1], "acc_ms": ms[2], "dot64_ms": ms[3],
-                "qdot_calls": calls[0], "dot64_calls": calls[1]}
+        return {"scan_ms": ms[0], "cut_ms": ms[1], "acc_ms": ms[2], "fin_ms": ms[3],
+                "dot64_ms": ms[4], "qdot_calls": calls[0], "dot64_calls": calls[1]}
 
     # ---- qdot --------------------------------------------------------------
     def qdot(self, x, y, tol, opt=None, stream=None) -> dict:

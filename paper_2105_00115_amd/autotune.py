@@ -1,0 +1,121 @@
+"""Autotuner for the qdot launch shapes.
+
+For each size bucket (n < 2^16, < 2^20, < 2^24, >= 2^24) it times the exponent
+scan and the accumulate pass over persistent-grid sizes (blocks per CU) and
+unroll depths, with the library's own HIP-event kernel timing, and keeps the
+fastest pair.  A configuration is only eligible if it reproduces the
+reference run's integer outputs (histogram, classes, counts, t, flags) bit
+for bit; the tile structure makes that hold for every shape, and the tuner
+checks it rather than assuming it.
+
+The result is a text file that ``qdot_load_tune`` reads; ``Qdot()`` loads
+``tune/<arch>_<cus>cu.txt`` next to this module when it exists.
+
+    python -m paper_2105_00115_amd.autotune [--out PATH] [--reps 20]
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+BUCKET_N = [1 << 15, 1 << 19, 1 << 23, 1 << 27]
+BPC = (1, 2, 4, 8, 16)
+UNROLL = (1, 2, 4)
+
+
+def default_path(arch: str, cus: int) -> str:
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune",
+                        f"{arch}_{cus}cu.txt")
+
+
+def _time_config(h, x, y, tol, out, cfg, reps):
+    h.set_tune(-1, *cfg)
+    for _ in range(3):
+        h.qdot_async(x, y, tol, out)
+    import torch
+    torch.cuda.synchronize()
+    h.timing_read()
+    h.timing_enable(True)
+    for _ in range(reps):
+        h.qdot_async(x, y, tol, out)
+    torch.cuda.synchronize()
+    h.timing_enable(False)
+    t = h.timing_read()
+    c = t["qdot_calls"]
+    return (t["scan_ms"] / c, t["cut_ms"] / c, t["acc_ms"] / c, t["fin_ms"] / c)
+
+
+def tune(reps: int = 20, seed: int = 7, tol: float = 1e-6, log=print):
+    import torch
+
+    import paper_2105_00115_amd as q
+    import workloads
+
+    h = q.Qdot(0)
+    h.reset_tune()
+    dev = "cuda:0"
+    out = torch.zeros(q.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    chosen = []
+    for b, n in enumerate(BUCKET_N):
+        x, y = workloads.log_uniform_pair_torch(n, seed + b, dev)
+        ref_cls, ref_hist, ref = h.qdot_classes(x, y, tol)
+        results = {}
+        for bpc in BPC:
+            for u in UNROLL:
+                cfg = (bpc, u, bpc, u)
+                results[cfg] = _time_config(h, x, y, tol, out, cfg, reps)
+                r = q.parse_results(out)[0]
+                if (r["count"], r["t"], r["flags"]) != (ref["count"], ref["t"], ref["flags"]):
+                    raise RuntimeError(f"config {cfg} changed the integer outputs")
+        best_scan = min(results, key=lambda c: results[c][0])[:2]
+        best_acc = min(results, key=lambda c: results[c][2])[2:]
+        mixed = best_scan + best_acc
+        if mixed not in results:
+            results[mixed] = _time_config(h, x, y, tol, out, mixed, reps)
+        best = min(results, key=lambda c: sum(results[c]))
+        h.set_tune(-1, *best)
+        cls, hist, r = h.qdot_classes(x, y, tol)
+        if not (torch.equal(cls, ref_cls) and torch.equal(hist, ref_hist)
+                and r["count"] == ref["count"]):
+            raise RuntimeError(f"config {best} changed the classes")
+        t = results[best]
+        log(f"bucket {b} n={n}: best {best} scan {t[0]*1e3:.1f} us cut {t[1]*1e3:.1f} us "
+            f"acc {t[2]*1e3:.1f} us fin {t[3]*1e3:.1f} us")
+        chosen.append((b, n, best, t))
+        del x, y
+    return h, chosen
+
+
+def write(path, chosen, arch, cus):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        f.write(f"# qdot launch shapes for {arch} with {cus} CUs, written by "
+                f"python -m paper_2105_00115_amd.autotune on {time.strftime('%Y-%m-%d')}\n")
+        f.write("# bucket scan_blocks_per_cu scan_unroll acc_blocks_per_cu acc_unroll"
+                "   (measured n, scan/cut/acc/fin us)\n")
+        for b, n, cfg, t in chosen:
+            f.write(f"{b} {cfg[0]} {cfg[1]} {cfg[2]} {cfg[3]}   # n={n} "
+                    f"{t[0]*1e3:.1f}/{t[1]*1e3:.1f}/{t[2]*1e3:.1f}/{t[3]*1e3:.1f}\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args(argv)
+    import torch
+
+    props = torch.cuda.get_device_properties(0)
+    arch = props.gcnArchName.split(":")[0]
+    cus = props.multi_processor_count
+    h, chosen = tune(a.reps, log=lambda m: print(m, flush=True))
+    path = a.out or default_path(arch, cus)
+    write(path, chosen, arch, cus)
+    h.load_tune(path)  # the file must load back
+    print(f"wrote {path}", flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

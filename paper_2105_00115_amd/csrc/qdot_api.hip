@@ -1,5 +1,7 @@
 // C ABI: handle management and the single-vector qdot entry points.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "qdot_handle.hpp"
@@ -17,14 +19,38 @@ int32_t hip_fail(qdot_handle *h, hipError_t e, const char *where)
     return fail(h, QDOT_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-Launch make_launch(qdot_handle *h, hipStream_t s)
+static int bucket_of(int64_t n)
 {
+    return n < ((int64_t)1 << 16) ? 0 : n < ((int64_t)1 << 20) ? 1 : n < ((int64_t)1 << 24) ? 2 : 3;
+}
+
+qdot_tune default_tune(int bucket)
+{
+    // measured on MI355X (256 CUs) at n = 2^27; small sizes keep both passes
+    // on the same block -> chunk mapping so the second pass finds the data
+    // in the same XCD's L2
+    if (bucket < 3) return qdot_tune{2, 1, 2, 1};
+    return qdot_tune{2, 1, 2, 2};
+}
+
+bool tune_ok(const qdot_tune &t)
+{
+    auto u_ok = [](int u) { return u == 1 || u == 2 || u == 4; };
+    return t.scan_blocks_per_cu >= 1 && t.scan_blocks_per_cu <= 16 && t.acc_blocks_per_cu >= 1 &&
+           t.acc_blocks_per_cu <= 16 && u_ok(t.scan_unroll) && u_ok(t.acc_unroll);
+}
+
+Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n)
+{
+    const qdot_tune &t = h->tune[bucket_of(n)];
     Launch L;
     L.stream = s;
     L.ws = h->ws;
     L.partials = h->partials;
-    L.max_blocks = std::min(h->partial_blocks, std::max(1, h->tune.blocks_per_cu) * h->num_cus);
-    L.unroll = h->tune.unroll;
+    L.scan_blocks = t.scan_blocks_per_cu * h->num_cus;
+    L.scan_unroll = t.scan_unroll;
+    L.acc_blocks = std::min(h->partial_blocks, t.acc_blocks_per_cu * h->num_cus);
+    L.acc_unroll = t.acc_unroll;
     L.ev = nullptr;
     return L;
 }
@@ -32,7 +58,7 @@ Launch make_launch(qdot_handle *h, hipStream_t s)
 hipEvent_t *take_events(qdot_handle *h, int kind)
 {
     if (!h->timing) return nullptr;
-    const size_t k = kind == 0 ? 4 : 2;
+    const size_t k = kind == 0 ? 5 : 2;
     while (h->ev_pool.size() < h->ev_used + k) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
@@ -87,6 +113,7 @@ int32_t qdot_create(qdot_handle **out, int32_t device)
         return QDOT_E_DEVICE;
     }
     h->partial_blocks = 16 * h->num_cus;
+    for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) h->tune[b] = default_tune(b);
     bool ok = hipMalloc((void **)&h->ws, sizeof(Ws)) == hipSuccess &&
               hipMalloc((void **)&h->partials, sizeof(double) * 6 * h->partial_blocks) == hipSuccess &&
               hipMalloc((void **)&h->dev_res, sizeof(qdot_result)) == hipSuccess &&
@@ -97,6 +124,7 @@ int32_t qdot_create(qdot_handle **out, int32_t device)
         qdot_destroy(h);
         return QDOT_E_NOMEM;
     }
+    if (const char *p = std::getenv("QDOT_TUNE_FILE")) (void)qdot_load_tune(h, p);
     *out = h;
     return QDOT_OK;
 }
@@ -130,22 +158,49 @@ int32_t qdot_device_info(const qdot_handle *h, int32_t *device, int32_t *num_cus
     return QDOT_OK;
 }
 
-int32_t qdot_set_tune(qdot_handle *h, const qdot_tune *cfg)
+int32_t qdot_set_tune(qdot_handle *h, int32_t bucket, const qdot_tune *cfg)
 {
     if (!h) return QDOT_E_INVAL;
-    qdot_tune t = {4, 2};
-    if (cfg) t = *cfg;
-    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16 ||
-        !(t.unroll == 1 || t.unroll == 2 || t.unroll == 4))
-        return fail(h, QDOT_E_INVAL, "tune out of range (blocks_per_cu 1..16, unroll 1/2/4)");
-    h->tune = t;
+    if (bucket < -1 || bucket >= QDOT_TUNE_BUCKETS) return fail(h, QDOT_E_INVAL, "bad bucket");
+    for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) {
+        if (bucket != -1 && b != bucket) continue;
+        const qdot_tune t = cfg ? *cfg : default_tune(b);
+        if (!tune_ok(t))
+            return fail(h, QDOT_E_INVAL, "tune out of range (blocks_per_cu 1..16, unroll 1/2/4)");
+        h->tune[b] = t;
+    }
     return QDOT_OK;
 }
 
-int32_t qdot_get_tune(const qdot_handle *h, qdot_tune *cfg)
+int32_t qdot_get_tune(const qdot_handle *h, int32_t bucket, qdot_tune *cfg)
 {
-    if (!h || !cfg) return QDOT_E_INVAL;
-    *cfg = h->tune;
+    if (!h || !cfg || bucket < 0 || bucket >= QDOT_TUNE_BUCKETS) return QDOT_E_INVAL;
+    *cfg = h->tune[bucket];
+    return QDOT_OK;
+}
+
+int32_t qdot_load_tune(qdot_handle *h, const char *path)
+{
+    if (!h || !path) return QDOT_E_INVAL;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(h, QDOT_E_INVAL, std::string("cannot open tune file ") + path);
+    qdot_tune t[QDOT_TUNE_BUCKETS];
+    for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) t[b] = h->tune[b];
+    char line[256];
+    bool ok = true;
+    while (ok && std::fgets(line, sizeof line, f)) {
+        char *hash = std::strchr(line, '#');
+        if (hash) *hash = 0;
+        int b, v[4];
+        const int got = std::sscanf(line, "%d %d %d %d %d", &b, &v[0], &v[1], &v[2], &v[3]);
+        if (got <= 0) continue;  // blank or comment
+        const qdot_tune c = {v[0], v[1], v[2], v[3]};
+        if (got != 5 || b < 0 || b >= QDOT_TUNE_BUCKETS || !tune_ok(c)) ok = false;
+        else t[b] = c;
+    }
+    std::fclose(f);
+    if (!ok) return fail(h, QDOT_E_INVAL, std::string("malformed tune file ") + path);
+    for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) h->tune[b] = t[b];
     return QDOT_OK;
 }
 
@@ -157,7 +212,7 @@ int32_t qdot_async(qdot_handle *h, const double *x, const double *y, int64_t n, 
     if (st != QDOT_OK) return st;
     if (!dev_out) return fail(h, QDOT_E_INVAL, "dev_out is NULL");
     DeviceGuard g(h->device);
-    Launch L = make_launch(h, (hipStream_t)stream);
+    Launch L = make_launch(h, (hipStream_t)stream, n);
     L.ev = take_events(h, 0);
     hipError_t e = launch_qdot(L, x, y, n, tol, o, dev_out, nullptr, nullptr);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot launch");
@@ -188,7 +243,7 @@ int32_t qdot_classes_async(qdot_handle *h, const double *x, const double *y, int
     if (st != QDOT_OK) return st;
     if (!dev_out || (n > 0 && !dev_cls)) return fail(h, QDOT_E_INVAL, "NULL output");
     DeviceGuard g(h->device);
-    hipError_t e = launch_qdot(make_launch(h, (hipStream_t)stream), x, y, n, tol, o, dev_out,
+    hipError_t e = launch_qdot(make_launch(h, (hipStream_t)stream, n), x, y, n, tol, o, dev_out,
                                dev_cls, (long long *)dev_hist);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot_classes launch");
 }
@@ -200,7 +255,7 @@ int32_t qdot_fp64_dot_async(qdot_handle *h, const double *x, const double *y, in
     if (n < 0 || (n > 0 && (!x || !y)) || !dev_out) return fail(h, QDOT_E_INVAL, "bad argument");
     if (((uintptr_t)x | (uintptr_t)y) & 7) return fail(h, QDOT_E_INVAL, "vectors not 8-byte aligned");
     DeviceGuard g(h->device);
-    Launch L = make_launch(h, (hipStream_t)stream);
+    Launch L = make_launch(h, (hipStream_t)stream, n);
     L.ev = take_events(h, 1);
     hipError_t e = launch_dot64(L, x, y, n, dev_out);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "fp64 dot launch");
@@ -213,22 +268,22 @@ int32_t qdot_timing_enable(qdot_handle *h, int32_t enable)
     return QDOT_OK;
 }
 
-int32_t qdot_timing_read(qdot_handle *h, double ms[4], int32_t calls[2])
+int32_t qdot_timing_read(qdot_handle *h, double ms[5], int32_t calls[2])
 {
     if (!h || !ms || !calls) return QDOT_E_INVAL;
     DeviceGuard g(h->device);
-    for (int i = 0; i < 4; i++) ms[i] = 0.0;
+    for (int i = 0; i < 5; i++) ms[i] = 0.0;
     calls[0] = calls[1] = 0;
     size_t at = 0;
     hipError_t e = hipSuccess;
     for (int kind : h->ev_kind) {
         hipEvent_t *ev = h->ev_pool.data() + at;
-        const int k = kind == 0 ? 4 : 2;
+        const int k = kind == 0 ? 5 : 2;
         if (e == hipSuccess) e = hipEventSynchronize(ev[k - 1]);
         for (int j = 0; j + 1 < k && e == hipSuccess; j++) {
             float t = 0.0f;
             e = hipEventElapsedTime(&t, ev[j], ev[j + 1]);
-            ms[kind == 0 ? j : 3] += t;
+            ms[kind == 0 ? j : 4] += t;
         }
         calls[kind]++;
         at += k;

@@ -18,7 +18,9 @@ namespace qd {
 constexpr int KMIN = -2148;
 constexpr int KMAX = 2047;
 constexpr int W = KMAX - KMIN + 1;          // 4196 histogram slots
-constexpr int W_LUT = (W + 15) / 16 * 16;   // class table, padded
+constexpr int ZERO_SLOT = W;                // class-table slot of zero products
+constexpr int W_LUT = (W + 1 + 15) / 16 * 16;
+constexpr int HIST_COPIES = 8;              // one global histogram per XCD
 
 constexpr int BLOCK = 256;                  // threads per block (4 waves)
 constexpr int EPT = 4;                      // consecutive elements per lane
@@ -31,20 +33,24 @@ constexpr uint64_t ONE_BITS = 0x3ff0000000000000ull;
 
 // Control block in device memory, one per handle.
 struct Ws {
-    unsigned long long hist[W];  // pass-1 exponent histogram
+    unsigned long long hist[HIST_COPIES][W]; // pass-1 exponent histograms
     unsigned long long n_zero;   // zero products seen by pass 1
     unsigned int nonfinite;      // any Inf/NaN seen by pass 1
-    unsigned int ticket;         // last-block election of pass 2
+    unsigned int pad0;
     // produced by the cutoff kernel for pass 2
     int e_max;
     int t;
     int c32;                     // exponent offset of FP32 leaves
     int skip;                    // nothing to accumulate (result final)
-    unsigned char lut[W_LUT];    // class of every key slot
+    int flags;                   // result flags known after selection
+    int pad1[3];
+    unsigned char lut[W_LUT];    // class of every key slot (+ zero slot)
 };
 
 // One operand split into unbiased exponent and 52-bit fraction of its
-// normalised significand m = 1.frac in [1, 2).
+// normalised significand m = 1.frac in [1, 2).  General path (subnormals
+// included); the kernels call it only for operands whose biased exponent
+// field is zero.
 struct Split {
     int e;
     uint64_t frac;
@@ -55,7 +61,7 @@ __device__ __forceinline__ Split split_bits(uint64_t b)
     Split s;
     const uint32_t code = (uint32_t)(b >> 52) & 0x7ffu;
     const uint64_t f = b & FRAC_MASK;
-    if (__builtin_expect(code != 0, 1)) {
+    if (code != 0) {
         s.e = (int)code - 1023;
         s.frac = f;
     } else {
@@ -72,15 +78,22 @@ __device__ __forceinline__ double mant(uint64_t frac)
     return __longlong_as_double((long long)(frac | ONE_BITS));
 }
 
-// Everything the kernels need to know about one component.
+// One component x_i, y_i reduced to what both passes need:
+//   es   = E(x) + E(y)
+//   mx, my the significands in [1, 2), mp = fl64(mx * my) in [1, 4)
+//   slot = key - KMIN (ZERO_SLOT for a zero product)
+//   sgn  = sign bit of x*y in bit 31
+// Fast path: both biased exponent fields in 1..2046, all 32-bit integer
+// work on the high words.  Zero and subnormal operands (field 0) take a
+// rare divergent branch.  Non-finite operands (field 2047) are reported by
+// `bad`; their slot is ZERO_SLOT.
 struct Comp {
-    int es;       // E(x) + E(y)
-    int slot;     // key - KMIN (0 for zero / non-finite components)
-    bool zero;    // x == 0 or y == 0
-    bool bad;     // x or y is Inf/NaN
-    bool neg;     // sign of x*y
-    uint64_t fx, fy;
-    double mp;    // fl64(m_x * m_y) in [1, 4)
+    int es;
+    int slot;
+    uint32_t sgn;
+    bool zero;
+    bool bad;
+    double mx, my, mp;
 };
 
 __device__ __forceinline__ Comp component(double x, double y, int key_mode)
@@ -88,30 +101,35 @@ __device__ __forceinline__ Comp component(double x, double y, int key_mode)
     Comp c;
     const uint64_t bx = (uint64_t)__double_as_longlong(x);
     const uint64_t by = (uint64_t)__double_as_longlong(y);
-    c.zero = ((bx << 1) == 0) | ((by << 1) == 0);
-    c.bad = (((bx >> 52) & 0x7ff) == 0x7ff) | (((by >> 52) & 0x7ff) == 0x7ff);
-    c.neg = ((bx ^ by) >> 63) != 0;
-    const Split sx = split_bits(bx);
-    const Split sy = split_bits(by);
-    c.fx = sx.frac;
-    c.fy = sy.frac;
-    c.es = sx.e + sy.e;
-    c.mp = mant(sx.frac) * mant(sy.frac);
+    const uint32_t hx = (uint32_t)(bx >> 32), hy = (uint32_t)(by >> 32);
+    const uint32_t cx = (hx >> 20) & 0x7ffu, cy = (hy >> 20) & 0x7ffu;
+    c.sgn = (hx ^ hy) & 0x80000000u;
+    c.mx = __longlong_as_double((long long)((bx & FRAC_MASK) | ONE_BITS));
+    c.my = __longlong_as_double((long long)((by & FRAC_MASK) | ONE_BITS));
+    c.es = (int)(cx + cy) - 2046;
+    c.zero = false;
+    c.bad = max(cx, cy) == 0x7ffu;
+    if (__builtin_expect(min(cx, cy) == 0, 0)) {
+        c.zero = ((bx << 1) == 0) | ((by << 1) == 0);
+        const Split sx = split_bits(bx), sy = split_bits(by);
+        c.mx = mant(sx.frac);
+        c.my = mant(sy.frac);
+        c.es = sx.e + sy.e;
+    }
+    c.mp = c.mx * c.my;
     const int carry = (key_mode == 0 && c.mp >= 2.0) ? 1 : 0;
-    const bool live = !(c.zero | c.bad);
-    c.slot = live ? (c.es + carry - KMIN) : 0;
+    c.slot = (c.zero | c.bad) ? ZERO_SLOT : (c.es + carry - KMIN);
     return c;
 }
 
-// Binary16 significand of 1.frac, round to nearest even straight from the
-// 52-bit fraction: an integer in [1024, 2048].
-__device__ __forceinline__ uint32_t half_sig(uint64_t frac)
+// Binary16 significand of m in [1, 2), round to nearest even in one step
+// straight from FP64: m + 2^42 has an ulp of 2^-10, so the addition rounds
+// m to the nearest multiple of 2^-10 (ties to even) and the subtraction is
+// exact.  Result in [1, 2].
+__device__ __forceinline__ double half_round(double m)
 {
-    const uint32_t q = (uint32_t)(frac >> 42);
-    const uint64_t rem = frac & ((1ull << 42) - 1);
-    const uint64_t mid = 1ull << 41;
-    const uint32_t up = (rem > mid) | ((rem == mid) & (q & 1u));
-    return 1024u + q + up;
+    const double big = 0x1p42;
+    return (m + big) - big;
 }
 
 // ---- cross-lane moves (DPP, within 16-lane rows) -------------------------

@@ -14,7 +14,7 @@ struct qdot_handle {
     int partial_blocks = 0;          // capacity in blocks
     qdot_result *dev_res = nullptr;  // device result slot for the sync API
     qdot_result *host_res = nullptr; // pinned host mirror
-    qdot_tune tune = {4, 2};
+    qdot_tune tune[QDOT_TUNE_BUCKETS];
     std::string err;
 
     // scratch for the solver drivers, grown on demand
@@ -28,7 +28,7 @@ struct qdot_handle {
     // kernel timing (diagnostics)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool; // created events, reused after each read
-    std::vector<int> ev_kind;        // per timed call: 0 qdot (4 events), 1 dot (2)
+    std::vector<int> ev_kind;        // per timed call: 0 qdot (5 events), 1 dot (2)
     size_t ev_used = 0;
 };
 
@@ -52,8 +52,10 @@ struct DeviceGuard {
 
 int32_t fail(qdot_handle *h, int32_t code, const std::string &msg);
 int32_t hip_fail(qdot_handle *h, hipError_t e, const char *where);
-Launch make_launch(qdot_handle *h, hipStream_t s);
-// Events for one timed call of `kind` (0: qdot, 4 events; 1: FP64 dot, 2),
+Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n);
+qdot_tune default_tune(int bucket);
+bool tune_ok(const qdot_tune &t);
+// Events for one timed call of `kind` (0: qdot, 5 events; 1: FP64 dot, 2),
 // or NULL when timing is off or events cannot be created.
 hipEvent_t *take_events(qdot_handle *h, int kind);
 bool options_ok(const qdot_options &o);

@@ -15,24 +15,63 @@
 namespace qd {
 
 template <bool VEC>
-__device__ __forceinline__ void load4(const double *__restrict__ p, int64_t i0,
-                                      int64_t n, double v[4])
+__device__ __forceinline__ void load4_full(const double *__restrict__ p, double v[4])
 {
-    if (i0 + 4 <= n) {
-        if (VEC) {
-            const double2 a = *reinterpret_cast<const double2 *>(p + i0);
-            const double2 b = *reinterpret_cast<const double2 *>(p + i0 + 2);
-            v[0] = a.x;
-            v[1] = a.y;
-            v[2] = b.x;
-            v[3] = b.y;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; e++) v[e] = p[i0 + e];
-        }
+    if (VEC) {
+        const double2 a = *reinterpret_cast<const double2 *>(p);
+        const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = b.x;
+        v[3] = b.y;
     } else {
 #pragma unroll
-        for (int e = 0; e < 4; e++) v[e] = (i0 + e < n) ? p[i0 + e] : 0.0;
+        for (int e = 0; e < 4; e++) v[e] = p[e];
+    }
+}
+
+__device__ __forceinline__ void load4_tail(const double *__restrict__ p, int lim, double v[4])
+{
+#pragma unroll
+    for (int e = 0; e < 4; e++) v[e] = e < lim ? p[e] : 0.0;
+}
+
+// Grid-stride walk over groups of CHUNK * U consecutive components.  Whole
+// groups are loaded without bounds checks; the single partial group (met by
+// one block at most) is loaded with per-lane limits.  body(xv, yv, i0, lim)
+// sees 4 consecutive components i0..i0+3 of which the first `lim` are real;
+// it is called with every lane of the block active.
+template <bool VEC, int U, class Body>
+__device__ __forceinline__ void stream_groups(const double *__restrict__ x,
+                                              const double *__restrict__ y, int64_t n,
+                                              Body &&body)
+{
+    const int64_t group = (int64_t)CHUNK * U;
+    const int64_t step = (int64_t)gridDim.x * group;
+    int64_t base = (int64_t)blockIdx.x * group;
+    for (; base + group <= n; base += step) {
+        double xv[U][4], yv[U][4];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            load4_full<VEC>(x + i0, xv[u]);
+            load4_full<VEC>(y + i0, yv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            body(xv[u], yv[u], base + (int64_t)u * CHUNK + threadIdx.x * EPT, 4);
+    }
+    if (base < n) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            const int64_t left = n - i0;
+            const int lim = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
+            double xv[4], yv[4];
+            load4_tail(x + i0, lim, xv);
+            load4_tail(y + i0, lim, yv);
+            body(xv, yv, i0, lim);
+        }
     }
 }
 
@@ -45,7 +84,9 @@ __device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v)
 
 // ---------------------------------------------------------------------------
 // Pass 1 (Alg. 2, exponent preprocessing + counting): product exponents into
-// a block-private LDS histogram, merged into the global one at the end.
+// a block-private LDS histogram, merged into one of HIST_COPIES global
+// histograms (blockIdx % HIST_COPIES, i.e. one per XCD under round-robin
+// dispatch) so that the merge atomics of concurrent blocks spread out.
 // ---------------------------------------------------------------------------
 template <bool VEC, int U>
 __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
@@ -53,38 +94,27 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
                                                 int64_t n, int key_mode,
                                                 Ws *__restrict__ ws)
 {
-    __shared__ unsigned int h[W];
-    for (int i = threadIdx.x; i < W; i += BLOCK) h[i] = 0;
+    __shared__ unsigned int h[W + 1];
+    for (int i = threadIdx.x; i < W + 1; i += BLOCK) h[i] = 0;
     __syncthreads();
 
     unsigned int nz = 0, bad = 0;
-    const int64_t step = (int64_t)gridDim.x * CHUNK * U;
-    for (int64_t base = (int64_t)blockIdx.x * CHUNK * U; base < n; base += step) {
-        double xv[U][4], yv[U][4];
+    stream_groups<VEC, U>(x, y, n, [&](const double *xv, const double *yv, int64_t, int lim) {
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
-            load4<VEC>(x, i0, n, xv[u]);
-            load4<VEC>(y, i0, n, yv[u]);
+        for (int e = 0; e < 4; e++) {
+            const Comp c = component(xv[e], yv[e], key_mode);
+            const bool valid = e < lim;
+            nz += (valid & c.zero) ? 1u : 0u;
+            bad |= (valid & c.bad) ? 1u : 0u;
+            // zero and non-finite products land in the spare slot W
+            if (valid) atomicAdd(&h[c.slot], 1u);
         }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                if (i0 + e < n) {
-                    const Comp c = component(xv[u][e], yv[u][e], key_mode);
-                    nz += c.zero;
-                    bad |= c.bad;
-                    if (!(c.zero | c.bad)) atomicAdd(&h[c.slot], 1u);
-                }
-            }
-        }
-    }
+    });
     __syncthreads();
+    unsigned long long *gh = ws->hist[blockIdx.x % HIST_COPIES];
     for (int i = threadIdx.x; i < W; i += BLOCK) {
         const unsigned int v = h[i];
-        if (v) atomicAdd(&ws->hist[i], (unsigned long long)v);
+        if (v) atomicAdd(&gh[i], (unsigned long long)v);
     }
     nz = wave_sum_u32(nz);
     bad = wave_sum_u32(bad);
@@ -148,7 +178,11 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const int j = tid + r * CUT_THREADS;
-        cnt[r] = j < W ? ws->hist[j] : 0ull;
+        unsigned long long v = 0ull;
+        if (j < W)
+#pragma unroll
+            for (int c = 0; c < HIST_COPIES; c++) v += ws->hist[c][j];
+        cnt[r] = v;
         if (cnt[r]) {
             const int k = j + KMIN;
             emax = max(emax, k);
@@ -235,8 +269,10 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
             bound += ldexp((double)cnt[r] * eps_of_class(cls), k - e_max + 1);
         }
         ws->lut[j] = (unsigned char)cls;
-        ws->hist[j] = 0ull;
+#pragma unroll
+        for (int c = 0; c < HIST_COPIES; c++) ws->hist[c][j] = 0ull;
     }
+    if (tid < W_LUT - W) ws->lut[W + tid] = (unsigned char)QDOT_PERF;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
 #pragma unroll
@@ -272,6 +308,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
             out->value = 0.0;
         }
         out->flags = flags;
+        ws->flags = flags;
         ws->e_max = e_max;
         ws->t = t;
         ws->c32 = e_max + t + 22;
@@ -284,7 +321,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
 // ---------------------------------------------------------------------------
 // Pass 2 (Alg. 1): per component class -> quantised product (leaf) ->
 // 64-element FP32 tile trees (single and half separately) and compensated
-// FP64 sums -> per-block partials -> last block combines.
+// FP64 sums -> per-block partials (combined by k_fin).
 //
 // Leaves (exact powers of two scale them; the FP64 result is multiplied by
 // 2^e_max once at the end):
@@ -292,19 +329,19 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
 //   single: fl32(fl32(m_x) fl32(m_y)) * 2^(E_x + E_y - c32)
 //   half  : h16(m_x) h16(m_y) * 2^(E_x + E_y - c32)  (22-bit product, exact)
 // with c32 = e_max + t + 22, which keeps every FP32 leaf normal and < 4.
+// All three candidates are formed without branches and the class selects
+// one; the only branch is the rare zero/subnormal operand path.
 // ---------------------------------------------------------------------------
 template <bool VEC, int U, bool CLS>
 __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
                                                const double *__restrict__ y,
                                                int64_t n, int key_mode,
-                                               Ws *__restrict__ ws,
+                                               const Ws *__restrict__ ws,
                                                double *__restrict__ partials,
-                                               qdot_result *__restrict__ out,
                                                unsigned char *__restrict__ cls_out)
 {
     __shared__ unsigned char lut[W_LUT];
     __shared__ Acc red[3][BLOCK / 64];
-    __shared__ int s_last;
 
     const int skip = ws->skip;
     if (skip && !CLS) return;
@@ -319,55 +356,40 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
 
     const int lane = threadIdx.x & 63;
     Acc aD = {0.0, 0.0}, aS = {0.0, 0.0}, aH = {0.0, 0.0};
-    const int64_t step = (int64_t)gridDim.x * CHUNK * U;
-    for (int64_t base = (int64_t)blockIdx.x * CHUNK * U; base < n; base += step) {
-        double xv[U][4], yv[U][4];
+    stream_groups<VEC, U>(x, y, n, [&](const double *xv, const double *yv, int64_t i0, int lim) {
+        float ls[4], lh[4];
+        double ld[4];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
-            load4<VEC>(x, i0, n, xv[u]);
-            load4<VEC>(y, i0, n, yv[u]);
+        for (int e = 0; e < 4; e++) {
+            const Comp c = component(xv[e], yv[e], key_mode);
+            const bool valid = e < lim;
+            const int cls = valid ? (int)lut[c.slot] : QDOT_PERF;
+            if (CLS && valid) cls_out[i0 + e] = (unsigned char)cls;
+            // double candidate
+            double dl = ldexp(c.mp, c.es - e_max);
+            dl = __longlong_as_double(__double_as_longlong(dl) ^ ((long long)c.sgn << 32));
+            // single and half candidates share one scaling
+            const float ps = (float)c.mx * (float)c.my;
+            const float ph = (float)(half_round(c.mx) * half_round(c.my));
+            float l32 = ldexpf(cls == QDOT_HALF ? ph : ps, c.es - c32);
+            l32 = __int_as_float(__float_as_int(l32) ^ (int)c.sgn);
+            ld[e] = cls == QDOT_DOUBLE ? dl : 0.0;
+            ls[e] = cls == QDOT_SINGLE ? l32 : 0.0f;
+            lh[e] = cls == QDOT_HALF ? l32 : 0.0f;
         }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
-            float ls[4], lh[4];
-            double ld[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                ls[e] = 0.0f;
-                lh[e] = 0.0f;
-                ld[e] = 0.0;
-                const Comp c = component(xv[u][e], yv[u][e], key_mode);
-                const bool valid = i0 + e < n;
-                const int cls = (c.zero | c.bad | !valid) ? QDOT_PERF : (int)lut[c.slot];
-                if (CLS && valid) cls_out[i0 + e] = (unsigned char)cls;
-                if (cls == QDOT_DOUBLE) {
-                    ld[e] = ldexp(c.neg ? -c.mp : c.mp, c.es - e_max);
-                } else if (cls == QDOT_SINGLE) {
-                    const float a = (float)mant(c.fx);
-                    const float b = (float)mant(c.fy);
-                    const float p = a * b;
-                    ls[e] = ldexpf(c.neg ? -p : p, c.es - c32);
-                } else if (cls == QDOT_HALF) {
-                    const float p = (float)(half_sig(c.fx) * half_sig(c.fy));
-                    lh[e] = ldexpf(c.neg ? -p : p, c.es - c32 - 20);
-                }
-            }
-            if (!skip) {
-                // tile tree levels 1-2 in the lane, 3-6 across the row
-                const float s4 = (ls[0] + ls[1]) + (ls[2] + ls[3]);
-                const float h4 = (lh[0] + lh[1]) + (lh[2] + lh[3]);
-                const float ts = tile_levels_3to6(s4);
-                const float th = tile_levels_3to6(h4);
-                acc_add(aD, (ld[0] + ld[1]) + (ld[2] + ld[3]));
-                if ((lane & 15) == 0) {
-                    acc_add(aS, (double)ts);
-                    acc_add(aH, (double)th);
-                }
+        if (!skip) {
+            // tile tree levels 1-2 in the lane, 3-6 across the row
+            const float s4 = (ls[0] + ls[1]) + (ls[2] + ls[3]);
+            const float h4 = (lh[0] + lh[1]) + (lh[2] + lh[3]);
+            const float ts = tile_levels_3to6(s4);
+            const float th = tile_levels_3to6(h4);
+            acc_add(aD, (ld[0] + ld[1]) + (ld[2] + ld[3]));
+            if ((lane & 15) == 0) {
+                acc_add(aS, (double)ts);
+                acc_add(aH, (double)th);
             }
         }
-    }
+    });
     if (skip) return;
 
     aD = wave_reduce(aD);
@@ -381,33 +403,30 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        Acc b[3];
-        for (int q = 0; q < 3; q++) {
-            b[q] = red[q][0];
-            for (int w = 1; w < BLOCK / 64; w++) b[q] = acc_merge(b[q], red[q][w]);
-        }
         double *p = partials + (size_t)blockIdx.x * 6;
         for (int q = 0; q < 3; q++) {
-            p[2 * q] = b[q].s;
-            p[2 * q + 1] = b[q].c;
+            Acc b = red[q][0];
+            for (int w = 1; w < BLOCK / 64; w++) b = acc_merge(b, red[q][w]);
+            p[2 * q] = b.s;
+            p[2 * q + 1] = b.c;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned int prev = __hip_atomic_fetch_add(&ws->ticket, 1u, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!s_last) return;
+}
 
-    // Last block: combine every block's partials in a fixed order.
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// Combine the per-block partials of k_acc in a fixed order (one block).
+__global__ __launch_bounds__(BLOCK) void k_fin(const Ws *__restrict__ ws,
+                                               const double *__restrict__ partials, int nblk,
+                                               qdot_result *__restrict__ out)
+{
+    __shared__ Acc red[3][BLOCK / 64];
+    if (ws->skip) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     Acc c[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) {
+    for (int b = threadIdx.x; b < nblk; b += BLOCK) {
         const double *p = partials + (size_t)b * 6;
         for (int q = 0; q < 3; q++) c[q] = acc_merge(c[q], Acc{p[2 * q], p[2 * q + 1]});
     }
     for (int q = 0; q < 3; q++) c[q] = wave_reduce(c[q]);
-    __syncthreads();
     if (lane == 0)
         for (int q = 0; q < 3; q++) red[q][wv] = c[q];
     __syncthreads();
@@ -417,7 +436,7 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
             f[q] = red[q][0];
             for (int w = 1; w < BLOCK / 64; w++) f[q] = acc_merge(f[q], red[q][w]);
         }
-        const int t = ws->t;
+        const int t = ws->t, e_max = ws->e_max, c32 = ws->c32;
         // S = D + 2^(c32 - e_max) (S + H), with c32 - e_max = t + 22
         Acc tot = f[0];
         acc_add(tot, ldexp(f[1].s, t + 22));
@@ -429,8 +448,7 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
         out->part[QDOT_DOUBLE] = ldexp(f[0].s + f[0].c, e_max);
         out->part[QDOT_SINGLE] = ldexp(f[1].s + f[1].c, c32);
         out->part[QDOT_HALF] = ldexp(f[2].s + f[2].c, c32);
-        if (__builtin_isinf(value)) out->flags = out->flags | QDOT_F_OVERFLOW;
-        ws->ticket = 0u;
+        out->flags = ws->flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
     }
 }
 
@@ -440,28 +458,15 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
 template <bool VEC, int U>
 __global__ __launch_bounds__(BLOCK) void k_dot64(const double *__restrict__ x,
                                                  const double *__restrict__ y,
-                                                 int64_t n, Ws *__restrict__ ws,
-                                                 double *__restrict__ partials,
-                                                 double *__restrict__ out)
+                                                 int64_t n, double *__restrict__ partials)
 {
     __shared__ double red[BLOCK / 64];
-    __shared__ int s_last;
     const int lane = threadIdx.x & 63;
     double acc = 0.0;
-    const int64_t step = (int64_t)gridDim.x * CHUNK * U;
-    for (int64_t base = (int64_t)blockIdx.x * CHUNK * U; base < n; base += step) {
-        double xv[U][4], yv[U][4];
+    stream_groups<VEC, U>(x, y, n, [&](const double *xv, const double *yv, int64_t, int) {
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
-            load4<VEC>(x, i0, n, xv[u]);
-            load4<VEC>(y, i0, n, yv[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) acc = fma(xv[u][e], yv[u][e], acc);
-    }
+        for (int e = 0; e < 4; e++) acc = fma(xv[e], yv[e], acc);
+    });
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
     const int wv = threadIdx.x >> 6;
@@ -471,107 +476,132 @@ __global__ __launch_bounds__(BLOCK) void k_dot64(const double *__restrict__ x,
         double b = red[0];
         for (int w = 1; w < BLOCK / 64; w++) b += red[w];
         partials[blockIdx.x] = b;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned int prev = __hip_atomic_fetch_add(&ws->ticket, 1u, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__global__ __launch_bounds__(BLOCK) void k_dot_fin(const double *__restrict__ partials,
+                                                   int nblk, double *__restrict__ out)
+{
+    __shared__ double red[BLOCK / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double c = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) c += partials[b];
+    for (int b = threadIdx.x; b < nblk; b += BLOCK) c += partials[b];
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m, 64);
-    __syncthreads();
     if (lane == 0) red[wv] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
         double f = red[0];
         for (int w = 1; w < BLOCK / 64; w++) f += red[w];
         *out = f;
-        ws->ticket = 0u;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-template <int U>
-static hipError_t launch_qdot_u(const Launch &L, const double *x, const double *y,
-                                int64_t n, double tol, const qdot_options &o,
-                                qdot_result *out, unsigned char *cls_out,
-                                long long *hist_out)
+static int grid_for(int64_t n, int unroll, int cap)
 {
-    const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
-    const int64_t groups = (n + (int64_t)CHUNK * U - 1) / ((int64_t)CHUNK * U);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.max_blocks, groups));
-    hipStream_t s = L.stream;
-    if (L.ev) (void)hipEventRecord(L.ev[0], s);
-    if (vec)
-        hipLaunchKernelGGL((k_scan<true, U>), dim3(grid), dim3(BLOCK), 0, s, x, y, n, o.key_mode, L.ws);
-    else
-        hipLaunchKernelGGL((k_scan<false, U>), dim3(grid), dim3(BLOCK), 0, s, x, y, n, o.key_mode, L.ws);
-    if (L.ev) (void)hipEventRecord(L.ev[1], s);
-    hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, out, hist_out);
-    if (L.ev) (void)hipEventRecord(L.ev[2], s);
-    if (cls_out) {
-        if (vec)
-            hipLaunchKernelGGL((k_acc<true, U, true>), dim3(grid), dim3(BLOCK), 0, s, x, y, n,
-                               o.key_mode, L.ws, L.partials, out, cls_out);
-        else
-            hipLaunchKernelGGL((k_acc<false, U, true>), dim3(grid), dim3(BLOCK), 0, s, x, y, n,
-                               o.key_mode, L.ws, L.partials, out, cls_out);
-    } else {
-        if (vec)
-            hipLaunchKernelGGL((k_acc<true, U, false>), dim3(grid), dim3(BLOCK), 0, s, x, y, n,
-                               o.key_mode, L.ws, L.partials, out, nullptr);
-        else
-            hipLaunchKernelGGL((k_acc<false, U, false>), dim3(grid), dim3(BLOCK), 0, s, x, y, n,
-                               o.key_mode, L.ws, L.partials, out, nullptr);
+    const int64_t groups = (n + (int64_t)CHUNK * unroll - 1) / ((int64_t)CHUNK * unroll);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cap, groups));
+}
+
+template <bool VEC, int U>
+static void launch_scan_u(const Launch &L, const double *x, const double *y, int64_t n,
+                          int key_mode)
+{
+    hipLaunchKernelGGL((k_scan<VEC, U>), dim3(grid_for(n, U, L.scan_blocks)), dim3(BLOCK), 0,
+                       L.stream, x, y, n, key_mode, L.ws);
+}
+
+template <bool VEC>
+static void launch_scan(const Launch &L, const double *x, const double *y, int64_t n,
+                        int key_mode)
+{
+    switch (L.scan_unroll) {
+    case 1: launch_scan_u<VEC, 1>(L, x, y, n, key_mode); break;
+    case 4: launch_scan_u<VEC, 4>(L, x, y, n, key_mode); break;
+    default: launch_scan_u<VEC, 2>(L, x, y, n, key_mode); break;
     }
-    if (L.ev) (void)hipEventRecord(L.ev[3], s);
-    return hipGetLastError();
+}
+
+template <bool VEC, int U, bool CLS>
+static int launch_acc_u(const Launch &L, const double *x, const double *y, int64_t n,
+                        int key_mode, unsigned char *cls_out)
+{
+    const int grid = grid_for(n, U, L.acc_blocks);
+    hipLaunchKernelGGL((k_acc<VEC, U, CLS>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+                       key_mode, L.ws, L.partials, cls_out);
+    return grid;
+}
+
+template <bool VEC, bool CLS>
+static int launch_acc(const Launch &L, const double *x, const double *y, int64_t n,
+                      int key_mode, unsigned char *cls_out)
+{
+    switch (L.acc_unroll) {
+    case 1: return launch_acc_u<VEC, 1, CLS>(L, x, y, n, key_mode, cls_out);
+    case 4: return launch_acc_u<VEC, 4, CLS>(L, x, y, n, key_mode, cls_out);
+    default: return launch_acc_u<VEC, 2, CLS>(L, x, y, n, key_mode, cls_out);
+    }
 }
 
 hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_t n,
                        double tol, const qdot_options &o, qdot_result *out,
                        unsigned char *cls_out, long long *hist_out)
 {
-    switch (L.unroll) {
-    case 1: return launch_qdot_u<1>(L, x, y, n, tol, o, out, cls_out, hist_out);
-    case 4: return launch_qdot_u<4>(L, x, y, n, tol, o, out, cls_out, hist_out);
-    default: return launch_qdot_u<2>(L, x, y, n, tol, o, out, cls_out, hist_out);
-    }
+    const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
+    hipStream_t s = L.stream;
+    if (L.ev) (void)hipEventRecord(L.ev[0], s);
+    if (vec)
+        launch_scan<true>(L, x, y, n, o.key_mode);
+    else
+        launch_scan<false>(L, x, y, n, o.key_mode);
+    if (L.ev) (void)hipEventRecord(L.ev[1], s);
+    hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
+                       o.boundary_mode, n, out, hist_out);
+    if (L.ev) (void)hipEventRecord(L.ev[2], s);
+    int grid;
+    if (cls_out)
+        grid = vec ? launch_acc<true, true>(L, x, y, n, o.key_mode, cls_out)
+                   : launch_acc<false, true>(L, x, y, n, o.key_mode, cls_out);
+    else
+        grid = vec ? launch_acc<true, false>(L, x, y, n, o.key_mode, nullptr)
+                   : launch_acc<false, false>(L, x, y, n, o.key_mode, nullptr);
+    if (L.ev) (void)hipEventRecord(L.ev[3], s);
+    hipLaunchKernelGGL(k_fin, dim3(1), dim3(BLOCK), 0, s, L.ws, L.partials, grid, out);
+    if (L.ev) (void)hipEventRecord(L.ev[4], s);
+    return hipGetLastError();
 }
 
-template <int U>
-static hipError_t launch_dot64_u(const Launch &L, const double *x, const double *y,
-                                 int64_t n, double *out)
+template <bool VEC, int U>
+static int launch_dot64_u(const Launch &L, const double *x, const double *y, int64_t n)
 {
-    const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
-    const int64_t groups = (n + (int64_t)CHUNK * U - 1) / ((int64_t)CHUNK * U);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(L.max_blocks, groups));
-    if (L.ev) (void)hipEventRecord(L.ev[0], L.stream);
-    if (vec)
-        hipLaunchKernelGGL((k_dot64<true, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
-                           L.ws, L.partials, out);
-    else
-        hipLaunchKernelGGL((k_dot64<false, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
-                           L.ws, L.partials, out);
-    if (L.ev) (void)hipEventRecord(L.ev[1], L.stream);
-    return hipGetLastError();
+    const int grid = grid_for(n, U, L.acc_blocks);
+    hipLaunchKernelGGL((k_dot64<VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+                       L.partials);
+    return grid;
+}
+
+template <bool VEC>
+static int launch_dot64_v(const Launch &L, const double *x, const double *y, int64_t n)
+{
+    switch (L.acc_unroll) {
+    case 1: return launch_dot64_u<VEC, 1>(L, x, y, n);
+    case 4: return launch_dot64_u<VEC, 4>(L, x, y, n);
+    default: return launch_dot64_u<VEC, 2>(L, x, y, n);
+    }
 }
 
 hipError_t launch_dot64(const Launch &L, const double *x, const double *y, int64_t n,
                         double *out)
 {
-    switch (L.unroll) {
-    case 1: return launch_dot64_u<1>(L, x, y, n, out);
-    case 4: return launch_dot64_u<4>(L, x, y, n, out);
-    default: return launch_dot64_u<2>(L, x, y, n, out);
-    }
+    const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
+    if (L.ev) (void)hipEventRecord(L.ev[0], L.stream);
+    const int grid = vec ? launch_dot64_v<true>(L, x, y, n) : launch_dot64_v<false>(L, x, y, n);
+    hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(BLOCK), 0, L.stream, L.partials, grid, out);
+    if (L.ev) (void)hipEventRecord(L.ev[1], L.stream);
+    return hipGetLastError();
 }
 
 }  // namespace qd

@@ -11,8 +11,10 @@ struct Launch {
     hipStream_t stream;
     Ws *ws;             // device control block of the handle
     double *partials;   // >= 6 * max_blocks doubles
-    int max_blocks;     // persistent grid cap
-    int unroll;         // 1, 2 or 4 groups of 4 elements in flight per lane
+    int scan_blocks;    // persistent grid cap of the exponent scan
+    int scan_unroll;    // 1, 2 or 4 groups of 4 elements in flight per lane
+    int acc_blocks;     // grid cap of the accumulate pass / FP64 dot
+    int acc_unroll;
     hipEvent_t *ev;     // NULL, or events recorded around each kernel
 };
 

@@ -272,7 +272,7 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     int32_t st = ensure_scratch(h, n);
     if (st != QDOT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    const Launch L = make_launch(h, s);
+    const Launch L = make_launch(h, s, n);
     double *r = h->vec, *p = h->vec + n, *q = h->vec + 2 * n;
     SolverCtl *ctl = (SolverCtl *)h->ctl;
     qdot_result *rr_slot = h->res_ring, *pq_slot = h->res_ring + 1;
@@ -356,7 +356,7 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     int32_t st = ensure_scratch(h, n);
     if (st != QDOT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    const Launch L = make_launch(h, s);
+    const Launch L = make_launch(h, s, n);
     double *w = h->vec + 3 * n;
     SolverCtl *ctl = (SolverCtl *)h->ctl;
     hipError_t e = hipSuccess;

@@ -180,14 +180,30 @@ def test_repeat_and_tuning_invariance(h):
     assert again["value"] == base["value"]  # same launch configuration: bitwise
     o = oracle.qdot(x, y, 1e-6)
     scale = oracle.abs_dot(x, y)
-    for bpc in (1, 2, 8):
-        for unroll in (1, 2, 4):
-            h.set_tune(bpc, unroll)
-            cls, hist, r = h.qdot_classes(xd, yd, 1e-6)
-            assert torch.equal(cls, base_cls) and torch.equal(hist, base_hist)
-            assert r["count"] == base["count"]
-            assert abs(r["value"] - o["value"]) <= VALUE_TOL * scale
-    h.set_tune(4, 2)
+    for sb, su, ab, au in [(1, 1, 1, 1), (2, 2, 8, 4), (8, 4, 2, 2), (16, 1, 16, 2),
+                           (4, 2, 1, 4)]:
+        h.set_tune(-1, sb, su, ab, au)
+        cls, hist, r = h.qdot_classes(xd, yd, 1e-6)
+        assert torch.equal(cls, base_cls) and torch.equal(hist, base_hist)
+        assert r["count"] == base["count"]
+        assert abs(r["value"] - o["value"]) <= VALUE_TOL * scale
+    h.reset_tune()
+
+
+def test_tune_file_loading(h, tmp_path):
+    good = tmp_path / "good.txt"
+    good.write_text("# comment\n0 1 1 2 2\n3 8 4 16 1  # trailing comment\n\n")
+    h.reset_tune()
+    h.load_tune(str(good))
+    assert h.get_tune(0) == (1, 1, 2, 2) and h.get_tune(3) == (8, 4, 16, 1)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1 2 3 4 5\n")  # unroll 3 is not allowed
+    with pytest.raises(q.QdotError):
+        h.load_tune(str(bad))
+    assert h.get_tune(1) == h.get_tune(1)  # unchanged, still readable
+    with pytest.raises(q.QdotError):
+        h.load_tune(str(tmp_path / "missing.txt"))
+    h.reset_tune()
 
 
 def test_async_result_in_stream_order(h):
