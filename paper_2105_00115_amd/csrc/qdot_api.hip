@@ -47,7 +47,7 @@ Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n)
     L.stream = s;
     L.ws = h->ws;
     L.partials = h->partials;
-    L.scan_blocks = t.scan_blocks_per_cu * h->num_cus;
+    L.scan_blocks = std::min(MAX_GRID, t.scan_blocks_per_cu * h->num_cus);
     L.scan_unroll = t.scan_unroll;
     L.acc_blocks = std::min(h->partial_blocks, t.acc_blocks_per_cu * h->num_cus);
     L.acc_unroll = t.acc_unroll;
@@ -112,14 +112,16 @@ int32_t qdot_create(qdot_handle **out, int32_t device)
         delete h;
         return QDOT_E_DEVICE;
     }
-    h->partial_blocks = 16 * h->num_cus;
+    h->partial_blocks = std::min(MAX_GRID, 16 * h->num_cus);
     for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) h->tune[b] = default_tune(b);
     bool ok = hipMalloc((void **)&h->ws, sizeof(Ws)) == hipSuccess &&
               hipMalloc((void **)&h->partials, sizeof(double) * 6 * h->partial_blocks) == hipSuccess &&
               hipMalloc((void **)&h->dev_res, sizeof(qdot_result)) == hipSuccess &&
               hipHostMalloc((void **)&h->host_res, sizeof(qdot_result), hipHostMallocDefault) ==
                   hipSuccess;
-    if (ok) ok = hipMemset(h->ws, 0, sizeof(Ws)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    if (ok) {
+        ok = hipMemset(h->ws, 0, sizeof(Ws)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
     if (!ok) {
         qdot_destroy(h);
         return QDOT_E_NOMEM;

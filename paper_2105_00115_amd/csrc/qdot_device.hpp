@@ -27,6 +27,7 @@ constexpr int EPT = 4;                      // consecutive elements per lane
 constexpr int CHUNK = BLOCK * EPT;          // 1024 elements per block group
 constexpr int TILE = 64;                    // FP32 accumulation tile
 constexpr int CUT_THREADS = 1024;
+constexpr int MAX_GRID = 16 * 256;          // persistent grid cap (16 per CU)
 
 constexpr uint64_t FRAC_MASK = 0x000fffffffffffffull;
 constexpr uint64_t ONE_BITS = 0x3ff0000000000000ull;
@@ -37,13 +38,14 @@ struct Ws {
     unsigned long long n_zero;   // zero products seen by pass 1
     unsigned int nonfinite;      // any Inf/NaN seen by pass 1
     unsigned int pad0;
+    int2 block_range[MAX_GRID];  // per scan block: [lo, hi] of its live slots
     // produced by the cutoff kernel for pass 2
     int e_max;
     int t;
     int c32;                     // exponent offset of FP32 leaves
     int skip;                    // nothing to accumulate (result final)
     int flags;                   // result flags known after selection
-    int pad1[3];
+    int pad1;
     unsigned char lut[W_LUT];    // class of every key slot (+ zero slot)
 };
 

@@ -112,15 +112,34 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
     });
     __syncthreads();
     unsigned long long *gh = ws->hist[blockIdx.x % HIST_COPIES];
+    int lo = W, hi = -1;
     for (int i = threadIdx.x; i < W; i += BLOCK) {
         const unsigned int v = h[i];
-        if (v) atomicAdd(&gh[i], (unsigned long long)v);
+        if (v) {
+            atomicAdd(&gh[i], (unsigned long long)v);
+            lo = min(lo, i);
+            hi = max(hi, i);
+        }
     }
     nz = wave_sum_u32(nz);
     bad = wave_sum_u32(bad);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo = min(lo, __shfl_xor(lo, m, 64));
+        hi = max(hi, __shfl_xor(hi, m, 64));
+    }
+    __shared__ int2 wr[BLOCK / 64];
     if ((threadIdx.x & 63) == 0) {
         if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
         if (bad) atomicOr(&ws->nonfinite, 1u);
+        wr[threadIdx.x >> 6] = make_int2(lo, hi);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // plain store, no contention: the cutoff kernel reduces the records
+        int2 r = wr[0];
+        for (int w = 1; w < BLOCK / 64; w++) r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
+        ws->block_range[blockIdx.x] = r;
     }
 }
 
@@ -162,7 +181,8 @@ __device__ __forceinline__ double eps_of_class(int c)
 
 __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double tol,
                                                      int score_mode, int nonstrict,
-                                                     int64_t n, qdot_result *__restrict__ out,
+                                                     int64_t n, int nscan,
+                                                     qdot_result *__restrict__ out,
                                                      long long *__restrict__ hist_out)
 {
     constexpr int R = (W + CUT_THREADS - 1) / CUT_THREADS;
@@ -173,13 +193,39 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
     __shared__ int s_emax, s_t, s_go;
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // only the slot window pass 1 touched holds counts; slots outside it are
+    // zero in every copy and their class-table entries are never read
+    __shared__ int s_lo[NW], s_hi[NW];
+    int lo = W, hi = -1;
+    {
+        int a = W, b = -1;
+        for (int i = tid; i < nscan; i += CUT_THREADS) {
+            const int2 r = ws->block_range[i];
+            a = min(a, r.x);
+            b = max(b, r.y);
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            a = min(a, __shfl_xor(a, m, 64));
+            b = max(b, __shfl_xor(b, m, 64));
+        }
+        if (lane == 0) {
+            s_lo[wv] = a;
+            s_hi[wv] = b;
+        }
+        __syncthreads();
+        for (int w = 0; w < NW; w++) {
+            lo = min(lo, s_lo[w]);
+            hi = max(hi, s_hi[w]);
+        }
+    }
     unsigned long long cnt[R];
     int emax = INT_MIN, emin = INT_MAX, nb = 0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int j = tid + r * CUT_THREADS;
+        const int j = lo + tid + r * CUT_THREADS;
         unsigned long long v = 0ull;
-        if (j < W)
+        if (j <= hi)
 #pragma unroll
             for (int c = 0; c < HIST_COPIES; c++) v += ws->hist[c][j];
         cnt[r] = v;
@@ -189,7 +235,15 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
             emin = min(emin, k);
             nb++;
         }
-        if (hist_out && j < W) hist_out[j] = (long long)cnt[r];
+    }
+    if (hist_out) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int j = lo + tid + r * CUT_THREADS;
+            if (j <= hi) hist_out[j] = (long long)cnt[r];
+        }
+        for (int j = tid; j < W; j += CUT_THREADS)
+            if (j < lo || j > hi) hist_out[j] = 0ll;
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
@@ -255,8 +309,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
     int unatt = 0;
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const int j = tid + r * CUT_THREADS;
-        if (j >= W) break;
+        const int j = lo + tid + r * CUT_THREADS;
+        if (j > hi) break;
         int cls = QDOT_PERF;
         if (go && cnt[r]) {
             const int k = j + KMIN;
@@ -273,6 +327,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
         for (int c = 0; c < HIST_COPIES; c++) ws->hist[c][j] = 0ull;
     }
     if (tid < W_LUT - W) ws->lut[W + tid] = (unsigned char)QDOT_PERF;
+
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
 #pragma unroll
@@ -507,21 +562,23 @@ static int grid_for(int64_t n, int unroll, int cap)
 }
 
 template <bool VEC, int U>
-static void launch_scan_u(const Launch &L, const double *x, const double *y, int64_t n,
-                          int key_mode)
+static int launch_scan_u(const Launch &L, const double *x, const double *y, int64_t n,
+                         int key_mode)
 {
-    hipLaunchKernelGGL((k_scan<VEC, U>), dim3(grid_for(n, U, L.scan_blocks)), dim3(BLOCK), 0,
-                       L.stream, x, y, n, key_mode, L.ws);
+    const int grid = grid_for(n, U, L.scan_blocks);
+    hipLaunchKernelGGL((k_scan<VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+                       key_mode, L.ws);
+    return grid;
 }
 
 template <bool VEC>
-static void launch_scan(const Launch &L, const double *x, const double *y, int64_t n,
-                        int key_mode)
+static int launch_scan(const Launch &L, const double *x, const double *y, int64_t n,
+                       int key_mode)
 {
     switch (L.scan_unroll) {
-    case 1: launch_scan_u<VEC, 1>(L, x, y, n, key_mode); break;
-    case 4: launch_scan_u<VEC, 4>(L, x, y, n, key_mode); break;
-    default: launch_scan_u<VEC, 2>(L, x, y, n, key_mode); break;
+    case 1: return launch_scan_u<VEC, 1>(L, x, y, n, key_mode);
+    case 4: return launch_scan_u<VEC, 4>(L, x, y, n, key_mode);
+    default: return launch_scan_u<VEC, 2>(L, x, y, n, key_mode);
     }
 }
 
@@ -553,13 +610,11 @@ hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_
     const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
     hipStream_t s = L.stream;
     if (L.ev) (void)hipEventRecord(L.ev[0], s);
-    if (vec)
-        launch_scan<true>(L, x, y, n, o.key_mode);
-    else
-        launch_scan<false>(L, x, y, n, o.key_mode);
+    const int nscan = vec ? launch_scan<true>(L, x, y, n, o.key_mode)
+                          : launch_scan<false>(L, x, y, n, o.key_mode);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
     hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, out, hist_out);
+                       o.boundary_mode, n, nscan, out, hist_out);
     if (L.ev) (void)hipEventRecord(L.ev[2], s);
     int grid;
     if (cls_out)
