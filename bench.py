@@ -44,9 +44,10 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n):
-    """HBM bytes per launch of the accumulate kernel from the committed
-    rocprofv3 counter runs, if they were taken on the current kernel."""
+def measured_traffic(n, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), if they
+    were taken on the current kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -54,7 +55,8 @@ def measured_traffic(n):
         return None
     if t.get("kernel_src_sha") != kernel_source_sha() or t.get("n") != n:
         return None
-    return t.get("hbm_bytes_per_launch")
+    k = t.get("per_kernel", {}).get(kernel)
+    return round(k["hbm_bytes_per_launch"]) if k else None
 
 
 def cpu_baseline(x_host, y_host, tol, budget_s=12.0):
@@ -161,7 +163,7 @@ def main():
     dominant, dom_ms = ("k_acc", acc_ms) if acc_ms >= scan_ms else ("k_scan", scan_ms)
     alg_bytes = 16.0 * n  # x_i and y_i once per pass
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(n)
+    traffic = measured_traffic(n, dominant)
 
     # CG on the 2D Poisson matrix 1024^2 (qdot tol 1e-8 vs FP64 dot)
     log("CG 2D Poisson 1024^2")
