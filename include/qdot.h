@@ -218,6 +218,34 @@ QDOT_API int32_t qdot_classes_async(qdot_handle *h, const double *x, const doubl
 QDOT_API int32_t qdot_fp64_dot_async(qdot_handle *h, const double *x, const double *y,
                             int64_t n, void *stream, double *dev_out);
 
+/* Batched ragged qdot: B independent instances stored back to back, all in
+ * one persistent kernel launch.
+ *   x_cat, y_cat : device FP64[offsets[B]]
+ *   offsets      : device int64[B + 1], offsets[0] = 0, non-decreasing;
+ *                  instance j is [offsets[j], offsets[j+1]).  Its 64-element
+ *                  accumulation tiles start at offsets[j].
+ *   host_offsets : host copy of offsets, used to plan the work queue.
+ *   tols         : device FP64[B]; an instance whose tolerance is not finite
+ *                  and > 0 gets status QDOT_E_INVAL (value NaN).
+ *   dev_out      : device qdot_result[B].
+ * Each instance's counts, classes, bins and value follow qdot on that
+ * instance alone (same readings, same tiles).  The first call with a new
+ * offsets layout plans it (allocates the per-layout state and uploads the
+ * work list, synchronously); later calls with the same layout only launch
+ * one kernel: no allocation, no memset, no host sync, graph-capturable.
+ * Up to 8 layouts are kept per handle.  Calls on one handle must be ordered
+ * on one stream.  Host-side argument errors return QDOT_E_INVAL. */
+QDOT_API int32_t qdot_batched_async(qdot_handle *h, const double *x_cat,
+                                    const double *y_cat, const int64_t *offsets,
+                                    const int64_t *host_offsets, const double *tols,
+                                    int32_t B, const qdot_options *opt, void *stream,
+                                    qdot_result *dev_out);
+
+/* Plan a batched layout ahead of time (e.g. before capturing
+ * qdot_batched_async into a graph).  Synchronous. */
+QDOT_API int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets,
+                                   int32_t B);
+
 /* y = A x for a CSR matrix (rows summed in stored order, each product and
  * sum one FP64 rounding).  Async. */
 QDOT_API int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double *x,

@@ -100,6 +100,9 @@ SIGNATURES = [
     ("qdot", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, C.POINTER(QdotResult)]),
     ("qdot_classes_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp, _vp, _vp]),
     ("qdot_fp64_dot_async", _i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    ("qdot_batched_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32, _OPT,
+                                  _vp, _vp]),
+    ("qdot_batched_plan", _i32, [_vp, C.POINTER(_i64), _i32]),
     ("qdot_spmv_async", _i32, [_vp, _CSR, _vp, _vp, _vp]),
     ("qdot_cg", _i32, [_vp, _CSR, _vp, _vp, _d, _d, _i32, _i32, _OPT, _vp,
                        C.POINTER(QdotCgResult), _vp]),
@@ -311,6 +314,50 @@ class Qdot:
         out = torch.empty(1, dtype=torch.float64, device=x.device)
         self.fp64_dot_async(x, y, out)
         return float(out.item())
+
+    # ---- batched ------------------------------------------------------------
+    @staticmethod
+    def _host_offsets(host_offsets):
+        import numpy as np
+        ho = np.ascontiguousarray(host_offsets, dtype=np.int64)
+        return ho, ho.ctypes.data_as(C.POINTER(C.c_int64))
+
+    def batched_plan(self, host_offsets):
+        ho, hp = self._host_offsets(host_offsets)
+        st = lib().qdot_batched_plan(self._h, hp, ho.shape[0] - 1)
+        if st != OK:
+            self._raise(st, "qdot_batched_plan")
+
+    def batched_async(self, x_cat, y_cat, offsets, host_offsets, tols, out, opt=None,
+                      stream=None):
+        """offsets (int64, B+1) and tols (float64, B) are device tensors,
+        host_offsets the same offsets on the host; out is a CUDA uint8
+        tensor of B * RESULT_BYTES."""
+        import torch
+        _check_vec(x_cat, "x_cat")
+        _check_vec(y_cat, "y_cat")
+        if not (offsets.is_cuda and offsets.dtype == torch.int64 and tols.is_cuda
+                and tols.dtype == torch.float64):
+            raise ValueError("offsets must be CUDA int64 and tols CUDA float64")
+        ho, hp = self._host_offsets(host_offsets)
+        B = ho.shape[0] - 1
+        st = lib().qdot_batched_async(self._h, _ptr(x_cat), _ptr(y_cat), _ptr(offsets), hp,
+                                      _ptr(tols), B, _opts(opt), _stream(stream), _ptr(out))
+        if st != OK:
+            self._raise(st, "qdot_batched_async")
+
+    def batched(self, x_cat, y_cat, host_offsets, tols, opt=None) -> list:
+        """Synchronous convenience wrapper: host offsets / tolerances."""
+        import numpy as np
+        import torch
+        ho = np.ascontiguousarray(host_offsets, dtype=np.int64)
+        dev = x_cat.device
+        off_d = torch.from_numpy(ho).to(dev)
+        tol_d = torch.as_tensor(np.asarray(tols, dtype=np.float64)).to(dev)
+        out = torch.zeros(max(1, ho.shape[0] - 1) * RESULT_BYTES, dtype=torch.uint8, device=dev)
+        self.batched_async(x_cat, y_cat, off_d, ho, tol_d, out, opt)
+        torch.cuda.current_stream().synchronize()
+        return parse_results(out)[: ho.shape[0] - 1]
 
     # ---- applications ------------------------------------------------------
     def spmv(self, A: Csr, x, y, stream=None):

@@ -146,6 +146,7 @@ int32_t qdot_destroy(qdot_handle *h)
     if (h->dres) (void)hipFree(h->dres);
     if (h->host_ctl) (void)hipHostFree(h->host_ctl);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    free_plans(h);
     delete h;
     return QDOT_OK;
 }

@@ -1,0 +1,521 @@
+// Batched ragged qdot: B independent instances in one persistent launch.
+//
+// The host plans a work queue once per offsets layout:
+//   P1    pass-1 chunks (CH components) of the large instances,
+//   SMALL whole small instances (n <= SMALL_MAX), done start to finish by
+//         one block with a block-local cutoff,
+//   P2    pass-2 chunks of the large instances,
+// in that order.  Blocks take items from a global ticket.  The block that
+// finishes the last P1 chunk of a large instance runs that instance's cutoff
+// and publishes its class table with release semantics; P2 chunks acquire
+// that flag before they start.  Every P1 item is dequeued before any P2
+// item and a P1 item never waits, so a waiting block only ever waits for
+// work that a running block holds: the launch cannot deadlock, whatever the
+// number of resident blocks.  The block that finishes the last P2 chunk of
+// an instance combines its partials in chunk order and resets the
+// instance's counters, so the next call needs no clearing pass: the launch
+// performs no allocation and no memset and can be captured in a HIP graph.
+//
+// Each instance's 64-element FP32 tiles start at its own first component;
+// chunks are multiples of 1024 components, so tiles never straddle chunks.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "qdot_blocks.hpp"
+#include "qdot_handle.hpp"
+
+namespace qd {
+
+constexpr int64_t CH = 32768;        // components per P1 / P2 chunk
+constexpr int64_t SMALL_MAX = 65536; // instances up to this size: one block
+constexpr int MAX_PLANS = 8;
+
+enum : int { IT_P1 = 0, IT_SMALL = 1, IT_P2 = 2 };
+
+struct BItem {
+    int type;
+    int inst;
+    int large;  // compact index of a large instance (P1, P2)
+    int slot;   // P2: partial slot
+    int64_t begin, end;
+};
+
+struct BLarge {
+    unsigned int p1_done, p2_done, ready, nchunks;
+    int lo, hi;
+    unsigned long long n_zero;
+    unsigned int bad;
+    int first_slot;
+    int e_max, t, c32, skip, flags;
+    int pad;
+};
+
+struct BState {
+    unsigned int next;
+    unsigned int exited;
+};
+
+struct BatchPlan {
+    std::vector<int64_t> offsets;
+    int B = 0, n_items = 0, n_large = 0, n_p2 = 0;
+    BItem *items = nullptr;
+    BLarge *large = nullptr;
+    unsigned int *hist = nullptr;
+    unsigned char *lut = nullptr;
+    double *partials = nullptr;
+    BState *state = nullptr;
+    uint64_t last_use = 0;
+};
+
+void free_plan(BatchPlan *p)
+{
+    if (!p) return;
+    (void)hipFree(p->items);
+    (void)hipFree(p->large);
+    (void)hipFree(p->hist);
+    (void)hipFree(p->lut);
+    (void)hipFree(p->partials);
+    (void)hipFree(p->state);
+    delete p;
+}
+
+// block-wide reduction of a range and two counters; result in every thread
+__device__ __forceinline__ void block_reduce_range(int &lo, int &hi, unsigned int &nz,
+                                                   unsigned int &bad, int4 *scratch)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo = min(lo, __shfl_xor(lo, m, 64));
+        hi = max(hi, __shfl_xor(hi, m, 64));
+        nz += __shfl_xor(nz, m, 64);
+        bad |= __shfl_xor(bad, m, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wv] = make_int4(lo, hi, (int)nz, (int)bad);
+    __syncthreads();
+    lo = W;
+    hi = -1;
+    nz = 0;
+    bad = 0;
+    for (int w = 0; w < BLOCK / 64; w++) {
+        lo = min(lo, scratch[w].x);
+        hi = max(hi, scratch[w].y);
+        nz += (unsigned int)scratch[w].z;
+        bad |= (unsigned int)scratch[w].w;
+    }
+}
+
+// Pass 1 of components [b, e) of one instance into the LDS histogram h.
+__device__ __forceinline__ void scan_into(const double *xi, const double *yi, int64_t b,
+                                          int64_t e, bool vec, int key_mode, unsigned int *h,
+                                          unsigned int &nz, unsigned int &bad)
+{
+    auto body = [&](const double *xv, const double *yv, int64_t, int lim) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const Comp c = component(xv[k], yv[k], key_mode);
+            const bool valid = k < lim;
+            nz += (valid & c.zero) ? 1u : 0u;
+            bad |= (valid & c.bad) ? 1u : 0u;
+            if (valid) atomicAdd(&h[c.slot], 1u);
+        }
+    };
+    if (vec)
+        stream_block_range<true>(xi, yi, b, e, body);
+    else
+        stream_block_range<false>(xi, yi, b, e, body);
+}
+
+__device__ __forceinline__ void accumulate_range(const double *xi, const double *yi, int64_t b,
+                                                 int64_t e, bool vec, int key_mode,
+                                                 const unsigned char *lut, int e_max, int c32,
+                                                 Acc a[3])
+{
+    auto body = [&](const double *xv, const double *yv, int64_t, int lim) {
+        acc_group<false>(xv, yv, lim, lut, key_mode, e_max, c32, true, a[0], a[1], a[2], nullptr);
+    };
+    if (vec)
+        stream_block_range<true>(xi, yi, b, e, body);
+    else
+        stream_block_range<false>(xi, yi, b, e, body);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch_init(BLarge *large, int n_large,
+                                                      unsigned char *lut)
+{
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n_large) return;
+    large[i].lo = W;
+    large[i].hi = -1;
+    for (int s = W; s < W_LUT; s++) lut[(size_t)i * W_LUT + s] = (unsigned char)QDOT_PERF;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
+                                                 const double *__restrict__ y,
+                                                 const int64_t *__restrict__ offsets,
+                                                 const double *__restrict__ tols,
+                                                 const BItem *__restrict__ items, int n_items,
+                                                 BLarge *__restrict__ large,
+                                                 unsigned int *__restrict__ ghist,
+                                                 unsigned char *__restrict__ glut,
+                                                 double *__restrict__ partials,
+                                                 BState *__restrict__ st,
+                                                 qdot_result *__restrict__ out, int key_mode,
+                                                 int score_mode, int nonstrict)
+{
+    __shared__ unsigned int h[W + 1];
+    __shared__ unsigned char lut[W_LUT];
+    __shared__ Acc red[3][BLOCK / 64];
+    __shared__ int4 scratch[BLOCK / 64];
+    __shared__ int s_item, s_flag;
+    const int tid = threadIdx.x;
+
+    for (int i = tid; i < W + 1; i += BLOCK) h[i] = 0;
+    for (int i = W + tid; i < W_LUT; i += BLOCK) lut[i] = (unsigned char)QDOT_PERF;
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd(&st->next, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const BItem I = items[it];
+        const int64_t off = offsets[I.inst];
+        const int64_t n = offsets[I.inst + 1] - off;
+        const double *xi = x + off;
+        const double *yi = y + off;
+        const bool vec = ((((uintptr_t)xi) | ((uintptr_t)yi)) & 15) == 0;
+        const double tol = tols[I.inst];
+
+        if (I.type == IT_SMALL) {
+            unsigned int nz = 0, bad = 0;
+            scan_into(xi, yi, 0, n, vec, key_mode, h, nz, bad);
+            __syncthreads();
+            int lo = W, hi = -1;
+            for (int j = tid; j < W; j += BLOCK)
+                if (h[j]) {
+                    lo = min(lo, j);
+                    hi = max(hi, j);
+                }
+            block_reduce_range(lo, hi, nz, bad, scratch);
+            auto get = [&](int j) { return (unsigned long long)h[j]; };
+            auto put = [&](int j, int c) { lut[j] = (unsigned char)c; };
+            auto clear = [&](int j) { h[j] = 0u; };
+            const CutParams p = block_cutoff<BLOCK>(lo, hi, nz, bad, n, tol, score_mode,
+                                                    nonstrict, get, put, clear, out + I.inst,
+                                                    nullptr);
+            if (tid == 0) h[W] = 0u;
+            __syncthreads();
+            if (!p.skip) {
+                Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+                accumulate_range(xi, yi, 0, n, vec, key_mode, lut, p.e_max, p.c32, a);
+                block_reduce3<BLOCK>(a, red);
+                if (tid == 0) combine_value(a, p.e_max, p.t, p.c32, p.flags, out + I.inst);
+            }
+        } else if (I.type == IT_P1) {
+            BLarge *L = large + I.large;
+            unsigned int *gh = ghist + (size_t)I.large * W;
+            unsigned int nz = 0, bad = 0;
+            scan_into(xi, yi, I.begin, I.end, vec, key_mode, h, nz, bad);
+            __syncthreads();
+            int lo = W, hi = -1;
+            for (int j = tid; j < W; j += BLOCK) {
+                const unsigned int v = h[j];
+                if (v) {
+                    atomicAdd(&gh[j], v);
+                    h[j] = 0u;
+                    lo = min(lo, j);
+                    hi = max(hi, j);
+                }
+            }
+            if (tid == 0) h[W] = 0u;
+            block_reduce_range(lo, hi, nz, bad, scratch);
+            if (tid == 0) {
+                if (hi >= 0) {
+                    atomicMin(&L->lo, lo);
+                    atomicMax(&L->hi, hi);
+                }
+                if (nz) atomicAdd(&L->n_zero, (unsigned long long)nz);
+                if (bad) atomicOr(&L->bad, 1u);
+            }
+            // every thread's merge atomics happen before the completion count
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (tid == 0) {
+                const unsigned int prev = __hip_atomic_fetch_add(&L->p1_done, 1u, __ATOMIC_ACQ_REL,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                s_flag = (prev + 1 == L->nchunks);
+            }
+            __syncthreads();
+            if (s_flag) {
+                // last P1 chunk of this instance: its cutoff selection
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const int glo = __hip_atomic_load(&L->lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int ghi = __hip_atomic_load(&L->hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long gnz =
+                    __hip_atomic_load(&L->n_zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned int gbad =
+                    __hip_atomic_load(&L->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                unsigned char *gl = glut + (size_t)I.large * W_LUT;
+                auto get = [&](int j) {
+                    return (unsigned long long)__hip_atomic_load(&gh[j], __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                };
+                auto put = [&](int j, int c) { gl[j] = (unsigned char)c; };
+                auto clear = [&](int j) { gh[j] = 0u; };
+                const CutParams p = block_cutoff<BLOCK>(glo, ghi, gnz, gbad, n, tol, score_mode,
+                                                        nonstrict, get, put, clear,
+                                                        out + I.inst, nullptr);
+                if (tid == 0) {
+                    L->e_max = p.e_max;
+                    L->t = p.t;
+                    L->c32 = p.c32;
+                    L->skip = p.skip;
+                    L->flags = p.flags;
+                    L->lo = W;
+                    L->hi = -1;
+                    L->n_zero = 0;
+                    L->bad = 0;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __syncthreads();
+                if (tid == 0)
+                    __hip_atomic_store(&L->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else {  // IT_P2
+            BLarge *L = large + I.large;
+            if (tid == 0)
+                while (__hip_atomic_load(&L->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+                    __builtin_amdgcn_s_sleep(2);
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int skip = L->skip, e_max = L->e_max, c32 = L->c32, t = L->t,
+                      flags = L->flags;
+            if (!skip) {
+                const unsigned int *src =
+                    reinterpret_cast<const unsigned int *>(glut + (size_t)I.large * W_LUT);
+                unsigned int *dst = reinterpret_cast<unsigned int *>(lut);
+                for (int i = tid; i < W_LUT / 4; i += BLOCK) dst[i] = src[i];
+                __syncthreads();
+                Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+                accumulate_range(xi, yi, I.begin, I.end, vec, key_mode, lut, e_max, c32, a);
+                block_reduce3<BLOCK>(a, red);
+                if (tid == 0) {
+                    double *p = partials + (size_t)I.slot * 6;
+                    for (int q = 0; q < 3; q++) {
+                        p[2 * q] = a[q].s;
+                        p[2 * q + 1] = a[q].c;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (tid == 0) {
+                const unsigned int prev = __hip_atomic_fetch_add(&L->p2_done, 1u, __ATOMIC_ACQ_REL,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                s_flag = (prev + 1 == L->nchunks);
+            }
+            __syncthreads();
+            if (s_flag) {
+                // last P2 chunk: combine the instance's partials in chunk order
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (!skip) {
+                    Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+                    const int nc = (int)L->nchunks;
+                    for (int c = tid; c < nc; c += BLOCK) {
+                        const double *p = partials + (size_t)(L->first_slot + c) * 6;
+                        for (int q = 0; q < 3; q++) a[q] = acc_merge(a[q], Acc{p[2 * q], p[2 * q + 1]});
+                    }
+                    block_reduce3<BLOCK>(a, red);
+                    if (tid == 0) combine_value(a, e_max, t, c32, flags, out + I.inst);
+                }
+                if (tid == 0) {
+                    L->p1_done = 0u;
+                    L->p2_done = 0u;
+                    L->ready = 0u;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const unsigned int e = __hip_atomic_fetch_add(&st->exited, 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+        if (e == gridDim.x - 1) {
+            st->next = 0u;
+            st->exited = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host planning
+// ---------------------------------------------------------------------------
+static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
+                          BatchPlan **out)
+{
+    BatchPlan *p = new BatchPlan();
+    p->B = B;
+    p->offsets.assign(host_offsets, host_offsets + B + 1);
+    std::vector<int> big, small;
+    for (int j = 0; j < B; j++) {
+        const int64_t n = host_offsets[j + 1] - host_offsets[j];
+        (n > SMALL_MAX ? big : small).push_back(j);
+    }
+    auto len = [&](int j) { return host_offsets[j + 1] - host_offsets[j]; };
+    std::stable_sort(big.begin(), big.end(), [&](int a, int b) { return len(a) > len(b); });
+    std::stable_sort(small.begin(), small.end(), [&](int a, int b) { return len(a) > len(b); });
+    std::vector<BItem> items;
+    std::vector<BLarge> lg(big.size());
+    int slot = 0;
+    for (size_t L = 0; L < big.size(); L++) {
+        const int j = big[L];
+        const int64_t n = len(j);
+        const unsigned int nc = (unsigned int)((n + CH - 1) / CH);
+        std::memset(&lg[L], 0, sizeof(BLarge));
+        lg[L].nchunks = nc;
+        lg[L].lo = W;
+        lg[L].hi = -1;
+        lg[L].first_slot = slot;
+        for (unsigned int c = 0; c < nc; c++)
+            items.push_back(BItem{IT_P1, j, (int)L, -1, (int64_t)c * CH,
+                                  std::min<int64_t>(n, (int64_t)(c + 1) * CH)});
+        slot += (int)nc;
+    }
+    for (int j : small) items.push_back(BItem{IT_SMALL, j, -1, -1, 0, len(j)});
+    for (size_t L = 0; L < big.size(); L++) {
+        const int j = big[L];
+        const int64_t n = len(j);
+        for (unsigned int c = 0; c < lg[L].nchunks; c++)
+            items.push_back(BItem{IT_P2, j, (int)L, lg[L].first_slot + (int)c, (int64_t)c * CH,
+                                  std::min<int64_t>(n, (int64_t)(c + 1) * CH)});
+    }
+    p->n_items = (int)items.size();
+    p->n_large = (int)big.size();
+    p->n_p2 = slot;
+    const size_t nl = std::max<size_t>(1, big.size());
+    bool ok = hipMalloc((void **)&p->items, sizeof(BItem) * std::max<size_t>(1, items.size())) == hipSuccess &&
+              hipMalloc((void **)&p->large, sizeof(BLarge) * nl) == hipSuccess &&
+              hipMalloc((void **)&p->hist, sizeof(unsigned int) * W * nl) == hipSuccess &&
+              hipMalloc((void **)&p->lut, (size_t)W_LUT * nl) == hipSuccess &&
+              hipMalloc((void **)&p->partials, sizeof(double) * 6 * std::max(1, slot)) == hipSuccess &&
+              hipMalloc((void **)&p->state, sizeof(BState)) == hipSuccess;
+    if (!ok) {
+        free_plan(p);
+        return fail(h, QDOT_E_NOMEM, "batched plan allocation failed");
+    }
+    hipError_t e = hipMemcpy(p->items, items.data(), sizeof(BItem) * items.size(),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess && !lg.empty())
+        e = hipMemcpy(p->large, lg.data(), sizeof(BLarge) * lg.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->hist, 0, sizeof(unsigned int) * W * nl);
+    if (e == hipSuccess) e = hipMemset(p->lut, 0, (size_t)W_LUT * nl);
+    if (e == hipSuccess) e = hipMemset(p->state, 0, sizeof(BState));
+    if (e == hipSuccess && !lg.empty()) {
+        hipLaunchKernelGGL(k_batch_init, dim3((unsigned)((lg.size() + BLOCK - 1) / BLOCK)),
+                           dim3(BLOCK), 0, 0, p->large, (int)lg.size(), p->lut);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(h, e, "batched plan upload");
+    }
+    *out = p;
+    return QDOT_OK;
+}
+
+static int32_t find_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B, BatchPlan **out)
+{
+    static uint64_t clock = 0;
+    for (void *vp : h->plans) {
+        BatchPlan *p = (BatchPlan *)vp;
+        if (p->B == B && std::equal(p->offsets.begin(), p->offsets.end(), host_offsets)) {
+            p->last_use = ++clock;
+            *out = p;
+            return QDOT_OK;
+        }
+    }
+    BatchPlan *p = nullptr;
+    int32_t st = build_plan(h, host_offsets, B, &p);
+    if (st != QDOT_OK) return st;
+    p->last_use = ++clock;
+    if ((int)h->plans.size() >= MAX_PLANS) {
+        auto oldest = std::min_element(h->plans.begin(), h->plans.end(), [](void *a, void *b) {
+            return ((BatchPlan *)a)->last_use < ((BatchPlan *)b)->last_use;
+        });
+        (void)hipDeviceSynchronize();
+        free_plan((BatchPlan *)*oldest);
+        h->plans.erase(oldest);
+    }
+    h->plans.push_back(p);
+    *out = p;
+    return QDOT_OK;
+}
+
+void free_plans(qdot_handle *h)
+{
+    for (void *p : h->plans) free_plan((BatchPlan *)p);
+    h->plans.clear();
+}
+
+static int32_t check_batch(qdot_handle *h, const int64_t *host_offsets, int32_t B)
+{
+    if (B < 0 || (B > 0 && !host_offsets)) return fail(h, QDOT_E_INVAL, "bad batch size or offsets");
+    if (B > 0 && host_offsets[0] != 0) return fail(h, QDOT_E_INVAL, "offsets[0] must be 0");
+    for (int j = 0; j < B; j++)
+        if (host_offsets[j + 1] < host_offsets[j])
+            return fail(h, QDOT_E_INVAL, "offsets must be non-decreasing");
+    return QDOT_OK;
+}
+
+}  // namespace qd
+
+using namespace qd;
+
+extern "C" {
+
+int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B)
+{
+    if (!h) return QDOT_E_INVAL;
+    int32_t st = check_batch(h, host_offsets, B);
+    if (st != QDOT_OK || B == 0) return st;
+    DeviceGuard g(h->device);
+    BatchPlan *p = nullptr;
+    return find_plan(h, host_offsets, B, &p);
+}
+
+int32_t qdot_batched_async(qdot_handle *h, const double *x_cat, const double *y_cat,
+                           const int64_t *offsets, const int64_t *host_offsets,
+                           const double *tols, int32_t B, const qdot_options *opt,
+                           void *stream, qdot_result *dev_out)
+{
+    if (!h) return QDOT_E_INVAL;
+    int32_t st = check_batch(h, host_offsets, B);
+    if (st != QDOT_OK) return st;
+    if (B == 0) return QDOT_OK;
+    const int64_t total = host_offsets[B];
+    if ((total > 0 && (!x_cat || !y_cat)) || !offsets || !tols || !dev_out)
+        return fail(h, QDOT_E_INVAL, "NULL pointer");
+    if (((uintptr_t)x_cat | (uintptr_t)y_cat) & 7)
+        return fail(h, QDOT_E_INVAL, "vectors not 8-byte aligned");
+    qdot_options o;
+    std::memset(&o, 0, sizeof o);
+    if (opt) o = *opt;
+    if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    DeviceGuard g(h->device);
+    BatchPlan *p = nullptr;
+    if ((st = find_plan(h, host_offsets, B, &p)) != QDOT_OK) return st;
+    const int grid = std::max(1, std::min(p->n_items, h->batch_blocks_per_cu * h->num_cus));
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets, tols,
+                       p->items, p->n_items, p->large, p->hist, p->lut, p->partials, p->state,
+                       dev_out, o.key_mode, o.score_mode, o.boundary_mode);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "batched launch");
+}
+
+}  // extern "C"

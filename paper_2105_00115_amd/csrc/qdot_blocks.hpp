@@ -1,0 +1,388 @@
+// Block-level pieces shared by the single-vector kernels and the persistent
+// batched kernel: streaming loops, the cutoff selection of one qdot by one
+// workgroup, the per-group leaf computation, and the final combine.
+#pragma once
+
+#include <climits>
+
+#include "qdot_device.hpp"
+
+namespace qd {
+
+// ---- loads ---------------------------------------------------------------
+template <bool VEC>
+__device__ __forceinline__ void load4_full(const double *__restrict__ p, double v[4])
+{
+    if (VEC) {
+        const double2 a = *reinterpret_cast<const double2 *>(p);
+        const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = b.x;
+        v[3] = b.y;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++) v[e] = p[e];
+    }
+}
+
+__device__ __forceinline__ void load4_tail(const double *__restrict__ p, int lim, double v[4])
+{
+#pragma unroll
+    for (int e = 0; e < 4; e++) v[e] = e < lim ? p[e] : 0.0;
+}
+
+// Grid-stride walk over groups of CHUNK * U consecutive components.  Whole
+// groups are loaded without bounds checks; the single partial group (met by
+// one block at most) is loaded with per-lane limits.  body(xv, yv, i0, lim)
+// sees 4 consecutive components i0..i0+3 of which the first `lim` are real;
+// it is called with every lane of the block active.
+template <bool VEC, int U, class Body>
+__device__ __forceinline__ void stream_groups(const double *__restrict__ x,
+                                              const double *__restrict__ y, int64_t n,
+                                              Body &&body)
+{
+    const int64_t group = (int64_t)CHUNK * U;
+    const int64_t step = (int64_t)gridDim.x * group;
+    int64_t base = (int64_t)blockIdx.x * group;
+    for (; base + group <= n; base += step) {
+        double xv[U][4], yv[U][4];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            load4_full<VEC>(x + i0, xv[u]);
+            load4_full<VEC>(y + i0, yv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            body(xv[u], yv[u], base + (int64_t)u * CHUNK + threadIdx.x * EPT, 4);
+    }
+    if (base < n) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            const int64_t left = n - i0;
+            const int lim = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
+            double xv[4], yv[4];
+            load4_tail(x + i0, lim, xv);
+            load4_tail(y + i0, lim, yv);
+            body(xv, yv, i0, lim);
+        }
+    }
+}
+
+// One block walks components [begin, end) of x, y (indices relative to the
+// vector start, begin a multiple of CHUNK) in groups of CHUNK.
+template <bool VEC, class Body>
+__device__ __forceinline__ void stream_block_range(const double *__restrict__ x,
+                                                   const double *__restrict__ y, int64_t begin,
+                                                   int64_t end, Body &&body)
+{
+    int64_t base = begin;
+    for (; base + CHUNK <= end; base += CHUNK) {
+        const int64_t i0 = base + threadIdx.x * EPT;
+        double xv[4], yv[4];
+        load4_full<VEC>(x + i0, xv);
+        load4_full<VEC>(y + i0, yv);
+        body(xv, yv, i0, 4);
+    }
+    if (base < end) {
+        const int64_t i0 = base + threadIdx.x * EPT;
+        const int64_t left = end - i0;
+        const int lim = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
+        double xv[4], yv[4];
+        load4_tail(x + i0, lim, xv);
+        load4_tail(y + i0, lim, yv);
+        body(xv, yv, i0, lim);
+    }
+}
+
+__device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// ---- cutoff selection (Alg. 2: bins -> scores -> precisions) ------------
+
+// t = floor(log2(eps / nb)): the largest integer tau with nb * 2^tau <= eps,
+// by integer comparison of 53-bit significands.  With eps = S * 2^(E - 52),
+// S in [2^52, 2^53), and nb scaled to N' = nb * 2^(53 - b) in the same
+// range (b = bit length of nb): nb * 2^tau = N' * 2^(tau - 53 + b), so
+// tau = E + 1 - b when N' <= S, else E - b.
+__device__ __forceinline__ int floor_log2_ratio(double eps, unsigned long long nb)
+{
+    const uint64_t bits = (uint64_t)__double_as_longlong(eps);
+    const Split s = split_bits(bits);
+    const uint64_t S = s.frac | (1ull << 52);
+    const int b = 64 - __clzll(nb);
+    const uint64_t Np = nb << (53 - b);
+    return s.e + 1 - b - (Np > S ? 1 : 0);
+}
+
+__device__ __forceinline__ int class_of(int sigma, int nonstrict)
+{
+    // eq. (precision-def) with m_half = 10, m_single = 23; the non-strict
+    // reading moves every boundary up by one (score <= m qualifies).
+    const int o = nonstrict ? 1 : 0;
+    if (sigma < 0 + o) return QDOT_PERF;
+    if (sigma < 10 + o) return QDOT_HALF;
+    if (sigma < 23 + o) return QDOT_SINGLE;
+    return QDOT_DOUBLE;
+}
+
+__device__ __forceinline__ double eps_of_class(int c)
+{
+    return c == QDOT_DOUBLE ? 0x1p-52 : c == QDOT_SINGLE ? 0x1p-23
+         : c == QDOT_HALF ? 0x1p-10 : 1.0;
+}
+
+struct CutParams {
+    int e_max, t, c32, skip, flags;
+};
+
+// Cutoff selection of one qdot by one workgroup of NT threads (all of them
+// must call it).  Only slots lo..hi may hold counts: get(j) returns the count
+// of slot j, clear(j) resets it after use, put(j, cls) stores the class of
+// slot j.  Writes every field of *out except value and part (which the
+// combine writes) unless nothing is to be accumulated, in which case *out is
+// final.  Returns the parameters of pass 2 to every thread.
+template <int NT, class Get, class Put, class Clear>
+__device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsigned int bad,
+                                  int64_t n, double tol, int score_mode, int nonstrict,
+                                  Get get, Put put, Clear clear, qdot_result *out,
+                                  long long *hist_out)
+{
+    constexpr int NW = NT / 64;
+    __shared__ int s_max[NW], s_min[NW], s_nb[NW], s_unatt[NW];
+    __shared__ unsigned long long s_cnt[NW][4];
+    __shared__ double s_bound[NW];
+    __shared__ CutParams s_prm;
+    __shared__ int s_go;
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // counts are read twice (here and when classifying) rather than kept in
+    // registers: the window is short and the reads hit LDS or L2
+    int emax = INT_MIN, emin = INT_MAX, nb = 0;
+    for (int j = lo + tid; j <= hi; j += NT) {
+        const unsigned long long v = (unsigned long long)get(j);
+        if (hist_out) hist_out[j] = (long long)v;
+        if (v) {
+            const int k = j + KMIN;
+            emax = max(emax, k);
+            emin = min(emin, k);
+            nb++;
+        }
+    }
+    if (hist_out)
+        for (int j = tid; j < W; j += NT)
+            if (j < lo || j > hi) hist_out[j] = 0ll;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        emax = max(emax, __shfl_xor(emax, m, 64));
+        emin = min(emin, __shfl_xor(emin, m, 64));
+        nb += __shfl_xor(nb, m, 64);
+    }
+    if (lane == 0) {
+        s_max[wv] = emax;
+        s_min[wv] = emin;
+        s_nb[wv] = nb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int a = INT_MIN, b = INT_MAX, c = 0;
+        for (int w = 0; w < NW; w++) {
+            a = max(a, s_max[w]);
+            b = min(b, s_min[w]);
+            c += s_nb[w];
+        }
+        out->n_zero = (long long)nzero;
+        out->n_bins = c;
+        out->e_max = c ? a : 0;
+        out->e_min = c ? b : 0;
+        for (int q = 0; q < 3; q++) out->part[q] = 0.0;
+        int go = 1, t = 0;
+        const bool tol_ok = tol > 0.0 && !__builtin_isinf(tol) && !__builtin_isnan(tol);
+        if (bad || !tol_ok) {
+            go = 0;
+            out->value = __longlong_as_double(0x7ff8000000000000ll);
+            for (int q = 0; q < 4; q++) out->count[q] = 0;
+            out->status = bad ? QDOT_E_NONFINITE : QDOT_E_INVAL;
+            out->flags = 0;
+            out->t = 0;
+            out->bound_rel = out->bound_abs = 0.0;
+        } else if (c == 0) {
+            go = 0;
+            out->value = 0.0;
+            for (int q = 0; q < 3; q++) out->count[q] = 0;
+            out->count[QDOT_PERF] = n;
+            out->status = QDOT_OK;
+            out->flags = QDOT_F_ALL_PERF;
+            out->t = 0;
+            out->bound_rel = out->bound_abs = 0.0;
+        } else {
+            t = floor_log2_ratio(tol, score_mode == 0 ? (unsigned long long)c : 1ull);
+            out->t = t;
+            out->status = QDOT_OK;
+        }
+        s_prm.e_max = a;
+        s_prm.t = t;
+        s_prm.c32 = a + t + 22;
+        s_prm.skip = 1;
+        s_prm.flags = 0;
+        s_go = go;
+    }
+    __syncthreads();
+    const int go = s_go;
+    const int e_max = s_prm.e_max, t = s_prm.t;
+
+    unsigned long long cc[4] = {0, 0, 0, 0};
+    double bound = 0.0;
+    int unatt = 0;
+    for (int j = lo + tid; j <= hi; j += NT) {
+        const unsigned long long v = (unsigned long long)get(j);
+        int cls = QDOT_PERF;
+        if (go && v) {
+            const int k = j + KMIN;
+            // eq. (bin-score-def) with exact bins (u_k = k)
+            const int sigma = ceil_log2_u64(v) + k - e_max - t + 1;
+            cls = class_of(sigma, nonstrict);
+            unatt |= sigma >= 52 + (nonstrict ? 1 : 0);
+            cc[cls] += v;
+            // Thm 3.3 term M_k 2^(k - e_max + 1) eps(class)
+            bound += ldexp((double)v * eps_of_class(cls), k - e_max + 1);
+        }
+        put(j, cls);
+        clear(j);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) cc[q] += __shfl_xor(cc[q], m, 64);
+        bound += __shfl_xor(bound, m, 64);
+        unatt |= __shfl_xor(unatt, m, 64);
+    }
+    if (lane == 0) {
+        for (int q = 0; q < 4; q++) s_cnt[wv][q] = cc[q];
+        s_bound[wv] = bound;
+        s_unatt[wv] = unatt;
+    }
+    __syncthreads();
+    if (tid == 0 && go) {
+        unsigned long long tc[4] = {0, 0, 0, 0};
+        double bsum = 0.0;
+        int ua = 0;
+        for (int w = 0; w < NW; w++) {
+            for (int q = 0; q < 4; q++) tc[q] += s_cnt[w][q];
+            bsum += s_bound[w];
+            ua |= s_unatt[w];
+        }
+        tc[QDOT_PERF] += nzero;
+        for (int q = 0; q < 4; q++) out->count[q] = (long long)tc[q];
+        out->bound_rel = bsum;
+        out->bound_abs = ldexp(bsum, e_max);
+        int flags = ua ? QDOT_F_UNATTAINABLE : 0;
+        // Thm 3.6: e_max - e_min <= -t - m_single
+        if ((long long)e_max - out->e_min <= -(long long)t - 23) flags |= QDOT_F_THM_ALL_DOUBLE;
+        const bool none_kept = (tc[0] + tc[1] + tc[2]) == 0;
+        if (none_kept) {
+            flags |= QDOT_F_ALL_PERF;
+            out->value = 0.0;
+        }
+        out->flags = flags;
+        s_prm.flags = flags;
+        s_prm.skip = none_kept ? 1 : 0;
+    }
+    __syncthreads();
+    return s_prm;
+}
+
+// ---- pass 2: leaves of 4 consecutive components ---------------------------
+//
+// Leaves (exact powers of two scale them; the FP64 result is multiplied by
+// 2^e_max once at the end):
+//   double: fl64(m_x m_y) * 2^(E_x + E_y - e_max)
+//   single: fl32(fl32(m_x) fl32(m_y)) * 2^(E_x + E_y - c32)
+//   half  : h16(m_x) h16(m_y) * 2^(E_x + E_y - c32)  (22-bit product, exact)
+// with c32 = e_max + t + 22, which keeps every FP32 leaf normal and < 4.
+// All three candidates are formed without branches and the class selects
+// one; the only branch is the rare zero/subnormal operand path.  The FP32
+// leaves of the 64-element tile are reduced by the adjacent-pairwise tree
+// (levels 1-2 in the lane, 3-6 across the 16-lane row), and one lane per
+// row adds the two tile sums to its FP64 accumulators.  Every lane of the
+// wave must be active.
+template <bool CLS>
+__device__ __forceinline__ void acc_group(const double *xv, const double *yv, int lim,
+                                          const unsigned char *lut, int key_mode, int e_max,
+                                          int c32, bool accumulate, Acc &aD, Acc &aS, Acc &aH,
+                                          unsigned char *cls_out)
+{
+    float ls[4], lh[4];
+    double ld[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const Comp c = component(xv[e], yv[e], key_mode);
+        const bool valid = e < lim;
+        const int cls = valid ? (int)lut[c.slot] : QDOT_PERF;
+        if (CLS && valid) cls_out[e] = (unsigned char)cls;
+        double dl = ldexp(c.mp, c.es - e_max);
+        dl = __longlong_as_double(__double_as_longlong(dl) ^ ((long long)c.sgn << 32));
+        const float ps = (float)c.mx * (float)c.my;
+        const float ph = (float)(half_round(c.mx) * half_round(c.my));
+        float l32 = ldexpf(cls == QDOT_HALF ? ph : ps, c.es - c32);
+        l32 = __int_as_float(__float_as_int(l32) ^ (int)c.sgn);
+        ld[e] = cls == QDOT_DOUBLE ? dl : 0.0;
+        ls[e] = cls == QDOT_SINGLE ? l32 : 0.0f;
+        lh[e] = cls == QDOT_HALF ? l32 : 0.0f;
+    }
+    if (accumulate) {
+        const float s4 = (ls[0] + ls[1]) + (ls[2] + ls[3]);
+        const float h4 = (lh[0] + lh[1]) + (lh[2] + lh[3]);
+        const float ts = tile_levels_3to6(s4);
+        const float th = tile_levels_3to6(h4);
+        acc_add(aD, (ld[0] + ld[1]) + (ld[2] + ld[3]));
+        if ((threadIdx.x & 15) == 0) {
+            acc_add(aS, (double)ts);
+            acc_add(aH, (double)th);
+        }
+    }
+}
+
+// Reduce three compensated accumulators over the block; the result is valid
+// in thread 0.  red must hold 3 * (blockDim / 64) entries.
+template <int NT>
+__device__ __forceinline__ void block_reduce3(Acc a[3], Acc (*red)[NT / 64])
+{
+    for (int q = 0; q < 3; q++) a[q] = wave_reduce(a[q]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        for (int q = 0; q < 3; q++) red[q][wv] = a[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; q++) {
+            Acc b = red[q][0];
+            for (int w = 1; w < NT / 64; w++) b = acc_merge(b, red[q][w]);
+            a[q] = b;
+        }
+}
+
+// value = 2^e_max (D + 2^(c32 - e_max) (S + H)), parts, overflow flag.
+__device__ __forceinline__ void combine_value(const Acc f[3], int e_max, int t, int c32,
+                                              int flags, qdot_result *out)
+{
+    Acc tot = f[0];
+    acc_add(tot, ldexp(f[1].s, t + 22));
+    acc_add(tot, ldexp(f[2].s, t + 22));
+    tot.c = tot.c + ldexp(f[1].c + f[2].c, t + 22);
+    const double S = tot.s + tot.c;
+    const double value = ldexp(S, e_max);
+    out->value = value;
+    out->part[QDOT_DOUBLE] = ldexp(f[0].s + f[0].c, e_max);
+    out->part[QDOT_SINGLE] = ldexp(f[1].s + f[1].c, c32);
+    out->part[QDOT_HALF] = ldexp(f[2].s + f[2].c, c32);
+    out->flags = flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
+}
+
+}  // namespace qd

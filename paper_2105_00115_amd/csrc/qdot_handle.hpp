@@ -25,6 +25,10 @@ struct qdot_handle {
     double *dres = nullptr;          // FP64-dot result slots
     void *host_ctl = nullptr;        // pinned mirror of ctl
 
+    // batched qdot: cached work plans (one per offsets layout) and grid size
+    std::vector<void *> plans;
+    int batch_blocks_per_cu = 4;
+
     // kernel timing (diagnostics)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool; // created events, reused after each read
@@ -59,5 +63,6 @@ bool tune_ok(const qdot_tune &t);
 // or NULL when timing is off or events cannot be created.
 hipEvent_t *take_events(qdot_handle *h, int kind);
 bool options_ok(const qdot_options &o);
+void free_plans(qdot_handle *h);
 
 }  // namespace qd

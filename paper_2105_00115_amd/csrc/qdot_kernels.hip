@@ -10,77 +10,9 @@
 // re-reads what the same XCD fetched in the first.
 #include "qdot_kernels.hpp"
 
-#include <climits>
+#include "qdot_blocks.hpp"
 
 namespace qd {
-
-template <bool VEC>
-__device__ __forceinline__ void load4_full(const double *__restrict__ p, double v[4])
-{
-    if (VEC) {
-        const double2 a = *reinterpret_cast<const double2 *>(p);
-        const double2 b = *reinterpret_cast<const double2 *>(p + 2);
-        v[0] = a.x;
-        v[1] = a.y;
-        v[2] = b.x;
-        v[3] = b.y;
-    } else {
-#pragma unroll
-        for (int e = 0; e < 4; e++) v[e] = p[e];
-    }
-}
-
-__device__ __forceinline__ void load4_tail(const double *__restrict__ p, int lim, double v[4])
-{
-#pragma unroll
-    for (int e = 0; e < 4; e++) v[e] = e < lim ? p[e] : 0.0;
-}
-
-// Grid-stride walk over groups of CHUNK * U consecutive components.  Whole
-// groups are loaded without bounds checks; the single partial group (met by
-// one block at most) is loaded with per-lane limits.  body(xv, yv, i0, lim)
-// sees 4 consecutive components i0..i0+3 of which the first `lim` are real;
-// it is called with every lane of the block active.
-template <bool VEC, int U, class Body>
-__device__ __forceinline__ void stream_groups(const double *__restrict__ x,
-                                              const double *__restrict__ y, int64_t n,
-                                              Body &&body)
-{
-    const int64_t group = (int64_t)CHUNK * U;
-    const int64_t step = (int64_t)gridDim.x * group;
-    int64_t base = (int64_t)blockIdx.x * group;
-    for (; base + group <= n; base += step) {
-        double xv[U][4], yv[U][4];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
-            load4_full<VEC>(x + i0, xv[u]);
-            load4_full<VEC>(y + i0, yv[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++)
-            body(xv[u], yv[u], base + (int64_t)u * CHUNK + threadIdx.x * EPT, 4);
-    }
-    if (base < n) {
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
-            const int64_t left = n - i0;
-            const int lim = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
-            double xv[4], yv[4];
-            load4_tail(x + i0, lim, xv);
-            load4_tail(y + i0, lim, yv);
-            body(xv, yv, i0, lim);
-        }
-    }
-}
-
-__device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
 
 // ---------------------------------------------------------------------------
 // Pass 1 (Alg. 2, exponent preprocessing + counting): product exponents into
@@ -144,58 +76,20 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
 }
 
 // ---------------------------------------------------------------------------
-// Cutoff selection (Alg. 2, bins -> scores -> precisions), one workgroup.
+// Cutoff selection (Alg. 2, bins -> scores -> precisions), one workgroup over
+// the live slot window of the 8 histogram copies.
 // ---------------------------------------------------------------------------
-
-// t = floor(log2(eps / nb)): the largest integer tau with nb * 2^tau <= eps,
-// by integer comparison of 53-bit significands.  With eps = S * 2^(E - 52),
-// S in [2^52, 2^53), and nb scaled to N' = nb * 2^(53 - b) in the same
-// range (b = bit length of nb): nb * 2^tau = N' * 2^(tau - 53 + b), so
-// tau = E + 1 - b when N' <= S, else E - b.
-__device__ int floor_log2_ratio(double eps, unsigned long long nb)
-{
-    const uint64_t bits = (uint64_t)__double_as_longlong(eps);
-    const Split s = split_bits(bits);
-    const uint64_t S = s.frac | (1ull << 52);
-    const int b = 64 - __clzll(nb);
-    const uint64_t Np = nb << (53 - b);
-    return s.e + 1 - b - (Np > S ? 1 : 0);
-}
-
-__device__ __forceinline__ int class_of(int sigma, int nonstrict)
-{
-    // eq. (precision-def) with m_half = 10, m_single = 23; the non-strict
-    // reading moves every boundary up by one (score <= m qualifies).
-    const int o = nonstrict ? 1 : 0;
-    if (sigma < 0 + o) return QDOT_PERF;
-    if (sigma < 10 + o) return QDOT_HALF;
-    if (sigma < 23 + o) return QDOT_SINGLE;
-    return QDOT_DOUBLE;
-}
-
-__device__ __forceinline__ double eps_of_class(int c)
-{
-    return c == QDOT_DOUBLE ? 0x1p-52 : c == QDOT_SINGLE ? 0x1p-23
-         : c == QDOT_HALF ? 0x1p-10 : 1.0;
-}
-
 __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double tol,
                                                      int score_mode, int nonstrict,
                                                      int64_t n, int nscan,
                                                      qdot_result *__restrict__ out,
                                                      long long *__restrict__ hist_out)
 {
-    constexpr int R = (W + CUT_THREADS - 1) / CUT_THREADS;
     constexpr int NW = CUT_THREADS / 64;
-    __shared__ int s_max[NW], s_min[NW], s_nb[NW], s_unatt[NW];
-    __shared__ unsigned long long s_cnt[NW][4];
-    __shared__ double s_bound[NW];
-    __shared__ int s_emax, s_t, s_go;
-
+    __shared__ int s_lo[NW], s_hi[NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // only the slot window pass 1 touched holds counts; slots outside it are
     // zero in every copy and their class-table entries are never read
-    __shared__ int s_lo[NW], s_hi[NW];
     int lo = W, hi = -1;
     {
         int a = W, b = -1;
@@ -219,157 +113,30 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
             hi = max(hi, s_hi[w]);
         }
     }
-    unsigned long long cnt[R];
-    int emax = INT_MIN, emin = INT_MAX, nb = 0;
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int j = lo + tid + r * CUT_THREADS;
+    const unsigned long long nzero = ws->n_zero;
+    const unsigned int bad = ws->nonfinite;
+    auto get = [&](int j) {
         unsigned long long v = 0ull;
-        if (j <= hi)
 #pragma unroll
-            for (int c = 0; c < HIST_COPIES; c++) v += ws->hist[c][j];
-        cnt[r] = v;
-        if (cnt[r]) {
-            const int k = j + KMIN;
-            emax = max(emax, k);
-            emin = min(emin, k);
-            nb++;
-        }
-    }
-    if (hist_out) {
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const int j = lo + tid + r * CUT_THREADS;
-            if (j <= hi) hist_out[j] = (long long)cnt[r];
-        }
-        for (int j = tid; j < W; j += CUT_THREADS)
-            if (j < lo || j > hi) hist_out[j] = 0ll;
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        emax = max(emax, __shfl_xor(emax, m, 64));
-        emin = min(emin, __shfl_xor(emin, m, 64));
-        nb += __shfl_xor(nb, m, 64);
-    }
-    if (lane == 0) {
-        s_max[wv] = emax;
-        s_min[wv] = emin;
-        s_nb[wv] = nb;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int a = INT_MIN, b = INT_MAX, c = 0;
-        for (int w = 0; w < NW; w++) {
-            a = max(a, s_max[w]);
-            b = min(b, s_min[w]);
-            c += s_nb[w];
-        }
-        const unsigned long long nzero = ws->n_zero;
-        const unsigned int bad = ws->nonfinite;
-        out->n_zero = (long long)nzero;
-        out->n_bins = c;
-        out->e_max = c ? a : 0;
-        out->e_min = c ? b : 0;
-        for (int q = 0; q < 3; q++) out->part[q] = 0.0;
-        int go = 1, t = 0;
-        if (bad) {
-            go = 0;
-            out->value = __longlong_as_double(0x7ff8000000000000ll);
-            for (int q = 0; q < 4; q++) out->count[q] = 0;
-            out->status = QDOT_E_NONFINITE;
-            out->flags = 0;
-            out->t = 0;
-            out->bound_rel = out->bound_abs = 0.0;
-        } else if (c == 0) {
-            go = 0;
-            out->value = 0.0;
-            for (int q = 0; q < 3; q++) out->count[q] = 0;
-            out->count[QDOT_PERF] = n;
-            out->status = QDOT_OK;
-            out->flags = QDOT_F_ALL_PERF;
-            out->t = 0;
-            out->bound_rel = out->bound_abs = 0.0;
-        } else {
-            t = floor_log2_ratio(tol, score_mode == 0 ? (unsigned long long)c : 1ull);
-            out->t = t;
-            out->status = QDOT_OK;
-        }
-        s_emax = a;
-        s_t = t;
-        s_go = go;
-        ws->n_zero = 0;
-        ws->nonfinite = 0;
-    }
-    __syncthreads();
-    const int go = s_go;
-    const int e_max = s_emax, t = s_t;
-
-    unsigned long long cc[4] = {0, 0, 0, 0};
-    double bound = 0.0;
-    int unatt = 0;
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int j = lo + tid + r * CUT_THREADS;
-        if (j > hi) break;
-        int cls = QDOT_PERF;
-        if (go && cnt[r]) {
-            const int k = j + KMIN;
-            // eq. (bin-score-def) with exact bins (u_k = k)
-            const int sigma = ceil_log2_u64(cnt[r]) + k - e_max - t + 1;
-            cls = class_of(sigma, nonstrict);
-            unatt |= sigma >= 52 + (nonstrict ? 1 : 0);
-            cc[cls] += cnt[r];
-            // Thm 3.3 term M_k 2^(k - e_max + 1) eps(class)
-            bound += ldexp((double)cnt[r] * eps_of_class(cls), k - e_max + 1);
-        }
-        ws->lut[j] = (unsigned char)cls;
+        for (int c = 0; c < HIST_COPIES; c++) v += ws->hist[c][j];
+        return v;
+    };
+    auto put = [&](int j, int cls) { ws->lut[j] = (unsigned char)cls; };
+    auto clear = [&](int j) {
 #pragma unroll
         for (int c = 0; c < HIST_COPIES; c++) ws->hist[c][j] = 0ull;
-    }
+    };
+    const CutParams p = block_cutoff<CUT_THREADS>(lo, hi, nzero, bad, n, tol, score_mode,
+                                                  nonstrict, get, put, clear, out, hist_out);
     if (tid < W_LUT - W) ws->lut[W + tid] = (unsigned char)QDOT_PERF;
-
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-#pragma unroll
-        for (int q = 0; q < 4; q++) cc[q] += __shfl_xor(cc[q], m, 64);
-        bound += __shfl_xor(bound, m, 64);
-        unatt |= __shfl_xor(unatt, m, 64);
-    }
-    if (lane == 0) {
-        for (int q = 0; q < 4; q++) s_cnt[wv][q] = cc[q];
-        s_bound[wv] = bound;
-        s_unatt[wv] = unatt;
-    }
-    __syncthreads();
-    if (tid == 0 && go) {
-        unsigned long long tc[4] = {0, 0, 0, 0};
-        double bsum = 0.0;
-        int ua = 0;
-        for (int w = 0; w < NW; w++) {
-            for (int q = 0; q < 4; q++) tc[q] += s_cnt[w][q];
-            bsum += s_bound[w];
-            ua |= s_unatt[w];
-        }
-        tc[QDOT_PERF] += (unsigned long long)out->n_zero;
-        for (int q = 0; q < 4; q++) out->count[q] = (long long)tc[q];
-        out->bound_rel = bsum;
-        out->bound_abs = ldexp(bsum, e_max);
-        int flags = ua ? QDOT_F_UNATTAINABLE : 0;
-        // Thm 3.6: e_max - e_min <= -t - m_single
-        if ((long long)e_max - out->e_min <= -(long long)t - 23) flags |= QDOT_F_THM_ALL_DOUBLE;
-        const bool none_kept = (tc[0] + tc[1] + tc[2]) == 0;
-        if (none_kept) {
-            flags |= QDOT_F_ALL_PERF;
-            out->value = 0.0;
-        }
-        out->flags = flags;
-        ws->flags = flags;
-        ws->e_max = e_max;
-        ws->t = t;
-        ws->c32 = e_max + t + 22;
-        ws->skip = none_kept ? 1 : 0;
-    } else if (tid == 0) {
-        ws->skip = 1;
+    if (tid == 0) {
+        ws->n_zero = 0;
+        ws->nonfinite = 0;
+        ws->e_max = p.e_max;
+        ws->t = p.t;
+        ws->c32 = p.c32;
+        ws->flags = p.flags;
+        ws->skip = p.skip;
     }
 }
 
@@ -412,38 +179,8 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
     const int lane = threadIdx.x & 63;
     Acc aD = {0.0, 0.0}, aS = {0.0, 0.0}, aH = {0.0, 0.0};
     stream_groups<VEC, U>(x, y, n, [&](const double *xv, const double *yv, int64_t i0, int lim) {
-        float ls[4], lh[4];
-        double ld[4];
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const Comp c = component(xv[e], yv[e], key_mode);
-            const bool valid = e < lim;
-            const int cls = valid ? (int)lut[c.slot] : QDOT_PERF;
-            if (CLS && valid) cls_out[i0 + e] = (unsigned char)cls;
-            // double candidate
-            double dl = ldexp(c.mp, c.es - e_max);
-            dl = __longlong_as_double(__double_as_longlong(dl) ^ ((long long)c.sgn << 32));
-            // single and half candidates share one scaling
-            const float ps = (float)c.mx * (float)c.my;
-            const float ph = (float)(half_round(c.mx) * half_round(c.my));
-            float l32 = ldexpf(cls == QDOT_HALF ? ph : ps, c.es - c32);
-            l32 = __int_as_float(__float_as_int(l32) ^ (int)c.sgn);
-            ld[e] = cls == QDOT_DOUBLE ? dl : 0.0;
-            ls[e] = cls == QDOT_SINGLE ? l32 : 0.0f;
-            lh[e] = cls == QDOT_HALF ? l32 : 0.0f;
-        }
-        if (!skip) {
-            // tile tree levels 1-2 in the lane, 3-6 across the row
-            const float s4 = (ls[0] + ls[1]) + (ls[2] + ls[3]);
-            const float h4 = (lh[0] + lh[1]) + (lh[2] + lh[3]);
-            const float ts = tile_levels_3to6(s4);
-            const float th = tile_levels_3to6(h4);
-            acc_add(aD, (ld[0] + ld[1]) + (ld[2] + ld[3]));
-            if ((lane & 15) == 0) {
-                acc_add(aS, (double)ts);
-                acc_add(aH, (double)th);
-            }
-        }
+        acc_group<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
+                       CLS ? cls_out + i0 : nullptr);
     });
     if (skip) return;
 
@@ -491,19 +228,7 @@ __global__ __launch_bounds__(BLOCK) void k_fin(const Ws *__restrict__ ws,
             f[q] = red[q][0];
             for (int w = 1; w < BLOCK / 64; w++) f[q] = acc_merge(f[q], red[q][w]);
         }
-        const int t = ws->t, e_max = ws->e_max, c32 = ws->c32;
-        // S = D + 2^(c32 - e_max) (S + H), with c32 - e_max = t + 22
-        Acc tot = f[0];
-        acc_add(tot, ldexp(f[1].s, t + 22));
-        acc_add(tot, ldexp(f[2].s, t + 22));
-        tot.c = tot.c + ldexp(f[1].c + f[2].c, t + 22);
-        const double S = tot.s + tot.c;
-        const double value = ldexp(S, e_max);
-        out->value = value;
-        out->part[QDOT_DOUBLE] = ldexp(f[0].s + f[0].c, e_max);
-        out->part[QDOT_SINGLE] = ldexp(f[1].s + f[1].c, c32);
-        out->part[QDOT_HALF] = ldexp(f[2].s + f[2].c, c32);
-        out->flags = ws->flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
+        combine_value(f, ws->e_max, ws->t, ws->c32, ws->flags, out);
     }
 }
 
