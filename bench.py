@@ -156,6 +156,8 @@ def main():
     torch.cuda.synchronize()
     torch_dot_ms = e0.elapsed_time(e1) / K
 
+    xh = x[: args.cpu_sample].cpu().numpy()
+    yh = y[: args.cpu_sample].cpu().numpy()
     scan_ms = tq["scan_ms"] / tq["qdot_calls"]
     cut_ms = tq["cut_ms"] / tq["qdot_calls"]
     acc_ms = tq["acc_ms"] / tq["qdot_calls"]
@@ -197,9 +199,45 @@ def main():
     lam_max = 6.0 + 6.0 * float(np.cos(np.pi / (m3 + 1)))
     del A
 
+    # batched ragged qdot: 4096 instances, n = round(10^U[2,6]), tol drawn
+    # from {1e-4, 1e-6, 1e-8}, one persistent launch (replayed as a graph)
+    log("batched ragged qdot, 4096 instances")
+    g = workloads.rng(2025)
+    sizes = np.rint(10.0 ** g.uniform(2, 6, 4096)).astype(np.int64)
+    offs = np.zeros(4097, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    btol = np.array([1e-4, 1e-6, 1e-8])[g.integers(0, 3, 4096)]
+    total = int(offs[-1])
+    del x, y
+    bx, by = workloads.log_uniform_pair_torch(total, 2025, dev)
+    off_d = torch.from_numpy(offs).to(dev)
+    tol_d = torch.from_numpy(btol).to(dev)
+    bout = torch.zeros(4096 * q.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    h.batched_plan(offs)
+    bs = torch.cuda.Stream()
+    bs.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(bs):
+        with torch.cuda.graph(graph, stream=bs):
+            h.batched_async(bx, by, off_d, offs, tol_d, bout)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / 10
+    bres = q.parse_results(bout)
+    batched = {"instances": 4096, "components": total, "ms_per_launch": round(batch_ms, 4),
+               "gelem_s": round(total / (batch_ms * 1e-3) / 1e9, 3),
+               "hbm_frac_2pass": round(32.0 * total / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "statuses_ok": sum(1 for r in bres if r["status"] == 0)}
+    del bx, by
+
     log(f"CPU oracle on a sample of {args.cpu_sample}")
-    xh = x[: args.cpu_sample].cpu().numpy()
-    yh = y[: args.cpu_sample].cpu().numpy()
     cpu = cpu_baseline(xh, yh, tol)
 
     value = n * K / wall / 1e9
@@ -240,6 +278,7 @@ def main():
             "relerr_vs_fp64_dot": abs(res["value"] - dot64) / abs(dot64) if dot64 else None,
             "torch_dot_value": float(tdot.item()),
             "cg_poisson2d_1024": cg,
+            "batched_ragged_4096": batched,
             "power_laplacian3d_128": {**pm, "abs_lambda_diff":
                                       abs(pm["qdot"]["lambda"] - pm["fp64"]["lambda"]),
                                       "lambda_max_closed_form": lam_max},

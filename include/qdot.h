@@ -257,7 +257,11 @@ QDOT_API int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double
  * when sqrt(c_k) <= rtol * ||b||_2 (||b|| by the FP64 dot) or after maxit
  * iterations.  trace: NULL or device qdot_result[2*maxit + 1] receiving
  * every qdot result in call order.  Synchronous; out (host) receives the
- * iteration count, status and residuals.  Returns out->status. */
+ * iteration count, status and residuals.  Returns out->status.
+ * The whole solve is one persistent launch of up to one block per CU
+ * (environment variable QDOT_CG_BLOCKS caps the block count).  A gang
+ * barrier that does not complete within its spin limit ends the solve with
+ * QDOT_E_DEVICE. */
 QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x,
                 double rtol, double qtol, int32_t maxit, int32_t use_qdot,
                 const qdot_options *opt, void *stream, qdot_cg_result *out,

@@ -147,6 +147,7 @@ int32_t qdot_destroy(qdot_handle *h)
     if (h->host_ctl) (void)hipHostFree(h->host_ctl);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     free_plans(h);
+    free_cg(h);
     delete h;
     return QDOT_OK;
 }

@@ -1,9 +1,15 @@
 // Batched ragged qdot: B independent instances in one persistent launch.
 //
 // The host plans a work queue once per offsets layout:
-//   P1    pass-1 chunks (CH components) of the large instances,
-//   SMALL whole small instances (n <= SMALL_MAX), done start to finish by
-//         one block with a block-local cutoff,
+//   P1    pass-1 chunks of the large instances: an instance of n components
+//         has nc = ceil(n / CH) chunks, chunk c taking the GROUP-sized
+//         component groups c, c + nc, c + 2 nc, ... so that the blocks on
+//         one instance read neighbouring addresses at any moment,
+//   SMALL runs of whole small instances (n <= SMALL_MAX each), grouped so
+//         that sum(n + SMALL_COST0) stays within SMALL_GROUP per item (the
+//         fixed term stands for the latency chain of one instance), each
+//         instance done start to finish by one block with a block-local
+//         cutoff,
 //   P2    pass-2 chunks of the large instances,
 // in that order.  Blocks take items from a global ticket.  The block that
 // finishes the last P1 chunk of a large instance runs that instance's cutoff
@@ -17,8 +23,9 @@
 // performs no allocation and no memset and can be captured in a HIP graph.
 //
 // Each instance's 64-element FP32 tiles start at its own first component;
-// chunks are multiples of 1024 components, so tiles never straddle chunks.
+// groups are multiples of 1024 components, so tiles never straddle chunks.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -27,18 +34,22 @@
 
 namespace qd {
 
-constexpr int64_t CH = 32768;        // components per P1 / P2 chunk
-constexpr int64_t SMALL_MAX = 65536; // instances up to this size: one block
+constexpr int64_t CH = 131072;        // components per P1 / P2 chunk
+constexpr int64_t SMALL_MAX = CH;     // instances up to this size: one block
+constexpr int64_t SMALL_COST0 = 8192; // fixed cost of one small instance, in components
+constexpr int64_t SMALL_GROUP = 65536; // cost budget of one item of small instances
+constexpr int SU = 2;                 // CHUNK groups in flight per thread
+constexpr int64_t GROUP = (int64_t)SU * CHUNK;
 constexpr int MAX_PLANS = 8;
 
 enum : int { IT_P1 = 0, IT_SMALL = 1, IT_P2 = 2 };
 
 struct BItem {
     int type;
-    int inst;
-    int large;  // compact index of a large instance (P1, P2)
+    int inst;   // P1 / P2: instance; SMALL: first entry in the small list
+    int large;  // P1 / P2: compact index of the large instance; SMALL: count
     int slot;   // P2: partial slot
-    int64_t begin, end;
+    int64_t first, stride;  // P1 / P2: the chunk's groups (see stream_strided)
 };
 
 struct BLarge {
@@ -65,6 +76,7 @@ struct BatchPlan {
     unsigned char *lut = nullptr;
     double *partials = nullptr;
     BState *state = nullptr;
+    int *small_list = nullptr;
     uint64_t last_use = 0;
 };
 
@@ -77,6 +89,7 @@ void free_plan(BatchPlan *p)
     (void)hipFree(p->lut);
     (void)hipFree(p->partials);
     (void)hipFree(p->state);
+    (void)hipFree(p->small_list);
     delete p;
 }
 
@@ -107,9 +120,10 @@ __device__ __forceinline__ void block_reduce_range(int &lo, int &hi, unsigned in
     }
 }
 
-// Pass 1 of components [b, e) of one instance into the LDS histogram h.
-__device__ __forceinline__ void scan_into(const double *xi, const double *yi, int64_t b,
-                                          int64_t e, bool vec, int key_mode, unsigned int *h,
+// Pass 1 over the groups first, first + stride, ... (below n) of one
+// instance into the LDS histogram h.
+__device__ __forceinline__ void scan_into(const double *xi, const double *yi, int64_t first,
+                                          int64_t stride, int64_t n, bool vec, int key_mode, unsigned int *h,
                                           unsigned int &nz, unsigned int &bad)
 {
     auto body = [&](const double *xv, const double *yv, int64_t, int lim) {
@@ -123,13 +137,14 @@ __device__ __forceinline__ void scan_into(const double *xi, const double *yi, in
         }
     };
     if (vec)
-        stream_block_range<true>(xi, yi, b, e, body);
+        stream_strided<true, SU>(xi, yi, first, stride, n, body);
     else
-        stream_block_range<false>(xi, yi, b, e, body);
+        stream_strided<false, SU>(xi, yi, first, stride, n, body);
 }
 
-__device__ __forceinline__ void accumulate_range(const double *xi, const double *yi, int64_t b,
-                                                 int64_t e, bool vec, int key_mode,
+__device__ __forceinline__ void accumulate_range(const double *xi, const double *yi,
+                                                 int64_t first, int64_t stride, int64_t n,
+                                                 bool vec, int key_mode,
                                                  const unsigned char *lut, int e_max, int c32,
                                                  Acc a[3])
 {
@@ -137,9 +152,9 @@ __device__ __forceinline__ void accumulate_range(const double *xi, const double 
         acc_group<false>(xv, yv, lim, lut, key_mode, e_max, c32, true, a[0], a[1], a[2], nullptr);
     };
     if (vec)
-        stream_block_range<true>(xi, yi, b, e, body);
+        stream_strided<true, SU>(xi, yi, first, stride, n, body);
     else
-        stream_block_range<false>(xi, yi, b, e, body);
+        stream_strided<false, SU>(xi, yi, first, stride, n, body);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_batch_init(BLarge *large, int n_large,
@@ -162,6 +177,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                                                  unsigned char *__restrict__ glut,
                                                  double *__restrict__ partials,
                                                  BState *__restrict__ st,
+                                                 const int *__restrict__ small_list,
                                                  qdot_result *__restrict__ out, int key_mode,
                                                  int score_mode, int nonstrict)
 {
@@ -170,6 +186,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
     __shared__ Acc red[3][BLOCK / 64];
     __shared__ int4 scratch[BLOCK / 64];
     __shared__ int s_item, s_flag;
+    __shared__ int4 s_prm2;
+    __shared__ qdot_result s_res;
     const int tid = threadIdx.x;
 
     for (int i = tid; i < W + 1; i += BLOCK) h[i] = 0;
@@ -183,16 +201,17 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
         __syncthreads();
         if (it >= n_items) break;
         const BItem I = items[it];
-        const int64_t off = offsets[I.inst];
-        const int64_t n = offsets[I.inst + 1] - off;
-        const double *xi = x + off;
-        const double *yi = y + off;
-        const bool vec = ((((uintptr_t)xi) | ((uintptr_t)yi)) & 15) == 0;
-        const double tol = tols[I.inst];
-
         if (I.type == IT_SMALL) {
+          for (int sj = 0; sj < I.large; sj++) {
+            const int inst = small_list[I.inst + sj];
+            const int64_t off = offsets[inst];
+            const int64_t n = offsets[inst + 1] - off;
+            const double *xi = x + off;
+            const double *yi = y + off;
+            const bool vec = ((((uintptr_t)xi) | ((uintptr_t)yi)) & 15) == 0;
+            const double tol = tols[inst];
             unsigned int nz = 0, bad = 0;
-            scan_into(xi, yi, 0, n, vec, key_mode, h, nz, bad);
+            scan_into(xi, yi, 0, GROUP, n, vec, key_mode, h, nz, bad);
             __syncthreads();
             int lo = W, hi = -1;
             for (int j = tid; j < W; j += BLOCK)
@@ -205,27 +224,37 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
             auto put = [&](int j, int c) { lut[j] = (unsigned char)c; };
             auto clear = [&](int j) { h[j] = 0u; };
             const CutParams p = block_cutoff<BLOCK>(lo, hi, nz, bad, n, tol, score_mode,
-                                                    nonstrict, get, put, clear, out + I.inst,
+                                                    nonstrict, get, put, clear, out + inst,
                                                     nullptr);
             if (tid == 0) h[W] = 0u;
             __syncthreads();
             if (!p.skip) {
                 Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-                accumulate_range(xi, yi, 0, n, vec, key_mode, lut, p.e_max, p.c32, a);
+                accumulate_range(xi, yi, 0, GROUP, n, vec, key_mode, lut, p.e_max, p.c32, a);
                 block_reduce3<BLOCK>(a, red);
-                if (tid == 0) combine_value(a, p.e_max, p.t, p.c32, p.flags, out + I.inst);
+                if (tid == 0) combine_value(a, p.e_max, p.t, p.c32, p.flags, out + inst);
             }
-        } else if (I.type == IT_P1) {
+            __syncthreads();
+          }
+          continue;
+        }
+        const int64_t off = offsets[I.inst];
+        const int64_t n = offsets[I.inst + 1] - off;
+        const double *xi = x + off;
+        const double *yi = y + off;
+        const bool vec = ((((uintptr_t)xi) | ((uintptr_t)yi)) & 15) == 0;
+        const double tol = tols[I.inst];
+        if (I.type == IT_P1) {
             BLarge *L = large + I.large;
             unsigned int *gh = ghist + (size_t)I.large * W;
             unsigned int nz = 0, bad = 0;
-            scan_into(xi, yi, I.begin, I.end, vec, key_mode, h, nz, bad);
+            scan_into(xi, yi, I.first, I.stride, n, vec, key_mode, h, nz, bad);
             __syncthreads();
             int lo = W, hi = -1;
             for (int j = tid; j < W; j += BLOCK) {
                 const unsigned int v = h[j];
                 if (v) {
-                    atomicAdd(&gh[j], v);
+                    __hip_atomic_fetch_add(&gh[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     h[j] = 0u;
                     lo = min(lo, j);
                     hi = max(hi, j);
@@ -235,118 +264,135 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
             block_reduce_range(lo, hi, nz, bad, scratch);
             if (tid == 0) {
                 if (hi >= 0) {
-                    atomicMin(&L->lo, lo);
-                    atomicMax(&L->hi, hi);
+                    __hip_atomic_fetch_min(&L->lo, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_max(&L->hi, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                if (nz) atomicAdd(&L->n_zero, (unsigned long long)nz);
-                if (bad) atomicOr(&L->bad, 1u);
+                if (nz)
+                    __hip_atomic_fetch_add(&L->n_zero, (unsigned long long)nz, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                if (bad) __hip_atomic_fetch_or(&L->bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            // every thread's merge atomics happen before the completion count
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            // every thread's merge has completed before the chunk counts itself
+            vmem_drain();
             __syncthreads();
             if (tid == 0) {
-                const unsigned int prev = __hip_atomic_fetch_add(&L->p1_done, 1u, __ATOMIC_ACQ_REL,
+                const unsigned int prev = __hip_atomic_fetch_add(&L->p1_done, 1u, __ATOMIC_RELAXED,
                                                                  __HIP_MEMORY_SCOPE_AGENT);
                 s_flag = (prev + 1 == L->nchunks);
             }
             __syncthreads();
             if (s_flag) {
-                // last P1 chunk of this instance: its cutoff selection
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                const int glo = __hip_atomic_load(&L->lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int ghi = __hip_atomic_load(&L->hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long gnz =
-                    __hip_atomic_load(&L->n_zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned int gbad =
-                    __hip_atomic_load(&L->bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // last P1 chunk of this instance: its cutoff selection, on
+                // the merged histogram that every other chunk completed
+                // before counting itself
+                const int glo = ld_dev(&L->lo);
+                const int ghi = ld_dev(&L->hi);
+                const unsigned long long gnz = ld_dev(&L->n_zero);
+                const unsigned int gbad = ld_dev(&L->bad);
                 unsigned char *gl = glut + (size_t)I.large * W_LUT;
-                auto get = [&](int j) {
-                    return (unsigned long long)__hip_atomic_load(&gh[j], __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT);
-                };
-                auto put = [&](int j, int c) { gl[j] = (unsigned char)c; };
-                auto clear = [&](int j) { gh[j] = 0u; };
+                auto get = [&](int j) { return (unsigned long long)ld_dev(&gh[j]); };
+                auto put = [&](int j, int c) { st_dev(&gl[j], (unsigned char)c); };
+                auto clear = [&](int j) { st_dev(&gh[j], 0u); };
                 const CutParams p = block_cutoff<BLOCK>(glo, ghi, gnz, gbad, n, tol, score_mode,
-                                                        nonstrict, get, put, clear,
-                                                        out + I.inst, nullptr);
+                                                        nonstrict, get, put, clear, &s_res,
+                                                        nullptr);
                 if (tid == 0) {
-                    L->e_max = p.e_max;
-                    L->t = p.t;
-                    L->c32 = p.c32;
-                    L->skip = p.skip;
-                    L->flags = p.flags;
-                    L->lo = W;
-                    L->hi = -1;
-                    L->n_zero = 0;
-                    L->bad = 0;
+                    // the combining block writes value, part and flags; this
+                    // block writes the rest (all of it when nothing is kept)
+                    qdot_result *o = out + I.inst;
+                    for (int q = 0; q < 4; q++) o->count[q] = s_res.count[q];
+                    o->n_zero = s_res.n_zero;
+                    o->e_min = s_res.e_min;
+                    o->e_max = s_res.e_max;
+                    o->n_bins = s_res.n_bins;
+                    o->t = s_res.t;
+                    o->bound_rel = s_res.bound_rel;
+                    o->bound_abs = s_res.bound_abs;
+                    o->status = s_res.status;
+                    if (p.skip) {
+                        o->value = s_res.value;
+                        for (int q = 0; q < 3; q++) o->part[q] = s_res.part[q];
+                        o->flags = s_res.flags;
+                    }
+                    st_dev(&L->e_max, p.e_max);
+                    st_dev(&L->t, p.t);
+                    st_dev(&L->c32, p.c32);
+                    st_dev(&L->skip, p.skip);
+                    st_dev(&L->flags, p.flags);
+                    st_dev(&L->lo, (int)W);
+                    st_dev(&L->hi, -1);
+                    st_dev(&L->n_zero, 0ull);
+                    st_dev(&L->bad, 0u);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                vmem_drain();
                 __syncthreads();
-                if (tid == 0)
-                    __hip_atomic_store(&L->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (tid == 0) st_dev(&L->ready, 1u);
             }
         } else {  // IT_P2
             BLarge *L = large + I.large;
-            if (tid == 0)
-                while (__hip_atomic_load(&L->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-                    __builtin_amdgcn_s_sleep(2);
+            if (tid == 0) {
+                while (ld_dev(&L->ready) == 0u) __builtin_amdgcn_s_sleep(2);
+                s_prm2 = make_int4(ld_dev(&L->skip), ld_dev(&L->e_max), ld_dev(&L->c32),
+                                   ld_dev(&L->flags));
+                s_flag = ld_dev(&L->t);
+            }
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const int skip = L->skip, e_max = L->e_max, c32 = L->c32, t = L->t,
-                      flags = L->flags;
+            const int skip = s_prm2.x, e_max = s_prm2.y, c32 = s_prm2.z, flags = s_prm2.w;
+            const int t = s_flag;
+            __syncthreads();
             if (!skip) {
                 const unsigned int *src =
                     reinterpret_cast<const unsigned int *>(glut + (size_t)I.large * W_LUT);
                 unsigned int *dst = reinterpret_cast<unsigned int *>(lut);
-                for (int i = tid; i < W_LUT / 4; i += BLOCK) dst[i] = src[i];
+                for (int i = tid; i < W_LUT / 4; i += BLOCK) dst[i] = ld_dev(&src[i]);
                 __syncthreads();
                 Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-                accumulate_range(xi, yi, I.begin, I.end, vec, key_mode, lut, e_max, c32, a);
+                accumulate_range(xi, yi, I.first, I.stride, n, vec, key_mode, lut, e_max, c32, a);
                 block_reduce3<BLOCK>(a, red);
                 if (tid == 0) {
                     double *p = partials + (size_t)I.slot * 6;
                     for (int q = 0; q < 3; q++) {
-                        p[2 * q] = a[q].s;
-                        p[2 * q + 1] = a[q].c;
+                        st_dev(&p[2 * q], a[q].s);
+                        st_dev(&p[2 * q + 1], a[q].c);
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            vmem_drain();
             __syncthreads();
             if (tid == 0) {
-                const unsigned int prev = __hip_atomic_fetch_add(&L->p2_done, 1u, __ATOMIC_ACQ_REL,
+                const unsigned int prev = __hip_atomic_fetch_add(&L->p2_done, 1u, __ATOMIC_RELAXED,
                                                                  __HIP_MEMORY_SCOPE_AGENT);
                 s_flag = (prev + 1 == L->nchunks);
             }
             __syncthreads();
             if (s_flag) {
                 // last P2 chunk: combine the instance's partials in chunk order
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 if (!skip) {
                     Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
                     const int nc = (int)L->nchunks;
                     for (int c = tid; c < nc; c += BLOCK) {
                         const double *p = partials + (size_t)(L->first_slot + c) * 6;
-                        for (int q = 0; q < 3; q++) a[q] = acc_merge(a[q], Acc{p[2 * q], p[2 * q + 1]});
+                        for (int q = 0; q < 3; q++)
+                            a[q] = acc_merge(a[q], Acc{ld_dev(&p[2 * q]), ld_dev(&p[2 * q + 1])});
                     }
                     block_reduce3<BLOCK>(a, red);
                     if (tid == 0) combine_value(a, e_max, t, c32, flags, out + I.inst);
                 }
                 if (tid == 0) {
-                    L->p1_done = 0u;
-                    L->p2_done = 0u;
-                    L->ready = 0u;
+                    st_dev(&L->p1_done, 0u);
+                    st_dev(&L->p2_done, 0u);
+                    st_dev(&L->ready, 0u);
                 }
             }
         }
         __syncthreads();
     }
     if (tid == 0) {
-        const unsigned int e = __hip_atomic_fetch_add(&st->exited, 1u, __ATOMIC_ACQ_REL,
+        const unsigned int e = __hip_atomic_fetch_add(&st->exited, 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
         if (e == gridDim.x - 1) {
-            st->next = 0u;
-            st->exited = 0u;
+            st_dev(&st->next, 0u);
+            st_dev(&st->exited, 0u);
         }
     }
 }
@@ -381,17 +427,26 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
         lg[L].hi = -1;
         lg[L].first_slot = slot;
         for (unsigned int c = 0; c < nc; c++)
-            items.push_back(BItem{IT_P1, j, (int)L, -1, (int64_t)c * CH,
-                                  std::min<int64_t>(n, (int64_t)(c + 1) * CH)});
+            items.push_back(BItem{IT_P1, j, (int)L, -1, (int64_t)c * GROUP, (int64_t)nc * GROUP});
         slot += (int)nc;
     }
-    for (int j : small) items.push_back(BItem{IT_SMALL, j, -1, -1, 0, len(j)});
+    std::vector<int> small_list(small.begin(), small.end());
+    for (size_t s0 = 0; s0 < small_list.size();) {
+        size_t s1 = s0;
+        int64_t cost = 0;
+        while (s1 < small_list.size() &&
+               (s1 == s0 || cost + len(small_list[s1]) + SMALL_COST0 <= SMALL_GROUP)) {
+            cost += len(small_list[s1]) + SMALL_COST0;
+            s1++;
+        }
+        items.push_back(BItem{IT_SMALL, (int)s0, (int)(s1 - s0), -1, 0, 0});
+        s0 = s1;
+    }
     for (size_t L = 0; L < big.size(); L++) {
         const int j = big[L];
-        const int64_t n = len(j);
         for (unsigned int c = 0; c < lg[L].nchunks; c++)
-            items.push_back(BItem{IT_P2, j, (int)L, lg[L].first_slot + (int)c, (int64_t)c * CH,
-                                  std::min<int64_t>(n, (int64_t)(c + 1) * CH)});
+            items.push_back(BItem{IT_P2, j, (int)L, lg[L].first_slot + (int)c, (int64_t)c * GROUP,
+                                  (int64_t)lg[L].nchunks * GROUP});
     }
     p->n_items = (int)items.size();
     p->n_large = (int)big.size();
@@ -402,7 +457,8 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
               hipMalloc((void **)&p->hist, sizeof(unsigned int) * W * nl) == hipSuccess &&
               hipMalloc((void **)&p->lut, (size_t)W_LUT * nl) == hipSuccess &&
               hipMalloc((void **)&p->partials, sizeof(double) * 6 * std::max(1, slot)) == hipSuccess &&
-              hipMalloc((void **)&p->state, sizeof(BState)) == hipSuccess;
+              hipMalloc((void **)&p->state, sizeof(BState)) == hipSuccess &&
+              hipMalloc((void **)&p->small_list, sizeof(int) * std::max<size_t>(1, small_list.size())) == hipSuccess;
     if (!ok) {
         free_plan(p);
         return fail(h, QDOT_E_NOMEM, "batched plan allocation failed");
@@ -414,6 +470,9 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     if (e == hipSuccess) e = hipMemset(p->hist, 0, sizeof(unsigned int) * W * nl);
     if (e == hipSuccess) e = hipMemset(p->lut, 0, (size_t)W_LUT * nl);
     if (e == hipSuccess) e = hipMemset(p->state, 0, sizeof(BState));
+    if (e == hipSuccess && !small_list.empty())
+        e = hipMemcpy(p->small_list, small_list.data(), sizeof(int) * small_list.size(),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess && !lg.empty()) {
         hipLaunchKernelGGL(k_batch_init, dim3((unsigned)((lg.size() + BLOCK - 1) / BLOCK)),
                            dim3(BLOCK), 0, 0, p->large, (int)lg.size(), p->lut);
@@ -509,11 +568,13 @@ int32_t qdot_batched_async(qdot_handle *h, const double *x_cat, const double *y_
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
     if ((st = find_plan(h, host_offsets, B, &p)) != QDOT_OK) return st;
-    const int grid = std::max(1, std::min(p->n_items, h->batch_blocks_per_cu * h->num_cus));
+    int bpc = h->batch_blocks_per_cu;
+    if (const char *e = std::getenv("QDOT_BATCH_BLOCKS_PER_CU")) bpc = std::max(1, std::min(16, std::atoi(e)));
+    const int grid = std::max(1, std::min(p->n_items, bpc * h->num_cus));
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets, tols,
                        p->items, p->n_items, p->large, p->hist, p->lut, p->partials, p->state,
-                       dev_out, o.key_mode, o.score_mode, o.boundary_mode);
+                       p->small_list, dev_out, o.key_mode, o.score_mode, o.boundary_mode);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "batched launch");
 }

@@ -37,15 +37,18 @@ __device__ __forceinline__ void load4_tail(const double *__restrict__ p, int lim
 // one block at most) is loaded with per-lane limits.  body(xv, yv, i0, lim)
 // sees 4 consecutive components i0..i0+3 of which the first `lim` are real;
 // it is called with every lane of the block active.
+// One block walks groups of U * CHUNK components of x, y: the groups that
+// start at first, first + stride, first + 2 * stride, ... below n (stride a
+// multiple of U * CHUNK).  Each thread loads EPT consecutive components of
+// each CHUNK, U CHUNKs in flight; the one partial group is bounds-checked.
 template <bool VEC, int U, class Body>
-__device__ __forceinline__ void stream_groups(const double *__restrict__ x,
-                                              const double *__restrict__ y, int64_t n,
-                                              Body &&body)
+__device__ __forceinline__ void stream_strided(const double *__restrict__ x,
+                                               const double *__restrict__ y, int64_t first,
+                                               int64_t stride, int64_t n, Body &&body)
 {
     const int64_t group = (int64_t)CHUNK * U;
-    const int64_t step = (int64_t)gridDim.x * group;
-    int64_t base = (int64_t)blockIdx.x * group;
-    for (; base + group <= n; base += step) {
+    int64_t base = first;
+    for (; base + group <= n; base += stride) {
         double xv[U][4], yv[U][4];
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -71,14 +74,40 @@ __device__ __forceinline__ void stream_groups(const double *__restrict__ x,
     }
 }
 
+// Grid-stride form: block b takes groups b, b + gridDim.x, ...
+template <bool VEC, int U, class Body>
+__device__ __forceinline__ void stream_groups(const double *__restrict__ x,
+                                              const double *__restrict__ y, int64_t n,
+                                              Body &&body)
+{
+    const int64_t group = (int64_t)CHUNK * U;
+    stream_strided<VEC, U>(x, y, (int64_t)blockIdx.x * group, (int64_t)gridDim.x * group, n,
+                           body);
+}
+
 // One block walks components [begin, end) of x, y (indices relative to the
-// vector start, begin a multiple of CHUNK) in groups of CHUNK.
-template <bool VEC, class Body>
+// vector start, begin a multiple of CHUNK) in groups of CHUNK, U groups'
+// loads in flight at a time while the range allows.
+template <bool VEC, class Body, int U = 1>
 __device__ __forceinline__ void stream_block_range(const double *__restrict__ x,
                                                    const double *__restrict__ y, int64_t begin,
                                                    int64_t end, Body &&body)
 {
     int64_t base = begin;
+    if constexpr (U > 1) {
+        for (; base + (int64_t)U * CHUNK <= end; base += (int64_t)U * CHUNK) {
+            double xv[U][4], yv[U][4];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+                load4_full<VEC>(x + i0, xv[u]);
+                load4_full<VEC>(y + i0, yv[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                body(xv[u], yv[u], base + (int64_t)u * CHUNK + threadIdx.x * EPT, 4);
+        }
+    }
     for (; base + CHUNK <= end; base += CHUNK) {
         const int64_t i0 = base + threadIdx.x * EPT;
         double xv[4], yv[4];
@@ -102,6 +131,35 @@ __device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v)
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     return v;
+}
+
+// ---- hand-over between blocks of one launch ------------------------------
+// Data that one block hands to another inside a launch travels only through
+// device-scope atomics: read-modify-writes, relaxed stores (written through
+// to the device's coherence point) and relaxed loads (served from it).  A
+// release then needs no writeback of the XCD's L2: it is enough that the
+// publishing thread's own memory operations have completed, which the
+// vector-memory counter wait in vmem_drain ensures, before the flag or count
+// that announces them is written.  An agent-scope release fence would write
+// back the whole L2 of the XCD, and an acquire fence would invalidate it;
+// with other blocks streaming that costs far more than the counter wait.
+__device__ __forceinline__ void vmem_drain()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <class T>
+__device__ __forceinline__ T ld_dev(const T *p)
+{
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ void st_dev(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- cutoff selection (Alg. 2: bins -> scores -> precisions) ------------

@@ -28,6 +28,7 @@ struct qdot_handle {
     // batched qdot: cached work plans (one per offsets layout) and grid size
     std::vector<void *> plans;
     int batch_blocks_per_cu = 4;
+    void *cg = nullptr;              // persistent CG buffers
 
     // kernel timing (diagnostics)
     bool timing = false;
@@ -64,5 +65,7 @@ bool tune_ok(const qdot_tune &t);
 hipEvent_t *take_events(qdot_handle *h, int kind);
 bool options_ok(const qdot_options &o);
 void free_plans(qdot_handle *h);
+void free_cg(qdot_handle *h);
+int32_t ensure_solver_vectors(qdot_handle *h, int64_t n);
 
 }  // namespace qd

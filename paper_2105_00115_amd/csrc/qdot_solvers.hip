@@ -25,7 +25,6 @@ struct SolverCtl {
 };
 
 constexpr int VB = 256;
-constexpr int CHECK_EVERY = 16;
 
 static inline int vgrid(int64_t n) { return (int)std::max<int64_t>(1, (n + VB - 1) / VB); }
 
@@ -53,87 +52,10 @@ __device__ __forceinline__ bool all_perforated(const qdot_result *r)
     return r && (r->flags & QDOT_F_ALL_PERF) && r->n_bins > 0;
 }
 
-__global__ void k_cg_init(SolverCtl *ctl, const double *c0, const qdot_result *c0res,
-                          const double *bb, double rtol)
-{
-    const double bn = sqrt(*bb);
-    ctl->bnorm = bn;
-    ctl->thresh = rtol * bn;
-    ctl->c = *c0;
-    ctl->iters = 0;
-    ctl->broke = 0;
-    ctl->status = QDOT_OK;
-    ctl->done = 0;
-    if (all_perforated(c0res)) {
-        ctl->status = QDOT_E_BREAKDOWN;
-        ctl->done = 1;
-    } else if (!(sqrt(ctl->c) > ctl->thresh)) {
-        ctl->done = 1;
-    }
-}
 
-// r0 = b - A x0 (q holds A x0), p0 = r0
-__global__ __launch_bounds__(VB) void k_cg_residual(int64_t n, const double *__restrict__ b,
-                                                    const double *__restrict__ q,
-                                                    double *__restrict__ r,
-                                                    double *__restrict__ p)
-{
-    const int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x;
-    if (i >= n) return;
-    const double v = b[i] - q[i];
-    r[i] = v;
-    if (p) p[i] = v;
-}
 
-// alpha = c / (p.q);  x += alpha p;  r -= alpha q
-__global__ __launch_bounds__(VB) void k_cg_update1(int64_t n, SolverCtl *ctl,
-                                                   const double *dval, const qdot_result *dres,
-                                                   double *__restrict__ x,
-                                                   const double *__restrict__ p,
-                                                   const double *__restrict__ q,
-                                                   double *__restrict__ r)
-{
-    if (ctl->done) return;
-    const double d = *dval;
-    const int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x;
-    if (!(d > 0.0) || !isfinite(d) || all_perforated(dres)) {
-        if (i == 0) ctl->broke = 1;
-        return;
-    }
-    if (i >= n) return;
-    const double alpha = ctl->c / d;
-    const double ap = alpha * p[i];
-    x[i] = x[i] + ap;
-    const double aq = alpha * q[i];
-    r[i] = r[i] - aq;
-}
 
-// beta = c' / c;  p = r + beta p
-__global__ __launch_bounds__(VB) void k_cg_update2(int64_t n, const SolverCtl *ctl,
-                                                   const double *cnval,
-                                                   double *__restrict__ p,
-                                                   const double *__restrict__ r)
-{
-    if (ctl->done || ctl->broke) return;
-    const int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x;
-    if (i >= n) return;
-    const double beta = *cnval / ctl->c;
-    const double bp = beta * p[i];
-    p[i] = r[i] + bp;
-}
 
-__global__ void k_cg_step(SolverCtl *ctl, const double *cnval, const qdot_result *cnres)
-{
-    if (ctl->done) return;
-    if (ctl->broke || all_perforated(cnres)) {
-        ctl->status = QDOT_E_BREAKDOWN;
-        ctl->done = 1;
-        return;
-    }
-    ctl->c = *cnval;
-    ctl->iters += 1;
-    if (!(sqrt(ctl->c) > ctl->thresh)) ctl->done = 1;
-}
 
 // power method: x = w / sqrt(c), lambda recorded
 __global__ __launch_bounds__(VB) void k_pm_update(int64_t n, SolverCtl *ctl,
@@ -186,7 +108,7 @@ static bool csr_ok(const qdot_csr *A)
            A->n < (int64_t)1 << 31 && A->nnz < (int64_t)1 << 31;
 }
 
-static int32_t ensure_scratch(qdot_handle *h, int64_t n)
+int32_t ensure_solver_vectors(qdot_handle *h, int64_t n)
 {
     if (!h->ctl) {
         if (hipMalloc(&h->ctl, sizeof(SolverCtl)) != hipSuccess ||
@@ -252,93 +174,6 @@ int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double *x, doub
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "spmv launch");
 }
 
-int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, double rtol,
-                double qtol, int32_t maxit, int32_t use_qdot, const qdot_options *opt,
-                void *stream, qdot_cg_result *out, qdot_result *trace)
-{
-    if (!h) return QDOT_E_INVAL;
-    if (!out) return fail(h, QDOT_E_INVAL, "out is NULL");
-    std::memset(out, 0, sizeof *out);
-    if (!csr_ok(A) || A->n == 0 || !b || !x) return fail(h, QDOT_E_INVAL, "bad CSR or vector");
-    if (!(rtol >= 0.0) || maxit < 0) return fail(h, QDOT_E_INVAL, "bad rtol or maxit");
-    qdot_options o;
-    std::memset(&o, 0, sizeof o);
-    if (opt) o = *opt;
-    if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
-    if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
-        return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
-    DeviceGuard g(h->device);
-    const int64_t n = A->n;
-    int32_t st = ensure_scratch(h, n);
-    if (st != QDOT_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    const Launch L = make_launch(h, s, n);
-    double *r = h->vec, *p = h->vec + n, *q = h->vec + 2 * n;
-    SolverCtl *ctl = (SolverCtl *)h->ctl;
-    qdot_result *rr_slot = h->res_ring, *pq_slot = h->res_ring + 1;
-    double *d_rr = h->dres, *d_pq = h->dres + 1, *d_bb = h->dres + 2;
-    hipError_t e = hipSuccess;
-    auto ok = [&](hipError_t x_) {
-        if (e == hipSuccess && x_ != hipSuccess) e = x_;
-        return e == hipSuccess;
-    };
-    const int gv = vgrid(n);
-
-    // r0 = b - A x0, p0 = r0, c0 = dot(r0, r0), ||b|| by the FP64 dot
-    hipLaunchKernelGGL(k_spmv, dim3(gv), dim3(VB), 0, s, n, A->rowptr, A->col, A->val, x, q,
-                       (const SolverCtl *)nullptr);
-    hipLaunchKernelGGL(k_cg_residual, dim3(gv), dim3(VB), 0, s, n, b, q, r, p);
-    ok(hipGetLastError());
-    ok(launch_dot64(L, b, b, n, d_bb));
-    const double *cval;
-    const qdot_result *cres;
-    ok(enqueue_dot(h, L, r, r, n, use_qdot, qtol, o, trace ? &trace[0] : rr_slot, d_rr, &cval,
-                   &cres));
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(1), 0, s, ctl, cval, cres, d_bb, rtol);
-    ok(hipGetLastError());
-
-    SolverCtl hc;
-    std::memset(&hc, 0, sizeof hc);
-    int32_t enq = 0;
-    while (e == hipSuccess) {
-        if ((st = read_ctl(h, s, hc)) != QDOT_OK) return st;
-        if (hc.done || enq >= maxit) break;
-        const int32_t batch = std::min<int32_t>(CHECK_EVERY, maxit - enq);
-        for (int32_t it = 0; it < batch && e == hipSuccess; it++, enq++) {
-            const double *dval, *cnval;
-            const qdot_result *dres, *cnres;
-            hipLaunchKernelGGL(k_spmv, dim3(gv), dim3(VB), 0, s, n, A->rowptr, A->col, A->val,
-                               p, q, (const SolverCtl *)ctl);
-            ok(enqueue_dot(h, L, p, q, n, use_qdot, qtol, o,
-                           trace ? &trace[1 + 2 * enq] : pq_slot, d_pq, &dval, &dres));
-            hipLaunchKernelGGL(k_cg_update1, dim3(gv), dim3(VB), 0, s, n, ctl, dval, dres, x, p,
-                               q, r);
-            ok(enqueue_dot(h, L, r, r, n, use_qdot, qtol, o,
-                           trace ? &trace[2 + 2 * enq] : rr_slot, d_rr, &cnval, &cnres));
-            hipLaunchKernelGGL(k_cg_update2, dim3(gv), dim3(VB), 0, s, n, ctl, cnval, p, r);
-            hipLaunchKernelGGL(k_cg_step, dim3(1), dim3(1), 0, s, ctl, cnval, cnres);
-            ok(hipGetLastError());
-        }
-    }
-    if (e != hipSuccess) return hip_fail(h, e, "cg launch");
-    // true residual ||b - A x|| / ||b||
-    hipLaunchKernelGGL(k_spmv, dim3(gv), dim3(VB), 0, s, n, A->rowptr, A->col, A->val, x, q,
-                       (const SolverCtl *)nullptr);
-    hipLaunchKernelGGL(k_cg_residual, dim3(gv), dim3(VB), 0, s, n, b, q, q, (double *)nullptr);
-    ok(hipGetLastError());
-    ok(launch_dot64(L, q, q, n, d_pq));
-    if (e != hipSuccess) return hip_fail(h, e, "cg residual launch");
-    double rq = 0.0;
-    e = hipMemcpyAsync(&rq, d_pq, sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(h, e, "cg residual read");
-    out->iters = hc.iters;
-    out->status = hc.status != QDOT_OK ? hc.status : (hc.done ? QDOT_OK : QDOT_E_MAXIT);
-    out->relres_est = hc.bnorm > 0 ? std::sqrt(hc.c) / hc.bnorm : 0.0;
-    out->relres_true = hc.bnorm > 0 ? std::sqrt(rq) / hc.bnorm : 0.0;
-    return out->status;
-}
-
 int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, double qtol,
                    int32_t use_qdot, const qdot_options *opt, void *stream, double *lambda,
                    double *lambda_trace)
@@ -353,7 +188,7 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
     DeviceGuard g(h->device);
     const int64_t n = A->n;
-    int32_t st = ensure_scratch(h, n);
+    int32_t st = ensure_solver_vectors(h, n);
     if (st != QDOT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const Launch L = make_launch(h, s, n);
