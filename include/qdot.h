@@ -125,6 +125,17 @@ typedef struct qdot_cg_result {
     double relres_true;   /* ||b - A x|| / ||b|| recomputed at exit (FP64) */
 } qdot_cg_result;
 
+/* One CG system of a batched launch (all pointers device memory). */
+typedef struct qdot_cg_system {
+    qdot_csr A;          /* square, A.n rows */
+    const double *b;     /* A.n right-hand side */
+    double *x;           /* A.n: x0 on entry, solution on exit */
+    double rtol;         /* stop when sqrt(c_k) <= rtol * ||b||_2 */
+    double qtol;         /* qdot tolerance of both inner products */
+    int32_t maxit;       /* iteration limit (QDOT_E_MAXIT beyond) */
+    int32_t use_qdot;    /* 0: plain FP64 inner products */
+} qdot_cg_system;
+
 /* ---- launch configuration (autotuner) ---------------------------------- */
 /* Launch shape of the two streaming passes.  Grids are persistent:
  * blocks_per_cu * CUs blocks of 256 threads, each thread keeping `unroll`
@@ -245,6 +256,37 @@ QDOT_API int32_t qdot_batched_async(qdot_handle *h, const double *x_cat,
  * qdot_batched_async into a graph).  Synchronous. */
 QDOT_API int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets,
                                    int32_t B);
+
+/* Batched launch of qdot instances and CG systems together: the B ragged
+ * instances (arguments as qdot_batched_async; B may be 0) and S CG systems
+ * (systems: host array of S descriptors; S may be 0) run in one persistent
+ * kernel launch.  Each CG system follows qdot_cg on that system alone (Alg.
+ * 4 with the same stopping rule and the same inner products); it is solved
+ * by a gang of up to 16 blocks (one per 16384 rows) that meet at barriers,
+ * gangs are formed before the qdot work items are handed out, largest
+ * system first.  dev_cg_out: device qdot_cg_result[S].  Planning happens on
+ * the first call with a new layout (offsets and system descriptors,
+ * compared by value) and is synchronous; later calls with the same layout
+ * launch two kernels (a re-arm pass over the gangs and the batch), allocate
+ * nothing and can be captured in a graph.  A gang barrier that does not
+ * complete within its spin limit gives that system status QDOT_E_DEVICE. */
+QDOT_API int32_t qdot_batch_run_async(qdot_handle *h, const double *x_cat,
+                                      const double *y_cat, const int64_t *offsets,
+                                      const int64_t *host_offsets, const double *tols,
+                                      int32_t B, const qdot_cg_system *systems, int32_t S,
+                                      const qdot_options *opt, void *stream,
+                                      qdot_result *dev_out, qdot_cg_result *dev_cg_out);
+
+/* Plan a layout of qdot_batch_run_async ahead of time (e.g. before graph
+ * capture).  Synchronous. */
+QDOT_API int32_t qdot_batch_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
+                                 const qdot_cg_system *systems, int32_t S);
+
+/* S CG systems in one persistent launch (qdot_batch_run_async with no qdot
+ * instances); host_out: host qdot_cg_result[S].  Synchronous. */
+QDOT_API int32_t qdot_cg_batched(qdot_handle *h, const qdot_cg_system *systems, int32_t S,
+                                 const qdot_options *opt, void *stream,
+                                 qdot_cg_result *host_out);
 
 /* y = A x for a CSR matrix (rows summed in stored order, each product and
  * sum one FP64 rounding).  Async. */

@@ -68,6 +68,14 @@ class QdotCgResult(C.Structure):
                 ("relres_est", C.c_double), ("relres_true", C.c_double)]
 
 
+class QdotCgSystem(C.Structure):
+    _fields_ = [("A", QdotCsr), ("b", C.c_void_p), ("x", C.c_void_p), ("rtol", C.c_double),
+                ("qtol", C.c_double), ("maxit", C.c_int32), ("use_qdot", C.c_int32)]
+
+
+CG_RESULT_BYTES = C.sizeof(QdotCgResult)
+
+
 class QdotTune(C.Structure):
     _fields_ = [("scan_blocks_per_cu", C.c_int32), ("scan_unroll", C.c_int32),
                 ("acc_blocks_per_cu", C.c_int32), ("acc_unroll", C.c_int32)]
@@ -103,6 +111,11 @@ SIGNATURES = [
     ("qdot_batched_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32, _OPT,
                                   _vp, _vp]),
     ("qdot_batched_plan", _i32, [_vp, C.POINTER(_i64), _i32]),
+    ("qdot_batch_run_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32,
+                                    C.POINTER(QdotCgSystem), _i32, _OPT, _vp, _vp, _vp]),
+    ("qdot_batch_plan", _i32, [_vp, C.POINTER(_i64), _i32, C.POINTER(QdotCgSystem), _i32]),
+    ("qdot_cg_batched", _i32, [_vp, C.POINTER(QdotCgSystem), _i32, _OPT, _vp,
+                               C.POINTER(QdotCgResult)]),
     ("qdot_spmv_async", _i32, [_vp, _CSR, _vp, _vp, _vp]),
     ("qdot_cg", _i32, [_vp, _CSR, _vp, _vp, _d, _d, _i32, _i32, _OPT, _vp,
                        C.POINTER(QdotCgResult), _vp]),
@@ -162,6 +175,17 @@ def _check_vec(t, name):
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == 1):
         raise ValueError(f"{name} must be a contiguous 1-D float64 CUDA tensor")
+
+
+def parse_cg_results(buf) -> list:
+    """qdot_cg_result records from a CUDA uint8 tensor, as dicts."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    out = []
+    for i in range(len(raw) // CG_RESULT_BYTES):
+        r = QdotCgResult.from_buffer_copy(raw, i * CG_RESULT_BYTES)
+        out.append({"status": r.status, "iters": r.iters, "relres_est": r.relres_est,
+                    "relres_true": r.relres_true})
+    return out
 
 
 def parse_results(buf) -> list:
@@ -358,6 +382,52 @@ class Qdot:
         self.batched_async(x_cat, y_cat, off_d, ho, tol_d, out, opt)
         torch.cuda.current_stream().synchronize()
         return parse_results(out)[: ho.shape[0] - 1]
+
+    # ---- batched launch of qdot instances and CG systems ---------------------
+    @staticmethod
+    def cg_systems(systems):
+        """systems: sequence of (Csr, b, x, rtol, qtol, maxit, use_qdot) with
+        device tensors b, x; returns the ctypes array (keep it alive)."""
+        arr = (QdotCgSystem * max(1, len(systems)))()
+        for i, (A, bv, xv, rtol, qtol, maxit, use) in enumerate(systems):
+            _check_vec(bv, "b")
+            _check_vec(xv, "x")
+            arr[i] = QdotCgSystem(A.c, bv.data_ptr(), xv.data_ptr(), float(rtol), float(qtol),
+                                  int(maxit), int(use))
+        return arr
+
+    def batch_plan(self, host_offsets, systems):
+        ho, hp = self._host_offsets(host_offsets if host_offsets is not None else [0])
+        arr = self.cg_systems(systems)
+        st = lib().qdot_batch_plan(self._h, hp, ho.shape[0] - 1, arr, len(systems))
+        if st != OK:
+            self._raise(st, "qdot_batch_plan")
+
+    def batch_run_async(self, x_cat, y_cat, offsets, host_offsets, tols, out, systems,
+                        cg_out, opt=None, stream=None):
+        """qdot instances as batched_async (host_offsets None for none) plus
+        CG systems (see cg_systems); cg_out: CUDA uint8 tensor of
+        len(systems) * CG_RESULT_BYTES."""
+        ho, hp = self._host_offsets(host_offsets if host_offsets is not None else [0])
+        B = ho.shape[0] - 1
+        arr = self.cg_systems(systems)
+        st = lib().qdot_batch_run_async(
+            self._h, _ptr(x_cat) if B else None, _ptr(y_cat) if B else None,
+            _ptr(offsets) if B else None, hp, _ptr(tols) if B else None, B, arr, len(systems),
+            _opts(opt), _stream(stream), _ptr(out) if B else None,
+            _ptr(cg_out) if systems else None)
+        if st != OK:
+            self._raise(st, "qdot_batch_run_async")
+
+    def cg_batched(self, systems, opt=None, stream=None) -> list:
+        """Solves every system in one launch; returns one result dict each."""
+        arr = self.cg_systems(systems)
+        res = (QdotCgResult * max(1, len(systems)))()
+        st = lib().qdot_cg_batched(self._h, arr, len(systems), _opts(opt), _stream(stream), res)
+        if st != OK:
+            self._raise(st, "qdot_cg_batched")
+        return [{"status": r.status, "iters": r.iters, "relres_est": r.relres_est,
+                 "relres_true": r.relres_true} for r in res[: len(systems)]]
 
     # ---- applications ------------------------------------------------------
     def spmv(self, A: Csr, x, y, stream=None):

@@ -30,6 +30,7 @@
 #include <numeric>
 
 #include "qdot_blocks.hpp"
+#include "qdot_cg.hpp"
 #include "qdot_handle.hpp"
 
 namespace qd {
@@ -41,14 +42,16 @@ constexpr int64_t SMALL_GROUP = 65536; // cost budget of one item of small insta
 constexpr int SU = 2;                 // CHUNK groups in flight per thread
 constexpr int64_t GROUP = (int64_t)SU * CHUNK;
 constexpr int MAX_PLANS = 8;
+constexpr int64_t CG_ROWS_PER_BLOCK = 16384;  // rows per gang block of a CG system
+constexpr int CG_GANG_MAX = 16;               // blocks per CG system at most
 
-enum : int { IT_P1 = 0, IT_SMALL = 1, IT_P2 = 2 };
+enum : int { IT_P1 = 0, IT_SMALL = 1, IT_P2 = 2, IT_CG = 3 };
 
 struct BItem {
     int type;
-    int inst;   // P1 / P2: instance; SMALL: first entry in the small list
-    int large;  // P1 / P2: compact index of the large instance; SMALL: count
-    int slot;   // P2: partial slot
+    int inst;   // P1 / P2: instance; SMALL: first entry in the small list; CG: system
+    int large;  // P1 / P2: compact index of the large instance; SMALL: count; CG: gang size
+    int slot;   // P2: partial slot; CG: block's place in the gang
     int64_t first, stride;  // P1 / P2: the chunk's groups (see stream_strided)
 };
 
@@ -69,7 +72,12 @@ struct BState {
 
 struct BatchPlan {
     std::vector<int64_t> offsets;
-    int B = 0, n_items = 0, n_large = 0, n_p2 = 0;
+    std::vector<qdot_cg_system> systems;
+    int B = 0, S = 0, n_items = 0, n_large = 0, n_p2 = 0, max_gang = 0;
+    CgSys *sys = nullptr;             // S device descriptors
+    Gang *gangs = nullptr;            // S gang states
+    double *cgvec = nullptr;          // r, p, q of every system
+    qdot_cg_result *cgres = nullptr;  // S results (synchronous CG entry)
     BItem *items = nullptr;
     BLarge *large = nullptr;
     unsigned int *hist = nullptr;
@@ -90,34 +98,11 @@ void free_plan(BatchPlan *p)
     (void)hipFree(p->partials);
     (void)hipFree(p->state);
     (void)hipFree(p->small_list);
+    (void)hipFree(p->sys);
+    (void)hipFree(p->gangs);
+    (void)hipFree(p->cgvec);
+    (void)hipFree(p->cgres);
     delete p;
-}
-
-// block-wide reduction of a range and two counters; result in every thread
-__device__ __forceinline__ void block_reduce_range(int &lo, int &hi, unsigned int &nz,
-                                                   unsigned int &bad, int4 *scratch)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        lo = min(lo, __shfl_xor(lo, m, 64));
-        hi = max(hi, __shfl_xor(hi, m, 64));
-        nz += __shfl_xor(nz, m, 64);
-        bad |= __shfl_xor(bad, m, 64);
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) scratch[wv] = make_int4(lo, hi, (int)nz, (int)bad);
-    __syncthreads();
-    lo = W;
-    hi = -1;
-    nz = 0;
-    bad = 0;
-    for (int w = 0; w < BLOCK / 64; w++) {
-        lo = min(lo, scratch[w].x);
-        hi = max(hi, scratch[w].y);
-        nz += (unsigned int)scratch[w].z;
-        bad |= (unsigned int)scratch[w].w;
-    }
 }
 
 // Pass 1 over the groups first, first + stride, ... (below n) of one
@@ -167,6 +152,20 @@ __global__ __launch_bounds__(BLOCK) void k_batch_init(BLarge *large, int n_large
     for (int s = W; s < W_LUT; s++) lut[(size_t)i * W_LUT + s] = (unsigned char)QDOT_PERF;
 }
 
+__global__ __launch_bounds__(BLOCK) void k_batch_gangs_init(Gang *gangs, int S)
+{
+    if (blockIdx.x >= (unsigned)S) return;
+    gang_reset(gangs + blockIdx.x);
+    if (threadIdx.x == 0) gangs[blockIdx.x].bar_gen = 0;
+}
+
+// Re-arms the gangs of a plan whose previous launch aborted (a bounded wait
+// ran out); a clean gang leaves its state ready for the next launch.
+__global__ __launch_bounds__(BLOCK) void k_gang_rearm(Gang *gangs, int S)
+{
+    if (blockIdx.x < (unsigned)S && gangs[blockIdx.x].abort) gang_reset(gangs + blockIdx.x);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                                                  const double *__restrict__ y,
                                                  const int64_t *__restrict__ offsets,
@@ -178,16 +177,20 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                                                  double *__restrict__ partials,
                                                  BState *__restrict__ st,
                                                  const int *__restrict__ small_list,
-                                                 qdot_result *__restrict__ out, int key_mode,
+                                                 qdot_result *__restrict__ out,
+                                                 const CgSys *__restrict__ sys,
+                                                 Gang *__restrict__ gangs,
+                                                 qdot_cg_result *__restrict__ cg_out, int key_mode,
                                                  int score_mode, int nonstrict)
 {
-    __shared__ unsigned int h[W + 1];
-    __shared__ unsigned char lut[W_LUT];
-    __shared__ Acc red[3][BLOCK / 64];
-    __shared__ int4 scratch[BLOCK / 64];
+    __shared__ CgLds LD;
+    unsigned int *h = LD.h;
+    unsigned char *lut = LD.lut;
+    auto &red = LD.red;
+    int4 *scratch = LD.scratch;
+    qdot_result &s_res = LD.res;
     __shared__ int s_item, s_flag;
     __shared__ int4 s_prm2;
-    __shared__ qdot_result s_res;
     const int tid = threadIdx.x;
 
     for (int i = tid; i < W + 1; i += BLOCK) h[i] = 0;
@@ -201,6 +204,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
         __syncthreads();
         if (it >= n_items) break;
         const BItem I = items[it];
+        if (I.type == IT_CG) {
+            // one block of a CG gang: its other blocks hold the neighbouring
+            // tickets, so they are taken by blocks that are running
+            cg_solve(sys[I.inst], gangs + I.inst, I.large, I.slot, key_mode, score_mode,
+                     nonstrict, LD, cg_out + I.inst);
+            __syncthreads();
+            continue;
+        }
         if (I.type == IT_SMALL) {
           for (int sj = 0; sj < I.large; sj++) {
             const int inst = small_list[I.inst + sj];
@@ -400,12 +411,28 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
 // ---------------------------------------------------------------------------
 // host planning
 // ---------------------------------------------------------------------------
+static bool same_system(const qdot_cg_system &a, const qdot_cg_system &b)
+{
+    return a.A.n == b.A.n && a.A.nnz == b.A.nnz && a.A.rowptr == b.A.rowptr &&
+           a.A.col == b.A.col && a.A.val == b.A.val && a.b == b.b && a.x == b.x &&
+           a.rtol == b.rtol && a.qtol == b.qtol && a.maxit == b.maxit &&
+           a.use_qdot == b.use_qdot;
+}
+
+static int gang_size(int64_t n)
+{
+    return (int)std::max<int64_t>(
+        1, std::min<int64_t>(CG_GANG_MAX, (n + CG_ROWS_PER_BLOCK - 1) / CG_ROWS_PER_BLOCK));
+}
+
 static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
-                          BatchPlan **out)
+                          const qdot_cg_system *systems, int32_t S, BatchPlan **out)
 {
     BatchPlan *p = new BatchPlan();
     p->B = B;
-    p->offsets.assign(host_offsets, host_offsets + B + 1);
+    p->S = S;
+    if (B > 0) p->offsets.assign(host_offsets, host_offsets + B + 1);
+    if (S > 0) p->systems.assign(systems, systems + S);
     std::vector<int> big, small;
     for (int j = 0; j < B; j++) {
         const int64_t n = host_offsets[j + 1] - host_offsets[j];
@@ -415,6 +442,17 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     std::stable_sort(big.begin(), big.end(), [&](int a, int b) { return len(a) > len(b); });
     std::stable_sort(small.begin(), small.end(), [&](int a, int b) { return len(a) > len(b); });
     std::vector<BItem> items;
+    // CG gangs first, largest system first: their solves are the longest
+    // chains of the launch, and the qdot items fill the other blocks
+    std::vector<int> cg_order(S);
+    std::iota(cg_order.begin(), cg_order.end(), 0);
+    std::stable_sort(cg_order.begin(), cg_order.end(),
+                     [&](int a, int c) { return systems[a].A.n > systems[c].A.n; });
+    for (int s : cg_order) {
+        const int G = gang_size(systems[s].A.n);
+        p->max_gang = std::max(p->max_gang, G);
+        for (int gb = 0; gb < G; gb++) items.push_back(BItem{IT_CG, s, G, gb, 0, 0});
+    }
     std::vector<BLarge> lg(big.size());
     int slot = 0;
     for (size_t L = 0; L < big.size(); L++) {
@@ -451,17 +489,45 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     p->n_items = (int)items.size();
     p->n_large = (int)big.size();
     p->n_p2 = slot;
+    int64_t cg_rows = 0;
+    for (int s = 0; s < S; s++) cg_rows += systems[s].A.n;
     const size_t nl = std::max<size_t>(1, big.size());
+    const size_t ns = std::max<int32_t>(1, S);
     bool ok = hipMalloc((void **)&p->items, sizeof(BItem) * std::max<size_t>(1, items.size())) == hipSuccess &&
               hipMalloc((void **)&p->large, sizeof(BLarge) * nl) == hipSuccess &&
               hipMalloc((void **)&p->hist, sizeof(unsigned int) * W * nl) == hipSuccess &&
               hipMalloc((void **)&p->lut, (size_t)W_LUT * nl) == hipSuccess &&
               hipMalloc((void **)&p->partials, sizeof(double) * 6 * std::max(1, slot)) == hipSuccess &&
               hipMalloc((void **)&p->state, sizeof(BState)) == hipSuccess &&
-              hipMalloc((void **)&p->small_list, sizeof(int) * std::max<size_t>(1, small_list.size())) == hipSuccess;
+              hipMalloc((void **)&p->small_list, sizeof(int) * std::max<size_t>(1, small_list.size())) == hipSuccess &&
+              hipMalloc((void **)&p->sys, sizeof(CgSys) * ns) == hipSuccess &&
+              hipMalloc((void **)&p->gangs, sizeof(Gang) * ns) == hipSuccess &&
+              hipMalloc((void **)&p->cgres, sizeof(qdot_cg_result) * ns) == hipSuccess &&
+              hipMalloc((void **)&p->cgvec, sizeof(double) * std::max<int64_t>(1, 3 * cg_rows)) == hipSuccess;
     if (!ok) {
         free_plan(p);
         return fail(h, QDOT_E_NOMEM, "batched plan allocation failed");
+    }
+    std::vector<CgSys> dsys(S);
+    int64_t vo = 0;
+    for (int s = 0; s < S; s++) {
+        const qdot_cg_system &q = systems[s];
+        CgSys &d = dsys[s];
+        d.n = q.A.n;
+        d.rowptr = q.A.rowptr;
+        d.col = q.A.col;
+        d.val = q.A.val;
+        d.b = q.b;
+        d.x = q.x;
+        d.r = p->cgvec + vo;
+        d.p = p->cgvec + vo + q.A.n;
+        d.q = p->cgvec + vo + 2 * q.A.n;
+        vo += 3 * q.A.n;
+        d.rtol = q.rtol;
+        d.qtol = q.qtol;
+        d.maxit = q.maxit;
+        d.use_qdot = q.use_qdot ? 1 : 0;
+        d.trace = nullptr;
     }
     hipError_t e = hipMemcpy(p->items, items.data(), sizeof(BItem) * items.size(),
                              hipMemcpyHostToDevice);
@@ -473,9 +539,15 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     if (e == hipSuccess && !small_list.empty())
         e = hipMemcpy(p->small_list, small_list.data(), sizeof(int) * small_list.size(),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess && S > 0)
+        e = hipMemcpy(p->sys, dsys.data(), sizeof(CgSys) * S, hipMemcpyHostToDevice);
     if (e == hipSuccess && !lg.empty()) {
         hipLaunchKernelGGL(k_batch_init, dim3((unsigned)((lg.size() + BLOCK - 1) / BLOCK)),
                            dim3(BLOCK), 0, 0, p->large, (int)lg.size(), p->lut);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && S > 0) {
+        hipLaunchKernelGGL(k_batch_gangs_init, dim3((unsigned)S), dim3(BLOCK), 0, 0, p->gangs, S);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -487,19 +559,23 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     return QDOT_OK;
 }
 
-static int32_t find_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B, BatchPlan **out)
+static int32_t find_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
+                         const qdot_cg_system *systems, int32_t S, BatchPlan **out)
 {
     static uint64_t clock = 0;
     for (void *vp : h->plans) {
         BatchPlan *p = (BatchPlan *)vp;
-        if (p->B == B && std::equal(p->offsets.begin(), p->offsets.end(), host_offsets)) {
-            p->last_use = ++clock;
-            *out = p;
-            return QDOT_OK;
-        }
+        if (p->B != B || p->S != S) continue;
+        if (B > 0 && !std::equal(p->offsets.begin(), p->offsets.end(), host_offsets)) continue;
+        bool same = true;
+        for (int s = 0; s < S && same; s++) same = same_system(p->systems[s], systems[s]);
+        if (!same) continue;
+        p->last_use = ++clock;
+        *out = p;
+        return QDOT_OK;
     }
     BatchPlan *p = nullptr;
-    int32_t st = build_plan(h, host_offsets, B, &p);
+    int32_t st = build_plan(h, host_offsets, B, systems, S, &p);
     if (st != QDOT_OK) return st;
     p->last_use = ++clock;
     if ((int)h->plans.size() >= MAX_PLANS) {
@@ -531,6 +607,72 @@ static int32_t check_batch(qdot_handle *h, const int64_t *host_offsets, int32_t 
     return QDOT_OK;
 }
 
+static int32_t check_systems(qdot_handle *h, const qdot_cg_system *systems, int32_t S)
+{
+    if (S < 0 || (S > 0 && !systems)) return fail(h, QDOT_E_INVAL, "bad system count or array");
+    for (int s = 0; s < S; s++) {
+        const qdot_cg_system &q = systems[s];
+        if (q.A.n <= 0 || q.A.nnz < 0 || !q.A.rowptr || !q.A.col || !q.A.val || !q.b || !q.x ||
+            q.A.n >= ((int64_t)1 << 31) || q.A.nnz >= ((int64_t)1 << 31))
+            return fail(h, QDOT_E_INVAL, "bad CSR or vector in a CG system");
+        if (!(q.rtol >= 0.0) || q.maxit < 0) return fail(h, QDOT_E_INVAL, "bad rtol or maxit");
+        if (q.use_qdot && (!(q.qtol > 0.0) || !std::isfinite(q.qtol)))
+            return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
+    }
+    return QDOT_OK;
+}
+
+// Plans (when needed) and launches the work of one batch: B qdot instances
+// and S CG systems in one persistent launch.
+static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y_cat,
+                            const int64_t *offsets, const int64_t *host_offsets,
+                            const double *tols, int32_t B, const qdot_cg_system *systems,
+                            int32_t S, const qdot_options *opt, void *stream,
+                            qdot_result *dev_out, qdot_cg_result *dev_cg_out, BatchPlan **used)
+{
+    int32_t st = check_batch(h, host_offsets, B);
+    if (st != QDOT_OK) return st;
+    if ((st = check_systems(h, systems, S)) != QDOT_OK) return st;
+    if (B == 0 && S == 0) return QDOT_OK;
+    if (B > 0) {
+        const int64_t total = host_offsets[B];
+        if ((total > 0 && (!x_cat || !y_cat)) || !offsets || !tols || !dev_out)
+            return fail(h, QDOT_E_INVAL, "NULL pointer");
+        if (((uintptr_t)x_cat | (uintptr_t)y_cat) & 7)
+            return fail(h, QDOT_E_INVAL, "vectors not 8-byte aligned");
+    }
+    if (S > 0 && !dev_cg_out) return fail(h, QDOT_E_INVAL, "NULL CG result array");
+    qdot_options o;
+    std::memset(&o, 0, sizeof o);
+    if (opt) o = *opt;
+    if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    DeviceGuard g(h->device);
+    BatchPlan *p = nullptr;
+    if ((st = find_plan(h, host_offsets, B, systems, S, &p)) != QDOT_OK) return st;
+    int bpc = h->batch_blocks_per_cu;
+    if (const char *e = std::getenv("QDOT_BATCH_BLOCKS_PER_CU")) bpc = std::max(1, std::min(16, std::atoi(e)));
+    const int grid = std::max(1, std::min(p->n_items, bpc * h->num_cus));
+    if (p->max_gang > 0) {
+        // a gang waits for its own blocks only, so it needs that many
+        // blocks resident at once
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BLOCK, 0);
+        if (e != hipSuccess) return hip_fail(h, e, "occupancy query");
+        if ((int64_t)per_cu * h->num_cus < p->max_gang)
+            return fail(h, QDOT_E_DEVICE, "CG gang larger than the resident blocks");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (S > 0) hipLaunchKernelGGL(k_gang_rearm, dim3((unsigned)S), dim3(BLOCK), 0, s, p->gangs, S);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets, tols,
+                       p->items, p->n_items, p->large, p->hist, p->lut, p->partials, p->state,
+                       p->small_list, dev_out, p->sys, p->gangs, dev_cg_out, o.key_mode,
+                       o.score_mode, o.boundary_mode);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "batched launch");
+    if (used) *used = p;
+    return QDOT_OK;
+}
+
 }  // namespace qd
 
 using namespace qd;
@@ -539,12 +681,20 @@ extern "C" {
 
 int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B)
 {
+    return qdot_batch_plan(h, host_offsets, B, nullptr, 0);
+}
+
+int32_t qdot_batch_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
+                        const qdot_cg_system *systems, int32_t S)
+{
     if (!h) return QDOT_E_INVAL;
     int32_t st = check_batch(h, host_offsets, B);
-    if (st != QDOT_OK || B == 0) return st;
+    if (st != QDOT_OK) return st;
+    if ((st = check_systems(h, systems, S)) != QDOT_OK) return st;
+    if (B == 0 && S == 0) return QDOT_OK;
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
-    return find_plan(h, host_offsets, B, &p);
+    return find_plan(h, host_offsets, B, systems, S, &p);
 }
 
 int32_t qdot_batched_async(qdot_handle *h, const double *x_cat, const double *y_cat,
@@ -553,30 +703,44 @@ int32_t qdot_batched_async(qdot_handle *h, const double *x_cat, const double *y_
                            void *stream, qdot_result *dev_out)
 {
     if (!h) return QDOT_E_INVAL;
-    int32_t st = check_batch(h, host_offsets, B);
+    return batch_launch(h, x_cat, y_cat, offsets, host_offsets, tols, B, nullptr, 0, opt, stream,
+                        dev_out, nullptr, nullptr);
+}
+
+int32_t qdot_batch_run_async(qdot_handle *h, const double *x_cat, const double *y_cat,
+                             const int64_t *offsets, const int64_t *host_offsets,
+                             const double *tols, int32_t B, const qdot_cg_system *systems,
+                             int32_t S, const qdot_options *opt, void *stream,
+                             qdot_result *dev_out, qdot_cg_result *dev_cg_out)
+{
+    if (!h) return QDOT_E_INVAL;
+    return batch_launch(h, x_cat, y_cat, offsets, host_offsets, tols, B, systems, S, opt, stream,
+                        dev_out, dev_cg_out, nullptr);
+}
+
+int32_t qdot_cg_batched(qdot_handle *h, const qdot_cg_system *systems, int32_t S,
+                        const qdot_options *opt, void *stream, qdot_cg_result *host_out)
+{
+    if (!h) return QDOT_E_INVAL;
+    if (S > 0 && !host_out) return fail(h, QDOT_E_INVAL, "out is NULL");
+    if (S <= 0) return S == 0 ? QDOT_OK : fail(h, QDOT_E_INVAL, "bad system count");
+    int32_t st = qdot_batch_plan(h, nullptr, 0, systems, S);
     if (st != QDOT_OK) return st;
-    if (B == 0) return QDOT_OK;
-    const int64_t total = host_offsets[B];
-    if ((total > 0 && (!x_cat || !y_cat)) || !offsets || !tols || !dev_out)
-        return fail(h, QDOT_E_INVAL, "NULL pointer");
-    if (((uintptr_t)x_cat | (uintptr_t)y_cat) & 7)
-        return fail(h, QDOT_E_INVAL, "vectors not 8-byte aligned");
-    qdot_options o;
-    std::memset(&o, 0, sizeof o);
-    if (opt) o = *opt;
-    if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
-    if ((st = find_plan(h, host_offsets, B, &p)) != QDOT_OK) return st;
-    int bpc = h->batch_blocks_per_cu;
-    if (const char *e = std::getenv("QDOT_BATCH_BLOCKS_PER_CU")) bpc = std::max(1, std::min(16, std::atoi(e)));
-    const int grid = std::max(1, std::min(p->n_items, bpc * h->num_cus));
+    if ((st = find_plan(h, nullptr, 0, systems, S, &p)) != QDOT_OK) return st;
+    if ((st = batch_launch(h, nullptr, nullptr, nullptr, nullptr, nullptr, 0, systems, S, opt,
+                           stream, nullptr, p->cgres, nullptr)) != QDOT_OK)
+        return st;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets, tols,
-                       p->items, p->n_items, p->large, p->hist, p->lut, p->partials, p->state,
-                       p->small_list, dev_out, o.key_mode, o.score_mode, o.boundary_mode);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "batched launch");
+    hipError_t e = hipMemcpyAsync(host_out, p->cgres, sizeof(qdot_cg_result) * S,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "batched CG");
+    for (int i = 0; i < S; i++)
+        if (host_out[i].status == QDOT_E_DEVICE)
+            return fail(h, QDOT_E_DEVICE, "CG gang barrier timed out");
+    return QDOT_OK;
 }
 
 }  // extern "C"

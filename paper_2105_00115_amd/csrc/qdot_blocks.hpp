@@ -133,6 +133,33 @@ __device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v)
     return v;
 }
 
+// block-wide reduction of a range and two counters; result in every thread
+__device__ __forceinline__ void block_reduce_range(int &lo, int &hi, unsigned int &nz,
+                                                   unsigned int &bad, int4 *scratch)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo = min(lo, __shfl_xor(lo, m, 64));
+        hi = max(hi, __shfl_xor(hi, m, 64));
+        nz += __shfl_xor(nz, m, 64);
+        bad |= __shfl_xor(bad, m, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wv] = make_int4(lo, hi, (int)nz, (int)bad);
+    __syncthreads();
+    lo = W;
+    hi = -1;
+    nz = 0;
+    bad = 0;
+    for (int w = 0; w < BLOCK / 64; w++) {
+        lo = min(lo, scratch[w].x);
+        hi = max(hi, scratch[w].y);
+        nz += (unsigned int)scratch[w].z;
+        bad |= (unsigned int)scratch[w].w;
+    }
+}
+
 // ---- hand-over between blocks of one launch ------------------------------
 // Data that one block hands to another inside a launch travels only through
 // device-scope atomics: read-modify-writes, relaxed stores (written through

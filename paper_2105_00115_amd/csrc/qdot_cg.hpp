@@ -1,0 +1,425 @@
+// Device side of conjugate gradient (Alg. 4) run by a gang of blocks inside
+// one launch; used by the single-system CG launch and by the batched launch.
+//
+// A gang of G blocks solves one system; block b of the gang owns a
+// contiguous slice of rows and every vector update, SpMV row and qdot pass
+// on that slice.  Gang barriers (an arrival counter and a generation word)
+// separate the steps that need data from other slices:
+//   before the SpMV (p complete), after a qdot's pass 1 (histogram merged),
+//   after its pass 2 (partials written),
+// five per iteration.  Between those barriers every block computes the
+// cutoff and the final combine of each qdot itself, from the same merged
+// histogram and the same partials in the same order, so every block holds
+// bit-identical scalars (alpha, beta, c) and takes the same branches: the
+// gang never needs to broadcast a decision.  Two histogram buffers rotate so
+// that block 0 can clear the one just used without an extra barrier.
+//
+// Every wait is bounded: a barrier that does not complete within the spin
+// limit raises the gang's abort flag, every block leaves, and the call
+// reports QDOT_E_DEVICE.  The grid never exceeds one block per CU per gang
+// slot, so all blocks of a gang are resident together.
+#pragma once
+#include <cmath>
+
+#include "qdot_blocks.hpp"
+
+namespace qd {
+
+constexpr unsigned SPIN_LIMIT = 1u << 26;
+
+struct CgSys {
+    int64_t n;
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const double *b;
+    double *x;
+    double *r, *p, *q;  // scratch, n each
+    double rtol, qtol;
+    int maxit, use_qdot;
+    qdot_result *trace;  // nullable: 2 * maxit + 1 results
+};
+
+struct GangQ {  // per gang and qdot buffer
+    unsigned int hist[W];
+    int lo, hi;
+    unsigned long long n_zero;
+    unsigned int bad;
+    unsigned int pad;
+};
+
+struct Gang {
+    unsigned int bar_count;
+    unsigned int bar_gen;
+    unsigned int abort;
+    unsigned int pad;
+    GangQ qb[2];
+    double partials[2][256 * 6];  // up to MAX_GANG blocks per gang
+};
+
+constexpr int MAX_GANG = 256;
+
+// ---------------------------------------------------------------------------
+// Gang barrier.  Everything a block hands to the others (vector entries,
+// histogram merges, partials, clears) is written with device-scope atomics
+// or write-through stores and read with device-scope loads, so arriving
+// needs only the block's own memory operations to have completed
+// (vmem_drain) and leaving needs no cache invalidation.
+__device__ bool gang_barrier(Gang *gg, int G)
+{
+    __shared__ int s_ok;
+    vmem_drain();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned int gen = ld_dev(&gg->bar_gen);
+        const unsigned int arrived =
+            __hip_atomic_fetch_add(&gg->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (arrived == (unsigned)G) {
+            st_dev(&gg->bar_count, 0u);
+            vmem_drain();
+            st_dev(&gg->bar_gen, gen + 1);
+        } else {
+            unsigned int spins = 0;
+            while (ld_dev(&gg->bar_gen) == gen) {
+                if (ld_dev(&gg->abort) || ++spins > SPIN_LIMIT) {
+                    __hip_atomic_fetch_or(&gg->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+struct DotOut {
+    double value;
+    bool all_perf;  // qdot perforated every component of a nonzero vector
+    bool ok;        // gang still healthy
+};
+
+// Shared-memory workspace of one block (CG and batched kernels).
+struct CgLds {
+    unsigned int h[W + 1];
+    unsigned char lut[W_LUT];
+    Acc red[3][BLOCK / 64];
+    int4 scratch[BLOCK / 64];
+    qdot_result res;
+    double dval;
+};
+
+// a.b over the gang's rows by qdot (buffer k), value identical in every block.
+__device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, int64_t n, int64_t r0, int64_t r1,
+                            double tol, int key_mode, int score_mode, int nonstrict, Gang *gg,
+                            int G, int gb, int k, CgLds &L, qdot_result *trace_slot)
+{
+    DotOut o = {0.0, false, true};
+    GangQ &Q = gg->qb[k];
+    const bool vec = ((((uintptr_t)a) | ((uintptr_t)bv)) & 15) == 0;
+    // pass 1 over own rows
+    unsigned int nz = 0, bad = 0;
+    auto scan = [&](const double *xv, const double *yv, int64_t, int lim) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const Comp c = component(xv[e], yv[e], key_mode);
+            const bool valid = e < lim;
+            nz += (valid & c.zero) ? 1u : 0u;
+            bad |= (valid & c.bad) ? 1u : 0u;
+            if (valid) atomicAdd(&L.h[c.slot], 1u);
+        }
+    };
+    if (vec)
+        stream_strided<true, 2>(a, bv, r0, 2 * CHUNK, r1, scan);
+    else
+        stream_strided<false, 2>(a, bv, r0, 2 * CHUNK, r1, scan);
+    __syncthreads();
+    int lo = W, hi = -1;
+    for (int j = threadIdx.x; j < W; j += BLOCK) {
+        const unsigned int v = L.h[j];
+        if (v) {
+            __hip_atomic_fetch_add(&Q.hist[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            L.h[j] = 0u;
+            lo = min(lo, j);
+            hi = max(hi, j);
+        }
+    }
+    if (threadIdx.x == 0) L.h[W] = 0u;
+    block_reduce_range(lo, hi, nz, bad, L.scratch);
+    if (threadIdx.x == 0) {
+        if (hi >= 0) {
+            __hip_atomic_fetch_min(&Q.lo, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(&Q.hi, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (nz)
+            __hip_atomic_fetch_add(&Q.n_zero, (unsigned long long)nz, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (bad) __hip_atomic_fetch_or(&Q.bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!gang_barrier(gg, G)) {
+        o.ok = false;
+        return o;
+    }
+    // cutoff, redundantly in every block, into the block's own class table
+    const int glo = ld_dev(&Q.lo);
+    const int ghi = ld_dev(&Q.hi);
+    const unsigned long long gnz = ld_dev(&Q.n_zero);
+    const unsigned int gbad = ld_dev(&Q.bad);
+    auto get = [&](int j) { return (unsigned long long)ld_dev(&Q.hist[j]); };
+    auto put = [&](int j, int c) { L.lut[j] = (unsigned char)c; };
+    auto noclear = [&](int) {};
+    const CutParams p = block_cutoff<BLOCK>(glo, ghi, gnz, gbad, n, tol, score_mode, nonstrict,
+                                            get, put, noclear, &L.res, nullptr);
+    // pass 2 over own rows
+    if (!p.skip) {
+        Acc acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        auto body = [&](const double *xv, const double *yv, int64_t, int lim) {
+            acc_group<false>(xv, yv, lim, L.lut, key_mode, p.e_max, p.c32, true, acc[0], acc[1],
+                             acc[2], nullptr);
+        };
+        if (vec)
+            stream_strided<true, 2>(a, bv, r0, 2 * CHUNK, r1, body);
+        else
+            stream_strided<false, 2>(a, bv, r0, 2 * CHUNK, r1, body);
+        block_reduce3<BLOCK>(acc, L.red);
+        if (threadIdx.x == 0) {
+            double *pp = gg->partials[k] + gb * 6;
+            for (int q = 0; q < 3; q++) {
+                st_dev(&pp[2 * q], acc[q].s);
+                st_dev(&pp[2 * q + 1], acc[q].c);
+            }
+        }
+    }
+    if (!gang_barrier(gg, G)) {
+        o.ok = false;
+        return o;
+    }
+    if (!p.skip) {
+        // combine the gang's partials in block order, in every block
+        Acc acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        for (int c = threadIdx.x; c < G; c += BLOCK) {
+            const double *pp = gg->partials[k] + c * 6;
+            for (int q = 0; q < 3; q++)
+                acc[q] = acc_merge(acc[q], Acc{ld_dev(&pp[2 * q]), ld_dev(&pp[2 * q + 1])});
+        }
+        block_reduce3<BLOCK>(acc, L.red);
+        if (threadIdx.x == 0) combine_value(acc, p.e_max, p.t, p.c32, p.flags, &L.res);
+    }
+    __syncthreads();
+    o.value = L.res.value;
+    o.all_perf = (L.res.flags & QDOT_F_ALL_PERF) && L.res.n_bins > 0;
+    if (threadIdx.x == 0 && trace_slot) *trace_slot = L.res;
+    // block 0 clears this buffer for the qdot after next; every block has
+    // finished reading it (it passed the barrier above after its cutoff)
+    if (gb == 0) {
+        for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) st_dev(&Q.hist[j], 0u);
+        if (threadIdx.x == 0) {
+            st_dev(&Q.lo, (int)W);
+            st_dev(&Q.hi, -1);
+            st_dev(&Q.n_zero, 0ull);
+            st_dev(&Q.bad, 0u);
+        }
+    }
+    __syncthreads();
+    return o;
+}
+
+// a.b over the gang's rows in plain FP64 (partials buffer k).
+__device__ __forceinline__ DotOut gang_dot64(const double *a, const double *bv, int64_t r0, int64_t r1, Gang *gg,
+                             int G, int gb, int k, CgLds &L)
+{
+    DotOut o = {0.0, false, true};
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = r0 + threadIdx.x;
+    for (; i + 3 * BLOCK < r1; i += 4 * BLOCK) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) s[u] = fma(a[i + u * BLOCK], bv[i + u * BLOCK], s[u]);
+    }
+    for (; i < r1; i += BLOCK) s[0] = fma(a[i], bv[i], s[0]);
+    Acc acc[3] = {{(s[0] + s[1]) + (s[2] + s[3]), 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    block_reduce3<BLOCK>(acc, L.red);
+    if (threadIdx.x == 0) st_dev(&gg->partials[k][gb * 6], acc[0].s + acc[0].c);
+    if (!gang_barrier(gg, G)) {
+        o.ok = false;
+        return o;
+    }
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int c = 0; c < G; c++) v += ld_dev(&gg->partials[k][c * 6]);
+        L.dval = v;
+    }
+    __syncthreads();
+    o.value = L.dval;
+    __syncthreads();
+    return o;
+}
+
+// out[i] = sum_j val[j] * v[col[j]] over rows [r0, r1), each row summed in
+// column-storage order (plain multiply, then add).  v may hold entries that
+// other blocks wrote in this launch, so it is read with device-scope loads.
+// A thread takes SR rows at once so that their loads overlap.
+constexpr int SR = 4;
+__device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, double *out, int64_t r0,
+                                          int64_t r1)
+{
+    for (int64_t base = r0; base < r1; base += (int64_t)SR * BLOCK) {
+        int32_t beg[SR], len[SR];
+        int maxlen = 0;
+#pragma unroll
+        for (int u = 0; u < SR; u++) {
+            const int64_t i = base + u * BLOCK + threadIdx.x;
+            beg[u] = 0;
+            len[u] = 0;
+            if (i < r1) {
+                beg[u] = S.rowptr[i];
+                len[u] = S.rowptr[i + 1] - beg[u];
+            }
+            maxlen = max(maxlen, len[u]);
+        }
+        double s[SR] = {0.0, 0.0, 0.0, 0.0};
+        for (int jj = 0; jj < maxlen; jj++) {
+#pragma unroll
+            for (int u = 0; u < SR; u++) {
+                if (jj < len[u]) {
+                    const int32_t j = beg[u] + jj;
+                    const double pr = S.val[j] * ld_dev(&v[S.col[j]]);
+                    s[u] = s[u] + pr;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SR; u++) {
+            const int64_t i = base + u * BLOCK + threadIdx.x;
+            if (i < r1) out[i] = s[u];
+        }
+    }
+}
+
+// One CG solve by one gang.
+__device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb, int key_mode, int score_mode,
+                         int nonstrict, CgLds &L, qdot_cg_result *res)
+{
+    const int64_t n = S.n;
+    // rows of this block: a multiple of CHUNK each, so qdot tiles line up
+    const int64_t per = ((n + G - 1) / G + CHUNK - 1) / CHUNK * CHUNK;
+    const int64_t r0 = min(n, (int64_t)gb * per), r1 = min(n, r0 + per);
+    int k = 0;  // qdot buffer / partials parity
+    int ntr = 0;
+    auto dot = [&](const double *a, const double *bv) {
+        DotOut o;
+        if (S.use_qdot) {
+            o = gang_qdot(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict, gg, G, gb, k,
+                          L, (gb == 0 && S.trace) ? S.trace + ntr : nullptr);
+            ntr++;
+        } else {
+            o = gang_dot64(a, bv, r0, r1, gg, G, gb, k, L);
+        }
+        k ^= 1;
+        return o;
+    };
+    int status = QDOT_OK, iters = 0;
+    bool healthy = true;
+    // r0 = b - A x0, p0 = r0
+    spmv_rows(S, S.x, S.q, r0, r1);
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+        const double v = S.b[i] - S.q[i];
+        S.r[i] = v;
+        st_dev(&S.p[i], v);
+    }
+    __syncthreads();
+    DotOut bb = gang_dot64(S.b, S.b, r0, r1, gg, G, gb, k, L);
+    k ^= 1;
+    const double bnorm = sqrt(bb.value);
+    const double thresh = S.rtol * bnorm;
+    DotOut c0 = dot(S.r, S.r);
+    healthy = bb.ok && c0.ok;
+    double c = c0.value;
+    bool done = false;
+    if (healthy && c0.all_perf) {
+        status = QDOT_E_BREAKDOWN;
+        done = true;
+    } else if (healthy && !(sqrt(c) > thresh)) {
+        done = true;
+    }
+    while (healthy && !done) {
+        if (iters >= S.maxit) {
+            status = QDOT_E_MAXIT;
+            break;
+        }
+        if (!(healthy = gang_barrier(gg, G))) break;  // p complete
+        spmv_rows(S, S.p, S.q, r0, r1);
+        __syncthreads();
+        const DotOut d = dot(S.p, S.q);
+        if (!(healthy = d.ok)) break;
+        if (!(d.value > 0.0) || !isfinite(d.value) || d.all_perf) {
+            status = QDOT_E_BREAKDOWN;
+            break;
+        }
+        const double alpha = c / d.value;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+            const double ap = alpha * S.p[i];
+            st_dev(&S.x[i], S.x[i] + ap);
+            const double aq = alpha * S.q[i];
+            S.r[i] = S.r[i] - aq;
+        }
+        __syncthreads();
+        const DotOut cn = dot(S.r, S.r);
+        if (!(healthy = cn.ok)) break;
+        if (cn.all_perf) {
+            status = QDOT_E_BREAKDOWN;
+            break;
+        }
+        const double beta = cn.value / c;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+            const double bp = beta * S.p[i];
+            st_dev(&S.p[i], S.r[i] + bp);
+        }
+        c = cn.value;
+        iters++;
+        if (!(sqrt(c) > thresh)) done = true;
+    }
+    double relres_true = 0.0;
+    if (healthy) healthy = gang_barrier(gg, G);  // x complete
+    if (healthy) {
+        spmv_rows(S, S.x, S.q, r0, r1);
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) S.q[i] = S.b[i] - S.q[i];
+        __syncthreads();
+        const DotOut rq = gang_dot64(S.q, S.q, r0, r1, gg, G, gb, k, L);
+        k ^= 1;
+        healthy = rq.ok;
+        relres_true = bnorm > 0.0 ? sqrt(rq.value) / bnorm : 0.0;
+    }
+    if (gb == 0 && threadIdx.x == 0) {
+        res->iters = iters;
+        res->status = healthy ? status : QDOT_E_DEVICE;
+        res->relres_est = bnorm > 0.0 ? sqrt(c) / bnorm : 0.0;
+        res->relres_true = relres_true;
+    }
+    // leave the gang buffers clean and every block past its last use of them
+    if (healthy) gang_barrier(gg, G);
+}
+
+// Clears a gang's barrier, abort flag and histogram buffers (plain stores;
+// used by a kernel of its own, before the launch that uses the gang).
+__device__ __forceinline__ void gang_reset(Gang *gg)
+{
+    for (int i = threadIdx.x; i < W; i += blockDim.x) {
+        gg->qb[0].hist[i] = 0u;
+        gg->qb[1].hist[i] = 0u;
+    }
+    if (threadIdx.x == 0) {
+        gg->bar_count = 0;
+        gg->abort = 0;
+        for (int k = 0; k < 2; k++) {
+            gg->qb[k].lo = W;
+            gg->qb[k].hi = -1;
+            gg->qb[k].n_zero = 0;
+            gg->qb[k].bad = 0;
+        }
+    }
+}
+
+}  // namespace qd

@@ -67,6 +67,7 @@ int main(void) {
   printf("qdot_csr %zu\n", sizeof(qdot_csr));
   printf("qdot_cg_result %zu\n", sizeof(qdot_cg_result));
   printf("qdot_tune %zu\n", sizeof(qdot_tune));
+  printf("qdot_cg_system %zu\n", sizeof(qdot_cg_system));
   P(qdot_result, value); P(qdot_result, count); P(qdot_result, n_zero);
   P(qdot_result, e_min); P(qdot_result, e_max); P(qdot_result, n_bins);
   P(qdot_result, t); P(qdot_result, part); P(qdot_result, bound_rel);
@@ -74,6 +75,8 @@ int main(void) {
   P(qdot_csr, n); P(qdot_csr, nnz); P(qdot_csr, rowptr); P(qdot_csr, col); P(qdot_csr, val);
   P(qdot_cg_result, iters); P(qdot_cg_result, status); P(qdot_cg_result, relres_est);
   P(qdot_cg_result, relres_true);
+  P(qdot_cg_system, A); P(qdot_cg_system, b); P(qdot_cg_system, x); P(qdot_cg_system, rtol);
+  P(qdot_cg_system, qtol); P(qdot_cg_system, maxit); P(qdot_cg_system, use_qdot);
   return 0;
 }
 """
@@ -89,7 +92,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
     types = {"qdot_result": q.QdotResult, "qdot_options": q.QdotOptions,
              "qdot_csr": q.QdotCsr, "qdot_cg_result": q.QdotCgResult,
-             "qdot_tune": q.QdotTune}
+             "qdot_tune": q.QdotTune, "qdot_cg_system": q.QdotCgSystem}
     for k, v in got.items():
         if "." in k:
             t, f = k.split(".")

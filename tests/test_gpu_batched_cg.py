@@ -1,0 +1,160 @@
+"""GPU parity of CG systems solved inside the batched persistent launch.
+
+Each system must behave as Alg. 4 on that system alone: the iteration count
+of the qdot-CG within one of the oracle's CG and of the FP64-dot twin (the
+stopping test compares a rounded inner product with a threshold, so one
+iteration of slack covers a rounding that lands on the other side), the
+true residual below the solver tolerance, and the solution close to the
+oracle's.  CG systems and qdot instances share the launch without changing
+either's results, and the launch replays from a captured graph.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+import paper_2105_00115_amd as q  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+INT_KEYS = ("count", "n_zero", "e_min", "e_max", "n_bins", "t", "flags", "status")
+
+
+@pytest.fixture(scope="module")
+def h():
+    handle = q.Qdot(0)
+    yield handle
+    handle.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def poisson_system(m, seed, use_qdot, rtol=1e-10, qtol=1e-8, maxit=20000):
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    b = workloads.normal_vector(m * m, seed)
+    x = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    return {"m": m, "csr": (rp, col, val), "A": A, "b_host": b, "b": dev(b), "x": x,
+            "args": (A, None, x, rtol, qtol, maxit, use_qdot)}
+
+
+def as_tuple(s):
+    A, _, x, rtol, qtol, maxit, use = s["args"]
+    return (A, s["b"], x, rtol, qtol, maxit, use)
+
+
+SIDES = (16, 32, 45, 64, 100, 140)  # 140^2 = 19600 rows: a gang of two blocks
+
+
+def test_cg_batched_matches_oracle_and_fp64_twin(h):
+    sq = [poisson_system(m, 100 + m, 1) for m in SIDES]
+    sf = [poisson_system(m, 100 + m, 0) for m in SIDES]
+    res = h.cg_batched([as_tuple(s) for s in sq + sf])
+    for i, m in enumerate(SIDES):
+        rq, rf = res[i], res[len(SIDES) + i]
+        assert rq["status"] == q.OK and rf["status"] == q.OK, (m, rq, rf)
+        assert abs(rq["iters"] - rf["iters"]) <= 1, (m, rq["iters"], rf["iters"])
+        assert rq["relres_true"] < 1e-9 and rf["relres_true"] < 1e-9, m
+        rp, col, val = sq[i]["csr"]
+        o = oracle.cg(rp, col, val, sq[i]["b_host"], 1e-10, 1e-8, 20000, 1)
+        assert abs(o["iters"] - rq["iters"]) <= 1, (m, o["iters"], rq["iters"])
+        xq = sq[i]["x"].cpu().numpy()
+        np.testing.assert_allclose(xq, o["x"], rtol=0, atol=1e-7 * np.abs(o["x"]).max())
+
+
+def test_cg_batched_equals_single_system_solver(h):
+    sys = [poisson_system(m, 7 + m, 1) for m in (32, 140)]
+    res = h.cg_batched([as_tuple(s) for s in sys])
+    for s, r in zip(sys, res):
+        x1 = torch.zeros_like(s["x"])
+        r1 = h.cg(s["A"], s["b"], x1, 1e-10, 1e-8, 20000, 1)
+        assert abs(r1["iters"] - r["iters"]) <= 1, (s["m"], r1["iters"], r["iters"])
+
+
+def test_cg_batched_statuses_are_per_system(h):
+    ok = poisson_system(40, 3, 1)
+    short = poisson_system(40, 3, 1, maxit=3)
+    perf = poisson_system(24, 4, 1, qtol=1e300)  # every component perforated
+    res = h.cg_batched([as_tuple(s) for s in (ok, short, perf)])
+    assert res[0]["status"] == q.OK
+    assert res[1]["status"] == q.E_MAXIT and res[1]["iters"] == 3
+    assert res[2]["status"] == q.E_BREAKDOWN
+
+
+def ragged(seed, count):
+    g = workloads.rng(seed)
+    sizes = [70000, 140000] + list(np.rint(10 ** g.uniform(1, 5, count)).astype(int))
+    offsets = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    x, y = workloads.log_uniform_pair(int(offsets[-1]), seed + 1)
+    tols = np.array([1e-4, 1e-6, 1e-8])[g.integers(0, 3, len(sizes))]
+    return offsets, x, y, tols
+
+
+def check_qdot(res, offsets, x, y, tols):
+    for j in range(len(tols)):
+        a, b = offsets[j], offsets[j + 1]
+        o = oracle.qdot(x[a:b], y[a:b], tols[j])
+        for k in INT_KEYS:
+            assert res[j][k] == o[k], (j, k)
+        if o["status"] == oracle.OK:
+            assert abs(res[j]["value"] - o["value"]) <= 1e-13 * oracle.abs_dot(x[a:b], y[a:b])
+
+
+def test_batch_run_mixes_qdot_instances_and_cg_systems(h):
+    offsets, x, y, tols = ragged(11, 40)
+    sys = [poisson_system(m, 50 + m, u) for m in (20, 64, 150) for u in (1, 0)]
+    xd, yd = dev(x), dev(y)
+    off_d = torch.from_numpy(offsets).to("cuda:0")
+    out = torch.zeros(len(tols) * q.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    cg_out = torch.zeros(len(sys) * q.CG_RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    h.batch_run_async(xd, yd, off_d, offsets, dev(tols), out, [as_tuple(s) for s in sys], cg_out)
+    torch.cuda.synchronize()
+    check_qdot(q.parse_results(out), offsets, x, y, tols)
+    cg = q.parse_cg_results(cg_out)
+    for i in range(0, len(sys), 2):
+        assert cg[i]["status"] == q.OK and cg[i + 1]["status"] == q.OK
+        assert abs(cg[i]["iters"] - cg[i + 1]["iters"]) <= 1
+        assert cg[i]["relres_true"] < 1e-9
+
+
+def test_batch_run_graph_replay(h):
+    offsets, x, y, tols = ragged(12, 20)
+    sys = [poisson_system(m, 60 + m, 1) for m in (24, 90)]
+    tup = [as_tuple(s) for s in sys]
+    xd, yd = dev(x), dev(y)
+    off_d = torch.from_numpy(offsets).to("cuda:0")
+    tol_d = dev(tols)
+    out = torch.zeros(len(tols) * q.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    cg_out = torch.zeros(len(sys) * q.CG_RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    h.batch_run_async(xd, yd, off_d, offsets, tol_d, out, tup, cg_out)
+    torch.cuda.synchronize()
+    eager, eager_cg = out.clone(), cg_out.clone()
+    eager_x = [s["x"].clone() for s in sys]
+    h.batch_plan(offsets, tup)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            h.batch_run_async(xd, yd, off_d, offsets, tol_d, out, tup, cg_out)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.zero_()
+        cg_out.zero_()
+        for s in sys:
+            s["x"].zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        assert torch.equal(cg_out, eager_cg), rep
+        for s, ex in zip(sys, eager_x):
+            assert torch.equal(s["x"], ex), rep
+        h.qdot(xd[:5000], yd[:5000], 1e-6)  # eager work between replays
+        torch.cuda.synchronize()
