@@ -10,8 +10,10 @@ the timed region; K steps are timed between two device synchronisations.
 Printed: one JSON line with Gelem/s, the roofline of the dominant kernel
 (HBM-bound: 16 algorithmic bytes per component per pass), the plain FP64 dot
 on the same buffers, the paper's approximation speedup and efficiency, the
-CG iteration counts (2D Poisson 1024^2) and power-method eigenvalue error
-(3D Laplacian 128^3), and the CPU oracle timed on a sample.
+CG iteration counts (2D Poisson 1024^2), the power-method eigenvalue error
+(3D Laplacian 128^3), the batched launch of 4096 ragged instances alone and
+together with 256 CG systems (graph replays), and the CPU oracle timed on a
+sample.
 """
 from __future__ import annotations
 
@@ -35,10 +37,11 @@ def log(msg):
 
 
 def kernel_source_sha() -> str:
-    src = os.path.join(ROOT, "paper_2105_00115_amd", "csrc", "qdot_kernels.hip")
-    dev = os.path.join(ROOT, "paper_2105_00115_amd", "csrc", "qdot_device.hpp")
+    """Hash of the sources the single-qdot kernels are built from."""
+    csrc = os.path.join(ROOT, "paper_2105_00115_amd", "csrc")
     h = hashlib.sha256()
-    for p in (src, dev):
+    for name in ("qdot_kernels.hip", "qdot_device.hpp", "qdot_blocks.hpp"):
+        p = os.path.join(csrc, name)
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -235,6 +238,67 @@ def main():
                "gelem_s": round(total / (batch_ms * 1e-3) / 1e9, 3),
                "hbm_frac_2pass": round(32.0 * total / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "statuses_ok": sum(1 for r in bres if r["status"] == 0)}
+
+    # the same 4096 instances plus 256 CG systems (2D Poisson, side
+    # round(2^U[5,9]), qdot tol 1e-8, stop at 1e-10) in one launch, captured
+    # with the zeroing of every x0; an FP64-dot twin launch of the systems
+    # gives the per-system iteration comparison
+    log("batched qdot + 256 CG systems in one launch")
+    gs = workloads.rng(2026)
+    sides = np.rint(2.0 ** gs.uniform(5, 9, 256)).astype(np.int64)
+    mats = {}
+    rows = int((sides ** 2).sum())
+    xall = torch.zeros(rows, dtype=torch.float64, device=dev)
+    ball = torch.empty(rows, dtype=torch.float64, device=dev)
+    sys_q, sys_f, ro = [], [], 0
+    for k, m in enumerate(sides):
+        m = int(m)
+        if m not in mats:
+            mats[m] = q.Csr(*workloads.poisson2d_csr(m), device=dev)
+        nn = m * m
+        ball[ro:ro + nn] = torch.from_numpy(workloads.normal_vector(nn, 3000 + k)).to(dev)
+        sys_q.append((mats[m], ball[ro:ro + nn], xall[ro:ro + nn], 1e-10, 1e-8, 20000, 1))
+        sys_f.append((mats[m], ball[ro:ro + nn], xall[ro:ro + nn], 1e-10, 1e-8, 20000, 0))
+        ro += nn
+    cgo = torch.zeros(256 * q.CG_RESULT_BYTES, dtype=torch.uint8, device=dev)
+    h.batch_plan(offs, sys_q)
+    graph2 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(bs):
+        with torch.cuda.graph(graph2, stream=bs):
+            xall.zero_()
+            h.batch_run_async(bx, by, off_d, offs, tol_d, bout, sys_q, cgo)
+    torch.cuda.synchronize()
+    graph2.replay()
+    torch.cuda.synchronize()
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        graph2.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    run_ms = e0.elapsed_time(e1) / reps
+    cq = q.parse_cg_results(cgo)
+    bres2 = q.parse_results(bout)
+    same_qdot = all(a == b for a, b in zip(bres, bres2))
+    xall.zero_()
+    c0 = time.perf_counter()
+    cf = h.cg_batched(sys_f)
+    twin_s = time.perf_counter() - c0
+    d_it = [abs(a["iters"] - b["iters"]) for a, b in zip(cq, cf)]
+    batched_cg = {
+        "systems": 256, "rows": rows, "sides_min_max": [int(sides.min()), int(sides.max())],
+        "ms_per_launch_with_qdot_instances": round(run_ms, 3),
+        "qdot_results_unchanged_by_cg": same_qdot,
+        "cg_status_ok": sum(1 for r in cq if r["status"] == 0),
+        "cg_iters_total": int(sum(r["iters"] for r in cq)),
+        "cg_iters_max": int(max(r["iters"] for r in cq)),
+        "fp64_twin_status_ok": sum(1 for r in cf if r["status"] == 0),
+        "fp64_twin_seconds": round(twin_s, 3),
+        "iters_equal_to_fp64_twin": sum(1 for d in d_it if d == 0),
+        "iters_max_abs_diff_vs_fp64_twin": int(max(d_it)),
+        "max_relres_true": max(r["relres_true"] for r in cq),
+    }
+    del graph2, xall, ball, mats, sys_q, sys_f
     del bx, by
 
     log(f"CPU oracle on a sample of {args.cpu_sample}")
@@ -279,6 +343,7 @@ def main():
             "torch_dot_value": float(tdot.item()),
             "cg_poisson2d_1024": cg,
             "batched_ragged_4096": batched,
+            "batched_4096_plus_256_cg": batched_cg,
             "power_laplacian3d_128": {**pm, "abs_lambda_diff":
                                       abs(pm["qdot"]["lambda"] - pm["fp64"]["lambda"]),
                                       "lambda_max_closed_form": lam_max},

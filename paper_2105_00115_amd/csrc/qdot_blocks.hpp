@@ -32,11 +32,6 @@ __device__ __forceinline__ void load4_tail(const double *__restrict__ p, int lim
     for (int e = 0; e < 4; e++) v[e] = e < lim ? p[e] : 0.0;
 }
 
-// Grid-stride walk over groups of CHUNK * U consecutive components.  Whole
-// groups are loaded without bounds checks; the single partial group (met by
-// one block at most) is loaded with per-lane limits.  body(xv, yv, i0, lim)
-// sees 4 consecutive components i0..i0+3 of which the first `lim` are real;
-// it is called with every lane of the block active.
 // One block walks groups of U * CHUNK components of x, y: the groups that
 // start at first, first + stride, first + 2 * stride, ... below n (stride a
 // multiple of U * CHUNK).  Each thread loads EPT consecutive components of
@@ -74,7 +69,12 @@ __device__ __forceinline__ void stream_strided(const double *__restrict__ x,
     }
 }
 
-// Grid-stride form: block b takes groups b, b + gridDim.x, ...
+// Grid-stride walk over groups of CHUNK * U consecutive components: block b
+// takes groups b, b + gridDim.x, ...  Whole groups are loaded without bounds
+// checks; the single partial group (met by one block at most) is loaded with
+// per-lane limits.  body(xv, yv, i0, lim) sees 4 consecutive components
+// i0..i0+3 of which the first `lim` are real; it is called with every lane
+// of the block active.
 template <bool VEC, int U, class Body>
 __device__ __forceinline__ void stream_groups(const double *__restrict__ x,
                                               const double *__restrict__ y, int64_t n,

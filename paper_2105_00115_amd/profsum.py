@@ -8,6 +8,13 @@ converts average durations of the named kernels into GB/s.
 
     python -m paper_2105_00115_amd.profsum TRACE.csv --first 55 \
         --kernels k_scan,k_cut,k_acc,k_dot64 --bytes k_scan=2147483648,...
+
+With ``--pmc WRITE.csv`` the first file is a FETCH_SIZE counter collection
+and the second a WRITE_SIZE one (``rocprofv3 --pmc``, csv output): each
+kernel's counters (KiB per dispatch, averaged over its first N dispatches)
+are scaled to bytes by what the same counters read for a copy of known
+size (``--calib KERNEL:GRID:BYTES``, bytes read = bytes written) and
+compared with ``--algo`` bytes per launch; ``--json`` writes the table.
 """
 from __future__ import annotations
 
@@ -46,13 +53,75 @@ def summarise(path, first=None, kernels=None):
     return groups
 
 
+def counters(path, first=None, kernels=None):
+    """{short name: [counter values in dispatch order]} and the grid of each."""
+    groups = OrderedDict()
+    with open(path) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Dispatch_Id"]))
+    for r in rows:
+        name = short_name(r["Kernel_Name"])
+        base = name.split("<")[0]
+        g = groups.setdefault(base, [])
+        g.append((int(r["Grid_Size"]), float(r["Counter_Value"]), name))
+    out = OrderedDict()
+    for base, g in groups.items():
+        if kernels and base not in kernels:
+            continue
+        out[base] = g[:first] if first else g
+    return out, groups
+
+
+def pmc_main(a):
+    kernels = a.kernels.split(",") if a.kernels else None
+    fetch, fall = counters(a.trace, a.first, kernels)
+    write, wall = counters(a.pmc, a.first, kernels)
+    ck, cgrid, cbytes = a.calib.split(":")
+    cgrid, cbytes = int(cgrid), float(cbytes)
+    cf = [v for g, v, _ in fall.get(ck, []) if g == cgrid]
+    cw = [v for g, v, _ in wall.get(ck, []) if g == cgrid]
+    if not cf or not cw:
+        raise SystemExit(f"calibration kernel {ck} with grid {cgrid} not found")
+    ff = cbytes / 1024.0 / cf[0]
+    wf = cbytes / 1024.0 / cw[0]
+    algo = float(a.algo) if a.algo else None
+    table = OrderedDict()
+    print(f"fetch factor {ff:.4f}, write factor {wf:.4f} "
+          f"({ck} grid {cgrid}: FETCH {cf[0]:.1f} KiB, WRITE {cw[0]:.1f} KiB)")
+    print("| kernel | dispatches | FETCH_SIZE KiB (raw) | WRITE_SIZE KiB (raw) | "
+          "HBM bytes / launch (scaled) | / algorithmic |")
+    print("|---|---|---|---|---|---|")
+    for base in (kernels or fetch.keys()):
+        if base not in fetch or base not in write:
+            continue
+        fv = [v for _, v, _ in fetch[base]]
+        wv = [v for _, v, _ in write[base]]
+        f_avg, w_avg = sum(fv) / len(fv), sum(wv) / len(wv)
+        hb = (f_avg * ff + w_avg * wf) * 1024.0
+        ratio = hb / algo if algo else None
+        table[base] = {"fetch_kib_raw": f_avg, "write_kib_raw": w_avg,
+                       "hbm_bytes_per_launch": hb, "ratio_to_algorithmic": ratio}
+        print(f"| {fetch[base][0][2]} | {len(fv)} | {f_avg:.1f} | {w_avg:.1f} | {hb:.4e} | "
+              f"{'' if ratio is None else f'{ratio:.4f}'} |")
+    if a.json:
+        import json
+        with open(a.json, "w") as f:
+            json.dump({"fetch_factor": ff, "write_factor": wf, "per_kernel": table}, f,
+                      indent=1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("trace")
+    ap.add_argument("--pmc", default=None, help="WRITE_SIZE csv (trace is FETCH_SIZE)")
+    ap.add_argument("--calib", default="__amd_rocclr_copyBuffer:131072:268435456")
+    ap.add_argument("--algo", default=None, help="algorithmic bytes per launch")
+    ap.add_argument("--json", default=None)
     ap.add_argument("--first", type=int, default=None)
     ap.add_argument("--kernels", default=None)
     ap.add_argument("--bytes", default="", help="kernel=bytes_per_launch,...")
     a = ap.parse_args(argv)
+    if a.pmc:
+        return pmc_main(a)
     kernels = set(a.kernels.split(",")) if a.kernels else None
     nbytes = dict(kv.split("=") for kv in a.bytes.split(",") if kv)
     groups = summarise(a.trace, a.first, kernels)
