@@ -159,6 +159,25 @@ def main():
     torch.cuda.synchronize()
     torch_dot_ms = e0.elapsed_time(e1) / K
 
+    # one-pass mode (accum_mode 1): same classes, exact per-bin sums, x and y
+    # read once
+    log(f"one-pass mode warmup {Wm}, timed {K}")
+    s1 = [0, 0, 0, 1]
+    out1 = torch.zeros(q.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    for _ in range(Wm):
+        h.qdot_async(x, y, tol, out1, opt=s1)
+    torch.cuda.synchronize()
+    h.timing_enable(True)
+    c0 = time.perf_counter()
+    for _ in range(K):
+        h.qdot_async(x, y, tol, out1, opt=s1)
+    torch.cuda.synchronize()
+    c1 = time.perf_counter()
+    h.timing_enable(False)
+    t1p = h.timing_read()
+    res1 = q.parse_results(out1)[0]
+    wall1 = c1 - c0
+
     xh = x[: args.cpu_sample].cpu().numpy()
     yh = y[: args.cpu_sample].cpu().numpy()
     scan_ms = tq["scan_ms"] / tq["qdot_calls"]
@@ -340,6 +359,19 @@ def main():
                        "bound_rel": res["bound_rel"], "flags": res["flags"],
                        "value": res["value"]},
             "relerr_vs_fp64_dot": abs(res["value"] - dot64) / abs(dot64) if dot64 else None,
+            "one_pass": {
+                "gelem_s": round(n * K / wall1 / 1e9, 3),
+                "ms_per_call": round(wall1 / K * 1e3, 4),
+                "kernel_ms": {"k_s1_scan": round(t1p["scan_ms"] / t1p["qdot_calls"], 4),
+                              "k_cut": round(t1p["cut_ms"] / t1p["qdot_calls"], 4),
+                              "k_s1_fin": round(t1p["fin_ms"] / t1p["qdot_calls"], 4)},
+                "scan_frac_hbm": round(alg_bytes / (t1p["scan_ms"] / t1p["qdot_calls"] * 1e-3)
+                                       / 1e9 / HBM_PEAK_GBS, 4),
+                "vs_fp64_dot": round(d64_ms / (wall1 / K * 1e3), 4),
+                "counts_equal_two_pass": res1["count"] == res["count"],
+                "value": res1["value"],
+                "relerr_vs_fp64_dot": abs(res1["value"] - dot64) / abs(dot64) if dot64 else None,
+            },
             "torch_dot_value": float(tdot.item()),
             "cg_poisson2d_1024": cg,
             "batched_ragged_4096": batched,

@@ -86,8 +86,17 @@ typedef struct qdot_options {
      *    narrowest precision whose mantissa width is >= the score). */
     int32_t boundary_mode;
     /* 0: FP32 leaves summed in FP32 inside 64-element tiles of the index
-     *    order (adjacent-pairwise tree), then at FP64;
-     * 1: reserved (exact per-bin accumulation); QDOT_E_INVAL for now. */
+     *    order (adjacent-pairwise tree), then at FP64 (two passes over x, y);
+     * 1: one pass over x, y: the same classes and leaves (Alg. 1), summed
+     *    exactly and rounded once.  While scanning the exponents, every
+     *    block keeps per-bin candidate sums of all three precisions for the
+     *    bins near its running maximum key and each kept bin takes its
+     *    class's sum after the cutoff.  Accepted by qdot_async, qdot and
+     *    qdot_power when n <= 2^30 and the tolerance keeps every possibly
+     *    kept bin within 255 exponents of e_max (ceil(log2 n) - t_min + 1
+     *    <= 255, t_min the smallest t any histogram of n components can
+     *    give: tol >= about 1e-60 at n = 2^27); QDOT_E_INVAL otherwise and
+     *    in the classes, batched and CG entry points. */
     int32_t accum_mode;
 } qdot_options;
 

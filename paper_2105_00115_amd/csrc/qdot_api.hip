@@ -51,6 +51,7 @@ Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n)
     L.scan_unroll = t.scan_unroll;
     L.acc_blocks = std::min(h->partial_blocks, t.acc_blocks_per_cu * h->num_cus);
     L.acc_unroll = t.acc_unroll;
+    L.s1tab = h->s1tab;
     L.ev = nullptr;
     return L;
 }
@@ -73,7 +74,36 @@ hipEvent_t *take_events(qdot_handle *h, int kind)
 bool options_ok(const qdot_options &o)
 {
     return (o.key_mode == 0 || o.key_mode == 1) && (o.score_mode == 0 || o.score_mode == 1) &&
-           (o.boundary_mode == 0 || o.boundary_mode == 1) && o.accum_mode == 0;
+           (o.boundary_mode == 0 || o.boundary_mode == 1) &&
+           (o.accum_mode == 0 || o.accum_mode == 1);
+}
+
+static int ceil_log2_host(int64_t v)
+{
+    int c = 0;
+    while (((int64_t)1 << c) < v) c++;
+    return c;
+}
+
+// A bin k can be kept only if its score ceil(log2 M_k) + k - e_max - t + 1
+// reaches the lowest class boundary (0, or 1 in the non-strict reading is
+// higher, so 0 bounds both): e_max - k <= ceil(log2 n) - t + 1.  t is
+// smallest for the largest possible bin count min(n, W): t >= floor(log2
+// tol) - ceil(log2 min(n, W)) - 1 (adjusted score) or floor(log2 tol) (raw).
+int s1_depth(int64_t n, double tol, const qdot_options &o)
+{
+    int e2 = 0;
+    (void)std::frexp(tol, &e2);  // tol = f 2^e2, f in [0.5, 1)
+    const int fl = e2 - 1;       // floor(log2 tol)
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(n, W));
+    const int t_low = o.score_mode == 0 ? fl - ceil_log2_host(nb) - 1 : fl;
+    // bins e_max - d for d = 0 .. ceil(log2 n) - t_low + 1
+    return ceil_log2_host(std::max<int64_t>(1, n)) - t_low + 2;
+}
+
+bool s1_admissible(int64_t n, double tol, const qdot_options &o)
+{
+    return n <= S1_MAX_N && s1_depth(n, tol, o) <= S1_WIN;
 }
 
 static int32_t check_qdot_args(qdot_handle *h, const double *x, const double *y, int64_t n,
@@ -87,6 +117,9 @@ static int32_t check_qdot_args(qdot_handle *h, const double *x, const double *y,
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (o.accum_mode == 1 && !s1_admissible(n, tol, o))
+        return fail(h, QDOT_E_INVAL, "accum_mode 1 needs n <= 2^30 and a tolerance whose "
+                                     "kept bins fit the one-pass window");
     return QDOT_OK;
 }
 
@@ -117,10 +150,14 @@ int32_t qdot_create(qdot_handle **out, int32_t device)
     bool ok = hipMalloc((void **)&h->ws, sizeof(Ws)) == hipSuccess &&
               hipMalloc((void **)&h->partials, sizeof(double) * 6 * h->partial_blocks) == hipSuccess &&
               hipMalloc((void **)&h->dev_res, sizeof(qdot_result)) == hipSuccess &&
+              hipMalloc((void **)&h->s1tab, sizeof(double) * HIST_COPIES * W * S1_PIECES) ==
+                  hipSuccess &&
               hipHostMalloc((void **)&h->host_res, sizeof(qdot_result), hipHostMallocDefault) ==
                   hipSuccess;
     if (ok) {
-        ok = hipMemset(h->ws, 0, sizeof(Ws)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+        ok = hipMemset(h->ws, 0, sizeof(Ws)) == hipSuccess &&
+             hipMemset(h->s1tab, 0, sizeof(double) * HIST_COPIES * W * S1_PIECES) == hipSuccess &&
+             hipDeviceSynchronize() == hipSuccess;
     }
     if (!ok) {
         qdot_destroy(h);
@@ -137,6 +174,7 @@ int32_t qdot_destroy(qdot_handle *h)
     DeviceGuard g(h->device);
     (void)hipDeviceSynchronize();
     if (h->ws) (void)hipFree(h->ws);
+    if (h->s1tab) (void)hipFree(h->s1tab);
     if (h->partials) (void)hipFree(h->partials);
     if (h->dev_res) (void)hipFree(h->dev_res);
     if (h->host_res) (void)hipHostFree(h->host_res);
@@ -246,6 +284,7 @@ int32_t qdot_classes_async(qdot_handle *h, const double *x, const double *y, int
     int32_t st = check_qdot_args(h, x, y, n, tol, opt, o);
     if (st != QDOT_OK) return st;
     if (!dev_out || (n > 0 && !dev_cls)) return fail(h, QDOT_E_INVAL, "NULL output");
+    if (o.accum_mode != 0) return fail(h, QDOT_E_INVAL, "qdot_classes_async needs accum_mode 0");
     DeviceGuard g(h->device);
     hipError_t e = launch_qdot(make_launch(h, (hipStream_t)stream, n), x, y, n, tol, o, dev_out,
                                dev_cls, (long long *)dev_hist);

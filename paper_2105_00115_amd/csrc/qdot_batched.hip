@@ -646,6 +646,7 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (o.accum_mode != 0) return fail(h, QDOT_E_INVAL, "the batched and CG launches need accum_mode 0");
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
     if ((st = find_plan(h, host_offsets, B, systems, S, &p)) != QDOT_OK) return st;

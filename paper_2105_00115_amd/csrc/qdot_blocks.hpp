@@ -434,6 +434,41 @@ __device__ __forceinline__ void acc_group(const double *xv, const double *yv, in
     }
 }
 
+// ---- one-pass mode: candidate leaves relative to the component's bin -----
+// A component with key k (bin 2^k) has, for every precision, the leaf of
+// Alg. 1 divided by 2^k: s * L * 2^(E_x + E_y - k) with L = fl64(m_x m_y),
+// fl32(fl32(m_x) fl32(m_y)) or r16(m_x) r16(m_y); the factor is 1 or 1/2
+// (the product key's carry), so every candidate lies in (-4, 4) on a fixed
+// grid: 2^-21 (half), 2^-24 (single), 2^-52 (double).  The single and
+// double candidates are split, by rounding to coarser grids with the
+// add-and-subtract trick (exact), into pieces whose sums over up to 2^30
+// components stay exact in FP64 in any order:
+//   half   h                       grid 2^-21, |sum| < 2^32
+//   single a (2^-20) + b           |b| <= 2^-21, grid 2^-24
+//   double a (2^-20) + b (2^-40) + c   |b| <= 2^-21, |c| <= 2^-41, grid 2^-52
+// so the candidate sums of a bin can be formed by atomic adds in any order
+// and the class chosen afterwards.
+__device__ __forceinline__ void s1_pieces(const Comp &c, int key_mode, double p[S1_PIECES])
+{
+    const double c20 = 0x1.8p+32;  // ulp 2^-20 over the whole range of use
+    const double c40 = 0x1.8p+12;  // ulp 2^-40
+    const double sc = (key_mode == 0 && c.mp >= 2.0) ? 0.5 : 1.0;
+    const double sg = c.sgn ? -1.0 : 1.0;
+    const double vd = sg * (c.mp * sc);
+    const double vs = sg * ((double)((float)c.mx * (float)c.my) * sc);
+    const double vh = sg * ((half_round(c.mx) * half_round(c.my)) * sc);
+    p[0] = vh;
+    const double sa = (vs + c20) - c20;
+    p[1] = sa;
+    p[2] = vs - sa;
+    const double da = (vd + c20) - c20;
+    const double dr = vd - da;
+    const double db = (dr + c40) - c40;
+    p[3] = da;
+    p[4] = db;
+    p[5] = dr - db;
+}
+
 // Reduce three compensated accumulators over the block; the result is valid
 // in thread 0.  red must hold 3 * (blockDim / 64) entries.
 template <int NT>

@@ -112,30 +112,44 @@ struct CgLds {
     double dval;
 };
 
+// Pass 1 of qdot for one component pair, into the block's LDS histogram.
+__device__ __forceinline__ void scan_pair(double a, double b, int key_mode, CgLds &L,
+                                          unsigned int &nz, unsigned int &bad)
+{
+    const Comp c = component(a, b, key_mode);
+    nz += c.zero ? 1u : 0u;
+    bad |= c.bad ? 1u : 0u;
+    atomicAdd(&L.h[c.slot], 1u);
+}
+
 // a.b over the gang's rows by qdot (buffer k), value identical in every block.
+// With `scanned` the caller has already put its rows' keys into L.h (while
+// it produced a or b) and passes its zero count and non-finite flag.
 __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, int64_t n, int64_t r0, int64_t r1,
                             double tol, int key_mode, int score_mode, int nonstrict, Gang *gg,
-                            int G, int gb, int k, CgLds &L, qdot_result *trace_slot)
+                            int G, int gb, int k, CgLds &L, qdot_result *trace_slot,
+                            bool scanned = false, unsigned int nz = 0, unsigned int bad = 0)
 {
     DotOut o = {0.0, false, true};
     GangQ &Q = gg->qb[k];
     const bool vec = ((((uintptr_t)a) | ((uintptr_t)bv)) & 15) == 0;
-    // pass 1 over own rows
-    unsigned int nz = 0, bad = 0;
-    auto scan = [&](const double *xv, const double *yv, int64_t, int lim) {
+    if (!scanned) {
+        // pass 1 over own rows
+        auto scan = [&](const double *xv, const double *yv, int64_t, int lim) {
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const Comp c = component(xv[e], yv[e], key_mode);
-            const bool valid = e < lim;
-            nz += (valid & c.zero) ? 1u : 0u;
-            bad |= (valid & c.bad) ? 1u : 0u;
-            if (valid) atomicAdd(&L.h[c.slot], 1u);
-        }
-    };
-    if (vec)
-        stream_strided<true, 2>(a, bv, r0, 2 * CHUNK, r1, scan);
-    else
-        stream_strided<false, 2>(a, bv, r0, 2 * CHUNK, r1, scan);
+            for (int e = 0; e < 4; e++) {
+                const Comp c = component(xv[e], yv[e], key_mode);
+                const bool valid = e < lim;
+                nz += (valid & c.zero) ? 1u : 0u;
+                bad |= (valid & c.bad) ? 1u : 0u;
+                if (valid) atomicAdd(&L.h[c.slot], 1u);
+            }
+        };
+        if (vec)
+            stream_strided<true, 2>(a, bv, r0, 2 * CHUNK, r1, scan);
+        else
+            stream_strided<false, 2>(a, bv, r0, 2 * CHUNK, r1, scan);
+    }
     __syncthreads();
     int lo = W, hi = -1;
     for (int j = threadIdx.x; j < W; j += BLOCK) {
@@ -260,14 +274,22 @@ __device__ __forceinline__ DotOut gang_dot64(const double *a, const double *bv, 
 // out[i] = sum_j val[j] * v[col[j]] over rows [r0, r1), each row summed in
 // column-storage order (plain multiply, then add).  v may hold entries that
 // other blocks wrote in this launch, so it is read with device-scope loads.
-// A thread takes SR rows at once so that their loads overlap.
-constexpr int SR = 4;
+// A thread takes SR rows at once and issues the column and value loads of
+// their first SNZ entries, then every gather, before it adds: two memory
+// latencies per SR rows instead of two per entry.  Longer rows finish in a
+// plain loop.
+constexpr int SR = 2;
+constexpr int SNZ = 8;
+// With SCAN the row result is also keyed against v's own entry (pass 1 of
+// the qdot v . out that follows, fused here so that v and out are not read
+// again for it).
+template <bool SCAN = false>
 __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, double *out, int64_t r0,
-                                          int64_t r1)
+                                          int64_t r1, int key_mode = 0, CgLds *L = nullptr,
+                                          unsigned int *nz = nullptr, unsigned int *bad = nullptr)
 {
     for (int64_t base = r0; base < r1; base += (int64_t)SR * BLOCK) {
         int32_t beg[SR], len[SR];
-        int maxlen = 0;
 #pragma unroll
         for (int u = 0; u < SR; u++) {
             const int64_t i = base + u * BLOCK + threadIdx.x;
@@ -277,23 +299,40 @@ __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, doubl
                 beg[u] = S.rowptr[i];
                 len[u] = S.rowptr[i + 1] - beg[u];
             }
-            maxlen = max(maxlen, len[u]);
         }
-        double s[SR] = {0.0, 0.0, 0.0, 0.0};
-        for (int jj = 0; jj < maxlen; jj++) {
+        int32_t ci[SR][SNZ];
+        double pv[SR][SNZ];
 #pragma unroll
-            for (int u = 0; u < SR; u++) {
+        for (int u = 0; u < SR; u++)
+#pragma unroll
+            for (int jj = 0; jj < SNZ; jj++) {
+                ci[u][jj] = 0;
+                pv[u][jj] = 0.0;
                 if (jj < len[u]) {
-                    const int32_t j = beg[u] + jj;
-                    const double pr = S.val[j] * ld_dev(&v[S.col[j]]);
-                    s[u] = s[u] + pr;
+                    ci[u][jj] = S.col[beg[u] + jj];
+                    pv[u][jj] = S.val[beg[u] + jj];
                 }
             }
-        }
+#pragma unroll
+        for (int u = 0; u < SR; u++)
+#pragma unroll
+            for (int jj = 0; jj < SNZ; jj++)
+                if (jj < len[u]) pv[u][jj] = pv[u][jj] * ld_dev(&v[ci[u][jj]]);
 #pragma unroll
         for (int u = 0; u < SR; u++) {
+            double s = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < SNZ; jj++)
+                if (jj < len[u]) s = s + pv[u][jj];
+            for (int32_t j = beg[u] + SNZ; j < beg[u] + len[u]; j++) {
+                const double pr = S.val[j] * ld_dev(&v[S.col[j]]);
+                s = s + pr;
+            }
             const int64_t i = base + u * BLOCK + threadIdx.x;
-            if (i < r1) out[i] = s[u];
+            if (i < r1) {
+                out[i] = s;
+                if (SCAN) scan_pair(v[i], s, key_mode, *L, *nz, *bad);
+            }
         }
     }
 }
@@ -308,11 +347,12 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
     const int64_t r0 = min(n, (int64_t)gb * per), r1 = min(n, r0 + per);
     int k = 0;  // qdot buffer / partials parity
     int ntr = 0;
-    auto dot = [&](const double *a, const double *bv) {
+    auto dot = [&](const double *a, const double *bv, bool scanned = false, unsigned int nz = 0,
+                   unsigned int bad = 0) {
         DotOut o;
         if (S.use_qdot) {
             o = gang_qdot(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict, gg, G, gb, k,
-                          L, (gb == 0 && S.trace) ? S.trace + ntr : nullptr);
+                          L, (gb == 0 && S.trace) ? S.trace + ntr : nullptr, scanned, nz, bad);
             ntr++;
         } else {
             o = gang_dot64(a, bv, r0, r1, gg, G, gb, k, L);
@@ -350,32 +390,75 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
             break;
         }
         if (!(healthy = gang_barrier(gg, G))) break;  // p complete
-        spmv_rows(S, S.p, S.q, r0, r1);
+        unsigned int nz1 = 0, bad1 = 0;
+        if (S.use_qdot)
+            spmv_rows<true>(S, S.p, S.q, r0, r1, key_mode, &L, &nz1, &bad1);
+        else
+            spmv_rows(S, S.p, S.q, r0, r1);
         __syncthreads();
-        const DotOut d = dot(S.p, S.q);
+        const DotOut d = dot(S.p, S.q, S.use_qdot != 0, nz1, bad1);
         if (!(healthy = d.ok)) break;
         if (!(d.value > 0.0) || !isfinite(d.value) || d.all_perf) {
             status = QDOT_E_BREAKDOWN;
             break;
         }
         const double alpha = c / d.value;
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
-            const double ap = alpha * S.p[i];
-            st_dev(&S.x[i], S.x[i] + ap);
-            const double aq = alpha * S.q[i];
-            S.r[i] = S.r[i] - aq;
+        // x += alpha p, r -= alpha q (four rows' loads in flight per thread),
+        // with pass 1 of the qdot r . r that follows fused in
+        unsigned int nz2 = 0, bad2 = 0;
+        const bool scan_r = S.use_qdot != 0;
+        auto xr_row = [&](int64_t i, double pi, double xi, double qi, double ri) {
+            const double ap = alpha * pi;
+            st_dev(&S.x[i], xi + ap);
+            const double aq = alpha * qi;
+            const double rn = ri - aq;
+            S.r[i] = rn;
+            if (scan_r) scan_pair(rn, rn, key_mode, L, nz2, bad2);
+        };
+        {
+            int64_t i = r0 + threadIdx.x;
+            for (; i + 3 * BLOCK < r1; i += 4 * BLOCK) {
+                double pi[4], xi[4], qi[4], ri[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    pi[u] = S.p[i + u * BLOCK];
+                    xi[u] = S.x[i + u * BLOCK];
+                    qi[u] = S.q[i + u * BLOCK];
+                    ri[u] = S.r[i + u * BLOCK];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) xr_row(i + u * BLOCK, pi[u], xi[u], qi[u], ri[u]);
+            }
+            for (; i < r1; i += BLOCK) xr_row(i, S.p[i], S.x[i], S.q[i], S.r[i]);
         }
         __syncthreads();
-        const DotOut cn = dot(S.r, S.r);
+        const DotOut cn = dot(S.r, S.r, scan_r, nz2, bad2);
         if (!(healthy = cn.ok)) break;
         if (cn.all_perf) {
             status = QDOT_E_BREAKDOWN;
             break;
         }
         const double beta = cn.value / c;
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
-            const double bp = beta * S.p[i];
-            st_dev(&S.p[i], S.r[i] + bp);
+        // p = r + beta p (four rows' loads in flight per thread)
+        {
+            int64_t i = r0 + threadIdx.x;
+            for (; i + 3 * BLOCK < r1; i += 4 * BLOCK) {
+                double pi[4], ri[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    pi[u] = S.p[i + u * BLOCK];
+                    ri[u] = S.r[i + u * BLOCK];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const double bp = beta * pi[u];
+                    st_dev(&S.p[i + u * BLOCK], ri[u] + bp);
+                }
+            }
+            for (; i < r1; i += BLOCK) {
+                const double bp = beta * S.p[i];
+                st_dev(&S.p[i], S.r[i] + bp);
+            }
         }
         c = cn.value;
         iters++;

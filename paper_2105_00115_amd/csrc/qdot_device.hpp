@@ -45,9 +45,17 @@ struct Ws {
     int c32;                     // exponent offset of FP32 leaves
     int skip;                    // nothing to accumulate (result final)
     int flags;                   // result flags known after selection
+    int s1_lo, s1_hi;            // live slot range of the last scan (one-pass mode)
     int pad1;
     unsigned char lut[W_LUT];    // class of every key slot (+ zero slot)
 };
+
+// One-pass (exact per-bin) accumulation: a block keeps candidate sums for
+// the S1_WIN bins below its running maximum key; S1_PIECES exact FP64 sums
+// per bin (half leaf; single leaf in two pieces; double leaf in three).
+constexpr int S1_WIN = 256;
+constexpr int S1_PIECES = 6;
+constexpr int64_t S1_MAX_N = (int64_t)1 << 30;  // bound of the exact-sum argument
 
 // One operand split into unbiased exponent and 52-bit fraction of its
 // normalised significand m = 1.frac in [1, 2).  General path (subnormals

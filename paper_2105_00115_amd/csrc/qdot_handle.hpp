@@ -12,6 +12,7 @@ struct qdot_handle {
     qd::Ws *ws = nullptr;            // device control block
     double *partials = nullptr;      // per-block partials
     int partial_blocks = 0;          // capacity in blocks
+    double *s1tab = nullptr;         // one-pass mode per-bin sums (kept zero between calls)
     qdot_result *dev_res = nullptr;  // device result slot for the sync API
     qdot_result *host_res = nullptr; // pinned host mirror
     qdot_tune tune[QDOT_TUNE_BUCKETS];
@@ -64,6 +65,9 @@ bool tune_ok(const qdot_tune &t);
 // or NULL when timing is off or events cannot be created.
 hipEvent_t *take_events(qdot_handle *h, int kind);
 bool options_ok(const qdot_options &o);
+// One-pass mode (accum_mode 1) preconditions: n within the exact-sum bound
+// and a kept-bin depth below the window for any histogram of n components.
+bool s1_admissible(int64_t n, double tol, const qdot_options &o);
 void free_plans(qdot_handle *h);
 void free_cg(qdot_handle *h);
 int32_t ensure_solver_vectors(qdot_handle *h, int64_t n);

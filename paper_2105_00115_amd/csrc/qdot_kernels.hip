@@ -137,6 +137,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
         ws->c32 = p.c32;
         ws->flags = p.flags;
         ws->skip = p.skip;
+        ws->s1_lo = lo;
+        ws->s1_hi = hi;
     }
 }
 
@@ -229,6 +231,212 @@ __global__ __launch_bounds__(BLOCK) void k_fin(const Ws *__restrict__ ws,
             for (int w = 1; w < BLOCK / 64; w++) f[q] = acc_merge(f[q], red[q][w]);
         }
         combine_value(f, ws->e_max, ws->t, ws->c32, ws->flags, out);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-pass mode (exact per-bin accumulation): the scan that also forms, per
+// bin, the candidate sums of every precision, so the data is read once.
+//
+// A component of bin k can be kept only if its score is >= 0, i.e. if
+// e_max - k <= ceil(log2 M_k) - t + 1; the host passes `depth`, a bound of
+// that over every histogram n components can give, and admits the mode only
+// when depth <= S1_WIN.  The block's own running maximum key `top` never
+// exceeds e_max, so the bins below top - depth + 1 are perforated whatever
+// the rest of the data holds, and the `depth` bins under `top` (slot = bin
+// mod S1_WIN) are all a block has to keep.  `top` is block-uniform: each group's new maximum is agreed
+// at a barrier (two alternating LDS words, so one barrier per group
+// suffices), and when it rises the slots of the entering bins are cleared
+// before anyone adds to them.  The candidate pieces are exact in any order
+// (s1_pieces), so LDS and global atomic adds give the same sums every run.
+// At the end each block adds its window into one of HIST_COPIES global
+// tables; k_s1_fin picks each kept bin's class and clears the tables.
+// ---------------------------------------------------------------------------
+template <bool VEC, int U>
+__global__ __launch_bounds__(BLOCK) void k_s1_scan(const double *__restrict__ x,
+                                                   const double *__restrict__ y,
+                                                   int64_t n, int key_mode, int depth,
+                                                   Ws *__restrict__ ws,
+                                                   double *__restrict__ tab)
+{
+    __shared__ unsigned int h[W + 1];
+    __shared__ double win[S1_WIN][S1_PIECES];
+    __shared__ int s_top[2];
+    __shared__ int2 wr[BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int i = tid; i < W + 1; i += BLOCK) h[i] = 0;
+    for (int i = tid; i < S1_WIN * S1_PIECES; i += BLOCK) (&win[0][0])[i] = 0.0;
+    if (tid < 2) s_top[tid] = -1;
+    __syncthreads();
+
+    int top = -1;  // highest live slot seen so far by the block (-1: none)
+    unsigned int nz = 0, bad = 0;
+    const int64_t group = (int64_t)CHUNK * U;
+    const int64_t step = (int64_t)gridDim.x * group;
+    int par = 0;
+    for (int64_t base = (int64_t)blockIdx.x * group; base < n; base += step, par ^= 1) {
+        double xv[U][4], yv[U][4];
+        int lim[U];
+        const bool full = base + group <= n;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + tid * EPT;
+            if (full) {
+                lim[u] = 4;
+                load4_full<VEC>(x + i0, xv[u]);
+                load4_full<VEC>(y + i0, yv[u]);
+            } else {
+                const int64_t left = n - i0;
+                lim[u] = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
+                load4_tail(x + i0, lim[u], xv[u]);
+                load4_tail(y + i0, lim[u], yv[u]);
+            }
+        }
+        int live[U][4];
+        int wmax = -1;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const Comp c = component(xv[u][e], yv[u][e], key_mode);
+                const bool valid = e < lim[u];
+                nz += (valid & c.zero) ? 1u : 0u;
+                bad |= (valid & c.bad) ? 1u : 0u;
+                if (valid) atomicAdd(&h[c.slot], 1u);
+                live[u][e] = (valid && c.slot != ZERO_SLOT) ? c.slot : -1;
+                wmax = max(wmax, live[u][e]);
+            }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
+        if (lane == 0 && wmax > top) atomicMax(&s_top[par], wmax);
+        __syncthreads();
+        const int nt = s_top[par];
+        if (nt > top) {
+            // bins top+1 .. nt enter; their slots held bins that now lie
+            // below the window
+            const int nclr = min(nt - top, S1_WIN);
+            for (int i = tid; i < nclr * S1_PIECES; i += BLOCK)
+                win[(nt - i / S1_PIECES) & (S1_WIN - 1)][i % S1_PIECES] = 0.0;
+            __syncthreads();
+            top = nt;
+        }
+        const int wlo = top - depth + 1;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                if (live[u][e] >= wlo && live[u][e] >= 0) {
+                    const Comp c = component(xv[u][e], yv[u][e], key_mode);
+                    double pc[S1_PIECES];
+                    s1_pieces(c, key_mode, pc);
+                    double *w = win[live[u][e] & (S1_WIN - 1)];
+#pragma unroll
+                    for (int q = 0; q < S1_PIECES; q++)
+                        if (pc[q] != 0.0) atomicAdd(&w[q], pc[q]);
+                }
+            }
+    }
+    __syncthreads();
+
+    // histogram merge and live range, as in k_scan
+    unsigned long long *gh = ws->hist[blockIdx.x % HIST_COPIES];
+    int lo = W, hi = -1;
+    for (int i = tid; i < W; i += BLOCK) {
+        const unsigned int v = h[i];
+        if (v) {
+            atomicAdd(&gh[i], (unsigned long long)v);
+            lo = min(lo, i);
+            hi = max(hi, i);
+        }
+    }
+    nz = wave_sum_u32(nz);
+    bad = wave_sum_u32(bad);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo = min(lo, __shfl_xor(lo, m, 64));
+        hi = max(hi, __shfl_xor(hi, m, 64));
+    }
+    if (lane == 0) {
+        if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
+        if (bad) atomicOr(&ws->nonfinite, 1u);
+        wr[tid >> 6] = make_int2(lo, hi);
+    }
+    // window -> global table (bins top .. top - depth + 1, non-zero sums)
+    if (top >= 0) {
+        double *tb = tab + (size_t)(blockIdx.x % HIST_COPIES) * W * S1_PIECES;
+        for (int i = tid; i < depth * S1_PIECES; i += BLOCK) {
+            const int bin = top - i / S1_PIECES;
+            if (bin < 0) continue;
+            const double v = win[bin & (S1_WIN - 1)][i % S1_PIECES];
+            if (v != 0.0) atomicAdd(&tb[(size_t)bin * S1_PIECES + i % S1_PIECES], v);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int2 r = wr[0];
+        for (int w = 1; w < BLOCK / 64; w++) r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
+        ws->block_range[blockIdx.x] = r;
+    }
+}
+
+// One-pass mode, final step (one block): every kept bin contributes the
+// candidate sum of its class, scaled by 2^(k - e_max); the sums of the
+// table copies and pieces are exact, their scaled total is summed with
+// compensation and rounded once.  The block then clears the table over the
+// live range for the next call.
+__global__ __launch_bounds__(BLOCK) void k_s1_fin(const Ws *__restrict__ ws,
+                                                  double *__restrict__ tab,
+                                                  qdot_result *__restrict__ out)
+{
+    __shared__ Acc red[3][BLOCK / 64];
+    const int tid = threadIdx.x;
+    const int lo = ws->s1_lo, hi = ws->s1_hi;
+    if (!ws->skip) {
+        const int e_max = ws->e_max;
+        const int top = e_max - KMIN;
+        Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};  // double, single, half
+        for (int j = tid; j < S1_WIN; j += BLOCK) {
+            const int bin = top - j;
+            if (bin < lo) continue;
+            const int cls = ws->lut[bin];
+            if (cls == QDOT_PERF) continue;
+            double v[S1_PIECES] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int c = 0; c < HIST_COPIES; c++) {
+                const double *tb = tab + ((size_t)c * W + bin) * S1_PIECES;
+#pragma unroll
+                for (int q = 0; q < S1_PIECES; q++) v[q] += tb[q];
+            }
+            if (cls == QDOT_DOUBLE) {
+                acc_add(a[0], ldexp(v[3], -j));
+                acc_add(a[0], ldexp(v[4], -j));
+                acc_add(a[0], ldexp(v[5], -j));
+            } else if (cls == QDOT_SINGLE) {
+                acc_add(a[1], ldexp(v[1], -j));
+                acc_add(a[1], ldexp(v[2], -j));
+            } else {
+                acc_add(a[2], ldexp(v[0], -j));
+            }
+        }
+        block_reduce3<BLOCK>(a, red);
+        if (tid == 0) {
+            Acc tot = a[0];
+            acc_add(tot, a[1].s);
+            acc_add(tot, a[2].s);
+            tot.c = tot.c + (a[1].c + a[2].c);
+            const double value = ldexp(tot.s + tot.c, e_max);
+            out->value = value;
+            out->part[QDOT_DOUBLE] = ldexp(a[0].s + a[0].c, e_max);
+            out->part[QDOT_SINGLE] = ldexp(a[1].s + a[1].c, e_max);
+            out->part[QDOT_HALF] = ldexp(a[2].s + a[2].c, e_max);
+            out->flags = ws->flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
+        }
+    }
+    if (hi >= lo) {
+        const int64_t cnt = (int64_t)(hi - lo + 1) * S1_PIECES;
+        for (int c = 0; c < HIST_COPIES; c++) {
+            double *tb = tab + ((size_t)c * W + lo) * S1_PIECES;
+            for (int64_t i = tid; i < cnt; i += BLOCK) tb[i] = 0.0;
+        }
     }
 }
 
@@ -328,10 +536,54 @@ static int launch_acc(const Launch &L, const double *x, const double *y, int64_t
     }
 }
 
+template <bool VEC, int U>
+static int launch_s1_u(const Launch &L, const double *x, const double *y, int64_t n,
+                       int key_mode, int depth)
+{
+    const int grid = grid_for(n, U, L.scan_blocks);
+    hipLaunchKernelGGL((k_s1_scan<VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+                       key_mode, depth, L.ws, L.s1tab);
+    return grid;
+}
+
+template <bool VEC>
+static int launch_s1(const Launch &L, const double *x, const double *y, int64_t n,
+                     int key_mode, int depth)
+{
+    switch (L.scan_unroll) {
+    case 1: return launch_s1_u<VEC, 1>(L, x, y, n, key_mode, depth);
+    case 4: return launch_s1_u<VEC, 4>(L, x, y, n, key_mode, depth);
+    default: return launch_s1_u<VEC, 2>(L, x, y, n, key_mode, depth);
+    }
+}
+
+// One-pass mode: scan with per-bin candidate sums, cutoff, pick per bin.
+static hipError_t launch_qdot_s1(const Launch &L, const double *x, const double *y, int64_t n,
+                                 double tol, const qdot_options &o, qdot_result *out)
+{
+    const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
+    hipStream_t s = L.stream;
+    if (L.ev) (void)hipEventRecord(L.ev[0], s);
+    const int depth = s1_depth(n, tol, o);
+    const int nscan = vec ? launch_s1<true>(L, x, y, n, o.key_mode, depth)
+                          : launch_s1<false>(L, x, y, n, o.key_mode, depth);
+    if (L.ev) (void)hipEventRecord(L.ev[1], s);
+    hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
+                       o.boundary_mode, n, nscan, out, nullptr);
+    if (L.ev) {
+        (void)hipEventRecord(L.ev[2], s);
+        (void)hipEventRecord(L.ev[3], s);
+    }
+    hipLaunchKernelGGL(k_s1_fin, dim3(1), dim3(BLOCK), 0, s, L.ws, L.s1tab, out);
+    if (L.ev) (void)hipEventRecord(L.ev[4], s);
+    return hipGetLastError();
+}
+
 hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_t n,
                        double tol, const qdot_options &o, qdot_result *out,
                        unsigned char *cls_out, long long *hist_out)
 {
+    if (o.accum_mode == 1) return launch_qdot_s1(L, x, y, n, tol, o, out);
     const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
     hipStream_t s = L.stream;
     if (L.ev) (void)hipEventRecord(L.ev[0], s);

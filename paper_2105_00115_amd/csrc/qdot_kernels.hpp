@@ -15,8 +15,14 @@ struct Launch {
     int scan_unroll;    // 1, 2 or 4 groups of 4 elements in flight per lane
     int acc_blocks;     // grid cap of the accumulate pass / FP64 dot
     int acc_unroll;
+    double *s1tab;      // one-pass mode: HIST_COPIES x W x S1_PIECES sums (zero between calls)
     hipEvent_t *ev;     // NULL, or events recorded around each kernel
 };
+
+// One-pass mode: number of bins below e_max that can hold kept components,
+// for any histogram of n components at this tolerance (the mode is admitted
+// when it is <= S1_WIN).
+int s1_depth(int64_t n, double tol, const qdot_options &o);
 
 // Enqueue scan -> cutoff -> accumulate for one qdot.  cls_out (n bytes) and
 // hist_out (W int64) are optional debug outputs.

@@ -186,6 +186,8 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
     if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
+    if (use_qdot && o.accum_mode == 1 && !s1_admissible(A->n, qtol, o))
+        return fail(h, QDOT_E_INVAL, "accum_mode 1 not admissible for this n and qtol");
     DeviceGuard g(h->device);
     const int64_t n = A->n;
     int32_t st = ensure_solver_vectors(h, n);

@@ -273,6 +273,13 @@ def test_golden_worked_examples(name):
         assert Fraction(r["bound_rel"]) == F(ex["bound_rel"])
     if "exact" in ex:
         assert Fraction(oracle.dot_exact(x, y)) == F(ex["exact"])
+    # the one-pass reading: same classes and counts, value summed exactly
+    r1 = oracle.qdot(x, y, tol, opt=[0, 0, 0, 1], want_classes=True)
+    for k in ("count", "n_bins", "e_max", "e_min", "t", "flags", "n_zero"):
+        assert r1[k] == r[k], k
+    assert np.array_equal(r1["classes"], r["classes"])
+    v1 = ex["value_s1"]
+    assert Fraction(r1["value"]) == (F(v1) if isinstance(v1, str) else Fraction(v1))
 
 
 # --------------------------------------------------------------------------
@@ -401,6 +408,45 @@ def test_exact_products_all_double_equal_exact_dot():
     r = oracle.qdot(x, y, 1e-300)
     assert r["count"][oracle.DOUBLE] == 3000
     assert r["value"] == oracle.dot_exact(x, y)
+
+
+def test_s1_exact_products_all_double_equal_exact_dot():
+    g = workloads.rng(82)
+    x = np.ldexp(g.integers(1, 1 << 20, 3000).astype(float), g.integers(-40, 40, 3000))
+    y = np.ldexp(g.integers(1, 1 << 20, 3000).astype(float), g.integers(-40, 40, 3000))
+    y[::3] *= -1.0
+    r = oracle.qdot(x, y, 1e-300, opt=[0, 0, 0, 1])
+    assert r["count"][oracle.DOUBLE] == 3000
+    assert r["value"] == oracle.dot_exact(x, y)
+
+
+def test_s1_short_significands_sum_kept_products_exactly():
+    # with at most 11 significant bits per operand every leaf of every class
+    # equals x_i y_i exactly, so the one-pass value is the correctly rounded
+    # sum of the kept products (classes taken from the oracle, pinned above)
+    g = workloads.rng(83)
+    n = 5000
+    x = np.ldexp(g.integers(1 << 10, 1 << 11, n).astype(float), g.integers(-60, 20, n))
+    y = np.ldexp(g.integers(1 << 10, 1 << 11, n).astype(float), g.integers(-60, 20, n))
+    x[g.random(n) < 0.5] *= -1.0
+    for tol in (1e-3, 1e-6, 1e-9):
+        r = oracle.qdot(x, y, tol, opt=[0, 0, 0, 1], want_classes=True)
+        kept = r["classes"] != oracle.PERF
+        assert 0 < kept.sum() < n
+        exact = sum((Fraction(a) * Fraction(b) for a, b, k in zip(x, y, kept) if k), Fraction(0))
+        assert Fraction(r["value"]) == Fraction(float(exact)), tol
+        # and the classes mix precisions
+        assert len(set(r["classes"][kept].tolist())) >= 2
+
+
+def test_s1_value_is_permutation_invariant():
+    x, y = workloads.log_uniform_pair(30000, 84)
+    g = workloads.rng(85)
+    a = oracle.qdot(x, y, 1e-6, opt=[0, 0, 0, 1])
+    for _ in range(3):
+        pm = g.permutation(len(x))
+        b = oracle.qdot(x[pm], y[pm], 1e-6, opt=[0, 0, 0, 1])
+        assert b["value"] == a["value"] and b["count"] == a["count"]
 
 
 def test_accum_modes_share_classes():
