@@ -156,6 +156,8 @@ typedef struct qdot_tune {
     int32_t scan_unroll;
     int32_t acc_blocks_per_cu;  /* accumulate pass and FP64 dot, 1..16 */
     int32_t acc_unroll;
+    int32_t onepass_blocks_per_cu; /* one-pass scan (accum_mode 1), 1..16 */
+    int32_t onepass_unroll;
 } qdot_tune;
 
 /* Tuning is kept per size bucket: n < 2^16, < 2^20, < 2^24, >= 2^24. */
@@ -185,8 +187,9 @@ QDOT_API int32_t qdot_set_tune(qdot_handle *h, int32_t bucket, const qdot_tune *
 QDOT_API int32_t qdot_get_tune(const qdot_handle *h, int32_t bucket, qdot_tune *cfg);
 
 /* Load tuned configurations from a text file written by the autotuner: one
- * line per bucket, "bucket scan_bpc scan_unroll acc_bpc acc_unroll", '#'
- * starts a comment.  Invalid lines are rejected with QDOT_E_INVAL and leave
+ * line per bucket, "bucket scan_bpc scan_unroll acc_bpc acc_unroll
+ * [onepass_bpc onepass_unroll]" (without the last two the bucket's one-pass
+ * shape is left as it is), '#' starts a comment.  Invalid lines are rejected with QDOT_E_INVAL and leave
  * the handle unchanged.  qdot_create also loads the file named by the
  * environment variable QDOT_TUNE_FILE when it is set. */
 QDOT_API int32_t qdot_load_tune(qdot_handle *h, const char *path);

@@ -78,7 +78,8 @@ CG_RESULT_BYTES = C.sizeof(QdotCgResult)
 
 class QdotTune(C.Structure):
     _fields_ = [("scan_blocks_per_cu", C.c_int32), ("scan_unroll", C.c_int32),
-                ("acc_blocks_per_cu", C.c_int32), ("acc_unroll", C.c_int32)]
+                ("acc_blocks_per_cu", C.c_int32), ("acc_unroll", C.c_int32),
+                ("onepass_blocks_per_cu", C.c_int32), ("onepass_unroll", C.c_int32)]
 
 
 TUNE_BUCKETS = 4  # n < 2^16, < 2^20, < 2^24, >= 2^24
@@ -254,9 +255,9 @@ class Qdot:
         return d.value, c.value
 
     def set_tune(self, bucket: int, scan_bpc: int, scan_unroll: int, acc_bpc: int,
-                 acc_unroll: int):
+                 acc_unroll: int, onepass_bpc: int = 4, onepass_unroll: int = 1):
         """bucket -1 sets all size buckets."""
-        cfg = QdotTune(scan_bpc, scan_unroll, acc_bpc, acc_unroll)
+        cfg = QdotTune(scan_bpc, scan_unroll, acc_bpc, acc_unroll, onepass_bpc, onepass_unroll)
         st = lib().qdot_set_tune(self._h, int(bucket), C.byref(cfg))
         if st != OK:
             self._raise(st, "qdot_set_tune")
@@ -269,7 +270,8 @@ class Qdot:
         st = lib().qdot_get_tune(self._h, int(bucket), C.byref(t))
         if st != OK:
             raise QdotError(st, "qdot_get_tune")
-        return (t.scan_blocks_per_cu, t.scan_unroll, t.acc_blocks_per_cu, t.acc_unroll)
+        return (t.scan_blocks_per_cu, t.scan_unroll, t.acc_blocks_per_cu, t.acc_unroll,
+                t.onepass_blocks_per_cu, t.onepass_unroll)
 
     def load_tune(self, path: str):
         st = lib().qdot_load_tune(self._h, os.fsencode(path))

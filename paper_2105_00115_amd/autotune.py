@@ -30,16 +30,16 @@ def default_path(arch: str, cus: int) -> str:
                         f"{arch}_{cus}cu.txt")
 
 
-def _time_config(h, x, y, tol, out, cfg, reps):
+def _time_config(h, x, y, tol, out, cfg, reps, opt=None):
     h.set_tune(-1, *cfg)
     for _ in range(3):
-        h.qdot_async(x, y, tol, out)
+        h.qdot_async(x, y, tol, out, opt=opt)
     import torch
     torch.cuda.synchronize()
     h.timing_read()
     h.timing_enable(True)
     for _ in range(reps):
-        h.qdot_async(x, y, tol, out)
+        h.qdot_async(x, y, tol, out, opt=opt)
     torch.cuda.synchronize()
     h.timing_enable(False)
     t = h.timing_read()
@@ -75,15 +75,30 @@ def tune(reps: int = 20, seed: int = 7, tol: float = 1e-6, log=print):
         if mixed not in results:
             results[mixed] = _time_config(h, x, y, tol, out, mixed, reps)
         best = min(results, key=lambda c: sum(results[c]))
+        # one-pass scan (accum_mode 1): its value is an exact sum, so every
+        # shape must give the same bits
+        one = [0, 0, 0, 1]
+        h.set_tune(-1, *best)
+        ref1 = h.qdot(x, y, tol, opt=one)
+        res1 = {}
+        for bpc in BPC:
+            for u in UNROLL:
+                cfg = best + (bpc, u)
+                res1[cfg] = _time_config(h, x, y, tol, out, cfg, reps, opt=one)
+                r = q.parse_results(out)[0]
+                if (r["count"], r["value"]) != (ref1["count"], ref1["value"]):
+                    raise RuntimeError(f"one-pass config {cfg} changed the result")
+        best = min(res1, key=lambda c: sum(res1[c]))
         h.set_tune(-1, *best)
         cls, hist, r = h.qdot_classes(x, y, tol)
         if not (torch.equal(cls, ref_cls) and torch.equal(hist, ref_hist)
                 and r["count"] == ref["count"]):
             raise RuntimeError(f"config {best} changed the classes")
-        t = results[best]
+        t = results[best[:4]]
+        t1 = res1[best]
         log(f"bucket {b} n={n}: best {best} scan {t[0]*1e3:.1f} us cut {t[1]*1e3:.1f} us "
-            f"acc {t[2]*1e3:.1f} us fin {t[3]*1e3:.1f} us")
-        chosen.append((b, n, best, t))
+            f"acc {t[2]*1e3:.1f} us fin {t[3]*1e3:.1f} us; one-pass scan {t1[0]*1e3:.1f} us")
+        chosen.append((b, n, best, t + (t1[0],)))
         del x, y
     return h, chosen
 
@@ -94,10 +109,12 @@ def write(path, chosen, arch, cus):
         f.write(f"# qdot launch shapes for {arch} with {cus} CUs, written by "
                 f"python -m paper_2105_00115_amd.autotune on {time.strftime('%Y-%m-%d')}\n")
         f.write("# bucket scan_blocks_per_cu scan_unroll acc_blocks_per_cu acc_unroll"
-                "   (measured n, scan/cut/acc/fin us)\n")
+                " onepass_blocks_per_cu onepass_unroll"
+                "   (measured n, scan/cut/acc/fin us, one-pass scan us)\n")
         for b, n, cfg, t in chosen:
-            f.write(f"{b} {cfg[0]} {cfg[1]} {cfg[2]} {cfg[3]}   # n={n} "
-                    f"{t[0]*1e3:.1f}/{t[1]*1e3:.1f}/{t[2]*1e3:.1f}/{t[3]*1e3:.1f}\n")
+            f.write(f"{b} {' '.join(str(c) for c in cfg)}   # n={n} "
+                    f"{t[0]*1e3:.1f}/{t[1]*1e3:.1f}/{t[2]*1e3:.1f}/{t[3]*1e3:.1f}, "
+                    f"{t[4]*1e3:.1f}\n")
 
 
 def main(argv=None):

@@ -29,15 +29,18 @@ qdot_tune default_tune(int bucket)
     // measured on MI355X (256 CUs) at n = 2^27; small sizes keep both passes
     // on the same block -> chunk mapping so the second pass finds the data
     // in the same XCD's L2
-    if (bucket < 3) return qdot_tune{2, 1, 2, 1};
-    return qdot_tune{2, 1, 2, 2};
+    // in the same XCD's L2; the one-pass scan wants more resident blocks
+    if (bucket < 3) return qdot_tune{2, 1, 2, 1, 4, 1};
+    return qdot_tune{2, 1, 2, 2, 4, 1};
 }
 
 bool tune_ok(const qdot_tune &t)
 {
     auto u_ok = [](int u) { return u == 1 || u == 2 || u == 4; };
-    return t.scan_blocks_per_cu >= 1 && t.scan_blocks_per_cu <= 16 && t.acc_blocks_per_cu >= 1 &&
-           t.acc_blocks_per_cu <= 16 && u_ok(t.scan_unroll) && u_ok(t.acc_unroll);
+    auto b_ok = [](int b) { return b >= 1 && b <= 16; };
+    return b_ok(t.scan_blocks_per_cu) && b_ok(t.acc_blocks_per_cu) &&
+           b_ok(t.onepass_blocks_per_cu) && u_ok(t.scan_unroll) && u_ok(t.acc_unroll) &&
+           u_ok(t.onepass_unroll);
 }
 
 Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n)
@@ -51,6 +54,8 @@ Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n)
     L.scan_unroll = t.scan_unroll;
     L.acc_blocks = std::min(h->partial_blocks, t.acc_blocks_per_cu * h->num_cus);
     L.acc_unroll = t.acc_unroll;
+    L.s1_blocks = std::min(MAX_GRID, t.onepass_blocks_per_cu * h->num_cus);
+    L.s1_unroll = t.onepass_unroll;
     L.s1tab = h->s1tab;
     L.ev = nullptr;
     return L;
@@ -208,7 +213,7 @@ int32_t qdot_set_tune(qdot_handle *h, int32_t bucket, const qdot_tune *cfg)
         if (bucket != -1 && b != bucket) continue;
         const qdot_tune t = cfg ? *cfg : default_tune(b);
         if (!tune_ok(t))
-            return fail(h, QDOT_E_INVAL, "tune out of range (blocks_per_cu 1..16, unroll 1/2/4)");
+            return fail(h, QDOT_E_INVAL, "tune out of range (blocks per CU 1..16, unroll 1/2/4)");
         h->tune[b] = t;
     }
     return QDOT_OK;
@@ -233,11 +238,24 @@ int32_t qdot_load_tune(qdot_handle *h, const char *path)
     while (ok && std::fgets(line, sizeof line, f)) {
         char *hash = std::strchr(line, '#');
         if (hash) *hash = 0;
-        int b, v[4];
-        const int got = std::sscanf(line, "%d %d %d %d %d", &b, &v[0], &v[1], &v[2], &v[3]);
+        int b = -1, v[6] = {0, 0, 0, 0, 0, 0};
+        const int got = std::sscanf(line, "%d %d %d %d %d %d %d", &b, &v[0], &v[1], &v[2], &v[3],
+                                    &v[4], &v[5]);
         if (got <= 0) continue;  // blank or comment
-        const qdot_tune c = {v[0], v[1], v[2], v[3]};
-        if (got != 5 || b < 0 || b >= QDOT_TUNE_BUCKETS || !tune_ok(c)) ok = false;
+        if ((got != 5 && got != 7) || b < 0 || b >= QDOT_TUNE_BUCKETS) {
+            ok = false;
+            continue;
+        }
+        qdot_tune c = t[b];
+        c.scan_blocks_per_cu = v[0];
+        c.scan_unroll = v[1];
+        c.acc_blocks_per_cu = v[2];
+        c.acc_unroll = v[3];
+        if (got == 7) {
+            c.onepass_blocks_per_cu = v[4];
+            c.onepass_unroll = v[5];
+        }
+        if (!tune_ok(c)) ok = false;
         else t[b] = c;
     }
     std::fclose(f);

@@ -48,6 +48,9 @@ struct GangQ {  // per gang and qdot buffer
     unsigned int pad;
 };
 
+constexpr int BAR_GROUPS = 8;    // first level of the barrier of a large gang
+constexpr int BAR_TWO_LEVEL = 64; // gangs larger than this use two levels
+
 struct Gang {
     unsigned int bar_count;
     unsigned int bar_gen;
@@ -55,6 +58,7 @@ struct Gang {
     unsigned int pad;
     GangQ qb[2];
     double partials[2][256 * 6];  // up to MAX_GANG blocks per gang
+    unsigned int bar_sub[BAR_GROUPS][32];  // group counters, one 128-byte line each
 };
 
 constexpr int MAX_GANG = 256;
@@ -64,8 +68,11 @@ constexpr int MAX_GANG = 256;
 // histogram merges, partials, clears) is written with device-scope atomics
 // or write-through stores and read with device-scope loads, so arriving
 // needs only the block's own memory operations to have completed
-// (vmem_drain) and leaving needs no cache invalidation.
-__device__ bool gang_barrier(Gang *gg, int G)
+// (vmem_drain) and leaving needs no cache invalidation.  A gang of more than
+// BAR_TWO_LEVEL blocks arrives in two levels: each block on the counter of
+// its group (gb mod BAR_GROUPS), the last of a group on the gang counter, so
+// no counter takes more than G / BAR_GROUPS serialised atomics.
+__device__ bool gang_barrier(Gang *gg, int G, int gb)
 {
     __shared__ int s_ok;
     vmem_drain();
@@ -73,9 +80,27 @@ __device__ bool gang_barrier(Gang *gg, int G)
     if (threadIdx.x == 0) {
         int ok = 1;
         const unsigned int gen = ld_dev(&gg->bar_gen);
-        const unsigned int arrived =
-            __hip_atomic_fetch_add(&gg->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-        if (arrived == (unsigned)G) {
+        bool last;
+        if (G > BAR_TWO_LEVEL) {
+            const int grp = gb % BAR_GROUPS;
+            const unsigned int members = (unsigned)((G - grp + BAR_GROUPS - 1) / BAR_GROUPS);
+            unsigned int *sc = &gg->bar_sub[grp][0];
+            last = false;
+            if (__hip_atomic_fetch_add(sc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 ==
+                members) {
+                // re-arm the group counter before the gang can be released
+                // (its members wait for the generation below)
+                st_dev(sc, 0u);
+                vmem_drain();
+                last = __hip_atomic_fetch_add(&gg->bar_count, 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) + 1 ==
+                       (unsigned)BAR_GROUPS;
+            }
+        } else {
+            last = __hip_atomic_fetch_add(&gg->bar_count, 1u, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) + 1 == (unsigned)G;
+        }
+        if (last) {
             st_dev(&gg->bar_count, 0u);
             vmem_drain();
             st_dev(&gg->bar_gen, gen + 1);
@@ -173,7 +198,7 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
                                    __HIP_MEMORY_SCOPE_AGENT);
         if (bad) __hip_atomic_fetch_or(&Q.bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (!gang_barrier(gg, G)) {
+    if (!gang_barrier(gg, G, gb)) {
         o.ok = false;
         return o;
     }
@@ -207,7 +232,7 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
             }
         }
     }
-    if (!gang_barrier(gg, G)) {
+    if (!gang_barrier(gg, G, gb)) {
         o.ok = false;
         return o;
     }
@@ -256,14 +281,22 @@ __device__ __forceinline__ DotOut gang_dot64(const double *a, const double *bv, 
     Acc acc[3] = {{(s[0] + s[1]) + (s[2] + s[3]), 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     block_reduce3<BLOCK>(acc, L.red);
     if (threadIdx.x == 0) st_dev(&gg->partials[k][gb * 6], acc[0].s + acc[0].c);
-    if (!gang_barrier(gg, G)) {
+    if (!gang_barrier(gg, G, gb)) {
         o.ok = false;
         return o;
     }
+    // every block sums the gang's partials in the same fixed order (thread
+    // c loads partial c, then a fixed tree), so all hold the same value
+    double v = 0.0;
+    for (int c = threadIdx.x; c < G; c += BLOCK) v += ld_dev(&gg->partials[k][c * 6]);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63) == 0) L.red[0][threadIdx.x >> 6].s = v;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double v = 0.0;
-        for (int c = 0; c < G; c++) v += ld_dev(&gg->partials[k][c * 6]);
-        L.dval = v;
+        double f = L.red[0][0].s;
+        for (int w = 1; w < BLOCK / 64; w++) f += L.red[0][w].s;
+        L.dval = f;
     }
     __syncthreads();
     o.value = L.dval;
@@ -389,7 +422,7 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
             status = QDOT_E_MAXIT;
             break;
         }
-        if (!(healthy = gang_barrier(gg, G))) break;  // p complete
+        if (!(healthy = gang_barrier(gg, G, gb))) break;  // p complete
         unsigned int nz1 = 0, bad1 = 0;
         if (S.use_qdot)
             spmv_rows<true>(S, S.p, S.q, r0, r1, key_mode, &L, &nz1, &bad1);
@@ -465,7 +498,7 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
         if (!(sqrt(c) > thresh)) done = true;
     }
     double relres_true = 0.0;
-    if (healthy) healthy = gang_barrier(gg, G);  // x complete
+    if (healthy) healthy = gang_barrier(gg, G, gb);  // x complete
     if (healthy) {
         spmv_rows(S, S.x, S.q, r0, r1);
         for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) S.q[i] = S.b[i] - S.q[i];
@@ -482,7 +515,7 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
         res->relres_true = relres_true;
     }
     // leave the gang buffers clean and every block past its last use of them
-    if (healthy) gang_barrier(gg, G);
+    if (healthy) gang_barrier(gg, G, gb);
 }
 
 // Clears a gang's barrier, abort flag and histogram buffers (plain stores;
@@ -493,6 +526,7 @@ __device__ __forceinline__ void gang_reset(Gang *gg)
         gg->qb[0].hist[i] = 0u;
         gg->qb[1].hist[i] = 0u;
     }
+    if (threadIdx.x < BAR_GROUPS) gg->bar_sub[threadIdx.x][0] = 0u;
     if (threadIdx.x == 0) {
         gg->bar_count = 0;
         gg->abort = 0;

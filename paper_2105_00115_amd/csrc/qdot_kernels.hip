@@ -263,6 +263,7 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const double *__restrict__ x,
     __shared__ double win[S1_WIN][S1_PIECES];
     __shared__ int s_top[2];
     __shared__ int2 wr[BLOCK / 64];
+    __shared__ double2 qxy[BLOCK / 64][128];  // per-wave queue of in-window components
     const int tid = threadIdx.x, lane = tid & 63;
     for (int i = tid; i < W + 1; i += BLOCK) h[i] = 0;
     for (int i = tid; i < S1_WIN * S1_PIECES; i += BLOCK) (&win[0][0])[i] = 0.0;
@@ -321,20 +322,45 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const double *__restrict__ x,
             top = nt;
         }
         const int wlo = top - depth + 1;
+        // compact the wave's in-window components into its LDS queue and
+        // process them 64 at a time with every lane busy
+        double2 *qw = qxy[tid >> 6];
+        int qn = 0;  // wave-uniform
+        auto drain = [&](int cnt) {
+            __builtin_amdgcn_wave_barrier();
+            if (lane < cnt) {
+                const double2 v = qw[lane];
+                const Comp c = component(v.x, v.y, key_mode);
+                double pc[S1_PIECES];
+                s1_pieces(c, key_mode, pc);
+                double *w = win[c.slot & (S1_WIN - 1)];
+#pragma unroll
+                for (int q = 0; q < S1_PIECES; q++)
+                    if (pc[q] != 0.0) atomicAdd(&w[q], pc[q]);
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
 #pragma unroll
         for (int u = 0; u < U; u++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                if (live[u][e] >= wlo && live[u][e] >= 0) {
-                    const Comp c = component(xv[u][e], yv[u][e], key_mode);
-                    double pc[S1_PIECES];
-                    s1_pieces(c, key_mode, pc);
-                    double *w = win[live[u][e] & (S1_WIN - 1)];
-#pragma unroll
-                    for (int q = 0; q < S1_PIECES; q++)
-                        if (pc[q] != 0.0) atomicAdd(&w[q], pc[q]);
+                const bool in = live[u][e] >= wlo && live[u][e] >= 0;
+                const unsigned long long m = __ballot(in);
+                if (in) {
+                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                             (unsigned)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                    qw[pos] = make_double2(xv[u][e], yv[u][e]);
+                }
+                qn += __popcll(m);
+                if (qn >= 64) {
+                    drain(64);
+                    if (lane < qn - 64) qw[lane] = qw[64 + lane];
+                    __builtin_amdgcn_wave_barrier();
+                    qn -= 64;
                 }
             }
+        if (qn > 0) drain(qn);
     }
     __syncthreads();
 
@@ -540,7 +566,7 @@ template <bool VEC, int U>
 static int launch_s1_u(const Launch &L, const double *x, const double *y, int64_t n,
                        int key_mode, int depth)
 {
-    const int grid = grid_for(n, U, L.scan_blocks);
+    const int grid = grid_for(n, U, L.s1_blocks);
     hipLaunchKernelGGL((k_s1_scan<VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
                        key_mode, depth, L.ws, L.s1tab);
     return grid;
@@ -550,7 +576,7 @@ template <bool VEC>
 static int launch_s1(const Launch &L, const double *x, const double *y, int64_t n,
                      int key_mode, int depth)
 {
-    switch (L.scan_unroll) {
+    switch (L.s1_unroll) {
     case 1: return launch_s1_u<VEC, 1>(L, x, y, n, key_mode, depth);
     case 4: return launch_s1_u<VEC, 4>(L, x, y, n, key_mode, depth);
     default: return launch_s1_u<VEC, 2>(L, x, y, n, key_mode, depth);

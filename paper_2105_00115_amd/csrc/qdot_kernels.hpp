@@ -15,6 +15,8 @@ struct Launch {
     int scan_unroll;    // 1, 2 or 4 groups of 4 elements in flight per lane
     int acc_blocks;     // grid cap of the accumulate pass / FP64 dot
     int acc_unroll;
+    int s1_blocks;      // grid cap and unroll of the one-pass scan
+    int s1_unroll;
     double *s1tab;      // one-pass mode: HIST_COPIES x W x S1_PIECES sums (zero between calls)
     hipEvent_t *ev;     // NULL, or events recorded around each kernel
 };

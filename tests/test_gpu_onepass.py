@@ -157,8 +157,9 @@ def test_exact_so_independent_of_order_runs_and_launch_shape(h):
     pm = workloads.rng(16).permutation(len(x))
     assert h.qdot(dev(x[pm]), dev(y[pm]), 1e-6, opt=S1)["value"] == r0["value"]
     try:
-        for cfg in ((1, 1, 1, 1), (4, 4, 4, 4), (16, 2, 16, 2)):
-            h.set_tune(-1, *cfg)
+        for ob, ou in ((1, 1), (4, 4), (16, 2), (8, 1)):
+            h.set_tune(-1, 2, 1, 2, 2, ob, ou)
+            cfg = (ob, ou)
             r = h.qdot(xd, yd, 1e-6, opt=S1)
             assert r["value"] == r0["value"] and r["count"] == r0["count"], cfg
     finally:

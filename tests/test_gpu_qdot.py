@@ -192,10 +192,13 @@ def test_repeat_and_tuning_invariance(h):
 
 def test_tune_file_loading(h, tmp_path):
     good = tmp_path / "good.txt"
-    good.write_text("# comment\n0 1 1 2 2\n3 8 4 16 1  # trailing comment\n\n")
+    good.write_text("# comment\n0 1 1 2 2\n3 8 4 16 1  # trailing comment\n2 1 2 4 4 8 2\n\n")
     h.reset_tune()
+    d0 = h.get_tune(0)
     h.load_tune(str(good))
-    assert h.get_tune(0) == (1, 1, 2, 2) and h.get_tune(3) == (8, 4, 16, 1)
+    # a 5-column line leaves the one-pass shape as it was
+    assert h.get_tune(0) == (1, 1, 2, 2) + d0[4:] and h.get_tune(3)[:4] == (8, 4, 16, 1)
+    assert h.get_tune(2) == (1, 2, 4, 4, 8, 2)
     bad = tmp_path / "bad.txt"
     bad.write_text("1 2 3 4 5\n")  # unroll 3 is not allowed
     with pytest.raises(q.QdotError):
