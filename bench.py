@@ -367,6 +367,7 @@ def main():
                               "k_s1_fin": round(t1p["fin_ms"] / t1p["qdot_calls"], 4)},
                 "scan_frac_hbm": round(alg_bytes / (t1p["scan_ms"] / t1p["qdot_calls"] * 1e-3)
                                        / 1e9 / HBM_PEAK_GBS, 4),
+                "scan_traffic": measured_traffic(n, "k_s1_scan"),
                 "vs_fp64_dot": round(d64_ms / (wall1 / K * 1e3), 4),
                 "counts_equal_two_pass": res1["count"] == res["count"],
                 "value": res1["value"],
