@@ -253,7 +253,30 @@ def main():
     torch.cuda.synchronize()
     batch_ms = e0.elapsed_time(e1) / 10
     bres = q.parse_results(bout)
+    # the same launch in the one-pass mode (each instance read once)
+    s1 = [0, 0, 0, 1]
+    bout1 = torch.zeros_like(bout)
+    h.batch_plan(offs, [], opt=s1)
+    graph1 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(bs):
+        with torch.cuda.graph(graph1, stream=bs):
+            h.batched_async(bx, by, off_d, offs, tol_d, bout1, opt=s1)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        graph1.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        graph1.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    batch1_ms = e0.elapsed_time(e1) / 10
+    bres1 = q.parse_results(bout1)
+    del graph1
     batched = {"instances": 4096, "components": total, "ms_per_launch": round(batch_ms, 4),
+               "one_pass_ms_per_launch": round(batch1_ms, 4),
+               "one_pass_gelem_s": round(total / (batch1_ms * 1e-3) / 1e9, 3),
+               "one_pass_counts_equal": all(a["count"] == c["count"] for a, c in zip(bres, bres1)),
                "gelem_s": round(total / (batch_ms * 1e-3) / 1e9, 3),
                "hbm_frac_2pass": round(32.0 * total / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "statuses_ok": sum(1 for r in bres if r["status"] == 0)}

@@ -91,12 +91,13 @@ typedef struct qdot_options {
      *    exactly and rounded once.  While scanning the exponents, every
      *    block keeps per-bin candidate sums of all three precisions for the
      *    bins near its running maximum key and each kept bin takes its
-     *    class's sum after the cutoff.  Accepted by qdot_async, qdot and
-     *    qdot_power when n <= 2^30 and the tolerance keeps every possibly
-     *    kept bin within 255 exponents of e_max (ceil(log2 n) - t_min + 1
-     *    <= 255, t_min the smallest t any histogram of n components can
-     *    give: tol >= about 1e-60 at n = 2^27); QDOT_E_INVAL otherwise and
-     *    in the classes, batched and CG entry points. */
+     *    class's sum after the cutoff.  Accepted by qdot_async, qdot,
+     *    qdot_power and (for the qdot instances) the batched entry points
+     *    when n <= 2^30 and the tolerance keeps every possibly kept bin
+     *    within 255 exponents of e_max (ceil(log2 n) - t_min + 1 <= 255,
+     *    t_min the smallest t any histogram of n components can give: tol
+     *    >= about 1e-60 at n = 2^27); QDOT_E_INVAL otherwise and in
+     *    qdot_classes_async and qdot_cg. */
     int32_t accum_mode;
 } qdot_options;
 
@@ -270,7 +271,10 @@ QDOT_API int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets,
                                    int32_t B);
 
 /* Batched launch of qdot instances and CG systems together: the B ragged
- * instances (arguments as qdot_batched_async; B may be 0) and S CG systems
+ * instances (arguments as qdot_batched_async; B may be 0; with accum_mode 1
+ * each instance is read once, and an instance whose tolerance does not
+ * admit the one-pass mode gets status QDOT_E_INVAL) and S CG systems (their
+ * inner products always use accum_mode 0)
  * (systems: host array of S descriptors; S may be 0) run in one persistent
  * kernel launch.  Each CG system follows qdot_cg on that system alone (Alg.
  * 4 with the same stopping rule and the same inner products); it is solved
@@ -290,9 +294,11 @@ QDOT_API int32_t qdot_batch_run_async(qdot_handle *h, const double *x_cat,
                                       qdot_result *dev_out, qdot_cg_result *dev_cg_out);
 
 /* Plan a layout of qdot_batch_run_async ahead of time (e.g. before graph
- * capture).  Synchronous. */
+ * capture); opt (NULL = defaults) must carry the accum_mode of the later
+ * calls, whose plans differ.  Synchronous. */
 QDOT_API int32_t qdot_batch_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
-                                 const qdot_cg_system *systems, int32_t S);
+                                 const qdot_cg_system *systems, int32_t S,
+                                 const qdot_options *opt);
 
 /* S CG systems in one persistent launch (qdot_batch_run_async with no qdot
  * instances); host_out: host qdot_cg_result[S].  Synchronous. */

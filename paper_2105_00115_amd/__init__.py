@@ -114,7 +114,8 @@ SIGNATURES = [
     ("qdot_batched_plan", _i32, [_vp, C.POINTER(_i64), _i32]),
     ("qdot_batch_run_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32,
                                     C.POINTER(QdotCgSystem), _i32, _OPT, _vp, _vp, _vp]),
-    ("qdot_batch_plan", _i32, [_vp, C.POINTER(_i64), _i32, C.POINTER(QdotCgSystem), _i32]),
+    ("qdot_batch_plan", _i32, [_vp, C.POINTER(_i64), _i32, C.POINTER(QdotCgSystem), _i32,
+                               _OPT]),
     ("qdot_cg_batched", _i32, [_vp, C.POINTER(QdotCgSystem), _i32, _OPT, _vp,
                                C.POINTER(QdotCgResult)]),
     ("qdot_spmv_async", _i32, [_vp, _CSR, _vp, _vp, _vp]),
@@ -398,10 +399,10 @@ class Qdot:
                                   int(maxit), int(use))
         return arr
 
-    def batch_plan(self, host_offsets, systems):
+    def batch_plan(self, host_offsets, systems, opt=None):
         ho, hp = self._host_offsets(host_offsets if host_offsets is not None else [0])
         arr = self.cg_systems(systems)
-        st = lib().qdot_batch_plan(self._h, hp, ho.shape[0] - 1, arr, len(systems))
+        st = lib().qdot_batch_plan(self._h, hp, ho.shape[0] - 1, arr, len(systems), _opts(opt))
         if st != OK:
             self._raise(st, "qdot_batch_plan")
 

@@ -73,7 +73,8 @@ struct BState {
 struct BatchPlan {
     std::vector<int64_t> offsets;
     std::vector<qdot_cg_system> systems;
-    int B = 0, S = 0, n_items = 0, n_large = 0, n_p2 = 0, max_gang = 0;
+    int B = 0, S = 0, accum = 0, n_items = 0, n_large = 0, n_p2 = 0, max_gang = 0;
+    double *ltab = nullptr;           // one-pass mode: per large instance W x S1_PIECES sums
     CgSys *sys = nullptr;             // S device descriptors
     Gang *gangs = nullptr;            // S gang states
     double *cgvec = nullptr;          // r, p, q of every system
@@ -102,6 +103,7 @@ void free_plan(BatchPlan *p)
     (void)hipFree(p->gangs);
     (void)hipFree(p->cgvec);
     (void)hipFree(p->cgres);
+    (void)hipFree(p->ltab);
     delete p;
 }
 
@@ -142,6 +144,125 @@ __device__ __forceinline__ void accumulate_range(const double *xi, const double 
         stream_strided<false, SU>(xi, yi, first, stride, n, body);
 }
 
+// One-pass mode: window depth of an instance, or -1 when its kept bins
+// could lie beyond the window (or n is past the exact-sum bound).  An
+// invalid tolerance gets depth 1: the cutoff then reports it.
+__device__ __forceinline__ int s1_window_depth(int64_t n, double tol, int score_mode)
+{
+    if (!(tol > 0.0) || __builtin_isinf(tol)) return 1;
+    const int d = s1_depth_dev(n, tol, score_mode);
+    return (n > S1_MAX_N || d > S1_WIN) ? -1 : d;
+}
+
+__device__ __forceinline__ void write_invalid(qdot_result *o)
+{
+    o->value = __longlong_as_double(0x7ff8000000000000ll);
+    for (int q = 0; q < 4; q++) o->count[q] = 0;
+    o->n_zero = 0;
+    o->e_min = o->e_max = o->n_bins = o->t = 0;
+    for (int q = 0; q < 3; q++) o->part[q] = 0.0;
+    o->bound_rel = o->bound_abs = 0.0;
+    o->flags = 0;
+    o->status = QDOT_E_INVAL;
+}
+
+// One-pass chunk of a large instance: scan with the block's candidate-sum
+// window, merge the histogram and add the window into the instance's bin
+// table (device-scope atomics; the sums are exact in any order), then count
+// the chunk.  The last chunk selects the cutoff, picks each kept bin's class
+// sum from the table, writes the whole result, and clears the table and the
+// instance's counters for the next launch.
+template <class Red>
+__device__ __forceinline__ void p1_onepass(const double *xi, const double *yi, int64_t n,
+                                           double tol, bool vec, const BItem &I, BLarge *L,
+                                           unsigned int *gh, double *tb, qdot_result *o,
+                                           unsigned int *h, unsigned char *lut, Red &red,
+                                           int4 *scratch, qdot_result &s_res, S1Lds &S1,
+                                           int &s_flag, int key_mode, int score_mode,
+                                           int nonstrict)
+{
+    const int tid = threadIdx.x;
+    const int depth = s1_window_depth(n, tol, score_mode);
+    const int dw = depth < 0 ? 0 : depth;  // no window when the mode is refused
+    unsigned int nz = 0, bad = 0;
+    int top = -1;
+    s1_begin(S1);
+    __syncthreads();
+    if (vec)
+        s1_stream<true, SU>(xi, yi, I.first, I.stride, n, key_mode, dw, h, S1, top, nz, bad);
+    else
+        s1_stream<false, SU>(xi, yi, I.first, I.stride, n, key_mode, dw, h, S1, top, nz, bad);
+    __syncthreads();
+    int lo = W, hi = -1;
+    for (int j = tid; j < W; j += BLOCK) {
+        const unsigned int v = h[j];
+        if (v) {
+            __hip_atomic_fetch_add(&gh[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            h[j] = 0u;
+            lo = min(lo, j);
+            hi = max(hi, j);
+        }
+    }
+    if (tid == 0) h[W] = 0u;
+    if (top >= 0)
+        for (int i = tid; i < dw * S1_PIECES; i += BLOCK) {
+            const int bin = top - i / S1_PIECES;
+            if (bin < 0) continue;
+            const double v = S1.win[bin & (S1_WIN - 1)][i % S1_PIECES];
+            if (v != 0.0)
+                __hip_atomic_fetch_add(&tb[(size_t)bin * S1_PIECES + i % S1_PIECES], v,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    block_reduce_range(lo, hi, nz, bad, scratch);
+    if (tid == 0) {
+        if (hi >= 0) {
+            __hip_atomic_fetch_min(&L->lo, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(&L->hi, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (nz)
+            __hip_atomic_fetch_add(&L->n_zero, (unsigned long long)nz, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (bad) __hip_atomic_fetch_or(&L->bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the chunk's merges and table adds complete before it counts itself
+    vmem_drain();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned int prev =
+            __hip_atomic_fetch_add(&L->p1_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_flag = (prev + 1 == L->nchunks);
+    }
+    __syncthreads();
+    if (!s_flag) return;
+    const int glo = ld_dev(&L->lo);
+    const int ghi = ld_dev(&L->hi);
+    const unsigned long long gnz = ld_dev(&L->n_zero);
+    const unsigned int gbad = ld_dev(&L->bad);
+    auto get = [&](int j) { return (unsigned long long)ld_dev(&gh[j]); };
+    auto put = [&](int j, int c) { lut[j] = (unsigned char)c; };
+    auto clear = [&](int j) { st_dev(&gh[j], 0u); };
+    const CutParams p = block_cutoff<BLOCK>(glo, ghi, gnz, gbad, n, tol, score_mode, nonstrict,
+                                            get, put, clear, &s_res, nullptr);
+    if (depth >= 0 && !p.skip)
+        s1_pick(p.e_max, max(glo, p.e_max - KMIN - depth + 1), p.flags, lut,
+                [&](int bin, int q) { return ld_dev(&tb[(size_t)bin * S1_PIECES + q]); }, red,
+                &s_res);
+    __syncthreads();
+    if (tid == 0) {
+        if (depth < 0) write_invalid(o);
+        else *o = s_res;
+        st_dev(&L->lo, (int)W);
+        st_dev(&L->hi, -1);
+        st_dev(&L->n_zero, 0ull);
+        st_dev(&L->bad, 0u);
+        st_dev(&L->p1_done, 0u);
+    }
+    if (ghi >= glo) {
+        const int64_t cnt = (int64_t)(ghi - glo + 1) * S1_PIECES;
+        for (int64_t i = tid; i < cnt; i += BLOCK) st_dev(&tb[(size_t)glo * S1_PIECES + i], 0.0);
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_batch_init(BLarge *large, int n_large,
                                                       unsigned char *lut)
 {
@@ -180,10 +301,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                                                  qdot_result *__restrict__ out,
                                                  const CgSys *__restrict__ sys,
                                                  Gang *__restrict__ gangs,
-                                                 qdot_cg_result *__restrict__ cg_out, int key_mode,
-                                                 int score_mode, int nonstrict)
+                                                 qdot_cg_result *__restrict__ cg_out,
+                                                 double *__restrict__ ltab, int key_mode,
+                                                 int score_mode, int nonstrict, int accum_mode)
 {
     __shared__ CgLds LD;
+    __shared__ S1Lds S1;
     unsigned int *h = LD.h;
     unsigned char *lut = LD.lut;
     auto &red = LD.red;
@@ -222,7 +345,23 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
             const bool vec = ((((uintptr_t)xi) | ((uintptr_t)yi)) & 15) == 0;
             const double tol = tols[inst];
             unsigned int nz = 0, bad = 0;
-            scan_into(xi, yi, 0, GROUP, n, vec, key_mode, h, nz, bad);
+            int top = -1, depth = 0;
+            if (accum_mode == 1) {
+                depth = s1_window_depth(n, tol, score_mode);
+                if (depth < 0) {  // kept bins could lie beyond the window
+                    if (tid == 0) write_invalid(out + inst);
+                    __syncthreads();
+                    continue;
+                }
+                s1_begin(S1);
+                __syncthreads();
+                if (vec)
+                    s1_stream<true, SU>(xi, yi, 0, GROUP, n, key_mode, depth, h, S1, top, nz, bad);
+                else
+                    s1_stream<false, SU>(xi, yi, 0, GROUP, n, key_mode, depth, h, S1, top, nz, bad);
+            } else {
+                scan_into(xi, yi, 0, GROUP, n, vec, key_mode, h, nz, bad);
+            }
             __syncthreads();
             int lo = W, hi = -1;
             for (int j = tid; j < W; j += BLOCK)
@@ -239,7 +378,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                                                     nullptr);
             if (tid == 0) h[W] = 0u;
             __syncthreads();
-            if (!p.skip) {
+            if (accum_mode == 1) {
+                // one pass: each kept bin's class sum straight from the window
+                if (!p.skip)
+                    s1_pick(p.e_max, max(lo, top - depth + 1), p.flags, lut,
+                            [&](int bin, int q) { return S1.win[bin & (S1_WIN - 1)][q]; }, red,
+                            out + inst);
+            } else if (!p.skip) {
                 Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
                 accumulate_range(xi, yi, 0, GROUP, n, vec, key_mode, lut, p.e_max, p.c32, a);
                 block_reduce3<BLOCK>(a, red);
@@ -255,7 +400,11 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
         const double *yi = y + off;
         const bool vec = ((((uintptr_t)xi) | ((uintptr_t)yi)) & 15) == 0;
         const double tol = tols[I.inst];
-        if (I.type == IT_P1) {
+        if (I.type == IT_P1 && accum_mode == 1) {
+            p1_onepass(xi, yi, n, tol, vec, I, large + I.large, ghist + (size_t)I.large * W,
+                       ltab + (size_t)I.large * W * S1_PIECES, out + I.inst, h, lut, red,
+                       scratch, s_res, S1, s_flag, key_mode, score_mode, nonstrict);
+        } else if (I.type == IT_P1) {
             BLarge *L = large + I.large;
             unsigned int *gh = ghist + (size_t)I.large * W;
             unsigned int nz = 0, bad = 0;
@@ -426,11 +575,12 @@ static int gang_size(int64_t n)
 }
 
 static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
-                          const qdot_cg_system *systems, int32_t S, BatchPlan **out)
+                          const qdot_cg_system *systems, int32_t S, int accum, BatchPlan **out)
 {
     BatchPlan *p = new BatchPlan();
     p->B = B;
     p->S = S;
+    p->accum = accum;
     if (B > 0) p->offsets.assign(host_offsets, host_offsets + B + 1);
     if (S > 0) p->systems.assign(systems, systems + S);
     std::vector<int> big, small;
@@ -480,7 +630,8 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
         items.push_back(BItem{IT_SMALL, (int)s0, (int)(s1 - s0), -1, 0, 0});
         s0 = s1;
     }
-    for (size_t L = 0; L < big.size(); L++) {
+    // the one-pass mode has no second pass
+    for (size_t L = 0; accum == 0 && L < big.size(); L++) {
         const int j = big[L];
         for (unsigned int c = 0; c < lg[L].nchunks; c++)
             items.push_back(BItem{IT_P2, j, (int)L, lg[L].first_slot + (int)c, (int64_t)c * GROUP,
@@ -503,7 +654,9 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
               hipMalloc((void **)&p->sys, sizeof(CgSys) * ns) == hipSuccess &&
               hipMalloc((void **)&p->gangs, sizeof(Gang) * ns) == hipSuccess &&
               hipMalloc((void **)&p->cgres, sizeof(qdot_cg_result) * ns) == hipSuccess &&
-              hipMalloc((void **)&p->cgvec, sizeof(double) * std::max<int64_t>(1, 3 * cg_rows)) == hipSuccess;
+              hipMalloc((void **)&p->cgvec, sizeof(double) * std::max<int64_t>(1, 3 * cg_rows)) == hipSuccess &&
+              (accum == 0 ||
+               hipMalloc((void **)&p->ltab, sizeof(double) * W * S1_PIECES * nl) == hipSuccess);
     if (!ok) {
         free_plan(p);
         return fail(h, QDOT_E_NOMEM, "batched plan allocation failed");
@@ -536,6 +689,7 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     if (e == hipSuccess) e = hipMemset(p->hist, 0, sizeof(unsigned int) * W * nl);
     if (e == hipSuccess) e = hipMemset(p->lut, 0, (size_t)W_LUT * nl);
     if (e == hipSuccess) e = hipMemset(p->state, 0, sizeof(BState));
+    if (e == hipSuccess && p->ltab) e = hipMemset(p->ltab, 0, sizeof(double) * W * S1_PIECES * nl);
     if (e == hipSuccess && !small_list.empty())
         e = hipMemcpy(p->small_list, small_list.data(), sizeof(int) * small_list.size(),
                       hipMemcpyHostToDevice);
@@ -560,12 +714,12 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
 }
 
 static int32_t find_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
-                         const qdot_cg_system *systems, int32_t S, BatchPlan **out)
+                         const qdot_cg_system *systems, int32_t S, int accum, BatchPlan **out)
 {
     static uint64_t clock = 0;
     for (void *vp : h->plans) {
         BatchPlan *p = (BatchPlan *)vp;
-        if (p->B != B || p->S != S) continue;
+        if (p->B != B || p->S != S || p->accum != accum) continue;
         if (B > 0 && !std::equal(p->offsets.begin(), p->offsets.end(), host_offsets)) continue;
         bool same = true;
         for (int s = 0; s < S && same; s++) same = same_system(p->systems[s], systems[s]);
@@ -575,7 +729,7 @@ static int32_t find_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
         return QDOT_OK;
     }
     BatchPlan *p = nullptr;
-    int32_t st = build_plan(h, host_offsets, B, systems, S, &p);
+    int32_t st = build_plan(h, host_offsets, B, systems, S, accum, &p);
     if (st != QDOT_OK) return st;
     p->last_use = ++clock;
     if ((int)h->plans.size() >= MAX_PLANS) {
@@ -646,10 +800,10 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
-    if (o.accum_mode != 0) return fail(h, QDOT_E_INVAL, "the batched and CG launches need accum_mode 0");
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
-    if ((st = find_plan(h, host_offsets, B, systems, S, &p)) != QDOT_OK) return st;
+    const int accum = B > 0 ? o.accum_mode : 0;  // CG systems always use the default reading
+    if ((st = find_plan(h, host_offsets, B, systems, S, accum, &p)) != QDOT_OK) return st;
     int bpc = h->batch_blocks_per_cu;
     if (const char *e = std::getenv("QDOT_BATCH_BLOCKS_PER_CU")) bpc = std::max(1, std::min(16, std::atoi(e)));
     const int grid = std::max(1, std::min(p->n_items, bpc * h->num_cus));
@@ -666,8 +820,8 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
     if (S > 0) hipLaunchKernelGGL(k_gang_rearm, dim3((unsigned)S), dim3(BLOCK), 0, s, p->gangs, S);
     hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets, tols,
                        p->items, p->n_items, p->large, p->hist, p->lut, p->partials, p->state,
-                       p->small_list, dev_out, p->sys, p->gangs, dev_cg_out, o.key_mode,
-                       o.score_mode, o.boundary_mode);
+                       p->small_list, dev_out, p->sys, p->gangs, dev_cg_out, p->ltab, o.key_mode,
+                       o.score_mode, o.boundary_mode, accum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batched launch");
     if (used) *used = p;
@@ -682,20 +836,24 @@ extern "C" {
 
 int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B)
 {
-    return qdot_batch_plan(h, host_offsets, B, nullptr, 0);
+    return qdot_batch_plan(h, host_offsets, B, nullptr, 0, nullptr);
 }
 
 int32_t qdot_batch_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
-                        const qdot_cg_system *systems, int32_t S)
+                        const qdot_cg_system *systems, int32_t S, const qdot_options *opt)
 {
     if (!h) return QDOT_E_INVAL;
     int32_t st = check_batch(h, host_offsets, B);
     if (st != QDOT_OK) return st;
     if ((st = check_systems(h, systems, S)) != QDOT_OK) return st;
+    qdot_options o;
+    std::memset(&o, 0, sizeof o);
+    if (opt) o = *opt;
+    if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
     if (B == 0 && S == 0) return QDOT_OK;
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
-    return find_plan(h, host_offsets, B, systems, S, &p);
+    return find_plan(h, host_offsets, B, systems, S, B > 0 ? o.accum_mode : 0, &p);
 }
 
 int32_t qdot_batched_async(qdot_handle *h, const double *x_cat, const double *y_cat,
@@ -725,11 +883,11 @@ int32_t qdot_cg_batched(qdot_handle *h, const qdot_cg_system *systems, int32_t S
     if (!h) return QDOT_E_INVAL;
     if (S > 0 && !host_out) return fail(h, QDOT_E_INVAL, "out is NULL");
     if (S <= 0) return S == 0 ? QDOT_OK : fail(h, QDOT_E_INVAL, "bad system count");
-    int32_t st = qdot_batch_plan(h, nullptr, 0, systems, S);
+    int32_t st = qdot_batch_plan(h, nullptr, 0, systems, S, opt);
     if (st != QDOT_OK) return st;
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
-    if ((st = find_plan(h, nullptr, 0, systems, S, &p)) != QDOT_OK) return st;
+    if ((st = find_plan(h, nullptr, 0, systems, S, 0, &p)) != QDOT_OK) return st;
     if ((st = batch_launch(h, nullptr, nullptr, nullptr, nullptr, nullptr, 0, systems, S, opt,
                            stream, nullptr, p->cgres, nullptr)) != QDOT_OK)
         return st;

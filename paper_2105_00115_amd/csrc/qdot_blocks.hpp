@@ -488,6 +488,181 @@ __device__ __forceinline__ void block_reduce3(Acc a[3], Acc (*red)[NT / 64])
         }
 }
 
+// Number of bins below e_max that can hold kept components, for any
+// histogram of n components at tolerance tol (tol finite and > 0): a bin k
+// is kept only if ceil(log2 M_k) + k - e_max - t + 1 >= 0, and t is at least
+// floor(log2 tol) - ceil(log2 min(n, W)) - 1 (adjusted score) or
+// floor(log2 tol) (raw score).  The one-pass mode needs it <= S1_WIN.
+__device__ __forceinline__ int s1_depth_dev(int64_t n, double tol, int score_mode)
+{
+    const int fl = ilogb(tol);
+    const long long nb = n < 1 ? 1 : (n < W ? n : W);
+    const int t_low = score_mode == 0 ? fl - ceil_log2_u64((unsigned long long)nb) - 1 : fl;
+    return ceil_log2_u64((unsigned long long)(n < 1 ? 1 : n)) - t_low + 2;
+}
+
+// LDS of one block's one-pass window: candidate sums of the bins within
+// `depth` of the running maximum key (slot = bin mod S1_WIN), the two
+// alternating words on which each group's new maximum is agreed, and one
+// queue per wave of in-window components.
+struct S1Lds {
+    double win[S1_WIN][S1_PIECES];
+    int top2[2];
+    double2 q[BLOCK / 64][128];
+};
+
+// Start a window (every thread; the caller synchronises before use).
+__device__ __forceinline__ void s1_begin(S1Lds &S)
+{
+    for (int i = threadIdx.x; i < S1_WIN * S1_PIECES; i += BLOCK) (&S.win[0][0])[i] = 0.0;
+    if (threadIdx.x < 2) S.top2[threadIdx.x] = -1;
+}
+
+// One block streams the groups first, first + stride, ... (GROUP = U * CHUNK
+// components each) below n: keys into the LDS histogram h (W + 1 slots),
+// zero / non-finite counts, and the candidate sums of every component whose
+// bin lies within `depth` of the block's running maximum live slot `top`
+// (-1 on entry for a fresh window).  `top` is agreed at a barrier per group;
+// when it rises the slots of the entering bins are cleared first.  The
+// in-window components are compacted per wave and processed 64 at a time.
+// Every thread of the block must call it with the same arguments.
+template <bool VEC, int U>
+__device__ __forceinline__ void s1_stream(const double *__restrict__ x,
+                                          const double *__restrict__ y, int64_t first,
+                                          int64_t stride, int64_t n, int key_mode, int depth,
+                                          unsigned int *h, S1Lds &S, int &top, unsigned int &nz,
+                                          unsigned int &bad)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t group = (int64_t)CHUNK * U;
+    int par = 0;
+    for (int64_t base = first; base < n; base += stride, par ^= 1) {
+        double xv[U][4], yv[U][4];
+        int lim[U];
+        const bool full = base + group <= n;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + tid * EPT;
+            if (full) {
+                lim[u] = 4;
+                load4_full<VEC>(x + i0, xv[u]);
+                load4_full<VEC>(y + i0, yv[u]);
+            } else {
+                const int64_t left = n - i0;
+                lim[u] = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
+                load4_tail(x + i0, lim[u], xv[u]);
+                load4_tail(y + i0, lim[u], yv[u]);
+            }
+        }
+        int live[U][4];
+        int wmax = -1;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const Comp c = component(xv[u][e], yv[u][e], key_mode);
+                const bool valid = e < lim[u];
+                nz += (valid & c.zero) ? 1u : 0u;
+                bad |= (valid & c.bad) ? 1u : 0u;
+                if (valid) atomicAdd(&h[c.slot], 1u);
+                live[u][e] = (valid && c.slot != ZERO_SLOT) ? c.slot : -1;
+                wmax = max(wmax, live[u][e]);
+            }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
+        if (lane == 0 && wmax > top) atomicMax(&S.top2[par], wmax);
+        __syncthreads();
+        const int nt = S.top2[par];
+        if (nt > top) {
+            // bins top+1 .. nt enter; their slots held bins now below the window
+            const int nclr = min(nt - top, S1_WIN);
+            for (int i = tid; i < nclr * S1_PIECES; i += BLOCK)
+                S.win[(nt - i / S1_PIECES) & (S1_WIN - 1)][i % S1_PIECES] = 0.0;
+            __syncthreads();
+            top = nt;
+        }
+        const int wlo = top - depth + 1;
+        double2 *qw = S.q[tid >> 6];
+        int qn = 0;  // wave-uniform
+        auto drain = [&](int cnt) {
+            __builtin_amdgcn_wave_barrier();
+            if (lane < cnt) {
+                const double2 v = qw[lane];
+                const Comp c = component(v.x, v.y, key_mode);
+                double pc[S1_PIECES];
+                s1_pieces(c, key_mode, pc);
+                double *w = S.win[c.slot & (S1_WIN - 1)];
+#pragma unroll
+                for (int q = 0; q < S1_PIECES; q++)
+                    if (pc[q] != 0.0) atomicAdd(&w[q], pc[q]);
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const bool in = live[u][e] >= wlo && live[u][e] >= 0;
+                const unsigned long long m = __ballot(in);
+                if (in) {
+                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                             (unsigned)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                    qw[pos] = make_double2(xv[u][e], yv[u][e]);
+                }
+                qn += __popcll(m);
+                if (qn >= 64) {
+                    drain(64);
+                    if (lane < qn - 64) qw[lane] = qw[64 + lane];
+                    __builtin_amdgcn_wave_barrier();
+                    qn -= 64;
+                }
+            }
+        if (qn > 0) drain(qn);
+    }
+}
+
+// One-pass pick: each kept bin k in [e_max - S1_WIN + 1, e_max] (and >= lo)
+// contributes the candidate sum of its class (get(bin, piece), an exact
+// FP64 number), scaled by 2^(k - e_max); the block sums them with
+// compensation and thread 0 writes value, parts and flags.  lut holds the
+// class of every slot.  Every thread must call it.
+template <class Get>
+__device__ __forceinline__ void s1_pick(int e_max, int lo, int flags, const unsigned char *lut,
+                                        Get get, Acc (*red)[BLOCK / 64], qdot_result *out)
+{
+    const int top = e_max - KMIN;
+    Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};  // double, single, half
+    for (int j = threadIdx.x; j < S1_WIN; j += BLOCK) {
+        const int bin = top - j;
+        if (bin < lo) continue;
+        const int cls = lut[bin];
+        if (cls == QDOT_DOUBLE) {
+            acc_add(a[0], ldexp(get(bin, 3), -j));
+            acc_add(a[0], ldexp(get(bin, 4), -j));
+            acc_add(a[0], ldexp(get(bin, 5), -j));
+        } else if (cls == QDOT_SINGLE) {
+            acc_add(a[1], ldexp(get(bin, 1), -j));
+            acc_add(a[1], ldexp(get(bin, 2), -j));
+        } else if (cls == QDOT_HALF) {
+            acc_add(a[2], ldexp(get(bin, 0), -j));
+        }
+    }
+    block_reduce3<BLOCK>(a, red);
+    if (threadIdx.x == 0) {
+        Acc tot = a[0];
+        acc_add(tot, a[1].s);
+        acc_add(tot, a[2].s);
+        tot.c = tot.c + (a[1].c + a[2].c);
+        const double value = ldexp(tot.s + tot.c, e_max);
+        out->value = value;
+        out->part[QDOT_DOUBLE] = ldexp(a[0].s + a[0].c, e_max);
+        out->part[QDOT_SINGLE] = ldexp(a[1].s + a[1].c, e_max);
+        out->part[QDOT_HALF] = ldexp(a[2].s + a[2].c, e_max);
+        out->flags = flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
+    }
+}
+
 // value = 2^e_max (D + 2^(c32 - e_max) (S + H)), parts, overflow flag.
 __device__ __forceinline__ void combine_value(const Acc f[3], int e_max, int t, int c32,
                                               int flags, qdot_result *out)

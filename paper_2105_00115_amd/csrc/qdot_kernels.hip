@@ -260,108 +260,18 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const double *__restrict__ x,
                                                    double *__restrict__ tab)
 {
     __shared__ unsigned int h[W + 1];
-    __shared__ double win[S1_WIN][S1_PIECES];
-    __shared__ int s_top[2];
+    __shared__ S1Lds S;
     __shared__ int2 wr[BLOCK / 64];
-    __shared__ double2 qxy[BLOCK / 64][128];  // per-wave queue of in-window components
     const int tid = threadIdx.x, lane = tid & 63;
     for (int i = tid; i < W + 1; i += BLOCK) h[i] = 0;
-    for (int i = tid; i < S1_WIN * S1_PIECES; i += BLOCK) (&win[0][0])[i] = 0.0;
-    if (tid < 2) s_top[tid] = -1;
+    s1_begin(S);
     __syncthreads();
 
     int top = -1;  // highest live slot seen so far by the block (-1: none)
     unsigned int nz = 0, bad = 0;
     const int64_t group = (int64_t)CHUNK * U;
-    const int64_t step = (int64_t)gridDim.x * group;
-    int par = 0;
-    for (int64_t base = (int64_t)blockIdx.x * group; base < n; base += step, par ^= 1) {
-        double xv[U][4], yv[U][4];
-        int lim[U];
-        const bool full = base + group <= n;
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + tid * EPT;
-            if (full) {
-                lim[u] = 4;
-                load4_full<VEC>(x + i0, xv[u]);
-                load4_full<VEC>(y + i0, yv[u]);
-            } else {
-                const int64_t left = n - i0;
-                lim[u] = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
-                load4_tail(x + i0, lim[u], xv[u]);
-                load4_tail(y + i0, lim[u], yv[u]);
-            }
-        }
-        int live[U][4];
-        int wmax = -1;
-#pragma unroll
-        for (int u = 0; u < U; u++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const Comp c = component(xv[u][e], yv[u][e], key_mode);
-                const bool valid = e < lim[u];
-                nz += (valid & c.zero) ? 1u : 0u;
-                bad |= (valid & c.bad) ? 1u : 0u;
-                if (valid) atomicAdd(&h[c.slot], 1u);
-                live[u][e] = (valid && c.slot != ZERO_SLOT) ? c.slot : -1;
-                wmax = max(wmax, live[u][e]);
-            }
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
-        if (lane == 0 && wmax > top) atomicMax(&s_top[par], wmax);
-        __syncthreads();
-        const int nt = s_top[par];
-        if (nt > top) {
-            // bins top+1 .. nt enter; their slots held bins that now lie
-            // below the window
-            const int nclr = min(nt - top, S1_WIN);
-            for (int i = tid; i < nclr * S1_PIECES; i += BLOCK)
-                win[(nt - i / S1_PIECES) & (S1_WIN - 1)][i % S1_PIECES] = 0.0;
-            __syncthreads();
-            top = nt;
-        }
-        const int wlo = top - depth + 1;
-        // compact the wave's in-window components into its LDS queue and
-        // process them 64 at a time with every lane busy
-        double2 *qw = qxy[tid >> 6];
-        int qn = 0;  // wave-uniform
-        auto drain = [&](int cnt) {
-            __builtin_amdgcn_wave_barrier();
-            if (lane < cnt) {
-                const double2 v = qw[lane];
-                const Comp c = component(v.x, v.y, key_mode);
-                double pc[S1_PIECES];
-                s1_pieces(c, key_mode, pc);
-                double *w = win[c.slot & (S1_WIN - 1)];
-#pragma unroll
-                for (int q = 0; q < S1_PIECES; q++)
-                    if (pc[q] != 0.0) atomicAdd(&w[q], pc[q]);
-            }
-            __builtin_amdgcn_wave_barrier();
-        };
-#pragma unroll
-        for (int u = 0; u < U; u++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const bool in = live[u][e] >= wlo && live[u][e] >= 0;
-                const unsigned long long m = __ballot(in);
-                if (in) {
-                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                             (unsigned)(m >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                    qw[pos] = make_double2(xv[u][e], yv[u][e]);
-                }
-                qn += __popcll(m);
-                if (qn >= 64) {
-                    drain(64);
-                    if (lane < qn - 64) qw[lane] = qw[64 + lane];
-                    __builtin_amdgcn_wave_barrier();
-                    qn -= 64;
-                }
-            }
-        if (qn > 0) drain(qn);
-    }
+    s1_stream<VEC, U>(x, y, (int64_t)blockIdx.x * group, (int64_t)gridDim.x * group, n, key_mode,
+                      depth, h, S, top, nz, bad);
     __syncthreads();
 
     // histogram merge and live range, as in k_scan
@@ -393,7 +303,7 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const double *__restrict__ x,
         for (int i = tid; i < depth * S1_PIECES; i += BLOCK) {
             const int bin = top - i / S1_PIECES;
             if (bin < 0) continue;
-            const double v = win[bin & (S1_WIN - 1)][i % S1_PIECES];
+            const double v = S.win[bin & (S1_WIN - 1)][i % S1_PIECES];
             if (v != 0.0) atomicAdd(&tb[(size_t)bin * S1_PIECES + i % S1_PIECES], v);
         }
     }
@@ -406,10 +316,10 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const double *__restrict__ x,
 }
 
 // One-pass mode, final step (one block): every kept bin contributes the
-// candidate sum of its class, scaled by 2^(k - e_max); the sums of the
-// table copies and pieces are exact, their scaled total is summed with
-// compensation and rounded once.  The block then clears the table over the
-// live range for the next call.
+// candidate sum of its class, summed over the table copies (exact), scaled
+// by 2^(k - e_max); the scaled total is summed with compensation and
+// rounded once.  The block then clears the tables over the live range for
+// the next call.
 __global__ __launch_bounds__(BLOCK) void k_s1_fin(const Ws *__restrict__ ws,
                                                   double *__restrict__ tab,
                                                   qdot_result *__restrict__ out)
@@ -418,44 +328,12 @@ __global__ __launch_bounds__(BLOCK) void k_s1_fin(const Ws *__restrict__ ws,
     const int tid = threadIdx.x;
     const int lo = ws->s1_lo, hi = ws->s1_hi;
     if (!ws->skip) {
-        const int e_max = ws->e_max;
-        const int top = e_max - KMIN;
-        Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};  // double, single, half
-        for (int j = tid; j < S1_WIN; j += BLOCK) {
-            const int bin = top - j;
-            if (bin < lo) continue;
-            const int cls = ws->lut[bin];
-            if (cls == QDOT_PERF) continue;
-            double v[S1_PIECES] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int c = 0; c < HIST_COPIES; c++) {
-                const double *tb = tab + ((size_t)c * W + bin) * S1_PIECES;
-#pragma unroll
-                for (int q = 0; q < S1_PIECES; q++) v[q] += tb[q];
-            }
-            if (cls == QDOT_DOUBLE) {
-                acc_add(a[0], ldexp(v[3], -j));
-                acc_add(a[0], ldexp(v[4], -j));
-                acc_add(a[0], ldexp(v[5], -j));
-            } else if (cls == QDOT_SINGLE) {
-                acc_add(a[1], ldexp(v[1], -j));
-                acc_add(a[1], ldexp(v[2], -j));
-            } else {
-                acc_add(a[2], ldexp(v[0], -j));
-            }
-        }
-        block_reduce3<BLOCK>(a, red);
-        if (tid == 0) {
-            Acc tot = a[0];
-            acc_add(tot, a[1].s);
-            acc_add(tot, a[2].s);
-            tot.c = tot.c + (a[1].c + a[2].c);
-            const double value = ldexp(tot.s + tot.c, e_max);
-            out->value = value;
-            out->part[QDOT_DOUBLE] = ldexp(a[0].s + a[0].c, e_max);
-            out->part[QDOT_SINGLE] = ldexp(a[1].s + a[1].c, e_max);
-            out->part[QDOT_HALF] = ldexp(a[2].s + a[2].c, e_max);
-            out->flags = ws->flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
-        }
+        auto get = [&](int bin, int q) {
+            double v = 0.0;
+            for (int c = 0; c < HIST_COPIES; c++) v += tab[((size_t)c * W + bin) * S1_PIECES + q];
+            return v;
+        };
+        s1_pick(ws->e_max, lo, ws->flags, ws->lut, get, red, out);
     }
     if (hi >= lo) {
         const int64_t cnt = (int64_t)(hi - lo + 1) * S1_PIECES;

@@ -182,9 +182,87 @@ def test_inadmissible_requests_are_rejected(h):
         h.qdot(xd, yd, 1e-80, opt=S1)  # kept bins could lie beyond the window
     with pytest.raises(q.QdotError):
         h.qdot_classes(xd, yd, 1e-6, opt=S1)
+    # in a batch, only the instance whose tolerance is refused fails
     offs = np.array([0, 500, 1000], dtype=np.int64)
-    with pytest.raises(q.QdotError):
-        h.batched(xd, yd, offs, [1e-6, 1e-6], opt=S1)
+    res = h.batched(xd, yd, offs, [1e-6, 1e-80], opt=S1)
+    assert res[0]["status"] == q.OK and res[1]["status"] == q.E_INVAL
+    assert np.isnan(res[1]["value"])
+
+
+def _ragged(seed, extra, count, hi=3e5):
+    g = workloads.rng(seed)
+    sizes = list(extra) + list(np.rint(10 ** g.uniform(0, np.log10(hi), count)).astype(int))
+    offsets = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    x, y = workloads.log_uniform_pair(int(offsets[-1]), seed + 1)
+    tols = np.array([1e-4, 1e-6, 1e-8, 1e-3, 1e-12])[g.integers(0, 5, len(sizes))]
+    return offsets, x, y, tols
+
+
+def _check_batched_s1(res, offsets, x, y, tols, opt=S1):
+    for j in range(len(tols)):
+        a, b = offsets[j], offsets[j + 1]
+        o = oracle.qdot(x[a:b], y[a:b], tols[j], opt=opt)
+        for k in INT_KEYS:
+            assert res[j][k] == o[k], (j, b - a, k, res[j][k], o[k])
+        if o["status"] == oracle.OK:
+            scale = oracle.abs_dot(x[a:b], y[a:b])
+            assert abs(res[j]["value"] - o["value"]) <= VALUE_TOL * scale, (j, b - a)
+            for c in range(3):
+                assert abs(res[j]["part"][c] - o["part"][c]) <= VALUE_TOL * scale, (j, c)
+
+
+def test_batched_one_pass_matches_oracle(h):
+    # instances above 131072 components go through one-pass chunks that
+    # merge into a per-instance bin table; the rest are done by one block
+    edge = (0, 1, 65, 1025, 65536, 131072, 131073, 300001, 700000)
+    offsets, x, y, tols = _ragged(21, edge, 80)
+    res = h.batched(dev(x), dev(y), offsets, tols, opt=S1)
+    _check_batched_s1(res, offsets, x, y, tols)
+    # repeat: the bin tables and counters were left clean, the sums are exact
+    res2 = h.batched(dev(x), dev(y), offsets, tols, opt=S1)
+    assert res2 == res
+
+
+@pytest.mark.parametrize("opt", [[1, 0, 0, 1], [0, 1, 1, 1]])
+def test_batched_one_pass_options(h, opt):
+    offsets, x, y, tols = _ragged(22, (200000, 5000), 20)
+    res = h.batched(dev(x), dev(y), offsets, tols, opt=opt)
+    _check_batched_s1(res, offsets, x, y, tols, opt=opt)
+
+
+def test_batched_one_pass_nonfinite_and_graph_replay(h):
+    offsets, x, y, tols = _ragged(23, (250000, 3000), 15)
+    xb = x.copy()
+    xb[offsets[0] + 11] = np.inf
+    xb[offsets[1] + 7] = np.nan
+    res = h.batched(dev(xb), dev(y), offsets, tols, opt=S1)
+    assert res[0]["status"] == q.E_NONFINITE and res[1]["status"] == q.E_NONFINITE
+    # the state is clean for the next call, which is captured and replayed
+    xd, yd = dev(x), dev(y)
+    off_d = torch.from_numpy(offsets).to("cuda:0")
+    tol_d = dev(tols)
+    n_inst = len(tols)
+    eager = torch.zeros(n_inst * q.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    h.batched_async(xd, yd, off_d, offsets, tol_d, eager, opt=S1)
+    torch.cuda.synchronize()
+    _check_batched_s1(q.parse_results(eager), offsets, x, y, tols)
+    out = torch.zeros_like(eager)
+    h.batch_plan(offsets, [], opt=S1)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            h.batched_async(xd, yd, off_d, offsets, tol_d, out, opt=S1)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        h.qdot(xd[:1000], yd[:1000], 1e-6, opt=S1)
+        torch.cuda.synchronize()
 
 
 @pytest.mark.timeout(600)
