@@ -62,21 +62,49 @@ def measured_traffic(n, kernel):
     return round(k["hbm_bytes_per_launch"]) if k else None
 
 
-def cpu_baseline(x_host, y_host, tol, budget_s=12.0):
-    """The oracle as it stands (single-threaded C), on a bounded sample."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x_host, y_host, tol, gpu_results, budget_s=12.0):
+    """The oracle as it stands (single-threaded C), timed on a bounded sample,
+    and the GPU's results on the same sample checked against it and against
+    the correctly rounded dot (gpu_results: {mode: qdot result dict})."""
     import oracle
 
     n = len(x_host)
     reps, t = 0, 0.0
+    o = None
     while t < budget_s and reps < 20:
         t0 = time.perf_counter()
-        oracle.qdot(x_host, y_host, tol)
+        o = oracle.qdot(x_host, y_host, tol)
         t += time.perf_counter() - t0
         reps += 1
+    exact = oracle.dot_exact(x_host, y_host)
+    scale = oracle.abs_dot(x_host, y_host)
+    o1 = oracle.qdot(x_host, y_host, tol, opt=[0, 0, 0, 1])
+    check = {}
+    for mode, r in gpu_results.items():
+        ref = o if mode == "two_pass" else o1
+        check[mode] = {
+            "counts_equal_oracle": r["count"] == ref["count"],
+            "value_diff_over_sum_abs": abs(r["value"] - ref["value"]) / scale,
+            "relerr_vs_exact_dot": abs(r["value"] - exact) / abs(exact) if exact else None,
+            "bound_rel": r["bound_rel"],
+        }
     return {"value": round(n * reps / t / 1e9, 6), "unit": "Gelem/s", "cores": 1,
             "kind": "oracle",
             "sample": f"first {n} components of the same x, y, qdot at tol={tol}, "
-                      f"{reps} repetitions, {t:.1f} s total, single-threaded"}
+                      f"{reps} repetitions, {t:.1f} s total, single-threaded",
+            "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+            "gpu_check_on_sample": check}
 
 
 def main():
@@ -178,8 +206,37 @@ def main():
     res1 = q.parse_results(out1)[0]
     wall1 = c1 - c0
 
+    # one call captured in a HIP graph, replays timed one by one: median
+    def replay_median(opt, reps=25):
+        gq = torch.cuda.CUDAGraph()
+        gs_ = torch.cuda.Stream()
+        gs_.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(gs_):
+            with torch.cuda.graph(gq, stream=gs_):
+                h.qdot_async(x, y, tol, out, opt=opt)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            gq.replay()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0.record()
+            gq.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    rep2 = replay_median(None)
+    rep1 = replay_median(s1)
+
     xh = x[: args.cpu_sample].cpu().numpy()
     yh = y[: args.cpu_sample].cpu().numpy()
+    # the GPU on the CPU sample (checked against the oracle in the CPU leg)
+    xs_d, ys_d = x[: args.cpu_sample], y[: args.cpu_sample]
+    gpu_sample = {"two_pass": h.qdot(xs_d, ys_d, tol), "one_pass": h.qdot(xs_d, ys_d, tol, opt=s1)}
+    del xs_d, ys_d
     scan_ms = tq["scan_ms"] / tq["qdot_calls"]
     cut_ms = tq["cut_ms"] / tq["qdot_calls"]
     acc_ms = tq["acc_ms"] / tq["qdot_calls"]
@@ -344,7 +401,7 @@ def main():
     del bx, by
 
     log(f"CPU oracle on a sample of {args.cpu_sample}")
-    cpu = cpu_baseline(xh, yh, tol)
+    cpu = cpu_baseline(xh, yh, tol, gpu_sample)
 
     value = n * K / wall / 1e9
     line = {
@@ -382,6 +439,10 @@ def main():
                        "bound_rel": res["bound_rel"], "flags": res["flags"],
                        "value": res["value"]},
             "relerr_vs_fp64_dot": abs(res["value"] - dot64) / abs(dot64) if dot64 else None,
+            "graph_replay_median_ms": {"two_pass": round(rep2, 4), "one_pass": round(rep1, 4)},
+            "alg_frac_hbm_whole_call": {
+                "two_pass": round(16.0 * n / (wall / K) / 1e9 / HBM_PEAK_GBS, 4),
+                "one_pass": round(16.0 * n / (wall1 / K) / 1e9 / HBM_PEAK_GBS, 4)},
             "one_pass": {
                 "gelem_s": round(n * K / wall1 / 1e9, 3),
                 "ms_per_call": round(wall1 / K * 1e3, 4),
