@@ -37,8 +37,29 @@ __global__ __launch_bounds__(VB) void k_spmv(int64_t n, const int32_t *__restric
     if (ctl && ctl->done) return;
     const int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x;
     if (i >= n) return;
+    // the first SNZ entries' column and value loads, then their gathers, are
+    // all in flight before the row is summed in storage order
+    constexpr int SNZ = 8;
+    const int32_t beg = rowptr[i], len = rowptr[i + 1] - beg;
+    int32_t ci[SNZ];
+    double pv[SNZ];
+#pragma unroll
+    for (int jj = 0; jj < SNZ; jj++) {
+        ci[jj] = 0;
+        pv[jj] = 0.0;
+        if (jj < len) {
+            ci[jj] = col[beg + jj];
+            pv[jj] = val[beg + jj];
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < SNZ; jj++)
+        if (jj < len) pv[jj] = pv[jj] * x[ci[jj]];
     double s = 0.0;
-    for (int32_t j = rowptr[i]; j < rowptr[i + 1]; j++) {
+#pragma unroll
+    for (int jj = 0; jj < SNZ; jj++)
+        if (jj < len) s = s + pv[jj];
+    for (int32_t j = beg + SNZ; j < beg + len; j++) {
         const double p = val[j] * x[col[j]];
         s = s + p;
     }

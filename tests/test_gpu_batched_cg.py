@@ -76,6 +76,19 @@ def test_cg_batched_equals_single_system_solver(h):
         assert abs(r1["iters"] - r["iters"]) <= 1, (s["m"], r1["iters"], r["iters"])
 
 
+def test_cg_batched_long_rows(h):
+    # a random SPD matrix with rows of 6..23 entries (the SpMV tail loop),
+    # 20000 rows: a gang of two blocks
+    rp, col, val = workloads.random_spd_csr(20000, 6, 3)
+    A = q.Csr(rp, col, val)
+    bh = workloads.normal_vector(20000, 8)
+    x = torch.zeros(20000, dtype=torch.float64, device="cuda:0")
+    r = h.cg_batched([(A, dev(bh), x, 1e-10, 1e-8, 2000, 1)])[0]
+    o = oracle.cg(rp, col, val, bh, 1e-10, 1e-8, 2000, 1)
+    assert r["status"] == q.OK and abs(r["iters"] - o["iters"]) <= 1, (r["iters"], o["iters"])
+    np.testing.assert_allclose(x.cpu().numpy(), o["x"], rtol=0, atol=1e-7 * np.abs(o["x"]).max())
+
+
 def test_cg_batched_statuses_are_per_system(h):
     ok = poisson_system(40, 3, 1)
     short = poisson_system(40, 3, 1, maxit=3)

@@ -44,6 +44,32 @@ def test_spmv_bitwise(h, m):
     np.testing.assert_array_equal(y.cpu().numpy(), oracle.spmv(rp, col, val, x))
 
 
+def test_spmv_bitwise_long_rows(h):
+    # rows of 6..23 entries: the unrolled first 8 entries and the tail loop
+    rp, col, val = workloads.random_spd_csr(3000, 6, 1)
+    A = q.Csr(rp, col, val)
+    x = workloads.normal_vector(3000, 4)
+    y = torch.empty(3000, dtype=torch.float64, device="cuda:0")
+    h.spmv(A, dev(x), y)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(y.cpu().numpy(), oracle.spmv(rp, col, val, x))
+
+
+def test_cg_long_rows(h):
+    rp, col, val = workloads.random_spd_csr(5000, 6, 2)
+    A = q.Csr(rp, col, val)
+    b = workloads.normal_vector(5000, 7)
+    for use in (1, 0):
+        x = torch.zeros(5000, dtype=torch.float64, device="cuda:0")
+        r = h.cg(A, dev(b), x, 1e-10, 1e-8, 2000, use)
+        o = oracle.cg(rp, col, val, b, 1e-10, 1e-8, 2000, use)
+        assert r["status"] == q.OK and o["status"] == oracle.OK
+        assert abs(r["iters"] - o["iters"]) <= 1, (use, r["iters"], o["iters"])
+        assert r["relres_true"] < 1e-9
+        np.testing.assert_allclose(x.cpu().numpy(), o["x"], rtol=0,
+                                   atol=1e-7 * np.abs(o["x"]).max())
+
+
 @pytest.mark.parametrize("m", [32, 64, 128])
 def test_cg_iteration_parity(h, m):
     rp, col, val = workloads.poisson2d_csr(m)

@@ -146,6 +146,41 @@ def laplacian3d_csr(m: int):
     return _stencil_csr((m, m, m), 6.0)
 
 
+def random_spd_csr(n: int, extra_per_row: int, seed: int):
+    """Random sparse symmetric strictly diagonally dominant matrix (SPD):
+    each row gets about 2 * extra_per_row off-diagonal entries -U(0.1, 1)
+    at random columns (symmetrised), and a diagonal of 1 + the absolute row
+    sum.  Rows are sorted by column: (rowptr, col, val) as int32/int32/f64.
+    Used for rows longer than the stencil matrices have."""
+    g = rng(seed)
+    i = np.repeat(np.arange(n, dtype=np.int64), extra_per_row)
+    j = g.integers(0, n, n * extra_per_row)
+    keep = i != j
+    i, j = i[keep], j[keep]
+    v = -g.uniform(0.1, 1.0, i.shape[0])
+    rows = np.concatenate([i, j])
+    cols = np.concatenate([j, i])
+    vals = np.concatenate([v, v])
+    key = rows * n + cols
+    order = np.argsort(key, kind="stable")
+    key, rows, cols, vals = key[order], rows[order], cols[order], vals[order]
+    first = np.ones(key.shape[0], dtype=bool)
+    first[1:] = key[1:] != key[:-1]
+    grp = np.cumsum(first) - 1
+    vals = np.bincount(grp, weights=vals)          # merge duplicate positions
+    rows, cols = rows[first], cols[first]
+    diag = 1.0 + np.bincount(rows, weights=np.abs(vals), minlength=n)
+    rows = np.concatenate([rows, np.arange(n)])
+    cols = np.concatenate([cols, np.arange(n)])
+    vals = np.concatenate([vals, diag])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return rowptr.astype(np.int32), cols.astype(np.int32), vals.astype(np.float64)
+
+
 def ragged_batch(count: int, seed: int, n_lo: float = 1e2, n_hi: float = 1e6,
                  tols=(1e-4, 1e-6, 1e-8), mag_lo: float = -20.0,
                  mag_hi: float = 20.0, max_total: int | None = None):
