@@ -236,6 +236,16 @@ QDOT_API int32_t qdot_classes_async(qdot_handle *h, const double *x, const doubl
                            void *stream, uint8_t *dev_cls, int64_t *dev_hist,
                            qdot_result *dev_out);
 
+/* Minimal entry: qdot of device vectors x, y (n components, 8-byte
+ * aligned) at tolerance tol with the default options, on a handle the
+ * library keeps per device (created on the first call on the current
+ * device, kept until the process ends), on the null stream, synchronous.
+ * value (host) receives the approximate dot product; counts (host, may be
+ * NULL) the DOUBLE, SINGLE, HALF, PERF counts.  Returns the status as qdot
+ * does.  Calls are serialised across host threads. */
+QDOT_API int32_t qdot_simple(const double *x, const double *y, int64_t n, double tol,
+                             double *value, int64_t counts[4]);
+
 /* Plain FP64 dot product sum_i x_i y_i (the full-precision kernel that
  * qdot approximates; the comparison baseline of Sec. 4.1).  dev_out: one
  * double in device memory.  Async. */

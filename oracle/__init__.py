@@ -76,7 +76,7 @@ def lib():
     L.orc_qdot.argtypes = [_dp, _dp, C.c_int64, C.c_double, _i32p,
                            C.POINTER(OrcResult), _u8p, _i32p, _i64p]
     L.orc_qdot.restype = C.c_int
-    for f in ("orc_dot_exact", "orc_abs_dot"):
+    for f in ("orc_dot_exact", "orc_abs_dot", "orc_dot_dot2"):
         getattr(L, f).argtypes = [_dp, _dp, C.c_int64]
         getattr(L, f).restype = C.c_double
     L.orc_sum_exact.argtypes = [_dp, C.c_int64]
@@ -153,6 +153,24 @@ def dot_exact(x, y) -> float:
     x, xp = _f64(x)
     y, yp = _f64(y)
     return lib().orc_dot_exact(xp, yp, x.shape[0])
+
+
+def dot_dot2(x, y) -> float:
+    """Ogita-Rump-Oishi Dot2 compensated dot (published algorithm)."""
+    x, xp = _f64(x)
+    y, yp = _f64(y)
+    return lib().orc_dot_dot2(xp, yp, len(x))
+
+
+def bound_thm34(r: dict, exact: float):
+    """A-posteriori form of the bound (Thm 3.4): with E = flexp(exact dot),
+    sum_k M_k 2^(k - E + 1) eps(class_k) = bound_rel * 2^(e_max - E); the
+    theorem needs e_max <= E (returned as hyp)."""
+    import math
+    if exact == 0.0 or r["n_bins"] == 0:
+        return {"hyp": False, "bound_thm3_rel": math.inf}
+    E = math.frexp(abs(exact))[1] - 1
+    return {"hyp": r["e_max"] <= E, "bound_thm3_rel": math.ldexp(r["bound_rel"], r["e_max"] - E)}
 
 
 def abs_dot(x, y) -> float:

@@ -138,6 +138,28 @@ double orc_dot_exact(const double *x, const double *y, int64_t n)
     return r;
 }
 
+/* Dot2 (Ogita, Rump and Oishi, "Accurate sum and dot product", SIAM J. Sci.
+ * Comput. 2005): the running sum p and a running correction s; every
+ * product is split exactly (TwoProduct, here by fma) and every addition to
+ * p exactly (Knuth's TwoSum); the errors are added in plain FP64.  Result as
+ * if computed in twice the working precision, then rounded. */
+double orc_dot_dot2(const double *x, const double *y, int64_t n)
+{
+    if (n <= 0) return 0.0;
+    double p = x[0] * y[0];
+    double s = fma(x[0], y[0], -p);
+    for (int64_t i = 1; i < n; i++) {
+        const double h = x[i] * y[i];
+        const double r = fma(x[i], y[i], -h);
+        const double q = p + h;            /* TwoSum(p, h) = (q, e) */
+        const double z = q - p;
+        const double e = (p - (q - z)) + (h - z);
+        p = q;
+        s = s + (e + r);
+    }
+    return p + s;
+}
+
 double orc_abs_dot(const double *x, const double *y, int64_t n)
 {
     xsum s;

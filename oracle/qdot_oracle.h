@@ -66,6 +66,9 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
 /* correctly rounded sum_i x_i y_i (valid while no product over- or
  * underflows), and correctly rounded sum_i |x_i y_i| */
 double orc_dot_exact(const double *x, const double *y, int64_t n);
+/* Ogita-Rump-Oishi Dot2: compensated dot product, result as if computed
+ * in twice FP64 precision and rounded (error bound u|xy| + gamma_n^2 sum|x_i y_i|). */
+double orc_dot_dot2(const double *x, const double *y, int64_t n);
 double orc_abs_dot(const double *x, const double *y, int64_t n);
 /* correctly rounded sum of n doubles */
 double orc_sum_exact(const double *v, int64_t n);

@@ -107,6 +107,7 @@ SIGNATURES = [
     ("qdot_timing_read", _i32, [_vp, C.POINTER(_d), C.POINTER(_i32)]),
     ("qdot_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp]),
     ("qdot", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, C.POINTER(QdotResult)]),
+    ("qdot_simple", _i32, [_vp, _vp, _i64, _d, C.POINTER(_d), C.POINTER(_i64)]),
     ("qdot_classes_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp, _vp, _vp]),
     ("qdot_fp64_dot_async", _i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
     ("qdot_batched_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32, _OPT,
@@ -208,6 +209,19 @@ class Csr:
         self.n = self.rowptr.numel() - 1
         self.c = QdotCsr(self.n, self.col.numel(), self.rowptr.data_ptr(),
                          self.col.data_ptr(), self.val.data_ptr())
+
+
+def qdot_simple(x, y, tol):
+    """The library's minimal entry point: (value, counts) of qdot(x, y) at
+    tol with default options on its own per-device handle, synchronous."""
+    _check_vec(x, "x")
+    _check_vec(y, "y")
+    v = C.c_double()
+    counts = (C.c_int64 * 4)()
+    st = lib().qdot_simple(_ptr(x), _ptr(y), x.numel(), float(tol), C.byref(v), counts)
+    if st not in (OK, E_NONFINITE):
+        raise QdotError(st, "qdot_simple")
+    return v.value, list(counts)
 
 
 def tuned_file(device: int = 0):

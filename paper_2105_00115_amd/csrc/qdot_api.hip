@@ -3,6 +3,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "qdot_handle.hpp"
 
@@ -292,6 +294,32 @@ int32_t qdot(qdot_handle *h, const double *x, const double *y, int64_t n, double
     if (e != hipSuccess) return hip_fail(h, e, "qdot result copy");
     *host_out = *h->host_res;
     return host_out->status;
+}
+
+int32_t qdot_simple(const double *x, const double *y, int64_t n, double tol, double *value,
+                    int64_t counts[4])
+{
+    if (!value) return QDOT_E_INVAL;
+    static std::mutex mu;
+    static std::map<int, qdot_handle *> handles;  // per device, kept for the process
+    std::lock_guard<std::mutex> lock(mu);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return QDOT_E_DEVICE;
+    qdot_handle *&h = handles[dev];
+    if (!h) {
+        const int32_t st = qdot_create(&h, dev);
+        if (st != QDOT_OK) {
+            h = nullptr;
+            return st;
+        }
+    }
+    qdot_result r;
+    const int32_t st = qdot(h, x, y, n, tol, nullptr, nullptr, &r);
+    if (st != QDOT_OK && st != QDOT_E_NONFINITE) return st;
+    *value = r.value;
+    if (counts)
+        for (int q = 0; q < 4; q++) counts[q] = r.count[q];
+    return st;
 }
 
 int32_t qdot_classes_async(qdot_handle *h, const double *x, const double *y, int64_t n,

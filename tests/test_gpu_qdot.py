@@ -222,6 +222,20 @@ def test_async_result_in_stream_order(h):
         assert res["count"] == o["count"] and res["t"] == o["t"]
 
 
+def test_minimal_entry_point(h):
+    x, y = workloads.log_uniform_pair(50000, 19)
+    xd, yd = dev(x), dev(y)
+    v, counts = q.qdot_simple(xd, yd, 1e-6)
+    r = h.qdot(xd, yd, 1e-6)
+    assert counts == r["count"]
+    o = oracle.qdot(x, y, 1e-6)
+    assert counts == o["count"]
+    # its own handle may use another launch shape: FP64 reduction order only
+    assert abs(v - o["value"]) <= VALUE_TOL * oracle.abs_dot(x, y)
+    with pytest.raises(q.QdotError):
+        q.qdot_simple(xd, yd, -1.0)
+
+
 def test_fp64_dot_baseline(h):
     x, y = workloads.log_uniform_pair(1 << 20, 18)
     d = h.fp64_dot(dev(x), dev(y))

@@ -227,6 +227,44 @@ def test_dot_exact_against_fractions():
         assert oracle.abs_dot(x, y) == float(qa)  # Fraction -> float rounds to nearest
 
 
+def test_dot2_within_its_published_bound():
+    # Dot2 (Ogita-Rump-Oishi): |dot2 - x.y| <= u |x.y| + gamma_n^2 sum|x_i y_i|,
+    # u = 2^-53, gamma_n = n u / (1 - n u); checked against Fractions, also on
+    # sums with heavy cancellation, where a plain FP64 dot fails the bound
+    u = Fraction(1, 2 ** 53)
+    g = workloads.rng(9)
+    worst_plain_fails = False
+    for trial in range(40):
+        n = int(g.integers(2, 400))
+        x, y = workloads.log_uniform_pair(n, 200 + trial, -8, 8)
+        if trial % 2:
+            x = np.concatenate([x, -x])
+            y = np.concatenate([y, y * (1 + 2.0 ** -40)])
+            n = len(x)
+        q = sum((Fraction(a) * Fraction(b) for a, b in zip(x.tolist(), y.tolist())), Fraction(0))
+        qa = sum((abs(Fraction(a) * Fraction(b)) for a, b in zip(x.tolist(), y.tolist())),
+                 Fraction(0))
+        gam = n * u / (1 - n * u)
+        bound = u * abs(q) + gam * gam * qa
+        assert abs(Fraction(oracle.dot_dot2(x, y)) - q) <= bound, trial
+        plain = Fraction(float(np.dot(x, y)))
+        worst_plain_fails |= abs(plain - q) > bound
+    assert worst_plain_fails  # the cases are hard enough to tell the two apart
+    assert oracle.dot_dot2(np.zeros(0), np.zeros(0)) == 0.0
+
+
+def test_thm34_helper_matches_the_definition():
+    x, y = workloads.log_uniform_pair(20000, 43)
+    r = oracle.qdot(x, y, 1e-6)
+    exact = oracle.dot_exact(x, y)
+    b = oracle.bound_thm34(r, exact)
+    E = exp_of_fraction(Fraction(exact))
+    assert b["hyp"] == (r["e_max"] <= E)
+    assert Fraction(b["bound_thm3_rel"]) == Fraction(r["bound_rel"]) * Fraction(2) ** (r["e_max"] - E)
+    err = abs(Fraction(r["value"]) - Fraction(exact)) / abs(Fraction(exact))
+    assert err <= Fraction(b["bound_thm3_rel"]) * (1 + Fraction(1, 2 ** 20))
+
+
 # --------------------------------------------------------------------------
 # Hand-derived worked examples
 # --------------------------------------------------------------------------
