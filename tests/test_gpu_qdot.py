@@ -222,6 +222,36 @@ def test_async_result_in_stream_order(h):
         assert res["count"] == o["count"] and res["t"] == o["t"]
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_graph_replay_of_one_call(h, mode):
+    # no memset nodes: the workspace is reset by the kernels themselves
+    opt = [0, 0, 0, mode]
+    x, y = workloads.log_uniform_pair(300001, 20)
+    xd, yd = dev(x), dev(y)
+    eager = torch.zeros(q.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    h.qdot_async(xd, yd, 1e-6, eager, opt=opt)
+    torch.cuda.synchronize()
+    out = torch.zeros_like(eager)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            h.qdot_async(xd, yd, 1e-6, out, opt=opt)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        h.qdot(xd[:7000], yd[:7000], 1e-3, opt=opt)  # eager work on the same handle
+        torch.cuda.synchronize()
+    o = oracle.qdot(x, y, 1e-6, opt=opt)
+    r = q.parse_results(out)[0]
+    assert r["count"] == o["count"]
+    assert abs(r["value"] - o["value"]) <= VALUE_TOL * oracle.abs_dot(x, y)
+
+
 def test_minimal_entry_point(h):
     x, y = workloads.log_uniform_pair(50000, 19)
     xd, yd = dev(x), dev(y)
