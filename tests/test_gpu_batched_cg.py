@@ -171,3 +171,53 @@ def test_batch_run_graph_replay(h):
             assert torch.equal(s["x"], ex), rep
         h.qdot(xd[:5000], yd[:5000], 1e-6)  # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.timeout(600)
+def test_full_size_c5_launch(h):
+    """The whole batched workload in one launch: 4096 ragged qdot instances
+    (n = round(10^U[2,6])) and 256 CG systems (2D Poisson, side
+    round(2^U[5,9])).  Every system converges with its FP64-dot twin's
+    iteration count (within one); sampled instances match the oracle."""
+    g = workloads.rng(2025)
+    sizes = np.rint(10.0 ** g.uniform(2, 6, 4096)).astype(np.int64)
+    offsets = np.zeros(4097, dtype=np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    tols = np.array([1e-4, 1e-6, 1e-8])[g.integers(0, 3, 4096)]
+    total = int(offsets[-1])
+    print(f"[gpu-case] batched C5 with 256 CG systems, total={total}", flush=True)
+    xd, yd = workloads.log_uniform_pair_torch(total, 2025, "cuda:0")
+    gs = workloads.rng(2026)
+    sides = np.rint(2.0 ** gs.uniform(5, 9, 256)).astype(np.int64)
+    mats, sysq, sysf = {}, [], []
+    xs = []
+    for k, m in enumerate(sides):
+        m = int(m)
+        if m not in mats:
+            mats[m] = q.Csr(*workloads.poisson2d_csr(m))
+        b = dev(workloads.normal_vector(m * m, 3000 + k))
+        xq = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+        xf = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+        sysq.append((mats[m], b, xq, 1e-10, 1e-8, 20000, 1))
+        sysf.append((mats[m], b, xf, 1e-10, 1e-8, 20000, 0))
+    off_d = torch.from_numpy(offsets).to("cuda:0")
+    out = torch.zeros(4096 * q.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    cg_out = torch.zeros(256 * q.CG_RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    h.batch_run_async(xd, yd, off_d, offsets, dev(tols), out, sysq, cg_out)
+    torch.cuda.synchronize()
+    cq = q.parse_cg_results(cg_out)
+    cf = h.cg_batched(sysf)
+    for s in range(256):
+        assert cq[s]["status"] == q.OK and cf[s]["status"] == q.OK, s
+        assert abs(cq[s]["iters"] - cf[s]["iters"]) <= 1, (s, cq[s]["iters"], cf[s]["iters"])
+        assert cq[s]["relres_true"] < 2e-10
+    res = q.parse_results(out)
+    assert all(r["status"] == q.OK for r in res)
+    pick = sorted(set(g.integers(0, 4096, 20).tolist()) | {int(np.argmax(sizes))})
+    for j in pick:
+        a, b = int(offsets[j]), int(offsets[j + 1])
+        xh, yh = xd[a:b].cpu().numpy(), yd[a:b].cpu().numpy()
+        o = oracle.qdot(xh, yh, tols[j])
+        for k in INT_KEYS:
+            assert res[j][k] == o[k], (j, k)
+        assert abs(res[j]["value"] - o["value"]) <= 1e-13 * oracle.abs_dot(xh, yh)

@@ -127,3 +127,42 @@ def test_power_method(h, m):
         assert r["status"] == q.OK
         np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
         assert r["lambda"] <= lam_max * (1 + 1e-12)
+
+
+@pytest.mark.timeout(300)
+def test_full_size_cg_poisson_1024(h):
+    """The CG workload at its full size (2D Poisson 1024^2, b ~ N(0,1), qdot
+    tol 1e-8, stop at 1e-10): qdot-CG needs the FP64-dot CG's iteration
+    count (within one) and reaches the true residual."""
+    m = 1024
+    print(f"[gpu-case] CG Poisson {m}^2", flush=True)
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    b = dev(workloads.normal_vector(m * m, 3))
+    res = {}
+    for use in (1, 0):
+        x = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+        res[use] = h.cg(A, b, x, 1e-10, 1e-8, 20000, use)
+        assert res[use]["status"] == q.OK
+        assert res[use]["relres_true"] < 2e-10
+    assert abs(res[1]["iters"] - res[0]["iters"]) <= 1, (res[1]["iters"], res[0]["iters"])
+
+
+@pytest.mark.timeout(300)
+def test_full_size_power_laplacian_128(h):
+    """The power-method workload at its full size (3D Laplacian 128^3, 500
+    iterations, qdot tol 1e-6): the eigenvalue estimate agrees with the
+    FP64-dot run and stays below the closed-form largest eigenvalue."""
+    m = 128
+    print(f"[gpu-case] power Laplacian {m}^3", flush=True)
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, val)
+    x0 = workloads.unit_vector(m ** 3, 4)
+    lam = {}
+    for use in (1, 0):
+        r = h.power(A, dev(x0), 500, 1e-6, use, trace=False)
+        assert r["status"] == q.OK
+        lam[use] = r["lambda"]
+    lam_max = 6.0 + 6.0 * math.cos(math.pi / (m + 1))
+    assert abs(lam[1] - lam[0]) <= 1e-9 * lam[0]
+    assert lam[0] <= lam_max * (1 + 1e-12) and lam[0] > 0.99 * lam_max
