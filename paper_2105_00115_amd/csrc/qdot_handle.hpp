@@ -18,8 +18,8 @@ struct qdot_handle {
     qdot_tune tune[QDOT_TUNE_BUCKETS];
     std::string err;
 
-    // scratch for the solver drivers, grown on demand
-    double *vec = nullptr;           // 4 * vec_n doubles
+    // scratch of the power method, grown on demand
+    double *vec = nullptr;           // w = A x, vec_n doubles
     int64_t vec_n = 0;
     void *ctl = nullptr;             // solver control block
     qdot_result *res_ring = nullptr; // solver result slots

@@ -1,5 +1,7 @@
 // qdot kernels for gfx950: exponent scan, cutoff selection, fused
-// quantize-and-accumulate, and the plain FP64 dot used as the baseline.
+// quantize-and-accumulate (two passes over x, y), the one-pass scan with
+// per-bin candidate sums and its final pick (accum_mode 1), and the plain
+// FP64 dot used as the baseline.
 //
 // Data layout: x and y are FP64 vectors read in groups of 4 consecutive
 // elements per lane (two 16-byte loads per operand when both are 16-byte

@@ -26,8 +26,9 @@ struct Launch {
 // when it is <= S1_WIN).
 int s1_depth(int64_t n, double tol, const qdot_options &o);
 
-// Enqueue scan -> cutoff -> accumulate for one qdot.  cls_out (n bytes) and
-// hist_out (W int64) are optional debug outputs.
+// Enqueue one qdot: scan -> cutoff -> accumulate -> combine (accum_mode 0),
+// or one-pass scan -> cutoff -> pick (accum_mode 1).  cls_out (n bytes) and
+// hist_out (W int64) are optional debug outputs of mode 0.
 hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_t n,
                        double tol, const qdot_options &o, qdot_result *out,
                        unsigned char *cls_out, long long *hist_out);

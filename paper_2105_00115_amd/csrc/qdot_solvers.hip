@@ -1,12 +1,13 @@
-// Applications of qdot: CSR SpMV, conjugate gradient (Alg. 4) and the power
-// method (Alg. 5), with every inner product by qdot or by the plain FP64 dot.
+// CSR SpMV and the power method (Alg. 5), with both inner products of every
+// iteration by qdot or by the plain FP64 dot.  (Conjugate gradient runs as
+// a persistent launch: qdot_cg.hip, qdot_cg.hpp.)
 //
 // All state stays in device memory.  The host enqueues iterations in
 // batches and reads a small control block between batches; kernels of
-// iterations enqueued after convergence see the `done` flag and return, so
-// the iteration count is exact while the host syncs only once per batch.
-// Vector updates are one IEEE operation per product and per sum (no fused
-// multiply-add), the same arithmetic as a plain sequential loop.
+// iterations enqueued after a breakdown see the `done` flag and return, so
+// the host syncs only once per batch.  Vector updates are one IEEE operation
+// per product and per sum (no fused multiply-add), the same arithmetic as a
+// plain sequential loop.
 #include <cmath>
 #include <cstring>
 
@@ -15,9 +16,7 @@
 namespace qd {
 
 struct SolverCtl {
-    double c;          // CG: current r.r;  power: last lambda
-    double thresh;     // CG: rtol * ||b||
-    double bnorm;      // CG: ||b||
+    double c;          // last lambda
     int iters;
     int done;
     int broke;
@@ -72,11 +71,6 @@ __device__ __forceinline__ bool all_perforated(const qdot_result *r)
 {
     return r && (r->flags & QDOT_F_ALL_PERF) && r->n_bins > 0;
 }
-
-
-
-
-
 
 // power method: x = w / sqrt(c), lambda recorded
 __global__ __launch_bounds__(VB) void k_pm_update(int64_t n, SolverCtl *ctl,
@@ -142,7 +136,7 @@ int32_t ensure_solver_vectors(qdot_handle *h, int64_t n)
         if (h->vec) (void)hipFree(h->vec);
         h->vec = nullptr;
         h->vec_n = 0;
-        if (hipMalloc((void **)&h->vec, sizeof(double) * 4 * (size_t)std::max<int64_t>(n, 1)) !=
+        if (hipMalloc((void **)&h->vec, sizeof(double) * (size_t)std::max<int64_t>(n, 1)) !=
             hipSuccess)
             return fail(h, QDOT_E_NOMEM, "solver vector allocation failed");
         h->vec_n = n;
@@ -215,7 +209,7 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     if (st != QDOT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const Launch L = make_launch(h, s, n);
-    double *w = h->vec + 3 * n;
+    double *w = h->vec;
     SolverCtl *ctl = (SolverCtl *)h->ctl;
     hipError_t e = hipSuccess;
     auto ok = [&](hipError_t x_) {
