@@ -254,6 +254,13 @@ class Qdot:
             lib().qdot_destroy(self._h)
             self._h = C.c_void_p()
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
         try:
             self.close()

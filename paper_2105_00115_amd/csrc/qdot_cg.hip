@@ -117,7 +117,7 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
     DeviceGuard g(h->device);
     const int64_t n = A->n;
-    int32_t st = ensure_solver_vectors(h, n);
+    int32_t st = ensure_solver_vectors(h, 3 * n);  // r, p, q
     if (st != QDOT_OK) return st;
     if ((st = ensure_cg_buffers(h, 1, 1)) != QDOT_OK) return st;
     CgDev *d = (CgDev *)h->cg;

@@ -18,9 +18,10 @@ struct qdot_handle {
     qdot_tune tune[QDOT_TUNE_BUCKETS];
     std::string err;
 
-    // scratch of the power method, grown on demand
-    double *vec = nullptr;           // w = A x, vec_n doubles
-    int64_t vec_n = 0;
+    // solver scratch, grown on demand: the power method keeps w = A x
+    // (n doubles), the single-system CG keeps r, p, q (3 n doubles)
+    double *vec = nullptr;
+    int64_t vec_n = 0;               // doubles held at vec
     void *ctl = nullptr;             // solver control block
     qdot_result *res_ring = nullptr; // solver result slots
     double *dres = nullptr;          // FP64-dot result slots
@@ -70,6 +71,7 @@ bool options_ok(const qdot_options &o);
 bool s1_admissible(int64_t n, double tol, const qdot_options &o);
 void free_plans(qdot_handle *h);
 void free_cg(qdot_handle *h);
-int32_t ensure_solver_vectors(qdot_handle *h, int64_t n);
+// Grows the solver scratch to at least `doubles` doubles.
+int32_t ensure_solver_vectors(qdot_handle *h, int64_t doubles);
 
 }  // namespace qd

@@ -123,7 +123,7 @@ static bool csr_ok(const qdot_csr *A)
            A->n < (int64_t)1 << 31 && A->nnz < (int64_t)1 << 31;
 }
 
-int32_t ensure_solver_vectors(qdot_handle *h, int64_t n)
+int32_t ensure_solver_vectors(qdot_handle *h, int64_t doubles)
 {
     if (!h->ctl) {
         if (hipMalloc(&h->ctl, sizeof(SolverCtl)) != hipSuccess ||
@@ -132,14 +132,14 @@ int32_t ensure_solver_vectors(qdot_handle *h, int64_t n)
             hipHostMalloc(&h->host_ctl, sizeof(SolverCtl), hipHostMallocDefault) != hipSuccess)
             return fail(h, QDOT_E_NOMEM, "solver control allocation failed");
     }
-    if (h->vec_n < n) {
+    if (h->vec_n < doubles) {
         if (h->vec) (void)hipFree(h->vec);
         h->vec = nullptr;
         h->vec_n = 0;
-        if (hipMalloc((void **)&h->vec, sizeof(double) * (size_t)std::max<int64_t>(n, 1)) !=
+        if (hipMalloc((void **)&h->vec, sizeof(double) * (size_t)std::max<int64_t>(doubles, 1)) !=
             hipSuccess)
             return fail(h, QDOT_E_NOMEM, "solver vector allocation failed");
-        h->vec_n = n;
+        h->vec_n = doubles;
     }
     return QDOT_OK;
 }

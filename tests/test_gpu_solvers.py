@@ -113,6 +113,42 @@ def test_cg_maxit(h):
     assert r["status"] == q.E_MAXIT and r["iters"] == 10
 
 
+@pytest.mark.parametrize("first", ["power", "cg"])
+def test_power_and_cg_share_one_handle(first):
+    # the power method keeps one scratch vector, CG three: whichever runs
+    # first, the other must grow the scratch and give the same results as on
+    # a fresh handle
+    m = 12
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, val)
+    n = m ** 3
+    b = workloads.normal_vector(n, 11)
+    x0 = workloads.unit_vector(n, 12)
+
+    def run_power(hh):
+        return hh.power(A, dev(x0), 50, 1e-6, 1)["trace"]
+
+    def run_cg(hh):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        r = hh.cg(A, dev(b), x, 1e-10, 1e-8, 500, 1)
+        return r["iters"], x.cpu().numpy()
+
+    with q.Qdot(0) as fresh:
+        p_ref = run_power(fresh)
+    with q.Qdot(0) as fresh:
+        it_ref, x_ref = run_cg(fresh)
+    with q.Qdot(0) as hh:
+        if first == "power":
+            p_got = run_power(hh)
+            it_got, x_got = run_cg(hh)
+        else:
+            it_got, x_got = run_cg(hh)
+            p_got = run_power(hh)
+    np.testing.assert_array_equal(p_got, p_ref)
+    assert it_got == it_ref
+    np.testing.assert_array_equal(x_got, x_ref)
+
+
 @pytest.mark.parametrize("m", [6, 16])
 def test_power_method(h, m):
     rp, col, val = workloads.laplacian3d_csr(m)
