@@ -19,6 +19,7 @@ KMIN, KMAX = -2148, 2047
 W = KMAX - KMIN + 1
 DOUBLE, SINGLE, HALF, PERF = 0, 1, 2, 3
 F_UNATTAINABLE, F_THM_ALL_DOUBLE, F_ALL_PERF, F_OVERFLOW = 1, 2, 4, 8
+F_GUARANTEED, F_RESELECTED = 16, 32
 OK, E_INVAL, E_NONFINITE, E_BREAKDOWN, E_MAXIT = 0, 1, 2, 5, 6
 
 
@@ -37,6 +38,9 @@ class OrcResult(C.Structure):
         ("bound_rig", C.c_double),
         ("flags", C.c_int32),
         ("status", C.c_int32),
+        ("lower", C.c_double),
+        ("e_ref", C.c_int32),
+        ("passes", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -54,6 +58,9 @@ class OrcResult(C.Structure):
             "bound_rig": self.bound_rig,
             "flags": self.flags,
             "status": self.status,
+            "lower": self.lower,
+            "e_ref": self.e_ref,
+            "passes": self.passes,
         }
 
 
@@ -116,8 +123,10 @@ def _f64(a):
 def _opts(opt):
     if opt is None:
         return None, None
-    o = np.ascontiguousarray(opt, dtype=np.int32)
-    assert o.shape == (4,)
+    o = np.zeros(5, dtype=np.int32)
+    v = np.asarray(opt, dtype=np.int32).ravel()
+    assert v.shape[0] in (4, 5)  # {key, score, boundary, accum[, guard]} modes
+    o[:v.shape[0]] = v
     return o, o.ctypes.data_as(_i32p)
 
 

@@ -194,8 +194,8 @@ void orc_split(double v, int32_t *E, double *m)
  * key_mode 0 (product): the exponent of x*y itself, as Def. 3.1 and the
  *   theorems bin on flexp(x (.) y): E(x) + E(y), plus one when the
  *   significand product m_x m_y reaches 2.
- * key_mode 1 (sum): E(x) + E(y), as Alg. 2 line "exponent preprocessing"
- *   writes it. */
+ * key_mode 1 (sum): E(x) + E(y), as the exponent-preprocessing step of
+ *   Alg. 2 writes it. */
 int32_t orc_key(double x, double y, int32_t key_mode)
 {
     int32_t ex, ey;
@@ -280,86 +280,24 @@ static double eps_of(int cls)
     }
 }
 
-/* ------------------------------------------------------------------ */
-/* qdot (Alg. 3)                                                         */
-/* ------------------------------------------------------------------ */
-int orc_qdot(const double *x, const double *y, int64_t n, double tol,
-             const int32_t *opt, orc_result *r, uint8_t *cls_out,
-             int32_t *key_out, int64_t *hist_out)
+/* Classes of every bin (eq. (bin-score-def), eq. (precision-def)) with the
+ * scores taken against the reference exponent e_ref: e_max as Alg. 2 has
+ * it, or a lower estimate of flexp(x.y) when the guaranteed mode reselects
+ * (Thm 3.4 puts E in place of e_max).  Fills the class table C, the class
+ * counts, the Thm 3.3 sum relative to e_max and the selection flags. */
+static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e_ref,
+                       int32_t t, int32_t nonstrict, int64_t n_zero, uint8_t *C,
+                       orc_result *r)
 {
-    memset(r, 0, sizeof *r);
-    int32_t key_mode = opt ? opt[0] : 0;
-    int32_t score_mode = opt ? opt[1] : 0;
-    int32_t nonstrict = opt ? opt[2] : 0;
-    int32_t accum_mode = opt ? opt[3] : 0;
-    if (n < 0 || (n > 0 && (!x || !y)) || !(tol > 0.0) || !isfinite(tol) ||
-        key_mode < 0 || key_mode > 1 || score_mode < 0 || score_mode > 1 ||
-        nonstrict < 0 || nonstrict > 1 || accum_mode < 0 || accum_mode > 1) {
-        r->status = ORC_E_INVAL;
-        r->value = NAN;
-        return r->status;
-    }
-    for (int64_t i = 0; i < n; i++) {
-        if (!isfinite(x[i]) || !isfinite(y[i])) {
-            r->status = ORC_E_NONFINITE;
-            r->value = NAN;
-            return r->status;
-        }
-    }
-
-    /* Alg. 2, exponent preprocessing and exact bins: the bin of key k holds
-     * the components whose product has exponent k.  A zero product has no
-     * exponent; it is perforated (it contributes exactly nothing) and kept
-     * out of the bins, e_max, e_min and N_bins. */
-    int64_t *M = (int64_t *)calloc(ORC_W, sizeof(int64_t));
-    int32_t *key = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    for (int64_t i = 0; i < n; i++) {
-        if (x[i] == 0.0 || y[i] == 0.0) {
-            key[i] = INT32_MIN;
-            r->n_zero++;
-            continue;
-        }
-        key[i] = orc_key(x[i], y[i], key_mode);
-        M[key[i] - ORC_KMIN]++;
-    }
-    int32_t e_max = INT32_MIN, e_min = INT32_MAX, n_bins = 0;
-    for (int32_t k = ORC_KMIN; k <= ORC_KMAX; k++) {
-        if (M[k - ORC_KMIN] == 0) continue;
-        n_bins++;
-        if (k > e_max) e_max = k;
-        if (k < e_min) e_min = k;
-    }
-    if (hist_out) memcpy(hist_out, M, sizeof(int64_t) * ORC_W);
-    if (key_out)
-        for (int64_t i = 0; i < n; i++) key_out[i] = key[i];
-
-    if (n_bins == 0) { /* every product is zero: exact answer +0 */
-        r->value = 0.0;
-        r->count[ORC_PERF] = n;
-        r->flags = ORC_F_ALL_PERF;
-        if (cls_out)
-            for (int64_t i = 0; i < n; i++) cls_out[i] = ORC_PERF;
-        free(M);
-        free(key);
-        return ORC_OK;
-    }
-    r->e_max = e_max;
-    r->e_min = e_min;
-    r->n_bins = n_bins;
-
-    /* floor(log2 eps), with eps divided by N_bins in the default score */
-    int32_t t = orc_t(score_mode == 0 ? n_bins : 1, tol);
-    r->t = t;
-
-    /* bin scores eq. (bin-score-def) and precisions eq. (precision-def) */
-    uint8_t *C = (uint8_t *)malloc(ORC_W);
     xsum brel;
     xs_init(&brel);
+    for (int c = 0; c < 4; c++) r->count[c] = 0;
+    r->flags = 0;
     for (int32_t k = ORC_KMIN; k <= ORC_KMAX; k++) {
         int64_t Mk = M[k - ORC_KMIN];
         C[k - ORC_KMIN] = ORC_PERF;
         if (Mk == 0) continue; /* empty bin: score -inf */
-        int32_t sigma = orc_ceil_log2(Mk) + k - e_max - t + 1;
+        int32_t sigma = orc_ceil_log2(Mk) + k - e_ref - t + 1;
         int32_t c = orc_precision(sigma, nonstrict);
         if (nonstrict ? sigma > M_DOUBLE : sigma >= M_DOUBLE)
             r->flags |= ORC_F_UNATTAINABLE;
@@ -368,32 +306,38 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
         /* Thm 3.3 term M_k 2^(u_k - e_max + 1) eps(k), u_k = k */
         xs_add(&brel, ldexp((double)Mk * eps_of(c), k - e_max + 1));
     }
-    r->count[ORC_PERF] += r->n_zero;
+    r->count[ORC_PERF] += n_zero;
     r->bound_rel = xs_round(&brel);
     r->bound_abs = ldexp(r->bound_rel, e_max);
     xs_free(&brel);
     /* Thm 3.6 (early termination): all bins at input precision when
-     * e_max - e_min <= -floor(log2 eps) - m_single. */
-    if ((int64_t)e_max - e_min <= -(int64_t)t - M_SINGLE)
+     * e_ref - e_min <= -floor(log2 eps) - m_single. */
+    if ((int64_t)e_ref - e_min <= -(int64_t)t - M_SINGLE)
         r->flags |= ORC_F_THM_ALL_DOUBLE;
     if (r->count[ORC_DOUBLE] + r->count[ORC_SINGLE] + r->count[ORC_HALF] == 0)
         r->flags |= ORC_F_ALL_PERF;
+}
 
-    /* Alg. 1.  Every kept component is scaled to exponent 0 (x_i -> m_x,
-     * y_i -> m_y), cast to its bin's precision, multiplied there, and scaled
-     * back by 2^(E(x)+E(y)).  Scaling back is written relative to 2^e_max
-     * (double leaves) or 2^c32 (FP32 leaves); both offsets are exact powers
-     * of two and the final result is multiplied by 2^e_max once.
-     *   double: fl64(m_x m_y)
-     *   single: fl32(fl32(m_x) fl32(m_y))            (FP32 product)
-     *   half:   r16(m_x) r16(m_y), exact in FP32     (FP16 operands, FP32
-     *                                                 product/accumulation)
-     * FP32 leaves are summed in FP32 only inside 64-element tiles of the
-     * original index order (adjacent-pairwise tree); tile sums and double
-     * leaves are then summed at input precision: exactly, rounded once.
-     * c32 = e_max + t + 22 keeps every single/half leaf a normal FP32 number
-     * below 4 whatever the tolerance. */
-    int32_t c32 = e_max + t + 22;
+/* Alg. 1 over the classes C.  Every kept component is scaled to exponent 0
+ * (x_i -> m_x, y_i -> m_y), cast to its bin's precision, multiplied there,
+ * and scaled back by 2^(E(x)+E(y)).  Scaling back is written relative to
+ * 2^e_max (double leaves) or 2^c32 (FP32 leaves); both offsets are exact
+ * powers of two and the final result is multiplied by 2^e_max once.
+ *   double: fl64(m_x m_y)
+ *   single: fl32(fl32(m_x) fl32(m_y))            (FP32 product)
+ *   half:   r16(m_x) r16(m_y), exact in FP32     (FP16 operands, FP32
+ *                                                 product/accumulation)
+ * accum_mode 0: FP32 leaves are summed in FP32 only inside 64-element tiles
+ * of the original index order (adjacent-pairwise tree); tile sums and
+ * double leaves are then summed at input precision: exactly, rounded once.
+ * accum_mode 1: every leaf is summed exactly, rounded once.
+ * c32 = e_ref + t + 22 keeps every single/half leaf a normal FP32 number
+ * below 4 whatever the tolerance.  Returns S, the sum in units of 2^e_max;
+ * writes value, part, bound_rig and the overflow flag. */
+static double orc_compute(const double *x, const double *y, int64_t n, const int32_t *key,
+                          const uint8_t *C, int32_t e_max, int32_t c32, int32_t accum_mode,
+                          uint8_t *cls_out, orc_result *r)
+{
     xsum all, pd, ps, ph, rig;
     xs_init(&all);
     xs_init(&pd);
@@ -487,6 +431,182 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
     xs_free(&ps);
     xs_free(&ph);
     xs_free(&rig);
+    return S;
+}
+
+/* Guaranteed mode: a bound, in units of 2^e_max, of every error of one
+ * call (quantisation, FP32 tile trees, FP64 stage, subnormal scaling),
+ * computed from the histogram, the classes and the computed sum S alone so
+ * that the library can evaluate the same formula after pass 2:
+ *   a = (Q + T + F)(1 + 2^-40),
+ *   Q = sum_k M_k 2^(k-e_max+1) rho(class_k)   (|x_i y_i| < 2^(k+1) in bin
+ *       k; rho = the largest relative error of one leaf: 2^-53 double,
+ *       (1+2^-24)^3 - 1 single, (1+2^-11)^2 - 1 half, 1 perforated),
+ *   T = g6 (1 + 2^-9) sum over single/half bins of M_k 2^(k-e_max+1),
+ *   F = 2^-52 |S| + 4 gn^2 (1 + 2^-8) sum over kept bins of
+ *       M_k 2^(k-e_max+1) + (2n + 4) 2^-1074. */
+static double orc_guard_slack(const int64_t *M, const uint8_t *C, int32_t e_max, double S,
+                              int64_t n)
+{
+    const double rho[4] = {0x1p-53, 0x1.8p-23 + 0x1.8p-47 + 0x1p-72, 0x1p-10 + 0x1p-22, 1.0};
+    const double u32 = 0x1p-24, u64 = 0x1p-53;
+    const double g6 = 6.0 * u32 / (1.0 - 6.0 * u32);
+    const double nu = (double)n * u64;
+    const double gn = nu / (1.0 - nu);
+    xsum q, f32, kept;
+    xs_init(&q);
+    xs_init(&f32);
+    xs_init(&kept);
+    for (int32_t k = ORC_KMIN; k <= ORC_KMAX; k++) {
+        int64_t Mk = M[k - ORC_KMIN];
+        if (Mk == 0) continue;
+        int c = C[k - ORC_KMIN];
+        double w = ldexp((double)Mk, k - e_max + 1);
+        xs_add(&q, ldexp((double)Mk * rho[c], k - e_max + 1));
+        if (c == ORC_SINGLE || c == ORC_HALF) xs_add(&f32, w);
+        if (c != ORC_PERF) xs_add(&kept, w);
+    }
+    double Q = xs_round(&q);
+    double T = g6 * (1.0 + 0x1p-9) * xs_round(&f32);
+    double F = 0x1p-52 * fabs(S) + 4.0 * gn * gn * (1.0 + 0x1p-8) * xs_round(&kept) +
+               (2.0 * (double)n + 4.0) * 0x1p-1074;
+    xs_free(&q);
+    xs_free(&f32);
+    xs_free(&kept);
+    return (Q + T + F) * (1.0 + 0x1p-40);
+}
+
+/* Lower bound of |x.y| in units of 2^e_max from one computed sum: |S|
+ * less the slack; raised to 1 when every non-zero product has one sign
+ * (then |x.y| >= max |x_i y_i| >= 2^e_max). */
+static double orc_lower(const int64_t *M, const uint8_t *C, int32_t e_max, double S, int64_t n,
+                        int one_signed)
+{
+    double low = fabs(S) * (1.0 - 0x1p-52) - orc_guard_slack(M, C, e_max, S, n);
+    if (one_signed && low < 1.0) low = 1.0;
+    return low;
+}
+
+/* Thm 3.4 with E replaced by the certified E_lo = e_max + flexp(low) <=
+ * flexp(x.y): relerr <= bound_rel 2^(e_max - E_lo) <= tol. */
+static int orc_certified(double bound_rel, double low, double tol)
+{
+    return low > 0.0 && ldexp(bound_rel, -ilogb(low)) <= tol;
+}
+
+/* ------------------------------------------------------------------ */
+/* qdot (Alg. 3)                                                         */
+/* ------------------------------------------------------------------ */
+int orc_qdot(const double *x, const double *y, int64_t n, double tol,
+             const int32_t *opt, orc_result *r, uint8_t *cls_out,
+             int32_t *key_out, int64_t *hist_out)
+{
+    memset(r, 0, sizeof *r);
+    int32_t key_mode = opt ? opt[0] : 0;
+    int32_t score_mode = opt ? opt[1] : 0;
+    int32_t nonstrict = opt ? opt[2] : 0;
+    int32_t accum_mode = opt ? opt[3] : 0;
+    int32_t guard_mode = opt ? opt[4] : 0;
+    if (n < 0 || (n > 0 && (!x || !y)) || !(tol > 0.0) || !isfinite(tol) ||
+        key_mode < 0 || key_mode > 1 || score_mode < 0 || score_mode > 1 ||
+        nonstrict < 0 || nonstrict > 1 || accum_mode < 0 || accum_mode > 1 ||
+        guard_mode < 0 || guard_mode > 1 ||
+        (guard_mode == 1 && (key_mode != 0 || accum_mode != 0))) {
+        r->status = ORC_E_INVAL;
+        r->value = NAN;
+        return r->status;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        if (!isfinite(x[i]) || !isfinite(y[i])) {
+            r->status = ORC_E_NONFINITE;
+            r->value = NAN;
+            return r->status;
+        }
+    }
+
+    /* Alg. 2, exponent preprocessing and exact bins: the bin of key k holds
+     * the components whose product has exponent k.  A zero product has no
+     * exponent; it is perforated (it contributes exactly nothing) and kept
+     * out of the bins, e_max, e_min and N_bins. */
+    int64_t *M = (int64_t *)calloc(ORC_W, sizeof(int64_t));
+    int32_t *key = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int pos_seen = 0, neg_seen = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (x[i] == 0.0 || y[i] == 0.0) {
+            key[i] = INT32_MIN;
+            r->n_zero++;
+            continue;
+        }
+        key[i] = orc_key(x[i], y[i], key_mode);
+        M[key[i] - ORC_KMIN]++;
+        if ((x[i] < 0.0) != (y[i] < 0.0)) neg_seen = 1;
+        else pos_seen = 1;
+    }
+    int32_t e_max = INT32_MIN, e_min = INT32_MAX, n_bins = 0;
+    for (int32_t k = ORC_KMIN; k <= ORC_KMAX; k++) {
+        if (M[k - ORC_KMIN] == 0) continue;
+        n_bins++;
+        if (k > e_max) e_max = k;
+        if (k < e_min) e_min = k;
+    }
+    if (hist_out) memcpy(hist_out, M, sizeof(int64_t) * ORC_W);
+    if (key_out)
+        for (int64_t i = 0; i < n; i++) key_out[i] = key[i];
+
+    if (n_bins == 0) { /* every product is zero: exact answer +0 */
+        r->value = 0.0;
+        r->count[ORC_PERF] = n;
+        r->flags = ORC_F_ALL_PERF | (guard_mode ? ORC_F_GUARANTEED : 0);
+        if (cls_out)
+            for (int64_t i = 0; i < n; i++) cls_out[i] = ORC_PERF;
+        free(M);
+        free(key);
+        return ORC_OK;
+    }
+    r->e_max = e_max;
+    r->e_min = e_min;
+    r->n_bins = n_bins;
+
+    /* floor(log2 eps), with eps divided by N_bins in the default score */
+    int32_t t = orc_t(score_mode == 0 ? n_bins : 1, tol);
+    r->t = t;
+
+    /* bin scores and precisions against e_max, then Alg. 1 */
+    uint8_t *C = (uint8_t *)malloc(ORC_W);
+    int32_t e_ref = e_max;
+    orc_select(M, e_max, e_min, e_ref, t, nonstrict, r->n_zero, C, r);
+    int kept = !(r->flags & ORC_F_ALL_PERF);
+    double S = orc_compute(x, y, n, key, C, e_max, e_ref + t + 22, accum_mode, cls_out, r);
+    r->passes = kept;
+
+    if (guard_mode) {
+        /* Guaranteed mode (Thm 3.4).  A certified lower bound of |x.y|
+         * gives E_lo <= flexp(x.y); if the Thm 3.4 bound with E_lo does not
+         * meet tol, the classes are selected again against E_lo (or made
+         * all double when |x.y| is not bounded away from 0) and Alg. 1 runs
+         * a second time. */
+        const int one_signed = !(pos_seen && neg_seen);
+        double low = orc_lower(M, C, e_max, S, n, one_signed);
+        if (orc_certified(r->bound_rel, low, tol)) {
+            r->flags |= ORC_F_GUARANTEED;
+        } else {
+            int32_t ref2 = low > 0.0 ? e_max + ilogb(low) : e_min - t - 22 - nonstrict;
+            if (ref2 < e_max) {
+                e_ref = ref2;
+                orc_select(M, e_max, e_min, e_ref, t, nonstrict, r->n_zero, C, r);
+                int kept2 = !(r->flags & ORC_F_ALL_PERF);
+                S = orc_compute(x, y, n, key, C, e_max, e_ref + t + 22, accum_mode, cls_out, r);
+                double low2 = orc_lower(M, C, e_max, S, n, one_signed);
+                if (low2 > low) low = low2;
+                r->flags |= ORC_F_RESELECTED;
+                if (orc_certified(r->bound_rel, low, tol)) r->flags |= ORC_F_GUARANTEED;
+                r->passes = kept + kept2;
+            }
+        }
+        r->lower = low > 0.0 ? ldexp(low, e_max) : 0.0;
+    }
+    r->e_ref = e_ref;
+
     free(C);
     free(M);
     free(key);

@@ -35,6 +35,8 @@ extern "C" {
 #define ORC_F_THM_ALL_DOUBLE 2 /* early-termination condition (Thm 3.6) holds */
 #define ORC_F_ALL_PERF 4     /* no component kept; value is +0 */
 #define ORC_F_OVERFLOW 8     /* final scaling overflowed */
+#define ORC_F_GUARANTEED 16  /* guaranteed mode: Thm 3.4 bound with a certified E_lo <= tol */
+#define ORC_F_RESELECTED 32  /* guaranteed mode: classes selected again, Alg. 1 repeated */
 
 /* status */
 #define ORC_OK 0
@@ -54,9 +56,13 @@ typedef struct {
     double bound_rig; /* rigorous absolute bound on |value - x.y| */
     int32_t flags;
     int32_t status;
+    double lower;     /* guaranteed mode: certified lower bound of |x.y| (0: none) */
+    int32_t e_ref;    /* exponent the scores were taken against */
+    int32_t passes;   /* Alg. 1 sweeps that kept a component (0, 1 or 2) */
 } orc_result;
 
-/* opt: NULL or 4 ints {key_mode, score_mode, boundary_mode, accum_mode}.
+/* opt: NULL or 5 ints {key_mode, score_mode, boundary_mode, accum_mode,
+ * guard_mode}; guard_mode 1 needs key_mode 0 and accum_mode 0.
  * cls (n bytes), keys (n int32; zero products get INT32_MIN) and hist
  * (ORC_W int64) are optional outputs. */
 int orc_qdot(const double *x, const double *y, int64_t n, double tol,

@@ -318,6 +318,163 @@ def test_golden_worked_examples(name):
     assert np.array_equal(r1["classes"], r["classes"])
     v1 = ex["value_s1"]
     assert Fraction(r1["value"]) == (F(v1) if isinstance(v1, str) else Fraction(v1))
+    # the guaranteed mode (Thm 3.4), where the example works it out
+    if "expect_guard" in case:
+        eg = case["expect_guard"]
+        rg = oracle.qdot(x, y, tol, opt=[0, 0, 0, 0, 1], want_classes=True)
+        assert rg["status"] == oracle.OK
+        for k in ("count", "flags", "e_ref", "passes"):
+            assert rg[k] == eg[k], k
+        assert rg["classes"].tolist() == eg["classes"]
+        assert Fraction(rg["value"]) == F(eg["value"])
+        assert Fraction(rg["bound_rel"]) == F(eg["bound_rel"])
+        lo, hi = (F(v) for v in eg["lower_in"])
+        assert lo < Fraction(rg["lower"]) <= hi
+
+
+# --------------------------------------------------------------------------
+# Guaranteed mode (Thm 3.4)
+# --------------------------------------------------------------------------
+GUARD = [0, 0, 0, 0, 1]
+
+
+def _exact_fraction(x, y) -> Fraction:
+    return sum((Fraction(a) * Fraction(b) for a, b in zip(x.tolist(), y.tolist())), Fraction(0))
+
+
+def _cancelling(n, seed, rel):
+    """Random products plus one component that cancels all but a relative
+    `rel` of their sum: e_max lies far above flexp(x.y)."""
+    g = np.random.default_rng(seed)
+    x = g.standard_normal(n) * 10.0 ** g.uniform(-3, 3, n)
+    y = g.standard_normal(n)
+    d = float(_exact_fraction(x[:-1], y[:-1]))
+    x[-1] = -d * (1.0 + rel * g.uniform(-1.0, 1.0))
+    y[-1] = 1.0
+    return x, y
+
+
+def test_guard_lower_bound_never_exceeds_the_exact_dot():
+    # L 2^e_max <= |x.y| against exact rational arithmetic: on the paper's
+    # law, on random-sign paper distribution B, and on cancelling sums
+    cases = []
+    for s in range(5):
+        cases.append(workloads.log_uniform_pair(300, 100 + s))
+        xb, yb = workloads.paper_dist_b(300, 9, 200 + s)
+        cases.append((xb * np.random.default_rng(s).choice([-1.0, 1.0], 300), yb))
+        cases.append(_cancelling(300, 300 + s, 1e-6))
+        cases.append(_cancelling(300, 400 + s, 1e-14))
+    reselected = 0
+    for x, y in cases:
+        ex = abs(_exact_fraction(x, y))
+        for tol in (1e-1, 1e-3, 1e-6, 1e-10):
+            r = oracle.qdot(x, y, tol, opt=GUARD)
+            assert r["status"] == oracle.OK
+            assert Fraction(r["lower"]) <= ex, (tol, r["lower"], float(ex))
+            reselected += bool(r["flags"] & oracle.F_RESELECTED)
+    assert reselected > 0
+
+
+def test_guard_certified_results_meet_tol():
+    # certified: the Thm 3.4 bound taken with the true E meets tol, and the
+    # observed relative error is within tol
+    certified = 0
+    for s in range(6):
+        for x, y in (workloads.log_uniform_pair(2000, 500 + s), _cancelling(2000, 600 + s, 1e-6)):
+            ex = oracle.dot_exact(x, y)
+            for tol in (1e-3, 1e-6, 1e-10):
+                r = oracle.qdot(x, y, tol, opt=GUARD)
+                if r["flags"] & oracle.F_GUARANTEED:
+                    certified += 1
+                    assert oracle.bound_thm34(r, ex)["bound_thm3_rel"] <= tol
+                    assert abs(r["value"] - ex) <= tol * abs(ex)
+    assert certified >= 24
+
+
+def test_guard_reselects_against_a_certified_exponent():
+    # sums cancelling to ~3e-4 of their size at tol 1e-4: the selection
+    # against e_max misses tol; L > 0, so the classes are selected again
+    # against E_lo = e_max + flexp(L) < e_max, and the result meets tol
+    by_elo = 0
+    for s in range(12):
+        x, y = _cancelling(2000, 700 + s, 3e-4)
+        ex = oracle.dot_exact(x, y)
+        r0 = oracle.qdot(x, y, 1e-4)
+        rg = oracle.qdot(x, y, 1e-4, opt=GUARD)
+        assert abs(r0["value"] - ex) > 1e-4 * abs(ex)
+        assert rg["flags"] & oracle.F_RESELECTED and rg["flags"] & oracle.F_GUARANTEED
+        assert rg["passes"] == 2 and rg["e_ref"] < rg["e_max"]
+        assert abs(rg["value"] - ex) <= 1e-4 * abs(ex)
+        # E_lo is a certified lower bound of flexp(x.y)
+        assert rg["e_ref"] <= math.frexp(abs(ex))[1] - 1
+        if rg["e_ref"] > rg["e_min"] - rg["t"] - 22 and not rg["flags"] & oracle.F_UNATTAINABLE:
+            by_elo += 1
+            # Thm 3.5 against the reference: sum_k M_k 2^(k-e_ref+1) eps(k) <= N_bins 2^t
+            assert (math.ldexp(rg["bound_rel"], rg["e_max"] - rg["e_ref"])
+                    <= rg["n_bins"] * 2.0 ** rg["t"])
+    assert by_elo >= 8
+
+
+def test_guard_makes_every_bin_double_when_the_sum_may_vanish():
+    # sums cancelling to 1e-6 of their size at tol 1e-3: after the first
+    # sweep |x.y| is not bounded away from 0 (L <= 0), so the reselection
+    # makes every bin double (e_ref = e_min - t - 22) and the result meets tol
+    for s in range(5):
+        x, y = _cancelling(2000, 720 + s, 1e-6)
+        ex = oracle.dot_exact(x, y)
+        r0 = oracle.qdot(x, y, 1e-3)
+        rg = oracle.qdot(x, y, 1e-3, opt=GUARD)
+        assert abs(r0["value"] - ex) > 1e-3 * abs(ex)
+        assert rg["e_ref"] == rg["e_min"] - rg["t"] - 22
+        assert rg["count"][oracle.DOUBLE] == len(x) - rg["n_zero"]
+        assert rg["flags"] & oracle.F_RESELECTED and rg["flags"] & oracle.F_GUARANTEED
+        assert abs(rg["value"] - ex) <= 1e-3 * abs(ex)
+
+
+def test_guard_one_signed_products_certify_in_one_sweep():
+    # one sign: |x.y| >= max |x_i y_i| >= 2^e_max (the Thm 3.3 hypothesis),
+    # so the first selection is certified and nothing else changes
+    for s in range(3):
+        x = workloads.normal_vector(3000, 800 + s)
+        z = np.abs(workloads.normal_vector(3000, 900 + s)) * np.sign(x)
+        for y, tol in ((x, 1e-6), (z, 1e-10), (-z, 1e-3)):
+            r0 = oracle.qdot(x, y, tol, want_classes=True)
+            rg = oracle.qdot(x, y, tol, opt=GUARD, want_classes=True)
+            assert rg["flags"] == r0["flags"] | oracle.F_GUARANTEED
+            assert rg["passes"] == 1 and rg["e_ref"] == rg["e_max"]
+            assert rg["value"] == r0["value"]
+            assert np.array_equal(rg["classes"], r0["classes"])
+            assert rg["lower"] >= 2.0 ** rg["e_max"]
+    # where the rule decides: x = (1, 0.5), y = (1, 1), tol 4.  N_bins = 2,
+    # t = floor(log2 2) = 1; scores 0+0-0-1+1 = 0 (half) and 0-1-0-1+1 = -1
+    # (perforate).  The sweep gives S = 1 while the error bound holds the
+    # whole perforated 0.5 (a > 1), so |S| - a < 0; one sign lifts L to 1,
+    # E_lo = e_max, and bound_rel = 2*2^-10 + 1 <= 4 certifies one sweep
+    r = oracle.qdot(np.array([1.0, 0.5]), np.ones(2), 4.0, opt=GUARD, want_classes=True)
+    assert r["value"] == 1.0 and r["passes"] == 1 and r["e_ref"] == 0 and r["t"] == 1
+    assert r["classes"].tolist() == [oracle.HALF, oracle.PERF]
+    assert r["flags"] == oracle.F_GUARANTEED and r["lower"] == 1.0
+
+
+def test_guard_edge_cases():
+    for n in (0, 7):  # nothing to sum: +0 is exact
+        r = oracle.qdot(np.zeros(n), np.ones(n), 1e-6, opt=GUARD)
+        assert r["status"] == oracle.OK and r["value"] == 0.0
+        assert r["flags"] == oracle.F_ALL_PERF | oracle.F_GUARANTEED and r["passes"] == 0
+    x = np.array([1.0, -0.5])
+    y = np.ones(2)
+    assert oracle.qdot(x, y, 1e-6, opt=[1, 0, 0, 0, 1])["status"] == oracle.E_INVAL
+    assert oracle.qdot(x, y, 1e-6, opt=[0, 0, 0, 1, 1])["status"] == oracle.E_INVAL
+    assert oracle.qdot(np.array([np.inf]), np.ones(1), 1e-6, opt=GUARD)["status"] == oracle.E_NONFINITE
+    # tol 100 perforates both products (t = 5: scores -4, -5); mixed signs
+    # leave |x.y| unbounded from below, so every bin becomes double
+    # (e_ref = e_min - t - 22 = -28) and the exact 0.5 comes back
+    r0 = oracle.qdot(x, y, 100.0)
+    assert r0["value"] == 0.0 and r0["passes"] == 0 and r0["flags"] & oracle.F_ALL_PERF
+    r = oracle.qdot(x, y, 100.0, opt=GUARD, want_classes=True)
+    assert r["value"] == 0.5 and r["e_ref"] == -28 and r["passes"] == 1
+    assert r["classes"].tolist() == [oracle.DOUBLE, oracle.DOUBLE]
+    assert r["flags"] == oracle.F_RESELECTED | oracle.F_GUARANTEED
 
 
 # --------------------------------------------------------------------------
