@@ -71,6 +71,11 @@ extern "C" {
                                   holds: every bin is double */
 #define QDOT_F_ALL_PERF 4      /* no component kept; value is +0 */
 #define QDOT_F_OVERFLOW 8      /* the final scaling by 2^e_max overflowed */
+#define QDOT_F_GUARANTEED 16   /* guard_mode 1: the Thm 3.4 bound, taken with
+                                  a certified lower bound of |x.y| in place
+                                  of 2^E, is <= eps (see guard_mode) */
+#define QDOT_F_RESELECTED 32   /* guard_mode 1: the classes were selected a
+                                  second time and pass 2 was repeated */
 
 /* ---- options --------------------------------------------------------- */
 /* Zero-initialised = defaults. */
@@ -99,6 +104,34 @@ typedef struct qdot_options {
      *    >= about 1e-60 at n = 2^27); QDOT_E_INVAL otherwise and in
      *    qdot_classes_async and qdot_cg. */
     int32_t accum_mode;
+    /* 0: the classes are selected once, against e_max (Alg. 2); the
+     *    relative bound of Thm 3.3 then needs e_max <= flexp(x.y).
+     * 1: guaranteed-eps mode (Thm 3.4, for data whose products cancel).
+     *    After pass 2 the library bounds |x.y| from below by
+     *      L = |S| (1 - 2^-52) - a            (units of 2^e_max)
+     *    where S is the computed sum and a bounds every error of the call
+     *    from the histogram and the classes alone:
+     *      a = (Q + T + F) (1 + 2^-40),
+     *      Q = sum_k M_k 2^(k-e_max+1) rho(class_k)  (quantisation; rho =
+     *          2^-53, 3 2^-24 + 3 2^-48 + 2^-72, 2^-10 + 2^-22, 1 for
+     *          double, single, half, perforated),
+     *      T = g6 (1 + 2^-9) sum_{single, half bins} M_k 2^(k-e_max+1)
+     *          (FP32 tile trees, g6 = 6u/(1-6u), u = 2^-24),
+     *      F = 2^-52 |S| + 4 gn^2 (1 + 2^-8) sum_{kept bins} M_k 2^(k-e_max+1)
+     *          + (2n + 4) 2^-1074  (FP64 stage and leaves scaled into
+     *          the subnormal range, gn = n 2^-53 / (1 - n 2^-53)).
+     *    When every non-zero product has the same sign, L is raised to
+     *    1 (|x.y| >= max |x_i y_i| >= 2^e_max).  With E_lo = flexp(L) +
+     *    e_max <= flexp(x.y), the call is certified (QDOT_F_GUARANTEED)
+     *    when L > 0 and bound_rel 2^(e_max - E_lo) <= eps.  Otherwise the
+     *    classes are selected again with the reference exponent e_ref =
+     *    E_lo in place of e_max in the score (L > 0), or with e_ref =
+     *    e_min - t - 22 - boundary_mode, which makes every bin double
+     *    (L <= 0), pass 2 runs again (QDOT_F_RESELECTED) and the check is
+     *    repeated with the larger of the two lower bounds.  Needs key_mode
+     *    0 and accum_mode 0; accepted by qdot_async, qdot,
+     *    qdot_classes_async and qdot_power, QDOT_E_INVAL elsewhere. */
+    int32_t guard_mode;
 } qdot_options;
 
 /* ---- per-call result ------------------------------------------------- */
@@ -116,6 +149,15 @@ typedef struct qdot_result {
     double bound_abs;    /* 2^e_max * bound_rel (Thm 3.2 absolute bound) */
     int32_t flags;       /* QDOT_F_* */
     int32_t status;      /* QDOT_OK or QDOT_E_NONFINITE */
+    double lower;        /* guard_mode 1: certified lower bound L 2^e_max
+                            of |x.y| (0 when none is known; rounded to FP64,
+                            exact unless subnormal); 0 otherwise */
+    int32_t e_ref;       /* exponent the scores were taken against: e_max,
+                            or the guard_mode 1 reselection's reference */
+    int32_t passes;      /* sweeps over x, y that accumulated kept
+                            components: 1 (pass 2, or the one-pass mode's
+                            single sweep), 2 after a guard_mode 1
+                            reselection, 0 when nothing was kept */
 } qdot_result;
 
 /* ---- CSR matrix (device arrays, host struct) -------------------------- */
@@ -213,8 +255,9 @@ QDOT_API int32_t qdot_timing_read(qdot_handle *h, double ms[5], int32_t calls[2]
  *   opt  : NULL for defaults.
  *   dev_out : device pointer to one qdot_result, written in stream order.
  * n == 0 or all-zero products give value +0 with QDOT_F_ALL_PERF.
- * Enqueues three kernels; performs no allocation and no host sync, so it
- * may be captured in a HIP graph. */
+ * Enqueues four kernels (eight with guard_mode 1, whose second pass-2
+ * kernels return at once when no reselection is needed); performs no
+ * allocation and no host sync, so it may be captured in a HIP graph. */
 QDOT_API int32_t qdot_async(qdot_handle *h, const double *x, const double *y,
                    int64_t n, double tol, const qdot_options *opt,
                    void *stream, qdot_result *dev_out);

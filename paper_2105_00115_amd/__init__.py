@@ -24,13 +24,15 @@ LIB_PATH = os.path.join(PKG, "libqdot.so")
 OK, E_INVAL, E_NONFINITE, E_DEVICE, E_NOMEM, E_BREAKDOWN, E_MAXIT = range(7)
 DOUBLE, SINGLE, HALF, PERF = 0, 1, 2, 3
 F_UNATTAINABLE, F_THM_ALL_DOUBLE, F_ALL_PERF, F_OVERFLOW = 1, 2, 4, 8
+F_GUARANTEED, F_RESELECTED = 16, 32
 KMIN, KMAX = -2148, 2047
 W = KMAX - KMIN + 1
 
 
 class QdotOptions(C.Structure):
     _fields_ = [("key_mode", C.c_int32), ("score_mode", C.c_int32),
-                ("boundary_mode", C.c_int32), ("accum_mode", C.c_int32)]
+                ("boundary_mode", C.c_int32), ("accum_mode", C.c_int32),
+                ("guard_mode", C.c_int32)]
 
 
 class QdotResult(C.Structure):
@@ -47,6 +49,9 @@ class QdotResult(C.Structure):
         ("bound_abs", C.c_double),
         ("flags", C.c_int32),
         ("status", C.c_int32),
+        ("lower", C.c_double),
+        ("e_ref", C.c_int32),
+        ("passes", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -55,6 +60,7 @@ class QdotResult(C.Structure):
             "e_min": self.e_min, "e_max": self.e_max, "n_bins": self.n_bins,
             "t": self.t, "part": list(self.part), "bound_rel": self.bound_rel,
             "bound_abs": self.bound_abs, "flags": self.flags, "status": self.status,
+            "lower": self.lower, "e_ref": self.e_ref, "passes": self.passes,
         }
 
 

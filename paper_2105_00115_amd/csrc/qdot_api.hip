@@ -80,9 +80,12 @@ hipEvent_t *take_events(qdot_handle *h, int kind)
 
 bool options_ok(const qdot_options &o)
 {
+    // the guaranteed mode bins on the exponent of the product (the theorems'
+    // bins) and repeats pass 2, so it needs key_mode 0 and accum_mode 0
     return (o.key_mode == 0 || o.key_mode == 1) && (o.score_mode == 0 || o.score_mode == 1) &&
            (o.boundary_mode == 0 || o.boundary_mode == 1) &&
-           (o.accum_mode == 0 || o.accum_mode == 1);
+           (o.accum_mode == 0 || o.accum_mode == 1) &&
+           (o.guard_mode == 0 || (o.guard_mode == 1 && o.key_mode == 0 && o.accum_mode == 0));
 }
 
 static int ceil_log2_host(int64_t v)

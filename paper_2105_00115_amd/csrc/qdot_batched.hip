@@ -61,8 +61,7 @@ struct BLarge {
     unsigned long long n_zero;
     unsigned int bad;
     int first_slot;
-    int e_max, t, c32, skip, flags;
-    int pad;
+    int e_max, c32, skip, flags;
 };
 
 struct BState {
@@ -164,6 +163,9 @@ __device__ __forceinline__ void write_invalid(qdot_result *o)
     o->bound_rel = o->bound_abs = 0.0;
     o->flags = 0;
     o->status = QDOT_E_INVAL;
+    o->lower = 0.0;
+    o->e_ref = 0;
+    o->passes = 0;
 }
 
 // One-pass chunk of a large instance: scan with the block's candidate-sum
@@ -388,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                 Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
                 accumulate_range(xi, yi, 0, GROUP, n, vec, key_mode, lut, p.e_max, p.c32, a);
                 block_reduce3<BLOCK>(a, red);
-                if (tid == 0) combine_value(a, p.e_max, p.t, p.c32, p.flags, out + inst);
+                if (tid == 0) combine_value(a, p.e_max, p.c32, p.flags, out + inst);
             }
             __syncthreads();
           }
@@ -469,13 +471,15 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                     o->bound_rel = s_res.bound_rel;
                     o->bound_abs = s_res.bound_abs;
                     o->status = s_res.status;
+                    o->lower = s_res.lower;
+                    o->e_ref = s_res.e_ref;
+                    o->passes = s_res.passes;
                     if (p.skip) {
                         o->value = s_res.value;
                         for (int q = 0; q < 3; q++) o->part[q] = s_res.part[q];
                         o->flags = s_res.flags;
                     }
                     st_dev(&L->e_max, p.e_max);
-                    st_dev(&L->t, p.t);
                     st_dev(&L->c32, p.c32);
                     st_dev(&L->skip, p.skip);
                     st_dev(&L->flags, p.flags);
@@ -494,11 +498,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                 while (ld_dev(&L->ready) == 0u) __builtin_amdgcn_s_sleep(2);
                 s_prm2 = make_int4(ld_dev(&L->skip), ld_dev(&L->e_max), ld_dev(&L->c32),
                                    ld_dev(&L->flags));
-                s_flag = ld_dev(&L->t);
             }
             __syncthreads();
             const int skip = s_prm2.x, e_max = s_prm2.y, c32 = s_prm2.z, flags = s_prm2.w;
-            const int t = s_flag;
             __syncthreads();
             if (!skip) {
                 const unsigned int *src =
@@ -536,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                             a[q] = acc_merge(a[q], Acc{ld_dev(&p[2 * q]), ld_dev(&p[2 * q + 1])});
                     }
                     block_reduce3<BLOCK>(a, red);
-                    if (tid == 0) combine_value(a, e_max, t, c32, flags, out + I.inst);
+                    if (tid == 0) combine_value(a, e_max, c32, flags, out + I.inst);
                 }
                 if (tid == 0) {
                     st_dev(&L->p1_done, 0u);
@@ -800,6 +802,7 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (o.guard_mode != 0) return fail(h, QDOT_E_INVAL, "the batched launch needs guard_mode 0");
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
     const int accum = B > 0 ? o.accum_mode : 0;  // CG systems always use the default reading
@@ -850,6 +853,7 @@ int32_t qdot_batch_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (o.guard_mode != 0) return fail(h, QDOT_E_INVAL, "the batched launch needs guard_mode 0");
     if (B == 0 && S == 0) return QDOT_OK;
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;

@@ -232,12 +232,15 @@ struct CutParams {
 // of slot j, clear(j) resets it after use, put(j, cls) stores the class of
 // slot j.  Writes every field of *out except value and part (which the
 // combine writes) unless nothing is to be accumulated, in which case *out is
-// final.  Returns the parameters of pass 2 to every thread.
+// final.  Returns the parameters of pass 2 to every thread.  The scores are
+// taken against e_ref = e_max - dref (dref > 0 only when the guaranteed mode
+// reselects against a lower estimate of flexp(x.y), Thm 3.4); bound_rel
+// stays the Thm 3.3 sum relative to e_max.
 template <int NT, class Get, class Put, class Clear>
 __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsigned int bad,
                                   int64_t n, double tol, int score_mode, int nonstrict,
                                   Get get, Put put, Clear clear, qdot_result *out,
-                                  long long *hist_out)
+                                  long long *hist_out, int dref = 0)
 {
     constexpr int NW = NT / 64;
     __shared__ int s_max[NW], s_min[NW], s_nb[NW], s_unatt[NW];
@@ -286,6 +289,9 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
         out->n_bins = c;
         out->e_max = c ? a : 0;
         out->e_min = c ? b : 0;
+        out->e_ref = c ? a - dref : 0;
+        out->lower = 0.0;
+        out->passes = 0;
         for (int q = 0; q < 3; q++) out->part[q] = 0.0;
         int go = 1, t = 0;
         const bool tol_ok = tol > 0.0 && !__builtin_isinf(tol) && !__builtin_isnan(tol);
@@ -313,14 +319,14 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
         }
         s_prm.e_max = a;
         s_prm.t = t;
-        s_prm.c32 = a + t + 22;
+        s_prm.c32 = a - dref + t + 22;
         s_prm.skip = 1;
         s_prm.flags = 0;
         s_go = go;
     }
     __syncthreads();
     const int go = s_go;
-    const int e_max = s_prm.e_max, t = s_prm.t;
+    const int e_max = s_prm.e_max, t = s_prm.t, e_ref = e_max - dref;
 
     unsigned long long cc[4] = {0, 0, 0, 0};
     double bound = 0.0;
@@ -331,7 +337,7 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
         if (go && v) {
             const int k = j + KMIN;
             // eq. (bin-score-def) with exact bins (u_k = k)
-            const int sigma = ceil_log2_u64(v) + k - e_max - t + 1;
+            const int sigma = ceil_log2_u64(v) + k - e_ref - t + 1;
             cls = class_of(sigma, nonstrict);
             unatt |= sigma >= 52 + (nonstrict ? 1 : 0);
             cc[cls] += v;
@@ -368,9 +374,10 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
         out->bound_rel = bsum;
         out->bound_abs = ldexp(bsum, e_max);
         int flags = ua ? QDOT_F_UNATTAINABLE : 0;
-        // Thm 3.6: e_max - e_min <= -t - m_single
-        if ((long long)e_max - out->e_min <= -(long long)t - 23) flags |= QDOT_F_THM_ALL_DOUBLE;
+        // Thm 3.6: e_ref - e_min <= -t - m_single
+        if ((long long)e_ref - out->e_min <= -(long long)t - 23) flags |= QDOT_F_THM_ALL_DOUBLE;
         const bool none_kept = (tc[0] + tc[1] + tc[2]) == 0;
+        out->passes = none_kept ? 0 : 1;
         if (none_kept) {
             flags |= QDOT_F_ALL_PERF;
             out->value = 0.0;
@@ -663,14 +670,17 @@ __device__ __forceinline__ void s1_pick(int e_max, int lo, int flags, const unsi
     }
 }
 
-// value = 2^e_max (D + 2^(c32 - e_max) (S + H)), parts, overflow flag.
-__device__ __forceinline__ void combine_value(const Acc f[3], int e_max, int t, int c32,
-                                              int flags, qdot_result *out)
+// value = 2^e_max (D + 2^(c32 - e_max) (S + H)), parts, overflow flag;
+// returns the FP64 sum D + 2^(c32 - e_max) (S + H) before the scaling.
+__device__ __forceinline__ double combine_value(const Acc f[3], int e_max, int c32, int flags,
+                                                qdot_result *out)
 {
+    // FP32-class sums are in units of 2^c32, the total in units of 2^e_max
+    const int sh = c32 - e_max;
     Acc tot = f[0];
-    acc_add(tot, ldexp(f[1].s, t + 22));
-    acc_add(tot, ldexp(f[2].s, t + 22));
-    tot.c = tot.c + ldexp(f[1].c + f[2].c, t + 22);
+    acc_add(tot, ldexp(f[1].s, sh));
+    acc_add(tot, ldexp(f[2].s, sh));
+    tot.c = tot.c + ldexp(f[1].c + f[2].c, sh);
     const double S = tot.s + tot.c;
     const double value = ldexp(S, e_max);
     out->value = value;
@@ -678,6 +688,7 @@ __device__ __forceinline__ void combine_value(const Acc f[3], int e_max, int t, 
     out->part[QDOT_SINGLE] = ldexp(f[1].s + f[1].c, c32);
     out->part[QDOT_HALF] = ldexp(f[2].s + f[2].c, c32);
     out->flags = flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
+    return S;
 }
 
 }  // namespace qd

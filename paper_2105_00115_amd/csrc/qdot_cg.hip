@@ -112,7 +112,8 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
-    if (o.accum_mode != 0) return fail(h, QDOT_E_INVAL, "the batched and CG launches need accum_mode 0");
+    if (o.accum_mode != 0 || o.guard_mode != 0)
+        return fail(h, QDOT_E_INVAL, "the CG launch needs accum_mode 0 and guard_mode 0");
     if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
     DeviceGuard g(h->device);

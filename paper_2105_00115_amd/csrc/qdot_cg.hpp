@@ -245,7 +245,7 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
                 acc[q] = acc_merge(acc[q], Acc{ld_dev(&pp[2 * q]), ld_dev(&pp[2 * q + 1])});
         }
         block_reduce3<BLOCK>(acc, L.red);
-        if (threadIdx.x == 0) combine_value(acc, p.e_max, p.t, p.c32, p.flags, &L.res);
+        if (threadIdx.x == 0) combine_value(acc, p.e_max, p.c32, p.flags, &L.res);
     }
     __syncthreads();
     o.value = L.res.value;

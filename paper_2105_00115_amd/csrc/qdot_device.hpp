@@ -45,8 +45,16 @@ struct Ws {
     int c32;                     // exponent offset of FP32 leaves
     int skip;                    // nothing to accumulate (result final)
     int flags;                   // result flags known after selection
-    int s1_lo, s1_hi;            // live slot range of the last scan (one-pass mode)
+    int s1_lo, s1_hi;            // live slot range of the last scan
     int pad1;
+    // per scan block: bit 0 = a negative, bit 1 = a positive non-zero product
+    unsigned int block_signs[MAX_GRID];
+    // guaranteed mode (guard_mode 1)
+    long long hsave[W];          // the histogram, kept for the reselection
+    double s_last;               // S of the last two-pass combine (units of 2^e_max)
+    double g_low;                // lower bound of |x.y| after the first sweep (same units)
+    unsigned int signs;          // OR of block_signs over the last scan
+    int g_redo;                  // the reselection ran
     unsigned char lut[W_LUT];    // class of every key slot (+ zero slot)
 };
 

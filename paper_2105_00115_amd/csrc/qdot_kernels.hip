@@ -32,7 +32,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
     for (int i = threadIdx.x; i < W + 1; i += BLOCK) h[i] = 0;
     __syncthreads();
 
-    unsigned int nz = 0, bad = 0;
+    unsigned int nz = 0, bad = 0, sg = 0;
     stream_groups<VEC, U>(x, y, n, [&](const double *xv, const double *yv, int64_t, int lim) {
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -40,6 +40,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
             const bool valid = e < lim;
             nz += (valid & c.zero) ? 1u : 0u;
             bad |= (valid & c.bad) ? 1u : 0u;
+            sg |= (valid & !c.zero) ? (c.sgn ? 1u : 2u) : 0u;
             // zero and non-finite products land in the spare slot W
             if (valid) atomicAdd(&h[c.slot], 1u);
         }
@@ -61,19 +62,27 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
     for (int m = 32; m >= 1; m >>= 1) {
         lo = min(lo, __shfl_xor(lo, m, 64));
         hi = max(hi, __shfl_xor(hi, m, 64));
+        sg |= __shfl_xor(sg, m, 64);
     }
     __shared__ int2 wr[BLOCK / 64];
+    __shared__ unsigned int wsg[BLOCK / 64];
     if ((threadIdx.x & 63) == 0) {
         if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
         if (bad) atomicOr(&ws->nonfinite, 1u);
         wr[threadIdx.x >> 6] = make_int2(lo, hi);
+        wsg[threadIdx.x >> 6] = sg;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        // plain store, no contention: the cutoff kernel reduces the records
+        // plain stores, no contention: the cutoff kernel reduces the records
         int2 r = wr[0];
-        for (int w = 1; w < BLOCK / 64; w++) r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
+        unsigned int g = wsg[0];
+        for (int w = 1; w < BLOCK / 64; w++) {
+            r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
+            g |= wsg[w];
+        }
         ws->block_range[blockIdx.x] = r;
+        ws->block_signs[blockIdx.x] = g;
     }
 }
 
@@ -83,36 +92,43 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double tol,
                                                      int score_mode, int nonstrict,
-                                                     int64_t n, int nscan,
+                                                     int64_t n, int nscan, int guard,
                                                      qdot_result *__restrict__ out,
                                                      long long *__restrict__ hist_out)
 {
     constexpr int NW = CUT_THREADS / 64;
     __shared__ int s_lo[NW], s_hi[NW];
+    __shared__ unsigned int s_sg[NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // only the slot window pass 1 touched holds counts; slots outside it are
     // zero in every copy and their class-table entries are never read
     int lo = W, hi = -1;
+    unsigned int sg = 0;
     {
         int a = W, b = -1;
+        unsigned int g = 0;
         for (int i = tid; i < nscan; i += CUT_THREADS) {
             const int2 r = ws->block_range[i];
             a = min(a, r.x);
             b = max(b, r.y);
+            if (guard) g |= ws->block_signs[i];
         }
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) {
             a = min(a, __shfl_xor(a, m, 64));
             b = max(b, __shfl_xor(b, m, 64));
+            g |= __shfl_xor(g, m, 64);
         }
         if (lane == 0) {
             s_lo[wv] = a;
             s_hi[wv] = b;
+            s_sg[wv] = g;
         }
         __syncthreads();
         for (int w = 0; w < NW; w++) {
             lo = min(lo, s_lo[w]);
             hi = max(hi, s_hi[w]);
+            sg |= s_sg[w];
         }
     }
     const unsigned long long nzero = ws->n_zero;
@@ -141,6 +157,7 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
         ws->skip = p.skip;
         ws->s1_lo = lo;
         ws->s1_hi = hi;
+        ws->signs = sg;
     }
 }
 
@@ -210,7 +227,7 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
 }
 
 // Combine the per-block partials of k_acc in a fixed order (one block).
-__global__ __launch_bounds__(BLOCK) void k_fin(const Ws *__restrict__ ws,
+__global__ __launch_bounds__(BLOCK) void k_fin(Ws *__restrict__ ws,
                                                const double *__restrict__ partials, int nblk,
                                                qdot_result *__restrict__ out)
 {
@@ -232,7 +249,165 @@ __global__ __launch_bounds__(BLOCK) void k_fin(const Ws *__restrict__ ws,
             f[q] = red[q][0];
             for (int w = 1; w < BLOCK / 64; w++) f[q] = acc_merge(f[q], red[q][w]);
         }
-        combine_value(f, ws->e_max, ws->t, ws->c32, ws->flags, out);
+        ws->s_last = combine_value(f, ws->e_max, ws->c32, ws->flags, out);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Guaranteed mode (guard_mode 1, Thm 3.4).  After a sweep of pass 2 the sum
+// S (units of 2^e_max) and a bound a of every error of the call, evaluated
+// from the histogram and the classes alone,
+//   a = (Q + T + F)(1 + 2^-40),
+//   Q = sum_k M_k 2^(k-e_max+1) rho(class_k)                  quantisation
+//   T = g6 (1 + 2^-9) sum_{single, half bins} M_k 2^(k-e_max+1)  FP32 trees
+//   F = 2^-52 |S| + 4 gn^2 (1 + 2^-8) sum_{kept bins} M_k 2^(k-e_max+1)
+//       + (2n + 4) 2^-1074                  FP64 stage, subnormal scaling
+// give the lower bound L = |S| (1 - 2^-52) - a of |x.y|, raised to 1 when
+// every non-zero product has one sign (|x.y| >= max |x_i y_i| >= 2^e_max).
+// When L > 0, E_lo = e_max + flexp(L) <= flexp(x.y), and the call is
+// certified when bound_rel 2^(e_max - E_lo) <= eps.
+// Stage 0 (after the first sweep): certify, or reselect against E_lo (or
+// make every bin double when L <= 0) so that the second sweep of k_acc and
+// k_fin runs.  Stage 1 (after the second sweep; returns unless it ran):
+// check again with the larger of the two lower bounds.
+// One workgroup of CUT_THREADS threads.
+// ---------------------------------------------------------------------------
+struct GuardSums {
+    double q, f32, kept;
+};
+
+__device__ __forceinline__ double guard_rho(int c)
+{
+    // largest relative error of one leaf of each class
+    return c == QDOT_DOUBLE ? 0x1p-53
+         : c == QDOT_SINGLE ? 0x1.8p-23 + 0x1.8p-47 + 0x1p-72  // (1+2^-24)^3 - 1
+         : c == QDOT_HALF   ? 0x1p-10 + 0x1p-22                // (1+2^-11)^2 - 1
+                            : 1.0;
+}
+
+template <int NT>
+__device__ GuardSums guard_sums(const long long *__restrict__ hs,
+                                const unsigned char *__restrict__ lut, int lo, int hi, int e_max)
+{
+    constexpr int NW = NT / 64;
+    __shared__ double s_v[3][NW];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int j = lo + tid; j <= hi; j += NT) {
+        const long long m = hs[j];
+        if (m == 0) continue;
+        const int e = j + KMIN - e_max + 1;
+        const int c = lut[j];
+        const double w = ldexp((double)m, e);
+        v[0] += ldexp((double)m * guard_rho(c), e);
+        v[1] += (c == QDOT_SINGLE || c == QDOT_HALF) ? w : 0.0;
+        v[2] += c != QDOT_PERF ? w : 0.0;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        for (int q = 0; q < 3; q++) v[q] += __shfl_xor(v[q], m, 64);
+    if (lane == 0)
+        for (int q = 0; q < 3; q++) s_v[q][wv] = v[q];
+    __syncthreads();
+    GuardSums g = {0.0, 0.0, 0.0};
+    for (int w = 0; w < NW; w++) {
+        g.q += s_v[0][w];
+        g.f32 += s_v[1][w];
+        g.kept += s_v[2][w];
+    }
+    __syncthreads();
+    return g;
+}
+
+__device__ __forceinline__ double guard_lower(const GuardSums &g, double S, int64_t n,
+                                              unsigned int signs)
+{
+    const double g6 = 6.0 * 0x1p-24 / (1.0 - 6.0 * 0x1p-24);
+    const double nu = (double)n * 0x1p-53;
+    const double gn = nu / (1.0 - nu);
+    const double F = 0x1p-52 * fabs(S) + 4.0 * gn * gn * (1.0 + 0x1p-8) * g.kept +
+                     (2.0 * (double)n + 4.0) * 0x1p-1074;
+    const double a = (g.q + g6 * (1.0 + 0x1p-9) * g.f32 + F) * (1.0 + 0x1p-40);
+    double low = fabs(S) * (1.0 - 0x1p-52) - a;
+    if (signs != 3u && low < 1.0) low = 1.0;  // one sign: |x.y| >= 2^e_max
+    return low;
+}
+
+__device__ __forceinline__ bool guard_certified(double bound_rel, double low, double tol)
+{
+    return low > 0.0 && ldexp(bound_rel, -ilogb(low)) <= tol;
+}
+
+__global__ __launch_bounds__(CUT_THREADS) void k_guard(Ws *__restrict__ ws,
+                                                       const long long *__restrict__ hs,
+                                                       double tol, int score_mode, int nonstrict,
+                                                       int64_t n, int stage,
+                                                       qdot_result *__restrict__ out)
+{
+    __shared__ int s_go, s_dref, s_passes;
+    __shared__ unsigned long long s_nz;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int go;
+        if (stage == 0) {
+            ws->g_redo = 0;
+            go = out->status == QDOT_OK && out->n_bins > 0;
+            // every product zero: +0 is exact
+            if (out->status == QDOT_OK && out->n_bins == 0) out->flags |= QDOT_F_GUARANTEED;
+        } else {
+            go = ws->g_redo;
+        }
+        s_go = go;
+        s_dref = 0;
+        s_passes = out->passes;
+        s_nz = (unsigned long long)out->n_zero;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const int e_max = out->e_max;
+    const int lo = ws->s1_lo, hi = ws->s1_hi;
+    const GuardSums g = guard_sums<CUT_THREADS>(hs, ws->lut, lo, hi, e_max);
+    if (tid == 0) {
+        const double S = ws->skip ? 0.0 : ws->s_last;
+        double low = guard_lower(g, S, n, ws->signs);
+        if (stage == 0) {
+            if (guard_certified(out->bound_rel, low, tol)) {
+                out->flags |= QDOT_F_GUARANTEED;
+                out->lower = ldexp(low, e_max);
+                ws->skip = 1;
+            } else {
+                const int ref = low > 0.0 ? e_max + ilogb(low)
+                                          : out->e_min - out->t - 22 - nonstrict;
+                if (ref < e_max) {
+                    s_dref = e_max - ref;
+                    ws->g_low = low;
+                    ws->g_redo = 1;
+                } else {
+                    out->lower = low > 0.0 ? ldexp(low, e_max) : 0.0;
+                    ws->skip = 1;
+                }
+            }
+        } else {
+            low = fmax(low, ws->g_low);
+            out->flags |= QDOT_F_RESELECTED |
+                          (guard_certified(out->bound_rel, low, tol) ? QDOT_F_GUARANTEED : 0);
+            out->lower = low > 0.0 ? ldexp(low, e_max) : 0.0;
+        }
+    }
+    __syncthreads();
+    if (s_dref == 0) return;
+    // stage 0 reselection: scores against e_ref = e_max - dref
+    auto get = [&](int j) { return (unsigned long long)hs[j]; };
+    auto put = [&](int j, int cls) { ws->lut[j] = (unsigned char)cls; };
+    auto clear = [](int) {};
+    const CutParams p = block_cutoff<CUT_THREADS>(lo, hi, s_nz, 0u, n, tol, score_mode, nonstrict,
+                                                  get, put, clear, out, nullptr, s_dref);
+    if (tid == 0) {
+        ws->c32 = p.c32;
+        ws->flags = p.flags | QDOT_F_RESELECTED;
+        ws->skip = p.skip;
+        out->flags |= QDOT_F_RESELECTED;
+        out->passes = s_passes + (p.skip ? 0 : 1);
     }
 }
 
@@ -475,7 +650,7 @@ static hipError_t launch_qdot_s1(const Launch &L, const double *x, const double 
                           : launch_s1<false>(L, x, y, n, o.key_mode, depth);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
     hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, nscan, out, nullptr);
+                       o.boundary_mode, n, nscan, 0, out, nullptr);
     if (L.ev) {
         (void)hipEventRecord(L.ev[2], s);
         (void)hipEventRecord(L.ev[3], s);
@@ -491,23 +666,42 @@ hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_
 {
     if (o.accum_mode == 1) return launch_qdot_s1(L, x, y, n, tol, o, out);
     const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
+    const int guard = o.guard_mode;
+    // the guaranteed mode keeps the histogram for its reselection
+    long long *hs = hist_out;
+    if (guard && !hs)
+        hs = reinterpret_cast<long long *>(reinterpret_cast<char *>(L.ws) + offsetof(Ws, hsave));
     hipStream_t s = L.stream;
     if (L.ev) (void)hipEventRecord(L.ev[0], s);
     const int nscan = vec ? launch_scan<true>(L, x, y, n, o.key_mode)
                           : launch_scan<false>(L, x, y, n, o.key_mode);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
     hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, nscan, out, hist_out);
+                       o.boundary_mode, n, nscan, guard, out, hs);
     if (L.ev) (void)hipEventRecord(L.ev[2], s);
-    int grid;
-    if (cls_out)
-        grid = vec ? launch_acc<true, true>(L, x, y, n, o.key_mode, cls_out)
-                   : launch_acc<false, true>(L, x, y, n, o.key_mode, cls_out);
-    else
-        grid = vec ? launch_acc<true, false>(L, x, y, n, o.key_mode, nullptr)
-                   : launch_acc<false, false>(L, x, y, n, o.key_mode, nullptr);
+    auto sweep = [&]() {
+        int grid;
+        if (cls_out)
+            grid = vec ? launch_acc<true, true>(L, x, y, n, o.key_mode, cls_out)
+                       : launch_acc<false, true>(L, x, y, n, o.key_mode, cls_out);
+        else
+            grid = vec ? launch_acc<true, false>(L, x, y, n, o.key_mode, nullptr)
+                       : launch_acc<false, false>(L, x, y, n, o.key_mode, nullptr);
+        return grid;
+    };
+    int grid = sweep();
     if (L.ev) (void)hipEventRecord(L.ev[3], s);
     hipLaunchKernelGGL(k_fin, dim3(1), dim3(BLOCK), 0, s, L.ws, L.partials, grid, out);
+    if (guard) {
+        // certify or reselect; the second sweep returns at once unless the
+        // classes were selected again
+        hipLaunchKernelGGL(k_guard, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, hs, tol,
+                           o.score_mode, o.boundary_mode, n, 0, out);
+        grid = sweep();
+        hipLaunchKernelGGL(k_fin, dim3(1), dim3(BLOCK), 0, s, L.ws, L.partials, grid, out);
+        hipLaunchKernelGGL(k_guard, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, hs, tol,
+                           o.score_mode, o.boundary_mode, n, 1, out);
+    }
     if (L.ev) (void)hipEventRecord(L.ev[4], s);
     return hipGetLastError();
 }

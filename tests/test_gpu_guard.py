@@ -1,0 +1,238 @@
+"""GPU parity of the guaranteed-eps mode (guard_mode 1, Thm 3.4) through the
+C ABI.
+
+After the first sweep of pass 2 the library bounds |x.y| from below with the
+computed sum less an error bound evaluated from the histogram and the
+classes, certifies the call when the Thm 3.4 bound taken with that lower
+bound meets tol, and otherwise selects the classes again (against the
+certified exponent, or all double when the sum may vanish) and sweeps once
+more.  Integer outputs (classes, counts, flags, e_ref, passes) must match
+the oracle bit for bit, the value within 1e-13 * sum |x_i y_i|.  Both sides
+evaluate the same decision formula on their own sums, which differ by
+rounding order only; none of the seeded cases here has a lower bound at a
+power of two, where that difference could tip the decision.
+"""
+from __future__ import annotations
+
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+import paper_2105_00115_amd as q  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+VALUE_TOL = 1e-13
+GUARD = [0, 0, 0, 0, 1]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
+INT_KEYS = ("count", "n_zero", "e_min", "e_max", "n_bins", "t", "flags", "status", "e_ref",
+            "passes")
+
+
+@pytest.fixture(scope="module")
+def h():
+    handle = q.Qdot(0)
+    yield handle
+    handle.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def compare(h, x, y, tol, opt=GUARD, classes=True, xd=None, yd=None):
+    print(f"[gpu-case] guard n={len(x)} tol={tol} opt={opt}", flush=True)
+    xd = dev(x) if xd is None else xd
+    yd = dev(y) if yd is None else yd
+    if classes:
+        cls, hist, r = h.qdot_classes(xd, yd, tol, opt=opt)
+        o = oracle.qdot(x, y, tol, opt=opt, want_classes=True, want_hist=True)
+    else:
+        r = h.qdot(xd, yd, tol, opt=opt)
+        o = oracle.qdot(x, y, tol, opt=opt)
+    for k in INT_KEYS:
+        assert r[k] == o[k], (k, r[k], o[k])
+    if o["status"] != oracle.OK:
+        return r, o
+    if classes:
+        np.testing.assert_array_equal(cls.cpu().numpy(), o["classes"])
+        np.testing.assert_array_equal(hist.cpu().numpy(), o["hist"])
+    scale = oracle.abs_dot(x, y)
+    assert abs(r["value"] - o["value"]) <= VALUE_TOL * scale, (r["value"], o["value"], scale)
+    for c in range(3):
+        assert abs(r["part"][c] - o["part"][c]) <= VALUE_TOL * scale, c
+    assert abs(r["bound_rel"] - o["bound_rel"]) <= 1e-12 * abs(o["bound_rel"])
+    # L 2^e_max = |S| (1 - 2^-52) - a 2^e_max: the sums differ by rounding
+    # order, the error bounds by the order of their bin sums
+    assert abs(r["lower"] - o["lower"]) <= VALUE_TOL * scale + 1e-12 * abs(o["lower"])
+    return r, o
+
+
+def test_golden_cancelling_example(h):
+    case = next(c for c in json.load(open(GOLDEN))["cases"] if c["name"] == "guard_cancel")
+    x = np.array([float.fromhex(s) for s in case["x"]])
+    y = np.array([float.fromhex(s) for s in case["y"]])
+    r, _ = compare(h, x, y, float(case["tol"]))
+    eg = case["expect_guard"]
+    assert Fraction(r["value"]) == Fraction(1, 1024)
+    for k in ("count", "flags", "e_ref", "passes"):
+        assert r[k] == eg[k], k
+    # the default selection perforates the true result away
+    assert h.qdot(dev(x), dev(y), float(case["tol"]))["value"] == 0.0
+
+
+@pytest.mark.parametrize("n", [1, 1000, 1023, 65573, 300001])
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-10])
+def test_paper_law_certifies_in_one_sweep(h, n, tol):
+    # the single-qdot law (+-10^U[-20, 20]): certified by the first
+    # selection, so the result is the default mode's plus the flag
+    x, y = workloads.log_uniform_pair(n, 40 + n % 97)
+    r, _ = compare(h, x, y, tol)
+    d = h.qdot(dev(x), dev(y), tol)
+    assert r["flags"] == d["flags"] | q.F_GUARANTEED and r["passes"] == 1
+    assert r["value"] == d["value"] and r["count"] == d["count"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_reselection_against_a_certified_exponent(h, seed):
+    # sums cancelling to ~3e-4 of their size at tol 1e-4: the classes are
+    # selected again against E_lo < e_max
+    x, y = workloads.cancelling_pair(2000, 700 + seed, 3e-4)
+    r, o = compare(h, x, y, 1e-4)
+    assert r["flags"] & q.F_RESELECTED and r["flags"] & q.F_GUARANTEED
+    assert r["passes"] == 2 and r["e_ref"] < r["e_max"]
+    ex = oracle.dot_exact(x, y)
+    assert abs(r["value"] - ex) <= 1e-4 * abs(ex)
+
+
+@pytest.mark.parametrize("n", [2000, 131072 + 77])
+def test_all_double_when_the_sum_may_vanish(h, n):
+    x, y = workloads.cancelling_pair(n, 720 + n % 13, 1e-6)
+    r, _ = compare(h, x, y, 1e-3)
+    assert r["e_ref"] == r["e_min"] - r["t"] - 22
+    assert r["count"][q.DOUBLE] == n - r["n_zero"]
+    assert r["flags"] & q.F_RESELECTED
+
+
+def test_one_signed_products(h):
+    x = workloads.normal_vector(300001, 81)
+    r, _ = compare(h, x, x, 1e-6)
+    assert r["passes"] == 1 and r["flags"] & q.F_GUARANTEED and r["e_ref"] == r["e_max"]
+    assert r["lower"] >= 2.0 ** r["e_max"]
+    # the hand example where the one-sign rule decides (tol 4)
+    r, _ = compare(h, np.array([1.0, 0.5]), np.ones(2), 4.0)
+    assert r["value"] == 1.0 and r["flags"] == q.F_GUARANTEED and r["lower"] == 1.0
+
+
+@pytest.mark.parametrize("opt", [[0, 1, 0, 0, 1], [0, 0, 1, 0, 1], [0, 1, 1, 0, 1]])
+def test_options(h, opt):
+    for s in range(3):
+        x, y = workloads.cancelling_pair(3000, 740 + s, 3e-4)
+        compare(h, x, y, 1e-4, opt=opt)
+    x, y = workloads.log_uniform_pair(100000, 745)
+    compare(h, x, y, 1e-6, opt=opt)
+
+
+def test_edge_cases(h):
+    compare(h, np.zeros(1000), np.ones(1000), 1e-6)
+    # everything perforated by the first selection, mixed signs: all double
+    r, _ = compare(h, np.array([1.0, -0.5]), np.ones(2), 100.0)
+    assert r["value"] == 0.5 and r["e_ref"] == -28 and r["passes"] == 1
+    # subnormal and huge operands, zeros, a ragged tail
+    g = workloads.rng(82)
+    xs = np.ldexp(g.uniform(1, 2, 3001), g.integers(-1074, -1000, 3001)) * g.choice([-1, 1], 3001)
+    ys = np.ldexp(g.uniform(1, 2, 3001), g.integers(900, 1000, 3001))
+    xs[::11] = 0.0
+    compare(h, xs, ys, 1e-9)
+    # unaligned views (the scalar load path)
+    x, y = workloads.cancelling_pair(5001, 83, 3e-4)
+    xd, yd = dev(np.concatenate([[0.0], x])), dev(np.concatenate([[0.0], y]))
+    compare(h, x, y, 1e-4, xd=xd[1:], yd=yd[1:])
+    xb = np.ones(100)
+    xb[5] = np.inf
+    r = h.qdot(dev(xb), dev(np.ones(100)), 1e-6, opt=GUARD)
+    assert r["status"] == q.E_NONFINITE and np.isnan(r["value"])
+    assert r["flags"] == 0 and r["passes"] == 0
+
+
+def test_unsupported_combinations_are_rejected(h):
+    x, y = workloads.log_uniform_pair(1000, 84)
+    xd, yd = dev(x), dev(y)
+    for opt in ([1, 0, 0, 0, 1], [0, 0, 0, 1, 1], [0, 0, 0, 0, 2]):
+        with pytest.raises(q.QdotError):
+            h.qdot(xd, yd, 1e-6, opt=opt)
+    offs = np.array([0, 500, 1000], dtype=np.int64)
+    with pytest.raises(q.QdotError):
+        h.batched(xd, yd, offs, [1e-6, 1e-6], opt=GUARD)
+    rp, col, val = workloads.poisson2d_csr(8)
+    A = q.Csr(rp, col, val)
+    b = dev(workloads.normal_vector(64, 85))
+    with pytest.raises(q.QdotError):
+        h.cg(A, b, torch.zeros(64, dtype=torch.float64, device="cuda:0"), 1e-10, 1e-8, 100, 1,
+             opt=GUARD)
+
+
+@pytest.mark.parametrize("data", ["reselect", "certified"])
+def test_graph_replay(h, data):
+    # the eight kernels of one call, captured and replayed with eager work on
+    # the same handle in between; every replay equals the eager call
+    if data == "reselect":
+        x, y = workloads.cancelling_pair(200001, 86, 3e-4)
+        tol = 1e-4
+    else:
+        x, y = workloads.log_uniform_pair(200001, 87)
+        tol = 1e-6
+    xd, yd = dev(x), dev(y)
+    eager = torch.zeros(q.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    h.qdot_async(xd, yd, tol, eager, opt=GUARD)
+    torch.cuda.synchronize()
+    out = torch.zeros_like(eager)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            h.qdot_async(xd, yd, tol, out, opt=GUARD)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        # eager work in between, reselecting or not
+        h.qdot(xd[:7000], yd[:7000], 1e-3, opt=GUARD)
+        torch.cuda.synchronize()
+    r = q.parse_results(out)[0]
+    o = oracle.qdot(x, y, tol, opt=GUARD)
+    for k in INT_KEYS:
+        assert r[k] == o[k], k
+    assert abs(r["value"] - o["value"]) <= VALUE_TOL * oracle.abs_dot(x, y)
+    assert bool(r["flags"] & q.F_RESELECTED) == (data == "reselect")
+
+
+def test_power_method(h):
+    m = 6
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, val)
+    x0 = workloads.unit_vector(m ** 3, 88)
+    r = h.power(A, dev(x0), 100, 1e-6, 1, opt=GUARD)
+    o = oracle.power(rp, col, val, x0, 100, 1e-6, 1, opt=GUARD)
+    assert r["status"] == q.OK and o["status"] == oracle.OK
+    np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
+
+
+@pytest.mark.timeout(400)
+def test_full_size(h):
+    """n = 2**27 at tol 1e-6, the benchmark's workload and launch shape."""
+    n = 1 << 27
+    print(f"[gpu-case] guard full size n={n}", flush=True)
+    x, y = workloads.log_uniform_pair(n, 2027)
+    r, _ = compare(h, x, y, 1e-6, classes=False)
+    assert r["flags"] & q.F_GUARANTEED

@@ -342,16 +342,7 @@ def _exact_fraction(x, y) -> Fraction:
     return sum((Fraction(a) * Fraction(b) for a, b in zip(x.tolist(), y.tolist())), Fraction(0))
 
 
-def _cancelling(n, seed, rel):
-    """Random products plus one component that cancels all but a relative
-    `rel` of their sum: e_max lies far above flexp(x.y)."""
-    g = np.random.default_rng(seed)
-    x = g.standard_normal(n) * 10.0 ** g.uniform(-3, 3, n)
-    y = g.standard_normal(n)
-    d = float(_exact_fraction(x[:-1], y[:-1]))
-    x[-1] = -d * (1.0 + rel * g.uniform(-1.0, 1.0))
-    y[-1] = 1.0
-    return x, y
+_cancelling = workloads.cancelling_pair
 
 
 def test_guard_lower_bound_never_exceeds_the_exact_dot():

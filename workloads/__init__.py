@@ -24,8 +24,14 @@ value laws follow the workloads the qdot paper studies:
   Laplacians in the power-method study (Sec. 4.3).
 * ``ragged_batch``: many independent qdot instances with log-uniform lengths
   in [1e2, 1e6] and tolerances drawn from {1e-4, 1e-6, 1e-8}.
+* ``cancelling_pair``: products of random sign and size whose sum cancels to
+  a chosen relative level (the last component is set from the exact sum of
+  the others), so that the largest product exponent lies far above the
+  exponent of the dot product (the case Thm 3.4 covers).
 """
 from __future__ import annotations
+
+from fractions import Fraction
 
 import numpy as np
 
@@ -41,6 +47,7 @@ __all__ = [
     "ragged_batch",
     "cg_grid_sides",
     "log_uniform_pair_torch",
+    "cancelling_pair",
 ]
 
 
@@ -234,3 +241,18 @@ def log_uniform_pair_torch(n: int, seed: int, device="cuda:0"):
         del s
         out.append(v)
     return out[0], out[1]
+
+
+def cancelling_pair(n: int, seed: int, rel: float):
+    """x, y in FP64 with x.y about rel * |x_n y_n|: n - 1 products of
+    normal sign and size 10**U[-3, 3], then x_n = -(their exact sum) *
+    (1 + rel * U[-1, 1]) and y_n = 1 (the exact sum is taken in rationals
+    and rounded once)."""
+    g = rng(seed)
+    x = g.standard_normal(n) * 10.0 ** g.uniform(-3.0, 3.0, n)
+    y = g.standard_normal(n)
+    d = float(sum((Fraction(a) * Fraction(b) for a, b in zip(x[:-1].tolist(), y[:-1].tolist())),
+                  Fraction(0)))
+    x[-1] = -d * (1.0 + rel * g.uniform(-1.0, 1.0))
+    y[-1] = 1.0
+    return x, y
