@@ -228,6 +228,20 @@ def test_power_method(h):
     np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
 
 
+@pytest.mark.parametrize("rel", [1e-5, 1e-7])
+def test_paired_cancelling_device_workload(h, rel):
+    # the benchmark's cancelling workload at 2^20: reselected in both cases;
+    # certified at 1e-5, while at 1e-7 (E = e_max - 22) even double products
+    # cannot meet the Thm 3.4 bound (flagged unattainable)
+    xd, yd = workloads.paired_cancelling_torch(1 << 20, 41, rel)
+    x, y = xd.cpu().numpy(), yd.cpu().numpy()
+    r, _ = compare(h, x, y, 1e-6, classes=False, xd=xd, yd=yd)
+    assert r["flags"] & q.F_RESELECTED and r["passes"] == 2
+    assert bool(r["flags"] & q.F_GUARANTEED) == (rel == 1e-5)
+    ex = oracle.dot_exact(x, y)
+    assert abs(r["value"] - ex) <= 1e-6 * abs(ex)
+
+
 @pytest.mark.timeout(400)
 def test_full_size(h):
     """n = 2**27 at tol 1e-6, the benchmark's workload and launch shape."""

@@ -48,6 +48,7 @@ __all__ = [
     "cg_grid_sides",
     "log_uniform_pair_torch",
     "cancelling_pair",
+    "paired_cancelling_torch",
 ]
 
 
@@ -255,4 +256,31 @@ def cancelling_pair(n: int, seed: int, rel: float):
                   Fraction(0)))
     x[-1] = -d * (1.0 + rel * g.uniform(-1.0, 1.0))
     y[-1] = 1.0
+    return x, y
+
+
+def paired_cancelling_torch(n: int, seed: int, rel: float, device="cuda:0"):
+    """x, y in FP64 on the device, n even: a = +-10**U[-3, 3], b normal,
+    u = U[-1, 1] (m = n/2 each), x = [a, -a (1 + rel u)], y = [b, b].  The
+    products of the two halves cancel pair by pair up to rel, so x.y is about
+    rel * sqrt(m) times a typical product while e_max is that of the largest."""
+    import torch
+
+    assert n % 2 == 0
+    m = n // 2
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    e = torch.rand(m, generator=g, dtype=torch.float64, device=device)
+    e.mul_(6.0).sub_(3.0)
+    a = torch.pow(10.0, e)
+    del e
+    s = torch.randint(0, 2, (m,), generator=g, device=device, dtype=torch.int8)
+    a.mul_(1.0 - 2.0 * s.to(torch.float64))
+    del s
+    b = torch.randn(m, generator=g, dtype=torch.float64, device=device)
+    u = torch.rand(m, generator=g, dtype=torch.float64, device=device)
+    u.mul_(2.0 * rel).sub_(rel).add_(1.0)
+    x = torch.cat([a, -(a * u)])
+    del a, u
+    y = torch.cat([b, b])
     return x, y
