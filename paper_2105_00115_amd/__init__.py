@@ -150,6 +150,11 @@ def lib():
         raise RuntimeError(
             f"qdot HIP library not found at {LIB_PATH}; build it first "
             "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch bundles its own HIP runtime under the same soname as the system
+    # one the library links to; whichever is loaded first serves the whole
+    # process.  Loading torch first keeps its runtime (the one its kernels
+    # and allocator are built for) and binds the library to it as well.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     for name, res, args in SIGNATURES:
         f = getattr(L, name)

@@ -294,3 +294,21 @@ def test_full_size_c2(h):
     assert abs(r["value"] - o["value"]) <= VALUE_TOL * scale
     r2 = h.qdot(xd, yd, 1e-6)
     assert r2["value"] == r["value"]
+
+
+def test_binding_before_torch_in_a_fresh_process():
+    # a script that creates a handle before it imports torch itself: torch's
+    # HIP runtime must still be the one the process uses
+    import subprocess
+    import sys
+    code = ("import paper_2105_00115_amd as q\n"
+            "h = q.Qdot(0)\n"
+            "import torch\n"
+            "x = torch.ones(1000, dtype=torch.float64, device='cuda:0')\n"
+            "r = h.qdot(x, x, 1e-6)\n"
+            "assert r['value'] == 1000.0, r\n"
+            "print('ok')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=240)
+    assert p.returncode == 0 and p.stdout.strip().endswith("ok"), p.stderr[-2000:]

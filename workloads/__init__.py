@@ -49,6 +49,7 @@ __all__ = [
     "log_uniform_pair_torch",
     "cancelling_pair",
     "paired_cancelling_torch",
+    "paper_dist_torch",
 ]
 
 
@@ -284,3 +285,27 @@ def paired_cancelling_torch(n: int, seed: int, rel: float, device="cuda:0"):
     del a, u
     y = torch.cat([b, b])
     return x, y
+
+
+def paper_dist_torch(n: int, t: float, seed: int, family: str, device="cuda:0"):
+    """Families A and B of the error-bound study drawn on the device (the
+    law of ``paper_dist_a`` / ``paper_dist_b``, another random stream):
+    s * 2**p with s ~ U[0.5, 1) and p = round(U[-t/2, t/2]) (family "A") or
+    round(N(0, t/2)) (family "B"), x and y independent."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    out = []
+    for _ in range(2):
+        s = torch.rand(n, generator=g, dtype=torch.float64, device=device)
+        s.mul_(0.5).add_(0.5)
+        if family == "A":
+            p = torch.rand(n, generator=g, dtype=torch.float64, device=device)
+            p.mul_(t).sub_(0.5 * t)
+        else:
+            p = torch.randn(n, generator=g, dtype=torch.float64, device=device)
+            p.mul_(0.5 * t)
+        out.append(torch.ldexp(s, torch.round(p)))
+        del s, p
+    return out[0], out[1]
