@@ -71,6 +71,7 @@ _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
 _u8p = C.POINTER(C.c_uint8)
 _fp = C.POINTER(C.c_float)
+_fp = C.POINTER(C.c_float)
 
 
 def lib():
@@ -83,6 +84,9 @@ def lib():
     L.orc_qdot.argtypes = [_dp, _dp, C.c_int64, C.c_double, _i32p,
                            C.POINTER(OrcResult), _u8p, _i32p, _i64p]
     L.orc_qdot.restype = C.c_int
+    L.orc_qdot_f32.argtypes = [_fp, _fp, C.c_int64, C.c_double, _i32p,
+                               C.POINTER(OrcResult), _u8p, _i32p, _i64p]
+    L.orc_qdot_f32.restype = C.c_int
     for f in ("orc_dot_exact", "orc_abs_dot", "orc_dot_dot2"):
         getattr(L, f).argtypes = [_dp, _dp, C.c_int64]
         getattr(L, f).restype = C.c_double
@@ -130,13 +134,9 @@ def _opts(opt):
     return o, o.ctypes.data_as(_i32p)
 
 
-def qdot(x, y, tol, opt=None, want_classes=False, want_keys=False,
-         want_hist=False) -> dict:
-    """Oracle qdot.  Returns the result dict, plus 'classes' (uint8[n]),
-    'keys' (int32[n], zero products = INT32_MIN) and 'hist' (int64[W],
-    index k - KMIN) when asked."""
-    x, xp = _f64(x)
-    y, yp = _f64(y)
+def _qdot(fn, dtype, ptype, x, y, tol, opt, want_classes, want_keys, want_hist):
+    x = np.ascontiguousarray(x, dtype=dtype)
+    y = np.ascontiguousarray(y, dtype=dtype)
     assert x.shape == y.shape
     n = x.shape[0]
     o, op = _opts(opt)
@@ -144,10 +144,10 @@ def qdot(x, y, tol, opt=None, want_classes=False, want_keys=False,
     cls = np.zeros(n, dtype=np.uint8) if want_classes else None
     keys = np.zeros(n, dtype=np.int32) if want_keys else None
     hist = np.zeros(W, dtype=np.int64) if want_hist else None
-    lib().orc_qdot(xp, yp, n, float(tol), op, C.byref(r),
-                   cls.ctypes.data_as(_u8p) if cls is not None else None,
-                   keys.ctypes.data_as(_i32p) if keys is not None else None,
-                   hist.ctypes.data_as(_i64p) if hist is not None else None)
+    fn(x.ctypes.data_as(ptype), y.ctypes.data_as(ptype), n, float(tol), op, C.byref(r),
+       cls.ctypes.data_as(_u8p) if cls is not None else None,
+       keys.ctypes.data_as(_i32p) if keys is not None else None,
+       hist.ctypes.data_as(_i64p) if hist is not None else None)
     d = r.as_dict()
     if cls is not None:
         d["classes"] = cls
@@ -156,6 +156,23 @@ def qdot(x, y, tol, opt=None, want_classes=False, want_keys=False,
     if hist is not None:
         d["hist"] = hist
     return d
+
+
+def qdot(x, y, tol, opt=None, want_classes=False, want_keys=False,
+         want_hist=False) -> dict:
+    """Oracle qdot.  Returns the result dict, plus 'classes' (uint8[n]),
+    'keys' (int32[n], zero products = INT32_MIN) and 'hist' (int64[W],
+    index k - KMIN) when asked."""
+    return _qdot(lib().orc_qdot, np.float64, _dp, x, y, tol, opt, want_classes, want_keys,
+                 want_hist)
+
+
+def qdot_f32(x, y, tol, opt=None, want_classes=False, want_keys=False,
+             want_hist=False) -> dict:
+    """Oracle qdot of single-precision inputs (mu = m_single): as qdot, with
+    no double class."""
+    return _qdot(lib().orc_qdot_f32, np.float32, _fp, x, y, tol, opt, want_classes, want_keys,
+                 want_hist)
 
 
 def dot_exact(x, y) -> float:

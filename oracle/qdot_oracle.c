@@ -286,9 +286,14 @@ static double eps_of(int cls)
  * (Thm 3.4 puts E in place of e_max).  Fills the class table C, the class
  * counts, the Thm 3.3 sum relative to e_max and the selection flags. */
 static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e_ref,
-                       int32_t t, int32_t nonstrict, int64_t n_zero, uint8_t *C,
-                       orc_result *r)
+                       int32_t t, int32_t nonstrict, int mu_single, int64_t n_zero,
+                       uint8_t *C, orc_result *r)
 {
+    /* eq. (precision-def) admits a row only when mu is at least the row's
+     * mantissa width: with single inputs (mu = m_single) there is no double
+     * row, a bin scoring at or above m_single stays at the input precision
+     * and is flagged, as a double bin scoring at or above m_double is. */
+    const int32_t m_top = mu_single ? M_SINGLE : M_DOUBLE;
     xsum brel;
     xs_init(&brel);
     for (int c = 0; c < 4; c++) r->count[c] = 0;
@@ -299,7 +304,8 @@ static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e
         if (Mk == 0) continue; /* empty bin: score -inf */
         int32_t sigma = orc_ceil_log2(Mk) + k - e_ref - t + 1;
         int32_t c = orc_precision(sigma, nonstrict);
-        if (nonstrict ? sigma > M_DOUBLE : sigma >= M_DOUBLE)
+        if (mu_single && c == ORC_DOUBLE) c = ORC_SINGLE;
+        if (nonstrict ? sigma > m_top : sigma >= m_top)
             r->flags |= ORC_F_UNATTAINABLE;
         C[k - ORC_KMIN] = (uint8_t)c;
         r->count[c] += Mk;
@@ -311,8 +317,10 @@ static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e
     r->bound_abs = ldexp(r->bound_rel, e_max);
     xs_free(&brel);
     /* Thm 3.6 (early termination): all bins at input precision when
-     * e_ref - e_min <= -floor(log2 eps) - m_single. */
-    if ((int64_t)e_ref - e_min <= -(int64_t)t - M_SINGLE)
+     * e_ref - e_min <= -floor(log2 eps) - m, m the mantissa width of the
+     * precision just below the input's (m_single for double inputs, m_half
+     * for single inputs). */
+    if ((int64_t)e_ref - e_min <= -(int64_t)t - (mu_single ? M_HALF : M_SINGLE))
         r->flags |= ORC_F_THM_ALL_DOUBLE;
     if (r->count[ORC_DOUBLE] + r->count[ORC_SINGLE] + r->count[ORC_HALF] == 0)
         r->flags |= ORC_F_ALL_PERF;
@@ -497,9 +505,9 @@ static int orc_certified(double bound_rel, double low, double tol)
 /* ------------------------------------------------------------------ */
 /* qdot (Alg. 3)                                                         */
 /* ------------------------------------------------------------------ */
-int orc_qdot(const double *x, const double *y, int64_t n, double tol,
-             const int32_t *opt, orc_result *r, uint8_t *cls_out,
-             int32_t *key_out, int64_t *hist_out)
+static int qdot_core(const double *x, const double *y, int64_t n, double tol,
+                     const int32_t *opt, int mu_single, orc_result *r, uint8_t *cls_out,
+                     int32_t *key_out, int64_t *hist_out)
 {
     memset(r, 0, sizeof *r);
     int32_t key_mode = opt ? opt[0] : 0;
@@ -511,7 +519,8 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
         key_mode < 0 || key_mode > 1 || score_mode < 0 || score_mode > 1 ||
         nonstrict < 0 || nonstrict > 1 || accum_mode < 0 || accum_mode > 1 ||
         guard_mode < 0 || guard_mode > 1 ||
-        (guard_mode == 1 && (key_mode != 0 || accum_mode != 0))) {
+        (guard_mode == 1 && (key_mode != 0 || accum_mode != 0)) ||
+        (mu_single && (accum_mode != 0 || guard_mode != 0))) {
         r->status = ORC_E_INVAL;
         r->value = NAN;
         return r->status;
@@ -574,7 +583,7 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
     /* bin scores and precisions against e_max, then Alg. 1 */
     uint8_t *C = (uint8_t *)malloc(ORC_W);
     int32_t e_ref = e_max;
-    orc_select(M, e_max, e_min, e_ref, t, nonstrict, r->n_zero, C, r);
+    orc_select(M, e_max, e_min, e_ref, t, nonstrict, mu_single, r->n_zero, C, r);
     int kept = !(r->flags & ORC_F_ALL_PERF);
     double S = orc_compute(x, y, n, key, C, e_max, e_ref + t + 22, accum_mode, cls_out, r);
     r->passes = kept;
@@ -593,7 +602,7 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
             int32_t ref2 = low > 0.0 ? e_max + ilogb(low) : e_min - t - 22 - nonstrict;
             if (ref2 < e_max) {
                 e_ref = ref2;
-                orc_select(M, e_max, e_min, e_ref, t, nonstrict, r->n_zero, C, r);
+                orc_select(M, e_max, e_min, e_ref, t, nonstrict, mu_single, r->n_zero, C, r);
                 int kept2 = !(r->flags & ORC_F_ALL_PERF);
                 S = orc_compute(x, y, n, key, C, e_max, e_ref + t + 22, accum_mode, cls_out, r);
                 double low2 = orc_lower(M, C, e_max, S, n, one_signed);
@@ -611,6 +620,39 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
     free(M);
     free(key);
     return ORC_OK;
+}
+
+int orc_qdot(const double *x, const double *y, int64_t n, double tol,
+             const int32_t *opt, orc_result *r, uint8_t *cls_out,
+             int32_t *key_out, int64_t *hist_out)
+{
+    return qdot_core(x, y, n, tol, opt, 0, r, cls_out, key_out, hist_out);
+}
+
+/* Single-precision inputs (mu = m_single in eq. (precision-def)): every
+ * float is exactly a double, so the keys, the histogram and the leaves are
+ * those of the same values given as doubles; only the precision table ends
+ * at single. */
+int orc_qdot_f32(const float *x, const float *y, int64_t n, double tol,
+                 const int32_t *opt, orc_result *r, uint8_t *cls_out,
+                 int32_t *key_out, int64_t *hist_out)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) {
+        memset(r, 0, sizeof *r);
+        r->status = ORC_E_INVAL;
+        r->value = NAN;
+        return r->status;
+    }
+    double *xd = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *yd = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; i++) {
+        xd[i] = (double)x[i];
+        yd[i] = (double)y[i];
+    }
+    int st = qdot_core(xd, yd, n, tol, opt, 1, r, cls_out, key_out, hist_out);
+    free(xd);
+    free(yd);
+    return st;
 }
 
 /* ------------------------------------------------------------------ */

@@ -69,6 +69,13 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
              const int32_t *opt, orc_result *out, uint8_t *cls,
              int32_t *keys, int64_t *hist);
 
+/* The same for single-precision inputs (mu = m_single): no double class; a
+ * bin scoring at or above m_single stays single and is flagged
+ * unattainable.  accum_mode and guard_mode must be 0. */
+int orc_qdot_f32(const float *x, const float *y, int64_t n, double tol,
+                 const int32_t *opt, orc_result *out, uint8_t *cls,
+                 int32_t *keys, int64_t *hist);
+
 /* correctly rounded sum_i x_i y_i (valid while no product over- or
  * underflows), and correctly rounded sum_i |x_i y_i| */
 double orc_dot_exact(const double *x, const double *y, int64_t n);

@@ -469,6 +469,91 @@ def test_guard_edge_cases():
 
 
 # --------------------------------------------------------------------------
+# Single-precision inputs (mu = m_single in eq. (precision-def))
+# --------------------------------------------------------------------------
+
+def test_f32_small_integers_give_the_exact_dot():
+    # products and tile sums of small integers are exact in FP32, so at a
+    # tolerance that keeps everything the value is the integer dot product;
+    # every bin scores >= 23, which has no row when mu = m_single: single
+    # and flagged
+    g = np.random.default_rng(31)
+    for n in (1, 63, 64, 1000, 4097):
+        x = g.integers(-50, 51, n).astype(np.float32)
+        y = g.integers(-50, 51, n).astype(np.float32)
+        r = oracle.qdot_f32(x, y, 1e-30, want_classes=True)
+        nz = int(np.count_nonzero(x.astype(np.int64) * y.astype(np.int64)))
+        assert r["value"] == float(np.dot(x.astype(np.int64), y.astype(np.int64)))
+        assert r["count"] == [0, nz, 0, n - nz]
+        if nz:
+            assert r["flags"] & oracle.F_UNATTAINABLE
+
+
+def test_f32_hand_example():
+    # x = y = (1, 1, 1, 1), tol 1e-9: one bin (key 0, M = 4), t = floor(log2
+    # 1e-9) = -30, score 2 + 0 - 0 + 30 + 1 = 33.  Double inputs: double, no
+    # flag (33 < 52).  Single inputs: no double row, so single and
+    # unattainable (33 >= 23).  Thm 3.6: 0 <= 30 - 23 (double) and
+    # 0 <= 30 - 10 (single).  Both values are 4.
+    x = np.ones(4)
+    rd = oracle.qdot(x, x, 1e-9, want_classes=True)
+    rs = oracle.qdot_f32(x.astype(np.float32), x.astype(np.float32), 1e-9, want_classes=True)
+    assert rd["classes"].tolist() == [oracle.DOUBLE] * 4 and rd["flags"] == oracle.F_THM_ALL_DOUBLE
+    assert rs["classes"].tolist() == [oracle.SINGLE] * 4
+    assert rs["flags"] == oracle.F_UNATTAINABLE | oracle.F_THM_ALL_DOUBLE
+    assert rd["t"] == rs["t"] == -30 and rd["value"] == rs["value"] == 4.0
+    # bound: 4 * 2^1 * 2^-23 with eps(single)
+    assert Fraction(rs["bound_rel"]) == Fraction(8, 2 ** 23)
+
+
+def test_f32_is_the_double_selection_capped_at_single():
+    # floats are exact doubles: keys, histogram, t and scores are those of
+    # the double path; only the double class becomes single, and where the
+    # double path keeps no double bin the two results are identical
+    for s, tol in ((41, 1e-3), (42, 1e-6), (43, 1e-12)):
+        x, y = workloads.log_uniform_pair(6000, s, -15.0, 15.0)
+        xf, yf = x.astype(np.float32), y.astype(np.float32)
+        rs = oracle.qdot_f32(xf, yf, tol, want_classes=True, want_hist=True, want_keys=True)
+        rd = oracle.qdot(xf.astype(np.float64), yf.astype(np.float64), tol,
+                         want_classes=True, want_hist=True, want_keys=True)
+        assert np.array_equal(rs["keys"], rd["keys"]) and np.array_equal(rs["hist"], rd["hist"])
+        capped = np.where(rd["classes"] == oracle.DOUBLE, oracle.SINGLE, rd["classes"])
+        assert np.array_equal(rs["classes"], capped)
+        assert rs["t"] == rd["t"] and rs["e_max"] == rd["e_max"]
+        if rd["count"][oracle.DOUBLE] == 0:
+            assert rs["value"] == rd["value"] and rs["count"] == rd["count"]
+
+
+def test_f32_bound_on_positive_data():
+    # one-signed products: Thm 3.3 holds, error against exact rationals
+    for s, tol in ((44, 1e-3), (45, 1e-6), (46, 1e-9)):
+        xa, ya = workloads.paper_dist_b(3000, 13, s)
+        xf, yf = xa.astype(np.float32), ya.astype(np.float32)
+        r = oracle.qdot_f32(xf, yf, tol)
+        ex = _exact_fraction(xf.astype(np.float64), yf.astype(np.float64))
+        assert abs(Fraction(r["value"]) - ex) <= Fraction(r["bound_rel"]) * abs(ex)
+        # Thm 3.5 when every bin met its share.  With N_bins ~ 60, tol 1e-6
+        # gives t = -26 and the top bin scores >= 27 >= m_single: single
+        # inputs cannot meet it (flagged); tol 1e-3 (t = -16) can
+        if tol == 1e-3:
+            assert not r["flags"] & oracle.F_UNATTAINABLE and r["bound_rel"] <= tol
+        else:
+            assert r["flags"] & oracle.F_UNATTAINABLE
+
+
+def test_f32_edges():
+    # float subnormals are exact doubles: key of 2^-140 * 1 is -140
+    x = np.array([2.0 ** -140, 1.0], dtype=np.float32)
+    y = np.array([1.0, 0.0], dtype=np.float32)
+    r = oracle.qdot_f32(x, y, 1e-3, want_keys=True)
+    assert r["keys"][0] == -140 and r["n_zero"] == 1 and r["value"] == 2.0 ** -140
+    assert oracle.qdot_f32(x, y, 1e-3, opt=[0, 0, 0, 1])["status"] == oracle.E_INVAL
+    assert oracle.qdot_f32(x, y, 1e-3, opt=[0, 0, 0, 0, 1])["status"] == oracle.E_INVAL
+    x[1] = np.inf
+    assert oracle.qdot_f32(x, y, 1e-3)["status"] == oracle.E_NONFINITE
+
+
+# --------------------------------------------------------------------------
 # Histogram, partition, invariants
 # --------------------------------------------------------------------------
 
