@@ -269,6 +269,24 @@ def main():
             "reselected": bool(rc["flags"] & q.F_RESELECTED)}
     del xc, yc
 
+    # single-precision inputs (mu = m_single): the same vectors rounded to
+    # float, 8 bytes per component per pass
+    log("single-precision inputs")
+    xf, yf = x.float(), y.float()
+    for _ in range(2):
+        h.qdot_f32_async(xf, yf, tol, out)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    for _ in range(10):
+        h.qdot_f32_async(xf, yf, tol, out)
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - c0) / 10
+    rf = q.parse_results(out)[0]
+    fp32_inputs = {"gelem_s": round(n / tf / 1e9, 3), "ms_per_call": round(tf * 1e3, 4),
+                   "alg_gb_s": round(16.0 * n / tf / 1e9, 1), "count": rf["count"],
+                   "flags": rf["flags"]}
+    del xf, yf
+
     # one call captured in a HIP graph, replays timed one by one: median
     def replay_median(opt, reps=25):
         gq = torch.cuda.CUDAGraph()
@@ -505,6 +523,7 @@ def main():
             "graph_replay_median_ms": {"two_pass": round(rep2, 4), "one_pass": round(rep1, 4)},
             "other_tolerances": other_tol,
             "guaranteed_mode": guard,
+            "fp32_inputs": fp32_inputs,
             "paper_context": {
                 "note": "the paper states ratios only, on an unnamed NVIDIA GPU",
                 "approx_efficiency_paper": 0.025,

@@ -279,6 +279,32 @@ QDOT_API int32_t qdot_classes_async(qdot_handle *h, const double *x, const doubl
                            void *stream, uint8_t *dev_cls, int64_t *dev_hist,
                            qdot_result *dev_out);
 
+/* qdot of single-precision inputs (eq. (precision-def) with mu = m_single,
+ * the input precision the table allows; Sec. 3.2).  As qdot_async for
+ * device float vectors x, y (n components, 4-byte aligned; 16-byte aligned
+ * vectors take the vector-load path).  Every float is exactly a double, so
+ * keys, histogram, t and scores are those of the same values given as
+ * doubles; the precision table has no double row, so a bin scoring at or
+ * above m_single (23) stays single and sets QDOT_F_UNATTAINABLE, and
+ * QDOT_F_THM_ALL_DOUBLE means every bin is at the input precision (Thm 3.6
+ * with m_half: e_max - e_min <= -t - 10).  The result is FP64 and counts
+ * no double class.  accum_mode and guard_mode must be 0 (QDOT_E_INVAL
+ * otherwise).  No allocation, no host sync; graph-capturable. */
+QDOT_API int32_t qdot_f32_async(qdot_handle *h, const float *x, const float *y,
+                       int64_t n, double tol, const qdot_options *opt,
+                       void *stream, qdot_result *dev_out);
+
+/* Synchronous qdot_f32_async, as qdot is to qdot_async. */
+QDOT_API int32_t qdot_f32(qdot_handle *h, const float *x, const float *y, int64_t n,
+                 double tol, const qdot_options *opt, void *stream,
+                 qdot_result *host_out);
+
+/* qdot_classes_async for single-precision inputs. */
+QDOT_API int32_t qdot_f32_classes_async(qdot_handle *h, const float *x, const float *y,
+                               int64_t n, double tol, const qdot_options *opt,
+                               void *stream, uint8_t *dev_cls, int64_t *dev_hist,
+                               qdot_result *dev_out);
+
 /* Minimal entry: qdot of device vectors x, y (n components, 8-byte
  * aligned) at tolerance tol with the default options, on a handle the
  * library keeps per device (created on the first call on the current

@@ -115,6 +115,9 @@ SIGNATURES = [
     ("qdot", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, C.POINTER(QdotResult)]),
     ("qdot_simple", _i32, [_vp, _vp, _i64, _d, C.POINTER(_d), C.POINTER(_i64)]),
     ("qdot_classes_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp, _vp, _vp]),
+    ("qdot_f32_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp]),
+    ("qdot_f32", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, C.POINTER(QdotResult)]),
+    ("qdot_f32_classes_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp, _vp, _vp]),
     ("qdot_fp64_dot_async", _i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
     ("qdot_batched_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32, _OPT,
                                   _vp, _vp]),
@@ -185,10 +188,11 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _check_vec(t, name):
+def _check_vec(t, name, dtype=None):
     import torch
-    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == 1):
-        raise ValueError(f"{name} must be a contiguous 1-D float64 CUDA tensor")
+    dtype = torch.float64 if dtype is None else dtype
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.dim() == 1):
+        raise ValueError(f"{name} must be a contiguous 1-D {dtype} CUDA tensor")
 
 
 def parse_cg_results(buf) -> list:
@@ -357,6 +361,45 @@ class Qdot:
                                       _stream(stream), _ptr(cls), _ptr(hist), _ptr(out))
         if st != OK:
             self._raise(st, "qdot_classes_async")
+        torch.cuda.current_stream().synchronize()
+        return cls[:n], hist, parse_results(out)[0]
+
+    # ---- single-precision inputs (mu = m_single) ----------------------------
+    def qdot_f32(self, x, y, tol, opt=None, stream=None) -> dict:
+        import torch
+        _check_vec(x, "x", torch.float32)
+        _check_vec(y, "y", torch.float32)
+        r = QdotResult()
+        st = lib().qdot_f32(self._h, _ptr(x), _ptr(y), x.numel(), float(tol), _opts(opt),
+                            _stream(stream), C.byref(r))
+        if st not in (OK, E_NONFINITE):
+            self._raise(st, "qdot_f32")
+        return r.as_dict()
+
+    def qdot_f32_async(self, x, y, tol, out, opt=None, stream=None):
+        import torch
+        _check_vec(x, "x", torch.float32)
+        _check_vec(y, "y", torch.float32)
+        dst = C.c_void_p(out if isinstance(out, int) else out.data_ptr())
+        st = lib().qdot_f32_async(self._h, _ptr(x), _ptr(y), x.numel(), float(tol),
+                                  _opts(opt), _stream(stream), dst)
+        if st != OK:
+            self._raise(st, "qdot_f32_async")
+
+    def qdot_f32_classes(self, x, y, tol, opt=None, stream=None):
+        """(classes uint8[n], histogram int64[W], result dict), synchronised."""
+        import torch
+        _check_vec(x, "x", torch.float32)
+        _check_vec(y, "y", torch.float32)
+        n = x.numel()
+        cls = torch.empty(max(n, 1), dtype=torch.uint8, device=x.device)
+        hist = torch.empty(W, dtype=torch.int64, device=x.device)
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=x.device)
+        st = lib().qdot_f32_classes_async(self._h, _ptr(x), _ptr(y), n, float(tol),
+                                          _opts(opt), _stream(stream), _ptr(cls), _ptr(hist),
+                                          _ptr(out))
+        if st != OK:
+            self._raise(st, "qdot_f32_classes_async")
         torch.cuda.current_stream().synchronize()
         return cls[:n], hist, parse_results(out)[0]
 

@@ -116,17 +116,21 @@ bool s1_admissible(int64_t n, double tol, const qdot_options &o)
     return n <= S1_MAX_N && s1_depth(n, tol, o) <= S1_WIN;
 }
 
-static int32_t check_qdot_args(qdot_handle *h, const double *x, const double *y, int64_t n,
-                               double tol, const qdot_options *opt, qdot_options &o)
+template <class T>
+static int32_t check_qdot_args(qdot_handle *h, const T *x, const T *y, int64_t n, double tol,
+                               const qdot_options *opt, qdot_options &o)
 {
     if (!h) return QDOT_E_INVAL;
     if (n < 0) return fail(h, QDOT_E_INVAL, "n < 0");
     if (n > 0 && (!x || !y)) return fail(h, QDOT_E_INVAL, "NULL vector with n > 0");
-    if (((uintptr_t)x | (uintptr_t)y) & 7) return fail(h, QDOT_E_INVAL, "vectors not 8-byte aligned");
+    if (((uintptr_t)x | (uintptr_t)y) & (sizeof(T) - 1))
+        return fail(h, QDOT_E_INVAL, "vectors not aligned to their element size");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(h, QDOT_E_INVAL, "tol must be finite and > 0");
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (sizeof(T) == 4 && (o.accum_mode != 0 || o.guard_mode != 0))
+        return fail(h, QDOT_E_INVAL, "single-precision inputs need accum_mode 0 and guard_mode 0");
     if (o.accum_mode == 1 && !s1_admissible(n, tol, o))
         return fail(h, QDOT_E_INVAL, "accum_mode 1 needs n <= 2^30 and a tolerance whose "
                                      "kept bins fit the one-pass window");
@@ -297,6 +301,50 @@ int32_t qdot(qdot_handle *h, const double *x, const double *y, int64_t n, double
     if (e != hipSuccess) return hip_fail(h, e, "qdot result copy");
     *host_out = *h->host_res;
     return host_out->status;
+}
+
+int32_t qdot_f32_async(qdot_handle *h, const float *x, const float *y, int64_t n, double tol,
+                       const qdot_options *opt, void *stream, qdot_result *dev_out)
+{
+    qdot_options o;
+    int32_t st = check_qdot_args(h, x, y, n, tol, opt, o);
+    if (st != QDOT_OK) return st;
+    if (!dev_out) return fail(h, QDOT_E_INVAL, "dev_out is NULL");
+    DeviceGuard g(h->device);
+    Launch L = make_launch(h, (hipStream_t)stream, n);
+    L.ev = take_events(h, 0);
+    hipError_t e = launch_qdot_f32(L, x, y, n, tol, o, dev_out, nullptr, nullptr);
+    return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot_f32 launch");
+}
+
+int32_t qdot_f32(qdot_handle *h, const float *x, const float *y, int64_t n, double tol,
+                 const qdot_options *opt, void *stream, qdot_result *host_out)
+{
+    if (!host_out) return fail(h, QDOT_E_INVAL, "host_out is NULL");
+    int32_t st = qdot_f32_async(h, x, y, n, tol, opt, stream, h ? h->dev_res : nullptr);
+    if (st != QDOT_OK) return st;
+    DeviceGuard g(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(h->host_res, h->dev_res, sizeof(qdot_result),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "qdot_f32 result copy");
+    *host_out = *h->host_res;
+    return host_out->status;
+}
+
+int32_t qdot_f32_classes_async(qdot_handle *h, const float *x, const float *y, int64_t n,
+                               double tol, const qdot_options *opt, void *stream,
+                               uint8_t *dev_cls, int64_t *dev_hist, qdot_result *dev_out)
+{
+    qdot_options o;
+    int32_t st = check_qdot_args(h, x, y, n, tol, opt, o);
+    if (st != QDOT_OK) return st;
+    if (!dev_out || (n > 0 && !dev_cls)) return fail(h, QDOT_E_INVAL, "NULL output");
+    DeviceGuard g(h->device);
+    hipError_t e = launch_qdot_f32(make_launch(h, (hipStream_t)stream, n), x, y, n, tol, o,
+                                   dev_out, dev_cls, (long long *)dev_hist);
+    return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot_f32_classes launch");
 }
 
 int32_t qdot_simple(const double *x, const double *y, int64_t n, double tol, double *value,

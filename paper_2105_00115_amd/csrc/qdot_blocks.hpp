@@ -26,25 +26,42 @@ __device__ __forceinline__ void load4_full(const double *__restrict__ p, double 
     }
 }
 
-__device__ __forceinline__ void load4_tail(const double *__restrict__ p, int lim, double v[4])
+// single-precision inputs: 4 consecutive floats are one 16-byte load
+template <bool VEC>
+__device__ __forceinline__ void load4_full(const float *__restrict__ p, float v[4])
+{
+    if (VEC) {
+        const float4 a = *reinterpret_cast<const float4 *>(p);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = a.z;
+        v[3] = a.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++) v[e] = p[e];
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void load4_tail(const T *__restrict__ p, int lim, T v[4])
 {
 #pragma unroll
-    for (int e = 0; e < 4; e++) v[e] = e < lim ? p[e] : 0.0;
+    for (int e = 0; e < 4; e++) v[e] = e < lim ? p[e] : T(0);
 }
 
 // One block walks groups of U * CHUNK components of x, y: the groups that
 // start at first, first + stride, first + 2 * stride, ... below n (stride a
 // multiple of U * CHUNK).  Each thread loads EPT consecutive components of
 // each CHUNK, U CHUNKs in flight; the one partial group is bounds-checked.
-template <bool VEC, int U, class Body>
-__device__ __forceinline__ void stream_strided(const double *__restrict__ x,
-                                               const double *__restrict__ y, int64_t first,
-                                               int64_t stride, int64_t n, Body &&body)
+template <bool VEC, int U, class T, class Body>
+__device__ __forceinline__ void stream_strided(const T *__restrict__ x, const T *__restrict__ y,
+                                               int64_t first, int64_t stride, int64_t n,
+                                               Body &&body)
 {
     const int64_t group = (int64_t)CHUNK * U;
     int64_t base = first;
     for (; base + group <= n; base += stride) {
-        double xv[U][4], yv[U][4];
+        T xv[U][4], yv[U][4];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
@@ -61,7 +78,7 @@ __device__ __forceinline__ void stream_strided(const double *__restrict__ x,
             const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
             const int64_t left = n - i0;
             const int lim = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
-            double xv[4], yv[4];
+            T xv[4], yv[4];
             load4_tail(x + i0, lim, xv);
             load4_tail(y + i0, lim, yv);
             body(xv, yv, i0, lim);
@@ -75,55 +92,13 @@ __device__ __forceinline__ void stream_strided(const double *__restrict__ x,
 // per-lane limits.  body(xv, yv, i0, lim) sees 4 consecutive components
 // i0..i0+3 of which the first `lim` are real; it is called with every lane
 // of the block active.
-template <bool VEC, int U, class Body>
-__device__ __forceinline__ void stream_groups(const double *__restrict__ x,
-                                              const double *__restrict__ y, int64_t n,
-                                              Body &&body)
+template <bool VEC, int U, class T, class Body>
+__device__ __forceinline__ void stream_groups(const T *__restrict__ x, const T *__restrict__ y,
+                                              int64_t n, Body &&body)
 {
     const int64_t group = (int64_t)CHUNK * U;
     stream_strided<VEC, U>(x, y, (int64_t)blockIdx.x * group, (int64_t)gridDim.x * group, n,
                            body);
-}
-
-// One block walks components [begin, end) of x, y (indices relative to the
-// vector start, begin a multiple of CHUNK) in groups of CHUNK, U groups'
-// loads in flight at a time while the range allows.
-template <bool VEC, class Body, int U = 1>
-__device__ __forceinline__ void stream_block_range(const double *__restrict__ x,
-                                                   const double *__restrict__ y, int64_t begin,
-                                                   int64_t end, Body &&body)
-{
-    int64_t base = begin;
-    if constexpr (U > 1) {
-        for (; base + (int64_t)U * CHUNK <= end; base += (int64_t)U * CHUNK) {
-            double xv[U][4], yv[U][4];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
-                load4_full<VEC>(x + i0, xv[u]);
-                load4_full<VEC>(y + i0, yv[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < U; u++)
-                body(xv[u], yv[u], base + (int64_t)u * CHUNK + threadIdx.x * EPT, 4);
-        }
-    }
-    for (; base + CHUNK <= end; base += CHUNK) {
-        const int64_t i0 = base + threadIdx.x * EPT;
-        double xv[4], yv[4];
-        load4_full<VEC>(x + i0, xv);
-        load4_full<VEC>(y + i0, yv);
-        body(xv, yv, i0, 4);
-    }
-    if (base < end) {
-        const int64_t i0 = base + threadIdx.x * EPT;
-        const int64_t left = end - i0;
-        const int lim = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
-        double xv[4], yv[4];
-        load4_tail(x + i0, lim, xv);
-        load4_tail(y + i0, lim, yv);
-        body(xv, yv, i0, lim);
-    }
 }
 
 __device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v)
@@ -235,12 +210,13 @@ struct CutParams {
 // final.  Returns the parameters of pass 2 to every thread.  The scores are
 // taken against e_ref = e_max - dref (dref > 0 only when the guaranteed mode
 // reselects against a lower estimate of flexp(x.y), Thm 3.4); bound_rel
-// stays the Thm 3.3 sum relative to e_max.
+// stays the Thm 3.3 sum relative to e_max.  mu_single: the inputs are
+// single precision, so eq. (precision-def) has no double row.
 template <int NT, class Get, class Put, class Clear>
 __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsigned int bad,
                                   int64_t n, double tol, int score_mode, int nonstrict,
                                   Get get, Put put, Clear clear, qdot_result *out,
-                                  long long *hist_out, int dref = 0)
+                                  long long *hist_out, int dref = 0, int mu_single = 0)
 {
     constexpr int NW = NT / 64;
     __shared__ int s_max[NW], s_min[NW], s_nb[NW], s_unatt[NW];
@@ -339,7 +315,10 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
             // eq. (bin-score-def) with exact bins (u_k = k)
             const int sigma = ceil_log2_u64(v) + k - e_ref - t + 1;
             cls = class_of(sigma, nonstrict);
-            unatt |= sigma >= 52 + (nonstrict ? 1 : 0);
+            // single inputs (mu = m_single): no double row; such a bin stays
+            // at the input precision and is flagged like a double bin >= 52
+            if (mu_single && cls == QDOT_DOUBLE) cls = QDOT_SINGLE;
+            unatt |= sigma >= (mu_single ? 23 : 52) + (nonstrict ? 1 : 0);
             cc[cls] += v;
             // Thm 3.3 term M_k 2^(k - e_max + 1) eps(class)
             bound += ldexp((double)v * eps_of_class(cls), k - e_max + 1);
@@ -374,8 +353,10 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
         out->bound_rel = bsum;
         out->bound_abs = ldexp(bsum, e_max);
         int flags = ua ? QDOT_F_UNATTAINABLE : 0;
-        // Thm 3.6: e_ref - e_min <= -t - m_single
-        if ((long long)e_ref - out->e_min <= -(long long)t - 23) flags |= QDOT_F_THM_ALL_DOUBLE;
+        // Thm 3.6: e_ref - e_min <= -t - m, m = m_single (double inputs) or
+        // m_half (single inputs): every bin at the input precision
+        if ((long long)e_ref - out->e_min <= -(long long)t - (mu_single ? 10 : 23))
+            flags |= QDOT_F_THM_ALL_DOUBLE;
         const bool none_kept = (tc[0] + tc[1] + tc[2]) == 0;
         out->passes = none_kept ? 0 : 1;
         if (none_kept) {
@@ -404,8 +385,11 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
 // (levels 1-2 in the lane, 3-6 across the 16-lane row), and one lane per
 // row adds the two tile sums to its FP64 accumulators.  Every lane of the
 // wave must be active.
-template <bool CLS>
-__device__ __forceinline__ void acc_group(const double *xv, const double *yv, int lim,
+// T is the input type: a float operand is widened exactly to double, so the
+// same decomposition and leaves serve single-precision inputs (whose class
+// table never holds the double class).
+template <bool CLS, class T>
+__device__ __forceinline__ void acc_group(const T *xv, const T *yv, int lim,
                                           const unsigned char *lut, int key_mode, int e_max,
                                           int c32, bool accumulate, Acc &aD, Acc &aS, Acc &aH,
                                           unsigned char *cls_out)
@@ -414,7 +398,7 @@ __device__ __forceinline__ void acc_group(const double *xv, const double *yv, in
     double ld[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-        const Comp c = component(xv[e], yv[e], key_mode);
+        const Comp c = component((double)xv[e], (double)yv[e], key_mode);
         const bool valid = e < lim;
         const int cls = valid ? (int)lut[c.slot] : QDOT_PERF;
         if (CLS && valid) cls_out[e] = (unsigned char)cls;

@@ -22,9 +22,9 @@ namespace qd {
 // histograms (blockIdx % HIST_COPIES, i.e. one per XCD under round-robin
 // dispatch) so that the merge atomics of concurrent blocks spread out.
 // ---------------------------------------------------------------------------
-template <bool VEC, int U>
-__global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
-                                                const double *__restrict__ y,
+template <class T, bool VEC, int U>
+__global__ __launch_bounds__(BLOCK) void k_scan(const T *__restrict__ x,
+                                                const T *__restrict__ y,
                                                 int64_t n, int key_mode,
                                                 Ws *__restrict__ ws)
 {
@@ -33,10 +33,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
     __syncthreads();
 
     unsigned int nz = 0, bad = 0, sg = 0;
-    stream_groups<VEC, U>(x, y, n, [&](const double *xv, const double *yv, int64_t, int lim) {
+    // float inputs are widened exactly; the key is that of the same values
+    stream_groups<VEC, U>(x, y, n, [&](const T *xv, const T *yv, int64_t, int lim) {
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const Comp c = component(xv[e], yv[e], key_mode);
+            const Comp c = component((double)xv[e], (double)yv[e], key_mode);
             const bool valid = e < lim;
             nz += (valid & c.zero) ? 1u : 0u;
             bad |= (valid & c.bad) ? 1u : 0u;
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const double *__restrict__ x,
 __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double tol,
                                                      int score_mode, int nonstrict,
                                                      int64_t n, int nscan, int guard,
+                                                     int mu_single,
                                                      qdot_result *__restrict__ out,
                                                      long long *__restrict__ hist_out)
 {
@@ -145,7 +147,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
         for (int c = 0; c < HIST_COPIES; c++) ws->hist[c][j] = 0ull;
     };
     const CutParams p = block_cutoff<CUT_THREADS>(lo, hi, nzero, bad, n, tol, score_mode,
-                                                  nonstrict, get, put, clear, out, hist_out);
+                                                  nonstrict, get, put, clear, out, hist_out, 0,
+                                                  mu_single);
     if (tid < W_LUT - W) ws->lut[W + tid] = (unsigned char)QDOT_PERF;
     if (tid == 0) {
         ws->n_zero = 0;
@@ -175,9 +178,9 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
 // All three candidates are formed without branches and the class selects
 // one; the only branch is the rare zero/subnormal operand path.
 // ---------------------------------------------------------------------------
-template <bool VEC, int U, bool CLS>
-__global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
-                                               const double *__restrict__ y,
+template <class T, bool VEC, int U, bool CLS>
+__global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
+                                               const T *__restrict__ y,
                                                int64_t n, int key_mode,
                                                const Ws *__restrict__ ws,
                                                double *__restrict__ partials,
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const double *__restrict__ x,
 
     const int lane = threadIdx.x & 63;
     Acc aD = {0.0, 0.0}, aS = {0.0, 0.0}, aH = {0.0, 0.0};
-    stream_groups<VEC, U>(x, y, n, [&](const double *xv, const double *yv, int64_t i0, int lim) {
+    stream_groups<VEC, U>(x, y, n, [&](const T *xv, const T *yv, int64_t i0, int lim) {
         acc_group<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
                        CLS ? cls_out + i0 : nullptr);
     });
@@ -575,45 +578,51 @@ static int grid_for(int64_t n, int unroll, int cap)
     return (int)std::max<int64_t>(1, std::min<int64_t>(cap, groups));
 }
 
-template <bool VEC, int U>
-static int launch_scan_u(const Launch &L, const double *x, const double *y, int64_t n,
-                         int key_mode)
+// Groups in flight per wave: a group of single-precision inputs is half the
+// bytes of a double group, so float launches keep twice as many (at most 4).
+template <class T>
+static int unroll_for(int u)
+{
+    return sizeof(T) == 4 ? std::min(4, 2 * u) : u;
+}
+
+template <class T, bool VEC, int U>
+static int launch_scan_u(const Launch &L, const T *x, const T *y, int64_t n, int key_mode)
 {
     const int grid = grid_for(n, U, L.scan_blocks);
-    hipLaunchKernelGGL((k_scan<VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+    hipLaunchKernelGGL((k_scan<T, VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
                        key_mode, L.ws);
     return grid;
 }
 
-template <bool VEC>
-static int launch_scan(const Launch &L, const double *x, const double *y, int64_t n,
-                       int key_mode)
+template <class T, bool VEC>
+static int launch_scan(const Launch &L, const T *x, const T *y, int64_t n, int key_mode)
 {
-    switch (L.scan_unroll) {
-    case 1: return launch_scan_u<VEC, 1>(L, x, y, n, key_mode);
-    case 4: return launch_scan_u<VEC, 4>(L, x, y, n, key_mode);
-    default: return launch_scan_u<VEC, 2>(L, x, y, n, key_mode);
+    switch (unroll_for<T>(L.scan_unroll)) {
+    case 1: return launch_scan_u<T, VEC, 1>(L, x, y, n, key_mode);
+    case 4: return launch_scan_u<T, VEC, 4>(L, x, y, n, key_mode);
+    default: return launch_scan_u<T, VEC, 2>(L, x, y, n, key_mode);
     }
 }
 
-template <bool VEC, int U, bool CLS>
-static int launch_acc_u(const Launch &L, const double *x, const double *y, int64_t n,
-                        int key_mode, unsigned char *cls_out)
+template <class T, bool VEC, int U, bool CLS>
+static int launch_acc_u(const Launch &L, const T *x, const T *y, int64_t n, int key_mode,
+                        unsigned char *cls_out)
 {
     const int grid = grid_for(n, U, L.acc_blocks);
-    hipLaunchKernelGGL((k_acc<VEC, U, CLS>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+    hipLaunchKernelGGL((k_acc<T, VEC, U, CLS>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
                        key_mode, L.ws, L.partials, cls_out);
     return grid;
 }
 
-template <bool VEC, bool CLS>
-static int launch_acc(const Launch &L, const double *x, const double *y, int64_t n,
-                      int key_mode, unsigned char *cls_out)
+template <class T, bool VEC, bool CLS>
+static int launch_acc(const Launch &L, const T *x, const T *y, int64_t n, int key_mode,
+                      unsigned char *cls_out)
 {
-    switch (L.acc_unroll) {
-    case 1: return launch_acc_u<VEC, 1, CLS>(L, x, y, n, key_mode, cls_out);
-    case 4: return launch_acc_u<VEC, 4, CLS>(L, x, y, n, key_mode, cls_out);
-    default: return launch_acc_u<VEC, 2, CLS>(L, x, y, n, key_mode, cls_out);
+    switch (unroll_for<T>(L.acc_unroll)) {
+    case 1: return launch_acc_u<T, VEC, 1, CLS>(L, x, y, n, key_mode, cls_out);
+    case 4: return launch_acc_u<T, VEC, 4, CLS>(L, x, y, n, key_mode, cls_out);
+    default: return launch_acc_u<T, VEC, 2, CLS>(L, x, y, n, key_mode, cls_out);
     }
 }
 
@@ -650,7 +659,7 @@ static hipError_t launch_qdot_s1(const Launch &L, const double *x, const double 
                           : launch_s1<false>(L, x, y, n, o.key_mode, depth);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
     hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, nscan, 0, out, nullptr);
+                       o.boundary_mode, n, nscan, 0, 0, out, nullptr);
     if (L.ev) {
         (void)hipEventRecord(L.ev[2], s);
         (void)hipEventRecord(L.ev[3], s);
@@ -660,33 +669,37 @@ static hipError_t launch_qdot_s1(const Launch &L, const double *x, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_t n,
-                       double tol, const qdot_options &o, qdot_result *out,
-                       unsigned char *cls_out, long long *hist_out)
+// Two-pass qdot of T inputs (double, or float with mu = m_single): scan,
+// cutoff, accumulate, finalize, and in the guaranteed mode the guard stages
+// around a second sweep.
+template <class T>
+static hipError_t launch_qdot_t(const Launch &L, const T *x, const T *y, int64_t n, double tol,
+                                const qdot_options &o, qdot_result *out,
+                                unsigned char *cls_out, long long *hist_out)
 {
-    if (o.accum_mode == 1) return launch_qdot_s1(L, x, y, n, tol, o, out);
     const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
     const int guard = o.guard_mode;
+    const int mu_single = sizeof(T) == 4 ? 1 : 0;
     // the guaranteed mode keeps the histogram for its reselection
     long long *hs = hist_out;
     if (guard && !hs)
         hs = reinterpret_cast<long long *>(reinterpret_cast<char *>(L.ws) + offsetof(Ws, hsave));
     hipStream_t s = L.stream;
     if (L.ev) (void)hipEventRecord(L.ev[0], s);
-    const int nscan = vec ? launch_scan<true>(L, x, y, n, o.key_mode)
-                          : launch_scan<false>(L, x, y, n, o.key_mode);
+    const int nscan = vec ? launch_scan<T, true>(L, x, y, n, o.key_mode)
+                          : launch_scan<T, false>(L, x, y, n, o.key_mode);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
     hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, nscan, guard, out, hs);
+                       o.boundary_mode, n, nscan, guard, mu_single, out, hs);
     if (L.ev) (void)hipEventRecord(L.ev[2], s);
     auto sweep = [&]() {
         int grid;
         if (cls_out)
-            grid = vec ? launch_acc<true, true>(L, x, y, n, o.key_mode, cls_out)
-                       : launch_acc<false, true>(L, x, y, n, o.key_mode, cls_out);
+            grid = vec ? launch_acc<T, true, true>(L, x, y, n, o.key_mode, cls_out)
+                       : launch_acc<T, false, true>(L, x, y, n, o.key_mode, cls_out);
         else
-            grid = vec ? launch_acc<true, false>(L, x, y, n, o.key_mode, nullptr)
-                       : launch_acc<false, false>(L, x, y, n, o.key_mode, nullptr);
+            grid = vec ? launch_acc<T, true, false>(L, x, y, n, o.key_mode, nullptr)
+                       : launch_acc<T, false, false>(L, x, y, n, o.key_mode, nullptr);
         return grid;
     };
     int grid = sweep();
@@ -704,6 +717,21 @@ hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_
     }
     if (L.ev) (void)hipEventRecord(L.ev[4], s);
     return hipGetLastError();
+}
+
+hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_t n,
+                       double tol, const qdot_options &o, qdot_result *out,
+                       unsigned char *cls_out, long long *hist_out)
+{
+    if (o.accum_mode == 1) return launch_qdot_s1(L, x, y, n, tol, o, out);
+    return launch_qdot_t<double>(L, x, y, n, tol, o, out, cls_out, hist_out);
+}
+
+hipError_t launch_qdot_f32(const Launch &L, const float *x, const float *y, int64_t n,
+                           double tol, const qdot_options &o, qdot_result *out,
+                           unsigned char *cls_out, long long *hist_out)
+{
+    return launch_qdot_t<float>(L, x, y, n, tol, o, out, cls_out, hist_out);
 }
 
 template <bool VEC, int U>

@@ -33,6 +33,12 @@ hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_
                        double tol, const qdot_options &o, qdot_result *out,
                        unsigned char *cls_out, long long *hist_out);
 
+// The two-pass qdot of single-precision inputs (mu = m_single: no double
+// class); accum_mode and guard_mode must be 0.
+hipError_t launch_qdot_f32(const Launch &L, const float *x, const float *y, int64_t n,
+                           double tol, const qdot_options &o, qdot_result *out,
+                           unsigned char *cls_out, long long *hist_out);
+
 // Enqueue the plain FP64 dot; *out receives sum x_i y_i.
 hipError_t launch_dot64(const Launch &L, const double *x, const double *y, int64_t n,
                         double *out);

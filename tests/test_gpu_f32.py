@@ -1,0 +1,168 @@
+"""GPU parity of qdot on single-precision inputs (mu = m_single) through the
+C ABI: classes, histogram, counts and flags bit for bit against the oracle's
+float path, values within 1e-13 * sum |x_i y_i|."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+import paper_2105_00115_amd as q  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+VALUE_TOL = 1e-13
+INT_KEYS = ("count", "n_zero", "e_min", "e_max", "n_bins", "t", "flags", "status", "e_ref",
+            "passes")
+
+
+@pytest.fixture(scope="module")
+def h():
+    handle = q.Qdot(0)
+    yield handle
+    handle.close()
+
+
+def devf(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+def compare(h, x, y, tol, opt=None, xd=None, yd=None, classes=True):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    print(f"[gpu-case] f32 n={len(x)} tol={tol} opt={opt}", flush=True)
+    xd = devf(x) if xd is None else xd
+    yd = devf(y) if yd is None else yd
+    if classes:
+        cls, hist, r = h.qdot_f32_classes(xd, yd, tol, opt=opt)
+        o = oracle.qdot_f32(x, y, tol, opt=opt, want_classes=True, want_hist=True)
+    else:
+        r = h.qdot_f32(xd, yd, tol, opt=opt)
+        o = oracle.qdot_f32(x, y, tol, opt=opt)
+    for k in INT_KEYS:
+        assert r[k] == o[k], (k, r[k], o[k])
+    if o["status"] != oracle.OK:
+        return r, o
+    if classes:
+        np.testing.assert_array_equal(cls.cpu().numpy(), o["classes"])
+        np.testing.assert_array_equal(hist.cpu().numpy(), o["hist"])
+    scale = oracle.abs_dot(x.astype(np.float64), y.astype(np.float64))
+    assert abs(r["value"] - o["value"]) <= VALUE_TOL * scale, (r["value"], o["value"], scale)
+    for c in range(3):
+        assert abs(r["part"][c] - o["part"][c]) <= VALUE_TOL * scale, c
+    assert abs(r["bound_rel"] - o["bound_rel"]) <= 1e-12 * abs(o["bound_rel"])
+    assert r["count"][q.DOUBLE] == 0
+    return r, o
+
+
+def test_small_integers_exact(h):
+    g = workloads.rng(51)
+    for n in (1, 63, 64, 1000, 4097, 70001):
+        x = g.integers(-50, 51, n).astype(np.float32)
+        y = g.integers(-50, 51, n).astype(np.float32)
+        r, _ = compare(h, x, y, 1e-30)
+        assert r["value"] == float(np.dot(x.astype(np.int64), y.astype(np.int64)))
+
+
+def test_hand_example(h):
+    r, _ = compare(h, np.ones(4), np.ones(4), 1e-9)
+    assert r["value"] == 4.0 and r["t"] == -30
+    assert r["flags"] == q.F_UNATTAINABLE | q.F_THM_ALL_DOUBLE
+
+
+@pytest.mark.parametrize("n", [1, 1000, 1023, 65573, 300001])
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-10])
+def test_log_uniform_law(h, n, tol):
+    # the single-qdot law narrowed to the float range: +-10^U[-15, 15]
+    x, y = workloads.log_uniform_pair(n, 60 + n % 89, -15.0, 15.0)
+    compare(h, x, y, tol)
+
+
+@pytest.mark.parametrize("family,t", [("A", 10), ("A", 60), ("B", 5), ("B", 13), ("B", 30)])
+def test_paper_families(h, family, t):
+    fn = workloads.paper_dist_a if family == "A" else workloads.paper_dist_b
+    x, y = fn(50000, t, 70 + t)
+    for tol in (1e-2, 1e-5, 1e-8):
+        compare(h, x, y, tol)
+
+
+@pytest.mark.parametrize("opt", [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [1, 1, 1, 0]])
+def test_options(h, opt):
+    x, y = workloads.log_uniform_pair(100000, 75, -15.0, 15.0)
+    compare(h, x, y, 1e-6, opt=opt)
+
+
+def test_same_as_double_inputs_where_no_double_class(h):
+    # the widened values through the double path: identical keys, counts and
+    # value whenever that path keeps no double bin
+    x, y = workloads.log_uniform_pair(200000, 76, -15.0, 15.0)
+    xf, yf = devf(x), devf(y)
+    rs = h.qdot_f32(xf, yf, 1e-2)
+    rd = h.qdot(xf.double(), yf.double(), 1e-2)
+    assert rd["count"][q.DOUBLE] == 0
+    for k in ("count", "n_bins", "e_max", "e_min", "t", "flags", "bound_rel"):
+        assert rs[k] == rd[k], k
+    assert rs["value"] == rd["value"]
+
+
+def test_edge_cases(h):
+    compare(h, np.zeros(1000), np.ones(1000), 1e-6)
+    # float subnormals and zeros
+    g = workloads.rng(77)
+    xs = np.ldexp(g.uniform(1, 2, 3001), g.integers(-149, -126, 3001)) * g.choice([-1, 1], 3001)
+    ys = np.ldexp(g.uniform(1, 2, 3001), g.integers(60, 120, 3001))
+    xs[::13] = 0.0
+    compare(h, xs, ys, 1e-6)
+    # 4-byte but not 16-byte aligned views: the scalar load path
+    x, y = workloads.log_uniform_pair(20001, 78, -15.0, 15.0)
+    xd = devf(np.concatenate([[0.0], x]))
+    yd = devf(np.concatenate([[0.0], y]))
+    compare(h, x, y, 1e-6, xd=xd[1:], yd=yd[1:])
+    xb = np.ones(100, dtype=np.float32)
+    xb[7] = np.nan
+    r = h.qdot_f32(devf(xb), devf(np.ones(100)), 1e-6)
+    assert r["status"] == q.E_NONFINITE and np.isnan(r["value"])
+
+
+def test_rejected_options(h):
+    x = devf(np.ones(100))
+    for opt in ([0, 0, 0, 1], [0, 0, 0, 0, 1]):
+        with pytest.raises(q.QdotError):
+            h.qdot_f32(x, x, 1e-6, opt=opt)
+    with pytest.raises(ValueError):
+        h.qdot_f32(x.double(), x.double(), 1e-6)
+
+
+def test_graph_replay(h):
+    x, y = workloads.log_uniform_pair(300001, 79, -15.0, 15.0)
+    xd, yd = devf(x), devf(y)
+    eager = torch.zeros(q.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+    h.qdot_f32_async(xd, yd, 1e-6, eager)
+    torch.cuda.synchronize()
+    out = torch.zeros_like(eager)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            h.qdot_f32_async(xd, yd, 1e-6, out)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        h.qdot_f32(xd[:5000], yd[:5000], 1e-3)
+        torch.cuda.synchronize()
+
+
+@pytest.mark.timeout(400)
+def test_full_size(h):
+    """n = 2**27 floats (512 MiB per vector) at tol 1e-6."""
+    n = 1 << 27
+    print(f"[gpu-case] f32 full size n={n}", flush=True)
+    x, y = workloads.log_uniform_pair(n, 2028, -15.0, 15.0)
+    compare(h, x, y, 1e-6, classes=False)
