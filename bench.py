@@ -243,13 +243,13 @@ def main():
     g1 = [0, 0, 0, 0, 1]
     guard = {}
 
-    def time_calls(xv, yv, opt, calls=10):
+    def time_calls(xv, yv, opt, calls=10, tol_c=tol):
         for _ in range(2):
-            h.qdot_async(xv, yv, tol, out, opt=opt)
+            h.qdot_async(xv, yv, tol_c, out, opt=opt)
         torch.cuda.synchronize()
         c0 = time.perf_counter()
         for _ in range(calls):
-            h.qdot_async(xv, yv, tol, out, opt=opt)
+            h.qdot_async(xv, yv, tol_c, out, opt=opt)
         torch.cuda.synchronize()
         return (time.perf_counter() - c0) / calls
 
@@ -259,10 +259,12 @@ def main():
                          "passes": rg["passes"], "certified": bool(rg["flags"] & q.F_GUARANTEED),
                          "reselected": bool(rg["flags"] & q.F_RESELECTED)}
     xc, yc = workloads.paired_cancelling_torch(n, 41, 1e-4, dev)
-    for name, opt in (("default", None), ("guard", g1)):
-        tc = time_calls(xc, yc, opt)
+    cases = [(tol_c, name, opt) for tol_c in (tol, 1e-5)
+             for name, opt in (("default", None), ("guard", g1))]
+    for tol_c, name, opt in cases:
+        tc = time_calls(xc, yc, opt, tol_c=tol_c)
         rc = q.parse_results(out)[0]
-        guard["paired_cancelling_1e-4_" + name] = {
+        guard[f"paired_cancelling_1e-4_tol{tol_c:g}_" + name] = {
             "gelem_s": round(n / tc / 1e9, 3), "ms_per_call": round(tc * 1e3, 4),
             "passes": rc["passes"], "e_max": rc["e_max"], "e_ref": rc["e_ref"],
             "count": rc["count"], "certified": bool(rc["flags"] & q.F_GUARANTEED),
