@@ -45,16 +45,21 @@ bool tune_ok(const qdot_tune &t)
            u_ok(t.onepass_unroll);
 }
 
-Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n)
+Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n, bool single)
 {
     const qdot_tune &t = h->tune[bucket_of(n)];
+    // single-precision inputs: a group is half the bytes, so twice the
+    // blocks per CU (at most 8; the kernels also double the groups in
+    // flight), which measured fastest for both passes on 2^27 floats
+    const int f = single ? 2 : 1;
     Launch L;
     L.stream = s;
     L.ws = h->ws;
     L.partials = h->partials;
-    L.scan_blocks = std::min(MAX_GRID, t.scan_blocks_per_cu * h->num_cus);
+    L.scan_blocks = std::min(MAX_GRID, std::min(8, f * t.scan_blocks_per_cu) * h->num_cus);
     L.scan_unroll = t.scan_unroll;
-    L.acc_blocks = std::min(h->partial_blocks, t.acc_blocks_per_cu * h->num_cus);
+    L.acc_blocks = std::min(h->partial_blocks,
+                            std::min(8, f * t.acc_blocks_per_cu) * h->num_cus);
     L.acc_unroll = t.acc_unroll;
     L.s1_blocks = std::min(MAX_GRID, t.onepass_blocks_per_cu * h->num_cus);
     L.s1_unroll = t.onepass_unroll;
@@ -311,7 +316,7 @@ int32_t qdot_f32_async(qdot_handle *h, const float *x, const float *y, int64_t n
     if (st != QDOT_OK) return st;
     if (!dev_out) return fail(h, QDOT_E_INVAL, "dev_out is NULL");
     DeviceGuard g(h->device);
-    Launch L = make_launch(h, (hipStream_t)stream, n);
+    Launch L = make_launch(h, (hipStream_t)stream, n, true);
     L.ev = take_events(h, 0);
     hipError_t e = launch_qdot_f32(L, x, y, n, tol, o, dev_out, nullptr, nullptr);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot_f32 launch");
@@ -342,7 +347,7 @@ int32_t qdot_f32_classes_async(qdot_handle *h, const float *x, const float *y, i
     if (st != QDOT_OK) return st;
     if (!dev_out || (n > 0 && !dev_cls)) return fail(h, QDOT_E_INVAL, "NULL output");
     DeviceGuard g(h->device);
-    hipError_t e = launch_qdot_f32(make_launch(h, (hipStream_t)stream, n), x, y, n, tol, o,
+    hipError_t e = launch_qdot_f32(make_launch(h, (hipStream_t)stream, n, true), x, y, n, tol, o,
                                    dev_out, dev_cls, (long long *)dev_hist);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot_f32_classes launch");
 }

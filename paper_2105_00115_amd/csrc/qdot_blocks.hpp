@@ -385,9 +385,10 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
 // (levels 1-2 in the lane, 3-6 across the 16-lane row), and one lane per
 // row adds the two tile sums to its FP64 accumulators.  Every lane of the
 // wave must be active.
-// T is the input type: a float operand is widened exactly to double, so the
-// same decomposition and leaves serve single-precision inputs (whose class
-// table never holds the double class).
+// T is the input type.  Single-precision inputs (whose class table never
+// holds the double class) take the float decomposition: the same single and
+// half leaves bit for bit, formed in FP32 (the float significands are exact),
+// and no double leaf.
 template <bool CLS, class T>
 __device__ __forceinline__ void acc_group(const T *xv, const T *yv, int lim,
                                           const unsigned char *lut, int key_mode, int e_max,
@@ -395,6 +396,32 @@ __device__ __forceinline__ void acc_group(const T *xv, const T *yv, int lim,
                                           unsigned char *cls_out)
 {
     float ls[4], lh[4];
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const CompF c = component_f(xv[e], yv[e], key_mode);
+            const bool valid = e < lim;
+            const int cls = valid ? (int)lut[c.slot] : QDOT_PERF;
+            if (CLS && valid) cls_out[e] = (unsigned char)cls;
+            const float ps = c.mx * c.my;
+            const float ph = half_round_f(c.mx) * half_round_f(c.my);  // 22 bits: exact
+            float l32 = ldexpf(cls == QDOT_HALF ? ph : ps, c.es - c32);
+            l32 = __int_as_float(__float_as_int(l32) ^ (int)c.sgn);
+            ls[e] = cls == QDOT_SINGLE ? l32 : 0.0f;
+            lh[e] = cls == QDOT_HALF ? l32 : 0.0f;
+        }
+        if (accumulate) {
+            const float s4 = (ls[0] + ls[1]) + (ls[2] + ls[3]);
+            const float h4 = (lh[0] + lh[1]) + (lh[2] + lh[3]);
+            const float ts = tile_levels_3to6(s4);
+            const float th = tile_levels_3to6(h4);
+            if ((threadIdx.x & 15) == 0) {
+                acc_add(aS, (double)ts);
+                acc_add(aH, (double)th);
+            }
+        }
+        return;
+    }
     double ld[4];
 #pragma unroll
     for (int e = 0; e < 4; e++) {

@@ -140,6 +140,56 @@ __device__ __forceinline__ Comp component(double x, double y, int key_mode)
     return c;
 }
 
+// Single-precision operands: the same decomposition on 32-bit words.  The
+// significands are floats in [1, 2) (exact), and the product key's carry is
+// decided exactly from the FP32 product p and its FMA residual r (the exact
+// product is p + r; it reaches 2 iff p > 2, or p == 2 and r >= 0).  Zero and
+// subnormal operands take the double path: a float widens exactly.
+struct CompF {
+    int es;
+    int slot;
+    uint32_t sgn;
+    bool zero;
+    bool bad;
+    float mx, my;
+};
+
+__device__ __forceinline__ CompF component_f(float x, float y, int key_mode)
+{
+    CompF c;
+    const uint32_t bx = __float_as_uint(x), by = __float_as_uint(y);
+    const uint32_t cx = (bx >> 23) & 0xffu, cy = (by >> 23) & 0xffu;
+    c.sgn = (bx ^ by) & 0x80000000u;
+    if (__builtin_expect(min(cx, cy) == 0, 0)) {
+        const Comp d = component((double)x, (double)y, key_mode);
+        c.es = d.es;
+        c.slot = d.slot;
+        c.zero = d.zero;
+        c.bad = d.bad;
+        c.mx = (float)d.mx;
+        c.my = (float)d.my;
+        return c;
+    }
+    c.mx = __uint_as_float((bx & 0x7fffffu) | 0x3f800000u);
+    c.my = __uint_as_float((by & 0x7fffffu) | 0x3f800000u);
+    c.es = (int)(cx + cy) - 254;
+    c.zero = false;
+    c.bad = max(cx, cy) == 0xffu;
+    const float p = c.mx * c.my;
+    const float r = __builtin_fmaf(c.mx, c.my, -p);
+    const int carry = (key_mode == 0 && (p > 2.0f || (p == 2.0f && r >= 0.0f))) ? 1 : 0;
+    c.slot = c.bad ? ZERO_SLOT : (c.es + carry - KMIN);
+    return c;
+}
+
+// Binary16 significand of a float m in [1, 2): adding 2^13 leaves an ulp of
+// 2^-10, so the sum rounds m to 10 fraction bits (nearest even) exactly once.
+__device__ __forceinline__ float half_round_f(float m)
+{
+    const float big = 0x1p13f;
+    return (m + big) - big;
+}
+
 // Binary16 significand of m in [1, 2), round to nearest even in one step
 // straight from FP64: m + 2^42 has an ulp of 2^-10, so the addition rounds
 // m to the nearest multiple of 2^-10 (ties to even) and the subtraction is

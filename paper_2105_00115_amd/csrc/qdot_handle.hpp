@@ -59,7 +59,9 @@ struct DeviceGuard {
 
 int32_t fail(qdot_handle *h, int32_t code, const std::string &msg);
 int32_t hip_fail(qdot_handle *h, hipError_t e, const char *where);
-Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n);
+// Launch shape of a call on n components (the tune bucket of n); single:
+// single-precision inputs.
+Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n, bool single = false);
 qdot_tune default_tune(int bucket);
 bool tune_ok(const qdot_tune &t);
 // Events for one timed call of `kind` (0: qdot, 5 events; 1: FP64 dot, 2),

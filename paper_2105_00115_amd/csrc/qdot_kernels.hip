@@ -33,11 +33,14 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const T *__restrict__ x,
     __syncthreads();
 
     unsigned int nz = 0, bad = 0, sg = 0;
-    // float inputs are widened exactly; the key is that of the same values
+    // float inputs: the 32-bit decomposition gives the key of the same values
     stream_groups<VEC, U>(x, y, n, [&](const T *xv, const T *yv, int64_t, int lim) {
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const Comp c = component((double)xv[e], (double)yv[e], key_mode);
+            const auto c = [&]() {
+                if constexpr (sizeof(T) == 4) return component_f(xv[e], yv[e], key_mode);
+                else return component(xv[e], yv[e], key_mode);
+            }();
             const bool valid = e < lim;
             nz += (valid & c.zero) ? 1u : 0u;
             bad |= (valid & c.bad) ? 1u : 0u;
