@@ -4,7 +4,7 @@
  * qdot is the error-bounded quantized dot product of Diffenderfer,
  * Osei-Kuffuor and Menon ("Qdot: Quantized Dot Product Kernel for
  * Approximate High Performance Computing", arXiv 2105.00115).  Given FP64
- * vectors x, y and a relative tolerance eps it
+ * vectors x, y (or FP32 vectors, qdot_f32*) and a relative tolerance eps it
  *   1. bins the component products x_i y_i by their binary exponent
  *      (Def. 3.1 with exact binning, Sec. 3.2; Alg. 2),
  *   2. scores every non-empty bin (eq. bin-score-def) and gives it a
@@ -16,8 +16,8 @@
  *
  * Conventions for every entry point:
  *   - Vectors and matrices are device pointers (hipMalloc'd or any memory a
- *     gfx950 kernel may read), 8-byte aligned, owned by the caller; the
- *     library never frees or retains them past the call.
+ *     gfx950 kernel may read), aligned to their element size, owned by the
+ *     caller; the library never frees or retains them past the call.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Entry points named *_async only enqueue work and return; their
  *     results are written to device memory in stream order.  Others
@@ -63,12 +63,16 @@ extern "C" {
 #define QDOT_PERF 3 /* perforated: left out of the sum */
 
 /* ---- result flags ---------------------------------------------------- */
-#define QDOT_F_UNATTAINABLE 1  /* some bin scored >= m_double (52): no
-                                  precision row of eq. (precision-def)
-                                  applies; it stays double and the bound may
-                                  exceed eps */
-#define QDOT_F_THM_ALL_DOUBLE 2 /* Thm 3.6 condition e_max - e_min <= -t - 23
-                                  holds: every bin is double */
+#define QDOT_F_UNATTAINABLE 1  /* some bin scored >= the input precision's
+                                  mantissa width (52 for double inputs, 23
+                                  for single): no precision row of eq.
+                                  (precision-def) applies; it stays at the
+                                  input precision and the bound may exceed
+                                  eps */
+#define QDOT_F_THM_ALL_DOUBLE 2 /* Thm 3.6 condition e_max - e_min <= -t - m
+                                  holds (m = 23 for double inputs, 10 for
+                                  single): every bin is at the input
+                                  precision */
 #define QDOT_F_ALL_PERF 4      /* no component kept; value is +0 */
 #define QDOT_F_OVERFLOW 8      /* the final scaling by 2^e_max overflowed */
 #define QDOT_F_GUARANTEED 16   /* guard_mode 1: the Thm 3.4 bound, taken with
@@ -191,9 +195,11 @@ typedef struct qdot_cg_system {
 /* ---- launch configuration (autotuner) ---------------------------------- */
 /* Launch shape of the two streaming passes.  Grids are persistent:
  * blocks_per_cu * CUs blocks of 256 threads, each thread keeping `unroll`
- * groups of 4 consecutive components in flight (1, 2 or 4).  No setting
- * changes a class, a count or an FP32 tile sum: the 64-element tiles are
- * fixed by the index order. */
+ * groups of 4 consecutive components in flight (1, 2 or 4).  Calls on
+ * single-precision inputs (qdot_f32*) use twice the blocks per CU (at most
+ * 8) and twice the unroll (at most 4) of their bucket: their groups are
+ * half the bytes.  No setting changes a class, a count or an FP32 tile sum:
+ * the 64-element tiles are fixed by the index order. */
 typedef struct qdot_tune {
     int32_t scan_blocks_per_cu; /* exponent scan, 1..16 */
     int32_t scan_unroll;
@@ -232,9 +238,10 @@ QDOT_API int32_t qdot_get_tune(const qdot_handle *h, int32_t bucket, qdot_tune *
 /* Load tuned configurations from a text file written by the autotuner: one
  * line per bucket, "bucket scan_bpc scan_unroll acc_bpc acc_unroll
  * [onepass_bpc onepass_unroll]" (without the last two the bucket's one-pass
- * shape is left as it is), '#' starts a comment.  Invalid lines are rejected with QDOT_E_INVAL and leave
- * the handle unchanged.  qdot_create also loads the file named by the
- * environment variable QDOT_TUNE_FILE when it is set. */
+ * shape is left as it is), '#' starts a comment.  Invalid lines are
+ * rejected with QDOT_E_INVAL and leave the handle unchanged.  qdot_create
+ * also loads the file named by the environment variable QDOT_TUNE_FILE when
+ * it is set. */
 QDOT_API int32_t qdot_load_tune(qdot_handle *h, const char *path);
 
 /* Kernel timing (diagnostics).  While enabled, every qdot and FP64-dot call
@@ -242,9 +249,10 @@ QDOT_API int32_t qdot_load_tune(qdot_handle *h, const char *path);
  * launches (not allowed while the stream is being captured into a graph).
  * qdot_timing_read synchronises the recorded events and returns the summed
  * durations in milliseconds of the scan, cutoff, accumulate and finalize
- * kernels of qdot (ms[0..3]) and of the FP64 dot (ms[4], both of its
- * kernels), the number of qdot and FP64-dot calls timed (calls[0..1]), then
- * clears the record. */
+ * kernels of qdot (ms[0..3]; with guard_mode 1, ms[3] also covers the guard
+ * stages and the second sweep; in the one-pass mode ms[2] is 0 and ms[3]
+ * is the pick) and of the FP64 dot (ms[4], both of its kernels), the number
+ * of qdot and FP64-dot calls timed (calls[0..1]), then clears the record. */
 QDOT_API int32_t qdot_timing_enable(qdot_handle *h, int32_t enable);
 QDOT_API int32_t qdot_timing_read(qdot_handle *h, double ms[5], int32_t calls[2]);
 
@@ -337,7 +345,8 @@ QDOT_API int32_t qdot_fp64_dot_async(qdot_handle *h, const double *x, const doub
  * work list, synchronously); later calls with the same layout only launch
  * one kernel: no allocation, no memset, no host sync, graph-capturable.
  * Up to 8 layouts are kept per handle.  Calls on one handle must be ordered
- * on one stream.  Host-side argument errors return QDOT_E_INVAL. */
+ * on one stream.  Host-side argument errors, and guard_mode 1, return
+ * QDOT_E_INVAL. */
 QDOT_API int32_t qdot_batched_async(qdot_handle *h, const double *x_cat,
                                     const double *y_cat, const int64_t *offsets,
                                     const int64_t *host_offsets, const double *tols,
@@ -364,7 +373,8 @@ QDOT_API int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets,
  * compared by value) and is synchronous; later calls with the same layout
  * launch two kernels (a re-arm pass over the gangs and the batch), allocate
  * nothing and can be captured in a graph.  A gang barrier that does not
- * complete within its spin limit gives that system status QDOT_E_DEVICE. */
+ * complete within its spin limit gives that system status QDOT_E_DEVICE.
+ * guard_mode 1 is refused (QDOT_E_INVAL). */
 QDOT_API int32_t qdot_batch_run_async(qdot_handle *h, const double *x_cat,
                                       const double *y_cat, const int64_t *offsets,
                                       const int64_t *host_offsets, const double *tols,
@@ -400,7 +410,7 @@ QDOT_API int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double
  * The whole solve is one persistent launch of up to one block per CU
  * (environment variable QDOT_CG_BLOCKS caps the block count).  A gang
  * barrier that does not complete within its spin limit ends the solve with
- * QDOT_E_DEVICE. */
+ * QDOT_E_DEVICE.  accum_mode and guard_mode must be 0 (QDOT_E_INVAL). */
 QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x,
                 double rtol, double qtol, int32_t maxit, int32_t use_qdot,
                 const qdot_options *opt, void *stream, qdot_cg_result *out,
@@ -411,6 +421,7 @@ QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, dou
  * x = w / sqrt(c), with both dots by qdot at qtol when use_qdot != 0.
  * x: device FP64[n], unit vector on entry, last iterate on exit.
  * lambda (host): last lambda.  lambda_trace: NULL or device FP64[iters].
+ * opt: as qdot_async (the one-pass and guaranteed modes included).
  * Synchronous.  QDOT_E_BREAKDOWN if c <= 0 or not finite. */
 QDOT_API int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x,
                    int32_t iters, double qtol, int32_t use_qdot,
