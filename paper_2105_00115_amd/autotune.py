@@ -47,7 +47,9 @@ def _time_config(h, x, y, tol, out, cfg, reps, opt=None):
     return (t["scan_ms"] / c, t["cut_ms"] / c, t["acc_ms"] / c, t["fin_ms"] / c)
 
 
-def tune(reps: int = 20, seed: int = 7, tol: float = 1e-6, log=print):
+def tune(reps: int = 20, seed: int = 7, tol: float = 1e-6, log=print, buckets=None):
+    """Sweep the launch shapes of the buckets listed (all by default);
+    returns the handle and the chosen shapes with their timings."""
     import torch
 
     import paper_2105_00115_amd as q
@@ -59,6 +61,8 @@ def tune(reps: int = 20, seed: int = 7, tol: float = 1e-6, log=print):
     out = torch.zeros(q.RESULT_BYTES, dtype=torch.uint8, device=dev)
     chosen = []
     for b, n in enumerate(BUCKET_N):
+        if buckets is not None and b not in buckets:
+            continue
         x, y = workloads.log_uniform_pair_torch(n, seed + b, dev)
         ref_cls, ref_hist, ref = h.qdot_classes(x, y, tol)
         results = {}
@@ -121,13 +125,16 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--buckets", default=None,
+                    help="comma-separated bucket indices to tune (default: all)")
     a = ap.parse_args(argv)
     import torch
 
     props = torch.cuda.get_device_properties(0)
     arch = props.gcnArchName.split(":")[0]
     cus = props.multi_processor_count
-    h, chosen = tune(a.reps, log=lambda m: print(m, flush=True))
+    buckets = None if a.buckets is None else [int(b) for b in a.buckets.split(",")]
+    h, chosen = tune(a.reps, log=lambda m: print(m, flush=True), buckets=buckets)
     path = a.out or default_path(arch, cus)
     write(path, chosen, arch, cus)
     h.load_tune(path)  # the file must load back

@@ -312,3 +312,48 @@ def test_binding_before_torch_in_a_fresh_process():
     p = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
                        timeout=240)
     assert p.returncode == 0 and p.stdout.strip().endswith("ok"), p.stderr[-2000:]
+
+
+def test_device_info(h):
+    dev, cus = h.device_info()
+    assert dev == 0 and cus == torch.cuda.get_device_properties(0).multi_processor_count
+
+
+def test_timing_api(h):
+    x, y = workloads.log_uniform_pair(1 << 20, 90)
+    xd, yd = dev(x), dev(y)
+    h.timing_read()  # start from an empty record
+    h.timing_enable(True)
+    for _ in range(3):
+        h.qdot(xd, yd, 1e-6)
+    for _ in range(2):
+        h.fp64_dot(xd, yd)
+    t = h.timing_read()
+    h.timing_enable(False)
+    assert t["qdot_calls"] == 3 and t["dot64_calls"] == 2
+    assert t["scan_ms"] > 0 and t["acc_ms"] > 0 and t["dot64_ms"] > 0
+    assert t["cut_ms"] >= 0 and t["fin_ms"] >= 0
+    # read clears the record; calls while disabled are not timed
+    h.qdot(xd, yd, 1e-6)
+    t2 = h.timing_read()
+    assert t2["qdot_calls"] == 0 and t2["dot64_calls"] == 0 and t2["scan_ms"] == 0.0
+
+
+def test_autotuner_on_small_buckets(tmp_path):
+    # a short sweep of the two smallest buckets: every shape must reproduce
+    # the reference integer outputs (the tuner checks it), the file must load
+    # back, and the tuned handle must give the same counts as the defaults
+    from paper_2105_00115_amd import autotune
+    handle, chosen = autotune.tune(reps=2, buckets=[0, 1], log=lambda m: None)
+    path = str(tmp_path / "tune.txt")
+    autotune.write(path, chosen, "gfx950", handle.device_info()[1])
+    handle.close()
+    assert [c[0] for c in chosen] == [0, 1]
+    with q.Qdot(0, load_tuned=False) as tuned, q.Qdot(0, load_tuned=False) as plain:
+        tuned.load_tune(path)
+        for n in (30000, 500000):
+            x, y = workloads.log_uniform_pair(n, 91)
+            a = tuned.qdot(dev(x), dev(y), 1e-6)
+            b = plain.qdot(dev(x), dev(y), 1e-6)
+            assert a["count"] == b["count"] and a["flags"] == b["flags"]
+            assert abs(a["value"] - b["value"]) <= VALUE_TOL * oracle.abs_dot(x, y)
