@@ -520,7 +520,7 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
         nonstrict < 0 || nonstrict > 1 || accum_mode < 0 || accum_mode > 1 ||
         guard_mode < 0 || guard_mode > 1 ||
         (guard_mode == 1 && (key_mode != 0 || accum_mode != 0)) ||
-        (mu_single && (accum_mode != 0 || guard_mode != 0))) {
+        (mu_single && accum_mode != 0)) {
         r->status = ORC_E_INVAL;
         r->value = NAN;
         return r->status;
@@ -591,15 +591,19 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
     if (guard_mode) {
         /* Guaranteed mode (Thm 3.4).  A certified lower bound of |x.y|
          * gives E_lo <= flexp(x.y); if the Thm 3.4 bound with E_lo does not
-         * meet tol, the classes are selected again against E_lo (or made
-         * all double when |x.y| is not bounded away from 0) and Alg. 1 runs
-         * a second time. */
+         * meet tol, the classes are selected again against E_lo (or all set
+         * to the input precision when |x.y| is not bounded away from 0) and
+         * Alg. 1 runs a second time. */
         const int one_signed = !(pos_seen && neg_seen);
         double low = orc_lower(M, C, e_max, S, n, one_signed);
         if (orc_certified(r->bound_rel, low, tol)) {
             r->flags |= ORC_F_GUARANTEED;
         } else {
-            int32_t ref2 = low > 0.0 ? e_max + ilogb(low) : e_min - t - 22 - nonstrict;
+            /* the most precise reselection: every bin at the input
+             * precision, i.e. scoring >= m_single (double inputs) or
+             * >= m_half (single inputs), one more in the non-strict reading */
+            int32_t ref2 = low > 0.0 ? e_max + ilogb(low)
+                                     : e_min - t - (mu_single ? M_HALF : M_SINGLE) + 1 - nonstrict;
             if (ref2 < e_max) {
                 e_ref = ref2;
                 orc_select(M, e_max, e_min, e_ref, t, nonstrict, mu_single, r->n_zero, C, r);

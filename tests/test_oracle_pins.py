@@ -541,6 +541,24 @@ def test_f32_bound_on_positive_data():
             assert r["flags"] & oracle.F_UNATTAINABLE
 
 
+def test_f32_guaranteed_mode_hand_example():
+    # x = (1.5, -1.5, 2^-10), y = 1, tol 2^-5, as floats.  The first sweep is
+    # the double inputs' one (half, half, perforate: value 0, L < 0).  The
+    # most precise reselection for single inputs puts every bin at >= m_half:
+    # e_ref = e_min - t - 9 = -10 + 6 - 9 = -13, scores 1+0+13+6+1 = 21 and
+    # 0-10+13+6+1 = 10, both single.  The FP32 leaves 1.5, -1.5, 2^-10 and
+    # their tile sum are exact: value 2^-10.  a is about 2^-19, so L is just
+    # below 2^-10, E_lo = -11, and bound_rel 2^11 = (4 + 2^-9) 2^-23 2^11
+    # <= 2^-5: certified after two sweeps.
+    x = np.array([1.5, -1.5, 2.0 ** -10], dtype=np.float32)
+    r = oracle.qdot_f32(x, np.ones(3, dtype=np.float32), 2.0 ** -5, opt=GUARD,
+                        want_classes=True)
+    assert r["value"] == 2.0 ** -10 and r["e_ref"] == -13 and r["passes"] == 2
+    assert r["classes"].tolist() == [oracle.SINGLE] * 3
+    assert r["flags"] == oracle.F_RESELECTED | oracle.F_GUARANTEED
+    assert Fraction(r["bound_rel"]) == (4 + Fraction(1, 2 ** 9)) / 2 ** 23
+
+
 def test_f32_edges():
     # float subnormals are exact doubles: key of 2^-140 * 1 is -140
     x = np.array([2.0 ** -140, 1.0], dtype=np.float32)
@@ -548,7 +566,6 @@ def test_f32_edges():
     r = oracle.qdot_f32(x, y, 1e-3, want_keys=True)
     assert r["keys"][0] == -140 and r["n_zero"] == 1 and r["value"] == 2.0 ** -140
     assert oracle.qdot_f32(x, y, 1e-3, opt=[0, 0, 0, 1])["status"] == oracle.E_INVAL
-    assert oracle.qdot_f32(x, y, 1e-3, opt=[0, 0, 0, 0, 1])["status"] == oracle.E_INVAL
     x[1] = np.inf
     assert oracle.qdot_f32(x, y, 1e-3)["status"] == oracle.E_NONFINITE
 
