@@ -130,11 +130,12 @@ typedef struct qdot_options {
      *    when L > 0 and bound_rel 2^(e_max - E_lo) <= eps.  Otherwise the
      *    classes are selected again with the reference exponent e_ref =
      *    E_lo in place of e_max in the score (L > 0), or with e_ref =
-     *    e_min - t - 22 - boundary_mode, which makes every bin double
-     *    (L <= 0), pass 2 runs again (QDOT_F_RESELECTED) and the check is
-     *    repeated with the larger of the two lower bounds.  Needs key_mode
-     *    0 and accum_mode 0; accepted by qdot_async, qdot,
-     *    qdot_classes_async and qdot_power, QDOT_E_INVAL elsewhere. */
+     *    e_min - t - 22 - boundary_mode (single-precision inputs: - 9 -),
+     *    which puts every bin at the input precision (L <= 0), pass 2 runs
+     *    again (QDOT_F_RESELECTED) and the check is repeated with the
+     *    larger of the two lower bounds.  Needs key_mode 0 and accum_mode
+     *    0; accepted by qdot_async, qdot, qdot_classes_async, the qdot_f32
+     *    entry points and qdot_power, QDOT_E_INVAL elsewhere. */
     int32_t guard_mode;
 } qdot_options;
 
@@ -296,8 +297,9 @@ QDOT_API int32_t qdot_classes_async(qdot_handle *h, const double *x, const doubl
  * above m_single (23) stays single and sets QDOT_F_UNATTAINABLE, and
  * QDOT_F_THM_ALL_DOUBLE means every bin is at the input precision (Thm 3.6
  * with m_half: e_max - e_min <= -t - 10).  The result is FP64 and counts
- * no double class.  accum_mode and guard_mode must be 0 (QDOT_E_INVAL
- * otherwise).  No allocation, no host sync; graph-capturable. */
+ * no double class.  accum_mode must be 0 (QDOT_E_INVAL otherwise);
+ * guard_mode 1 reselects with every bin at most single.  No allocation, no
+ * host sync; graph-capturable. */
 QDOT_API int32_t qdot_f32_async(qdot_handle *h, const float *x, const float *y,
                        int64_t n, double tol, const qdot_options *opt,
                        void *stream, qdot_result *dev_out);

@@ -134,8 +134,8 @@ static int32_t check_qdot_args(qdot_handle *h, const T *x, const T *y, int64_t n
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
-    if (sizeof(T) == 4 && (o.accum_mode != 0 || o.guard_mode != 0))
-        return fail(h, QDOT_E_INVAL, "single-precision inputs need accum_mode 0 and guard_mode 0");
+    if (sizeof(T) == 4 && o.accum_mode != 0)
+        return fail(h, QDOT_E_INVAL, "single-precision inputs need accum_mode 0");
     if (o.accum_mode == 1 && !s1_admissible(n, tol, o))
         return fail(h, QDOT_E_INVAL, "accum_mode 1 needs n <= 2^30 and a tolerance whose "
                                      "kept bins fit the one-pass window");

@@ -347,7 +347,7 @@ __device__ __forceinline__ bool guard_certified(double bound_rel, double low, do
 __global__ __launch_bounds__(CUT_THREADS) void k_guard(Ws *__restrict__ ws,
                                                        const long long *__restrict__ hs,
                                                        double tol, int score_mode, int nonstrict,
-                                                       int64_t n, int stage,
+                                                       int64_t n, int stage, int mu_single,
                                                        qdot_result *__restrict__ out)
 {
     __shared__ int s_go, s_dref, s_passes;
@@ -382,8 +382,10 @@ __global__ __launch_bounds__(CUT_THREADS) void k_guard(Ws *__restrict__ ws,
                 out->lower = ldexp(low, e_max);
                 ws->skip = 1;
             } else {
+                // L <= 0: every bin at the input precision (scores >= 23 for
+                // double inputs, >= 10 for single; one more non-strict)
                 const int ref = low > 0.0 ? e_max + ilogb(low)
-                                          : out->e_min - out->t - 22 - nonstrict;
+                                          : out->e_min - out->t - (mu_single ? 9 : 22) - nonstrict;
                 if (ref < e_max) {
                     s_dref = e_max - ref;
                     ws->g_low = low;
@@ -407,7 +409,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_guard(Ws *__restrict__ ws,
     auto put = [&](int j, int cls) { ws->lut[j] = (unsigned char)cls; };
     auto clear = [](int) {};
     const CutParams p = block_cutoff<CUT_THREADS>(lo, hi, s_nz, 0u, n, tol, score_mode, nonstrict,
-                                                  get, put, clear, out, nullptr, s_dref);
+                                                  get, put, clear, out, nullptr, s_dref,
+                                                  mu_single);
     if (tid == 0) {
         ws->c32 = p.c32;
         ws->flags = p.flags | QDOT_F_RESELECTED;
@@ -712,11 +715,11 @@ static hipError_t launch_qdot_t(const Launch &L, const T *x, const T *y, int64_t
         // certify or reselect; the second sweep returns at once unless the
         // classes were selected again
         hipLaunchKernelGGL(k_guard, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, hs, tol,
-                           o.score_mode, o.boundary_mode, n, 0, out);
+                           o.score_mode, o.boundary_mode, n, 0, mu_single, out);
         grid = sweep();
         hipLaunchKernelGGL(k_fin, dim3(1), dim3(BLOCK), 0, s, L.ws, L.partials, grid, out);
         hipLaunchKernelGGL(k_guard, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, hs, tol,
-                           o.score_mode, o.boundary_mode, n, 1, out);
+                           o.score_mode, o.boundary_mode, n, 1, mu_single, out);
     }
     if (L.ev) (void)hipEventRecord(L.ev[4], s);
     return hipGetLastError();

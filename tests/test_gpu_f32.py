@@ -54,6 +54,7 @@ def compare(h, x, y, tol, opt=None, xd=None, yd=None, classes=True):
     for c in range(3):
         assert abs(r["part"][c] - o["part"][c]) <= VALUE_TOL * scale, c
     assert abs(r["bound_rel"] - o["bound_rel"]) <= 1e-12 * abs(o["bound_rel"])
+    assert abs(r["lower"] - o["lower"]) <= VALUE_TOL * scale + 1e-12 * abs(o["lower"])
     assert r["count"][q.DOUBLE] == 0
     return r, o
 
@@ -129,11 +130,42 @@ def test_edge_cases(h):
 
 def test_rejected_options(h):
     x = devf(np.ones(100))
-    for opt in ([0, 0, 0, 1], [0, 0, 0, 0, 1]):
+    for opt in ([0, 0, 0, 1], [1, 0, 0, 0, 1]):
         with pytest.raises(q.QdotError):
             h.qdot_f32(x, x, 1e-6, opt=opt)
     with pytest.raises(ValueError):
         h.qdot_f32(x.double(), x.double(), 1e-6)
+
+
+GUARD = [0, 0, 0, 0, 1]
+
+
+def test_guaranteed_mode_hand_example(h):
+    # all-single reselection: e_ref = e_min - t - 9 = -13, value 2^-10
+    r, _ = compare(h, np.array([1.5, -1.5, 2.0 ** -10]), np.ones(3), 2.0 ** -5, opt=GUARD)
+    assert r["value"] == 2.0 ** -10 and r["e_ref"] == -13 and r["passes"] == 2
+    assert r["flags"] == q.F_RESELECTED | q.F_GUARANTEED
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_guaranteed_mode_cancelling(h, seed):
+    # cancelling sums rounded to float: both sides take the same decisions
+    x, y = workloads.cancelling_pair(3000, 760 + seed, 3e-4)
+    for tol in (1e-4, 1e-2):
+        compare(h, x, y, tol, opt=GUARD)
+
+
+def test_guaranteed_mode_law(h):
+    # one-signed or not, the law's sums do not cancel: certified by the first
+    # selection while single precision can meet the budget; at 1e-3 some bin
+    # cannot (unattainable) but the whole bound still meets tol; at 1e-6 it
+    # does not
+    x, y = workloads.log_uniform_pair(300001, 764, -15.0, 15.0)
+    expect = {1e-2: q.F_GUARANTEED, 1e-3: q.F_GUARANTEED | q.F_UNATTAINABLE,
+              1e-6: q.F_UNATTAINABLE}
+    for tol, flags in expect.items():
+        r, _ = compare(h, x, y, tol, opt=GUARD)
+        assert r["flags"] == flags and r["passes"] == 1, (tol, r["flags"])
 
 
 def test_graph_replay(h):
