@@ -297,9 +297,9 @@ QDOT_API int32_t qdot_classes_async(qdot_handle *h, const double *x, const doubl
  * above m_single (23) stays single and sets QDOT_F_UNATTAINABLE, and
  * QDOT_F_THM_ALL_DOUBLE means every bin is at the input precision (Thm 3.6
  * with m_half: e_max - e_min <= -t - 10).  The result is FP64 and counts
- * no double class.  accum_mode must be 0 (QDOT_E_INVAL otherwise);
- * guard_mode 1 reselects with every bin at most single.  No allocation, no
- * host sync; graph-capturable. */
+ * no double class.  accum_mode 1 is the one-pass reading (same
+ * admissibility as for double inputs); guard_mode 1 reselects with every
+ * bin at most single.  No allocation, no host sync; graph-capturable. */
 QDOT_API int32_t qdot_f32_async(qdot_handle *h, const float *x, const float *y,
                        int64_t n, double tol, const qdot_options *opt,
                        void *stream, qdot_result *dev_out);
@@ -309,7 +309,7 @@ QDOT_API int32_t qdot_f32(qdot_handle *h, const float *x, const float *y, int64_
                  double tol, const qdot_options *opt, void *stream,
                  qdot_result *host_out);
 
-/* qdot_classes_async for single-precision inputs. */
+/* qdot_classes_async for single-precision inputs (accum_mode 0). */
 QDOT_API int32_t qdot_f32_classes_async(qdot_handle *h, const float *x, const float *y,
                                int64_t n, double tol, const qdot_options *opt,
                                void *stream, uint8_t *dev_cls, int64_t *dev_hist,

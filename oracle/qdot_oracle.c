@@ -519,8 +519,7 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
         key_mode < 0 || key_mode > 1 || score_mode < 0 || score_mode > 1 ||
         nonstrict < 0 || nonstrict > 1 || accum_mode < 0 || accum_mode > 1 ||
         guard_mode < 0 || guard_mode > 1 ||
-        (guard_mode == 1 && (key_mode != 0 || accum_mode != 0)) ||
-        (mu_single && accum_mode != 0)) {
+        (guard_mode == 1 && (key_mode != 0 || accum_mode != 0))) {
         r->status = ORC_E_INVAL;
         r->value = NAN;
         return r->status;

@@ -71,7 +71,7 @@ int orc_qdot(const double *x, const double *y, int64_t n, double tol,
 
 /* The same for single-precision inputs (mu = m_single): no double class; a
  * bin scoring at or above m_single stays single and is flagged
- * unattainable.  accum_mode must be 0. */
+ * unattainable. */
 int orc_qdot_f32(const float *x, const float *y, int64_t n, double tol,
                  const int32_t *opt, orc_result *out, uint8_t *cls,
                  int32_t *keys, int64_t *hist);

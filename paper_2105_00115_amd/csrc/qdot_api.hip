@@ -134,8 +134,6 @@ static int32_t check_qdot_args(qdot_handle *h, const T *x, const T *y, int64_t n
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
-    if (sizeof(T) == 4 && o.accum_mode != 0)
-        return fail(h, QDOT_E_INVAL, "single-precision inputs need accum_mode 0");
     if (o.accum_mode == 1 && !s1_admissible(n, tol, o))
         return fail(h, QDOT_E_INVAL, "accum_mode 1 needs n <= 2^30 and a tolerance whose "
                                      "kept bins fit the one-pass window");
@@ -346,6 +344,8 @@ int32_t qdot_f32_classes_async(qdot_handle *h, const float *x, const float *y, i
     int32_t st = check_qdot_args(h, x, y, n, tol, opt, o);
     if (st != QDOT_OK) return st;
     if (!dev_out || (n > 0 && !dev_cls)) return fail(h, QDOT_E_INVAL, "NULL output");
+    if (o.accum_mode != 0)
+        return fail(h, QDOT_E_INVAL, "qdot_f32_classes_async needs accum_mode 0");
     DeviceGuard g(h->device);
     hipError_t e = launch_qdot_f32(make_launch(h, (hipStream_t)stream, n, true), x, y, n, tol, o,
                                    dev_out, dev_cls, (long long *)dev_hist);

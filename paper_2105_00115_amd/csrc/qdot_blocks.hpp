@@ -544,18 +544,20 @@ __device__ __forceinline__ void s1_begin(S1Lds &S)
 // when it rises the slots of the entering bins are cleared first.  The
 // in-window components are compacted per wave and processed 64 at a time.
 // Every thread of the block must call it with the same arguments.
-template <bool VEC, int U>
-__device__ __forceinline__ void s1_stream(const double *__restrict__ x,
-                                          const double *__restrict__ y, int64_t first,
-                                          int64_t stride, int64_t n, int key_mode, int depth,
-                                          unsigned int *h, S1Lds &S, int &top, unsigned int &nz,
-                                          unsigned int &bad)
+// T is the input type: floats are widened exactly (their single and half
+// candidates are then those of the float path; the double candidate is never
+// picked, the class table having no double row).
+template <bool VEC, int U, class T>
+__device__ __forceinline__ void s1_stream(const T *__restrict__ x, const T *__restrict__ y,
+                                          int64_t first, int64_t stride, int64_t n,
+                                          int key_mode, int depth, unsigned int *h, S1Lds &S,
+                                          int &top, unsigned int &nz, unsigned int &bad)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t group = (int64_t)CHUNK * U;
     int par = 0;
     for (int64_t base = first; base < n; base += stride, par ^= 1) {
-        double xv[U][4], yv[U][4];
+        T xv[U][4], yv[U][4];
         int lim[U];
         const bool full = base + group <= n;
 #pragma unroll
@@ -578,7 +580,7 @@ __device__ __forceinline__ void s1_stream(const double *__restrict__ x,
         for (int u = 0; u < U; u++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const Comp c = component(xv[u][e], yv[u][e], key_mode);
+                const Comp c = component((double)xv[u][e], (double)yv[u][e], key_mode);
                 const bool valid = e < lim[u];
                 nz += (valid & c.zero) ? 1u : 0u;
                 bad |= (valid & c.bad) ? 1u : 0u;
@@ -626,7 +628,7 @@ __device__ __forceinline__ void s1_stream(const double *__restrict__ x,
                     const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
                                              (unsigned)(m >> 32),
                                              __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                    qw[pos] = make_double2(xv[u][e], yv[u][e]);
+                    qw[pos] = make_double2((double)xv[u][e], (double)yv[u][e]);
                 }
                 qn += __popcll(m);
                 if (qn >= 64) {

@@ -438,9 +438,9 @@ __global__ __launch_bounds__(CUT_THREADS) void k_guard(Ws *__restrict__ ws,
 // At the end each block adds its window into one of HIST_COPIES global
 // tables; k_s1_fin picks each kept bin's class and clears the tables.
 // ---------------------------------------------------------------------------
-template <bool VEC, int U>
-__global__ __launch_bounds__(BLOCK) void k_s1_scan(const double *__restrict__ x,
-                                                   const double *__restrict__ y,
+template <class T, bool VEC, int U>
+__global__ __launch_bounds__(BLOCK) void k_s1_scan(const T *__restrict__ x,
+                                                   const T *__restrict__ y,
                                                    int64_t n, int key_mode, int depth,
                                                    Ws *__restrict__ ws,
                                                    double *__restrict__ tab)
@@ -632,40 +632,42 @@ static int launch_acc(const Launch &L, const T *x, const T *y, int64_t n, int ke
     }
 }
 
-template <bool VEC, int U>
-static int launch_s1_u(const Launch &L, const double *x, const double *y, int64_t n,
-                       int key_mode, int depth)
+template <class T, bool VEC, int U>
+static int launch_s1_u(const Launch &L, const T *x, const T *y, int64_t n, int key_mode,
+                       int depth)
 {
     const int grid = grid_for(n, U, L.s1_blocks);
-    hipLaunchKernelGGL((k_s1_scan<VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+    hipLaunchKernelGGL((k_s1_scan<T, VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
                        key_mode, depth, L.ws, L.s1tab);
     return grid;
 }
 
-template <bool VEC>
-static int launch_s1(const Launch &L, const double *x, const double *y, int64_t n,
-                     int key_mode, int depth)
+template <class T, bool VEC>
+static int launch_s1(const Launch &L, const T *x, const T *y, int64_t n, int key_mode,
+                     int depth)
 {
-    switch (L.s1_unroll) {
-    case 1: return launch_s1_u<VEC, 1>(L, x, y, n, key_mode, depth);
-    case 4: return launch_s1_u<VEC, 4>(L, x, y, n, key_mode, depth);
-    default: return launch_s1_u<VEC, 2>(L, x, y, n, key_mode, depth);
+    switch (unroll_for<T>(L.s1_unroll)) {
+    case 1: return launch_s1_u<T, VEC, 1>(L, x, y, n, key_mode, depth);
+    case 4: return launch_s1_u<T, VEC, 4>(L, x, y, n, key_mode, depth);
+    default: return launch_s1_u<T, VEC, 2>(L, x, y, n, key_mode, depth);
     }
 }
 
 // One-pass mode: scan with per-bin candidate sums, cutoff, pick per bin.
-static hipError_t launch_qdot_s1(const Launch &L, const double *x, const double *y, int64_t n,
+template <class T>
+static hipError_t launch_qdot_s1(const Launch &L, const T *x, const T *y, int64_t n,
                                  double tol, const qdot_options &o, qdot_result *out)
 {
     const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
+    const int mu_single = sizeof(T) == 4 ? 1 : 0;
     hipStream_t s = L.stream;
     if (L.ev) (void)hipEventRecord(L.ev[0], s);
     const int depth = s1_depth(n, tol, o);
-    const int nscan = vec ? launch_s1<true>(L, x, y, n, o.key_mode, depth)
-                          : launch_s1<false>(L, x, y, n, o.key_mode, depth);
+    const int nscan = vec ? launch_s1<T, true>(L, x, y, n, o.key_mode, depth)
+                          : launch_s1<T, false>(L, x, y, n, o.key_mode, depth);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
     hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, nscan, 0, 0, out, nullptr);
+                       o.boundary_mode, n, nscan, 0, mu_single, out, nullptr);
     if (L.ev) {
         (void)hipEventRecord(L.ev[2], s);
         (void)hipEventRecord(L.ev[3], s);
@@ -729,7 +731,7 @@ hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_
                        double tol, const qdot_options &o, qdot_result *out,
                        unsigned char *cls_out, long long *hist_out)
 {
-    if (o.accum_mode == 1) return launch_qdot_s1(L, x, y, n, tol, o, out);
+    if (o.accum_mode == 1) return launch_qdot_s1<double>(L, x, y, n, tol, o, out);
     return launch_qdot_t<double>(L, x, y, n, tol, o, out, cls_out, hist_out);
 }
 
@@ -737,6 +739,7 @@ hipError_t launch_qdot_f32(const Launch &L, const float *x, const float *y, int6
                            double tol, const qdot_options &o, qdot_result *out,
                            unsigned char *cls_out, long long *hist_out)
 {
+    if (o.accum_mode == 1) return launch_qdot_s1<float>(L, x, y, n, tol, o, out);
     return launch_qdot_t<float>(L, x, y, n, tol, o, out, cls_out, hist_out);
 }
 

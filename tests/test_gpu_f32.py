@@ -130,9 +130,12 @@ def test_edge_cases(h):
 
 def test_rejected_options(h):
     x = devf(np.ones(100))
-    for opt in ([0, 0, 0, 1], [1, 0, 0, 0, 1]):
-        with pytest.raises(q.QdotError):
-            h.qdot_f32(x, x, 1e-6, opt=opt)
+    with pytest.raises(q.QdotError):
+        h.qdot_f32(x, x, 1e-6, opt=[1, 0, 0, 0, 1])  # guaranteed mode needs key_mode 0
+    with pytest.raises(q.QdotError):
+        h.qdot_f32(x, x, 1e-80, opt=[0, 0, 0, 1])  # one-pass window cannot hold the bins
+    with pytest.raises(q.QdotError):
+        h.qdot_f32_classes(x, x, 1e-6, opt=[0, 0, 0, 1])
     with pytest.raises(ValueError):
         h.qdot_f32(x.double(), x.double(), 1e-6)
 
@@ -168,6 +171,39 @@ def test_guaranteed_mode_law(h):
         assert r["flags"] == flags and r["passes"] == 1, (tol, r["flags"])
 
 
+S1 = [0, 0, 0, 1]
+
+
+@pytest.mark.parametrize("n", [1, 1023, 65573, 300001])
+@pytest.mark.parametrize("tol", [1e-2, 1e-5])
+def test_one_pass_law(h, n, tol):
+    x, y = workloads.log_uniform_pair(n, 80 + n % 83, -15.0, 15.0)
+    r, _ = compare(h, x, y, tol, opt=S1, classes=False)
+    d = h.qdot_f32(devf(x), devf(y), tol)
+    assert r["count"] == d["count"] and r["flags"] == d["flags"]
+
+
+def test_one_pass_exact(h):
+    # small integers: exact; and an exact sum cannot depend on the launch
+    # shape or the component order
+    g = workloads.rng(81)
+    xi = g.integers(-50, 51, 70001).astype(np.float32)
+    yi = g.integers(-50, 51, 70001).astype(np.float32)
+    r, _ = compare(h, xi, yi, 1e-30, opt=S1, classes=False)
+    assert r["value"] == float(np.dot(xi.astype(np.int64), yi.astype(np.int64)))
+    x, y = workloads.log_uniform_pair(400000, 82, -15.0, 15.0)
+    xd, yd = devf(x), devf(y)
+    r0 = h.qdot_f32(xd, yd, 1e-5, opt=S1)
+    pm = workloads.rng(83).permutation(len(x))
+    assert h.qdot_f32(devf(x[pm]), devf(y[pm]), 1e-5, opt=S1)["value"] == r0["value"]
+    try:
+        for ob, ou in ((1, 1), (4, 2), (16, 1)):
+            h.set_tune(-1, 2, 1, 2, 2, ob, ou)
+            assert h.qdot_f32(xd, yd, 1e-5, opt=S1)["value"] == r0["value"], (ob, ou)
+    finally:
+        h.reset_tune()
+
+
 def test_graph_replay(h):
     x, y = workloads.log_uniform_pair(300001, 79, -15.0, 15.0)
     xd, yd = devf(x), devf(y)
@@ -198,3 +234,4 @@ def test_full_size(h):
     print(f"[gpu-case] f32 full size n={n}", flush=True)
     x, y = workloads.log_uniform_pair(n, 2028, -15.0, 15.0)
     compare(h, x, y, 1e-6, classes=False)
+    compare(h, x, y, 1e-6, opt=S1, classes=False)

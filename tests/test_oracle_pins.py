@@ -541,6 +541,38 @@ def test_f32_bound_on_positive_data():
             assert r["flags"] & oracle.F_UNATTAINABLE
 
 
+def test_f32_one_pass_small_integers_and_shared_classes():
+    # the one-pass reading on float inputs: classes and counts of the
+    # two-pass reading, kept leaves summed exactly; small-integer products
+    # make both exact, and the sum of exactly representable leaves is exact
+    g = np.random.default_rng(33)
+    x = g.integers(-50, 51, 5000).astype(np.float32)
+    y = g.integers(-50, 51, 5000).astype(np.float32)
+    r1 = oracle.qdot_f32(x, y, 1e-30, opt=[0, 0, 0, 1])
+    assert r1["value"] == float(np.dot(x.astype(np.int64), y.astype(np.int64)))
+    xl, yl = workloads.log_uniform_pair(8000, 34, -15.0, 15.0)
+    xl, yl = xl.astype(np.float32), yl.astype(np.float32)
+    for tol in (1e-2, 1e-5):
+        r2 = oracle.qdot_f32(xl, yl, tol, want_classes=True)
+        r1 = oracle.qdot_f32(xl, yl, tol, opt=[0, 0, 0, 1], want_classes=True)
+        assert np.array_equal(r1["classes"], r2["classes"]) and r1["count"] == r2["count"]
+        # S1 = the exactly rounded sum of the same leaves: from the classes,
+        # single leaves fl32(x y), half leaves r16 r16 (exact), summed in
+        # rationals
+        tot = Fraction(0)
+        for xi, yi, c in zip(xl.tolist(), yl.tolist(), r1["classes"].tolist()):
+            if c == oracle.SINGLE:
+                tot += Fraction(float(np.float32(xi) * np.float32(yi)))
+            elif c == oracle.HALF:
+                mx, ex = math.frexp(abs(xi))
+                my, ey = math.frexp(abs(yi))
+                hx = float(np.float16(2 * mx)) * 2.0 ** (ex - 1)
+                hy = float(np.float16(2 * my)) * 2.0 ** (ey - 1)
+                sgn = 1 if (xi < 0) == (yi < 0) else -1
+                tot += sgn * Fraction(hx) * Fraction(hy)
+        assert Fraction(r1["value"]) == Fraction(float(tot))
+
+
 def test_f32_guaranteed_mode_hand_example():
     # x = (1.5, -1.5, 2^-10), y = 1, tol 2^-5, as floats.  The first sweep is
     # the double inputs' one (half, half, perforate: value 0, L < 0).  The
@@ -565,7 +597,6 @@ def test_f32_edges():
     y = np.array([1.0, 0.0], dtype=np.float32)
     r = oracle.qdot_f32(x, y, 1e-3, want_keys=True)
     assert r["keys"][0] == -140 and r["n_zero"] == 1 and r["value"] == 2.0 ** -140
-    assert oracle.qdot_f32(x, y, 1e-3, opt=[0, 0, 0, 1])["status"] == oracle.E_INVAL
     x[1] = np.inf
     assert oracle.qdot_f32(x, y, 1e-3)["status"] == oracle.E_NONFINITE
 
