@@ -398,7 +398,9 @@ QDOT_API int32_t qdot_cg_batched(qdot_handle *h, const qdot_cg_system *systems, 
                                  qdot_cg_result *host_out);
 
 /* y = A x for a CSR matrix (rows summed in stored order, each product and
- * sum one FP64 rounding).  Async. */
+ * sum one FP64 rounding).  col entries must lie in [0, n); rows of any
+ * length are accepted.  The grid holds up to 8 blocks per CU (environment
+ * variable QDOT_SPMV_BPC, 1..16, overrides it).  Async. */
 QDOT_API int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double *x,
                         double *y, void *stream);
 
@@ -423,7 +425,13 @@ QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, dou
  * x = w / sqrt(c), with both dots by qdot at qtol when use_qdot != 0.
  * x: device FP64[n], unit vector on entry, last iterate on exit.
  * lambda (host): last lambda.  lambda_trace: NULL or device FP64[iters].
- * opt: as qdot_async (the one-pass and guaranteed modes included).
+ * opt: as qdot_async (the one-pass and guaranteed modes included).  With
+ * the two-pass qdot the two inner products of an iteration are computed
+ * side by side: one pass-1 kernel reads x and w once for both, and the
+ * cutoff, pass-2 and combine kernels each run once for the pair (values
+ * as two separate qdot calls: classes and counts identical, sums within
+ * rounding of the block order).  The first call with use_qdot != 0
+ * allocates a second workspace on the handle.
  * Synchronous.  QDOT_E_BREAKDOWN if c <= 0 or not finite. */
 QDOT_API int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x,
                    int32_t iters, double qtol, int32_t use_qdot,

@@ -56,6 +56,7 @@ Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n, bool single)
     L.stream = s;
     L.ws = h->ws;
     L.partials = h->partials;
+    L.partial_cap = h->partial_blocks;
     L.scan_blocks = std::min(MAX_GRID, std::min(8, f * t.scan_blocks_per_cu) * h->num_cus);
     L.scan_unroll = t.scan_unroll;
     L.acc_blocks = std::min(h->partial_blocks,
@@ -191,6 +192,7 @@ int32_t qdot_destroy(qdot_handle *h)
     DeviceGuard g(h->device);
     (void)hipDeviceSynchronize();
     if (h->ws) (void)hipFree(h->ws);
+    if (h->ws2) (void)hipFree(h->ws2);
     if (h->s1tab) (void)hipFree(h->s1tab);
     if (h->partials) (void)hipFree(h->partials);
     if (h->dev_res) (void)hipFree(h->dev_res);

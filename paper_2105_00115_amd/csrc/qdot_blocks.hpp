@@ -135,6 +135,58 @@ __device__ __forceinline__ void block_reduce_range(int &lo, int &hi, unsigned in
     }
 }
 
+// End of pass 1 in one block: merges the block's LDS histogram h (W + 1
+// slots; slot W takes zero and non-finite products, and is not merged) into
+// copy blockIdx % HIST_COPIES of ws's global histograms, adds the zero count,
+// raises the non-finite flag, and stores the block's record at index rec
+// (its live slot range and the signs of its nonzero products: bit 0
+// negative, bit 1 positive) for the cutoff kernel.  nz, bad and sg are the
+// calling thread's own tallies.  Every thread calls it, after a barrier that
+// completes h; it ends with one, so it can be called again.
+__device__ __forceinline__ void scan_flush(const unsigned int *h, unsigned int nz,
+                                           unsigned int bad, unsigned int sg, Ws *ws, int rec)
+{
+    unsigned long long *gh = ws->hist[blockIdx.x % HIST_COPIES];
+    int lo = W, hi = -1;
+    for (int i = threadIdx.x; i < W; i += BLOCK) {
+        const unsigned int v = h[i];
+        if (v) {
+            atomicAdd(&gh[i], (unsigned long long)v);
+            lo = min(lo, i);
+            hi = max(hi, i);
+        }
+    }
+    nz = wave_sum_u32(nz);
+    bad = wave_sum_u32(bad);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo = min(lo, __shfl_xor(lo, m, 64));
+        hi = max(hi, __shfl_xor(hi, m, 64));
+        sg |= __shfl_xor(sg, m, 64);
+    }
+    __shared__ int2 wr[BLOCK / 64];
+    __shared__ unsigned int wsg[BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) {
+        if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
+        if (bad) atomicOr(&ws->nonfinite, 1u);
+        wr[threadIdx.x >> 6] = make_int2(lo, hi);
+        wsg[threadIdx.x >> 6] = sg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // plain stores, no contention: the cutoff kernel reduces the records
+        int2 r = wr[0];
+        unsigned int g = wsg[0];
+        for (int w = 1; w < BLOCK / 64; w++) {
+            r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
+            g |= wsg[w];
+        }
+        ws->block_range[rec] = r;
+        ws->block_signs[rec] = g;
+    }
+    __syncthreads();
+}
+
 // ---- hand-over between blocks of one launch ------------------------------
 // Data that one block hands to another inside a launch travels only through
 // device-scope atomics: read-modify-writes, relaxed stores (written through

@@ -10,6 +10,7 @@ struct qdot_handle {
     int device = 0;
     int num_cus = 0;
     qd::Ws *ws = nullptr;            // device control block
+    qd::Ws *ws2 = nullptr;           // second one, for the power method's paired products
     double *partials = nullptr;      // per-block partials
     int partial_blocks = 0;          // capacity in blocks
     double *s1tab = nullptr;         // one-pass mode per-bin sums (kept zero between calls)

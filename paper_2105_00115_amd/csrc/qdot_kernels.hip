@@ -50,56 +50,17 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const T *__restrict__ x,
         }
     });
     __syncthreads();
-    unsigned long long *gh = ws->hist[blockIdx.x % HIST_COPIES];
-    int lo = W, hi = -1;
-    for (int i = threadIdx.x; i < W; i += BLOCK) {
-        const unsigned int v = h[i];
-        if (v) {
-            atomicAdd(&gh[i], (unsigned long long)v);
-            lo = min(lo, i);
-            hi = max(hi, i);
-        }
-    }
-    nz = wave_sum_u32(nz);
-    bad = wave_sum_u32(bad);
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        lo = min(lo, __shfl_xor(lo, m, 64));
-        hi = max(hi, __shfl_xor(hi, m, 64));
-        sg |= __shfl_xor(sg, m, 64);
-    }
-    __shared__ int2 wr[BLOCK / 64];
-    __shared__ unsigned int wsg[BLOCK / 64];
-    if ((threadIdx.x & 63) == 0) {
-        if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
-        if (bad) atomicOr(&ws->nonfinite, 1u);
-        wr[threadIdx.x >> 6] = make_int2(lo, hi);
-        wsg[threadIdx.x >> 6] = sg;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // plain stores, no contention: the cutoff kernel reduces the records
-        int2 r = wr[0];
-        unsigned int g = wsg[0];
-        for (int w = 1; w < BLOCK / 64; w++) {
-            r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
-            g |= wsg[w];
-        }
-        ws->block_range[blockIdx.x] = r;
-        ws->block_signs[blockIdx.x] = g;
-    }
+    scan_flush(h, nz, bad, sg, ws, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Cutoff selection (Alg. 2, bins -> scores -> precisions), one workgroup over
 // the live slot window of the 8 histogram copies.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double tol,
-                                                     int score_mode, int nonstrict,
-                                                     int64_t n, int nscan, int guard,
-                                                     int mu_single,
-                                                     qdot_result *__restrict__ out,
-                                                     long long *__restrict__ hist_out)
+__device__ __forceinline__ void cut_body(Ws *__restrict__ ws, double tol, int score_mode,
+                                         int nonstrict, int64_t n, int nscan, int guard,
+                                         int mu_single, qdot_result *__restrict__ out,
+                                         long long *__restrict__ hist_out)
 {
     constexpr int NW = CUT_THREADS / 64;
     __shared__ int s_lo[NW], s_hi[NW];
@@ -167,6 +128,16 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
     }
 }
 
+__global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double tol,
+                                                     int score_mode, int nonstrict,
+                                                     int64_t n, int nscan, int guard,
+                                                     int mu_single,
+                                                     qdot_result *__restrict__ out,
+                                                     long long *__restrict__ hist_out)
+{
+    cut_body(ws, tol, score_mode, nonstrict, n, nscan, guard, mu_single, out, hist_out);
+}
+
 // ---------------------------------------------------------------------------
 // Pass 2 (Alg. 1): per component class -> quantised product (leaf) ->
 // 64-element FP32 tile trees (single and half separately) and compensated
@@ -181,13 +152,13 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
 // All three candidates are formed without branches and the class selects
 // one; the only branch is the rare zero/subnormal operand path.
 // ---------------------------------------------------------------------------
+// Block `blk` of `nblk` (grid-stride over groups) writes its partials at
+// partials + 6 * blk.
 template <class T, bool VEC, int U, bool CLS>
-__global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
-                                               const T *__restrict__ y,
-                                               int64_t n, int key_mode,
-                                               const Ws *__restrict__ ws,
-                                               double *__restrict__ partials,
-                                               unsigned char *__restrict__ cls_out)
+__device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__restrict__ y,
+                                         int64_t n, int key_mode, const Ws *__restrict__ ws,
+                                         double *__restrict__ partials,
+                                         unsigned char *__restrict__ cls_out, int blk, int nblk)
 {
     __shared__ unsigned char lut[W_LUT];
     __shared__ Acc red[3][BLOCK / 64];
@@ -205,7 +176,9 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
 
     const int lane = threadIdx.x & 63;
     Acc aD = {0.0, 0.0}, aS = {0.0, 0.0}, aH = {0.0, 0.0};
-    stream_groups<VEC, U>(x, y, n, [&](const T *xv, const T *yv, int64_t i0, int lim) {
+    const int64_t group = (int64_t)CHUNK * U;
+    stream_strided<VEC, U>(x, y, (int64_t)blk * group, (int64_t)nblk * group, n,
+                           [&](const T *xv, const T *yv, int64_t i0, int lim) {
         acc_group<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
                        CLS ? cls_out + i0 : nullptr);
     });
@@ -222,7 +195,7 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double *p = partials + (size_t)blockIdx.x * 6;
+        double *p = partials + (size_t)blk * 6;
         for (int q = 0; q < 3; q++) {
             Acc b = red[q][0];
             for (int w = 1; w < BLOCK / 64; w++) b = acc_merge(b, red[q][w]);
@@ -232,10 +205,21 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
     }
 }
 
+template <class T, bool VEC, int U, bool CLS>
+__global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
+                                               const T *__restrict__ y,
+                                               int64_t n, int key_mode,
+                                               const Ws *__restrict__ ws,
+                                               double *__restrict__ partials,
+                                               unsigned char *__restrict__ cls_out)
+{
+    acc_body<T, VEC, U, CLS>(x, y, n, key_mode, ws, partials, cls_out, blockIdx.x, gridDim.x);
+}
+
 // Combine the per-block partials of k_acc in a fixed order (one block).
-__global__ __launch_bounds__(BLOCK) void k_fin(Ws *__restrict__ ws,
-                                               const double *__restrict__ partials, int nblk,
-                                               qdot_result *__restrict__ out)
+__device__ __forceinline__ void fin_body(Ws *__restrict__ ws,
+                                         const double *__restrict__ partials, int nblk,
+                                         qdot_result *__restrict__ out)
 {
     __shared__ Acc red[3][BLOCK / 64];
     if (ws->skip) return;
@@ -257,6 +241,13 @@ __global__ __launch_bounds__(BLOCK) void k_fin(Ws *__restrict__ ws,
         }
         ws->s_last = combine_value(f, ws->e_max, ws->c32, ws->flags, out);
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fin(Ws *__restrict__ ws,
+                                               const double *__restrict__ partials, int nblk,
+                                               qdot_result *__restrict__ out)
+{
+    fin_body(ws, partials, nblk, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -680,10 +671,13 @@ static hipError_t launch_qdot_s1(const Launch &L, const T *x, const T *y, int64_
 // Two-pass qdot of T inputs (double, or float with mu = m_single): scan,
 // cutoff, accumulate, finalize, and in the guaranteed mode the guard stages
 // around a second sweep.
+// nscan_pre >= 0: pass 1 already ran into L.ws, in an earlier kernel on the
+// stream that left nscan_pre block records; the scan is not launched.
 template <class T>
 static hipError_t launch_qdot_t(const Launch &L, const T *x, const T *y, int64_t n, double tol,
                                 const qdot_options &o, qdot_result *out,
-                                unsigned char *cls_out, long long *hist_out)
+                                unsigned char *cls_out, long long *hist_out,
+                                int nscan_pre = -1)
 {
     const bool vec = ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
     const int guard = o.guard_mode;
@@ -694,8 +688,9 @@ static hipError_t launch_qdot_t(const Launch &L, const T *x, const T *y, int64_t
         hs = reinterpret_cast<long long *>(reinterpret_cast<char *>(L.ws) + offsetof(Ws, hsave));
     hipStream_t s = L.stream;
     if (L.ev) (void)hipEventRecord(L.ev[0], s);
-    const int nscan = vec ? launch_scan<T, true>(L, x, y, n, o.key_mode)
-                          : launch_scan<T, false>(L, x, y, n, o.key_mode);
+    const int nscan = nscan_pre >= 0 ? nscan_pre
+                      : vec          ? launch_scan<T, true>(L, x, y, n, o.key_mode)
+                                     : launch_scan<T, false>(L, x, y, n, o.key_mode);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
     hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
                        o.boundary_mode, n, nscan, guard, mu_single, out, hs);
@@ -741,6 +736,136 @@ hipError_t launch_qdot_f32(const Launch &L, const float *x, const float *y, int6
 {
     if (o.accum_mode == 1) return launch_qdot_s1<float>(L, x, y, n, tol, o, out);
     return launch_qdot_t<float>(L, x, y, n, tol, o, out, cls_out, hist_out);
+}
+
+// ---------------------------------------------------------------------------
+// Two inner products over the same n components, lambda = x . w and
+// c = w . w (the power method's pair, Alg. 5), one launch per step: pass 1
+// reads x and w once for the keys of both, and the cutoffs, pass-2 sweeps
+// and combines of the two run side by side (block 0 / the first half of the
+// grid on x . w into wa, the rest on w . w into wb).
+// ---------------------------------------------------------------------------
+template <bool VEC, int U>
+__global__ __launch_bounds__(BLOCK) void k_scan_pair(const double *__restrict__ x,
+                                                     const double *__restrict__ w, int64_t n,
+                                                     int key_mode, Ws *__restrict__ wa,
+                                                     Ws *__restrict__ wb)
+{
+    __shared__ unsigned int h[2 * (W + 1)];
+    for (int i = threadIdx.x; i < 2 * (W + 1); i += BLOCK) h[i] = 0;
+    __syncthreads();
+    unsigned int *ha = h, *hb = h + (W + 1);
+    unsigned int nza = 0, bada = 0, sga = 0, nzb = 0, badb = 0, sgb = 0;
+    stream_groups<VEC, U>(x, w, n, [&](const double *xv, const double *wv, int64_t, int lim) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const Comp a = component(xv[e], wv[e], key_mode);
+            const Comp b = component(wv[e], wv[e], key_mode);
+            const bool valid = e < lim;
+            nza += (valid & a.zero) ? 1u : 0u;
+            bada |= (valid & a.bad) ? 1u : 0u;
+            sga |= (valid & !a.zero) ? (a.sgn ? 1u : 2u) : 0u;
+            nzb += (valid & b.zero) ? 1u : 0u;
+            badb |= (valid & b.bad) ? 1u : 0u;
+            sgb |= (valid & !b.zero) ? (b.sgn ? 1u : 2u) : 0u;
+            if (valid) {
+                atomicAdd(&ha[a.slot], 1u);
+                atomicAdd(&hb[b.slot], 1u);
+            }
+        }
+    });
+    __syncthreads();
+    scan_flush(ha, nza, bada, sga, wa, blockIdx.x);
+    scan_flush(hb, nzb, badb, sgb, wb, blockIdx.x);
+}
+
+__global__ __launch_bounds__(CUT_THREADS) void k_cut_pair(Ws *__restrict__ wa,
+                                                          Ws *__restrict__ wb, double tol,
+                                                          int score_mode, int nonstrict,
+                                                          int64_t n, int nscan,
+                                                          qdot_result *__restrict__ out_a,
+                                                          qdot_result *__restrict__ out_b)
+{
+    if (blockIdx.x == 0)
+        cut_body(wa, tol, score_mode, nonstrict, n, nscan, 0, 0, out_a, nullptr);
+    else
+        cut_body(wb, tol, score_mode, nonstrict, n, nscan, 0, 0, out_b, nullptr);
+}
+
+// grid 2 * g: partials of x . w at [0, g), of w . w at [g, 2 g)
+template <bool VEC, int U>
+__global__ __launch_bounds__(BLOCK) void k_acc_pair(const double *__restrict__ x,
+                                                    const double *__restrict__ w, int64_t n,
+                                                    int key_mode, const Ws *__restrict__ wa,
+                                                    const Ws *__restrict__ wb,
+                                                    double *__restrict__ partials, int g)
+{
+    const int b = blockIdx.x;
+    if (b < g)
+        acc_body<double, VEC, U, false>(x, w, n, key_mode, wa, partials, nullptr, b, g);
+    else
+        acc_body<double, VEC, U, false>(w, w, n, key_mode, wb, partials + (size_t)6 * g,
+                                        nullptr, b - g, g);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fin_pair(Ws *__restrict__ wa, Ws *__restrict__ wb,
+                                                    const double *__restrict__ partials, int g,
+                                                    qdot_result *__restrict__ out_a,
+                                                    qdot_result *__restrict__ out_b)
+{
+    if (blockIdx.x == 0)
+        fin_body(wa, partials, g, out_a);
+    else
+        fin_body(wb, partials + (size_t)6 * g, g, out_b);
+}
+
+template <bool VEC, int U>
+static hipError_t launch_pair_u(const Launch &La, const Launch &Lb, const double *x,
+                                const double *w, int64_t n, double tol, const qdot_options &o,
+                                qdot_result *out_a, qdot_result *out_b)
+{
+    hipStream_t s = La.stream;
+    const int nscan = grid_for(n, U, La.scan_blocks);
+    hipLaunchKernelGGL((k_scan_pair<VEC, U>), dim3(nscan), dim3(BLOCK), 0, s, x, w, n,
+                       o.key_mode, La.ws, Lb.ws);
+    if (o.guard_mode) {
+        // the guard stages run per product, after the shared pass 1
+        hipError_t e = launch_qdot_t<double>(La, x, w, n, tol, o, out_a, nullptr, nullptr, nscan);
+        if (e == hipSuccess)
+            e = launch_qdot_t<double>(Lb, w, w, n, tol, o, out_b, nullptr, nullptr, nscan);
+        return e;
+    }
+    hipLaunchKernelGGL(k_cut_pair, dim3(2), dim3(CUT_THREADS), 0, s, La.ws, Lb.ws, tol,
+                       o.score_mode, o.boundary_mode, n, nscan, out_a, out_b);
+    const int g = std::min(grid_for(n, U, La.acc_blocks), La.partial_cap / 2);
+    hipLaunchKernelGGL((k_acc_pair<VEC, U>), dim3(2 * g), dim3(BLOCK), 0, s, x, w, n,
+                       o.key_mode, La.ws, Lb.ws, La.partials, g);
+    hipLaunchKernelGGL(k_fin_pair, dim3(2), dim3(BLOCK), 0, s, La.ws, Lb.ws, La.partials, g,
+                       out_a, out_b);
+    return hipGetLastError();
+}
+
+template <bool VEC>
+static hipError_t launch_pair_v(const Launch &La, const Launch &Lb, const double *x,
+                                const double *w, int64_t n, double tol, const qdot_options &o,
+                                qdot_result *out_a, qdot_result *out_b)
+{
+    // one unroll for both passes: the pass-1 kernel reads two operands per
+    // key pair, like pass 2
+    switch (unroll_for<double>(La.acc_unroll)) {
+    case 1: return launch_pair_u<VEC, 1>(La, Lb, x, w, n, tol, o, out_a, out_b);
+    case 4: return launch_pair_u<VEC, 4>(La, Lb, x, w, n, tol, o, out_a, out_b);
+    default: return launch_pair_u<VEC, 2>(La, Lb, x, w, n, tol, o, out_a, out_b);
+    }
+}
+
+hipError_t launch_qdot_pair(const Launch &La, const Launch &Lb, const double *x,
+                            const double *w, int64_t n, double tol, const qdot_options &o,
+                            qdot_result *out_a, qdot_result *out_b)
+{
+    const bool vec = ((((uintptr_t)x) | ((uintptr_t)w)) & 15) == 0;
+    return vec ? launch_pair_v<true>(La, Lb, x, w, n, tol, o, out_a, out_b)
+               : launch_pair_v<false>(La, Lb, x, w, n, tol, o, out_a, out_b);
 }
 
 template <bool VEC, int U>

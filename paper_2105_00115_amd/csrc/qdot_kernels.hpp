@@ -10,7 +10,8 @@ namespace qd {
 struct Launch {
     hipStream_t stream;
     Ws *ws;             // device control block of the handle
-    double *partials;   // >= 6 * max_blocks doubles
+    double *partials;   // 6 * partial_cap doubles
+    int partial_cap;    // blocks whose partials fit
     int scan_blocks;    // persistent grid cap of the exponent scan
     int scan_unroll;    // 1, 2 or 4 groups of 4 elements in flight per lane
     int acc_blocks;     // grid cap of the accumulate pass / FP64 dot
@@ -32,6 +33,15 @@ int s1_depth(int64_t n, double tol, const qdot_options &o);
 hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_t n,
                        double tol, const qdot_options &o, qdot_result *out,
                        unsigned char *cls_out, long long *hist_out);
+
+// The power method's pair of inner products, lambda = x . w into out_a and
+// c = w . w into out_b, two-pass (accum_mode 0), with one shared pass-1
+// kernel and the cutoffs, sweeps and combines of both in one launch each
+// (guard_mode 1: its stages per product after the shared pass 1).  La and
+// Lb differ only in their workspace; the partials of La hold both sweeps.
+hipError_t launch_qdot_pair(const Launch &La, const Launch &Lb, const double *x,
+                            const double *w, int64_t n, double tol, const qdot_options &o,
+                            qdot_result *out_a, qdot_result *out_b);
 
 // The two-pass qdot of single-precision inputs (mu = m_single: no double
 // class); accum_mode and guard_mode must be 0.

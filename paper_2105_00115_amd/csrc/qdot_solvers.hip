@@ -9,6 +9,7 @@
 // per product and per sum (no fused multiply-add), the same arithmetic as a
 // plain sequential loop.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "qdot_handle.hpp"
@@ -27,42 +28,77 @@ constexpr int VB = 256;
 
 static inline int vgrid(int64_t n) { return (int)std::max<int64_t>(1, (n + VB - 1) / VB); }
 
-__global__ __launch_bounds__(VB) void k_spmv(int64_t n, const int32_t *__restrict__ rowptr,
-                                             const int32_t *__restrict__ col,
-                                             const double *__restrict__ val,
-                                             const double *__restrict__ x, double *__restrict__ y,
-                                             const SolverCtl *__restrict__ ctl)
+// ---------------------------------------------------------------------------
+// CSR SpMV, y = A v, every row summed in column-storage order (plain
+// multiply, then add: the arithmetic of a sequential loop).
+//
+// A block takes BLOCK consecutive rows at a time (grid-stride over row
+// groups).  Their entries are one contiguous range of col/val, read
+// coalesced SP_NZ at a time: each thread loads SP_U (col, val) pairs, then
+// their gathers v[col], and leaves the products in LDS; after a barrier
+// each thread adds its own row's products from LDS in order.  A row that
+// runs past the staged range continues with the next one, so rows of any
+// length keep their order.
+constexpr int SP_U = 8;
+constexpr int SP_NZ = SP_U * BLOCK;
+constexpr int SPMV_BLOCKS_PER_CU = 8;
+
+__global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col,
+                                                const double *__restrict__ val,
+                                                const double *__restrict__ v,
+                                                double *__restrict__ y,
+                                                const SolverCtl *__restrict__ ctl)
 {
+    __shared__ double prod[SP_NZ];
     if (ctl && ctl->done) return;
-    const int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x;
-    if (i >= n) return;
-    // the first SNZ entries' column and value loads, then their gathers, are
-    // all in flight before the row is summed in storage order
-    constexpr int SNZ = 8;
-    const int32_t beg = rowptr[i], len = rowptr[i + 1] - beg;
-    int32_t ci[SNZ];
-    double pv[SNZ];
-#pragma unroll
-    for (int jj = 0; jj < SNZ; jj++) {
-        ci[jj] = 0;
-        pv[jj] = 0.0;
-        if (jj < len) {
-            ci[jj] = col[beg + jj];
-            pv[jj] = val[beg + jj];
+    for (int64_t r0 = (int64_t)blockIdx.x * BLOCK; r0 < n; r0 += (int64_t)gridDim.x * BLOCK) {
+        const int64_t r1 = min(n, r0 + (int64_t)BLOCK);
+        const int64_t i = r0 + threadIdx.x;
+        const bool row = i < r1;
+        int64_t beg = 0, end = 0;
+        if (row) {
+            beg = rowptr[i];
+            end = rowptr[i + 1];
         }
-    }
+        const int64_t b0 = rowptr[r0], b1 = rowptr[r1];
+        double s = 0.0;
+        for (int64_t c0 = b0; c0 < b1; c0 += SP_NZ) {
+            const int64_t c1 = min(b1, c0 + (int64_t)SP_NZ);
+            __syncthreads();  // the previous range's products are consumed
+            int32_t ci[SP_U];
+            double pv[SP_U];
 #pragma unroll
-    for (int jj = 0; jj < SNZ; jj++)
-        if (jj < len) pv[jj] = pv[jj] * x[ci[jj]];
-    double s = 0.0;
+            for (int u = 0; u < SP_U; u++) {
+                const int64_t j = c0 + u * BLOCK + threadIdx.x;
+                ci[u] = 0;
+                pv[u] = 0.0;
+                if (j < c1) {
+                    ci[u] = col[j];
+                    pv[u] = val[j];
+                }
+            }
 #pragma unroll
-    for (int jj = 0; jj < SNZ; jj++)
-        if (jj < len) s = s + pv[jj];
-    for (int32_t j = beg + SNZ; j < beg + len; j++) {
-        const double p = val[j] * x[col[j]];
-        s = s + p;
+            for (int u = 0; u < SP_U; u++)
+                if (c0 + u * BLOCK + threadIdx.x < c1) pv[u] = pv[u] * v[ci[u]];
+#pragma unroll
+            for (int u = 0; u < SP_U; u++) prod[u * BLOCK + threadIdx.x] = pv[u];
+            __syncthreads();
+            if (row) {
+                const int64_t lo = max(beg, c0), hi = min(end, c1);
+                for (int64_t j = lo; j < hi; j++) s = s + prod[j - c0];
+            }
+        }
+        if (row) y[i] = s;
     }
-    y[i] = s;
+}
+
+static int spmv_grid(const qdot_handle *h, int64_t n)
+{
+    int bpc = SPMV_BLOCKS_PER_CU;
+    if (const char *e = std::getenv("QDOT_SPMV_BPC")) bpc = std::max(1, std::min(16, std::atoi(e)));
+    const int64_t cap = std::min<int64_t>(MAX_GRID, (int64_t)bpc * h->num_cus);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + BLOCK - 1) / BLOCK));
 }
 
 // dot-product result flags: a qdot that perforated every component of a
@@ -72,7 +108,11 @@ __device__ __forceinline__ bool all_perforated(const qdot_result *r)
     return r && (r->flags & QDOT_F_ALL_PERF) && r->n_bins > 0;
 }
 
-// power method: x = w / sqrt(c), lambda recorded
+// Power method, end of an iteration: x = w / sqrt(c) and lambda recorded,
+// or the breakdown recorded.  Every block takes the same decision from the
+// same two results; block 0 alone writes the control block (the other
+// blocks read only its `done` word, at their start, and a breakdown makes
+// them return whichever value they see).
 __global__ __launch_bounds__(VB) void k_pm_update(int64_t n, SolverCtl *ctl,
                                                   const double *lamval,
                                                   const qdot_result *lamres,
@@ -85,27 +125,22 @@ __global__ __launch_bounds__(VB) void k_pm_update(int64_t n, SolverCtl *ctl,
     const double c = *cval;
     const int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x;
     if (!(c > 0.0) || !isfinite(c) || all_perforated(cres) || all_perforated(lamres)) {
-        if (i == 0) ctl->broke = 1;
+        if (i == 0) {
+            ctl->broke = 1;
+            ctl->status = QDOT_E_BREAKDOWN;
+            ctl->done = 1;
+        }
         return;
     }
     if (i == 0) {
-        if (trace) trace[k] = *lamval;
+        const double lam = *lamval;
+        if (trace) trace[k] = lam;
+        ctl->c = lam;
+        ctl->iters += 1;
     }
     if (i >= n) return;
     const double s = sqrt(c);
     x[i] = w[i] / s;
-}
-
-__global__ void k_pm_step(SolverCtl *ctl, const double *lamval)
-{
-    if (ctl->done) return;
-    if (ctl->broke) {
-        ctl->status = QDOT_E_BREAKDOWN;
-        ctl->done = 1;
-        return;
-    }
-    ctl->c = *lamval;
-    ctl->iters += 1;
 }
 
 __global__ void k_ctl_reset(SolverCtl *ctl)
@@ -140,6 +175,23 @@ int32_t ensure_solver_vectors(qdot_handle *h, int64_t doubles)
             hipSuccess)
             return fail(h, QDOT_E_NOMEM, "solver vector allocation failed");
         h->vec_n = doubles;
+    }
+    return QDOT_OK;
+}
+
+// A second qdot workspace: the power method's two inner products of an
+// iteration are selected and summed side by side.
+static int32_t ensure_second_ws(qdot_handle *h)
+{
+    if (h->ws2) return QDOT_OK;
+    if (hipMalloc((void **)&h->ws2, sizeof(Ws)) != hipSuccess) {
+        h->ws2 = nullptr;
+        return fail(h, QDOT_E_NOMEM, "second workspace allocation failed");
+    }
+    if (hipMemset(h->ws2, 0, sizeof(Ws)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(h->ws2);
+        h->ws2 = nullptr;
+        return fail(h, QDOT_E_DEVICE, "second workspace clear failed");
     }
     return QDOT_OK;
 }
@@ -183,8 +235,8 @@ int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double *x, doub
     if (!csr_ok(A) || (A->n > 0 && (!x || !y))) return fail(h, QDOT_E_INVAL, "bad CSR or vector");
     if (A->n == 0) return QDOT_OK;
     DeviceGuard g(h->device);
-    hipLaunchKernelGGL(k_spmv, dim3(vgrid(A->n)), dim3(VB), 0, (hipStream_t)stream, A->n,
-                       A->rowptr, A->col, A->val, x, y, (const SolverCtl *)nullptr);
+    hipLaunchKernelGGL(k_spmv, dim3(spmv_grid(h, A->n)), dim3(BLOCK), 0, (hipStream_t)stream,
+                       A->n, A->rowptr, A->col, A->val, x, y, (const SolverCtl *)nullptr);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "spmv launch");
 }
@@ -217,6 +269,14 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
         return e == hipSuccess;
     };
     const int gv = vgrid(n);
+    // with the two-pass qdot both inner products of an iteration share
+    // their launches (launch_qdot_pair); the one-pass mode and the FP64 dot
+    // take them one after the other
+    const bool paired = use_qdot && o.accum_mode == 0;
+    if (paired && (st = ensure_second_ws(h)) != QDOT_OK) return st;
+    Launch L2 = L;
+    L2.ws = h->ws2;
+    const int sg = spmv_grid(h, n);
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, s, ctl);
     ok(hipGetLastError());
     SolverCtl hc;
@@ -224,13 +284,21 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     for (int32_t k = 0; k < iters && e == hipSuccess; k++) {
         const double *lv, *cv;
         const qdot_result *lr, *cr;
-        hipLaunchKernelGGL(k_spmv, dim3(gv), dim3(VB), 0, s, n, A->rowptr, A->col, A->val, x, w,
-                           (const SolverCtl *)ctl);
-        ok(enqueue_dot(h, L, x, w, n, use_qdot, qtol, o, h->res_ring, h->dres, &lv, &lr));
-        ok(enqueue_dot(h, L, w, w, n, use_qdot, qtol, o, h->res_ring + 1, h->dres + 1, &cv, &cr));
+        hipLaunchKernelGGL(k_spmv, dim3(sg), dim3(BLOCK), 0, s, n, A->rowptr, A->col, A->val, x,
+                           w, (const SolverCtl *)ctl);
+        if (paired) {
+            ok(launch_qdot_pair(L, L2, x, w, n, qtol, o, h->res_ring, h->res_ring + 1));
+            lv = &h->res_ring[0].value;
+            lr = h->res_ring;
+            cv = &h->res_ring[1].value;
+            cr = h->res_ring + 1;
+        } else {
+            ok(enqueue_dot(h, L, x, w, n, use_qdot, qtol, o, h->res_ring, h->dres, &lv, &lr));
+            ok(enqueue_dot(h, L, w, w, n, use_qdot, qtol, o, h->res_ring + 1, h->dres + 1, &cv,
+                           &cr));
+        }
         hipLaunchKernelGGL(k_pm_update, dim3(gv), dim3(VB), 0, s, n, ctl, lv, lr, cv, cr, x, w,
                            lambda_trace, k);
-        hipLaunchKernelGGL(k_pm_step, dim3(1), dim3(1), 0, s, ctl, lv);
         ok(hipGetLastError());
         if ((k + 1) % 64 == 0) {
             if ((st = read_ctl(h, s, hc)) != QDOT_OK) return st;

@@ -55,6 +55,46 @@ def test_spmv_bitwise_long_rows(h):
     np.testing.assert_array_equal(y.cpu().numpy(), oracle.spmv(rp, col, val, x))
 
 
+def ragged_csr(n, seed):
+    """Random CSR with empty rows and rows longer than the SpMV's staged
+    range (2048 products), some straddling row groups of 256."""
+    g = workloads.rng(seed)
+    lens = g.integers(0, 12, n)
+    lens[1000:1300] = 0
+    for r, ln in ((5, 2500), (300, 9000), (511, 2049), (512, 2048), (767, 4097), (n - 1, 3000)):
+        lens[r] = ln
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(lens, out=rp[1:])
+    col = g.integers(0, n, int(rp[-1])).astype(np.int32)
+    val = g.standard_normal(int(rp[-1]))
+    return rp, col, val
+
+
+@pytest.fixture
+def spmv_blocks(monkeypatch):
+    """Sets the SpMV grid (blocks per CU) for one test."""
+    def put(bpc):
+        if bpc is not None:
+            monkeypatch.setenv("QDOT_SPMV_BPC", str(bpc))
+    return put
+
+
+@pytest.mark.parametrize("bpc", [None, 1])
+def test_spmv_bitwise_ragged(h, spmv_blocks, bpc):
+    # rows split over several staged ranges keep their order; with one block
+    # per CU the 274 row groups are walked grid-stride
+    n = 70000
+    rp, col, val = ragged_csr(n, 11)
+    spmv_blocks(bpc)
+    A = q.Csr(rp, col, val)
+    x = workloads.normal_vector(n, 12)
+    y = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    print(f"[gpu-case] spmv ragged n={n} nnz={rp[-1]} bpc={bpc}", flush=True)
+    h.spmv(A, dev(x), y)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(y.cpu().numpy(), oracle.spmv(rp, col, val, x))
+
+
 def test_cg_long_rows(h):
     rp, col, val = workloads.random_spd_csr(5000, 6, 2)
     A = q.Csr(rp, col, val)
@@ -163,6 +203,64 @@ def test_power_method(h, m):
         assert r["status"] == q.OK
         np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
         assert r["lambda"] <= lam_max * (1 + 1e-12)
+
+
+def test_power_method_grid_stride(h, spmv_blocks):
+    # 110592 rows on one block per CU: the SpMV walks two row groups in some
+    # blocks; both inner products share their launches (x.w and w.w)
+    m = 48
+    rp, col, val = workloads.laplacian3d_csr(m)
+    spmv_blocks(1)
+    A = q.Csr(rp, col, val)
+    x0 = workloads.unit_vector(m ** 3, 9)
+    print(f"[gpu-case] power grid-stride m={m}", flush=True)
+    for use_qdot in (1, 0):
+        r = h.power(A, dev(x0), 60, 1e-6, use_qdot)
+        o = oracle.power(rp, col, val, x0, 60, 1e-6, use_qdot)
+        assert r["status"] == q.OK
+        np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("m,opt", [(16, None), (40, None), (128, None), (16, [0, 0, 0, 0, 1])])
+def test_power_pair_matches_separate_calls(h, m, opt):
+    # one iteration: lambda = x0 . A x0 and c = w . w from the paired
+    # launches equal two separate qdot calls (same classes, same pass-2
+    # blocks), and x = w / sqrt(c)
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, val)
+    x0 = workloads.unit_vector(m ** 3, 14)
+    print(f"[gpu-case] power pair m={m} opt={opt}", flush=True)
+    xd = dev(x0)
+    r = h.power(A, xd, 1, 1e-6, 1, opt=opt)
+    w = torch.empty_like(xd)
+    h.spmv(A, dev(x0), w)
+    lam = h.qdot(dev(x0), w, 1e-6, opt=opt)
+    c = h.qdot(w, w, 1e-6, opt=opt)
+    assert r["status"] == q.OK
+    assert r["trace"][0] == lam["value"], (r["trace"][0], lam["value"])
+    np.testing.assert_allclose(xd.cpu().numpy(), w.cpu().numpy() / math.sqrt(c["value"]),
+                               rtol=4e-16, atol=0)
+
+
+def test_power_method_breakdown(h):
+    # A = 0: w = 0, so c = w.w = 0 at the first iteration.  The later
+    # iterations (up to the first control read, after 64) run on a broken
+    # state; the handle is still sound afterwards.
+    m = 8
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, np.zeros_like(val))
+    x0 = workloads.unit_vector(m ** 3, 10)
+    for use_qdot in (1, 0):
+        r = h.power(A, dev(x0), 100, 1e-6, use_qdot)
+        o = oracle.power(rp, col, np.zeros_like(val), x0, 100, 1e-6, use_qdot)
+        assert r["status"] == q.E_BREAKDOWN and o["status"] == oracle.E_BREAKDOWN
+    x, y = workloads.log_uniform_pair(5000, 13, -20.0, 20.0)
+    rr = h.qdot(dev(x), dev(y), 1e-6)
+    oo = oracle.qdot(x, y, 1e-6)
+    assert rr["count"] == oo["count"] and rr["flags"] == oo["flags"]
+    rl = h.power(q.Csr(rp, col, val), dev(x0), 20, 1e-6, 1)
+    ol = oracle.power(rp, col, val, x0, 20, 1e-6, 1)
+    np.testing.assert_allclose(rl["trace"], ol["trace"], rtol=1e-9, atol=0)
 
 
 @pytest.mark.timeout(300)
