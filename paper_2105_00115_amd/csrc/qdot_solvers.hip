@@ -3,11 +3,12 @@
 // a persistent launch: qdot_cg.hip, qdot_cg.hpp.)
 //
 // All state stays in device memory.  The host enqueues iterations in
-// batches and reads a small control block between batches; kernels of
-// iterations enqueued after a breakdown see the `done` flag and return, so
-// the host syncs only once per batch.  Vector updates are one IEEE operation
-// per product and per sum (no fused multiply-add), the same arithmetic as a
-// plain sequential loop.
+// batches of 64 and reads a small control block between batches, so it
+// syncs only once per batch.  After a breakdown the SpMV and the update of
+// the iterations still enqueued see the `done` flag and return; their inner
+// products run on the unchanged vectors and their results are not used.
+// Vector updates are one IEEE operation per product and per sum (no fused
+// multiply-add), the same arithmetic as a plain sequential loop.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
