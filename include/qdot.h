@@ -135,7 +135,8 @@ typedef struct qdot_options {
      *    again (QDOT_F_RESELECTED) and the check is repeated with the
      *    larger of the two lower bounds.  Needs key_mode 0 and accum_mode
      *    0; accepted by qdot_async, qdot, qdot_classes_async, the qdot_f32
-     *    entry points and qdot_power, QDOT_E_INVAL elsewhere. */
+     *    entry points, qdot_power and qdot_cg, QDOT_E_INVAL elsewhere (the
+     *    batched entry points). */
     int32_t guard_mode;
 } qdot_options;
 
@@ -414,7 +415,10 @@ QDOT_API int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double
  * The whole solve is one persistent launch of up to one block per CU
  * (environment variable QDOT_CG_BLOCKS caps the block count).  A gang
  * barrier that does not complete within its spin limit ends the solve with
- * QDOT_E_DEVICE.  accum_mode and guard_mode must be 0 (QDOT_E_INVAL). */
+ * QDOT_E_DEVICE.  accum_mode must be 0 (QDOT_E_INVAL).  guard_mode 1 runs
+ * the guaranteed mode on every qdot of the solve (same decisions, flags,
+ * lower bound and passes as qdot_async; a reselected product costs one more
+ * sweep of the gang's rows and one more gang barrier). */
 QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x,
                 double rtol, double qtol, int32_t maxit, int32_t use_qdot,
                 const qdot_options *opt, void *stream, qdot_cg_result *out,

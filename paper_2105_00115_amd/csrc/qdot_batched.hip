@@ -332,8 +332,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
         if (I.type == IT_CG) {
             // one block of a CG gang: its other blocks hold the neighbouring
             // tickets, so they are taken by blocks that are running
-            cg_solve(sys[I.inst], gangs + I.inst, I.large, I.slot, key_mode, score_mode,
-                     nonstrict, LD, cg_out + I.inst);
+            cg_solve<false>(sys[I.inst], gangs + I.inst, I.large, I.slot, key_mode, score_mode,
+                            nonstrict, LD, cg_out + I.inst);
             __syncthreads();
             continue;
         }

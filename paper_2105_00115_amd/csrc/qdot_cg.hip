@@ -9,6 +9,7 @@
 
 namespace qd {
 
+template <bool GUARD>
 __global__ __launch_bounds__(BLOCK) void k_cg_gangs(const CgSys *__restrict__ sys,
                                                     const int *__restrict__ gang_sys,
                                                     const int *__restrict__ gang_sys_off,
@@ -23,7 +24,8 @@ __global__ __launch_bounds__(BLOCK) void k_cg_gangs(const CgSys *__restrict__ sy
     const int g = blockIdx.x / G, gb = blockIdx.x % G;
     Gang *gg = gangs + g;
     for (int s = gang_sys_off[g]; s < gang_sys_off[g + 1]; s++) {
-        cg_solve(sys[gang_sys[s]], gg, G, gb, key_mode, score_mode, nonstrict, L, res + gang_sys[s]);
+        cg_solve<GUARD>(sys[gang_sys[s]], gg, G, gb, key_mode, score_mode, nonstrict, L,
+                        res + gang_sys[s]);
         if (__hip_atomic_load(&gg->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
     }
 }
@@ -112,8 +114,7 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
-    if (o.accum_mode != 0 || o.guard_mode != 0)
-        return fail(h, QDOT_E_INVAL, "the CG launch needs accum_mode 0 and guard_mode 0");
+    if (o.accum_mode != 0) return fail(h, QDOT_E_INVAL, "the CG launch needs accum_mode 0");
     if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
     DeviceGuard g(h->device);
@@ -147,8 +148,14 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     if (e == hipSuccess) e = hipMemcpyAsync(d->gsys, gl, sizeof gl, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_gang_init, dim3(1), dim3(BLOCK), 0, s, d->gangs, 1);
-        hipLaunchKernelGGL(k_cg_gangs, dim3(G), dim3(BLOCK), 0, s, d->sys, d->gsys, d->gsys + 1,
-                           d->gangs, G, d->res, o.key_mode, o.score_mode, o.boundary_mode);
+        if (o.guard_mode)
+            hipLaunchKernelGGL(k_cg_gangs<true>, dim3(G), dim3(BLOCK), 0, s, d->sys, d->gsys,
+                               d->gsys + 1, d->gangs, G, d->res, o.key_mode, o.score_mode,
+                               o.boundary_mode);
+        else
+            hipLaunchKernelGGL(k_cg_gangs<false>, dim3(G), dim3(BLOCK), 0, s, d->sys, d->gsys,
+                               d->gsys + 1, d->gangs, G, d->res, o.key_mode, o.score_mode,
+                               o.boundary_mode);
         e = hipGetLastError();
     }
     if (e == hipSuccess)

@@ -7,7 +7,8 @@
 // separate the steps that need data from other slices:
 //   before the SpMV (p complete), after a qdot's pass 1 (histogram merged),
 //   after its pass 2 (partials written),
-// five per iteration.  Between those barriers every block computes the
+// five per iteration (one more for an inner product that the guaranteed
+// mode sums again).  Between those barriers every block computes the
 // cutoff and the final combine of each qdot itself, from the same merged
 // histogram and the same partials in the same order, so every block holds
 // bit-identical scalars (alpha, beta, c) and takes the same branches: the
@@ -40,12 +41,15 @@ struct CgSys {
     qdot_result *trace;  // nullable: 2 * maxit + 1 results
 };
 
+constexpr int MAX_GANG = 256;
+
 struct GangQ {  // per gang and qdot buffer
     unsigned int hist[W];
-    int lo, hi;
-    unsigned long long n_zero;
-    unsigned int bad;
-    unsigned int pad;
+    // per block: live slot range, zero count, and non-finite flag (bit 0)
+    // with the signs of the nonzero products (bit 1 negative, bit 2
+    // positive); written by every block for every inner product, so never
+    // cleared
+    int4 rec[MAX_GANG];
 };
 
 constexpr int BAR_GROUPS = 8;    // first level of the barrier of a large gang
@@ -57,11 +61,10 @@ struct Gang {
     unsigned int abort;
     unsigned int pad;
     GangQ qb[2];
-    double partials[2][256 * 6];  // up to MAX_GANG blocks per gang
+    double partials[2][MAX_GANG * 6];
     unsigned int bar_sub[BAR_GROUPS][32];  // group counters, one 128-byte line each
 };
 
-constexpr int MAX_GANG = 256;
 
 // ---------------------------------------------------------------------------
 // Gang barrier.  Everything a block hands to the others (vector entries,
@@ -135,25 +138,42 @@ struct CgLds {
     int4 scratch[BLOCK / 64];
     qdot_result res;
     double dval;
+    double sval;  // S of the last qdot combine (units of 2^e_max)
 };
 
 // Pass 1 of qdot for one component pair, into the block's LDS histogram.
 __device__ __forceinline__ void scan_pair(double a, double b, int key_mode, CgLds &L,
-                                          unsigned int &nz, unsigned int &bad)
+                                          unsigned int &nz, unsigned int &bad, unsigned int &sg)
 {
     const Comp c = component(a, b, key_mode);
     nz += c.zero ? 1u : 0u;
     bad |= c.bad ? 1u : 0u;
+    sg |= c.zero ? 0u : (c.sgn ? 1u : 2u);
     atomicAdd(&L.h[c.slot], 1u);
 }
 
 // a.b over the gang's rows by qdot (buffer k), value identical in every block.
 // With `scanned` the caller has already put its rows' keys into L.h (while
-// it produced a or b) and passes its zero count and non-finite flag.
-__device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, int64_t n, int64_t r0, int64_t r1,
-                            double tol, int key_mode, int score_mode, int nonstrict, Gang *gg,
-                            int G, int gb, int k, CgLds &L, qdot_result *trace_slot,
-                            bool scanned = false, unsigned int nz = 0, unsigned int bad = 0)
+// it produced a or b) and passes its zero count, non-finite flag and sign
+// bits.  After the histogram merge each block copies the merged window into
+// its LDS histogram (counts of one system fit 32 bits) and selects from
+// there; the copy is cleared before returning.
+//
+// GUARD (guard_mode 1): after the combine every block evaluates the lower
+// bound of Thm 3.4 from its copy of the histogram and its class table, and
+// certifies the result or reselects against E_lo (or makes every bin
+// double) and sums its rows again, into the other partials buffer (free:
+// every block has read it in the previous inner product), then checks again
+// with the larger lower bound: the steps and flags of the single-vector
+// guaranteed mode, one more gang barrier when it reselects.
+template <bool GUARD>
+__device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, int64_t n,
+                                            int64_t r0, int64_t r1, double tol, int key_mode,
+                                            int score_mode, int nonstrict, Gang *gg,
+                                            int G, int gb, int k, CgLds &L,
+                                            qdot_result *trace_slot, bool scanned = false,
+                                            unsigned int nz = 0, unsigned int bad = 0,
+                                            unsigned int sg = 0)
 {
     DotOut o = {0.0, false, true};
     GangQ &Q = gg->qb[k];
@@ -167,6 +187,7 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
                 const bool valid = e < lim;
                 nz += (valid & c.zero) ? 1u : 0u;
                 bad |= (valid & c.bad) ? 1u : 0u;
+                sg |= (valid & !c.zero) ? (c.sgn ? 1u : 2u) : 0u;
                 if (valid) atomicAdd(&L.h[c.slot], 1u);
             }
         };
@@ -187,37 +208,51 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
         }
     }
     if (threadIdx.x == 0) L.h[W] = 0u;
-    block_reduce_range(lo, hi, nz, bad, L.scratch);
+    // the block's record, a plain write-through store: same-word atomics of
+    // every block would queue at one address, and the wait for them before
+    // the barrier would put that whole queue on every block's path
+    unsigned int bs = (bad ? 1u : 0u) | (sg << 1);
+    block_reduce_range(lo, hi, nz, bs, L.scratch);
     if (threadIdx.x == 0) {
-        if (hi >= 0) {
-            __hip_atomic_fetch_min(&Q.lo, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_max(&Q.hi, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (nz)
-            __hip_atomic_fetch_add(&Q.n_zero, (unsigned long long)nz, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        if (bad) __hip_atomic_fetch_or(&Q.bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int *rec = &Q.rec[gb].x;
+        st_dev(rec, lo);
+        st_dev(rec + 1, hi);
+        st_dev(rec + 2, (int)nz);
+        st_dev(rec + 3, (int)bs);
     }
     if (!gang_barrier(gg, G, gb)) {
         o.ok = false;
         return o;
     }
+    // the gang's records, reduced in every block (counts of one system fit
+    // 32 bits), then the merged histogram window into this block's LDS copy
+    int glo = W, ghi = -1;
+    unsigned int gz = 0, gbs = 0;
+    for (int c = threadIdx.x; c < G; c += BLOCK) {
+        const int *rec = &Q.rec[c].x;
+        glo = min(glo, ld_dev(rec));
+        ghi = max(ghi, ld_dev(rec + 1));
+        gz += (unsigned int)ld_dev(rec + 2);
+        gbs |= (unsigned int)ld_dev(rec + 3);
+    }
+    block_reduce_range(glo, ghi, gz, gbs, L.scratch);
+    const unsigned long long gnz = gz;
+    const unsigned int gbad = gbs & 1u;
+    const unsigned int gsg = gbs >> 1;
+    for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) L.h[j] = ld_dev(&Q.hist[j]);
+    __syncthreads();
     // cutoff, redundantly in every block, into the block's own class table
-    const int glo = ld_dev(&Q.lo);
-    const int ghi = ld_dev(&Q.hi);
-    const unsigned long long gnz = ld_dev(&Q.n_zero);
-    const unsigned int gbad = ld_dev(&Q.bad);
-    auto get = [&](int j) { return (unsigned long long)ld_dev(&Q.hist[j]); };
+    auto get = [&](int j) { return (unsigned long long)L.h[j]; };
     auto put = [&](int j, int c) { L.lut[j] = (unsigned char)c; };
     auto noclear = [&](int) {};
     const CutParams p = block_cutoff<BLOCK>(glo, ghi, gnz, gbad, n, tol, score_mode, nonstrict,
                                             get, put, noclear, &L.res, nullptr);
-    // pass 2 over own rows
-    if (!p.skip) {
+    // pass 2 over own rows into partials buffer kp, combine in every block
+    auto sweep = [&](const CutParams &cp, int kp, int flags) -> bool {
         Acc acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
         auto body = [&](const double *xv, const double *yv, int64_t, int lim) {
-            acc_group<false>(xv, yv, lim, L.lut, key_mode, p.e_max, p.c32, true, acc[0], acc[1],
-                             acc[2], nullptr);
+            acc_group<false>(xv, yv, lim, L.lut, key_mode, cp.e_max, cp.c32, true, acc[0],
+                             acc[1], acc[2], nullptr);
         };
         if (vec)
             stream_strided<true, 2>(a, bv, r0, 2 * CHUNK, r1, body);
@@ -225,43 +260,105 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
             stream_strided<false, 2>(a, bv, r0, 2 * CHUNK, r1, body);
         block_reduce3<BLOCK>(acc, L.red);
         if (threadIdx.x == 0) {
-            double *pp = gg->partials[k] + gb * 6;
+            double *pp = gg->partials[kp] + gb * 6;
             for (int q = 0; q < 3; q++) {
                 st_dev(&pp[2 * q], acc[q].s);
                 st_dev(&pp[2 * q + 1], acc[q].c);
             }
         }
-    }
-    if (!gang_barrier(gg, G, gb)) {
+        if (!gang_barrier(gg, G, gb)) return false;
+        // the gang's partials in block order, in every block
+        Acc f[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        for (int c = threadIdx.x; c < G; c += BLOCK) {
+            const double *pp = gg->partials[kp] + c * 6;
+            for (int q = 0; q < 3; q++)
+                f[q] = acc_merge(f[q], Acc{ld_dev(&pp[2 * q]), ld_dev(&pp[2 * q + 1])});
+        }
+        block_reduce3<BLOCK>(f, L.red);
+        if (threadIdx.x == 0) L.sval = combine_value(f, cp.e_max, cp.c32, flags, &L.res);
+        return true;
+    };
+    if (threadIdx.x == 0) L.sval = 0.0;
+    if (!p.skip) {
+        if (!sweep(p, k, p.flags)) {
+            o.ok = false;
+            return o;
+        }
+    } else if (!gang_barrier(gg, G, gb)) {
         o.ok = false;
         return o;
     }
-    if (!p.skip) {
-        // combine the gang's partials in block order, in every block
-        Acc acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-        for (int c = threadIdx.x; c < G; c += BLOCK) {
-            const double *pp = gg->partials[k] + c * 6;
-            for (int q = 0; q < 3; q++)
-                acc[q] = acc_merge(acc[q], Acc{ld_dev(&pp[2 * q]), ld_dev(&pp[2 * q + 1])});
-        }
-        block_reduce3<BLOCK>(acc, L.red);
-        if (threadIdx.x == 0) combine_value(acc, p.e_max, p.c32, p.flags, &L.res);
-    }
     __syncthreads();
+    // block 0 clears the gang buffer for the qdot after next; every block
+    // has finished reading it (its copy was taken before the barrier above)
+    if (gb == 0) {
+        for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) st_dev(&Q.hist[j], 0u);
+    }
+    if constexpr (GUARD) {
+        __shared__ int s_go, s_dref, s_passes;
+        __shared__ double s_low;
+        if (threadIdx.x == 0) {
+            s_go = L.res.status == QDOT_OK && L.res.n_bins > 0;
+            // every product zero: +0 is exact
+            if (L.res.status == QDOT_OK && L.res.n_bins == 0) L.res.flags |= QDOT_F_GUARANTEED;
+            s_dref = 0;
+            s_passes = L.res.passes;
+        }
+        __syncthreads();
+        if (s_go) {
+            const int e_max = L.res.e_max;
+            const GuardSums g0 = guard_sums<BLOCK>(get, L.lut, glo, ghi, e_max);
+            if (threadIdx.x == 0) {
+                const double low = guard_lower(g0, L.sval, n, gsg);
+                if (guard_certified(L.res.bound_rel, low, tol)) {
+                    L.res.flags |= QDOT_F_GUARANTEED;
+                    L.res.lower = ldexp(low, e_max);
+                } else {
+                    // L <= 0: every bin double (scores >= 23, one more
+                    // non-strict)
+                    const int ref = low > 0.0 ? e_max + ilogb(low)
+                                              : L.res.e_min - L.res.t - 22 - nonstrict;
+                    if (ref < e_max) {
+                        s_dref = e_max - ref;
+                        s_low = low;
+                    } else {
+                        L.res.lower = low > 0.0 ? ldexp(low, e_max) : 0.0;
+                    }
+                }
+            }
+            __syncthreads();
+            if (s_dref) {
+                // reselection against e_ref = e_max - dref, second sweep
+                const CutParams p2 = block_cutoff<BLOCK>(glo, ghi, gnz, 0u, n, tol, score_mode,
+                                                         nonstrict, get, put, noclear, &L.res,
+                                                         nullptr, s_dref);
+                if (threadIdx.x == 0) {
+                    L.res.flags |= QDOT_F_RESELECTED;
+                    L.res.passes = s_passes + (p2.skip ? 0 : 1);
+                    L.sval = 0.0;
+                }
+                if (!p2.skip && !sweep(p2, k ^ 1, p2.flags | QDOT_F_RESELECTED)) {
+                    o.ok = false;
+                    return o;
+                }
+                __syncthreads();
+                const GuardSums g1 = guard_sums<BLOCK>(get, L.lut, glo, ghi, e_max);
+                if (threadIdx.x == 0) {
+                    const double low = fmax(guard_lower(g1, L.sval, n, gsg), s_low);
+                    L.res.flags |= QDOT_F_RESELECTED |
+                                   (guard_certified(L.res.bound_rel, low, tol) ? QDOT_F_GUARANTEED
+                                                                               : 0);
+                    L.res.lower = low > 0.0 ? ldexp(low, e_max) : 0.0;
+                }
+            }
+        }
+        __syncthreads();
+    }
     o.value = L.res.value;
     o.all_perf = (L.res.flags & QDOT_F_ALL_PERF) && L.res.n_bins > 0;
     if (threadIdx.x == 0 && trace_slot) *trace_slot = L.res;
-    // block 0 clears this buffer for the qdot after next; every block has
-    // finished reading it (it passed the barrier above after its cutoff)
-    if (gb == 0) {
-        for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) st_dev(&Q.hist[j], 0u);
-        if (threadIdx.x == 0) {
-            st_dev(&Q.lo, (int)W);
-            st_dev(&Q.hi, -1);
-            st_dev(&Q.n_zero, 0ull);
-            st_dev(&Q.bad, 0u);
-        }
-    }
+    // the LDS copy of the histogram back to zero for the next scan
+    for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) L.h[j] = 0u;
     __syncthreads();
     return o;
 }
@@ -319,7 +416,8 @@ constexpr int SNZ = 8;
 template <bool SCAN = false>
 __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, double *out, int64_t r0,
                                           int64_t r1, int key_mode = 0, CgLds *L = nullptr,
-                                          unsigned int *nz = nullptr, unsigned int *bad = nullptr)
+                                          unsigned int *nz = nullptr, unsigned int *bad = nullptr,
+                                          unsigned int *sg = nullptr)
 {
     for (int64_t base = r0; base < r1; base += (int64_t)SR * BLOCK) {
         int32_t beg[SR], len[SR];
@@ -364,15 +462,17 @@ __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, doubl
             const int64_t i = base + u * BLOCK + threadIdx.x;
             if (i < r1) {
                 out[i] = s;
-                if (SCAN) scan_pair(v[i], s, key_mode, *L, *nz, *bad);
+                if (SCAN) scan_pair(v[i], s, key_mode, *L, *nz, *bad, *sg);
             }
         }
     }
 }
 
 // One CG solve by one gang.
-__device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb, int key_mode, int score_mode,
-                         int nonstrict, CgLds &L, qdot_cg_result *res)
+template <bool GUARD>
+__device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb, int key_mode,
+                                         int score_mode, int nonstrict, CgLds &L,
+                                         qdot_cg_result *res)
 {
     const int64_t n = S.n;
     // rows of this block: a multiple of CHUNK each, so qdot tiles line up
@@ -381,11 +481,12 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
     int k = 0;  // qdot buffer / partials parity
     int ntr = 0;
     auto dot = [&](const double *a, const double *bv, bool scanned = false, unsigned int nz = 0,
-                   unsigned int bad = 0) {
+                   unsigned int bad = 0, unsigned int sg = 0) {
         DotOut o;
         if (S.use_qdot) {
-            o = gang_qdot(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict, gg, G, gb, k,
-                          L, (gb == 0 && S.trace) ? S.trace + ntr : nullptr, scanned, nz, bad);
+            o = gang_qdot<GUARD>(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict, gg,
+                                 G, gb, k, L, (gb == 0 && S.trace) ? S.trace + ntr : nullptr,
+                                 scanned, nz, bad, sg);
             ntr++;
         } else {
             o = gang_dot64(a, bv, r0, r1, gg, G, gb, k, L);
@@ -423,13 +524,13 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
             break;
         }
         if (!(healthy = gang_barrier(gg, G, gb))) break;  // p complete
-        unsigned int nz1 = 0, bad1 = 0;
+        unsigned int nz1 = 0, bad1 = 0, sg1 = 0;
         if (S.use_qdot)
-            spmv_rows<true>(S, S.p, S.q, r0, r1, key_mode, &L, &nz1, &bad1);
+            spmv_rows<true>(S, S.p, S.q, r0, r1, key_mode, &L, &nz1, &bad1, &sg1);
         else
             spmv_rows(S, S.p, S.q, r0, r1);
         __syncthreads();
-        const DotOut d = dot(S.p, S.q, S.use_qdot != 0, nz1, bad1);
+        const DotOut d = dot(S.p, S.q, S.use_qdot != 0, nz1, bad1, sg1);
         if (!(healthy = d.ok)) break;
         if (!(d.value > 0.0) || !isfinite(d.value) || d.all_perf) {
             status = QDOT_E_BREAKDOWN;
@@ -438,7 +539,7 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
         const double alpha = c / d.value;
         // x += alpha p, r -= alpha q (four rows' loads in flight per thread),
         // with pass 1 of the qdot r . r that follows fused in
-        unsigned int nz2 = 0, bad2 = 0;
+        unsigned int nz2 = 0, bad2 = 0, sg2 = 0;
         const bool scan_r = S.use_qdot != 0;
         auto xr_row = [&](int64_t i, double pi, double xi, double qi, double ri) {
             const double ap = alpha * pi;
@@ -446,7 +547,7 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
             const double aq = alpha * qi;
             const double rn = ri - aq;
             S.r[i] = rn;
-            if (scan_r) scan_pair(rn, rn, key_mode, L, nz2, bad2);
+            if (scan_r) scan_pair(rn, rn, key_mode, L, nz2, bad2, sg2);
         };
         {
             int64_t i = r0 + threadIdx.x;
@@ -465,7 +566,7 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
             for (; i < r1; i += BLOCK) xr_row(i, S.p[i], S.x[i], S.q[i], S.r[i]);
         }
         __syncthreads();
-        const DotOut cn = dot(S.r, S.r, scan_r, nz2, bad2);
+        const DotOut cn = dot(S.r, S.r, scan_r, nz2, bad2, sg2);
         if (!(healthy = cn.ok)) break;
         if (cn.all_perf) {
             status = QDOT_E_BREAKDOWN;
@@ -530,12 +631,6 @@ __device__ __forceinline__ void gang_reset(Gang *gg)
     if (threadIdx.x == 0) {
         gg->bar_count = 0;
         gg->abort = 0;
-        for (int k = 0; k < 2; k++) {
-            gg->qb[k].lo = W;
-            gg->qb[k].hi = -1;
-            gg->qb[k].n_zero = 0;
-            gg->qb[k].bad = 0;
-        }
     }
 }
 

@@ -251,90 +251,14 @@ __global__ __launch_bounds__(BLOCK) void k_fin(Ws *__restrict__ ws,
 }
 
 // ---------------------------------------------------------------------------
-// Guaranteed mode (guard_mode 1, Thm 3.4).  After a sweep of pass 2 the sum
-// S (units of 2^e_max) and a bound a of every error of the call, evaluated
-// from the histogram and the classes alone,
-//   a = (Q + T + F)(1 + 2^-40),
-//   Q = sum_k M_k 2^(k-e_max+1) rho(class_k)                  quantisation
-//   T = g6 (1 + 2^-9) sum_{single, half bins} M_k 2^(k-e_max+1)  FP32 trees
-//   F = 2^-52 |S| + 4 gn^2 (1 + 2^-8) sum_{kept bins} M_k 2^(k-e_max+1)
-//       + (2n + 4) 2^-1074                  FP64 stage, subnormal scaling
-// give the lower bound L = |S| (1 - 2^-52) - a of |x.y|, raised to 1 when
-// every non-zero product has one sign (|x.y| >= max |x_i y_i| >= 2^e_max).
-// When L > 0, E_lo = e_max + flexp(L) <= flexp(x.y), and the call is
-// certified when bound_rel 2^(e_max - E_lo) <= eps.
+// Guaranteed mode (guard_mode 1, Thm 3.4): the lower bound L of |x.y| and
+// the certification test are those of guard_sums / guard_lower.
 // Stage 0 (after the first sweep): certify, or reselect against E_lo (or
 // make every bin double when L <= 0) so that the second sweep of k_acc and
 // k_fin runs.  Stage 1 (after the second sweep; returns unless it ran):
 // check again with the larger of the two lower bounds.
 // One workgroup of CUT_THREADS threads.
 // ---------------------------------------------------------------------------
-struct GuardSums {
-    double q, f32, kept;
-};
-
-__device__ __forceinline__ double guard_rho(int c)
-{
-    // largest relative error of one leaf of each class
-    return c == QDOT_DOUBLE ? 0x1p-53
-         : c == QDOT_SINGLE ? 0x1.8p-23 + 0x1.8p-47 + 0x1p-72  // (1+2^-24)^3 - 1
-         : c == QDOT_HALF   ? 0x1p-10 + 0x1p-22                // (1+2^-11)^2 - 1
-                            : 1.0;
-}
-
-template <int NT>
-__device__ GuardSums guard_sums(const long long *__restrict__ hs,
-                                const unsigned char *__restrict__ lut, int lo, int hi, int e_max)
-{
-    constexpr int NW = NT / 64;
-    __shared__ double s_v[3][NW];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int j = lo + tid; j <= hi; j += NT) {
-        const long long m = hs[j];
-        if (m == 0) continue;
-        const int e = j + KMIN - e_max + 1;
-        const int c = lut[j];
-        const double w = ldexp((double)m, e);
-        v[0] += ldexp((double)m * guard_rho(c), e);
-        v[1] += (c == QDOT_SINGLE || c == QDOT_HALF) ? w : 0.0;
-        v[2] += c != QDOT_PERF ? w : 0.0;
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-        for (int q = 0; q < 3; q++) v[q] += __shfl_xor(v[q], m, 64);
-    if (lane == 0)
-        for (int q = 0; q < 3; q++) s_v[q][wv] = v[q];
-    __syncthreads();
-    GuardSums g = {0.0, 0.0, 0.0};
-    for (int w = 0; w < NW; w++) {
-        g.q += s_v[0][w];
-        g.f32 += s_v[1][w];
-        g.kept += s_v[2][w];
-    }
-    __syncthreads();
-    return g;
-}
-
-__device__ __forceinline__ double guard_lower(const GuardSums &g, double S, int64_t n,
-                                              unsigned int signs)
-{
-    const double g6 = 6.0 * 0x1p-24 / (1.0 - 6.0 * 0x1p-24);
-    const double nu = (double)n * 0x1p-53;
-    const double gn = nu / (1.0 - nu);
-    const double F = 0x1p-52 * fabs(S) + 4.0 * gn * gn * (1.0 + 0x1p-8) * g.kept +
-                     (2.0 * (double)n + 4.0) * 0x1p-1074;
-    const double a = (g.q + g6 * (1.0 + 0x1p-9) * g.f32 + F) * (1.0 + 0x1p-40);
-    double low = fabs(S) * (1.0 - 0x1p-52) - a;
-    if (signs != 3u && low < 1.0) low = 1.0;  // one sign: |x.y| >= 2^e_max
-    return low;
-}
-
-__device__ __forceinline__ bool guard_certified(double bound_rel, double low, double tol)
-{
-    return low > 0.0 && ldexp(bound_rel, -ilogb(low)) <= tol;
-}
-
 __global__ __launch_bounds__(CUT_THREADS) void k_guard(Ws *__restrict__ ws,
                                                        const long long *__restrict__ hs,
                                                        double tol, int score_mode, int nonstrict,
@@ -363,7 +287,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_guard(Ws *__restrict__ ws,
     if (!s_go) return;
     const int e_max = out->e_max;
     const int lo = ws->s1_lo, hi = ws->s1_hi;
-    const GuardSums g = guard_sums<CUT_THREADS>(hs, ws->lut, lo, hi, e_max);
+    const GuardSums g =
+        guard_sums<CUT_THREADS>([&](int j) { return hs[j]; }, ws->lut, lo, hi, e_max);
     if (tid == 0) {
         const double S = ws->skip ? 0.0 : ws->s_last;
         double low = guard_lower(g, S, n, ws->signs);

@@ -174,9 +174,9 @@ def test_unsupported_combinations_are_rejected(h):
     rp, col, val = workloads.poisson2d_csr(8)
     A = q.Csr(rp, col, val)
     b = dev(workloads.normal_vector(64, 85))
-    with pytest.raises(q.QdotError):
+    with pytest.raises(q.QdotError):  # the one-pass mode is not a CG mode
         h.cg(A, b, torch.zeros(64, dtype=torch.float64, device="cuda:0"), 1e-10, 1e-8, 100, 1,
-             opt=GUARD)
+             opt=[0, 0, 0, 1])
 
 
 @pytest.mark.parametrize("data", ["reselect", "certified"])
@@ -226,6 +226,75 @@ def test_power_method(h):
     o = oracle.power(rp, col, val, x0, 100, 1e-6, 1, opt=GUARD)
     assert r["status"] == q.OK and o["status"] == oracle.OK
     np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
+
+
+CG_KEYS = ("count", "n_zero", "e_min", "e_max", "n_bins", "t", "flags", "status", "e_ref",
+           "passes")
+
+
+def check_cg_trace(rt, ot, scale, upto):
+    for i in range(upto):
+        for k in CG_KEYS:
+            assert rt[i][k] == ot[i][k], (i, k, rt[i][k], ot[i][k])
+        assert abs(rt[i]["value"] - ot[i]["value"]) <= 1e-13 * scale[i], i
+        assert abs(rt[i]["lower"] - ot[i]["lower"]) <= 1e-13 * scale[i] + 1e-12 * abs(ot[i]["lower"])
+
+
+@pytest.mark.parametrize("m", [32, 128])
+def test_cg_guaranteed_mode(h, m):
+    # Poisson with a normal right-hand side: the oracle's CG with the same
+    # mode takes the same decisions on the first inner products (r0 = b
+    # exactly; later ones see vectors that differ by rounding), and the
+    # iteration count matches the FP64-dot CG
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    b = workloads.normal_vector(m * m, 86)
+    print(f"[gpu-case] cg guaranteed m={m}", flush=True)
+    x = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    r = h.cg(A, dev(b), x, 1e-10, 1e-8, 20000, 1, opt=GUARD, trace=True)
+    o = oracle.cg(rp, col, val, b, 1e-10, 1e-8, 20000, 1, opt=GUARD, want_trace=True)
+    xf = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    rf = h.cg(A, dev(b), xf, 1e-10, 1e-8, 20000, 0)
+    assert r["status"] == q.OK and o["status"] == oracle.OK
+    assert abs(r["iters"] - o["iters"]) <= 1 and abs(r["iters"] - rf["iters"]) <= 1
+    assert r["relres_true"] < 1e-9
+    check_cg_trace(r["trace"], o["trace"], [float(np.dot(b, b))], 1)
+    assert r["trace"][0]["flags"] & q.F_GUARANTEED  # r.r: one sign
+    assert all(t["flags"] & q.F_GUARANTEED for t in r["trace"][0::2])
+
+
+def cancelling_diagonal(n, seed, rel):
+    """Diagonal A = diag(+1, ..., -1, ...) and b with b.Ab = rel * b.b: the
+    first p.Ap cancels to rel of its terms' sum."""
+    g = workloads.rng(seed)
+    b = g.standard_normal(n)
+    half = n // 2
+    s1, s2 = np.dot(b[:half], b[:half]), np.dot(b[half:], b[half:])
+    b[half:] *= np.sqrt(s1 * (1 - rel) / (s2 * (1 + rel)))
+    a = np.ones(n)
+    a[half:] = -1.0
+    rp = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    return rp, col, a, b
+
+
+@pytest.mark.parametrize("n,rel", [(4096, 1e-6), (65536, 1e-7), (300000, 1e-8)])
+def test_cg_guaranteed_mode_reselects(h, n, rel):
+    # p0.Ap0 cancels: its first selection cannot be certified, the gang
+    # reselects against E_lo and sums again; decisions and values as the
+    # oracle's on the first two inner products
+    rp, col, val, b = cancelling_diagonal(n, 87, rel)
+    A = q.Csr(rp, col, val)
+    print(f"[gpu-case] cg guaranteed reselect n={n} rel={rel}", flush=True)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    r = h.cg(A, dev(b), x, 1e-10, 1e-8, 1, 1, opt=GUARD, trace=True)
+    o = oracle.cg(rp, col, val, b, 1e-10, 1e-8, 1, 1, opt=GUARD, want_trace=True)
+    assert r["status"] == o["status"] and r["iters"] == o["iters"] == 1
+    absq = float(np.sum(np.abs(val) * b * b))
+    check_cg_trace(r["trace"], o["trace"], [float(np.dot(b, b)), absq], 2)
+    pq = r["trace"][1]
+    assert pq["flags"] & q.F_RESELECTED and pq["passes"] == 2, pq["flags"]
+    assert pq["e_ref"] < pq["e_max"]
 
 
 @pytest.mark.parametrize("rel", [1e-5, 1e-7])
