@@ -412,8 +412,9 @@ QDOT_API int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double
  * iterations.  trace: NULL or device qdot_result[2*maxit + 1] receiving
  * every qdot result in call order.  Synchronous; out (host) receives the
  * iteration count, status and residuals.  Returns out->status.
- * The whole solve is one persistent launch of up to one block per CU
- * (environment variable QDOT_CG_BLOCKS caps the block count).  A gang
+ * The whole solve is one persistent launch of up to two blocks per CU
+ * (as many as can be resident together; at most 512, at least 1024 rows
+ * per block; environment variable QDOT_CG_BLOCKS caps the count).  A gang
  * barrier that does not complete within its spin limit ends the solve with
  * QDOT_E_DEVICE.  accum_mode must be 0 (QDOT_E_INVAL).  guard_mode 1 runs
  * the guaranteed mode on every qdot of the solve (same decisions, flags,

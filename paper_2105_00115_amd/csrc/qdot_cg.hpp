@@ -17,8 +17,9 @@
 //
 // Every wait is bounded: a barrier that does not complete within the spin
 // limit raises the gang's abort flag, every block leaves, and the call
-// reports QDOT_E_DEVICE.  The grid never exceeds one block per CU per gang
-// slot, so all blocks of a gang are resident together.
+// reports QDOT_E_DEVICE.  The launches size their grids so that all blocks
+// of a gang are resident together (the single-system launch: up to two
+// blocks per CU when the kernel's occupancy allows it).
 #pragma once
 #include <cmath>
 
@@ -41,10 +42,14 @@ struct CgSys {
     qdot_result *trace;  // nullable: 2 * maxit + 1 results
 };
 
-constexpr int MAX_GANG = 256;
+constexpr int MAX_GANG = 512;
+// block gb of a gang merges its histogram into copy gb % GANG_HIST_COPIES:
+// the merge atomics of one slot then queue 8 ways instead of G deep, and
+// every block waits for its own atomics before it arrives at the barrier
+constexpr int GANG_HIST_COPIES = 8;
 
 struct GangQ {  // per gang and qdot buffer
-    unsigned int hist[W];
+    unsigned int hist[GANG_HIST_COPIES][W];
     // per block: live slot range, zero count, and non-finite flag (bit 0)
     // with the signs of the nonzero products (bit 1 negative, bit 2
     // positive); written by every block for every inner product, so never
@@ -201,7 +206,8 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
     for (int j = threadIdx.x; j < W; j += BLOCK) {
         const unsigned int v = L.h[j];
         if (v) {
-            __hip_atomic_fetch_add(&Q.hist[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&Q.hist[gb % GANG_HIST_COPIES][j], v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             L.h[j] = 0u;
             lo = min(lo, j);
             hi = max(hi, j);
@@ -239,7 +245,12 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
     const unsigned long long gnz = gz;
     const unsigned int gbad = gbs & 1u;
     const unsigned int gsg = gbs >> 1;
-    for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) L.h[j] = ld_dev(&Q.hist[j]);
+    const int ncopy = min(G, GANG_HIST_COPIES);
+    for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) {
+        unsigned int v = 0u;
+        for (int c = 0; c < ncopy; c++) v += ld_dev(&Q.hist[c][j]);
+        L.h[j] = v;
+    }
     __syncthreads();
     // cutoff, redundantly in every block, into the block's own class table
     auto get = [&](int j) { return (unsigned long long)L.h[j]; };
@@ -292,7 +303,8 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
     // block 0 clears the gang buffer for the qdot after next; every block
     // has finished reading it (its copy was taken before the barrier above)
     if (gb == 0) {
-        for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) st_dev(&Q.hist[j], 0u);
+        for (int c = 0; c < ncopy; c++)
+            for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) st_dev(&Q.hist[c][j], 0u);
     }
     if constexpr (GUARD) {
         __shared__ int s_go, s_dref, s_passes;
@@ -624,8 +636,10 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
 __device__ __forceinline__ void gang_reset(Gang *gg)
 {
     for (int i = threadIdx.x; i < W; i += blockDim.x) {
-        gg->qb[0].hist[i] = 0u;
-        gg->qb[1].hist[i] = 0u;
+        for (int c = 0; c < GANG_HIST_COPIES; c++) {
+            gg->qb[0].hist[c][i] = 0u;
+            gg->qb[1].hist[c][i] = 0u;
+        }
     }
     if (threadIdx.x < BAR_GROUPS) gg->bar_sub[threadIdx.x][0] = 0u;
     if (threadIdx.x == 0) {
