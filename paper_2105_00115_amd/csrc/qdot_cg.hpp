@@ -12,8 +12,11 @@
 // cutoff and the final combine of each qdot itself, from the same merged
 // histogram and the same partials in the same order, so every block holds
 // bit-identical scalars (alpha, beta, c) and takes the same branches: the
-// gang never needs to broadcast a decision.  Two histogram buffers rotate so
-// that block 0 can clear the one just used without an extra barrier.
+// gang never needs to broadcast a decision.  The whole-gang reductions (the
+// blocks' pass-1 records and histogram copies at the first barrier of a
+// qdot, its partials at the second) are done once, by the last block to
+// arrive, before it releases the others; that block also clears the
+// histogram copies.  Two buffers alternate between consecutive qdots.
 //
 // Every wait is bounded: a barrier that does not complete within the spin
 // limit raises the gang's abort flag, every block leaves, and the call
@@ -55,6 +58,11 @@ struct GangQ {  // per gang and qdot buffer
     // positive); written by every block for every inner product, so never
     // cleared
     int4 rec[MAX_GANG];
+    // published by the last block to arrive at the merge barrier: the
+    // reduced records (lo, hi, zeros, flags) and the summed copies over
+    // [lo, hi] (the copies are cleared by the same block)
+    int4 sum;
+    unsigned int hm[W];
 };
 
 constexpr int BAR_GROUPS = 8;    // first level of the barrier of a large gang
@@ -67,6 +75,8 @@ struct Gang {
     unsigned int pad;
     GangQ qb[2];
     double partials[2][MAX_GANG * 6];
+    // partials[k] combined in block order by the last block to arrive
+    double pfin[2][6];
     unsigned int bar_sub[BAR_GROUPS][32];  // group counters, one 128-byte line each
 };
 
@@ -80,13 +90,20 @@ struct Gang {
 // BAR_TWO_LEVEL blocks arrives in two levels: each block on the counter of
 // its group (gb mod BAR_GROUPS), the last of a group on the gang counter, so
 // no counter takes more than G / BAR_GROUPS serialised atomics.
-__device__ bool gang_barrier(Gang *gg, int G, int gb)
+//
+// gang_barrier_then: the last block to arrive runs work() with all its
+// threads before it releases the others.  Reductions over the whole gang
+// (the blocks' records, histogram copies, partials) are done there once,
+// and every other block reads only the result: when every block reads all
+// G contributions the same words are fetched G times at once.
+template <class Work>
+__device__ bool gang_barrier_then(Gang *gg, int G, int gb, Work &&work)
 {
-    __shared__ int s_ok;
+    __shared__ int s_ok, s_last;
+    __shared__ unsigned int s_gen;
     vmem_drain();
     __syncthreads();
     if (threadIdx.x == 0) {
-        int ok = 1;
         const unsigned int gen = ld_dev(&gg->bar_gen);
         bool last;
         if (G > BAR_TWO_LEVEL) {
@@ -108,25 +125,38 @@ __device__ bool gang_barrier(Gang *gg, int G, int gb)
             last = __hip_atomic_fetch_add(&gg->bar_count, 1u, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT) + 1 == (unsigned)G;
         }
-        if (last) {
+        s_ok = 1;
+        s_last = last ? 1 : 0;
+        s_gen = gen;
+    }
+    __syncthreads();
+    if (s_last) {
+        work();
+        vmem_drain();
+        __syncthreads();
+        if (threadIdx.x == 0) {
             st_dev(&gg->bar_count, 0u);
             vmem_drain();
-            st_dev(&gg->bar_gen, gen + 1);
-        } else {
-            unsigned int spins = 0;
-            while (ld_dev(&gg->bar_gen) == gen) {
-                if (ld_dev(&gg->abort) || ++spins > SPIN_LIMIT) {
-                    __hip_atomic_fetch_or(&gg->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
+            st_dev(&gg->bar_gen, s_gen + 1);
         }
-        s_ok = ok;
+    } else if (threadIdx.x == 0) {
+        unsigned int spins = 0;
+        while (ld_dev(&gg->bar_gen) == s_gen) {
+            if (ld_dev(&gg->abort) || ++spins > SPIN_LIMIT) {
+                __hip_atomic_fetch_or(&gg->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
     }
     __syncthreads();
     return s_ok != 0;
+}
+
+__device__ __forceinline__ bool gang_barrier(Gang *gg, int G, int gb)
+{
+    return gang_barrier_then(gg, G, gb, [] {});
 }
 
 struct DotOut {
@@ -226,31 +256,49 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
         st_dev(rec + 2, (int)nz);
         st_dev(rec + 3, (int)bs);
     }
-    if (!gang_barrier(gg, G, gb)) {
+    // the last block to arrive reduces the gang's records (counts of one
+    // system fit 32 bits), sums the histogram copies over the live window
+    // into hm and clears the copies for the qdot after next
+    auto merge = [&]() {
+        int lo2 = W, hi2 = -1;
+        unsigned int z2 = 0, bs2 = 0;
+        for (int c = threadIdx.x; c < G; c += BLOCK) {
+            const int *rec = &Q.rec[c].x;
+            lo2 = min(lo2, ld_dev(rec));
+            hi2 = max(hi2, ld_dev(rec + 1));
+            z2 += (unsigned int)ld_dev(rec + 2);
+            bs2 |= (unsigned int)ld_dev(rec + 3);
+        }
+        block_reduce_range(lo2, hi2, z2, bs2, L.scratch);
+        const int ncopy = min(G, GANG_HIST_COPIES);
+        for (int j = lo2 + (int)threadIdx.x; j <= hi2; j += BLOCK) {
+            unsigned int v = 0u;
+            for (int c = 0; c < ncopy; c++) {
+                v += ld_dev(&Q.hist[c][j]);
+                st_dev(&Q.hist[c][j], 0u);
+            }
+            st_dev(&Q.hm[j], v);
+        }
+        if (threadIdx.x == 0) {
+            int *sm = &Q.sum.x;
+            st_dev(sm, lo2);
+            st_dev(sm + 1, hi2);
+            st_dev(sm + 2, (int)z2);
+            st_dev(sm + 3, (int)bs2);
+        }
+    };
+    if (!gang_barrier_then(gg, G, gb, merge)) {
         o.ok = false;
         return o;
     }
-    // the gang's records, reduced in every block (counts of one system fit
-    // 32 bits), then the merged histogram window into this block's LDS copy
-    int glo = W, ghi = -1;
-    unsigned int gz = 0, gbs = 0;
-    for (int c = threadIdx.x; c < G; c += BLOCK) {
-        const int *rec = &Q.rec[c].x;
-        glo = min(glo, ld_dev(rec));
-        ghi = max(ghi, ld_dev(rec + 1));
-        gz += (unsigned int)ld_dev(rec + 2);
-        gbs |= (unsigned int)ld_dev(rec + 3);
-    }
-    block_reduce_range(glo, ghi, gz, gbs, L.scratch);
-    const unsigned long long gnz = gz;
+    // the merged window into this block's LDS copy
+    const int glo = ld_dev(&Q.sum.x);
+    const int ghi = ld_dev(&Q.sum.y);
+    const unsigned long long gnz = (unsigned int)ld_dev(&Q.sum.z);
+    const unsigned int gbs = (unsigned int)ld_dev(&Q.sum.w);
     const unsigned int gbad = gbs & 1u;
     const unsigned int gsg = gbs >> 1;
-    const int ncopy = min(G, GANG_HIST_COPIES);
-    for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) {
-        unsigned int v = 0u;
-        for (int c = 0; c < ncopy; c++) v += ld_dev(&Q.hist[c][j]);
-        L.h[j] = v;
-    }
+    for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) L.h[j] = ld_dev(&Q.hm[j]);
     __syncthreads();
     // cutoff, redundantly in every block, into the block's own class table
     auto get = [&](int j) { return (unsigned long long)L.h[j]; };
@@ -277,16 +325,29 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
                 st_dev(&pp[2 * q + 1], acc[q].c);
             }
         }
-        if (!gang_barrier(gg, G, gb)) return false;
-        // the gang's partials in block order, in every block
-        Acc f[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-        for (int c = threadIdx.x; c < G; c += BLOCK) {
-            const double *pp = gg->partials[kp] + c * 6;
+        // the last block to arrive combines the gang's partials in block
+        // order; every block then finishes from the same six words
+        auto combine = [&]() {
+            Acc f[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+            for (int c = threadIdx.x; c < G; c += BLOCK) {
+                const double *pp = gg->partials[kp] + c * 6;
+                for (int q = 0; q < 3; q++)
+                    f[q] = acc_merge(f[q], Acc{ld_dev(&pp[2 * q]), ld_dev(&pp[2 * q + 1])});
+            }
+            block_reduce3<BLOCK>(f, L.red);
+            if (threadIdx.x == 0)
+                for (int q = 0; q < 3; q++) {
+                    st_dev(&gg->pfin[kp][2 * q], f[q].s);
+                    st_dev(&gg->pfin[kp][2 * q + 1], f[q].c);
+                }
+        };
+        if (!gang_barrier_then(gg, G, gb, combine)) return false;
+        if (threadIdx.x == 0) {
+            Acc f[3];
             for (int q = 0; q < 3; q++)
-                f[q] = acc_merge(f[q], Acc{ld_dev(&pp[2 * q]), ld_dev(&pp[2 * q + 1])});
+                f[q] = Acc{ld_dev(&gg->pfin[kp][2 * q]), ld_dev(&gg->pfin[kp][2 * q + 1])};
+            L.sval = combine_value(f, cp.e_max, cp.c32, flags, &L.res);
         }
-        block_reduce3<BLOCK>(f, L.red);
-        if (threadIdx.x == 0) L.sval = combine_value(f, cp.e_max, cp.c32, flags, &L.res);
         return true;
     };
     if (threadIdx.x == 0) L.sval = 0.0;
@@ -300,12 +361,6 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
         return o;
     }
     __syncthreads();
-    // block 0 clears the gang buffer for the qdot after next; every block
-    // has finished reading it (its copy was taken before the barrier above)
-    if (gb == 0) {
-        for (int c = 0; c < ncopy; c++)
-            for (int j = glo + (int)threadIdx.x; j <= ghi; j += BLOCK) st_dev(&Q.hist[c][j], 0u);
-    }
     if constexpr (GUARD) {
         __shared__ int s_go, s_dref, s_passes;
         __shared__ double s_low;

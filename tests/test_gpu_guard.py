@@ -240,7 +240,7 @@ def check_cg_trace(rt, ot, scale, upto):
         assert abs(rt[i]["lower"] - ot[i]["lower"]) <= 1e-13 * scale[i] + 1e-12 * abs(ot[i]["lower"])
 
 
-@pytest.mark.parametrize("m", [32, 128])
+@pytest.mark.parametrize("m", [8, 32, 128])
 def test_cg_guaranteed_mode(h, m):
     # Poisson with a normal right-hand side: the oracle's CG with the same
     # mode takes the same decisions on the first inner products (r0 = b
@@ -261,6 +261,19 @@ def test_cg_guaranteed_mode(h, m):
     check_cg_trace(r["trace"], o["trace"], [float(np.dot(b, b))], 1)
     assert r["trace"][0]["flags"] & q.F_GUARANTEED  # r.r: one sign
     assert all(t["flags"] & q.F_GUARANTEED for t in r["trace"][0::2])
+
+
+def test_cg_guaranteed_mode_zero_rhs(h):
+    # b = 0: r0.r0 has no nonzero product; +0 is exact (certified) and the
+    # solve stops before its first iteration, as in the oracle
+    rp, col, val = workloads.poisson2d_csr(8)
+    A = q.Csr(rp, col, val)
+    x = torch.zeros(64, dtype=torch.float64, device="cuda:0")
+    r = h.cg(A, dev(np.zeros(64)), x, 1e-10, 1e-8, 100, 1, opt=GUARD, trace=True)
+    o = oracle.cg(rp, col, val, np.zeros(64), 1e-10, 1e-8, 100, 1, opt=GUARD, want_trace=True)
+    assert r["status"] == o["status"] == q.OK and r["iters"] == o["iters"] == 0
+    check_cg_trace(r["trace"], o["trace"], [1.0], 1)
+    assert r["trace"][0]["flags"] == q.F_GUARANTEED | q.F_ALL_PERF
 
 
 def cancelling_diagonal(n, seed, rel):
