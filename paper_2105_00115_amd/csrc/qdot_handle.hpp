@@ -19,8 +19,9 @@ struct qdot_handle {
     qdot_tune tune[QDOT_TUNE_BUCKETS];
     std::string err;
 
-    // solver scratch, grown on demand: the power method keeps w = A x
-    // (n doubles), the single-system CG keeps r, p, q (3 n doubles)
+    // solver scratch, grown on demand: the power method keeps w = A x of
+    // the current and the previous iteration (2 n doubles), the
+    // single-system CG keeps r, p, q (3 n doubles)
     double *vec = nullptr;
     int64_t vec_n = 0;               // doubles held at vec
     void *ctl = nullptr;             // solver control block

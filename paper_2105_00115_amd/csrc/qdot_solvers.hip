@@ -44,15 +44,14 @@ constexpr int SP_U = 8;
 constexpr int SP_NZ = SP_U * BLOCK;
 constexpr int SPMV_BLOCKS_PER_CU = 8;
 
-__global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rowptr,
-                                                const int32_t *__restrict__ col,
-                                                const double *__restrict__ val,
-                                                const double *__restrict__ v,
-                                                double *__restrict__ y,
-                                                const SolverCtl *__restrict__ ctl)
+// The SpMV loop over a block's row groups.  gather(c) gives the vector entry
+// of column c; own(i, yi) is called once per row with its result.
+template <class Gather, class Own>
+__device__ __forceinline__ void spmv_lds(int64_t n, const int32_t *__restrict__ rowptr,
+                                         const int32_t *__restrict__ col,
+                                         const double *__restrict__ val, Gather &&gather,
+                                         Own &&own, double *prod)
 {
-    __shared__ double prod[SP_NZ];
-    if (ctl && ctl->done) return;
     for (int64_t r0 = (int64_t)blockIdx.x * BLOCK; r0 < n; r0 += (int64_t)gridDim.x * BLOCK) {
         const int64_t r1 = min(n, r0 + (int64_t)BLOCK);
         const int64_t i = r0 + threadIdx.x;
@@ -81,7 +80,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t *__rest
             }
 #pragma unroll
             for (int u = 0; u < SP_U; u++)
-                if (c0 + u * BLOCK + threadIdx.x < c1) pv[u] = pv[u] * v[ci[u]];
+                if (c0 + u * BLOCK + threadIdx.x < c1) pv[u] = pv[u] * gather(ci[u]);
 #pragma unroll
             for (int u = 0; u < SP_U; u++) prod[u * BLOCK + threadIdx.x] = pv[u];
             __syncthreads();
@@ -90,8 +89,78 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t *__rest
                 for (int64_t j = lo; j < hi; j++) s = s + prod[j - c0];
             }
         }
-        if (row) y[i] = s;
+        if (row) own(i, s);
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col,
+                                                const double *__restrict__ val,
+                                                const double *__restrict__ v,
+                                                double *__restrict__ y)
+{
+    __shared__ double prod[SP_NZ];
+    spmv_lds(
+        n, rowptr, col, val, [&](int32_t c) { return v[c]; },
+        [&](int64_t i, double yi) { y[i] = yi; }, prod);
+}
+
+// dot-product result flags: a qdot that perforated every component of a
+// nonzero vector breaks the solver down
+__device__ __forceinline__ bool all_perforated(const qdot_result *r)
+{
+    return r && (r->flags & QDOT_F_ALL_PERF) && r->n_bins > 0;
+}
+
+// Power method, iteration k: it first finishes iteration k - 1 (k > 0),
+// whose results lamval / cval are in device memory: breakdown, or lambda
+// recorded and x = w_{k-1} / sqrt(c).  It does not wait for that division
+// to be stored: the SpMV w_k = A x gathers w_{k-1}[c] / sqrt(c) itself, the
+// same rounded quotient, and each row writes its own x entry.  At k = 0 the
+// source is x itself, read as it is.  Every block takes the same decision
+// from the same results; block 0 alone writes the control block (the others
+// read only its `done` word at their start, and a breakdown makes them
+// return whichever value they see).
+__global__ __launch_bounds__(BLOCK) void k_pm_spmv(
+    int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ src, double *__restrict__ w,
+    double *__restrict__ x, SolverCtl *ctl, const double *lamval, const qdot_result *lamres,
+    const double *cval, const qdot_result *cres, double *__restrict__ trace, int k)
+{
+    __shared__ double prod[SP_NZ];
+    if (ctl->done) return;
+    double sc = 1.0;
+    if (k > 0) {
+        const double c = *cval;
+        const bool first_block = blockIdx.x == 0 && threadIdx.x == 0;
+        if (!(c > 0.0) || !isfinite(c) || all_perforated(cres) || all_perforated(lamres)) {
+            if (first_block) {
+                ctl->broke = 1;
+                ctl->status = QDOT_E_BREAKDOWN;
+                ctl->done = 1;
+            }
+            return;
+        }
+        if (first_block) {
+            const double lam = *lamval;
+            if (trace) trace[k - 1] = lam;
+            ctl->c = lam;
+            ctl->iters += 1;
+        }
+        sc = sqrt(c);
+    }
+    if (k == 0)
+        spmv_lds(
+            n, rowptr, col, val, [&](int32_t c) { return src[c]; },
+            [&](int64_t i, double yi) { w[i] = yi; }, prod);
+    else
+        spmv_lds(
+            n, rowptr, col, val, [&](int32_t c) { return src[c] / sc; },
+            [&](int64_t i, double yi) {
+                w[i] = yi;
+                x[i] = src[i] / sc;
+            },
+            prod);
 }
 
 static int spmv_grid(const qdot_handle *h, int64_t n)
@@ -102,18 +171,9 @@ static int spmv_grid(const qdot_handle *h, int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + BLOCK - 1) / BLOCK));
 }
 
-// dot-product result flags: a qdot that perforated every component of a
-// nonzero vector breaks the solver down
-__device__ __forceinline__ bool all_perforated(const qdot_result *r)
-{
-    return r && (r->flags & QDOT_F_ALL_PERF) && r->n_bins > 0;
-}
-
-// Power method, end of an iteration: x = w / sqrt(c) and lambda recorded,
-// or the breakdown recorded.  Every block takes the same decision from the
-// same two results; block 0 alone writes the control block (the other
-// blocks read only its `done` word, at their start, and a breakdown makes
-// them return whichever value they see).
+// Power method, end of the last iteration k: x = w / sqrt(c) and lambda
+// recorded, or the breakdown recorded (the step k_pm_spmv does for the
+// iteration before its own), with the same decision in every block.
 __global__ __launch_bounds__(VB) void k_pm_update(int64_t n, SolverCtl *ctl,
                                                   const double *lamval,
                                                   const qdot_result *lamres,
@@ -237,7 +297,7 @@ int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double *x, doub
     if (A->n == 0) return QDOT_OK;
     DeviceGuard g(h->device);
     hipLaunchKernelGGL(k_spmv, dim3(spmv_grid(h, A->n)), dim3(BLOCK), 0, (hipStream_t)stream,
-                       A->n, A->rowptr, A->col, A->val, x, y, (const SolverCtl *)nullptr);
+                       A->n, A->rowptr, A->col, A->val, x, y);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "spmv launch");
 }
@@ -258,11 +318,11 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
         return fail(h, QDOT_E_INVAL, "accum_mode 1 not admissible for this n and qtol");
     DeviceGuard g(h->device);
     const int64_t n = A->n;
-    int32_t st = ensure_solver_vectors(h, n);
+    int32_t st = ensure_solver_vectors(h, 2 * n);  // w of the iteration and the previous one
     if (st != QDOT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const Launch L = make_launch(h, s, n);
-    double *w = h->vec;
+    double *wbuf[2] = {h->vec, h->vec + n};
     SolverCtl *ctl = (SolverCtl *)h->ctl;
     hipError_t e = hipSuccess;
     auto ok = [&](hipError_t x_) {
@@ -282,11 +342,15 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     ok(hipGetLastError());
     SolverCtl hc;
     std::memset(&hc, 0, sizeof hc);
-    for (int32_t k = 0; k < iters && e == hipSuccess; k++) {
-        const double *lv, *cv;
-        const qdot_result *lr, *cr;
-        hipLaunchKernelGGL(k_spmv, dim3(sg), dim3(BLOCK), 0, s, n, A->rowptr, A->col, A->val, x,
-                           w, (const SolverCtl *)ctl);
+    // results of the last enqueued iteration (read by the next one's SpMV)
+    const double *lv = nullptr, *cv = nullptr;
+    const qdot_result *lr = nullptr, *cr = nullptr;
+    int32_t k = 0;
+    for (; k < iters && e == hipSuccess; k++) {
+        double *w = wbuf[k & 1];
+        const double *src = k == 0 ? x : wbuf[(k - 1) & 1];
+        hipLaunchKernelGGL(k_pm_spmv, dim3(sg), dim3(BLOCK), 0, s, n, A->rowptr, A->col, A->val,
+                           src, w, x, ctl, lv, lr, cv, cr, lambda_trace, k);
         if (paired) {
             ok(launch_qdot_pair(L, L2, x, w, n, qtol, o, h->res_ring, h->res_ring + 1));
             lv = &h->res_ring[0].value;
@@ -298,13 +362,18 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
             ok(enqueue_dot(h, L, w, w, n, use_qdot, qtol, o, h->res_ring + 1, h->dres + 1, &cv,
                            &cr));
         }
-        hipLaunchKernelGGL(k_pm_update, dim3(gv), dim3(VB), 0, s, n, ctl, lv, lr, cv, cr, x, w,
-                           lambda_trace, k);
         ok(hipGetLastError());
         if ((k + 1) % 64 == 0) {
             if ((st = read_ctl(h, s, hc)) != QDOT_OK) return st;
             if (hc.done) break;
         }
+    }
+    // the last enqueued iteration's update (returns at once after a
+    // breakdown)
+    if (k > 0 && e == hipSuccess) {
+        hipLaunchKernelGGL(k_pm_update, dim3(gv), dim3(VB), 0, s, n, ctl, lv, lr, cv, cr, x,
+                           wbuf[(k - 1) & 1], lambda_trace, k - 1);
+        ok(hipGetLastError());
     }
     if (e != hipSuccess) return hip_fail(h, e, "power launch");
     if ((st = read_ctl(h, s, hc)) != QDOT_OK) return st;

@@ -155,7 +155,7 @@ def test_cg_maxit(h):
 
 @pytest.mark.parametrize("first", ["power", "cg"])
 def test_power_and_cg_share_one_handle(first):
-    # the power method keeps one scratch vector, CG three: whichever runs
+    # the power method keeps two scratch vectors, CG three: whichever runs
     # first, the other must grow the scratch and give the same results as on
     # a fresh handle
     m = 12
@@ -215,10 +215,14 @@ def test_power_method_grid_stride(h, spmv_blocks):
     x0 = workloads.unit_vector(m ** 3, 9)
     print(f"[gpu-case] power grid-stride m={m}", flush=True)
     for use_qdot in (1, 0):
-        r = h.power(A, dev(x0), 60, 1e-6, use_qdot)
+        xd = dev(x0)
+        r = h.power(A, xd, 60, 1e-6, use_qdot)
         o = oracle.power(rp, col, val, x0, 60, 1e-6, use_qdot)
         assert r["status"] == q.OK
         np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
+        # the last iterate: each iteration's SpMV gathers w / sqrt(c) itself
+        # and writes x, and the final update writes the last one
+        np.testing.assert_allclose(xd.cpu().numpy(), o["x"], rtol=0, atol=1e-9)
 
 
 @pytest.mark.parametrize("m,opt", [(16, None), (40, None), (128, None), (16, [0, 0, 0, 0, 1])])
