@@ -433,10 +433,11 @@ QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, dou
  * opt: as qdot_async (the one-pass and guaranteed modes included).  With
  * the two-pass qdot the two inner products of an iteration are computed
  * side by side: one pass-1 kernel reads x and w once for both, and the
- * cutoff, pass-2 and combine kernels each run once for the pair (values
- * as two separate qdot calls: classes and counts identical, sums within
- * rounding of the block order).  The first call with use_qdot != 0
- * allocates a second workspace on the handle.
+ * cutoff, pass-2 and combine kernels each run once for the pair, with the
+ * results of two separate qdot calls.  Each iteration's SpMV also applies
+ * the previous iteration's x = w / sqrt(c).  The handle keeps 2n doubles
+ * of scratch (grown on demand) and, from the first call with the two-pass
+ * qdot, a second workspace.
  * Synchronous.  QDOT_E_BREAKDOWN if c <= 0 or not finite. */
 QDOT_API int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x,
                    int32_t iters, double qtol, int32_t use_qdot,
