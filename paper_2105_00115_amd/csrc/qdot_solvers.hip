@@ -242,14 +242,16 @@ int32_t ensure_solver_vectors(qdot_handle *h, int64_t doubles)
 
 // A second qdot workspace: the power method's two inner products of an
 // iteration are selected and summed side by side.
-static int32_t ensure_second_ws(qdot_handle *h)
+// It is cleared on the stream of the call that first needs it, ahead of
+// that call's kernels.
+static int32_t ensure_second_ws(qdot_handle *h, hipStream_t s)
 {
     if (h->ws2) return QDOT_OK;
     if (hipMalloc((void **)&h->ws2, sizeof(Ws)) != hipSuccess) {
         h->ws2 = nullptr;
         return fail(h, QDOT_E_NOMEM, "second workspace allocation failed");
     }
-    if (hipMemset(h->ws2, 0, sizeof(Ws)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    if (hipMemsetAsync(h->ws2, 0, sizeof(Ws), s) != hipSuccess) {
         (void)hipFree(h->ws2);
         h->ws2 = nullptr;
         return fail(h, QDOT_E_DEVICE, "second workspace clear failed");
@@ -334,7 +336,7 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     // their launches (launch_qdot_pair); the one-pass mode and the FP64 dot
     // take them one after the other
     const bool paired = use_qdot && o.accum_mode == 0;
-    if (paired && (st = ensure_second_ws(h)) != QDOT_OK) return st;
+    if (paired && (st = ensure_second_ws(h, s)) != QDOT_OK) return st;
     Launch L2 = L;
     L2.ws = h->ws2;
     const int sg = spmv_grid(h, n);

@@ -156,6 +156,28 @@ def test_edge_cases(h):
     compare(h, np.array([3.0]), np.array([-0.5]), 1e-6)
 
 
+def test_empty_inputs(h):
+    # n = 0: +0 with no bins, in every mode and entry point, as the oracle
+    e = torch.zeros(0, dtype=torch.float64, device="cuda:0")
+    z = np.zeros(0)
+    keys = ("count", "n_zero", "e_min", "e_max", "n_bins", "t", "flags", "status", "passes",
+            "e_ref")
+    for opt in (None, [0, 0, 0, 1], [0, 0, 0, 0, 1]):
+        r = h.qdot(e, e, 1e-6, opt=opt)
+        o = oracle.qdot(z, z, 1e-6, opt=opt)
+        for k in keys:
+            assert r[k] == o[k], (opt, k, r[k], o[k])
+        assert r["value"] == 0.0 and not np.signbit(r["value"])
+    cls, hist, r = h.qdot_classes(e, e, 1e-6)
+    assert cls.numel() == 0 and int(hist.abs().sum()) == 0 and r["n_bins"] == 0
+    ef = torch.zeros(0, dtype=torch.float32, device="cuda:0")
+    rf = h.qdot_f32(ef, ef, 1e-6)
+    of = oracle.qdot_f32(np.zeros(0, dtype=np.float32), np.zeros(0, dtype=np.float32), 1e-6)
+    for k in keys:
+        assert rf[k] == of[k], k
+    assert h.fp64_dot(e, e) == 0.0
+
+
 def test_nonfinite_and_bad_arguments(h):
     x, y = workloads.log_uniform_pair(3000, 15)
     for bad in (np.nan, np.inf, -np.inf):

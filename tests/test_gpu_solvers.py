@@ -246,6 +246,15 @@ def test_power_pair_matches_separate_calls(h, m, opt):
                                rtol=4e-16, atol=0)
 
 
+def test_power_method_zero_iterations(h):
+    rp, col, val = workloads.laplacian3d_csr(6)
+    x0 = workloads.unit_vector(216, 15)
+    xd = dev(x0)
+    r = h.power(q.Csr(rp, col, val), xd, 0, 1e-6, 1)
+    assert r["status"] == q.OK and r["lambda"] == 0.0
+    np.testing.assert_array_equal(xd.cpu().numpy(), x0)
+
+
 def test_power_method_breakdown(h):
     # A = 0: w = 0, so c = w.w = 0 at the first iteration.  The later
     # iterations (up to the first control read, after 64) run on a broken
