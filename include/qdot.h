@@ -101,12 +101,12 @@ typedef struct qdot_options {
      *    block keeps per-bin candidate sums of all three precisions for the
      *    bins near its running maximum key and each kept bin takes its
      *    class's sum after the cutoff.  Accepted by qdot_async, qdot,
-     *    qdot_power and (for the qdot instances) the batched entry points
-     *    when n <= 2^30 and the tolerance keeps every possibly kept bin
-     *    within 255 exponents of e_max (ceil(log2 n) - t_min + 1 <= 255,
-     *    t_min the smallest t any histogram of n components can give: tol
-     *    >= about 1e-60 at n = 2^27); QDOT_E_INVAL otherwise and in
-     *    qdot_classes_async and qdot_cg. */
+     *    qdot_power, qdot_cg and (for the qdot instances) the batched entry
+     *    points when n <= 2^30 and the tolerance keeps every possibly kept
+     *    bin within 255 exponents of e_max (ceil(log2 n) - t_min + 1 <=
+     *    255, t_min the smallest t any histogram of n components can give:
+     *    tol >= about 1e-60 at n = 2^27); QDOT_E_INVAL otherwise and in
+     *    qdot_classes_async. */
     int32_t accum_mode;
     /* 0: the classes are selected once, against e_max (Alg. 2); the
      *    relative bound of Thm 3.3 then needs e_max <= flexp(x.y).
@@ -416,10 +416,14 @@ QDOT_API int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double
  * (as many as can be resident together; at most 512, at least 1024 rows
  * per block; environment variable QDOT_CG_BLOCKS caps the count).  A gang
  * barrier that does not complete within its spin limit ends the solve with
- * QDOT_E_DEVICE.  accum_mode must be 0 (QDOT_E_INVAL).  guard_mode 1 runs
- * the guaranteed mode on every qdot of the solve (same decisions, flags,
- * lower bound and passes as qdot_async; a reselected product costs one more
- * sweep of the gang's rows and one more gang barrier). */
+ * QDOT_E_DEVICE.  guard_mode 1 runs the guaranteed mode on every qdot of
+ * the solve (same decisions, flags, lower bound and passes as qdot_async; a
+ * reselected product costs one more sweep of the gang's rows and one more
+ * gang barrier).  accum_mode 1 runs every qdot in the one-pass reading
+ * (admissibility as for qdot_async, else QDOT_E_INVAL); each block reads its
+ * rows once, and the last block to arrive at the one barrier of an inner
+ * product selects and picks for the gang.  The first such call allocates
+ * the gang's one-pass tables (2 x 4196 x 6 doubles) on the handle. */
 QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x,
                 double rtol, double qtol, int32_t maxit, int32_t use_qdot,
                 const qdot_options *opt, void *stream, qdot_cg_result *out,

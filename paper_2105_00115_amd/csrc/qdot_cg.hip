@@ -9,13 +9,16 @@
 
 namespace qd {
 
-template <bool GUARD>
+// GUARD: guard_mode 1; ACC1: accum_mode 1 (tab: the gang's one-pass
+// tables, zero on entry and on exit).
+template <bool GUARD, bool ACC1>
 __global__ __launch_bounds__(BLOCK) void k_cg_gangs(const CgSys *__restrict__ sys,
                                                     const int *__restrict__ gang_sys,
                                                     const int *__restrict__ gang_sys_off,
                                                     Gang *__restrict__ gangs, int G,
                                                     qdot_cg_result *__restrict__ res,
-                                                    int key_mode, int score_mode, int nonstrict)
+                                                    int key_mode, int score_mode, int nonstrict,
+                                                    double *__restrict__ tab)
 {
     __shared__ CgLds L;
     for (int i = threadIdx.x; i < W + 1; i += BLOCK) L.h[i] = 0u;
@@ -23,10 +26,18 @@ __global__ __launch_bounds__(BLOCK) void k_cg_gangs(const CgSys *__restrict__ sy
     __syncthreads();
     const int g = blockIdx.x / G, gb = blockIdx.x % G;
     Gang *gg = gangs + g;
-    for (int s = gang_sys_off[g]; s < gang_sys_off[g + 1]; s++) {
-        cg_solve<GUARD>(sys[gang_sys[s]], gg, G, gb, key_mode, score_mode, nonstrict, L,
-                        res + gang_sys[s]);
-        if (__hip_atomic_load(&gg->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    auto run = [&](S1Lds *S1) {
+        for (int s = gang_sys_off[g]; s < gang_sys_off[g + 1]; s++) {
+            cg_solve<GUARD, ACC1>(sys[gang_sys[s]], gg, G, gb, key_mode, score_mode, nonstrict,
+                                  L, res + gang_sys[s], S1, tab);
+            if (__hip_atomic_load(&gg->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        }
+    };
+    if constexpr (ACC1) {
+        __shared__ S1Lds S1;
+        run(&S1);
+    } else {
+        run(nullptr);
     }
 }
 
@@ -47,7 +58,10 @@ struct CgDev {
     Gang *gangs = nullptr;
     qdot_cg_result *res = nullptr;
     int n_gangs = 0, n_sys = 0;
+    double *s1tab = nullptr;  // one-pass tables of the gang (2 W S1_PIECES), zero between calls
 };
+
+constexpr size_t CG_S1TAB = (size_t)2 * W * S1_PIECES;
 
 int32_t ensure_cg_buffers(qdot_handle *h, int n_sys, int n_gangs)
 {
@@ -89,6 +103,7 @@ void free_cg(qdot_handle *h)
     (void)hipFree(d->gsys);
     (void)hipFree(d->gangs);
     (void)hipFree(d->res);
+    (void)hipFree(d->s1tab);
     delete d;
     h->cg = nullptr;
 }
@@ -114,9 +129,11 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
-    if (o.accum_mode != 0) return fail(h, QDOT_E_INVAL, "the CG launch needs accum_mode 0");
     if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
+    const bool acc1 = use_qdot && o.accum_mode == 1;
+    if (acc1 && !s1_admissible(A->n, qtol, o))
+        return fail(h, QDOT_E_INVAL, "accum_mode 1 not admissible for this n and qtol");
     DeviceGuard g(h->device);
     const int64_t n = A->n;
     int32_t st = ensure_solver_vectors(h, 3 * n);  // r, p, q
@@ -130,11 +147,14 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     // took 87 us instead of 92 with qdot and 49 instead of 59 with the FP64
     // dot.
     int per_cu = 0;
-    hipError_t oe = o.guard_mode
-                        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_gangs<true>,
-                                                                       BLOCK, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_gangs<false>,
-                                                                       BLOCK, 0);
+    hipError_t oe =
+        acc1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_gangs<false, true>,
+                                                           BLOCK, 0)
+        : o.guard_mode
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_gangs<true, false>, BLOCK,
+                                                           0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_gangs<false, false>,
+                                                           BLOCK, 0);
     if (oe != hipSuccess) return hip_fail(h, oe, "occupancy query");
     if (per_cu < 1) return fail(h, QDOT_E_DEVICE, "the CG kernel cannot be resident");
     int cap = std::min(MAX_GANG, std::min(per_cu, 2) * h->num_cus);
@@ -158,23 +178,43 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     const int gl[3] = {0, 0, 1};  // gang_sys = {0}; gang_sys_off = {0, 1}
     hipError_t e = hipMemcpyAsync(d->sys, &S, sizeof S, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d->gsys, gl, sizeof gl, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && acc1 && !d->s1tab) {
+        e = hipMalloc((void **)&d->s1tab, sizeof(double) * CG_S1TAB);
+        if (e != hipSuccess) {
+            d->s1tab = nullptr;
+            return fail(h, QDOT_E_NOMEM, "CG one-pass tables");
+        }
+        e = hipMemsetAsync(d->s1tab, 0, sizeof(double) * CG_S1TAB, s);
+    }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_gang_init, dim3(1), dim3(BLOCK), 0, s, d->gangs, 1);
-        if (o.guard_mode)
-            hipLaunchKernelGGL(k_cg_gangs<true>, dim3(G), dim3(BLOCK), 0, s, d->sys, d->gsys,
-                               d->gsys + 1, d->gangs, G, d->res, o.key_mode, o.score_mode,
-                               o.boundary_mode);
+        if (acc1)
+            hipLaunchKernelGGL((k_cg_gangs<false, true>), dim3(G), dim3(BLOCK), 0, s, d->sys,
+                               d->gsys, d->gsys + 1, d->gangs, G, d->res, o.key_mode,
+                               o.score_mode, o.boundary_mode, d->s1tab);
+        else if (o.guard_mode)
+            hipLaunchKernelGGL((k_cg_gangs<true, false>), dim3(G), dim3(BLOCK), 0, s, d->sys,
+                               d->gsys, d->gsys + 1, d->gangs, G, d->res, o.key_mode,
+                               o.score_mode, o.boundary_mode, (double *)nullptr);
         else
-            hipLaunchKernelGGL(k_cg_gangs<false>, dim3(G), dim3(BLOCK), 0, s, d->sys, d->gsys,
-                               d->gsys + 1, d->gangs, G, d->res, o.key_mode, o.score_mode,
-                               o.boundary_mode);
+            hipLaunchKernelGGL((k_cg_gangs<false, false>), dim3(G), dim3(BLOCK), 0, s, d->sys,
+                               d->gsys, d->gsys + 1, d->gangs, G, d->res, o.key_mode,
+                               o.score_mode, o.boundary_mode, (double *)nullptr);
         e = hipGetLastError();
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, d->res, sizeof(qdot_cg_result), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(h, e, "cg");
-    if (out->status == QDOT_E_DEVICE) return fail(h, QDOT_E_DEVICE, "cg gang barrier timed out");
+    if (out->status == QDOT_E_DEVICE) {
+        // an abandoned solve may leave one-pass table entries behind
+        if (d->s1tab && (hipMemsetAsync(d->s1tab, 0, sizeof(double) * CG_S1TAB, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess)) {
+            (void)hipFree(d->s1tab);
+            d->s1tab = nullptr;
+        }
+        return fail(h, QDOT_E_DEVICE, "cg gang barrier timed out");
+    }
     return out->status;
 }
 

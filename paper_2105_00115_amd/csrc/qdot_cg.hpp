@@ -77,6 +77,9 @@ struct Gang {
     double partials[2][MAX_GANG * 6];
     // partials[k] combined in block order by the last block to arrive
     double pfin[2][6];
+    // one-pass mode: the result of buffer k's qdot, published by the last
+    // block to arrive
+    qdot_result res[2];
     unsigned int bar_sub[BAR_GROUPS][32];  // group counters, one 128-byte line each
 };
 
@@ -430,6 +433,130 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
     return o;
 }
 
+// a.b over the gang's rows by the one-pass qdot (accum_mode 1, value as the
+// exact sum of the kept leaves), buffer k, value identical in every block.
+// Each block reads its rows once: keys into its LDS histogram and, for the
+// bins within `depth` of its running maximum, the candidate sums of every
+// precision into its LDS window (s1_stream), which it adds into the gang's
+// table `tab` (W x S1_PIECES sums, exact in any order, zero between calls).
+// The last block to arrive at the one barrier merges the records and the
+// histogram copies, selects, picks each kept bin's sum from the table,
+// clears the copies and the table over the live window and publishes the
+// result; the others read it.  No class table or second sweep is needed
+// outside that block, so an inner product costs one gang barrier.
+__device__ __forceinline__ DotOut gang_qdot_s1(const double *a, const double *bv, int64_t n,
+                                               int64_t r0, int64_t r1, double tol, int key_mode,
+                                               int score_mode, int nonstrict, Gang *gg, int G,
+                                               int gb, int k, CgLds &L, S1Lds &S1, double *tab,
+                                               qdot_result *trace_slot)
+{
+    DotOut o = {0.0, false, true};
+    GangQ &Q = gg->qb[k];
+    const bool vec = ((((uintptr_t)a) | ((uintptr_t)bv)) & 15) == 0;
+    // admitted by the host: depth <= S1_WIN
+    const int depth = s1_depth_dev(n, tol, score_mode);
+    unsigned int nz = 0, bad = 0;
+    int top = -1;
+    s1_begin(S1);
+    __syncthreads();
+    if (r1 > r0) {
+        if (vec)
+            s1_stream<true, 2>(a + r0, bv + r0, 0, 2 * CHUNK, r1 - r0, key_mode, depth, L.h, S1,
+                               top, nz, bad);
+        else
+            s1_stream<false, 2>(a + r0, bv + r0, 0, 2 * CHUNK, r1 - r0, key_mode, depth, L.h,
+                                S1, top, nz, bad);
+    }
+    __syncthreads();
+    int lo = W, hi = -1;
+    for (int j = threadIdx.x; j < W; j += BLOCK) {
+        const unsigned int v = L.h[j];
+        if (v) {
+            __hip_atomic_fetch_add(&Q.hist[gb % GANG_HIST_COPIES][j], v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            L.h[j] = 0u;
+            lo = min(lo, j);
+            hi = max(hi, j);
+        }
+    }
+    if (threadIdx.x == 0) L.h[W] = 0u;
+    if (top >= 0)
+        for (int i = threadIdx.x; i < depth * S1_PIECES; i += BLOCK) {
+            const int bin = top - i / S1_PIECES;
+            if (bin < 0) continue;
+            const double v = S1.win[bin & (S1_WIN - 1)][i % S1_PIECES];
+            if (v != 0.0)
+                __hip_atomic_fetch_add(&tab[(size_t)bin * S1_PIECES + i % S1_PIECES], v,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    unsigned int bs = bad ? 1u : 0u;
+    block_reduce_range(lo, hi, nz, bs, L.scratch);
+    if (threadIdx.x == 0) {
+        int *rec = &Q.rec[gb].x;
+        st_dev(rec, lo);
+        st_dev(rec + 1, hi);
+        st_dev(rec + 2, (int)nz);
+        st_dev(rec + 3, (int)bs);
+    }
+    auto finish = [&]() {
+        int lo2 = W, hi2 = -1;
+        unsigned int z2 = 0, bs2 = 0;
+        for (int c = threadIdx.x; c < G; c += BLOCK) {
+            const int *rec = &Q.rec[c].x;
+            lo2 = min(lo2, ld_dev(rec));
+            hi2 = max(hi2, ld_dev(rec + 1));
+            z2 += (unsigned int)ld_dev(rec + 2);
+            bs2 |= (unsigned int)ld_dev(rec + 3);
+        }
+        block_reduce_range(lo2, hi2, z2, bs2, L.scratch);
+        const int ncopy = min(G, GANG_HIST_COPIES);
+        for (int j = lo2 + (int)threadIdx.x; j <= hi2; j += BLOCK) {
+            unsigned int v = 0u;
+            for (int c = 0; c < ncopy; c++) {
+                v += ld_dev(&Q.hist[c][j]);
+                st_dev(&Q.hist[c][j], 0u);
+            }
+            L.h[j] = v;
+        }
+        __syncthreads();
+        auto get = [&](int j) { return (unsigned long long)L.h[j]; };
+        auto put = [&](int j, int c) { L.lut[j] = (unsigned char)c; };
+        auto noclear = [&](int) {};
+        const CutParams p = block_cutoff<BLOCK>(lo2, hi2, z2, bs2 & 1u, n, tol, score_mode,
+                                                nonstrict, get, put, noclear, &L.res, nullptr);
+        if (!p.skip)
+            s1_pick(p.e_max, max(lo2, p.e_max - KMIN - depth + 1), p.flags, L.lut,
+                    [&](int bin, int q) { return ld_dev(&tab[(size_t)bin * S1_PIECES + q]); },
+                    L.red, &L.res);
+        __syncthreads();
+        // the table and the LDS copy back to zero over the live window
+        if (hi2 >= lo2) {
+            for (int i = lo2 * S1_PIECES + (int)threadIdx.x; i < (hi2 + 1) * S1_PIECES;
+                 i += BLOCK)
+                st_dev(&tab[i], 0.0);
+            for (int j = lo2 + (int)threadIdx.x; j <= hi2; j += BLOCK) L.h[j] = 0u;
+        }
+        constexpr int NWORD = (int)(sizeof(qdot_result) / sizeof(unsigned long long));
+        if (threadIdx.x < NWORD)
+            st_dev(reinterpret_cast<unsigned long long *>(&gg->res[k]) + threadIdx.x,
+                   reinterpret_cast<const unsigned long long *>(&L.res)[threadIdx.x]);
+    };
+    if (!gang_barrier_then(gg, G, gb, finish)) {
+        o.ok = false;
+        return o;
+    }
+    constexpr int NWORD = (int)(sizeof(qdot_result) / sizeof(unsigned long long));
+    if (threadIdx.x < NWORD)
+        reinterpret_cast<unsigned long long *>(&L.res)[threadIdx.x] =
+            ld_dev(reinterpret_cast<const unsigned long long *>(&gg->res[k]) + threadIdx.x);
+    __syncthreads();
+    o.value = L.res.value;
+    o.all_perf = (L.res.flags & QDOT_F_ALL_PERF) && L.res.n_bins > 0;
+    if (threadIdx.x == 0 && trace_slot) *trace_slot = L.res;
+    __syncthreads();
+    return o;
+}
+
 // a.b over the gang's rows in plain FP64 (partials buffer k).
 __device__ __forceinline__ DotOut gang_dot64(const double *a, const double *bv, int64_t r0, int64_t r1, Gang *gg,
                              int G, int gb, int k, CgLds &L)
@@ -536,10 +663,14 @@ __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, doubl
 }
 
 // One CG solve by one gang.
-template <bool GUARD>
+// ACC1: every inner product by the one-pass qdot (gang_qdot_s1, with the
+// caller's LDS window S1 and the gang's table tab, 2 W S1_PIECES doubles);
+// otherwise by the two-pass qdot, guaranteed with GUARD.
+template <bool GUARD, bool ACC1 = false>
 __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb, int key_mode,
                                          int score_mode, int nonstrict, CgLds &L,
-                                         qdot_cg_result *res)
+                                         qdot_cg_result *res, S1Lds *S1 = nullptr,
+                                         double *tab = nullptr)
 {
     const int64_t n = S.n;
     // rows of this block: a multiple of CHUNK each, so qdot tiles line up
@@ -551,9 +682,13 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
                    unsigned int bad = 0, unsigned int sg = 0) {
         DotOut o;
         if (S.use_qdot) {
-            o = gang_qdot<GUARD>(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict, gg,
-                                 G, gb, k, L, (gb == 0 && S.trace) ? S.trace + ntr : nullptr,
-                                 scanned, nz, bad, sg);
+            qdot_result *ts = (gb == 0 && S.trace) ? S.trace + ntr : nullptr;
+            if constexpr (ACC1)
+                o = gang_qdot_s1(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict, gg,
+                                 G, gb, k, L, *S1, tab + (size_t)k * W * S1_PIECES, ts);
+            else
+                o = gang_qdot<GUARD>(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict,
+                                     gg, G, gb, k, L, ts, scanned, nz, bad, sg);
             ntr++;
         } else {
             o = gang_dot64(a, bv, r0, r1, gg, G, gb, k, L);
@@ -591,13 +726,16 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
             break;
         }
         if (!(healthy = gang_barrier(gg, G, gb))) break;  // p complete
+        // pass 1 of the two-pass qdot(p, q) rides in the SpMV; the one-pass
+        // qdot reads its rows itself
+        const bool scan_q = S.use_qdot != 0 && !ACC1;
         unsigned int nz1 = 0, bad1 = 0, sg1 = 0;
-        if (S.use_qdot)
+        if (scan_q)
             spmv_rows<true>(S, S.p, S.q, r0, r1, key_mode, &L, &nz1, &bad1, &sg1);
         else
             spmv_rows(S, S.p, S.q, r0, r1);
         __syncthreads();
-        const DotOut d = dot(S.p, S.q, S.use_qdot != 0, nz1, bad1, sg1);
+        const DotOut d = dot(S.p, S.q, scan_q, nz1, bad1, sg1);
         if (!(healthy = d.ok)) break;
         if (!(d.value > 0.0) || !isfinite(d.value) || d.all_perf) {
             status = QDOT_E_BREAKDOWN;
@@ -607,7 +745,7 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
         // x += alpha p, r -= alpha q (four rows' loads in flight per thread),
         // with pass 1 of the qdot r . r that follows fused in
         unsigned int nz2 = 0, bad2 = 0, sg2 = 0;
-        const bool scan_r = S.use_qdot != 0;
+        const bool scan_r = S.use_qdot != 0 && !ACC1;
         auto xr_row = [&](int64_t i, double pi, double xi, double qi, double ri) {
             const double ap = alpha * pi;
             st_dev(&S.x[i], xi + ap);

@@ -174,9 +174,9 @@ def test_unsupported_combinations_are_rejected(h):
     rp, col, val = workloads.poisson2d_csr(8)
     A = q.Csr(rp, col, val)
     b = dev(workloads.normal_vector(64, 85))
-    with pytest.raises(q.QdotError):  # the one-pass mode is not a CG mode
+    with pytest.raises(q.QdotError):  # guaranteed and one-pass modes do not combine
         h.cg(A, b, torch.zeros(64, dtype=torch.float64, device="cuda:0"), 1e-10, 1e-8, 100, 1,
-             opt=[0, 0, 0, 1])
+             opt=[0, 0, 0, 1, 1])
 
 
 @pytest.mark.parametrize("data", ["reselect", "certified"])

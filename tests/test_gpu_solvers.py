@@ -135,6 +135,67 @@ def test_cg_iteration_parity(h, m):
                                atol=1e-7 * np.abs(oq["x"]).max())
 
 
+ONE_PASS = [0, 0, 0, 1]
+
+
+@pytest.mark.parametrize("m", [32, 128])
+def test_cg_one_pass_mode(h, m):
+    # every inner product by the one-pass qdot: the oracle's CG with the same
+    # mode (first product bit for bit; iteration counts within one), and the
+    # FP64-dot CG's iteration count
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    b = workloads.normal_vector(m * m, 5)
+    print(f"[gpu-case] cg one-pass m={m}", flush=True)
+    x = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    r = h.cg(A, dev(b), x, 1e-10, 1e-8, 20000, 1, opt=ONE_PASS, trace=True)
+    o = oracle.cg(rp, col, val, b, 1e-10, 1e-8, 20000, 1, opt=ONE_PASS, want_trace=True)
+    xf = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    rf = h.cg(A, dev(b), xf, 1e-10, 1e-8, 20000, 0)
+    assert r["status"] == q.OK and o["status"] == oracle.OK
+    assert abs(r["iters"] - o["iters"]) <= 1 and abs(r["iters"] - rf["iters"]) <= 1
+    assert r["relres_true"] < 1e-9
+    t0, o0 = r["trace"][0], o["trace"][0]
+    for k in ("count", "n_zero", "n_bins", "e_max", "e_min", "t", "flags", "passes"):
+        assert t0[k] == o0[k], k
+    assert abs(t0["value"] - o0["value"]) <= 1e-13 * float(np.dot(b, b))
+    np.testing.assert_allclose(x.cpu().numpy(), o["x"], rtol=0, atol=1e-7 * np.abs(o["x"]).max())
+
+
+def test_cg_one_pass_repeatable_and_rejected(h):
+    # the gang's one-pass tables are left clean: a second solve on the same
+    # handle is bitwise the first; an inadmissible tolerance is refused
+    m = 64
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    b = dev(workloads.normal_vector(m * m, 6))
+    xs = []
+    for _ in range(2):
+        x = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+        r = h.cg(A, b, x, 1e-10, 1e-8, 20000, 1, opt=ONE_PASS)
+        assert r["status"] == q.OK
+        xs.append(x.cpu().numpy())
+    np.testing.assert_array_equal(xs[0], xs[1])
+    with pytest.raises(q.QdotError):
+        h.cg(A, b, torch.zeros(m * m, dtype=torch.float64, device="cuda:0"), 1e-10, 1e-300,
+             100, 1, opt=ONE_PASS)
+
+
+@pytest.mark.timeout(300)
+def test_full_size_cg_one_pass(h):
+    m = 1024
+    print(f"[gpu-case] CG one-pass Poisson {m}^2", flush=True)
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    b = dev(workloads.normal_vector(m * m, 3))
+    x = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    r = h.cg(A, b, x, 1e-10, 1e-8, 20000, 1, opt=ONE_PASS)
+    xf = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    rf = h.cg(A, b, xf, 1e-10, 1e-8, 20000, 0)
+    assert r["status"] == q.OK and r["relres_true"] < 2e-10
+    assert abs(r["iters"] - rf["iters"]) <= 1, (r["iters"], rf["iters"])
+
+
 def test_cg_breakdown_when_all_perforated(h):
     rp, col, val = workloads.poisson2d_csr(16)
     A = q.Csr(rp, col, val)
