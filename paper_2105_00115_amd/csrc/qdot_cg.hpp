@@ -8,15 +8,15 @@
 //   before the SpMV (p complete), after a qdot's pass 1 (histogram merged),
 //   after its pass 2 (partials written),
 // five per iteration (one more for an inner product that the guaranteed
-// mode sums again).  Between those barriers every block computes the
-// cutoff and the final combine of each qdot itself, from the same merged
-// histogram and the same partials in the same order, so every block holds
-// bit-identical scalars (alpha, beta, c) and takes the same branches: the
-// gang never needs to broadcast a decision.  The whole-gang reductions (the
-// blocks' pass-1 records and histogram copies at the first barrier of a
-// qdot, its partials at the second) are done once, by the last block to
-// arrive, before it releases the others; that block also clears the
-// histogram copies.  Two buffers alternate between consecutive qdots.
+// mode sums again; one fewer per inner product in the one-pass mode).  The
+// whole-gang reductions (the blocks' pass-1 records and histogram copies at
+// the first barrier of a qdot, its partials at the second) are done once,
+// by the last block to arrive, before it releases the others; that block
+// also clears the histogram copies.  Every block then computes the cutoff
+// itself from the same merged histogram and finishes the combine from the
+// same published words, so every block holds bit-identical scalars (alpha,
+// beta, c) and takes the same branches: no decision is broadcast.  Two
+// buffers alternate between consecutive qdots.
 //
 // Every wait is bounded: a barrier that does not complete within the spin
 // limit raises the gang's abort flag, every block leaves, and the call
