@@ -162,6 +162,39 @@ def test_cg_one_pass_mode(h, m):
     np.testing.assert_allclose(x.cpu().numpy(), o["x"], rtol=0, atol=1e-7 * np.abs(o["x"]).max())
 
 
+@pytest.mark.parametrize("opt", [[1, 0, 0, 0], [0, 1, 1, 0], [1, 1, 1, 1]])
+def test_cg_options(h, opt):
+    # key, score and boundary modes (and the one-pass reading) through the
+    # gang: the first inner product bit for bit, the iteration count within
+    # one of the oracle's CG with the same options
+    m = 32
+    rp, col, val = workloads.poisson2d_csr(m)
+    A = q.Csr(rp, col, val)
+    b = workloads.normal_vector(m * m, 16)
+    print(f"[gpu-case] cg options {opt}", flush=True)
+    x = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
+    r = h.cg(A, dev(b), x, 1e-10, 1e-8, 20000, 1, opt=opt, trace=True)
+    o = oracle.cg(rp, col, val, b, 1e-10, 1e-8, 20000, 1, opt=opt, want_trace=True)
+    assert r["status"] == q.OK and o["status"] == oracle.OK
+    assert abs(r["iters"] - o["iters"]) <= 1
+    t0, o0 = r["trace"][0], o["trace"][0]
+    for k in ("count", "n_zero", "n_bins", "e_max", "e_min", "t", "flags", "passes"):
+        assert t0[k] == o0[k], k
+    assert abs(t0["value"] - o0["value"]) <= 1e-13 * float(np.dot(b, b))
+
+
+@pytest.mark.parametrize("opt", [[1, 0, 0, 0], [0, 1, 1, 0]])
+def test_power_method_options(h, opt):
+    m = 12
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, val)
+    x0 = workloads.unit_vector(m ** 3, 17)
+    r = h.power(A, dev(x0), 80, 1e-6, 1, opt=opt)
+    o = oracle.power(rp, col, val, x0, 80, 1e-6, 1, opt=opt)
+    assert r["status"] == q.OK
+    np.testing.assert_allclose(r["trace"], o["trace"], rtol=1e-9, atol=0)
+
+
 def test_cg_one_pass_repeatable_and_rejected(h):
     # the gang's one-pass tables are left clean: a second solve on the same
     # handle is bitwise the first; an inadmissible tolerance is refused
