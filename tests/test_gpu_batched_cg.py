@@ -67,6 +67,20 @@ def test_cg_batched_matches_oracle_and_fp64_twin(h):
         np.testing.assert_allclose(xq, o["x"], rtol=0, atol=1e-7 * np.abs(o["x"]).max())
 
 
+@pytest.mark.parametrize("opt", [[1, 0, 0, 0], [0, 1, 1, 0]])
+def test_cg_batched_options(h, opt):
+    # key, score and boundary modes reach every gang: iteration counts within
+    # one of the oracle's CG with the same options
+    sq = [poisson_system(m, 200 + m, 1) for m in (16, 45, 140)]
+    res = h.cg_batched([as_tuple(s) for s in sq], opt=opt)
+    for s, r in zip(sq, res):
+        rp, col, val = s["csr"]
+        o = oracle.cg(rp, col, val, s["b_host"], 1e-10, 1e-8, 20000, 1, opt=opt)
+        assert r["status"] == q.OK and o["status"] == oracle.OK, (s["m"], r)
+        assert abs(o["iters"] - r["iters"]) <= 1, (s["m"], o["iters"], r["iters"])
+        assert r["relres_true"] < 1e-9
+
+
 def test_cg_batched_equals_single_system_solver(h):
     sys = [poisson_system(m, 7 + m, 1) for m in (32, 140)]
     res = h.cg_batched([as_tuple(s) for s in sys])
