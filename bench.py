@@ -131,8 +131,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE {world}); the sharded design is described in DESIGN.md",
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); multi-GPU sharding is a design, not an implementation",
               file=sys.stderr)
         sys.exit(2)
 
