@@ -113,7 +113,7 @@ def lib():
                          _dp, C.POINTER(OrcResult)]
     L.orc_cg.restype = C.c_int
     L.orc_power.argtypes = [C.c_int64, _i32p, _i32p, _dp, _dp, C.c_int32,
-                            C.c_double, C.c_int32, _i32p, _dp, _dp]
+                            C.c_double, C.c_int32, _i32p, _dp, _dp, C.POINTER(OrcResult)]
     L.orc_power.restype = C.c_int
     _lib = L
     return L
@@ -283,15 +283,23 @@ def cg(rowptr, col, val, b, rtol, qtol, maxit, use_qdot, opt=None, x0=None,
     return d
 
 
-def power(rowptr, col, val, x0, iters, qtol, use_qdot, opt=None) -> dict:
+def power(rowptr, col, val, x0, iters, qtol, use_qdot, opt=None,
+          want_results=False) -> dict:
+    """Oracle power method.  'trace' holds every lambda; with want_results,
+    'results' holds the two inner-product results of every iteration
+    (lambda's first), as many as were computed."""
     rp, cl, vl = _csr(rowptr, col, val)
     n = rp.shape[0] - 1
     x = np.array(x0, dtype=np.float64)
     o, op = _opts(opt)
     lam = C.c_double()
     tr = np.zeros(max(iters, 1), dtype=np.float64)
+    res = (OrcResult * max(2 * iters, 1))() if want_results else None
     st = lib().orc_power(n, rp.ctypes.data_as(_i32p), cl.ctypes.data_as(_i32p),
                          vl.ctypes.data_as(_dp), x.ctypes.data_as(_dp),
                          int(iters), float(qtol), int(use_qdot), op,
-                         C.byref(lam), tr.ctypes.data_as(_dp))
-    return {"status": st, "lambda": lam.value, "trace": tr[:iters], "x": x}
+                         C.byref(lam), tr.ctypes.data_as(_dp), res)
+    d = {"status": st, "lambda": lam.value, "trace": tr[:iters], "x": x}
+    if want_results:
+        d["results"] = [res[i].as_dict() for i in range(2 * iters)]
+    return d

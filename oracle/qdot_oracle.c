@@ -25,6 +25,14 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Internal class of single-precision inputs for the bins that eq.
+ * (precision-def) cannot lower: the product is formed at the input
+ * precision (FP32) and added at input precision or better, here exactly,
+ * with the double leaves (Alg. 1's accumulation at the precision of x and
+ * y; the FP32 tile trees are for the narrower classes).  Counted and
+ * reported as single. */
+#define ORC_SINGLE_IN 4
+
 /* mantissa widths m_half, m_single, m_double of eq. (precision-def) */
 #define M_HALF 10
 #define M_SINGLE 23
@@ -274,7 +282,8 @@ static double eps_of(int cls)
 {
     switch (cls) {
     case ORC_DOUBLE: return 0x1p-52;
-    case ORC_SINGLE: return 0x1p-23;
+    case ORC_SINGLE:
+    case ORC_SINGLE_IN: return 0x1p-23;
     case ORC_HALF: return 0x1p-10;
     default: return 1.0; /* perforated: the whole term is the error */
     }
@@ -292,7 +301,8 @@ static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e
     /* eq. (precision-def) admits a row only when mu is at least the row's
      * mantissa width: with single inputs (mu = m_single) there is no double
      * row, a bin scoring at or above m_single stays at the input precision
-     * and is flagged, as a double bin scoring at or above m_double is. */
+     * (ORC_SINGLE_IN) and is flagged, as a double bin scoring at or above
+     * m_double is. */
     const int32_t m_top = mu_single ? M_SINGLE : M_DOUBLE;
     xsum brel;
     xs_init(&brel);
@@ -304,11 +314,11 @@ static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e
         if (Mk == 0) continue; /* empty bin: score -inf */
         int32_t sigma = orc_ceil_log2(Mk) + k - e_ref - t + 1;
         int32_t c = orc_precision(sigma, nonstrict);
-        if (mu_single && c == ORC_DOUBLE) c = ORC_SINGLE;
+        if (mu_single && c == ORC_DOUBLE) c = ORC_SINGLE_IN;
         if (nonstrict ? sigma > m_top : sigma >= m_top)
             r->flags |= ORC_F_UNATTAINABLE;
         C[k - ORC_KMIN] = (uint8_t)c;
-        r->count[c] += Mk;
+        r->count[c == ORC_SINGLE_IN ? ORC_SINGLE : c] += Mk;
         /* Thm 3.3 term M_k 2^(u_k - e_max + 1) eps(k), u_k = k */
         xs_add(&brel, ldexp((double)Mk * eps_of(c), k - e_max + 1));
     }
@@ -335,6 +345,9 @@ static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e
  *   single: fl32(fl32(m_x) fl32(m_y))            (FP32 product)
  *   half:   r16(m_x) r16(m_y), exact in FP32     (FP16 operands, FP32
  *                                                 product/accumulation)
+ *   single inputs held at their own precision (ORC_SINGLE_IN): the single
+ *   product, summed with the double leaves relative to 2^e_max (a range no
+ *   FP32 tile could hold: such bins may sit anywhere below e_max).
  * accum_mode 0: FP32 leaves are summed in FP32 only inside 64-element tiles
  * of the original index order (adjacent-pairwise tree); tile sums and
  * double leaves are then summed at input precision: exactly, rounded once.
@@ -385,6 +398,13 @@ static double orc_compute(const double *x, const double *y, int64_t n, const int
                     xs_add(&all, leaf);
                     xs_add(&pd, leaf);
                     xs_add(&rig, xy_abs_rel * 0x1p-53);
+                } else if (c == ORC_SINGLE_IN) {
+                    float a = (float)mx, b = (float)my;
+                    float p = a * b;
+                    double leaf = ldexp((double)(neg ? -p : p), es - e_max);
+                    xs_add(&all, leaf);
+                    xs_add(&ps, leaf);
+                    xs_add(&rig, xy_abs_rel * dS);
                 } else if (c == ORC_SINGLE) {
                     float a = (float)mx, b = (float)my;
                     float p = a * b;
@@ -401,7 +421,7 @@ static double orc_compute(const double *x, const double *y, int64_t n, const int
                     xs_add(&rig, xy_abs_rel); /* perforated: whole term */
                 }
             }
-            if (cls_out) cls_out[i] = c;
+            if (cls_out) cls_out[i] = c == ORC_SINGLE_IN ? ORC_SINGLE : c;
         }
         if (accum_mode == 0) {
             double th = ldexp((double)orc_tree64(lh), c32 - e_max);
@@ -456,7 +476,9 @@ static double orc_compute(const double *x, const double *y, int64_t n, const int
 static double orc_guard_slack(const int64_t *M, const uint8_t *C, int32_t e_max, double S,
                               int64_t n)
 {
-    const double rho[4] = {0x1p-53, 0x1.8p-23 + 0x1.8p-47 + 0x1p-72, 0x1p-10 + 0x1p-22, 1.0};
+    /* indexed by class; ORC_SINGLE_IN (4) takes single's */
+    const double rho[5] = {0x1p-53, 0x1.8p-23 + 0x1.8p-47 + 0x1p-72, 0x1p-10 + 0x1p-22, 1.0,
+                           0x1.8p-23 + 0x1.8p-47 + 0x1p-72};
     const double u32 = 0x1p-24, u64 = 0x1p-53;
     const double g6 = 6.0 * u32 / (1.0 - 6.0 * u32);
     const double nu = (double)n * u64;
@@ -768,7 +790,7 @@ int orc_cg(int64_t n, const int32_t *rowptr, const int32_t *col,
 int orc_power(int64_t n, const int32_t *rowptr, const int32_t *col,
               const double *val, double *x, int32_t iters, double qtol,
               int32_t use_qdot, const int32_t *opt, double *lambda,
-              double *lambda_trace)
+              double *lambda_trace, orc_result *trace)
 {
     double *w = (double *)malloc(sizeof(double) * (size_t)n);
     int st = ORC_OK;
@@ -776,9 +798,9 @@ int orc_power(int64_t n, const int32_t *rowptr, const int32_t *col,
     for (int32_t k = 0; k < iters; k++) {
         orc_spmv(n, rowptr, col, val, x, w);
         double c;
-        st = inner(x, w, n, use_qdot, qtol, opt, &lam, NULL);
+        st = inner(x, w, n, use_qdot, qtol, opt, &lam, trace ? &trace[2 * k] : NULL);
         if (st != ORC_OK) break;
-        st = inner(w, w, n, use_qdot, qtol, opt, &c, NULL);
+        st = inner(w, w, n, use_qdot, qtol, opt, &c, trace ? &trace[2 * k + 1] : NULL);
         if (st != ORC_OK) break;
         if (!(c > 0.0) || !isfinite(c)) {
             st = ORC_E_BREAKDOWN;

@@ -111,11 +111,12 @@ int orc_cg(int64_t n, const int32_t *rowptr, const int32_t *col,
 
 /* Power method: per iteration w = A x, lambda = dot(x, w), c = dot(w, w),
  * x = w / sqrt(c).  x is a unit vector on entry and exit. lambda_trace
- * (nullable, iters) receives every lambda. */
+ * (nullable, iters) receives every lambda; trace (nullable, 2*iters) the
+ * results of both inner products of every iteration, lambda's first. */
 int orc_power(int64_t n, const int32_t *rowptr, const int32_t *col,
               const double *val, double *x, int32_t iters, double qtol,
               int32_t use_qdot, const int32_t *opt, double *lambda,
-              double *lambda_trace);
+              double *lambda_trace, orc_result *trace);
 
 #ifdef __cplusplus
 }

@@ -246,7 +246,7 @@ __device__ __forceinline__ int class_of(int sigma, int nonstrict)
 
 __device__ __forceinline__ double eps_of_class(int c)
 {
-    return c == QDOT_DOUBLE ? 0x1p-52 : c == QDOT_SINGLE ? 0x1p-23
+    return c == QDOT_DOUBLE ? 0x1p-52 : (c == QDOT_SINGLE || c == SINGLE_IN) ? 0x1p-23
          : c == QDOT_HALF ? 0x1p-10 : 1.0;
 }
 
@@ -369,9 +369,9 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
             cls = class_of(sigma, nonstrict);
             // single inputs (mu = m_single): no double row; such a bin stays
             // at the input precision and is flagged like a double bin >= 52
-            if (mu_single && cls == QDOT_DOUBLE) cls = QDOT_SINGLE;
+            if (mu_single && cls == QDOT_DOUBLE) cls = SINGLE_IN;
             unatt |= sigma >= (mu_single ? 23 : 52) + (nonstrict ? 1 : 0);
-            cc[cls] += v;
+            cc[cls == SINGLE_IN ? QDOT_SINGLE : cls] += v;
             // Thm 3.3 term M_k 2^(k - e_max + 1) eps(class)
             bound += ldexp((double)v * eps_of_class(cls), k - e_max + 1);
         }
@@ -444,7 +444,7 @@ __device__ __forceinline__ double guard_rho(int c)
 {
     // largest relative error of one leaf of each class
     return c == QDOT_DOUBLE ? 0x1p-53
-         : c == QDOT_SINGLE ? 0x1.8p-23 + 0x1.8p-47 + 0x1p-72  // (1+2^-24)^3 - 1
+         : (c == QDOT_SINGLE || c == SINGLE_IN) ? 0x1.8p-23 + 0x1.8p-47 + 0x1p-72  // (1+2^-24)^3 - 1
          : c == QDOT_HALF   ? 0x1p-10 + 0x1p-22                // (1+2^-11)^2 - 1
                             : 1.0;
 }
@@ -529,24 +529,32 @@ __device__ __forceinline__ void acc_group(const T *xv, const T *yv, int lim,
 {
     float ls[4], lh[4];
     if constexpr (sizeof(T) == 4) {
+        // bins held at the input precision (SINGLE_IN): the FP32 product,
+        // summed in FP64 relative to 2^e_max with the double class's sums
+        double li[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const CompF c = component_f(xv[e], yv[e], key_mode);
             const bool valid = e < lim;
             const int cls = valid ? (int)lut[c.slot] : QDOT_PERF;
-            if (CLS && valid) cls_out[e] = (unsigned char)cls;
+            if (CLS && valid)
+                cls_out[e] = (unsigned char)(cls == SINGLE_IN ? QDOT_SINGLE : cls);
             const float ps = c.mx * c.my;
             const float ph = half_round_f(c.mx) * half_round_f(c.my);  // 22 bits: exact
             float l32 = ldexpf(cls == QDOT_HALF ? ph : ps, c.es - c32);
             l32 = __int_as_float(__float_as_int(l32) ^ (int)c.sgn);
             ls[e] = cls == QDOT_SINGLE ? l32 : 0.0f;
             lh[e] = cls == QDOT_HALF ? l32 : 0.0f;
+            double l64 = ldexp((double)ps, c.es - e_max);
+            l64 = __longlong_as_double(__double_as_longlong(l64) ^ ((long long)c.sgn << 32));
+            li[e] = cls == SINGLE_IN ? l64 : 0.0;
         }
         if (accumulate) {
             const float s4 = (ls[0] + ls[1]) + (ls[2] + ls[3]);
             const float h4 = (lh[0] + lh[1]) + (lh[2] + lh[3]);
             const float ts = tile_levels_3to6(s4);
             const float th = tile_levels_3to6(h4);
+            acc_add(aD, (li[0] + li[1]) + (li[2] + li[3]));
             if ((threadIdx.x & 15) == 0) {
                 acc_add(aS, (double)ts);
                 acc_add(aH, (double)th);
@@ -793,7 +801,7 @@ __device__ __forceinline__ void s1_pick(int e_max, int lo, int flags, const unsi
             acc_add(a[0], ldexp(get(bin, 3), -j));
             acc_add(a[0], ldexp(get(bin, 4), -j));
             acc_add(a[0], ldexp(get(bin, 5), -j));
-        } else if (cls == QDOT_SINGLE) {
+        } else if (cls == QDOT_SINGLE || cls == SINGLE_IN) {
             acc_add(a[1], ldexp(get(bin, 1), -j));
             acc_add(a[1], ldexp(get(bin, 2), -j));
         } else if (cls == QDOT_HALF) {
@@ -817,8 +825,10 @@ __device__ __forceinline__ void s1_pick(int e_max, int lo, int flags, const unsi
 
 // value = 2^e_max (D + 2^(c32 - e_max) (S + H)), parts, overflow flag;
 // returns the FP64 sum D + 2^(c32 - e_max) (S + H) before the scaling.
+// mu_single: single-precision inputs, whose D holds the bins kept at the
+// input precision (SINGLE_IN); they are reported in part[SINGLE].
 __device__ __forceinline__ double combine_value(const Acc f[3], int e_max, int c32, int flags,
-                                                qdot_result *out)
+                                                qdot_result *out, int mu_single = 0)
 {
     // FP32-class sums are in units of 2^c32, the total in units of 2^e_max
     const int sh = c32 - e_max;
@@ -829,8 +839,10 @@ __device__ __forceinline__ double combine_value(const Acc f[3], int e_max, int c
     const double S = tot.s + tot.c;
     const double value = ldexp(S, e_max);
     out->value = value;
-    out->part[QDOT_DOUBLE] = ldexp(f[0].s + f[0].c, e_max);
-    out->part[QDOT_SINGLE] = ldexp(f[1].s + f[1].c, c32);
+    const double pd = ldexp(f[0].s + f[0].c, e_max);
+    const double ps = ldexp(f[1].s + f[1].c, c32);
+    out->part[QDOT_DOUBLE] = mu_single ? 0.0 : pd;
+    out->part[QDOT_SINGLE] = mu_single ? ps + pd : ps;
     out->part[QDOT_HALF] = ldexp(f[2].s + f[2].c, c32);
     out->flags = flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
     return S;

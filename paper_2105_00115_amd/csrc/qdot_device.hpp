@@ -29,6 +29,13 @@ constexpr int TILE = 64;                    // FP32 accumulation tile
 constexpr int CUT_THREADS = 1024;
 constexpr int MAX_GRID = 16 * 256;          // persistent grid cap (16 per CU)
 
+// Class-table code of a single-precision input bin that eq. (precision-def)
+// cannot lower (score at or above m_single): the product is formed in FP32,
+// the input precision, and added in FP64 with the double leaves relative to
+// 2^e_max, since such bins may lie anywhere below e_max.  Counted and
+// reported as QDOT_SINGLE; never present for double inputs.
+constexpr int SINGLE_IN = 4;
+
 constexpr uint64_t FRAC_MASK = 0x000fffffffffffffull;
 constexpr uint64_t ONE_BITS = 0x3ff0000000000000ull;
 
@@ -46,7 +53,7 @@ struct Ws {
     int skip;                    // nothing to accumulate (result final)
     int flags;                   // result flags known after selection
     int s1_lo, s1_hi;            // live slot range of the last scan
-    int pad1;
+    int mu_single;               // the last selection was for single-precision inputs
     // per scan block: bit 0 = a negative, bit 1 = a positive non-zero product
     unsigned int block_signs[MAX_GRID];
     // guaranteed mode (guard_mode 1)

@@ -125,6 +125,7 @@ __device__ __forceinline__ void cut_body(Ws *__restrict__ ws, double tol, int sc
         ws->s1_lo = lo;
         ws->s1_hi = hi;
         ws->signs = sg;
+        ws->mu_single = mu_single;
     }
 }
 
@@ -239,7 +240,7 @@ __device__ __forceinline__ void fin_body(Ws *__restrict__ ws,
             f[q] = red[q][0];
             for (int w = 1; w < BLOCK / 64; w++) f[q] = acc_merge(f[q], red[q][w]);
         }
-        ws->s_last = combine_value(f, ws->e_max, ws->c32, ws->flags, out);
+        ws->s_last = combine_value(f, ws->e_max, ws->c32, ws->flags, out, ws->mu_single);
     }
 }
 

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import workloads
+from parity_util import check_instances, host
 
 torch = pytest.importorskip("torch")
 import paper_2105_00115_amd as q  # noqa: E402
@@ -152,26 +153,23 @@ def test_batched_graph_replay(h):
 
 
 @pytest.mark.timeout(600)
-def test_batched_c5_full_size_sampled(h):
+@pytest.mark.parametrize("accum", [0, 1])
+def test_batched_c5_full_size(h, accum):
     """4096 instances, lengths round(10^U[2,6]) (about 4.45e8 components in
     all), tolerances from {1e-4, 1e-6, 1e-8}: the launch the batched
-    benchmark times.  Parity on a seeded sample of instances."""
+    benchmark times, in both readings of the accumulation.  Every instance
+    against the oracle on that instance alone."""
     g = workloads.rng(2025)
     sizes = np.rint(10.0 ** g.uniform(2, 6, 4096)).astype(np.int64)
     offsets = np.zeros(4097, dtype=np.int64)
     np.cumsum(sizes, out=offsets[1:])
     tols = np.array([1e-4, 1e-6, 1e-8])[g.integers(0, 3, 4096)]
     total = int(offsets[-1])
-    print(f"[gpu-case] batched C5 total={total}", flush=True)
+    opt = [0, 0, 0, accum]
+    print(f"[gpu-case] batched C5 total={total} accum_mode={accum}", flush=True)
     xd, yd = workloads.log_uniform_pair_torch(total, 2025, "cuda:0")
-    res = h.batched(xd, yd, offsets, tols)
-    pick = sorted(set(g.integers(0, 4096, 40).tolist()) | {int(np.argmax(sizes))})
-    for j in pick:
-        a, b = int(offsets[j]), int(offsets[j + 1])
-        xs = xd[a:b].cpu().numpy()
-        ys = yd[a:b].cpu().numpy()
-        o = oracle.qdot(xs, ys, tols[j])
-        for k in INT_KEYS:
-            assert res[j][k] == o[k], (j, k)
-        assert abs(res[j]["value"] - o["value"]) <= VALUE_TOL * oracle.abs_dot(xs, ys)
+    res = h.batched(xd, yd, offsets, tols, opt=opt)
+    xh, yh = host(xd), host(yd)
+    del xd, yd
+    assert check_instances(res, offsets, xh, yh, tols, opt=opt) == 4096
     assert sum(sum(r["count"]) for r in res) == total

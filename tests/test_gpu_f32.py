@@ -171,6 +171,21 @@ def test_guaranteed_mode_law(h):
         assert r["flags"] == flags and r["passes"] == 1, (tol, r["flags"])
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_wide_range_cancelling_sums(h, seed):
+    # products spanning 10^+-18 (more exponents than one FP32 number holds)
+    # that cancel to ~1e-3: the guaranteed mode reselects every bin to
+    # single or above, bins held at the input precision are summed in FP64;
+    # the default mode at a tiny tolerance holds every bin there
+    x, y = workloads.cancelling_wide_f32(4001, 50 + seed)
+    for tol in (1e-3, 1e-6, 1e-10):
+        r, o = compare(h, x, y, tol, opt=GUARD)
+        assert np.isfinite(r["value"]) and r["flags"] & q.F_RESELECTED
+    for opt in (None, [0, 0, 0, 1]):
+        r, o = compare(h, x, y, 1e-300, opt=opt, classes=opt is None)
+        assert r["flags"] & q.F_UNATTAINABLE and r["count"][q.SINGLE] == 4001
+
+
 S1 = [0, 0, 0, 1]
 
 

@@ -256,7 +256,7 @@ def test_cg_guaranteed_mode(h, m):
     xf = torch.zeros(m * m, dtype=torch.float64, device="cuda:0")
     rf = h.cg(A, dev(b), xf, 1e-10, 1e-8, 20000, 0)
     assert r["status"] == q.OK and o["status"] == oracle.OK
-    assert abs(r["iters"] - o["iters"]) <= 1 and abs(r["iters"] - rf["iters"]) <= 1
+    assert abs(r["iters"] - o["iters"]) <= 1 and r["iters"] == rf["iters"]
     assert r["relres_true"] < 1e-9
     check_cg_trace(r["trace"], o["trace"], [float(np.dot(b, b))], 1)
     assert r["trace"][0]["flags"] & q.F_GUARANTEED  # r.r: one sign

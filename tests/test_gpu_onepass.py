@@ -265,11 +265,3 @@ def test_batched_one_pass_nonfinite_and_graph_replay(h):
         torch.cuda.synchronize()
 
 
-@pytest.mark.timeout(600)
-def test_full_size_c2_one_pass(h):
-    """n = 2**27 at tol 1e-6 in the default launch configuration: integer
-    outputs and value against the oracle's one-pass reading."""
-    n = 1 << 27
-    print(f"[gpu-case] one-pass full size n={n}", flush=True)
-    x, y = workloads.log_uniform_pair(n, 2027)
-    compare_s1(h, x, y, 1e-6)

@@ -591,6 +591,58 @@ def test_f32_guaranteed_mode_hand_example():
     assert Fraction(r["bound_rel"]) == (4 + Fraction(1, 2 ** 9)) / 2 ** 23
 
 
+def _f32_product_sum(x, y) -> Fraction:
+    """Exact sum of the float32-rounded products (numpy float32 multiply: one
+    IEEE rounding per product, all normal here)."""
+    p = (x.astype(np.float32) * y.astype(np.float32)).astype(np.float64)
+    return sum((Fraction(v) for v in p.tolist()), Fraction(0))
+
+
+def test_f32_bins_held_at_input_precision_sum_the_float_products():
+    # Single inputs whose bins score at or above m_single cannot be lowered
+    # (no double row): each product is formed in FP32 and added at input
+    # precision or better.  With every bin held there (tol 1e-300) the value
+    # is the correctly rounded sum of the float32 products, even when the
+    # products span far more exponents than one FP32 number can hold
+    # (10^+-18 -> keys from -120 to 119, and y = 1 keeps every product
+    # exact).
+    for seed in range(3):
+        x, y = workloads.cancelling_wide_f32(4001, 40 + seed)
+        r = oracle.qdot_f32(x, y, 1e-300, want_classes=True)
+        assert r["status"] == oracle.OK
+        assert r["flags"] & oracle.F_UNATTAINABLE
+        assert r["count"][oracle.SINGLE] == 4001
+        assert set(r["classes"].tolist()) == {oracle.SINGLE}
+        assert Fraction(r["value"]) == Fraction(float(_f32_product_sum(x, y)))
+        assert r["part"][oracle.SINGLE] == r["value"] and r["part"][oracle.DOUBLE] == 0.0
+    # random operands (products rounded in FP32): the same identity
+    g = np.random.default_rng(44)
+    x = (g.standard_normal(3000) * 10.0 ** g.uniform(-15, 15, 3000)).astype(np.float32)
+    y = (g.standard_normal(3000) * 10.0 ** g.uniform(-15, 15, 3000)).astype(np.float32)
+    r = oracle.qdot_f32(x, y, 1e-300)
+    assert Fraction(r["value"]) == Fraction(float(_f32_product_sum(x, y)))
+
+
+def test_f32_guaranteed_mode_on_wide_cancelling_sums():
+    # Products spanning 10^+-18 with random signs, cancelling to ~1e-3 of
+    # the largest: the first selection holds the top bins at single (no
+    # double row) and perforates most others; the sum is not bounded away
+    # from 0, so the reselection puts every bin at single or above.  The
+    # result is finite, within the rigorous bound, its lower bound never
+    # exceeds |x.y| (Fractions), and a certified result meets tol.
+    for seed in range(4):
+        x, y = workloads.cancelling_wide_f32(4001, 50 + seed)
+        ex = _f32_product_sum(x, y)  # y = 1: the float products are exact
+        for tol in (1e-3, 1e-6, 1e-10):
+            r = oracle.qdot_f32(x, y, tol, opt=GUARD)
+            assert r["status"] == oracle.OK and math.isfinite(r["value"]), (seed, tol)
+            assert r["flags"] & oracle.F_RESELECTED
+            assert abs(Fraction(r["value"]) - ex) <= Fraction(r["bound_rig"])
+            assert Fraction(r["lower"]) <= abs(ex)
+            if r["flags"] & oracle.F_GUARANTEED:
+                assert abs(Fraction(r["value"]) - ex) <= Fraction(tol) * abs(ex)
+
+
 def test_f32_edges():
     # float subnormals are exact doubles: key of 2^-140 * 1 is -140
     x = np.array([2.0 ** -140, 1.0], dtype=np.float32)

@@ -260,6 +260,20 @@ def cancelling_pair(n: int, seed: int, rel: float):
     return x, y
 
 
+def cancelling_wide_f32(n: int, seed: int, lo: float = -18.0, hi: float = 18.0,
+                        rel: float = 1e-3):
+    """x, y as float32 vectors whose products span 10**U[lo, hi] with random
+    signs (y = 1), and whose sum cancels: the last x is set, in float32, to
+    minus the exact sum of the others times (1 + rel * U[-1, 1]).  With the
+    default range the products span more exponents than any FP32 number."""
+    g = rng(seed)
+    x = (g.choice([-1.0, 1.0], n) * 10.0 ** g.uniform(lo, hi, n)).astype(np.float32)
+    y = np.ones(n, dtype=np.float32)
+    d = float(sum((Fraction(float(a)) for a in x[:-1].tolist()), Fraction(0)))
+    x[-1] = np.float32(-d * (1.0 + rel * g.uniform(-1.0, 1.0)))
+    return x, y
+
+
 def paired_cancelling_torch(n: int, seed: int, rel: float, device="cuda:0"):
     """x, y in FP64 on the device, n even: a = +-10**U[-3, 3], b normal,
     u = U[-1, 1] (m = n/2 each), x = [a, -a (1 + rel u)], y = [b, b].  The
