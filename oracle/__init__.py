@@ -127,9 +127,10 @@ def _f64(a):
 def _opts(opt):
     if opt is None:
         return None, None
-    o = np.zeros(5, dtype=np.int32)
+    o = np.zeros(7, dtype=np.int32)
     v = np.asarray(opt, dtype=np.int32).ravel()
-    assert v.shape[0] in (4, 5)  # {key, score, boundary, accum[, guard]} modes
+    # {key, score, boundary, accum[, guard[, bin_mode, bin_param]]}
+    assert v.shape[0] in (4, 5, 7)
     o[:v.shape[0]] = v
     return o, o.ctypes.data_as(_i32p)
 

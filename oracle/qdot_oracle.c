@@ -289,14 +289,85 @@ static double eps_of(int cls)
     }
 }
 
+/* One (l, u]-exponent bin (Def. 3.1) over the keys: it holds the keys
+ * lo = l + 1 .. u, M components in all. */
+typedef struct {
+    int32_t lo, u;
+    int64_t M;
+} orc_bin;
+
+/* M_a 2^u_a > M_b 2^u_b (the bins' terms of the Thm 3.2 bound before
+ * eps(k)), ties to the higher u.  Counts below 2^53 convert exactly. */
+static int orc_bin_heavier(const orc_bin *a, const orc_bin *b)
+{
+    int32_t d = a->u - b->u;
+    if (d >= 64) return 1;
+    if (d <= -64) return 0;
+    double va = ldexp((double)a->M, d), vb = (double)b->M;
+    if (va != vb) return va > vb;
+    return a->u > b->u;
+}
+
+/* Partition of [e_min, e_max] into exponent bins, by the binning strategies
+ * Sec. 3.2 weighs (the passage the typeset paper keeps names exact binning;
+ * the authors' draft of it also defines the other two):
+ *   bin_mode 0, exact: singletons (u - 1, u], u = e_min .. e_max;
+ *   bin_mode 1, ranged of width w = bin_param: (u_k - w, u_k] with
+ *     u_k = e_min + k w - 1, k = 1, 2, ... (the last may reach past e_max);
+ *   bin_mode 2, variable width (bin splitting) with at most s = bin_param
+ *     splits: start from the single bin (e_min - 1, e_max]; each split takes
+ *     the non-empty bin of more than one exponent with the largest term
+ *     M_k 2^(u_k) of the Thm 3.2 bound (ties to the higher u_k) and halves
+ *     it: (l, u] -> (l, m], (m, u] with m = l + ceil((u - l) / 2).  The
+ *     draft fixes neither the bin that is split nor where; this reading
+ *     splits where the bound is largest, at the middle.  s >= e_max - e_min
+ *     splits reach exact binning.
+ * Empty bins are kept (they have no score and do not count in N_bins).
+ * Returns the number of bins written to `bins` (at most ORC_W + 1). */
+static int orc_partition(const int64_t *M, int32_t e_min, int32_t e_max, int32_t bin_mode,
+                         int32_t bin_param, orc_bin *bins)
+{
+    int nb = 0;
+    if (bin_mode != 2) {
+        int32_t w = bin_mode == 1 ? bin_param : 1;
+        for (int32_t lo = e_min; lo <= e_max; lo += w) {
+            orc_bin b = {lo, lo + w - 1, 0};
+            for (int32_t k = lo; k <= b.u && k <= e_max; k++) b.M += M[k - ORC_KMIN];
+            bins[nb++] = b;
+        }
+        return nb;
+    }
+    orc_bin all = {e_min, e_max, 0};
+    for (int32_t k = e_min; k <= e_max; k++) all.M += M[k - ORC_KMIN];
+    bins[nb++] = all;
+    for (int32_t s = 0; s < bin_param; s++) {
+        int best = -1;
+        for (int i = 0; i < nb; i++) {
+            if (bins[i].M == 0 || bins[i].u == bins[i].lo) continue;
+            if (best < 0 || orc_bin_heavier(&bins[i], &bins[best])) best = i;
+        }
+        if (best < 0) break; /* every non-empty bin is a single exponent */
+        orc_bin b = bins[best];
+        int32_t l = b.lo - 1;
+        int32_t m = l + (b.u - l + 1) / 2;   /* l + ceil((u - l) / 2) */
+        orc_bin lower = {b.lo, m, 0}, upper = {m + 1, b.u, 0};
+        for (int32_t k = lower.lo; k <= lower.u; k++) lower.M += M[k - ORC_KMIN];
+        upper.M = b.M - lower.M;
+        bins[best] = upper;
+        bins[nb++] = lower;
+    }
+    return nb;
+}
+
 /* Classes of every bin (eq. (bin-score-def), eq. (precision-def)) with the
  * scores taken against the reference exponent e_ref: e_max as Alg. 2 has
  * it, or a lower estimate of flexp(x.y) when the guaranteed mode reselects
- * (Thm 3.4 puts E in place of e_max).  Fills the class table C, the class
- * counts, the Thm 3.3 sum relative to e_max and the selection flags. */
-static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e_ref,
-                       int32_t t, int32_t nonstrict, int mu_single, int64_t n_zero,
-                       uint8_t *C, orc_result *r)
+ * (Thm 3.4 puts E in place of e_max).  Fills the class table C (per key:
+ * the class of the key's bin), the class counts, the Thm 3.3 sum relative
+ * to e_max and the selection flags. */
+static void orc_select(const orc_bin *bins, int nbins, int32_t e_max, int32_t e_min,
+                       int32_t e_ref, int32_t t, int32_t nonstrict, int mu_single,
+                       int64_t n_zero, uint8_t *C, orc_result *r)
 {
     /* eq. (precision-def) admits a row only when mu is at least the row's
      * mantissa width: with single inputs (mu = m_single) there is no double
@@ -308,19 +379,20 @@ static void orc_select(const int64_t *M, int32_t e_max, int32_t e_min, int32_t e
     xs_init(&brel);
     for (int c = 0; c < 4; c++) r->count[c] = 0;
     r->flags = 0;
-    for (int32_t k = ORC_KMIN; k <= ORC_KMAX; k++) {
-        int64_t Mk = M[k - ORC_KMIN];
-        C[k - ORC_KMIN] = ORC_PERF;
+    for (int32_t k = ORC_KMIN; k <= ORC_KMAX; k++) C[k - ORC_KMIN] = ORC_PERF;
+    for (int i = 0; i < nbins; i++) {
+        int64_t Mk = bins[i].M;
+        int32_t u = bins[i].u;
         if (Mk == 0) continue; /* empty bin: score -inf */
-        int32_t sigma = orc_ceil_log2(Mk) + k - e_ref - t + 1;
+        int32_t sigma = orc_ceil_log2(Mk) + u - e_ref - t + 1;
         int32_t c = orc_precision(sigma, nonstrict);
         if (mu_single && c == ORC_DOUBLE) c = ORC_SINGLE_IN;
         if (nonstrict ? sigma > m_top : sigma >= m_top)
             r->flags |= ORC_F_UNATTAINABLE;
-        C[k - ORC_KMIN] = (uint8_t)c;
+        for (int32_t k = bins[i].lo; k <= u && k <= ORC_KMAX; k++) C[k - ORC_KMIN] = (uint8_t)c;
         r->count[c == ORC_SINGLE_IN ? ORC_SINGLE : c] += Mk;
-        /* Thm 3.3 term M_k 2^(u_k - e_max + 1) eps(k), u_k = k */
-        xs_add(&brel, ldexp((double)Mk * eps_of(c), k - e_max + 1));
+        /* Thm 3.3 term M_k 2^(u_k - e_max + 1) eps(k) */
+        xs_add(&brel, ldexp((double)Mk * eps_of(c), u - e_max + 1));
     }
     r->count[ORC_PERF] += n_zero;
     r->bound_rel = xs_round(&brel);
@@ -410,12 +482,17 @@ static double orc_compute(const double *x, const double *y, int64_t n, const int
                     float p = a * b;
                     ls[j] = ldexpf(neg ? -p : p, es - c32);
                     xs_add(&rig, xy_abs_rel * dS);
+                    /* a leaf below the FP32 normal range (possible only in a
+                     * bin wider than exact) is rounded to a multiple of
+                     * 2^-149: absolute error <= 2^-150 (units 2^c32) */
+                    if (fabsf(ls[j]) <= 0x1p-126f) xs_add(&rig, ldexp(1.0, c32 - e_max - 150));
                     tile_abs += fabs((double)ls[j]);
                 } else if (c == ORC_HALF) {
                     double hx = orc_r16(mx), hy = orc_r16(my);
                     float p = (float)(hx * hy); /* < 2^22: exact */
                     lh[j] = ldexpf(neg ? -p : p, es - c32 - 20);
                     xs_add(&rig, xy_abs_rel * dH);
+                    if (fabsf(lh[j]) <= 0x1p-126f) xs_add(&rig, ldexp(1.0, c32 - e_max - 150));
                     tile_abs += fabs((double)lh[j]);
                 } else {
                     xs_add(&rig, xy_abs_rel); /* perforated: whole term */
@@ -537,11 +614,17 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
     int32_t nonstrict = opt ? opt[2] : 0;
     int32_t accum_mode = opt ? opt[3] : 0;
     int32_t guard_mode = opt ? opt[4] : 0;
+    int32_t bin_mode = opt ? opt[5] : 0;
+    int32_t bin_param = opt ? opt[6] : 0;
     if (n < 0 || (n > 0 && (!x || !y)) || !(tol > 0.0) || !isfinite(tol) ||
         key_mode < 0 || key_mode > 1 || score_mode < 0 || score_mode > 1 ||
         nonstrict < 0 || nonstrict > 1 || accum_mode < 0 || accum_mode > 1 ||
         guard_mode < 0 || guard_mode > 1 ||
-        (guard_mode == 1 && (key_mode != 0 || accum_mode != 0))) {
+        (guard_mode == 1 && (key_mode != 0 || accum_mode != 0)) ||
+        bin_mode < 0 || bin_mode > 2 ||
+        (bin_mode == 1 && (bin_param < 1 || bin_param > ORC_W)) ||
+        (bin_mode == 2 && (bin_param < 0 || bin_param > ORC_W)) ||
+        (bin_mode != 0 && (accum_mode != 0 || guard_mode != 0))) {
         r->status = ORC_E_INVAL;
         r->value = NAN;
         return r->status;
@@ -575,10 +658,14 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
     int32_t e_max = INT32_MIN, e_min = INT32_MAX, n_bins = 0;
     for (int32_t k = ORC_KMIN; k <= ORC_KMAX; k++) {
         if (M[k - ORC_KMIN] == 0) continue;
-        n_bins++;
         if (k > e_max) e_max = k;
         if (k < e_min) e_min = k;
     }
+    /* Alg. 2's bins: a partition of [e_min, e_max]; N_bins counts the
+     * non-empty ones */
+    orc_bin *bins = (orc_bin *)malloc(sizeof(orc_bin) * (ORC_W + 1));
+    int nbins = e_max >= e_min ? orc_partition(M, e_min, e_max, bin_mode, bin_param, bins) : 0;
+    for (int i = 0; i < nbins; i++) n_bins += bins[i].M > 0;
     if (hist_out) memcpy(hist_out, M, sizeof(int64_t) * ORC_W);
     if (key_out)
         for (int64_t i = 0; i < n; i++) key_out[i] = key[i];
@@ -589,6 +676,7 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
         r->flags = ORC_F_ALL_PERF | (guard_mode ? ORC_F_GUARANTEED : 0);
         if (cls_out)
             for (int64_t i = 0; i < n; i++) cls_out[i] = ORC_PERF;
+        free(bins);
         free(M);
         free(key);
         return ORC_OK;
@@ -604,7 +692,7 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
     /* bin scores and precisions against e_max, then Alg. 1 */
     uint8_t *C = (uint8_t *)malloc(ORC_W);
     int32_t e_ref = e_max;
-    orc_select(M, e_max, e_min, e_ref, t, nonstrict, mu_single, r->n_zero, C, r);
+    orc_select(bins, nbins, e_max, e_min, e_ref, t, nonstrict, mu_single, r->n_zero, C, r);
     int kept = !(r->flags & ORC_F_ALL_PERF);
     double S = orc_compute(x, y, n, key, C, e_max, e_ref + t + 22, accum_mode, cls_out, r);
     r->passes = kept;
@@ -627,7 +715,8 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
                                      : e_min - t - (mu_single ? M_HALF : M_SINGLE) + 1 - nonstrict;
             if (ref2 < e_max) {
                 e_ref = ref2;
-                orc_select(M, e_max, e_min, e_ref, t, nonstrict, mu_single, r->n_zero, C, r);
+                orc_select(bins, nbins, e_max, e_min, e_ref, t, nonstrict, mu_single, r->n_zero,
+                           C, r);
                 int kept2 = !(r->flags & ORC_F_ALL_PERF);
                 S = orc_compute(x, y, n, key, C, e_max, e_ref + t + 22, accum_mode, cls_out, r);
                 double low2 = orc_lower(M, C, e_max, S, n, one_signed);
@@ -642,6 +731,7 @@ static int qdot_core(const double *x, const double *y, int64_t n, double tol,
     r->e_ref = e_ref;
 
     free(C);
+    free(bins);
     free(M);
     free(key);
     return ORC_OK;

@@ -61,8 +61,11 @@ typedef struct {
     int32_t passes;   /* Alg. 1 sweeps that kept a component (0, 1 or 2) */
 } orc_result;
 
-/* opt: NULL or 5 ints {key_mode, score_mode, boundary_mode, accum_mode,
- * guard_mode}; guard_mode 1 needs key_mode 0 and accum_mode 0.
+/* opt: NULL or 7 ints {key_mode, score_mode, boundary_mode, accum_mode,
+ * guard_mode, bin_mode, bin_param}; guard_mode 1 needs key_mode 0 and
+ * accum_mode 0.  bin_mode: 0 exact bins, 1 ranged bins of width bin_param
+ * (1..ORC_W), 2 variable-width bins from at most bin_param splits
+ * (0..ORC_W); modes 1 and 2 need accum_mode 0 and guard_mode 0.
  * cls (n bytes), keys (n int32; zero products get INT32_MIN) and hist
  * (ORC_W int64) are optional outputs. */
 int orc_qdot(const double *x, const double *y, int64_t n, double tol,

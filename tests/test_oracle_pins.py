@@ -654,6 +654,113 @@ def test_f32_edges():
 
 
 # --------------------------------------------------------------------------
+# Binning strategies of Sec. 3.2: ranged and variable-width bins
+# --------------------------------------------------------------------------
+
+def _ranged(w):
+    return [0, 0, 0, 0, 0, 1, w]
+
+
+def _variable(s):
+    return [0, 0, 0, 0, 0, 2, s]
+
+
+def test_ranged_and_variable_bins_reduce_to_exact_binning():
+    # ranged bins of width 1 are the exact bins; enough splits of the
+    # variable-width partition (e_max - e_min) end in singletons too
+    for seed in range(3):
+        x, y = workloads.log_uniform_pair(5000, 60 + seed)
+        x[::53] = 0.0
+        for tol in (1e-3, 1e-6, 1e-10):
+            e = oracle.qdot(x, y, tol, want_classes=True)
+            span = e["e_max"] - e["e_min"]
+            for opt in (_ranged(1), _variable(span), _variable(span + 7)):
+                r = oracle.qdot(x, y, tol, opt=opt, want_classes=True)
+                for k in ("count", "n_bins", "t", "flags", "value", "bound_rel", "bound_rig"):
+                    assert r[k] == e[k], (opt, k)
+                assert np.array_equal(r["classes"], e["classes"])
+
+
+def test_binning_worked_example():
+    # x = y = (1, 2^-3, 2^-9, 2^-15), tol 1e-6: keys 0, -6, -18, -30, e_max 0,
+    # e_min -30 (the exact bins give double, single, half, perforate).
+    x = np.array([1.0, 2.0 ** -3, 2.0 ** -9, 2.0 ** -15])
+    exact = Fraction(1) + Fraction(2) ** -6 + Fraction(2) ** -18 + Fraction(2) ** -30
+    D, S, H, P = oracle.DOUBLE, oracle.SINGLE, oracle.HALF, oracle.PERF
+    # Ranged, w = 8: u_k = -30 + 8k - 1 -> (-31,-23] {-30}, (-23,-15] {-18},
+    # (-15,-7] empty, (-7,1] {-6, 0}: N_bins 3, t = -22 (2^-22 <= 1e-6/3 <
+    # 2^-21).  Scores 1 + 1 - 0 + 22 + 1 = 25 (double), 0 - 15 + 23 = 8
+    # (half), 0 - 23 + 23 = 0 (half): nothing perforated, the value is exact.
+    r = oracle.qdot(x, x, 1e-6, opt=_ranged(8), want_classes=True)
+    assert r["n_bins"] == 3 and r["t"] == -22
+    assert r["classes"].tolist() == [D, D, H, H]
+    assert Fraction(r["value"]) == exact
+    assert Fraction(r["bound_rel"]) == (2 * Fraction(2) ** 2 * Fraction(2) ** -52
+                                        + Fraction(2) ** -14 * Fraction(2) ** -10
+                                        + Fraction(2) ** -22 * Fraction(2) ** -10)
+    # Variable width from (-31, 0]: no split -> one bin, M 4, u 0, N_bins 1,
+    # t = -20, score 2 + 0 + 20 + 1 = 23: all double.
+    r = oracle.qdot(x, x, 1e-6, opt=_variable(0), want_classes=True)
+    assert r["n_bins"] == 1 and r["t"] == -20 and r["classes"].tolist() == [D] * 4
+    # one split at m = -31 + 16 = -15: (-31,-15] {-18,-30}, (-15,0] {0,-6};
+    # N_bins 2, t = -21; scores 1 + 0 + 21 + 1 = 23 (double), 1 - 15 + 22 = 8
+    # (half)
+    r = oracle.qdot(x, x, 1e-6, opt=_variable(1), want_classes=True)
+    assert r["n_bins"] == 2 and r["t"] == -21 and r["classes"].tolist() == [D, D, H, H]
+    # second split: (-15,0] has the larger term (2 * 2^0): (-15,-7] empty and
+    # (-7,0]; third: (-7,0] -> (-7,-3] {-6} and (-3,0] {0}.  N_bins 3,
+    # t = -22; scores 0 + 0 + 23 = 23 (double), 0 - 3 + 23 = 20 (single),
+    # 1 - 15 + 23 = 9 (half)
+    r2 = oracle.qdot(x, x, 1e-6, opt=_variable(2), want_classes=True)
+    assert r2["n_bins"] == 2 and r2["classes"].tolist() == [D, D, H, H]
+    r = oracle.qdot(x, x, 1e-6, opt=_variable(3), want_classes=True)
+    assert r["n_bins"] == 3 and r["t"] == -22 and r["classes"].tolist() == [D, S, H, H]
+    assert Fraction(r["value"]) == exact
+
+
+def test_binned_selection_meets_the_per_bin_budget_and_the_bound():
+    # On random data: keys of one ranged bin share a class; variable-width
+    # selections use at most s + 1 bins; every non-capped bin's Thm 3.5 term
+    # M_k 2^(u_k - e_max + 1) eps(k) is <= 2^t (checked via bound_rel <=
+    # N_bins 2^t, an exact comparison); the error is within the rigorous bound
+    for seed in range(3):
+        x, y = workloads.log_uniform_pair(4000, 70 + seed)
+        ex = _exact_fraction(x, y)
+        for tol in (1e-2, 1e-6, 1e-12):
+            for opt in (_ranged(2), _ranged(5), _ranged(16), _ranged(64), _variable(0),
+                        _variable(2), _variable(9), _variable(40)):
+                r = oracle.qdot(x, y, tol, opt=opt, want_classes=True, want_keys=True)
+                assert r["status"] == oracle.OK and sum(r["count"]) == len(x)
+                if opt[5] == 1:
+                    w = opt[6]
+                    grp = {}
+                    for kk, c in zip(r["keys"].tolist(), r["classes"].tolist()):
+                        grp.setdefault((kk - r["e_min"]) // w, set()).add(c)
+                    assert all(len(v) == 1 for v in grp.values())
+                else:
+                    assert r["n_bins"] <= opt[6] + 1
+                if not r["flags"] & oracle.F_UNATTAINABLE:
+                    assert Fraction(r["bound_rel"]) <= r["n_bins"] * Fraction(2) ** r["t"]
+                assert abs(Fraction(r["value"]) - ex) <= Fraction(r["bound_rig"])
+
+
+def test_binned_selection_options_and_limits():
+    x, y = workloads.log_uniform_pair(300, 80)
+    for bad in ([0, 0, 0, 0, 0, 1, 0], [0, 0, 0, 0, 0, 3, 1], [0, 0, 0, 1, 0, 1, 4],
+                [0, 0, 0, 0, 1, 2, 4], [0, 0, 0, 0, 0, 2, -1]):
+        assert oracle.qdot(x, y, 1e-6, opt=bad)["status"] == oracle.E_INVAL, bad
+    # single-precision inputs take the binned selection too
+    r = oracle.qdot_f32(x.astype(np.float32), y.astype(np.float32), 1e-4, opt=_ranged(3))
+    assert r["status"] == oracle.OK and r["count"][oracle.DOUBLE] == 0
+    # wide bins may push FP32 leaves below the normal range: still bounded
+    xw, yw = workloads.log_uniform_pair(3000, 81, -60.0, 60.0)
+    ex = _exact_fraction(xw, yw)
+    for opt in (_ranged(300), _variable(1)):
+        r = oracle.qdot(xw, yw, 1e-1, opt=opt)
+        assert abs(Fraction(r["value"]) - ex) <= Fraction(r["bound_rig"])
+
+
+# --------------------------------------------------------------------------
 # Histogram, partition, invariants
 # --------------------------------------------------------------------------
 
