@@ -62,6 +62,26 @@ def measured_traffic(n, kernel):
     return round(k["hbm_bytes_per_launch"]) if k else None
 
 
+def class_mix(results, n, series):
+    """Per-iteration share of components per precision of a solver's qdot
+    results, two per iteration: series maps a name to the index of its first
+    result (then every second one); shares at five points of the run and the
+    mean over it, in the order DOUBLE, SINGLE, HALF, PERF."""
+    out = {}
+    for name, off in series.items():
+        rows = [r["count"] for r in results[off::2]]
+        if not rows:
+            continue
+        k = len(rows)
+        picks = sorted({0, k // 4, k // 2, (3 * k) // 4, k - 1})
+        out[name] = {
+            "iterations": k,
+            "share_at": {str(i): [round(c / n, 6) for c in rows[i]] for i in picks},
+            "mean_share": [round(sum(r[c] for r in rows) / (k * n), 6) for c in range(4)],
+        }
+    return out
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -71,6 +91,52 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def error_report(r, ref_dot, tol):
+    """relerr of one GPU result against a reference dot, with Thm 3.3's
+    hypothesis e_max <= flexp(x.y) and the a-posteriori bound of Thm 3.4."""
+    import oracle
+
+    b = oracle.bound_thm34(r, ref_dot)
+    rel = abs(r["value"] - ref_dot) / abs(ref_dot) if ref_dot else None
+    return {"relerr": rel, "bound_rel": r["bound_rel"], "hyp_e_max_le_flexp": b["hyp"],
+            "bound_thm34_rel": b["bound_thm3_rel"],
+            "within_thm34_bound": rel is not None and rel <= b["bound_thm3_rel"],
+            "within_tol": rel is not None and rel <= tol,
+            "count": r["count"], "flags": r["flags"]}
+
+
+def full_size_errors(x_full, y_full, full_results):
+    """Every full-size GPU result (full_results: {tol: {mode: result}})
+    against the oracle's compensated Dot2 of the whole vectors."""
+    import oracle
+
+    t0 = time.perf_counter()
+    d2 = oracle.dot_dot2(x_full, y_full)
+    t_d2 = time.perf_counter() - t0
+    out = {"reference": "oracle dot_dot2 (Ogita-Rump-Oishi) of all n components",
+           "dot2_seconds": round(t_d2, 3), "dot2": d2}
+    for tl, modes in full_results.items():
+        out[f"tol{tl:g}"] = {m: error_report(r, d2, tl) for m, r in modes.items()}
+    return out
+
+
+def c1_report(x1, y1, tol, gpu_results, latency_us):
+    """The small single qdot (n = 1e5): GPU results against the oracle
+    (counts bit for bit, value within 1e-13 sum |x_i y_i|) and the exact dot,
+    beside its latency per call."""
+    import oracle
+
+    exact = oracle.dot_exact(x1, y1)
+    scale = oracle.abs_dot(x1, y1)
+    out = {"n": len(x1), "tol": tol, "us_per_call_graph_replay_median": latency_us}
+    for mode, r in gpu_results.items():
+        o = oracle.qdot(x1, y1, tol, opt=[0, 0, 0, 1] if mode == "one_pass" else None)
+        out[mode] = {"counts_equal_oracle": r["count"] == o["count"],
+                     "value_diff_over_sum_abs": abs(r["value"] - o["value"]) / scale,
+                     **error_report(r, exact, tol)}
+    return out
 
 
 def cpu_baseline(x_host, y_host, tol, gpu_results, budget_s=12.0):
@@ -222,8 +288,10 @@ def main():
 
     # the other tolerances of the workload, both modes (10 calls each)
     other_tol = {}
+    full_results = {tol: {"two_pass": res, "one_pass": res1}}
     for tl in (1e-3, 1e-10):
         row = {}
+        full_results[tl] = {}
         for name, opt in (("two_pass", None), ("one_pass", s1)):
             for _ in range(2):
                 h.qdot_async(x, y, tl, out, opt=opt)
@@ -233,7 +301,8 @@ def main():
                 h.qdot_async(x, y, tl, out, opt=opt)
             torch.cuda.synchronize()
             row[name + "_gelem_s"] = round(n * 10 / (time.perf_counter() - c0) / 1e9, 3)
-            row[name + "_count"] = q.parse_results(out)[0]["count"]
+            full_results[tl][name] = q.parse_results(out)[0]
+            row[name + "_count"] = full_results[tl][name]["count"]
         other_tol[str(tl)] = row
 
     # guaranteed-eps mode (guard_mode 1, Thm 3.4): on this workload the first
@@ -302,13 +371,16 @@ def main():
     del xf, yf
 
     # one call captured in a HIP graph, replays timed one by one: median
-    def replay_median(opt, reps=25):
+    def replay_median(opt, reps=25, xv=None, yv=None, dst=None):
+        xv = x if xv is None else xv
+        yv = y if yv is None else yv
+        dst = out if dst is None else dst
         gq = torch.cuda.CUDAGraph()
         gs_ = torch.cuda.Stream()
         gs_.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(gs_):
             with torch.cuda.graph(gq, stream=gs_):
-                h.qdot_async(x, y, tol, out, opt=opt)
+                h.qdot_async(xv, yv, tol, dst, opt=opt)
         torch.cuda.synchronize()
         for _ in range(3):
             gq.replay()
@@ -325,6 +397,17 @@ def main():
 
     rep2 = replay_median(None)
     rep1 = replay_median(s1)
+
+    # the small single qdot (n = 1e5, same law, tol 1e-6): a latency case
+    log("small qdot n=1e5: graph replay latency")
+    n1 = 100_000
+    x1h, y1h = workloads.log_uniform_pair(n1, 1)
+    x1d, y1d = torch.from_numpy(x1h).to(dev), torch.from_numpy(y1h).to(dev)
+    c1_lat, c1_res = {}, {}
+    for name, opt in (("two_pass", None), ("one_pass", s1)):
+        c1_lat[name] = round(replay_median(opt, reps=101, xv=x1d, yv=y1d) * 1e3, 2)
+        c1_res[name] = q.parse_results(out)[0]
+    del x1d, y1d
 
     xh = x[: args.cpu_sample].cpu().numpy()
     yh = y[: args.cpu_sample].cpu().numpy()
@@ -354,7 +437,14 @@ def main():
         r = h.cg(A, b, xs, 1e-10, 1e-8, 20000, use)
         cg[name] = {"iters": r["iters"], "status": r["status"],
                     "relres_true": r["relres_true"],
-                    "seconds": round(time.perf_counter() - c0, 3)}
+                    "seconds": round(time.perf_counter() - c0, 3),
+                    "us_per_iter": round((time.perf_counter() - c0) / max(r["iters"], 1) * 1e6,
+                                         2)}
+    # per-iteration class mix of both inner products (a traced re-run):
+    # trace[0] = r0.r0, then p.Ap (2k + 1) and r.r (2k + 2) of iteration k
+    xs = torch.zeros(m * m, dtype=torch.float64, device=dev)
+    rt = h.cg(A, b, xs, 1e-10, 1e-8, 20000, 1, trace=True)
+    cg["class_mix"] = class_mix(rt["trace"], m * m, {"p.Ap": 1, "r.r": 2})
     del A, b
 
     # power method on the 3D Laplacian 128^3, 500 iterations, qdot tol 1e-6
@@ -364,12 +454,19 @@ def main():
     A = q.Csr(rp, col, val, device=dev)
     x0 = workloads.unit_vector(m3 ** 3, 4)
     pm = {}
-    for name, use in (("qdot", 1), ("fp64", 0)):
+    for name, use, opt in (("qdot", 1, None), ("fp64", 0, None), ("qdot_one_pass", 1, s1)):
         xs = torch.from_numpy(x0).to(dev)
+        h.power(A, xs, 5, 1e-6, use, opt=opt, trace=False)  # warm (allocations)
+        xs = torch.from_numpy(x0).to(dev)
+        torch.cuda.synchronize()
         c0 = time.perf_counter()
-        r = h.power(A, xs, 500, 1e-6, use, trace=False)
+        r = h.power(A, xs, 500, 1e-6, use, opt=opt, trace=False)
         pm[name] = {"lambda": r["lambda"], "status": r["status"],
-                    "seconds": round(time.perf_counter() - c0, 3)}
+                    "seconds": round(time.perf_counter() - c0, 4)}
+    xs = torch.from_numpy(x0).to(dev)
+    rt = h.power(A, xs, 500, 1e-6, 1, trace=False, results=True)
+    # results[2k] = x.w (lambda), [2k + 1] = w.w of iteration k
+    pm["class_mix"] = class_mix(rt["results"], m3 ** 3, {"x.w": 0, "w.w": 1})
     lam_max = 6.0 + 6.0 * float(np.cos(np.pi / (m3 + 1)))
     del A
 
@@ -382,6 +479,8 @@ def main():
     np.cumsum(sizes, out=offs[1:])
     btol = np.array([1e-4, 1e-6, 1e-8])[g.integers(0, 3, 4096)]
     total = int(offs[-1])
+    # host copies for the full-size error report of the CPU leg
+    x_full, y_full = x.cpu().numpy(), y.cpu().numpy()
     del x, y
     bx, by = workloads.log_uniform_pair_torch(total, 2025, dev)
     off_d = torch.from_numpy(offs).to(dev)
@@ -497,6 +596,10 @@ def main():
 
     log(f"CPU oracle on a sample of {args.cpu_sample}")
     cpu = cpu_baseline(xh, yh, tol, gpu_sample)
+    log("oracle checks: full-size errors vs Dot2, small-qdot parity")
+    full_err = full_size_errors(x_full, y_full, full_results)
+    del x_full, y_full
+    c1 = c1_report(x1h, y1h, tol, c1_res, c1_lat)
 
     value = n * K / wall / 1e9
     line = {
@@ -563,6 +666,8 @@ def main():
                 "value": res1["value"],
                 "relerr_vs_fp64_dot": abs(res1["value"] - dot64) / abs(dot64) if dot64 else None,
             },
+            "full_size_errors_vs_oracle_dot2": full_err,
+            "small_qdot_1e5": c1,
             "torch_dot_value": float(tdot.item()),
             "cg_poisson2d_1024": cg,
             "batched_ragged_4096": batched,

@@ -85,7 +85,13 @@ extern "C" {
 /* Zero-initialised = defaults. */
 typedef struct qdot_options {
     /* 0: key = exponent of the product x_i*y_i (Def. 3.1, the theorems);
-     * 1: key = E(x_i) + E(y_i) (Alg. 2, exponent preprocessing line). */
+     * 1: key = E(x_i) + E(y_i) (Alg. 2, exponent preprocessing line), with
+     *    the key taken as the bin's exponent u_k in the score and in
+     *    bound_rel, as Alg. 2 is printed.  A bin of key k then holds
+     *    products up to 2^(k+2), not 2^(k+1) as Thm 3.2 assumes, so under
+     *    key_mode 1 bound_rel (and bound_abs) may understate the Thm 3.3
+     *    bound of those bins by up to a factor 2 and is not an upper bound
+     *    of the error. */
     int32_t key_mode;
     /* 0: score with eps / N_bins (experiments of Sec. 4.1), so that Thm 3.5
      *    bounds the relative error by eps;  1: score with eps itself. */
@@ -434,6 +440,12 @@ QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, dou
  * x = w / sqrt(c), with both dots by qdot at qtol when use_qdot != 0.
  * x: device FP64[n], unit vector on entry, last iterate on exit.
  * lambda (host): last lambda.  lambda_trace: NULL or device FP64[iters].
+ * trace: NULL or device qdot_result[2 * iters]: with use_qdot != 0, the
+ * results of iteration k's two qdot calls, lambda = qdot(x, w) at 2k and
+ * c = qdot(w, w) at 2k + 1 (their counts are the per-precision component
+ * shares the APM study of Sec. 4.3 plots); not written when use_qdot is 0.
+ * After a breakdown, entries past the iteration that broke down are
+ * unspecified.
  * opt: as qdot_async (the one-pass and guaranteed modes included).  With
  * the two-pass qdot the two inner products of an iteration are computed
  * side by side: one pass-1 kernel reads x and w once for both, and the
@@ -446,7 +458,7 @@ QDOT_API int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, dou
 QDOT_API int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x,
                    int32_t iters, double qtol, int32_t use_qdot,
                    const qdot_options *opt, void *stream, double *lambda,
-                   double *lambda_trace);
+                   double *lambda_trace, qdot_result *trace);
 
 #ifdef __cplusplus
 }

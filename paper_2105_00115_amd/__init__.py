@@ -132,7 +132,7 @@ SIGNATURES = [
     ("qdot_cg", _i32, [_vp, _CSR, _vp, _vp, _d, _d, _i32, _i32, _OPT, _vp,
                        C.POINTER(QdotCgResult), _vp]),
     ("qdot_power", _i32, [_vp, _CSR, _vp, _i32, _d, _i32, _OPT, _vp,
-                          C.POINTER(_d), _vp]),
+                          C.POINTER(_d), _vp, _vp]),
 ]
 
 _lib = None
@@ -533,17 +533,23 @@ class Qdot:
         return d
 
     def power(self, A: Csr, x, iters, qtol, use_qdot, opt=None, trace=True,
-              stream=None) -> dict:
+              results=False, stream=None) -> dict:
+        """trace: return every lambda; results: also every qdot result
+        (d["results"][2k] is lambda's, [2k + 1] c's, of iteration k)."""
         import torch
         _check_vec(x, "x")
         tr = torch.zeros(max(iters, 1), dtype=torch.float64, device=x.device) if trace else None
+        rs = (torch.zeros(max(2 * iters, 1) * RESULT_BYTES, dtype=torch.uint8, device=x.device)
+              if results else None)
         lam = C.c_double()
         st = lib().qdot_power(self._h, C.byref(A.c), _ptr(x), int(iters), float(qtol),
                               int(use_qdot), _opts(opt), _stream(stream), C.byref(lam),
-                              _ptr(tr))
+                              _ptr(tr), _ptr(rs))
         if st not in (OK, E_BREAKDOWN):
             self._raise(st, "qdot_power")
         d = {"status": st, "lambda": lam.value}
         if trace:
             d["trace"] = tr[:iters].cpu().numpy()
+        if results:
+            d["results"] = parse_results(rs[: 2 * iters * RESULT_BYTES])
         return d

@@ -306,7 +306,7 @@ int32_t qdot_spmv_async(qdot_handle *h, const qdot_csr *A, const double *x, doub
 
 int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, double qtol,
                    int32_t use_qdot, const qdot_options *opt, void *stream, double *lambda,
-                   double *lambda_trace)
+                   double *lambda_trace, qdot_result *trace)
 {
     if (!h) return QDOT_E_INVAL;
     if (!csr_ok(A) || A->n == 0 || !x || iters < 0) return fail(h, QDOT_E_INVAL, "bad argument");
@@ -353,16 +353,19 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
         const double *src = k == 0 ? x : wbuf[(k - 1) & 1];
         hipLaunchKernelGGL(k_pm_spmv, dim3(sg), dim3(BLOCK), 0, s, n, A->rowptr, A->col, A->val,
                            src, w, x, ctl, lv, lr, cv, cr, lambda_trace, k);
+        // the qdot results of iteration k: straight into the caller's trace
+        // when one is given, else the handle's two slots
+        qdot_result *ra = trace && use_qdot ? trace + 2 * (int64_t)k : h->res_ring;
+        qdot_result *rb = ra + 1;
         if (paired) {
-            ok(launch_qdot_pair(L, L2, x, w, n, qtol, o, h->res_ring, h->res_ring + 1));
-            lv = &h->res_ring[0].value;
-            lr = h->res_ring;
-            cv = &h->res_ring[1].value;
-            cr = h->res_ring + 1;
+            ok(launch_qdot_pair(L, L2, x, w, n, qtol, o, ra, rb));
+            lv = &ra->value;
+            lr = ra;
+            cv = &rb->value;
+            cr = rb;
         } else {
-            ok(enqueue_dot(h, L, x, w, n, use_qdot, qtol, o, h->res_ring, h->dres, &lv, &lr));
-            ok(enqueue_dot(h, L, w, w, n, use_qdot, qtol, o, h->res_ring + 1, h->dres + 1, &cv,
-                           &cr));
+            ok(enqueue_dot(h, L, x, w, n, use_qdot, qtol, o, ra, h->dres, &lv, &lr));
+            ok(enqueue_dot(h, L, w, w, n, use_qdot, qtol, o, rb, h->dres + 1, &cv, &cr));
         }
         ok(hipGetLastError());
         if ((k + 1) % 64 == 0) {

@@ -8,7 +8,9 @@ two inner products lands near the stopping threshold.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -388,6 +390,49 @@ def test_full_size_cg_poisson_1024(h):
         assert res[use]["status"] == q.OK
         assert res[use]["relres_true"] < 2e-10
     assert res[1]["iters"] == res[0]["iters"], (res[1]["iters"], res[0]["iters"])
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.mark.timeout(300)
+def test_full_size_power_trace_matches_oracle(h):
+    """The power-method workload at its full size (3D Laplacian 128^3, unit
+    N(0,1) start seed 4, 500 iterations, both inner products by qdot at tol
+    1e-6) against the oracle's run stored by make_solver_goldens.py: every
+    lambda within rtol 1e-9 (the FP64 sums of the two sides are taken in
+    other orders, so x_k may differ in its last bits), the per-class counts
+    of both inner products of iteration 0 bit for bit (same x_0, and w_0 =
+    A x_0 is formed by the same rounded operations on both sides), and those
+    of every 50th iteration within 1e-5 n in total.  The FP64-dot run
+    against the oracle's exact-dot run, lambda within rtol 1e-9."""
+    m, iters = 128, 500
+    with open(os.path.join(GOLDEN, "power_laplacian3d_128.json")) as f:
+        gold = json.load(f)
+    assert gold["iters"] == iters and gold["qtol"] == 1e-6
+    print(f"[gpu-case] power Laplacian {m}^3 trace vs oracle", flush=True)
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, val)
+    x0 = workloads.unit_vector(m ** 3, 4)
+    r = h.power(A, dev(x0), iters, 1e-6, 1, results=True)
+    assert r["status"] == q.OK
+    lam_o = np.array([float.fromhex(v) for v in gold["qdot"]["lambda_hex"]])
+    np.testing.assert_allclose(r["trace"], lam_o, rtol=1e-9, atol=0)
+    n = m ** 3
+    for k, (ca, cb) in gold["qdot"]["counts_every_50"].items():
+        k = int(k)
+        ga, gb = r["results"][2 * k]["count"], r["results"][2 * k + 1]["count"]
+        if k == 0:
+            assert ga == ca and gb == cb, (k, ga, ca, gb, cb)
+        else:
+            diff = sum(abs(a - b) for a, b in zip(ga + gb, ca + cb))
+            assert diff <= 1e-5 * n, (k, ga, ca, gb, cb)
+    r0 = h.power(A, dev(x0), iters, 1e-6, 0)
+    assert r0["status"] == q.OK
+    lam_e = np.array([float.fromhex(v) for v in gold["exact_dot"]["lambda_hex"]])
+    np.testing.assert_allclose(r0["trace"], lam_e, rtol=1e-9, atol=0)
+    print(f"[gpu-case] |lambda_500 qdot - oracle| = {abs(r['lambda'] - lam_o[-1]):.3e}, "
+          f"|qdot - FP64| = {abs(r['lambda'] - r0['lambda']):.3e}", flush=True)
 
 
 @pytest.mark.timeout(300)
