@@ -431,10 +431,10 @@ def main():
     A = q.Csr(rp, col, val, device=dev)
     b = torch.from_numpy(workloads.normal_vector(m * m, 3)).to(dev)
     cg = {}
-    for name, use in (("qdot", 1), ("fp64", 0)):
+    for name, use, opt in (("qdot", 1, None), ("fp64", 0, None), ("qdot_one_pass", 1, s1)):
         xs = torch.zeros(m * m, dtype=torch.float64, device=dev)
         c0 = time.perf_counter()
-        r = h.cg(A, b, xs, 1e-10, 1e-8, 20000, use)
+        r = h.cg(A, b, xs, 1e-10, 1e-8, 20000, use, opt=opt)
         cg[name] = {"iters": r["iters"], "status": r["status"],
                     "relres_true": r["relres_true"],
                     "seconds": round(time.perf_counter() - c0, 3),
@@ -656,8 +656,7 @@ def main():
                 "gelem_s": round(n * K / wall1 / 1e9, 3),
                 "ms_per_call": round(wall1 / K * 1e3, 4),
                 "kernel_ms": {"k_s1_scan": round(t1p["scan_ms"] / t1p["qdot_calls"], 4),
-                              "k_cut": round(t1p["cut_ms"] / t1p["qdot_calls"], 4),
-                              "k_s1_fin": round(t1p["fin_ms"] / t1p["qdot_calls"], 4)},
+                              "k_s1_cutfin": round(t1p["cut_ms"] / t1p["qdot_calls"], 4)},
                 "scan_frac_hbm": round(alg_bytes / (t1p["scan_ms"] / t1p["qdot_calls"] * 1e-3)
                                        / 1e9 / HBM_PEAK_GBS, 4),
                 "scan_traffic": measured_traffic(n, "k_s1_scan"),

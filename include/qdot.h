@@ -144,6 +144,23 @@ typedef struct qdot_options {
      *    entry points, qdot_power and qdot_cg, QDOT_E_INVAL elsewhere (the
      *    batched entry points). */
     int32_t guard_mode;
+    /* Binning strategy (Sec. 3.2), the partition of [e_min, e_max] into the
+     * bins that are scored:
+     * 0: exact bins, one exponent each (the default; bin_param unused);
+     * 1: ranged bins of width w = bin_param (1..4196), (u_k - w, u_k] with
+     *    u_k = e_min + k w - 1, k = 1, 2, ...;
+     * 2: variable-width bins from at most s = bin_param (0..4196) splits:
+     *    from the one bin (e_min - 1, e_max], each split halves, at
+     *    l + ceil((u - l) / 2), the non-empty bin of more than one exponent
+     *    whose Thm 3.2 term M_k 2^(u_k) is largest (ties to the higher u_k).
+     * A bin is scored with its upper exponent u_k (eq. bin-score-def), its
+     * class holds for all its keys, N_bins counts the non-empty bins and the
+     * Thm 3.3 term of a bin is M_k 2^(u_k - e_max + 1) eps(class).  Modes 1
+     * and 2 need accum_mode 0 and guard_mode 0 and are accepted by
+     * qdot_async, qdot, qdot_classes_async and the
+     * qdot_f32 entry points; QDOT_E_INVAL elsewhere. */
+    int32_t bin_mode;
+    int32_t bin_param;
 } qdot_options;
 
 /* ---- per-call result ------------------------------------------------- */
@@ -215,6 +232,12 @@ typedef struct qdot_tune {
     int32_t acc_unroll;
     int32_t onepass_blocks_per_cu; /* one-pass scan (accum_mode 1), 1..16 */
     int32_t onepass_unroll;
+    int32_t acc_form;    /* accumulate pass: 0 every candidate leaf formed in
+                            place, 1 kept components compacted per wave and
+                            their leaves formed 64 at a time (same tile
+                            sums bit for bit) */
+    int32_t hist_copies; /* global histogram copies the scan blocks spread
+                            their merges over: 1, 2, 4 or 8 */
 } qdot_tune;
 
 /* Tuning is kept per size bucket: n < 2^16, < 2^20, < 2^24, >= 2^24. */
@@ -245,8 +268,10 @@ QDOT_API int32_t qdot_get_tune(const qdot_handle *h, int32_t bucket, qdot_tune *
 
 /* Load tuned configurations from a text file written by the autotuner: one
  * line per bucket, "bucket scan_bpc scan_unroll acc_bpc acc_unroll
- * [onepass_bpc onepass_unroll]" (without the last two the bucket's one-pass
- * shape is left as it is), '#' starts a comment.  Invalid lines are
+ * [onepass_bpc onepass_unroll [acc_form hist_copies]]" (fields left out keep
+ * the bucket's current values), and optionally one line "batch
+ * blocks_per_cu chunk cg_rows_per_block cg_gang_max" (qdot_batch_tune);
+ * '#' starts a comment.  Invalid lines are
  * rejected with QDOT_E_INVAL and leave the handle unchanged.  qdot_create
  * also loads the file named by the environment variable QDOT_TUNE_FILE when
  * it is set. */
@@ -258,8 +283,8 @@ QDOT_API int32_t qdot_load_tune(qdot_handle *h, const char *path);
  * qdot_timing_read synchronises the recorded events and returns the summed
  * durations in milliseconds of the scan, cutoff, accumulate and finalize
  * kernels of qdot (ms[0..3]; with guard_mode 1, ms[3] also covers the guard
- * stages and the second sweep; in the one-pass mode ms[2] is 0 and ms[3]
- * is the pick) and of the FP64 dot (ms[4], both of its kernels), the number
+ * stages and the second sweep; in the one-pass mode ms[1] is the single
+ * cutoff-and-pick kernel and ms[2], ms[3] are 0) and of the FP64 dot (ms[4], both of its kernels), the number
  * of qdot and FP64-dot calls timed (calls[0..1]), then clears the record. */
 QDOT_API int32_t qdot_timing_enable(qdot_handle *h, int32_t enable);
 QDOT_API int32_t qdot_timing_read(qdot_handle *h, double ms[5], int32_t calls[2]);
@@ -355,12 +380,37 @@ QDOT_API int32_t qdot_fp64_dot_async(qdot_handle *h, const double *x, const doub
  * one kernel: no allocation, no memset, no host sync, graph-capturable.
  * Up to 8 layouts are kept per handle.  Calls on one handle must be ordered
  * on one stream.  Host-side argument errors, and guard_mode 1, return
- * QDOT_E_INVAL. */
+ * QDOT_E_INVAL.  The pass-2 chunks of a large instance wait for its cutoff
+ * with a spin limit; a chunk that waits past it gives that instance status
+ * QDOT_E_DEVICE (the work order makes the wait end long before). */
 QDOT_API int32_t qdot_batched_async(qdot_handle *h, const double *x_cat,
                                     const double *y_cat, const int64_t *offsets,
                                     const int64_t *host_offsets, const double *tols,
                                     int32_t B, const qdot_options *opt, void *stream,
                                     qdot_result *dev_out);
+
+/* Launch shape of the batched launch (qdot_batched_async,
+ * qdot_batch_run_async, qdot_cg_batched).  Chosen by the autotuner; the
+ * defaults are {4, 131072, 16384, 16}. */
+typedef struct qdot_batch_tune {
+    int32_t blocks_per_cu;     /* persistent grid: blocks per CU, 1..16 (the
+                                  resident ones are capped by occupancy) */
+    int32_t chunk;             /* components per pass-1 / pass-2 chunk of a
+                                  large instance, and the largest instance one
+                                  block takes whole: 2^13..2^22, a multiple of
+                                  2048 */
+    int32_t cg_rows_per_block; /* a CG system of n rows gets ceil(n / this)
+                                  gang blocks, >= 1024 ... */
+    int32_t cg_gang_max;       /* ... and at most this many, 1..512 */
+} qdot_batch_tune;
+
+/* Set (cfg NULL: defaults) or read the handle's batched launch shape.
+ * Setting it frees the handle's cached batch plans (after a device sync);
+ * out-of-range values return QDOT_E_INVAL and change nothing.  No value of
+ * it changes a result: instances are split along whole 2048-component
+ * groups, so every 64-element tile and class is the same. */
+QDOT_API int32_t qdot_set_batch_tune(qdot_handle *h, const qdot_batch_tune *cfg);
+QDOT_API int32_t qdot_get_batch_tune(const qdot_handle *h, qdot_batch_tune *cfg);
 
 /* Plan a batched layout ahead of time (e.g. before capturing
  * qdot_batched_async into a graph).  Synchronous. */
@@ -375,7 +425,8 @@ QDOT_API int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets,
  * (systems: host array of S descriptors; S may be 0) run in one persistent
  * kernel launch.  Each CG system follows qdot_cg on that system alone (Alg.
  * 4 with the same stopping rule and the same inner products); it is solved
- * by a gang of up to 16 blocks (one per 16384 rows) that meet at barriers,
+ * by a gang of blocks (one per cg_rows_per_block rows, at most cg_gang_max:
+ * qdot_batch_tune) that meet at barriers,
  * gangs are formed before the qdot work items are handed out, largest
  * system first.  dev_cg_out: device qdot_cg_result[S].  Planning happens on
  * the first call with a new layout (offsets and system descriptors,

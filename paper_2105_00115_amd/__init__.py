@@ -32,7 +32,7 @@ W = KMAX - KMIN + 1
 class QdotOptions(C.Structure):
     _fields_ = [("key_mode", C.c_int32), ("score_mode", C.c_int32),
                 ("boundary_mode", C.c_int32), ("accum_mode", C.c_int32),
-                ("guard_mode", C.c_int32)]
+                ("guard_mode", C.c_int32), ("bin_mode", C.c_int32), ("bin_param", C.c_int32)]
 
 
 class QdotResult(C.Structure):
@@ -85,7 +85,13 @@ CG_RESULT_BYTES = C.sizeof(QdotCgResult)
 class QdotTune(C.Structure):
     _fields_ = [("scan_blocks_per_cu", C.c_int32), ("scan_unroll", C.c_int32),
                 ("acc_blocks_per_cu", C.c_int32), ("acc_unroll", C.c_int32),
-                ("onepass_blocks_per_cu", C.c_int32), ("onepass_unroll", C.c_int32)]
+                ("onepass_blocks_per_cu", C.c_int32), ("onepass_unroll", C.c_int32),
+                ("acc_form", C.c_int32), ("hist_copies", C.c_int32)]
+
+
+class QdotBatchTune(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("chunk", C.c_int32),
+                ("cg_rows_per_block", C.c_int32), ("cg_gang_max", C.c_int32)]
 
 
 TUNE_BUCKETS = 4  # n < 2^16, < 2^20, < 2^24, >= 2^24
@@ -121,6 +127,8 @@ SIGNATURES = [
     ("qdot_fp64_dot_async", _i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
     ("qdot_batched_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32, _OPT,
                                   _vp, _vp]),
+    ("qdot_set_batch_tune", _i32, [_vp, C.POINTER(QdotBatchTune)]),
+    ("qdot_get_batch_tune", _i32, [_vp, C.POINTER(QdotBatchTune)]),
     ("qdot_batched_plan", _i32, [_vp, C.POINTER(_i64), _i32]),
     ("qdot_batch_run_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32,
                                     C.POINTER(QdotCgSystem), _i32, _OPT, _vp, _vp, _vp]),
@@ -292,9 +300,11 @@ class Qdot:
         return d.value, c.value
 
     def set_tune(self, bucket: int, scan_bpc: int, scan_unroll: int, acc_bpc: int,
-                 acc_unroll: int, onepass_bpc: int = 4, onepass_unroll: int = 1):
+                 acc_unroll: int, onepass_bpc: int = 4, onepass_unroll: int = 1,
+                 acc_form: int = 0, hist_copies: int = 8):
         """bucket -1 sets all size buckets."""
-        cfg = QdotTune(scan_bpc, scan_unroll, acc_bpc, acc_unroll, onepass_bpc, onepass_unroll)
+        cfg = QdotTune(scan_bpc, scan_unroll, acc_bpc, acc_unroll, onepass_bpc, onepass_unroll,
+                       acc_form, hist_copies)
         st = lib().qdot_set_tune(self._h, int(bucket), C.byref(cfg))
         if st != OK:
             self._raise(st, "qdot_set_tune")
@@ -308,7 +318,28 @@ class Qdot:
         if st != OK:
             raise QdotError(st, "qdot_get_tune")
         return (t.scan_blocks_per_cu, t.scan_unroll, t.acc_blocks_per_cu, t.acc_unroll,
-                t.onepass_blocks_per_cu, t.onepass_unroll)
+                t.onepass_blocks_per_cu, t.onepass_unroll, t.acc_form, t.hist_copies)
+
+    def set_batch_tune(self, blocks_per_cu=None, chunk=None, cg_rows_per_block=None,
+                       cg_gang_max=None):
+        """Launch shape of the batched launch; None keeps a field, no
+        argument at all restores the defaults."""
+        if all(v is None for v in (blocks_per_cu, chunk, cg_rows_per_block, cg_gang_max)):
+            st = lib().qdot_set_batch_tune(self._h, None)
+        else:
+            cur = self.get_batch_tune()
+            cfg = QdotBatchTune(*[cur[i] if v is None else int(v) for i, v in enumerate(
+                (blocks_per_cu, chunk, cg_rows_per_block, cg_gang_max))])
+            st = lib().qdot_set_batch_tune(self._h, C.byref(cfg))
+        if st != OK:
+            self._raise(st, "qdot_set_batch_tune")
+
+    def get_batch_tune(self):
+        t = QdotBatchTune()
+        st = lib().qdot_get_batch_tune(self._h, C.byref(t))
+        if st != OK:
+            raise QdotError(st, "qdot_get_batch_tune")
+        return (t.blocks_per_cu, t.chunk, t.cg_rows_per_block, t.cg_gang_max)
 
     def load_tune(self, path: str):
         st = lib().qdot_load_tune(self._h, os.fsencode(path))

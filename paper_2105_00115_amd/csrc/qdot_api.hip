@@ -21,7 +21,7 @@ int32_t hip_fail(qdot_handle *h, hipError_t e, const char *where)
     return fail(h, QDOT_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-static int bucket_of(int64_t n)
+int bucket_of(int64_t n)
 {
     return n < ((int64_t)1 << 16) ? 0 : n < ((int64_t)1 << 20) ? 1 : n < ((int64_t)1 << 24) ? 2 : 3;
 }
@@ -32,41 +32,50 @@ qdot_tune default_tune(int bucket)
     // on the same block -> chunk mapping so the second pass finds the data
     // in the same XCD's L2
     // in the same XCD's L2; the one-pass scan wants more resident blocks
-    if (bucket < 3) return qdot_tune{2, 1, 2, 1, 4, 1};
-    return qdot_tune{2, 1, 2, 2, 4, 1};
+    if (bucket < 3) return qdot_tune{2, 1, 2, 1, 4, 1, 0, HIST_COPIES};
+    return qdot_tune{2, 1, 2, 2, 4, 1, 0, HIST_COPIES};
 }
 
 bool tune_ok(const qdot_tune &t)
 {
     auto u_ok = [](int u) { return u == 1 || u == 2 || u == 4; };
     auto b_ok = [](int b) { return b >= 1 && b <= 16; };
+    auto c_ok = [](int c) { return c == 1 || c == 2 || c == 4 || c == HIST_COPIES; };
     return b_ok(t.scan_blocks_per_cu) && b_ok(t.acc_blocks_per_cu) &&
            b_ok(t.onepass_blocks_per_cu) && u_ok(t.scan_unroll) && u_ok(t.acc_unroll) &&
-           u_ok(t.onepass_unroll);
+           u_ok(t.onepass_unroll) && (t.acc_form == 0 || t.acc_form == 1) &&
+           c_ok(t.hist_copies);
 }
 
-Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n, bool single)
+Launch make_launch_tuned(const qdot_tune &t, int num_cus, Ws *ws, double *partials,
+                         int partial_cap, double *s1tab, hipStream_t s, bool single)
 {
-    const qdot_tune &t = h->tune[bucket_of(n)];
     // single-precision inputs: a group is half the bytes, so twice the
     // blocks per CU (at most 8; the kernels also double the groups in
     // flight), which measured fastest for both passes on 2^27 floats
     const int f = single ? 2 : 1;
     Launch L;
     L.stream = s;
-    L.ws = h->ws;
-    L.partials = h->partials;
-    L.partial_cap = h->partial_blocks;
-    L.scan_blocks = std::min(MAX_GRID, std::min(8, f * t.scan_blocks_per_cu) * h->num_cus);
+    L.ws = ws;
+    L.partials = partials;
+    L.partial_cap = partial_cap;
+    L.scan_blocks = std::min(MAX_GRID, std::min(8, f * t.scan_blocks_per_cu) * num_cus);
     L.scan_unroll = t.scan_unroll;
-    L.acc_blocks = std::min(h->partial_blocks,
-                            std::min(8, f * t.acc_blocks_per_cu) * h->num_cus);
+    L.acc_blocks = std::min(partial_cap, std::min(8, f * t.acc_blocks_per_cu) * num_cus);
     L.acc_unroll = t.acc_unroll;
-    L.s1_blocks = std::min(MAX_GRID, t.onepass_blocks_per_cu * h->num_cus);
+    L.s1_blocks = std::min(MAX_GRID, t.onepass_blocks_per_cu * num_cus);
     L.s1_unroll = t.onepass_unroll;
-    L.s1tab = h->s1tab;
+    L.s1tab = s1tab;
+    L.acc_form = t.acc_form;
+    L.hist_copies = t.hist_copies;
     L.ev = nullptr;
     return L;
+}
+
+Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n, bool single)
+{
+    return make_launch_tuned(h->tune[bucket_of(n)], h->num_cus, h->ws, h->partials,
+                             h->partial_blocks, h->s1tab, s, single);
 }
 
 hipEvent_t *take_events(qdot_handle *h, int kind)
@@ -88,10 +97,17 @@ bool options_ok(const qdot_options &o)
 {
     // the guaranteed mode bins on the exponent of the product (the theorems'
     // bins) and repeats pass 2, so it needs key_mode 0 and accum_mode 0
+    // the other binning strategies select once, for the two-pass reading
+    const bool bins_ok =
+        o.bin_mode == 0 ||
+        ((o.bin_mode == 1 ? (o.bin_param >= 1 && o.bin_param <= W)
+                          : o.bin_mode == 2 && o.bin_param >= 0 && o.bin_param <= W) &&
+         o.accum_mode == 0 && o.guard_mode == 0);
     return (o.key_mode == 0 || o.key_mode == 1) && (o.score_mode == 0 || o.score_mode == 1) &&
            (o.boundary_mode == 0 || o.boundary_mode == 1) &&
            (o.accum_mode == 0 || o.accum_mode == 1) &&
-           (o.guard_mode == 0 || (o.guard_mode == 1 && o.key_mode == 0 && o.accum_mode == 0));
+           (o.guard_mode == 0 || (o.guard_mode == 1 && o.key_mode == 0 && o.accum_mode == 0)) &&
+           bins_ok;
 }
 
 static int ceil_log2_host(int64_t v)
@@ -123,22 +139,38 @@ bool s1_admissible(int64_t n, double tol, const qdot_options &o)
 }
 
 template <class T>
+int32_t qdot_args(const T *x, const T *y, int64_t n, double tol, const qdot_options *opt,
+                  qdot_options &o, const char **msg)
+{
+    *msg = "";
+    if (n < 0) return *msg = "n < 0", QDOT_E_INVAL;
+    if (n > 0 && (!x || !y)) return *msg = "NULL vector with n > 0", QDOT_E_INVAL;
+    if (((uintptr_t)x | (uintptr_t)y) & (sizeof(T) - 1))
+        return *msg = "vectors not aligned to their element size", QDOT_E_INVAL;
+    if (!(tol > 0.0) || !std::isfinite(tol))
+        return *msg = "tol must be finite and > 0", QDOT_E_INVAL;
+    std::memset(&o, 0, sizeof o);
+    if (opt) o = *opt;
+    if (!options_ok(o)) return *msg = "unknown option value", QDOT_E_INVAL;
+    if (o.accum_mode == 1 && !s1_admissible(n, tol, o))
+        return *msg = "accum_mode 1 needs n <= 2^30 and a tolerance whose "
+                      "kept bins fit the one-pass window",
+               QDOT_E_INVAL;
+    return QDOT_OK;
+}
+template int32_t qdot_args<double>(const double *, const double *, int64_t, double,
+                                   const qdot_options *, qdot_options &, const char **);
+template int32_t qdot_args<float>(const float *, const float *, int64_t, double,
+                                  const qdot_options *, qdot_options &, const char **);
+
+template <class T>
 static int32_t check_qdot_args(qdot_handle *h, const T *x, const T *y, int64_t n, double tol,
                                const qdot_options *opt, qdot_options &o)
 {
     if (!h) return QDOT_E_INVAL;
-    if (n < 0) return fail(h, QDOT_E_INVAL, "n < 0");
-    if (n > 0 && (!x || !y)) return fail(h, QDOT_E_INVAL, "NULL vector with n > 0");
-    if (((uintptr_t)x | (uintptr_t)y) & (sizeof(T) - 1))
-        return fail(h, QDOT_E_INVAL, "vectors not aligned to their element size");
-    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(h, QDOT_E_INVAL, "tol must be finite and > 0");
-    std::memset(&o, 0, sizeof o);
-    if (opt) o = *opt;
-    if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
-    if (o.accum_mode == 1 && !s1_admissible(n, tol, o))
-        return fail(h, QDOT_E_INVAL, "accum_mode 1 needs n <= 2^30 and a tolerance whose "
-                                     "kept bins fit the one-pass window");
-    return QDOT_OK;
+    const char *msg;
+    const int32_t st = qdot_args(x, y, n, tol, opt, o, &msg);
+    return st == QDOT_OK ? st : fail(h, st, msg);
 }
 
 }  // namespace qd
@@ -227,7 +259,8 @@ int32_t qdot_set_tune(qdot_handle *h, int32_t bucket, const qdot_tune *cfg)
         if (bucket != -1 && b != bucket) continue;
         const qdot_tune t = cfg ? *cfg : default_tune(b);
         if (!tune_ok(t))
-            return fail(h, QDOT_E_INVAL, "tune out of range (blocks per CU 1..16, unroll 1/2/4)");
+            return fail(h, QDOT_E_INVAL, "tune out of range (blocks per CU 1..16, unroll "
+                                         "1/2/4, acc_form 0/1, hist_copies 1/2/4/8)");
         h->tune[b] = t;
     }
     return QDOT_OK;
@@ -247,16 +280,30 @@ int32_t qdot_load_tune(qdot_handle *h, const char *path)
     if (!f) return fail(h, QDOT_E_INVAL, std::string("cannot open tune file ") + path);
     qdot_tune t[QDOT_TUNE_BUCKETS];
     for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) t[b] = h->tune[b];
+    qdot_batch_tune bt;
+    (void)qdot_get_batch_tune(h, &bt);
+    bool have_batch = false;
     char line[256];
     bool ok = true;
     while (ok && std::fgets(line, sizeof line, f)) {
         char *hash = std::strchr(line, '#');
         if (hash) *hash = 0;
-        int b = -1, v[6] = {0, 0, 0, 0, 0, 0};
-        const int got = std::sscanf(line, "%d %d %d %d %d %d %d", &b, &v[0], &v[1], &v[2], &v[3],
-                                    &v[4], &v[5]);
+        // "batch blocks_per_cu chunk cg_rows_per_block cg_gang_max"
+        int bv[4];
+        if (std::sscanf(line, " batch %d %d %d %d", &bv[0], &bv[1], &bv[2], &bv[3]) == 4) {
+            bt = qdot_batch_tune{bv[0], bv[1], bv[2], bv[3]};
+            have_batch = true;
+            continue;
+        }
+        if (std::strstr(line, "batch")) {
+            ok = false;
+            continue;
+        }
+        int b = -1, v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &b, &v[0], &v[1], &v[2],
+                                    &v[3], &v[4], &v[5], &v[6], &v[7]);
         if (got <= 0) continue;  // blank or comment
-        if ((got != 5 && got != 7) || b < 0 || b >= QDOT_TUNE_BUCKETS) {
+        if ((got != 5 && got != 7 && got != 9) || b < 0 || b >= QDOT_TUNE_BUCKETS) {
             ok = false;
             continue;
         }
@@ -265,15 +312,25 @@ int32_t qdot_load_tune(qdot_handle *h, const char *path)
         c.scan_unroll = v[1];
         c.acc_blocks_per_cu = v[2];
         c.acc_unroll = v[3];
-        if (got == 7) {
+        if (got >= 7) {
             c.onepass_blocks_per_cu = v[4];
             c.onepass_unroll = v[5];
+        }
+        if (got == 9) {
+            c.acc_form = v[6];
+            c.hist_copies = v[7];
         }
         if (!tune_ok(c)) ok = false;
         else t[b] = c;
     }
     std::fclose(f);
     if (!ok) return fail(h, QDOT_E_INVAL, std::string("malformed tune file ") + path);
+    qdot_batch_tune cur;
+    (void)qdot_get_batch_tune(h, &cur);
+    if (have_batch && std::memcmp(&cur, &bt, sizeof bt) != 0) {
+        const int32_t st = qdot_set_batch_tune(h, &bt);
+        if (st != QDOT_OK) return st;
+    }
     for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) h->tune[b] = t[b];
     return QDOT_OK;
 }

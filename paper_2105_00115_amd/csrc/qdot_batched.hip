@@ -2,10 +2,10 @@
 //
 // The host plans a work queue once per offsets layout:
 //   P1    pass-1 chunks of the large instances: an instance of n components
-//         has nc = ceil(n / CH) chunks, chunk c taking the GROUP-sized
+//         has nc = ceil(n / chunk) chunks, chunk c taking the GROUP-sized
 //         component groups c, c + nc, c + 2 nc, ... so that the blocks on
 //         one instance read neighbouring addresses at any moment,
-//   SMALL runs of whole small instances (n <= SMALL_MAX each), grouped so
+//   SMALL runs of whole small instances (n <= chunk each), grouped so
 //         that sum(n + SMALL_COST0) stays within SMALL_GROUP per item (the
 //         fixed term stands for the latency chain of one instance), each
 //         instance done start to finish by one block with a block-local
@@ -14,7 +14,8 @@
 // in that order.  Blocks take items from a global ticket.  The block that
 // finishes the last P1 chunk of a large instance runs that instance's cutoff
 // and publishes its class table with release semantics; P2 chunks acquire
-// that flag before they start.  Every P1 item is dequeued before any P2
+// that flag before they start (a wait past the spin limit gives up and
+// marks the instance QDOT_E_DEVICE).  Every P1 item is dequeued before any P2
 // item and a P1 item never waits, so a waiting block only ever waits for
 // work that a running block holds: the launch cannot deadlock, whatever the
 // number of resident blocks.  The block that finishes the last P2 chunk of
@@ -35,15 +36,15 @@
 
 namespace qd {
 
-constexpr int64_t CH = 131072;        // components per P1 / P2 chunk
-constexpr int64_t SMALL_MAX = CH;     // instances up to this size: one block
+// Components per P1 / P2 chunk, and the largest instance one block takes
+// whole (SMALL), is the handle's batch_chunk (default 131072).
 constexpr int64_t SMALL_COST0 = 8192; // fixed cost of one small instance, in components
 constexpr int64_t SMALL_GROUP = 65536; // cost budget of one item of small instances
 constexpr int SU = 2;                 // CHUNK groups in flight per thread
 constexpr int64_t GROUP = (int64_t)SU * CHUNK;
 constexpr int MAX_PLANS = 8;
-constexpr int64_t CG_ROWS_PER_BLOCK = 16384;  // rows per gang block of a CG system
-constexpr int CG_GANG_MAX = 16;               // blocks per CG system at most
+// A CG system of n rows gets a gang of ceil(n / batch_cg_rows) blocks, at
+// most batch_cg_gang_max (handle fields; defaults 16384 and 16).
 
 enum : int { IT_P1 = 0, IT_SMALL = 1, IT_P2 = 2, IT_CG = 3 };
 
@@ -76,7 +77,7 @@ struct BatchPlan {
     double *ltab = nullptr;           // one-pass mode: per large instance W x S1_PIECES sums
     CgSys *sys = nullptr;             // S device descriptors
     Gang *gangs = nullptr;            // S gang states
-    double *cgvec = nullptr;          // r, p, q of every system
+    double *cgvec = nullptr;          // r, p (two buffers), q of every system
     qdot_cg_result *cgres = nullptr;  // S results (synchronous CG entry)
     BItem *items = nullptr;
     BLarge *large = nullptr;
@@ -146,11 +147,15 @@ __device__ __forceinline__ void accumulate_range(const double *xi, const double 
 // One-pass mode: window depth of an instance, or -1 when its kept bins
 // could lie beyond the window (or n is past the exact-sum bound).  An
 // invalid tolerance gets depth 1: the cutoff then reports it.
+// Window depth of a one-pass instance, or -1 when the mode is refused
+// (kept bins could lie beyond the window).  A depth below 1 means that no
+// bin can be kept (a tolerance large enough to perforate everything): the
+// window then holds the top bin alone, whose class is perforated.
 __device__ __forceinline__ int s1_window_depth(int64_t n, double tol, int score_mode)
 {
     if (!(tol > 0.0) || __builtin_isinf(tol)) return 1;
     const int d = s1_depth_dev(n, tol, score_mode);
-    return (n > S1_MAX_N || d > S1_WIN) ? -1 : d;
+    return (n > S1_MAX_N || d > S1_WIN) ? -1 : max(d, 1);
 }
 
 __device__ __forceinline__ void write_invalid(qdot_result *o)
@@ -187,13 +192,14 @@ __device__ __forceinline__ void p1_onepass(const double *xi, const double *yi, i
     const int depth = s1_window_depth(n, tol, score_mode);
     const int dw = depth < 0 ? 0 : depth;  // no window when the mode is refused
     unsigned int nz = 0, bad = 0;
-    int top = -1;
+    S1Run run = s1_run_start();
     s1_begin(S1);
     __syncthreads();
     if (vec)
-        s1_stream<true, SU>(xi, yi, I.first, I.stride, n, key_mode, dw, h, S1, top, nz, bad);
+        s1_stream<true, SU>(xi, yi, I.first, I.stride, n, key_mode, dw, h, S1, run, nz, bad);
     else
-        s1_stream<false, SU>(xi, yi, I.first, I.stride, n, key_mode, dw, h, S1, top, nz, bad);
+        s1_stream<false, SU>(xi, yi, I.first, I.stride, n, key_mode, dw, h, S1, run, nz, bad);
+    const int top = run.top;
     __syncthreads();
     int lo = W, hi = -1;
     for (int j = tid; j < W; j += BLOCK) {
@@ -357,10 +363,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                 }
                 s1_begin(S1);
                 __syncthreads();
+                S1Run run = s1_run_start();
                 if (vec)
-                    s1_stream<true, SU>(xi, yi, 0, GROUP, n, key_mode, depth, h, S1, top, nz, bad);
+                    s1_stream<true, SU>(xi, yi, 0, GROUP, n, key_mode, depth, h, S1, run, nz, bad);
                 else
-                    s1_stream<false, SU>(xi, yi, 0, GROUP, n, key_mode, depth, h, S1, top, nz, bad);
+                    s1_stream<false, SU>(xi, yi, 0, GROUP, n, key_mode, depth, h, S1, run, nz, bad);
+                top = run.top;
             } else {
                 scan_into(xi, yi, 0, GROUP, n, vec, key_mode, h, nz, bad);
             }
@@ -495,9 +503,25 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
         } else {  // IT_P2
             BLarge *L = large + I.large;
             if (tid == 0) {
-                while (ld_dev(&L->ready) == 0u) __builtin_amdgcn_s_sleep(2);
-                s_prm2 = make_int4(ld_dev(&L->skip), ld_dev(&L->e_max), ld_dev(&L->c32),
-                                   ld_dev(&L->flags));
+                // bounded like the gang barriers: a chunk that waits past the
+                // spin limit gives up, marks its instance QDOT_E_DEVICE and
+                // only counts itself below
+                unsigned int spins = 0;
+                bool ready = true;
+                while (ld_dev(&L->ready) == 0u) {
+                    if (++spins > SPIN_LIMIT) {
+                        ready = false;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (ready) {
+                    s_prm2 = make_int4(ld_dev(&L->skip), ld_dev(&L->e_max), ld_dev(&L->c32),
+                                       ld_dev(&L->flags));
+                } else {
+                    st_dev(&out[I.inst].status, (int32_t)QDOT_E_DEVICE);
+                    s_prm2 = make_int4(1, 0, 0, 0);
+                }
             }
             __syncthreads();
             const int skip = s_prm2.x, e_max = s_prm2.y, c32 = s_prm2.z, flags = s_prm2.w;
@@ -570,10 +594,10 @@ static bool same_system(const qdot_cg_system &a, const qdot_cg_system &b)
            a.use_qdot == b.use_qdot;
 }
 
-static int gang_size(int64_t n)
+static int gang_size(const qdot_handle *h, int64_t n)
 {
-    return (int)std::max<int64_t>(
-        1, std::min<int64_t>(CG_GANG_MAX, (n + CG_ROWS_PER_BLOCK - 1) / CG_ROWS_PER_BLOCK));
+    const int64_t rows = h->batch_cg_rows;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(h->batch_cg_gang_max, (n + rows - 1) / rows));
 }
 
 static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
@@ -588,7 +612,7 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     std::vector<int> big, small;
     for (int j = 0; j < B; j++) {
         const int64_t n = host_offsets[j + 1] - host_offsets[j];
-        (n > SMALL_MAX ? big : small).push_back(j);
+        (n > h->batch_chunk ? big : small).push_back(j);
     }
     auto len = [&](int j) { return host_offsets[j + 1] - host_offsets[j]; };
     std::stable_sort(big.begin(), big.end(), [&](int a, int b) { return len(a) > len(b); });
@@ -601,7 +625,7 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     std::stable_sort(cg_order.begin(), cg_order.end(),
                      [&](int a, int c) { return systems[a].A.n > systems[c].A.n; });
     for (int s : cg_order) {
-        const int G = gang_size(systems[s].A.n);
+        const int G = gang_size(h, systems[s].A.n);
         p->max_gang = std::max(p->max_gang, G);
         for (int gb = 0; gb < G; gb++) items.push_back(BItem{IT_CG, s, G, gb, 0, 0});
     }
@@ -610,7 +634,7 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
     for (size_t L = 0; L < big.size(); L++) {
         const int j = big[L];
         const int64_t n = len(j);
-        const unsigned int nc = (unsigned int)((n + CH - 1) / CH);
+        const unsigned int nc = (unsigned int)((n + h->batch_chunk - 1) / h->batch_chunk);
         std::memset(&lg[L], 0, sizeof(BLarge));
         lg[L].nchunks = nc;
         lg[L].lo = W;
@@ -656,7 +680,7 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
               hipMalloc((void **)&p->sys, sizeof(CgSys) * ns) == hipSuccess &&
               hipMalloc((void **)&p->gangs, sizeof(Gang) * ns) == hipSuccess &&
               hipMalloc((void **)&p->cgres, sizeof(qdot_cg_result) * ns) == hipSuccess &&
-              hipMalloc((void **)&p->cgvec, sizeof(double) * std::max<int64_t>(1, 3 * cg_rows)) == hipSuccess &&
+              hipMalloc((void **)&p->cgvec, sizeof(double) * std::max<int64_t>(1, 4 * cg_rows)) == hipSuccess &&
               (accum == 0 ||
                hipMalloc((void **)&p->ltab, sizeof(double) * W * S1_PIECES * nl) == hipSuccess);
     if (!ok) {
@@ -676,8 +700,9 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
         d.x = q.x;
         d.r = p->cgvec + vo;
         d.p = p->cgvec + vo + q.A.n;
-        d.q = p->cgvec + vo + 2 * q.A.n;
-        vo += 3 * q.A.n;
+        d.pb = p->cgvec + vo + 2 * q.A.n;
+        d.q = p->cgvec + vo + 3 * q.A.n;
+        vo += 4 * q.A.n;
         d.rtol = q.rtol;
         d.qtol = q.qtol;
         d.maxit = q.maxit;
@@ -802,13 +827,14 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (o.bin_mode != 0)
+        return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
     if (o.guard_mode != 0) return fail(h, QDOT_E_INVAL, "the batched launch needs guard_mode 0");
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
     const int accum = B > 0 ? o.accum_mode : 0;  // CG systems always use the default reading
     if ((st = find_plan(h, host_offsets, B, systems, S, accum, &p)) != QDOT_OK) return st;
-    int bpc = h->batch_blocks_per_cu;
-    if (const char *e = std::getenv("QDOT_BATCH_BLOCKS_PER_CU")) bpc = std::max(1, std::min(16, std::atoi(e)));
+    const int bpc = h->batch_blocks_per_cu;
     const int grid = std::max(1, std::min(p->n_items, bpc * h->num_cus));
     if (p->max_gang > 0) {
         // a gang waits for its own blocks only, so it needs that many
@@ -837,6 +863,39 @@ using namespace qd;
 
 extern "C" {
 
+int32_t qdot_set_batch_tune(qdot_handle *h, const qdot_batch_tune *cfg)
+{
+    if (!h) return QDOT_E_INVAL;
+    qdot_batch_tune t = cfg ? *cfg : qdot_batch_tune{4, 131072, 16384, 16};
+    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16 || t.chunk < (1 << 13) ||
+        t.chunk > (1 << 22) || t.chunk % GROUP != 0 || t.cg_rows_per_block < CHUNK ||
+        t.cg_gang_max < 1 || t.cg_gang_max > MAX_GANG)
+        return fail(h, QDOT_E_INVAL, "batch tune out of range (blocks per CU 1..16, chunk "
+                                     "2^13..2^22 in multiples of 2048, CG rows per block >= "
+                                     "1024, gang 1..512)");
+    DeviceGuard g(h->device);
+    // the cached plans were cut with the old shape
+    if (!h->plans.empty()) {
+        (void)hipDeviceSynchronize();
+        free_plans(h);
+    }
+    h->batch_blocks_per_cu = t.blocks_per_cu;
+    h->batch_chunk = t.chunk;
+    h->batch_cg_rows = t.cg_rows_per_block;
+    h->batch_cg_gang_max = t.cg_gang_max;
+    return QDOT_OK;
+}
+
+int32_t qdot_get_batch_tune(const qdot_handle *h, qdot_batch_tune *cfg)
+{
+    if (!h || !cfg) return QDOT_E_INVAL;
+    cfg->blocks_per_cu = h->batch_blocks_per_cu;
+    cfg->chunk = (int32_t)h->batch_chunk;
+    cfg->cg_rows_per_block = (int32_t)h->batch_cg_rows;
+    cfg->cg_gang_max = h->batch_cg_gang_max;
+    return QDOT_OK;
+}
+
 int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B)
 {
     return qdot_batch_plan(h, host_offsets, B, nullptr, 0, nullptr);
@@ -853,6 +912,8 @@ int32_t qdot_batch_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (o.bin_mode != 0)
+        return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
     if (o.guard_mode != 0) return fail(h, QDOT_E_INVAL, "the batched launch needs guard_mode 0");
     if (B == 0 && S == 0) return QDOT_OK;
     DeviceGuard g(h->device);

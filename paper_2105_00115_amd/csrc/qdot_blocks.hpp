@@ -137,16 +137,18 @@ __device__ __forceinline__ void block_reduce_range(int &lo, int &hi, unsigned in
 
 // End of pass 1 in one block: merges the block's LDS histogram h (W + 1
 // slots; slot W takes zero and non-finite products, and is not merged) into
-// copy blockIdx % HIST_COPIES of ws's global histograms, adds the zero count,
+// copy blockIdx % copies of ws's global histograms (copies <= HIST_COPIES;
+// the cutoff reads all HIST_COPIES), adds the zero count,
 // raises the non-finite flag, and stores the block's record at index rec
 // (its live slot range and the signs of its nonzero products: bit 0
 // negative, bit 1 positive) for the cutoff kernel.  nz, bad and sg are the
 // calling thread's own tallies.  Every thread calls it, after a barrier that
 // completes h; it ends with one, so it can be called again.
 __device__ __forceinline__ void scan_flush(const unsigned int *h, unsigned int nz,
-                                           unsigned int bad, unsigned int sg, Ws *ws, int rec)
+                                           unsigned int bad, unsigned int sg, Ws *ws, int rec,
+                                           int copies = HIST_COPIES)
 {
-    unsigned long long *gh = ws->hist[blockIdx.x % HIST_COPIES];
+    unsigned long long *gh = ws->hist[blockIdx.x % copies];
     int lo = W, hi = -1;
     for (int i = threadIdx.x; i < W; i += BLOCK) {
         const unsigned int v = h[i];
@@ -214,6 +216,52 @@ template <class T>
 __device__ __forceinline__ void st_dev(T *p, T v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Pass-1 merge of a block whose LDS histogram is a window of nwin slots
+// starting at slot base (keys outside it were added to the global copy
+// directly; lo, hi cover those): as scan_flush.
+__device__ __forceinline__ void scan_flush_window(const unsigned int *h, int base, int nwin,
+                                                  int lo, int hi, unsigned int nz,
+                                                  unsigned int bad, unsigned int sg, Ws *ws,
+                                                  int rec, int copies)
+{
+    unsigned long long *gh = ws->hist[blockIdx.x % copies];
+    for (int i = threadIdx.x; i < nwin; i += BLOCK) {
+        const unsigned int v = h[i];
+        if (v) {
+            atomicAdd(&gh[base + i], (unsigned long long)v);
+            lo = min(lo, base + i);
+            hi = max(hi, base + i);
+        }
+    }
+    nz = wave_sum_u32(nz);
+    bad = wave_sum_u32(bad);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo = min(lo, __shfl_xor(lo, m, 64));
+        hi = max(hi, __shfl_xor(hi, m, 64));
+        sg |= __shfl_xor(sg, m, 64);
+    }
+    __shared__ int2 wr[BLOCK / 64];
+    __shared__ unsigned int wsg[BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) {
+        if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
+        if (bad) atomicOr(&ws->nonfinite, 1u);
+        wr[threadIdx.x >> 6] = make_int2(lo, hi);
+        wsg[threadIdx.x >> 6] = sg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int2 r = wr[0];
+        unsigned int g = wsg[0];
+        for (int w = 1; w < BLOCK / 64; w++) {
+            r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
+            g |= wsg[w];
+        }
+        ws->block_range[rec] = r;
+        ws->block_signs[rec] = g;
+    }
 }
 
 // ---- cutoff selection (Alg. 2: bins -> scores -> precisions) ------------
@@ -423,6 +471,290 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
     return s_prm;
 }
 
+// ---- other binning strategies (Sec. 3.2) ------------------------------------
+//
+// Exact bins hold one exponent each.  The other two partitions of
+// [e_min, e_max] that Sec. 3.2 weighs (its draft text defines them):
+//   bin_mode 1: ranged bins of width w = bin_param, (u_k - w, u_k] with
+//     u_k = e_min + k w - 1, k = 1, 2, ... (the last may reach past e_max);
+//   bin_mode 2: variable-width bins from at most bin_param splits: start
+//     from the one bin (e_min - 1, e_max]; each split takes the non-empty bin
+//     of more than one exponent whose Thm 3.2 term M_k 2^(u_k) is largest
+//     (ties to the higher u_k) and halves it at l + ceil((u - l) / 2).
+// A bin's score (eq. bin-score-def) uses its upper exponent u_k, its class
+// applies to all its keys, N_bins counts the non-empty bins and the Thm 3.3
+// term is M_k 2^(u_k - e_max + 1) eps(class).  Bins are kept as slot ranges
+// [lo, u] (slot = key - KMIN; u may pass the last slot for ranged bins).
+struct BinLds {
+    short lo[W + 1], u[W + 1];
+    unsigned long long m[W + 1];
+    int nb;
+    int best;
+    unsigned long long part[CUT_THREADS / 64];
+    int bestw[CUT_THREADS / 64];
+};
+
+// bin a's term M 2^u exceeds bin b's (ties to the higher u); counts below
+// 2^53 convert exactly
+__device__ __forceinline__ bool bin_heavier(const BinLds &B, int a, int b)
+{
+    const int d = (int)B.u[a] - (int)B.u[b];
+    if (d >= 64) return true;
+    if (d <= -64) return false;
+    const double va = ldexp((double)B.m[a], d), vb = (double)B.m[b];
+    if (va != vb) return va > vb;
+    return B.u[a] > B.u[b];
+}
+
+// Sum of get(j) over slots [a, b] by the whole block (result in every thread).
+template <int NT, class Get>
+__device__ __forceinline__ unsigned long long block_range_sum(BinLds &B, int a, int b, Get get)
+{
+    unsigned long long v = 0ull;
+    for (int j = a + (int)threadIdx.x; j <= b; j += NT) v += (unsigned long long)get(j);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) B.part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long t = 0ull;
+    for (int w = 0; w < NT / 64; w++) t += B.part[w];
+    return t;
+}
+
+// As block_cutoff (same outputs, same pass-2 parameters), for bin_mode 1 or
+// 2.  Only slots lo..hi may hold counts.
+template <int NT, class Get, class Put, class Clear>
+__device__ CutParams block_cutoff_bins(BinLds &B, int lo, int hi, unsigned long long nzero,
+                                       unsigned int bad, int64_t n, double tol, int score_mode,
+                                       int nonstrict, int bin_mode, int bin_param, Get get,
+                                       Put put, Clear clear, qdot_result *out,
+                                       long long *hist_out, int mu_single = 0)
+{
+    constexpr int NW = NT / 64;
+    __shared__ int s_max[NW], s_min[NW], s_nb[NW], s_unatt[NW];
+    __shared__ unsigned long long s_cnt[NW][4];
+    __shared__ double s_bound[NW];
+    __shared__ CutParams s_prm;
+    __shared__ int s_go;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    // e_max, e_min over the live keys
+    int smax = -1, smin = W;
+    for (int j = lo + tid; j <= hi; j += NT) {
+        const unsigned long long v = (unsigned long long)get(j);
+        if (hist_out) hist_out[j] = (long long)v;
+        if (v) {
+            smax = max(smax, j);
+            smin = min(smin, j);
+        }
+    }
+    if (hist_out)
+        for (int j = tid; j < W; j += NT)
+            if (j < lo || j > hi) hist_out[j] = 0ll;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        smax = max(smax, __shfl_xor(smax, m, 64));
+        smin = min(smin, __shfl_xor(smin, m, 64));
+    }
+    if (lane == 0) {
+        s_max[wv] = smax;
+        s_min[wv] = smin;
+    }
+    __syncthreads();
+    smax = -1;
+    smin = W;
+    for (int w = 0; w < NW; w++) {
+        smax = max(smax, s_max[w]);
+        smin = min(smin, s_min[w]);
+    }
+    const bool any = smax >= 0;
+
+    // the partition
+    if (any && bin_mode == 1) {
+        const int w = bin_param;
+        const int nbr = (smax - smin) / w + 1;
+        for (int b = tid; b < nbr; b += NT) {
+            const int a = smin + b * w, u = a + w - 1;
+            unsigned long long m = 0ull;
+            for (int j = a; j <= min(u, smax); j++) m += (unsigned long long)get(j);
+            B.lo[b] = (short)a;
+            B.u[b] = (short)u;
+            B.m[b] = m;
+        }
+        if (tid == 0) B.nb = nbr;
+    } else if (any) {
+        const unsigned long long all = block_range_sum<NT>(B, smin, smax, get);
+        if (tid == 0) {
+            B.lo[0] = (short)smin;
+            B.u[0] = (short)smax;
+            B.m[0] = all;
+            B.nb = 1;
+        }
+        __syncthreads();
+        for (int sp = 0; sp < bin_param; sp++) {
+            // the heaviest splittable bin
+            const int nb = B.nb;
+            int best = -1;
+            for (int i = tid; i < nb; i += NT)
+                if (B.m[i] > 0 && B.u[i] > B.lo[i] && (best < 0 || bin_heavier(B, i, best)))
+                    best = i;
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) {
+                const int o = __shfl_xor(best, m, 64);
+                if (o >= 0 && (best < 0 || bin_heavier(B, o, best))) best = o;
+            }
+            if (lane == 0) B.bestw[wv] = best;
+            __syncthreads();
+            if (tid == 0) {
+                int b2 = -1;
+                for (int w = 0; w < NW; w++) {
+                    const int o = B.bestw[w];
+                    if (o >= 0 && (b2 < 0 || bin_heavier(B, o, b2))) b2 = o;
+                }
+                B.best = b2;
+            }
+            __syncthreads();
+            const int bi = B.best;
+            if (bi < 0) break;  // every non-empty bin is a single exponent
+            const int l = (int)B.lo[bi] - 1, u = B.u[bi];
+            const int mid = l + (u - l + 1) / 2;
+            const unsigned long long ml = block_range_sum<NT>(B, l + 1, mid, get);
+            if (tid == 0) {
+                const unsigned long long mb = B.m[bi];
+                const int k = B.nb;
+                B.lo[k] = (short)(l + 1);
+                B.u[k] = (short)mid;
+                B.m[k] = ml;
+                B.lo[bi] = (short)(mid + 1);
+                B.m[bi] = mb - ml;
+                B.nb = k + 1;
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    const int nbt = any ? B.nb : 0;
+    int nbk = 0;
+    for (int i = tid; i < nbt; i += NT) nbk += B.m[i] > 0 ? 1 : 0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) nbk += __shfl_xor(nbk, m, 64);
+    if (lane == 0) s_nb[wv] = nbk;
+    __syncthreads();
+    if (tid == 0) {
+        int c = 0;
+        for (int w = 0; w < NW; w++) c += s_nb[w];
+        const int a = any ? smax + KMIN : 0;
+        out->n_zero = (long long)nzero;
+        out->n_bins = c;
+        out->e_max = c ? a : 0;
+        out->e_min = c ? smin + KMIN : 0;
+        out->e_ref = c ? a : 0;
+        out->lower = 0.0;
+        out->passes = 0;
+        for (int q = 0; q < 3; q++) out->part[q] = 0.0;
+        int go = 1, t = 0;
+        const bool tol_ok = tol > 0.0 && !__builtin_isinf(tol) && !__builtin_isnan(tol);
+        if (bad || !tol_ok) {
+            go = 0;
+            out->value = __longlong_as_double(0x7ff8000000000000ll);
+            for (int q = 0; q < 4; q++) out->count[q] = 0;
+            out->status = bad ? QDOT_E_NONFINITE : QDOT_E_INVAL;
+            out->flags = 0;
+            out->t = 0;
+            out->bound_rel = out->bound_abs = 0.0;
+        } else if (c == 0) {
+            go = 0;
+            out->value = 0.0;
+            for (int q = 0; q < 3; q++) out->count[q] = 0;
+            out->count[QDOT_PERF] = n;
+            out->status = QDOT_OK;
+            out->flags = QDOT_F_ALL_PERF;
+            out->t = 0;
+            out->bound_rel = out->bound_abs = 0.0;
+        } else {
+            t = floor_log2_ratio(tol, score_mode == 0 ? (unsigned long long)c : 1ull);
+            out->t = t;
+            out->status = QDOT_OK;
+        }
+        s_prm.e_max = a;
+        s_prm.t = t;
+        s_prm.c32 = a + t + 22;
+        s_prm.skip = 1;
+        s_prm.flags = 0;
+        s_go = go;
+    }
+    __syncthreads();
+    const int go = s_go;
+    const int e_max = s_prm.e_max, t = s_prm.t;
+    // every live slot's class is set by its bin below; empty slots of the
+    // window outside every bin stay perforated
+    for (int j = lo + tid; j <= hi; j += NT)
+        if (!go || j < smin || j > smax) put(j, QDOT_PERF);
+    unsigned long long cc[4] = {0, 0, 0, 0};
+    double bound = 0.0;
+    int unatt = 0;
+    for (int i = tid; i < nbt; i += NT) {
+        const unsigned long long v = B.m[i];
+        const int ua = B.u[i], la = B.lo[i];
+        int cls = QDOT_PERF;
+        if (go && v) {
+            const int uk = ua + KMIN;
+            const int sigma = ceil_log2_u64(v) + uk - e_max - t + 1;
+            cls = class_of(sigma, nonstrict);
+            if (mu_single && cls == QDOT_DOUBLE) cls = SINGLE_IN;
+            unatt |= sigma >= (mu_single ? 23 : 52) + (nonstrict ? 1 : 0);
+            cc[cls == SINGLE_IN ? QDOT_SINGLE : cls] += v;
+            bound += ldexp((double)v * eps_of_class(cls), uk - e_max + 1);
+        }
+        if (go)
+            for (int j = max(la, lo); j <= min(ua, hi); j++) put(j, cls);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) cc[q] += __shfl_xor(cc[q], m, 64);
+        bound += __shfl_xor(bound, m, 64);
+        unatt |= __shfl_xor(unatt, m, 64);
+    }
+    if (lane == 0) {
+        for (int q = 0; q < 4; q++) s_cnt[wv][q] = cc[q];
+        s_bound[wv] = bound;
+        s_unatt[wv] = unatt;
+    }
+    __syncthreads();
+    // the counts are no longer read: clear the window
+    for (int j = lo + tid; j <= hi; j += NT) clear(j);
+    if (tid == 0 && go) {
+        unsigned long long tc[4] = {0, 0, 0, 0};
+        double bsum = 0.0;
+        int ua = 0;
+        for (int w = 0; w < NW; w++) {
+            for (int q = 0; q < 4; q++) tc[q] += s_cnt[w][q];
+            bsum += s_bound[w];
+            ua |= s_unatt[w];
+        }
+        tc[QDOT_PERF] += nzero;
+        for (int q = 0; q < 4; q++) out->count[q] = (long long)tc[q];
+        out->bound_rel = bsum;
+        out->bound_abs = ldexp(bsum, e_max);
+        int flags = ua ? QDOT_F_UNATTAINABLE : 0;
+        if ((long long)e_max - out->e_min <= -(long long)t - (mu_single ? 10 : 23))
+            flags |= QDOT_F_THM_ALL_DOUBLE;
+        const bool none_kept = (tc[0] + tc[1] + tc[2]) == 0;
+        out->passes = none_kept ? 0 : 1;
+        if (none_kept) {
+            flags |= QDOT_F_ALL_PERF;
+            out->value = 0.0;
+        }
+        out->flags = flags;
+        s_prm.flags = flags;
+        s_prm.skip = none_kept ? 1 : 0;
+    }
+    __syncthreads();
+    return s_prm;
+}
+
 // ---- guaranteed mode (Thm 3.4) ---------------------------------------------
 // After a sweep of pass 2 with sum S (units of 2^e_max), a bound a of every
 // error of the call, evaluated from the histogram and the classes alone,
@@ -592,6 +924,128 @@ __device__ __forceinline__ void acc_group(const T *xv, const T *yv, int lim,
     }
 }
 
+// ---- pass 2, compacting form ----------------------------------------------
+//
+// The same leaves, tile trees and FP64 sums as acc_group, with the leaf work
+// done only for kept components.  Each lane classifies its 4 components from
+// their keys; the kept ones are compacted per wave into an LDS queue
+// (operands, position in the wave's 256-component group, class) and taken
+// 64 at a time by the whole wave, which forms each queued component's leaf:
+// a double leaf goes straight into the lane's compensated FP64 sum, an FP32
+// leaf into the group's leaf slot of its class.  The lanes then read their
+// 4 slots of each FP32 class back (zero where nothing was kept), reduce the
+// 64-element tiles by the same adjacent-pairwise tree, and clear the slots.
+// FP32 tile sums are therefore bit for bit those of acc_group; only the
+// order of the FP64 additions differs, which the compensated sums absorb.
+struct AccWaveLds {
+    double2 q[128];  // queued operands
+    int qm[128];     // queued position (bits 0..7) and class (bits 8..)
+    float ls[256];   // single leaves of the group's components (0: none)
+    float lh[256];   // half leaves
+};
+
+// Zero the leaf slots (every thread of the block, before the first group).
+template <int NT>
+__device__ __forceinline__ void acc_q_begin(AccWaveLds *wl)
+{
+    for (int i = threadIdx.x; i < (NT / 64) * 256; i += NT) {
+        wl[i / 256].ls[i % 256] = 0.0f;
+        wl[i / 256].lh[i % 256] = 0.0f;
+    }
+}
+
+template <bool CLS, class T>
+__device__ __forceinline__ void acc_group_q(const T *xv, const T *yv, int lim,
+                                            const unsigned char *lut, int key_mode, int e_max,
+                                            int c32, bool accumulate, Acc &aD, Acc &aS, Acc &aH,
+                                            unsigned char *cls_out, AccWaveLds &wl)
+{
+    const int lane = threadIdx.x & 63;
+    int cls[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        int slot;
+        if constexpr (sizeof(T) == 4) slot = component_f(xv[e], yv[e], key_mode).slot;
+        else slot = component((double)xv[e], (double)yv[e], key_mode).slot;
+        cls[e] = e < lim ? (int)lut[slot] : QDOT_PERF;
+        if (CLS && e < lim)
+            cls_out[e] = (unsigned char)(cls[e] == SINGLE_IN ? QDOT_SINGLE : cls[e]);
+    }
+    if (!accumulate) return;
+    // leaf of one queued component (lanes below cnt)
+    auto drain = [&](int cnt) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const double2 v = wl.q[lane];
+            const int m = wl.qm[lane];
+            const int idx = m & 255, c = m >> 8;
+            float l32;
+            if constexpr (sizeof(T) == 4) {
+                const CompF d = component_f((float)v.x, (float)v.y, key_mode);
+                const float ps = d.mx * d.my;
+                const float ph = half_round_f(d.mx) * half_round_f(d.my);  // exact
+                if (c == SINGLE_IN) {
+                    double l64 = ldexp((double)ps, d.es - e_max);
+                    l64 = __longlong_as_double(__double_as_longlong(l64) ^
+                                               ((long long)d.sgn << 32));
+                    acc_add(aD, l64);
+                }
+                l32 = ldexpf(c == QDOT_HALF ? ph : ps, d.es - c32);
+                l32 = __int_as_float(__float_as_int(l32) ^ (int)d.sgn);
+            } else {
+                const Comp d = component(v.x, v.y, key_mode);
+                if (c == QDOT_DOUBLE) {
+                    double dl = ldexp(d.mp, d.es - e_max);
+                    dl = __longlong_as_double(__double_as_longlong(dl) ^ ((long long)d.sgn << 32));
+                    acc_add(aD, dl);
+                }
+                const float ps = (float)d.mx * (float)d.my;
+                const float ph = (float)(half_round(d.mx) * half_round(d.my));
+                l32 = ldexpf(c == QDOT_HALF ? ph : ps, d.es - c32);
+                l32 = __int_as_float(__float_as_int(l32) ^ (int)d.sgn);
+            }
+            if (c == QDOT_SINGLE) wl.ls[idx] = l32;
+            if (c == QDOT_HALF) wl.lh[idx] = l32;
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    int qn = 0;  // wave-uniform
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const bool kept = cls[e] != QDOT_PERF;
+        const unsigned long long m = __ballot(kept);
+        if (kept) {
+            const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                     (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            wl.q[pos] = make_double2((double)xv[e], (double)yv[e]);
+            wl.qm[pos] = (lane * 4 + e) | (cls[e] << 8);
+        }
+        qn += __popcll(m);
+        if (qn >= 64) {
+            drain(64);
+            if (lane < qn - 64) {
+                wl.q[lane] = wl.q[64 + lane];
+                wl.qm[lane] = wl.qm[64 + lane];
+            }
+            __builtin_amdgcn_wave_barrier();
+            qn -= 64;
+        }
+    }
+    if (qn > 0) drain(qn);
+    // the group's FP32 tiles: 16 lanes x 4 slots each, levels 1-2 in the
+    // lane, 3-6 across the row; then the slots back to zero
+    const float4 sv = *reinterpret_cast<const float4 *>(&wl.ls[lane * 4]);
+    const float4 hv = *reinterpret_cast<const float4 *>(&wl.lh[lane * 4]);
+    *reinterpret_cast<float4 *>(&wl.ls[lane * 4]) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    *reinterpret_cast<float4 *>(&wl.lh[lane * 4]) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float ts = tile_levels_3to6((sv.x + sv.y) + (sv.z + sv.w));
+    const float th = tile_levels_3to6((hv.x + hv.y) + (hv.z + hv.w));
+    if ((threadIdx.x & 15) == 0) {
+        acc_add(aS, (double)ts);
+        acc_add(aH, (double)th);
+    }
+}
+
 // ---- one-pass mode: candidate leaves relative to the component's bin -----
 // A component with key k (bin 2^k) has, for every precision, the leaf of
 // Alg. 1 divided by 2^k: s * L * 2^(E_x + E_y - k) with L = fl64(m_x m_y),
@@ -676,27 +1130,108 @@ __device__ __forceinline__ void s1_begin(S1Lds &S)
     if (threadIdx.x < 2) S.top2[threadIdx.x] = -1;
 }
 
+// Running state of a block's one-pass window between groups.
+struct S1Run {
+    int top;  // highest live slot seen so far by the block (-1: none)
+    int par;  // which of the two LDS words the next group agrees top in
+};
+
+__device__ __forceinline__ S1Run s1_run_start() { return S1Run{-1, 0}; }
+
+// One group of K components per thread (component e of this thread is real
+// when valid[e]): keys into the LDS histogram h (W + 1 slots), zero /
+// non-finite counts, and the candidate sums of every component whose bin
+// lies within `depth` of the block's running maximum live slot run.top.
+// The new maximum is agreed at a barrier; when it rises the slots of the
+// entering bins are cleared first.  The in-window components are compacted
+// per wave and processed 64 at a time.  Every thread of the block must call
+// it (with the same depth).  T is the input type: floats are widened
+// exactly (their single and half candidates are then those of the float
+// path; the double candidate is never picked, the class table having no
+// double row).
+template <int K, class T>
+__device__ __forceinline__ void s1_group(const T (&xv)[K], const T (&yv)[K],
+                                         const bool (&valid)[K], int key_mode, int depth,
+                                         unsigned int *h, S1Lds &S, S1Run &run,
+                                         unsigned int &nz, unsigned int &bad)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    int live[K];
+    int wmax = -1;
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const Comp c = component((double)xv[e], (double)yv[e], key_mode);
+        nz += (valid[e] & c.zero) ? 1u : 0u;
+        bad |= (valid[e] & c.bad) ? 1u : 0u;
+        if (valid[e]) atomicAdd(&h[c.slot], 1u);
+        live[e] = (valid[e] && c.slot != ZERO_SLOT) ? c.slot : -1;
+        wmax = max(wmax, live[e]);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
+    if (lane == 0 && wmax > run.top) atomicMax(&S.top2[run.par], wmax);
+    __syncthreads();
+    const int nt = S.top2[run.par];
+    run.par ^= 1;
+    if (nt > run.top) {
+        // bins top+1 .. nt enter; their slots held bins now below the window
+        const int nclr = min(nt - run.top, S1_WIN);
+        for (int i = tid; i < nclr * S1_PIECES; i += BLOCK)
+            S.win[(nt - i / S1_PIECES) & (S1_WIN - 1)][i % S1_PIECES] = 0.0;
+        __syncthreads();
+        run.top = nt;
+    }
+    const int wlo = run.top - depth + 1;
+    double2 *qw = S.q[tid >> 6];
+    int qn = 0;  // wave-uniform
+    auto drain = [&](int cnt) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const double2 v = qw[lane];
+            const Comp c = component(v.x, v.y, key_mode);
+            double pc[S1_PIECES];
+            s1_pieces(c, key_mode, pc);
+            double *w = S.win[c.slot & (S1_WIN - 1)];
+#pragma unroll
+            for (int q = 0; q < S1_PIECES; q++)
+                if (pc[q] != 0.0) atomicAdd(&w[q], pc[q]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const bool in = live[e] >= wlo && live[e] >= 0;
+        const unsigned long long m = __ballot(in);
+        if (in) {
+            const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                     (unsigned)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            qw[pos] = make_double2((double)xv[e], (double)yv[e]);
+        }
+        qn += __popcll(m);
+        if (qn >= 64) {
+            drain(64);
+            if (lane < qn - 64) qw[lane] = qw[64 + lane];
+            __builtin_amdgcn_wave_barrier();
+            qn -= 64;
+        }
+    }
+    if (qn > 0) drain(qn);
+}
+
 // One block streams the groups first, first + stride, ... (GROUP = U * CHUNK
-// components each) below n: keys into the LDS histogram h (W + 1 slots),
-// zero / non-finite counts, and the candidate sums of every component whose
-// bin lies within `depth` of the block's running maximum live slot `top`
-// (-1 on entry for a fresh window).  `top` is agreed at a barrier per group;
-// when it rises the slots of the entering bins are cleared first.  The
-// in-window components are compacted per wave and processed 64 at a time.
-// Every thread of the block must call it with the same arguments.
-// T is the input type: floats are widened exactly (their single and half
-// candidates are then those of the float path; the double candidate is never
-// picked, the class table having no double row).
+// components each) below n through s1_group (4 consecutive components per
+// thread and CHUNK, U CHUNKs per group).  Every thread of the block must call
+// it with the same arguments.
 template <bool VEC, int U, class T>
 __device__ __forceinline__ void s1_stream(const T *__restrict__ x, const T *__restrict__ y,
                                           int64_t first, int64_t stride, int64_t n,
                                           int key_mode, int depth, unsigned int *h, S1Lds &S,
-                                          int &top, unsigned int &nz, unsigned int &bad)
+                                          S1Run &run, unsigned int &nz, unsigned int &bad)
 {
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int64_t group = (int64_t)CHUNK * U;
-    int par = 0;
-    for (int64_t base = first; base < n; base += stride, par ^= 1) {
+    for (int64_t base = first; base < n; base += stride) {
         T xv[U][4], yv[U][4];
         int lim[U];
         const bool full = base + group <= n;
@@ -714,71 +1249,17 @@ __device__ __forceinline__ void s1_stream(const T *__restrict__ x, const T *__re
                 load4_tail(y + i0, lim[u], yv[u]);
             }
         }
-        int live[U][4];
-        int wmax = -1;
+        T xf[U * 4], yf[U * 4];
+        bool vf[U * 4];
 #pragma unroll
         for (int u = 0; u < U; u++)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const Comp c = component((double)xv[u][e], (double)yv[u][e], key_mode);
-                const bool valid = e < lim[u];
-                nz += (valid & c.zero) ? 1u : 0u;
-                bad |= (valid & c.bad) ? 1u : 0u;
-                if (valid) atomicAdd(&h[c.slot], 1u);
-                live[u][e] = (valid && c.slot != ZERO_SLOT) ? c.slot : -1;
-                wmax = max(wmax, live[u][e]);
+                xf[u * 4 + e] = xv[u][e];
+                yf[u * 4 + e] = yv[u][e];
+                vf[u * 4 + e] = e < lim[u];
             }
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
-        if (lane == 0 && wmax > top) atomicMax(&S.top2[par], wmax);
-        __syncthreads();
-        const int nt = S.top2[par];
-        if (nt > top) {
-            // bins top+1 .. nt enter; their slots held bins now below the window
-            const int nclr = min(nt - top, S1_WIN);
-            for (int i = tid; i < nclr * S1_PIECES; i += BLOCK)
-                S.win[(nt - i / S1_PIECES) & (S1_WIN - 1)][i % S1_PIECES] = 0.0;
-            __syncthreads();
-            top = nt;
-        }
-        const int wlo = top - depth + 1;
-        double2 *qw = S.q[tid >> 6];
-        int qn = 0;  // wave-uniform
-        auto drain = [&](int cnt) {
-            __builtin_amdgcn_wave_barrier();
-            if (lane < cnt) {
-                const double2 v = qw[lane];
-                const Comp c = component(v.x, v.y, key_mode);
-                double pc[S1_PIECES];
-                s1_pieces(c, key_mode, pc);
-                double *w = S.win[c.slot & (S1_WIN - 1)];
-#pragma unroll
-                for (int q = 0; q < S1_PIECES; q++)
-                    if (pc[q] != 0.0) atomicAdd(&w[q], pc[q]);
-            }
-            __builtin_amdgcn_wave_barrier();
-        };
-#pragma unroll
-        for (int u = 0; u < U; u++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const bool in = live[u][e] >= wlo && live[u][e] >= 0;
-                const unsigned long long m = __ballot(in);
-                if (in) {
-                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                             (unsigned)(m >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                    qw[pos] = make_double2((double)xv[u][e], (double)yv[u][e]);
-                }
-                qn += __popcll(m);
-                if (qn >= 64) {
-                    drain(64);
-                    if (lane < qn - 64) qw[lane] = qw[64 + lane];
-                    __builtin_amdgcn_wave_barrier();
-                    qn -= 64;
-                }
-            }
-        if (qn > 0) drain(qn);
+        s1_group<U * 4>(xf, yf, vf, key_mode, depth, h, S, run, nz, bad);
     }
 }
 
@@ -787,13 +1268,13 @@ __device__ __forceinline__ void s1_stream(const T *__restrict__ x, const T *__re
 // FP64 number), scaled by 2^(k - e_max); the block sums them with
 // compensation and thread 0 writes value, parts and flags.  lut holds the
 // class of every slot.  Every thread must call it.
-template <class Get>
-__device__ __forceinline__ void s1_pick(int e_max, int lo, int flags, const unsigned char *lut,
-                                        Get get, Acc (*red)[BLOCK / 64], qdot_result *out)
+template <int NT, class Get>
+__device__ __forceinline__ void s1_pick_nt(int e_max, int lo, int flags, const unsigned char *lut,
+                                        Get get, Acc (*red)[NT / 64], qdot_result *out)
 {
     const int top = e_max - KMIN;
     Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};  // double, single, half
-    for (int j = threadIdx.x; j < S1_WIN; j += BLOCK) {
+    for (int j = threadIdx.x; j < S1_WIN; j += NT) {
         const int bin = top - j;
         if (bin < lo) continue;
         const int cls = lut[bin];
@@ -808,7 +1289,7 @@ __device__ __forceinline__ void s1_pick(int e_max, int lo, int flags, const unsi
             acc_add(a[2], ldexp(get(bin, 0), -j));
         }
     }
-    block_reduce3<BLOCK>(a, red);
+    block_reduce3<NT>(a, red);
     if (threadIdx.x == 0) {
         Acc tot = a[0];
         acc_add(tot, a[1].s);
@@ -821,6 +1302,13 @@ __device__ __forceinline__ void s1_pick(int e_max, int lo, int flags, const unsi
         out->part[QDOT_HALF] = ldexp(a[2].s + a[2].c, e_max);
         out->flags = flags | (__builtin_isinf(value) ? QDOT_F_OVERFLOW : 0);
     }
+}
+
+template <class Get>
+__device__ __forceinline__ void s1_pick(int e_max, int lo, int flags, const unsigned char *lut,
+                                        Get get, Acc (*red)[BLOCK / 64], qdot_result *out)
+{
+    s1_pick_nt<BLOCK>(e_max, lo, flags, lut, get, red, out);
 }
 
 // value = 2^e_max (D + 2^(c32 - e_max) (S + H)), parts, overflow flag;

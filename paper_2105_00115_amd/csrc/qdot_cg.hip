@@ -129,6 +129,8 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (o.bin_mode != 0)
+        return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
     if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
     const bool acc1 = use_qdot && o.accum_mode == 1;
@@ -136,7 +138,7 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
         return fail(h, QDOT_E_INVAL, "accum_mode 1 not admissible for this n and qtol");
     DeviceGuard g(h->device);
     const int64_t n = A->n;
-    int32_t st = ensure_solver_vectors(h, 3 * n);  // r, p, q
+    int32_t st = ensure_solver_vectors(h, 4 * n);  // r, p (two buffers), q
     if (st != QDOT_OK) return st;
     if ((st = ensure_cg_buffers(h, 1, 1)) != QDOT_OK) return st;
     CgDev *d = (CgDev *)h->cg;
@@ -169,7 +171,8 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     S.x = x;
     S.r = h->vec;
     S.p = h->vec + n;
-    S.q = h->vec + 2 * n;
+    S.pb = h->vec + 2 * n;
+    S.q = h->vec + 3 * n;
     S.rtol = rtol;
     S.qtol = qtol;
     S.maxit = maxit;

@@ -21,7 +21,7 @@ struct qdot_handle {
 
     // solver scratch, grown on demand: the power method keeps w = A x of
     // the current and the previous iteration (2 n doubles), the
-    // single-system CG keeps r, p, q (3 n doubles)
+    // single-system CG keeps r, two p buffers and q (4 n doubles)
     double *vec = nullptr;
     int64_t vec_n = 0;               // doubles held at vec
     void *ctl = nullptr;             // solver control block
@@ -32,6 +32,9 @@ struct qdot_handle {
     // batched qdot: cached work plans (one per offsets layout) and grid size
     std::vector<void *> plans;
     int batch_blocks_per_cu = 4;
+    int64_t batch_chunk = 131072;    // components per chunk of a large instance
+    int64_t batch_cg_rows = 16384;   // CG rows per gang block
+    int batch_cg_gang_max = 16;      // CG gang blocks at most
     void *cg = nullptr;              // persistent CG buffers
 
     // kernel timing (diagnostics)
@@ -64,6 +67,18 @@ int32_t hip_fail(qdot_handle *h, hipError_t e, const char *where);
 // Launch shape of a call on n components (the tune bucket of n); single:
 // single-precision inputs.
 Launch make_launch(qdot_handle *h, hipStream_t s, int64_t n, bool single = false);
+// The same from explicit parts: tune entry t, CU count, and the workspace
+// (control block, partials for partial_cap blocks, one-pass tables).
+Launch make_launch_tuned(const qdot_tune &t, int num_cus, Ws *ws, double *partials,
+                         int partial_cap, double *s1tab, hipStream_t s, bool single);
+// Tune bucket of a call on n components.
+int bucket_of(int64_t n);
+// Host-side argument check of a single qdot call (T = double or float):
+// QDOT_OK, or QDOT_E_INVAL with a static message in *msg.  o receives the
+// options (zero-initialised defaults when opt is NULL).
+template <class T>
+int32_t qdot_args(const T *x, const T *y, int64_t n, double tol, const qdot_options *opt,
+                  qdot_options &o, const char **msg);
 qdot_tune default_tune(int bucket);
 bool tune_ok(const qdot_tune &t);
 // Events for one timed call of `kind` (0: qdot, 5 events; 1: FP64 dot, 2),

@@ -18,15 +18,15 @@ namespace qd {
 
 // ---------------------------------------------------------------------------
 // Pass 1 (Alg. 2, exponent preprocessing + counting): product exponents into
-// a block-private LDS histogram, merged into one of HIST_COPIES global
-// histograms (blockIdx % HIST_COPIES, i.e. one per XCD under round-robin
+// a block-private LDS histogram, merged into one of `copies` (<= HIST_COPIES)
+// global histograms (blockIdx % copies; 8: one per XCD under round-robin
 // dispatch) so that the merge atomics of concurrent blocks spread out.
 // ---------------------------------------------------------------------------
 template <class T, bool VEC, int U>
 __global__ __launch_bounds__(BLOCK) void k_scan(const T *__restrict__ x,
                                                 const T *__restrict__ y,
                                                 int64_t n, int key_mode,
-                                                Ws *__restrict__ ws)
+                                                Ws *__restrict__ ws, int copies)
 {
     __shared__ unsigned int h[W + 1];
     for (int i = threadIdx.x; i < W + 1; i += BLOCK) h[i] = 0;
@@ -50,17 +50,22 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const T *__restrict__ x,
         }
     });
     __syncthreads();
-    scan_flush(h, nz, bad, sg, ws, blockIdx.x);
+    scan_flush(h, nz, bad, sg, ws, blockIdx.x, copies);
 }
 
 // ---------------------------------------------------------------------------
 // Cutoff selection (Alg. 2, bins -> scores -> precisions), one workgroup over
 // the live slot window of the 8 histogram copies.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void cut_body(Ws *__restrict__ ws, double tol, int score_mode,
-                                         int nonstrict, int64_t n, int nscan, int guard,
-                                         int mu_single, qdot_result *__restrict__ out,
-                                         long long *__restrict__ hist_out)
+// BINS: bin_mode / bin_param select the partition (exact bins when 0; the
+// other strategies need the block's BinLds, so only kernels that admit them
+// instantiate this).
+template <bool BINS = false>
+__device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, int score_mode,
+                                              int nonstrict, int64_t n, int nscan, int guard,
+                                              int mu_single, qdot_result *__restrict__ out,
+                                              long long *__restrict__ hist_out,
+                                              int bin_mode = 0, int bin_param = 0)
 {
     constexpr int NW = CUT_THREADS / 64;
     __shared__ int s_lo[NW], s_hi[NW];
@@ -110,9 +115,20 @@ __device__ __forceinline__ void cut_body(Ws *__restrict__ ws, double tol, int sc
 #pragma unroll
         for (int c = 0; c < HIST_COPIES; c++) ws->hist[c][j] = 0ull;
     };
-    const CutParams p = block_cutoff<CUT_THREADS>(lo, hi, nzero, bad, n, tol, score_mode,
-                                                  nonstrict, get, put, clear, out, hist_out, 0,
-                                                  mu_single);
+    CutParams p;
+    if constexpr (BINS) {
+        __shared__ BinLds B;
+        if (bin_mode != 0)
+            p = block_cutoff_bins<CUT_THREADS>(B, lo, hi, nzero, bad, n, tol, score_mode,
+                                               nonstrict, bin_mode, bin_param, get, put, clear,
+                                               out, hist_out, mu_single);
+        else
+            p = block_cutoff<CUT_THREADS>(lo, hi, nzero, bad, n, tol, score_mode, nonstrict,
+                                          get, put, clear, out, hist_out, 0, mu_single);
+    } else {
+        p = block_cutoff<CUT_THREADS>(lo, hi, nzero, bad, n, tol, score_mode, nonstrict, get,
+                                      put, clear, out, hist_out, 0, mu_single);
+    }
     if (tid < W_LUT - W) ws->lut[W + tid] = (unsigned char)QDOT_PERF;
     if (tid == 0) {
         ws->n_zero = 0;
@@ -127,6 +143,7 @@ __device__ __forceinline__ void cut_body(Ws *__restrict__ ws, double tol, int sc
         ws->signs = sg;
         ws->mu_single = mu_single;
     }
+    return p;
 }
 
 __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double tol,
@@ -137,6 +154,18 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
                                                      long long *__restrict__ hist_out)
 {
     cut_body(ws, tol, score_mode, nonstrict, n, nscan, guard, mu_single, out, hist_out);
+}
+
+// k_cut with a binning strategy other than exact bins (Sec. 3.2)
+__global__ __launch_bounds__(CUT_THREADS) void k_cut_bins(Ws *__restrict__ ws, double tol,
+                                                          int score_mode, int nonstrict,
+                                                          int64_t n, int nscan, int mu_single,
+                                                          qdot_result *__restrict__ out,
+                                                          long long *__restrict__ hist_out,
+                                                          int bin_mode, int bin_param)
+{
+    cut_body<true>(ws, tol, score_mode, nonstrict, n, nscan, 0, mu_single, out, hist_out,
+                   bin_mode, bin_param);
 }
 
 // ---------------------------------------------------------------------------
@@ -155,7 +184,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
 // ---------------------------------------------------------------------------
 // Block `blk` of `nblk` (grid-stride over groups) writes its partials at
 // partials + 6 * blk.
-template <class T, bool VEC, int U, bool CLS>
+// Q: the compacting form of the leaf work (acc_group_q), else acc_group.
+template <class T, bool VEC, int U, bool CLS, bool Q = false>
 __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__restrict__ y,
                                          int64_t n, int key_mode, const Ws *__restrict__ ws,
                                          double *__restrict__ partials,
@@ -163,6 +193,7 @@ __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__res
 {
     __shared__ unsigned char lut[W_LUT];
     __shared__ Acc red[3][BLOCK / 64];
+    __shared__ AccWaveLds wl[Q ? BLOCK / 64 : 1];
 
     const int skip = ws->skip;
     if (skip && !CLS) return;
@@ -173,6 +204,7 @@ __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__res
     }
     const int e_max = ws->e_max;
     const int c32 = ws->c32;
+    if (Q) acc_q_begin<BLOCK>(wl);
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -180,8 +212,12 @@ __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__res
     const int64_t group = (int64_t)CHUNK * U;
     stream_strided<VEC, U>(x, y, (int64_t)blk * group, (int64_t)nblk * group, n,
                            [&](const T *xv, const T *yv, int64_t i0, int lim) {
-        acc_group<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
-                       CLS ? cls_out + i0 : nullptr);
+        if constexpr (Q)
+            acc_group_q<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
+                             CLS ? cls_out + i0 : nullptr, wl[threadIdx.x >> 6]);
+        else
+            acc_group<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
+                           CLS ? cls_out + i0 : nullptr);
     });
     if (skip) return;
 
@@ -206,7 +242,7 @@ __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__res
     }
 }
 
-template <class T, bool VEC, int U, bool CLS>
+template <class T, bool VEC, int U, bool CLS, bool Q>
 __global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
                                                const T *__restrict__ y,
                                                int64_t n, int key_mode,
@@ -214,7 +250,8 @@ __global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
                                                double *__restrict__ partials,
                                                unsigned char *__restrict__ cls_out)
 {
-    acc_body<T, VEC, U, CLS>(x, y, n, key_mode, ws, partials, cls_out, blockIdx.x, gridDim.x);
+    acc_body<T, VEC, U, CLS, Q>(x, y, n, key_mode, ws, partials, cls_out, blockIdx.x,
+                                gridDim.x);
 }
 
 // Combine the per-block partials of k_acc in a fixed order (one block).
@@ -352,15 +389,16 @@ __global__ __launch_bounds__(CUT_THREADS) void k_guard(Ws *__restrict__ ws,
 // suffices), and when it rises the slots of the entering bins are cleared
 // before anyone adds to them.  The candidate pieces are exact in any order
 // (s1_pieces), so LDS and global atomic adds give the same sums every run.
-// At the end each block adds its window into one of HIST_COPIES global
-// tables; k_s1_fin picks each kept bin's class and clears the tables.
+// At the end each block adds its window into one of `copies` global
+// tables; k_s1_cutfin selects the cutoff, picks each kept bin's class and
+// clears the tables.
 // ---------------------------------------------------------------------------
 template <class T, bool VEC, int U>
 __global__ __launch_bounds__(BLOCK) void k_s1_scan(const T *__restrict__ x,
                                                    const T *__restrict__ y,
                                                    int64_t n, int key_mode, int depth,
                                                    Ws *__restrict__ ws,
-                                                   double *__restrict__ tab)
+                                                   double *__restrict__ tab, int copies)
 {
     __shared__ unsigned int h[W + 1];
     __shared__ S1Lds S;
@@ -370,15 +408,16 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const T *__restrict__ x,
     s1_begin(S);
     __syncthreads();
 
-    int top = -1;  // highest live slot seen so far by the block (-1: none)
+    S1Run run = s1_run_start();
     unsigned int nz = 0, bad = 0;
     const int64_t group = (int64_t)CHUNK * U;
     s1_stream<VEC, U>(x, y, (int64_t)blockIdx.x * group, (int64_t)gridDim.x * group, n, key_mode,
-                      depth, h, S, top, nz, bad);
+                      depth, h, S, run, nz, bad);
+    const int top = run.top;  // highest live slot seen by the block (-1: none)
     __syncthreads();
 
     // histogram merge and live range, as in k_scan
-    unsigned long long *gh = ws->hist[blockIdx.x % HIST_COPIES];
+    unsigned long long *gh = ws->hist[blockIdx.x % copies];
     int lo = W, hi = -1;
     for (int i = tid; i < W; i += BLOCK) {
         const unsigned int v = h[i];
@@ -402,7 +441,7 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const T *__restrict__ x,
     }
     // window -> global table (bins top .. top - depth + 1, non-zero sums)
     if (top >= 0) {
-        double *tb = tab + (size_t)(blockIdx.x % HIST_COPIES) * W * S1_PIECES;
+        double *tb = tab + (size_t)(blockIdx.x % copies) * W * S1_PIECES;
         for (int i = tid; i < depth * S1_PIECES; i += BLOCK) {
             const int bin = top - i / S1_PIECES;
             if (bin < 0) continue;
@@ -418,31 +457,36 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const T *__restrict__ x,
     }
 }
 
-// One-pass mode, final step (one block): every kept bin contributes the
-// candidate sum of its class, summed over the table copies (exact), scaled
-// by 2^(k - e_max); the scaled total is summed with compensation and
-// rounded once.  The block then clears the tables over the live range for
-// the next call.
-__global__ __launch_bounds__(BLOCK) void k_s1_fin(const Ws *__restrict__ ws,
-                                                  double *__restrict__ tab,
-                                                  qdot_result *__restrict__ out)
+// One-pass mode, cutoff and pick in one workgroup: the cutoff of k_cut, then
+// (after a barrier, which makes the block's class-table stores visible to
+// all its threads) every kept bin contributes the candidate sum of its
+// class, summed over the table copies (exact), scaled by 2^(k - e_max); the
+// scaled total is summed with compensation and rounded once.  The block then
+// clears the tables over the live range for the next call.
+__global__ __launch_bounds__(CUT_THREADS) void k_s1_cutfin(Ws *__restrict__ ws, double tol,
+                                                           int score_mode, int nonstrict,
+                                                           int64_t n, int nscan, int mu_single,
+                                                           double *__restrict__ tab,
+                                                           qdot_result *__restrict__ out)
 {
-    __shared__ Acc red[3][BLOCK / 64];
-    const int tid = threadIdx.x;
+    __shared__ Acc red[3][CUT_THREADS / 64];
+    const CutParams p = cut_body(ws, tol, score_mode, nonstrict, n, nscan, 0, mu_single, out,
+                                 nullptr);
+    __syncthreads();
     const int lo = ws->s1_lo, hi = ws->s1_hi;
-    if (!ws->skip) {
+    if (!p.skip) {
         auto get = [&](int bin, int q) {
             double v = 0.0;
             for (int c = 0; c < HIST_COPIES; c++) v += tab[((size_t)c * W + bin) * S1_PIECES + q];
             return v;
         };
-        s1_pick(ws->e_max, lo, ws->flags, ws->lut, get, red, out);
+        s1_pick_nt<CUT_THREADS>(p.e_max, lo, p.flags, ws->lut, get, red, out);
     }
     if (hi >= lo) {
         const int64_t cnt = (int64_t)(hi - lo + 1) * S1_PIECES;
         for (int c = 0; c < HIST_COPIES; c++) {
             double *tb = tab + ((size_t)c * W + lo) * S1_PIECES;
-            for (int64_t i = tid; i < cnt; i += BLOCK) tb[i] = 0.0;
+            for (int64_t i = threadIdx.x; i < cnt; i += CUT_THREADS) tb[i] = 0.0;
         }
     }
 }
@@ -514,7 +558,7 @@ static int launch_scan_u(const Launch &L, const T *x, const T *y, int64_t n, int
 {
     const int grid = grid_for(n, U, L.scan_blocks);
     hipLaunchKernelGGL((k_scan<T, VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
-                       key_mode, L.ws);
+                       key_mode, L.ws, L.hist_copies);
     return grid;
 }
 
@@ -533,8 +577,12 @@ static int launch_acc_u(const Launch &L, const T *x, const T *y, int64_t n, int 
                         unsigned char *cls_out)
 {
     const int grid = grid_for(n, U, L.acc_blocks);
-    hipLaunchKernelGGL((k_acc<T, VEC, U, CLS>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
-                       key_mode, L.ws, L.partials, cls_out);
+    if (L.acc_form == 1)
+        hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, true>), dim3(grid), dim3(BLOCK), 0, L.stream,
+                           x, y, n, key_mode, L.ws, L.partials, cls_out);
+    else
+        hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, false>), dim3(grid), dim3(BLOCK), 0, L.stream,
+                           x, y, n, key_mode, L.ws, L.partials, cls_out);
     return grid;
 }
 
@@ -555,7 +603,7 @@ static int launch_s1_u(const Launch &L, const T *x, const T *y, int64_t n, int k
 {
     const int grid = grid_for(n, U, L.s1_blocks);
     hipLaunchKernelGGL((k_s1_scan<T, VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
-                       key_mode, depth, L.ws, L.s1tab);
+                       key_mode, depth, L.ws, L.s1tab, L.hist_copies);
     return grid;
 }
 
@@ -583,14 +631,13 @@ static hipError_t launch_qdot_s1(const Launch &L, const T *x, const T *y, int64_
     const int nscan = vec ? launch_s1<T, true>(L, x, y, n, o.key_mode, depth)
                           : launch_s1<T, false>(L, x, y, n, o.key_mode, depth);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
-    hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, nscan, 0, mu_single, out, nullptr);
+    hipLaunchKernelGGL(k_s1_cutfin, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
+                       o.boundary_mode, n, nscan, mu_single, L.s1tab, out);
     if (L.ev) {
         (void)hipEventRecord(L.ev[2], s);
         (void)hipEventRecord(L.ev[3], s);
+        (void)hipEventRecord(L.ev[4], s);
     }
-    hipLaunchKernelGGL(k_s1_fin, dim3(1), dim3(BLOCK), 0, s, L.ws, L.s1tab, out);
-    if (L.ev) (void)hipEventRecord(L.ev[4], s);
     return hipGetLastError();
 }
 
@@ -618,8 +665,13 @@ static hipError_t launch_qdot_t(const Launch &L, const T *x, const T *y, int64_t
                       : vec          ? launch_scan<T, true>(L, x, y, n, o.key_mode)
                                      : launch_scan<T, false>(L, x, y, n, o.key_mode);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
-    hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                       o.boundary_mode, n, nscan, guard, mu_single, out, hs);
+    if (o.bin_mode != 0)
+        hipLaunchKernelGGL(k_cut_bins, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol,
+                           o.score_mode, o.boundary_mode, n, nscan, mu_single, out, hs,
+                           o.bin_mode, o.bin_param);
+    else
+        hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
+                           o.boundary_mode, n, nscan, guard, mu_single, out, hs);
     if (L.ev) (void)hipEventRecord(L.ev[2], s);
     auto sweep = [&]() {
         int grid;
@@ -675,7 +727,7 @@ template <bool VEC, int U>
 __global__ __launch_bounds__(BLOCK) void k_scan_pair(const double *__restrict__ x,
                                                      const double *__restrict__ w, int64_t n,
                                                      int key_mode, Ws *__restrict__ wa,
-                                                     Ws *__restrict__ wb)
+                                                     Ws *__restrict__ wb, int copies)
 {
     __shared__ unsigned int h[2 * (W + 1)];
     for (int i = threadIdx.x; i < 2 * (W + 1); i += BLOCK) h[i] = 0;
@@ -701,8 +753,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_pair(const double *__restrict__ 
         }
     });
     __syncthreads();
-    scan_flush(ha, nza, bada, sga, wa, blockIdx.x);
-    scan_flush(hb, nzb, badb, sgb, wb, blockIdx.x);
+    scan_flush(ha, nza, bada, sga, wa, blockIdx.x, copies);
+    scan_flush(hb, nzb, badb, sgb, wb, blockIdx.x, copies);
 }
 
 __global__ __launch_bounds__(CUT_THREADS) void k_cut_pair(Ws *__restrict__ wa,
@@ -748,12 +800,15 @@ __global__ __launch_bounds__(BLOCK) void k_fin_pair(Ws *__restrict__ wa, Ws *__r
 template <bool VEC, int U>
 static hipError_t launch_pair_u(const Launch &La, const Launch &Lb, const double *x,
                                 const double *w, int64_t n, double tol, const qdot_options &o,
-                                qdot_result *out_a, qdot_result *out_b)
+                                qdot_result *out_a, qdot_result *out_b, int nscan_pre)
 {
     hipStream_t s = La.stream;
-    const int nscan = grid_for(n, U, La.scan_blocks);
-    hipLaunchKernelGGL((k_scan_pair<VEC, U>), dim3(nscan), dim3(BLOCK), 0, s, x, w, n,
-                       o.key_mode, La.ws, Lb.ws);
+    int nscan = nscan_pre;
+    if (nscan < 0) {
+        nscan = grid_for(n, U, La.scan_blocks);
+        hipLaunchKernelGGL((k_scan_pair<VEC, U>), dim3(nscan), dim3(BLOCK), 0, s, x, w, n,
+                           o.key_mode, La.ws, Lb.ws, La.hist_copies);
+    }
     if (o.guard_mode) {
         // the guard stages run per product, after the shared pass 1
         hipError_t e = launch_qdot_t<double>(La, x, w, n, tol, o, out_a, nullptr, nullptr, nscan);
@@ -774,24 +829,24 @@ static hipError_t launch_pair_u(const Launch &La, const Launch &Lb, const double
 template <bool VEC>
 static hipError_t launch_pair_v(const Launch &La, const Launch &Lb, const double *x,
                                 const double *w, int64_t n, double tol, const qdot_options &o,
-                                qdot_result *out_a, qdot_result *out_b)
+                                qdot_result *out_a, qdot_result *out_b, int nscan_pre)
 {
     // one unroll for both passes: the pass-1 kernel reads two operands per
     // key pair, like pass 2
     switch (unroll_for<double>(La.acc_unroll)) {
-    case 1: return launch_pair_u<VEC, 1>(La, Lb, x, w, n, tol, o, out_a, out_b);
-    case 4: return launch_pair_u<VEC, 4>(La, Lb, x, w, n, tol, o, out_a, out_b);
-    default: return launch_pair_u<VEC, 2>(La, Lb, x, w, n, tol, o, out_a, out_b);
+    case 1: return launch_pair_u<VEC, 1>(La, Lb, x, w, n, tol, o, out_a, out_b, nscan_pre);
+    case 4: return launch_pair_u<VEC, 4>(La, Lb, x, w, n, tol, o, out_a, out_b, nscan_pre);
+    default: return launch_pair_u<VEC, 2>(La, Lb, x, w, n, tol, o, out_a, out_b, nscan_pre);
     }
 }
 
 hipError_t launch_qdot_pair(const Launch &La, const Launch &Lb, const double *x,
                             const double *w, int64_t n, double tol, const qdot_options &o,
-                            qdot_result *out_a, qdot_result *out_b)
+                            qdot_result *out_a, qdot_result *out_b, int nscan_pre)
 {
     const bool vec = ((((uintptr_t)x) | ((uintptr_t)w)) & 15) == 0;
-    return vec ? launch_pair_v<true>(La, Lb, x, w, n, tol, o, out_a, out_b)
-               : launch_pair_v<false>(La, Lb, x, w, n, tol, o, out_a, out_b);
+    return vec ? launch_pair_v<true>(La, Lb, x, w, n, tol, o, out_a, out_b, nscan_pre)
+               : launch_pair_v<false>(La, Lb, x, w, n, tol, o, out_a, out_b, nscan_pre);
 }
 
 template <bool VEC, int U>

@@ -18,6 +18,8 @@ struct Launch {
     int acc_unroll;
     int s1_blocks;      // grid cap and unroll of the one-pass scan
     int s1_unroll;
+    int acc_form;       // accumulate pass: 0 every leaf formed in place, 1 compacting
+    int hist_copies;    // global histogram copies the scan blocks spread over (1..8)
     double *s1tab;      // one-pass mode: HIST_COPIES x W x S1_PIECES sums (zero between calls)
     hipEvent_t *ev;     // NULL, or events recorded around each kernel
 };
@@ -39,9 +41,11 @@ hipError_t launch_qdot(const Launch &L, const double *x, const double *y, int64_
 // kernel and the cutoffs, sweeps and combines of both in one launch each
 // (guard_mode 1: its stages per product after the shared pass 1).  La and
 // Lb differ only in their workspace; the partials of La hold both sweeps.
+// nscan_pre >= 0: pass 1 of both products already ran (into La.ws and
+// Lb.ws, nscan_pre block records each) in an earlier kernel on the stream.
 hipError_t launch_qdot_pair(const Launch &La, const Launch &Lb, const double *x,
                             const double *w, int64_t n, double tol, const qdot_options &o,
-                            qdot_result *out_a, qdot_result *out_b);
+                            qdot_result *out_a, qdot_result *out_b, int nscan_pre = -1);
 
 // The two-pass qdot of single-precision inputs (mu = m_single: no double
 // class); accum_mode and guard_mode must be 0.

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 
+#include "qdot_blocks.hpp"
 #include "qdot_handle.hpp"
 
 namespace qd {
@@ -112,6 +113,25 @@ __device__ __forceinline__ bool all_perforated(const qdot_result *r)
     return r && (r->flags & QDOT_F_ALL_PERF) && r->n_bins > 0;
 }
 
+// Pass 1 of the iteration's two inner products, lambda = x . w and c = w . w
+// (two-pass qdot), can ride in the SpMV, which forms both vectors row by
+// row: each row's keys go into a block-private LDS window of PM_HWIN slots
+// per product, placed below the previous iteration's e_max of that product
+// (PM_HWIN_ABOVE slots above it); a key outside the window, rare for the
+// slowly changing vectors of the method, goes straight into the block's
+// global histogram copy.  The windows are then merged as k_scan merges its
+// histogram, with the same per-block records, so the qdot kernels that
+// follow run without their own pass 1.
+constexpr int PM_HWIN = 512;
+constexpr int PM_HWIN_ABOVE = 64;
+
+struct PmScan {
+    Ws *ws[2];             // workspaces of x . w and w . w
+    const qdot_result *prev[2];  // previous iteration's results (window placement)
+    int key_mode;
+    int copies;
+};
+
 // Power method, iteration k: it first finishes iteration k - 1 (k > 0),
 // whose results lamval / cval are in device memory: breakdown, or lambda
 // recorded and x = w_{k-1} / sqrt(c).  It does not wait for that division
@@ -121,13 +141,17 @@ __device__ __forceinline__ bool all_perforated(const qdot_result *r)
 // from the same results; block 0 alone writes the control block (the others
 // read only its `done` word at their start, and a breakdown makes them
 // return whichever value they see).
+// With SCAN (k > 0) the SpMV also takes pass 1 of both inner products of
+// iteration k (PmScan).
+template <bool SCAN>
 __global__ __launch_bounds__(BLOCK) void k_pm_spmv(
     int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ src, double *__restrict__ w,
     double *__restrict__ x, SolverCtl *ctl, const double *lamval, const qdot_result *lamres,
-    const double *cval, const qdot_result *cres, double *__restrict__ trace, int k)
+    const double *cval, const qdot_result *cres, double *__restrict__ trace, int k, PmScan ps)
 {
     __shared__ double prod[SP_NZ];
+    __shared__ unsigned int hw[SCAN ? 2 : 1][SCAN ? PM_HWIN : 1];
     if (ctl->done) return;
     double sc = 1.0;
     if (k > 0) {
@@ -149,18 +173,66 @@ __global__ __launch_bounds__(BLOCK) void k_pm_spmv(
         }
         sc = sqrt(c);
     }
-    if (k == 0)
-        spmv_lds(
-            n, rowptr, col, val, [&](int32_t c) { return src[c]; },
-            [&](int64_t i, double yi) { w[i] = yi; }, prod);
-    else
+    if constexpr (!SCAN) {
+        if (k == 0)
+            spmv_lds(
+                n, rowptr, col, val, [&](int32_t c) { return src[c]; },
+                [&](int64_t i, double yi) { w[i] = yi; }, prod);
+        else
+            spmv_lds(
+                n, rowptr, col, val, [&](int32_t c) { return src[c] / sc; },
+                [&](int64_t i, double yi) {
+                    w[i] = yi;
+                    x[i] = src[i] / sc;
+                },
+                prod);
+    } else {
+        int base[2];
+        unsigned long long *gh[2];
+        unsigned int nz[2] = {0u, 0u}, bad[2] = {0u, 0u}, sg[2] = {0u, 0u};
+        int lo[2] = {W, W}, hi[2] = {-1, -1};
+        for (int p = 0; p < 2; p++) {
+            const qdot_result *pr = ps.prev[p];
+            const int top = (pr->status == QDOT_OK && pr->n_bins > 0)
+                                ? pr->e_max - KMIN + PM_HWIN_ABOVE
+                                : W / 2;
+            base[p] = max(0, min(W - PM_HWIN, top - PM_HWIN + 1));
+            gh[p] = ps.ws[p]->hist[blockIdx.x % ps.copies];
+            for (int j = threadIdx.x; j < PM_HWIN; j += BLOCK) hw[p][j] = 0u;
+        }
+        __syncthreads();
+        auto key = [&](int p, double a, double b) {
+            const Comp c = component(a, b, ps.key_mode);
+            nz[p] += c.zero ? 1u : 0u;
+            bad[p] |= c.bad ? 1u : 0u;
+            sg[p] |= c.zero ? 0u : (c.sgn ? 1u : 2u);
+            if (c.slot == ZERO_SLOT) return;
+            const int j = c.slot - base[p];
+            if ((unsigned)j < (unsigned)PM_HWIN) {
+                atomicAdd(&hw[p][j], 1u);
+            } else {
+                atomicAdd(&gh[p][c.slot], 1ull);
+                lo[p] = min(lo[p], c.slot);
+                hi[p] = max(hi[p], c.slot);
+            }
+        };
         spmv_lds(
             n, rowptr, col, val, [&](int32_t c) { return src[c] / sc; },
             [&](int64_t i, double yi) {
                 w[i] = yi;
-                x[i] = src[i] / sc;
+                const double xi = src[i] / sc;
+                x[i] = xi;
+                key(0, xi, yi);
+                key(1, yi, yi);
             },
             prod);
+        __syncthreads();
+        for (int p = 0; p < 2; p++) {
+            scan_flush_window(hw[p], base[p], PM_HWIN, lo[p], hi[p], nz[p], bad[p], sg[p],
+                              ps.ws[p], blockIdx.x, ps.copies);
+            __syncthreads();
+        }
+    }
 }
 
 static int spmv_grid(const qdot_handle *h, int64_t n)
@@ -314,6 +386,8 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     std::memset(&o, 0, sizeof o);
     if (opt) o = *opt;
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
+    if (o.bin_mode != 0)
+        return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
     if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
     if (use_qdot && o.accum_mode == 1 && !s1_admissible(A->n, qtol, o))
@@ -351,14 +425,24 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     for (; k < iters && e == hipSuccess; k++) {
         double *w = wbuf[k & 1];
         const double *src = k == 0 ? x : wbuf[(k - 1) & 1];
-        hipLaunchKernelGGL(k_pm_spmv, dim3(sg), dim3(BLOCK), 0, s, n, A->rowptr, A->col, A->val,
-                           src, w, x, ctl, lv, lr, cv, cr, lambda_trace, k);
         // the qdot results of iteration k: straight into the caller's trace
         // when one is given, else the handle's two slots
         qdot_result *ra = trace && use_qdot ? trace + 2 * (int64_t)k : h->res_ring;
         qdot_result *rb = ra + 1;
+        // after the first iteration the paired qdot's pass 1 rides in the
+        // SpMV (its windows placed by the previous iteration's results)
+        const bool fused = paired && k > 0;
+        const PmScan ps = {{L.ws, L2.ws}, {lr, cr}, o.key_mode, L.hist_copies};
+        if (fused)
+            hipLaunchKernelGGL(k_pm_spmv<true>, dim3(sg), dim3(BLOCK), 0, s, n, A->rowptr,
+                               A->col, A->val, src, w, x, ctl, lv, lr, cv, cr, lambda_trace, k,
+                               ps);
+        else
+            hipLaunchKernelGGL(k_pm_spmv<false>, dim3(sg), dim3(BLOCK), 0, s, n, A->rowptr,
+                               A->col, A->val, src, w, x, ctl, lv, lr, cv, cr, lambda_trace, k,
+                               ps);
         if (paired) {
-            ok(launch_qdot_pair(L, L2, x, w, n, qtol, o, ra, rb));
+            ok(launch_qdot_pair(L, L2, x, w, n, qtol, o, ra, rb, fused ? sg : -1));
             lv = &ra->value;
             lr = ra;
             cv = &rb->value;

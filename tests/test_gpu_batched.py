@@ -12,7 +12,8 @@ import pytest
 
 import oracle
 import workloads
-from parity_util import check_instances, host
+import parity_util
+from parity_util import host
 
 torch = pytest.importorskip("torch")
 import paper_2105_00115_amd as q  # noqa: E402
@@ -171,5 +172,25 @@ def test_batched_c5_full_size(h, accum):
     res = h.batched(xd, yd, offsets, tols, opt=opt)
     xh, yh = host(xd), host(yd)
     del xd, yd
-    assert check_instances(res, offsets, xh, yh, tols, opt=opt) == 4096
+    assert parity_util.check_instances(res, offsets, xh, yh, tols, opt=opt) == 4096
     assert sum(sum(r["count"]) for r in res) == total
+
+
+@pytest.mark.parametrize("shape", [(2, 65536), (8, 262144), (4, 8192)])
+def test_batched_under_other_batch_shapes(shape):
+    # blocks per CU and chunk size move work between blocks and items but
+    # never a tile or a class: every instance still equals the oracle's
+    bpc, chunk = shape
+    with q.Qdot(0, load_tuned=False) as hh:
+        hh.set_batch_tune(blocks_per_cu=bpc, chunk=chunk)
+        assert hh.get_batch_tune()[:2] == (bpc, chunk)
+        offsets, x, y, tols = ragged_case(31, EDGE + (300000,), count=40)
+        for opt in (None, [0, 0, 0, 1]):
+            res = hh.batched(dev(x), dev(y), offsets, tols, opt=opt)
+            check_instances(res, offsets, x, y, tols, opt=opt)
+        hh.set_batch_tune()
+        assert hh.get_batch_tune() == (4, 131072, 16384, 16)
+        with pytest.raises(q.QdotError):
+            hh.set_batch_tune(chunk=1000)  # not a multiple of 2048
+        with pytest.raises(q.QdotError):
+            hh.set_batch_tune(cg_gang_max=513)

@@ -233,3 +233,22 @@ def test_full_size_c5_launch(h):
     # every instance against the oracle on that instance alone
     xh, yh = host(xd), host(yd)
     assert check_instances(res, offsets, xh, yh, tols) == 4096
+
+
+@pytest.mark.parametrize("rows,gmax", [(4096, 64), (1024, 8)])
+def test_cg_batched_gang_sizing(rows, gmax):
+    # other gang sizes: every system still takes its FP64 twin's iteration
+    # count and stays within one of the oracle's
+    with q.Qdot(0, load_tuned=False) as hh:
+        hh.set_batch_tune(cg_rows_per_block=rows, cg_gang_max=gmax)
+        sides = (45, 140, 256)
+        sq = [poisson_system(m, 300 + m, 1) for m in sides]
+        sf = [poisson_system(m, 300 + m, 0) for m in sides]
+        res = hh.cg_batched([as_tuple(s) for s in sq + sf])
+        for i, m in enumerate(sides):
+            rq, rf = res[i], res[len(sides) + i]
+            assert rq["status"] == q.OK and rf["status"] == q.OK, (m, rq, rf)
+            assert rq["iters"] == rf["iters"], (m, rq["iters"], rf["iters"])
+            rp, col, val = sq[i]["csr"]
+            o = oracle.cg(rp, col, val, sq[i]["b_host"], 1e-10, 1e-8, 20000, 1)
+            assert abs(o["iters"] - rq["iters"]) <= 1, (m, o["iters"], rq["iters"])

@@ -181,9 +181,15 @@ def test_wide_range_cancelling_sums(h, seed):
     for tol in (1e-3, 1e-6, 1e-10):
         r, o = compare(h, x, y, tol, opt=GUARD)
         assert np.isfinite(r["value"]) and r["flags"] & q.F_RESELECTED
-    for opt in (None, [0, 0, 0, 1]):
-        r, o = compare(h, x, y, 1e-300, opt=opt, classes=opt is None)
-        assert r["flags"] & q.F_UNATTAINABLE and r["count"][q.SINGLE] == 4001
+    r, o = compare(h, x, y, 1e-300)
+    assert r["flags"] & q.F_UNATTAINABLE and r["count"][q.SINGLE] == 4001
+    # the one-pass mode: 1e-300 would put kept bins beyond its window of 256
+    # exponents (refused on the host); 1e-60 is admitted and holds the top
+    # bins at the input precision
+    with pytest.raises(q.QdotError):
+        h.qdot_f32(devf(x), devf(y), 1e-300, opt=[0, 0, 0, 1])
+    r, o = compare(h, x, y, 1e-60, opt=[0, 0, 0, 1], classes=False)
+    assert np.isfinite(r["value"]) and r["flags"] & q.F_UNATTAINABLE
 
 
 S1 = [0, 0, 0, 1]

@@ -202,9 +202,11 @@ def test_repeat_and_tuning_invariance(h):
     assert again["value"] == base["value"]  # same launch configuration: bitwise
     o = oracle.qdot(x, y, 1e-6)
     scale = oracle.abs_dot(x, y)
-    for sb, su, ab, au in [(1, 1, 1, 1), (2, 2, 8, 4), (8, 4, 2, 2), (16, 1, 16, 2),
-                           (4, 2, 1, 4)]:
-        h.set_tune(-1, sb, su, ab, au)
+    # launch shapes, both forms of the accumulate pass, histogram copies
+    for sb, su, ab, au, af, hc in [(1, 1, 1, 1, 0, 8), (2, 2, 8, 4, 1, 8), (8, 4, 2, 2, 1, 1),
+                                   (16, 1, 16, 2, 0, 2), (4, 2, 1, 4, 1, 4),
+                                   (2, 1, 2, 2, 1, 8)]:
+        h.set_tune(-1, sb, su, ab, au, 4, 1, af, hc)
         cls, hist, r = h.qdot_classes(xd, yd, 1e-6)
         assert torch.equal(cls, base_cls) and torch.equal(hist, base_hist)
         assert r["count"] == base["count"]
@@ -214,17 +216,24 @@ def test_repeat_and_tuning_invariance(h):
 
 def test_tune_file_loading(h, tmp_path):
     good = tmp_path / "good.txt"
-    good.write_text("# comment\n0 1 1 2 2\n3 8 4 16 1  # trailing comment\n2 1 2 4 4 8 2\n\n")
+    good.write_text("# comment\n0 1 1 2 2\n3 8 4 16 1  # trailing comment\n2 1 2 4 4 8 2\n"
+                    "1 2 1 2 2 4 1 1 4\n\n")
     h.reset_tune()
     d0 = h.get_tune(0)
+    d2 = h.get_tune(2)
     h.load_tune(str(good))
-    # a 5-column line leaves the one-pass shape as it was
+    # a 5-column line leaves the one-pass shape and the rest as they were
     assert h.get_tune(0) == (1, 1, 2, 2) + d0[4:] and h.get_tune(3)[:4] == (8, 4, 16, 1)
-    assert h.get_tune(2) == (1, 2, 4, 4, 8, 2)
-    bad = tmp_path / "bad.txt"
-    bad.write_text("1 2 3 4 5\n")  # unroll 3 is not allowed
-    with pytest.raises(q.QdotError):
-        h.load_tune(str(bad))
+    assert h.get_tune(2) == (1, 2, 4, 4, 8, 2) + d2[6:]
+    assert h.get_tune(1) == (2, 1, 2, 2, 4, 1, 1, 4)
+    for line in ("1 2 3 4 5\n",            # unroll 3 is not allowed
+                 "1 2 1 2 2 4 1 2 8\n",    # acc_form 2
+                 "1 2 1 2 2 4 1 0 3\n",    # 3 histogram copies
+                 "1 2 1 2 2 4 1 0\n"):     # 8 columns
+        bad = tmp_path / "bad.txt"
+        bad.write_text(line)
+        with pytest.raises(q.QdotError):
+            h.load_tune(str(bad))
     assert h.get_tune(1) == h.get_tune(1)  # unchanged, still readable
     with pytest.raises(q.QdotError):
         h.load_tune(str(tmp_path / "missing.txt"))
@@ -340,15 +349,22 @@ def test_timing_api(h):
 
 
 def test_autotuner_on_small_buckets(tmp_path):
-    # a short sweep of the two smallest buckets: every shape must reproduce
-    # the reference integer outputs (the tuner checks it), the file must load
-    # back, and the tuned handle must give the same counts as the defaults
+    # a short sweep of the two smallest buckets: every swept shape (grid,
+    # groups in flight, both accumulate forms, 1/2/4/8 histogram copies, the
+    # one-pass grid) must reproduce the reference classes and histogram bit
+    # for bit (the tuner compares them and raises otherwise), the file must
+    # load back, and the tuned handle must give the same counts as the
+    # defaults
     from paper_2105_00115_amd import autotune
-    handle, chosen = autotune.tune(reps=2, buckets=[0, 1], log=lambda m: None)
+    handle, chosen, checked = autotune.tune(reps=2, buckets=[0, 1], log=lambda m: None)
     path = str(tmp_path / "tune.txt")
-    autotune.write(path, chosen, "gfx950", handle.device_info()[1])
+    autotune.write(path, chosen, "gfx950", handle.device_info()[1], batch=(4, 131072, 16384, 16))
     handle.close()
     assert [c[0] for c in chosen] == [0, 1]
+    # per bucket: 15 grid shapes, up to 1 mixed, 7 form/copies shapes, 1 final
+    assert checked >= 2 * (15 + 7 + 1)
+    for c in chosen:
+        assert c[2][6] in autotune.ACC_FORM and c[2][7] in autotune.HIST_COPIES
     with q.Qdot(0, load_tuned=False) as tuned, q.Qdot(0, load_tuned=False) as plain:
         tuned.load_tune(path)
         for n in (30000, 500000):
