@@ -157,7 +157,7 @@ typedef struct qdot_options {
      * class holds for all its keys, N_bins counts the non-empty bins and the
      * Thm 3.3 term of a bin is M_k 2^(u_k - e_max + 1) eps(class).  Modes 1
      * and 2 need accum_mode 0 and guard_mode 0 and are accepted by
-     * qdot_async, qdot, qdot_classes_async and the
+     * qdot_async, qdot, qdot_classes_async, qdot_noalloc_async and the
      * qdot_f32 entry points; QDOT_E_INVAL elsewhere. */
     int32_t bin_mode;
     int32_t bin_param;
@@ -302,6 +302,28 @@ QDOT_API int32_t qdot_timing_read(qdot_handle *h, double ms[5], int32_t calls[2]
 QDOT_API int32_t qdot_async(qdot_handle *h, const double *x, const double *y,
                    int64_t n, double tol, const qdot_options *opt,
                    void *stream, qdot_result *dev_out);
+
+/* qdot_async without a handle and without any allocation, for callers that
+ * cannot allocate device memory: code recorded under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments
+ * (minus the handle), options, kernels, results and async errors as
+ * qdot_async, on the current device, with the default launch shapes.
+ *   Workspace: a fixed device array of about 2.2 MB inside the library
+ *   (control block and histograms ~0.35 MB, partials for 4096 blocks,
+ *   one-pass per-bin tables), one copy per GPU, held until the process
+ *   ends.  Its size does not depend on n: every grid of the call is capped
+ *   to the partials it holds, so no n is refused for lack of room (n is
+ *   limited only as for qdot_async; accum_mode 1 needs n <= 2^30).
+ *   The first call on a device also clears that device's array, in order
+ *   on `stream`.  Every call on one GPU shares its array: calls must be
+ *   ordered (one stream, or synchronised); calls that overlap on one GPU
+ *   race and give wrong results.
+ * Returns QDOT_E_INVAL for the argument errors of qdot_async or a NULL
+ * dev_out, QDOT_E_DEVICE when a HIP call fails (no message is kept: there
+ * is no handle).  Performs no hipMalloc, hipFree or host sync. */
+QDOT_API int32_t qdot_noalloc_async(const double *x, const double *y, int64_t n,
+                           double tol, const qdot_options *opt, void *stream,
+                           qdot_result *dev_out);
 
 /* Synchronous qdot: as qdot_async, then copies the result to host_out and
  * synchronises the stream.  Returns the result's status (QDOT_OK or

@@ -119,6 +119,7 @@ SIGNATURES = [
     ("qdot_timing_read", _i32, [_vp, C.POINTER(_d), C.POINTER(_i32)]),
     ("qdot_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp]),
     ("qdot", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, C.POINTER(QdotResult)]),
+    ("qdot_noalloc_async", _i32, [_vp, _vp, _i64, _d, _OPT, _vp, _vp]),
     ("qdot_simple", _i32, [_vp, _vp, _i64, _d, C.POINTER(_d), C.POINTER(_i64)]),
     ("qdot_classes_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp, _vp, _vp]),
     ("qdot_f32_async", _i32, [_vp, _vp, _vp, _i64, _d, _OPT, _vp, _vp]),
@@ -245,6 +246,20 @@ def qdot_simple(x, y, tol):
     if st not in (OK, E_NONFINITE):
         raise QdotError(st, "qdot_simple")
     return v.value, list(counts)
+
+
+def qdot_noalloc_async(x, y, tol, out, opt=None, stream=None):
+    """The library's allocation-free qdot (no handle; the workspace is a
+    fixed device array inside the library).  out: CUDA uint8 tensor of
+    RESULT_BYTES (or an integer device address), written in stream order
+    on the current device."""
+    _check_vec(x, "x")
+    _check_vec(y, "y")
+    dst = C.c_void_p(out if isinstance(out, int) else out.data_ptr())
+    st = lib().qdot_noalloc_async(_ptr(x), _ptr(y), x.numel(), float(tol), _opts(opt),
+                                  _stream(stream), dst)
+    if st != OK:
+        raise QdotError(st, "qdot_noalloc_async")
 
 
 def tuned_file(device: int = 0):
