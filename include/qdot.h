@@ -232,12 +232,18 @@ typedef struct qdot_tune {
     int32_t acc_unroll;
     int32_t onepass_blocks_per_cu; /* one-pass scan (accum_mode 1), 1..16 */
     int32_t onepass_unroll;
-    int32_t acc_form;    /* accumulate pass: 0 every candidate leaf formed in
-                            place, 1 kept components compacted per wave and
-                            their leaves formed 64 at a time (same tile
-                            sums bit for bit) */
-    int32_t hist_copies; /* global histogram copies the scan blocks spread
-                            their merges over: 1, 2, 4 or 8 */
+    int32_t acc_form;    /* accumulate pass of double inputs: 0 every
+                            candidate leaf formed in place, 1 kept
+                            components compacted per wave and their leaves
+                            formed 64 at a time (same tile sums bit for
+                            bit); float inputs use 0 */
+    int32_t hist_copies; /* global histogram copies the scan blocks of
+                            double inputs spread their merges over: 1, 2, 4
+                            or 8; float inputs use 8 */
+    int32_t block_threads; /* threads per block of the scan and accumulate
+                              passes of aligned double inputs: 128, 256 or
+                              512 (the blocks-per-CU fields count blocks of
+                              256 threads); other inputs use 256 */
 } qdot_tune;
 
 /* Tuning is kept per size bucket: n < 2^16, < 2^20, < 2^24, >= 2^24. */
@@ -268,9 +274,11 @@ QDOT_API int32_t qdot_get_tune(const qdot_handle *h, int32_t bucket, qdot_tune *
 
 /* Load tuned configurations from a text file written by the autotuner: one
  * line per bucket, "bucket scan_bpc scan_unroll acc_bpc acc_unroll
- * [onepass_bpc onepass_unroll [acc_form hist_copies]]" (fields left out keep
- * the bucket's current values), and optionally one line "batch
- * blocks_per_cu chunk cg_rows_per_block cg_gang_max" (qdot_batch_tune);
+ * [onepass_bpc onepass_unroll [acc_form hist_copies [block_threads]]]" (fields left out keep
+ * the bucket's current values), and optionally one line "solver
+ * batch_bpc batch_chunk cg_rows_per_block cg_gang_max spmv_bpc cg_bpc
+ * power_scan_in_spmv"
+ * (qdot_solver_tune);
  * '#' starts a comment.  Invalid lines are
  * rejected with QDOT_E_INVAL and leave the handle unchanged.  qdot_create
  * also loads the file named by the environment variable QDOT_TUNE_FILE when
@@ -411,28 +419,40 @@ QDOT_API int32_t qdot_batched_async(qdot_handle *h, const double *x_cat,
                                     int32_t B, const qdot_options *opt, void *stream,
                                     qdot_result *dev_out);
 
-/* Launch shape of the batched launch (qdot_batched_async,
- * qdot_batch_run_async, qdot_cg_batched).  Chosen by the autotuner; the
- * defaults are {4, 131072, 16384, 16}. */
-typedef struct qdot_batch_tune {
-    int32_t blocks_per_cu;     /* persistent grid: blocks per CU, 1..16 (the
-                                  resident ones are capped by occupancy) */
-    int32_t chunk;             /* components per pass-1 / pass-2 chunk of a
-                                  large instance, and the largest instance one
-                                  block takes whole: 2^13..2^22, a multiple of
-                                  2048 */
-    int32_t cg_rows_per_block; /* a CG system of n rows gets ceil(n / this)
-                                  gang blocks, >= 1024 ... */
+/* Launch shapes of the solvers and the batched launch.  Chosen by the
+ * autotuner; the defaults are {4, 131072, 16384, 16, 8, 2, 0}. */
+typedef struct qdot_solver_tune {
+    int32_t batch_blocks_per_cu; /* batched launch (qdot_batched_async,
+                                    qdot_batch_run_async, qdot_cg_batched):
+                                    persistent grid, blocks per CU, 1..16
+                                    (the resident ones are capped by
+                                    occupancy) */
+    int32_t batch_chunk;       /* components per pass-1 / pass-2 chunk of a
+                                  large batched instance, and the largest
+                                  instance one block takes whole: 2^13..2^22,
+                                  a multiple of 2048 */
+    int32_t cg_rows_per_block; /* a batched CG system of n rows gets
+                                  ceil(n / this) gang blocks, >= 1024 ... */
     int32_t cg_gang_max;       /* ... and at most this many, 1..512 */
-} qdot_batch_tune;
+    int32_t spmv_blocks_per_cu; /* SpMV grid (qdot_spmv_async, the power
+                                   method), blocks per CU, 1..16 */
+    int32_t cg_blocks_per_cu;  /* qdot_cg: gang blocks per CU, 1..2 (capped by
+                                  occupancy and by one block per 1024 rows) */
+    int32_t power_scan_in_spmv; /* qdot_power, two-pass qdot: 1 takes pass 1
+                                   of both inner products inside the SpMV
+                                   after the first iteration, 0 in a kernel
+                                   of its own (same results) */
+} qdot_solver_tune;
 
-/* Set (cfg NULL: defaults) or read the handle's batched launch shape.
- * Setting it frees the handle's cached batch plans (after a device sync);
- * out-of-range values return QDOT_E_INVAL and change nothing.  No value of
- * it changes a result: instances are split along whole 2048-component
- * groups, so every 64-element tile and class is the same. */
-QDOT_API int32_t qdot_set_batch_tune(qdot_handle *h, const qdot_batch_tune *cfg);
-QDOT_API int32_t qdot_get_batch_tune(const qdot_handle *h, qdot_batch_tune *cfg);
+/* Set (cfg NULL: defaults) or read the handle's solver and batched launch
+ * shapes.  Setting them frees the handle's cached batch plans (after a
+ * device sync); out-of-range values return QDOT_E_INVAL and change
+ * nothing.  No value changes a class, a count or an FP32 tile sum
+ * (instances and row slices are split along whole 2048-component groups);
+ * values move only by the order of compensated FP64 sums, and a CG
+ * iteration count only as far as that moves its stopping test. */
+QDOT_API int32_t qdot_set_solver_tune(qdot_handle *h, const qdot_solver_tune *cfg);
+QDOT_API int32_t qdot_get_solver_tune(const qdot_handle *h, qdot_solver_tune *cfg);
 
 /* Plan a batched layout ahead of time (e.g. before capturing
  * qdot_batched_async into a graph).  Synchronous. */
@@ -448,7 +468,7 @@ QDOT_API int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets,
  * kernel launch.  Each CG system follows qdot_cg on that system alone (Alg.
  * 4 with the same stopping rule and the same inner products); it is solved
  * by a gang of blocks (one per cg_rows_per_block rows, at most cg_gang_max:
- * qdot_batch_tune) that meet at barriers,
+ * qdot_solver_tune) that meet at barriers,
  * gangs are formed before the qdot work items are handed out, largest
  * system first.  dev_cg_out: device qdot_cg_result[S].  Planning happens on
  * the first call with a new layout (offsets and system descriptors,

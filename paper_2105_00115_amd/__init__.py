@@ -86,12 +86,18 @@ class QdotTune(C.Structure):
     _fields_ = [("scan_blocks_per_cu", C.c_int32), ("scan_unroll", C.c_int32),
                 ("acc_blocks_per_cu", C.c_int32), ("acc_unroll", C.c_int32),
                 ("onepass_blocks_per_cu", C.c_int32), ("onepass_unroll", C.c_int32),
-                ("acc_form", C.c_int32), ("hist_copies", C.c_int32)]
+                ("acc_form", C.c_int32), ("hist_copies", C.c_int32),
+                ("block_threads", C.c_int32)]
 
 
-class QdotBatchTune(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int32), ("chunk", C.c_int32),
-                ("cg_rows_per_block", C.c_int32), ("cg_gang_max", C.c_int32)]
+class QdotSolverTune(C.Structure):
+    _fields_ = [("batch_blocks_per_cu", C.c_int32), ("batch_chunk", C.c_int32),
+                ("cg_rows_per_block", C.c_int32), ("cg_gang_max", C.c_int32),
+                ("spmv_blocks_per_cu", C.c_int32), ("cg_blocks_per_cu", C.c_int32),
+                ("power_scan_in_spmv", C.c_int32)]
+
+
+SOLVER_TUNE_FIELDS = tuple(f for f, _ in QdotSolverTune._fields_)
 
 
 TUNE_BUCKETS = 4  # n < 2^16, < 2^20, < 2^24, >= 2^24
@@ -128,8 +134,8 @@ SIGNATURES = [
     ("qdot_fp64_dot_async", _i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
     ("qdot_batched_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32, _OPT,
                                   _vp, _vp]),
-    ("qdot_set_batch_tune", _i32, [_vp, C.POINTER(QdotBatchTune)]),
-    ("qdot_get_batch_tune", _i32, [_vp, C.POINTER(QdotBatchTune)]),
+    ("qdot_set_solver_tune", _i32, [_vp, C.POINTER(QdotSolverTune)]),
+    ("qdot_get_solver_tune", _i32, [_vp, C.POINTER(QdotSolverTune)]),
     ("qdot_batched_plan", _i32, [_vp, C.POINTER(_i64), _i32]),
     ("qdot_batch_run_async", _i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), _vp, _i32,
                                     C.POINTER(QdotCgSystem), _i32, _OPT, _vp, _vp, _vp]),
@@ -316,10 +322,10 @@ class Qdot:
 
     def set_tune(self, bucket: int, scan_bpc: int, scan_unroll: int, acc_bpc: int,
                  acc_unroll: int, onepass_bpc: int = 4, onepass_unroll: int = 1,
-                 acc_form: int = 0, hist_copies: int = 8):
+                 acc_form: int = 0, hist_copies: int = 8, block_threads: int = 256):
         """bucket -1 sets all size buckets."""
         cfg = QdotTune(scan_bpc, scan_unroll, acc_bpc, acc_unroll, onepass_bpc, onepass_unroll,
-                       acc_form, hist_copies)
+                       acc_form, hist_copies, block_threads)
         st = lib().qdot_set_tune(self._h, int(bucket), C.byref(cfg))
         if st != OK:
             self._raise(st, "qdot_set_tune")
@@ -333,28 +339,32 @@ class Qdot:
         if st != OK:
             raise QdotError(st, "qdot_get_tune")
         return (t.scan_blocks_per_cu, t.scan_unroll, t.acc_blocks_per_cu, t.acc_unroll,
-                t.onepass_blocks_per_cu, t.onepass_unroll, t.acc_form, t.hist_copies)
+                t.onepass_blocks_per_cu, t.onepass_unroll, t.acc_form, t.hist_copies,
+                t.block_threads)
 
-    def set_batch_tune(self, blocks_per_cu=None, chunk=None, cg_rows_per_block=None,
-                       cg_gang_max=None):
-        """Launch shape of the batched launch; None keeps a field, no
-        argument at all restores the defaults."""
-        if all(v is None for v in (blocks_per_cu, chunk, cg_rows_per_block, cg_gang_max)):
-            st = lib().qdot_set_batch_tune(self._h, None)
+    def set_solver_tune(self, **fields):
+        """Launch shapes of the solvers and the batched launch (fields of
+        QdotSolverTune); fields not given keep their values, no argument
+        at all restores the defaults."""
+        if not fields:
+            st = lib().qdot_set_solver_tune(self._h, None)
         else:
-            cur = self.get_batch_tune()
-            cfg = QdotBatchTune(*[cur[i] if v is None else int(v) for i, v in enumerate(
-                (blocks_per_cu, chunk, cg_rows_per_block, cg_gang_max))])
-            st = lib().qdot_set_batch_tune(self._h, C.byref(cfg))
+            bad = set(fields) - set(SOLVER_TUNE_FIELDS)
+            if bad:
+                raise ValueError(f"unknown solver tune fields {sorted(bad)}")
+            cur = dict(zip(SOLVER_TUNE_FIELDS, self.get_solver_tune()))
+            cur.update({k: int(v) for k, v in fields.items()})
+            cfg = QdotSolverTune(*[cur[f] for f in SOLVER_TUNE_FIELDS])
+            st = lib().qdot_set_solver_tune(self._h, C.byref(cfg))
         if st != OK:
-            self._raise(st, "qdot_set_batch_tune")
+            self._raise(st, "qdot_set_solver_tune")
 
-    def get_batch_tune(self):
-        t = QdotBatchTune()
-        st = lib().qdot_get_batch_tune(self._h, C.byref(t))
+    def get_solver_tune(self):
+        t = QdotSolverTune()
+        st = lib().qdot_get_solver_tune(self._h, C.byref(t))
         if st != OK:
-            raise QdotError(st, "qdot_get_batch_tune")
-        return (t.blocks_per_cu, t.chunk, t.cg_rows_per_block, t.cg_gang_max)
+            raise QdotError(st, "qdot_get_solver_tune")
+        return tuple(getattr(t, f) for f in SOLVER_TUNE_FIELDS)
 
     def load_tune(self, path: str):
         st = lib().qdot_load_tune(self._h, os.fsencode(path))

@@ -8,6 +8,7 @@ kernel timing over
 * the two forms of the accumulate pass (every candidate leaf formed in
   place, or the kept components compacted per wave),
 * the number of global histogram copies the scan blocks merge into,
+* the threads per block of both passes (128, 256, 512),
 * the one-pass scan's grid and groups in flight,
 
 and keeps the fastest.  Every swept shape must reproduce the reference
@@ -16,9 +17,12 @@ counts, t and flags); the one-pass value, an exact sum, must be the same
 bits.  The tile structure makes that hold for every shape; the tuner checks
 it for each one rather than assuming it.
 
-Batched launch: blocks per CU and the chunk size on a ragged batch (counts
-bit for bit, values within 1e-13 of the reference run's scale), and the CG
-gang sizing (rows per gang block, largest gang) on a batch of CG systems.
+Solvers and batched launch, each on the benchmark workload it serves:
+blocks per CU and the chunk size on the 4096 ragged instances (counts, t
+and flags of every instance bit for bit), the CG gang sizing (rows per gang
+block, largest gang) on the 256 CG systems launched with them, the SpMV
+grid (the product bit for bit), whether the power method takes pass 1 in
+its SpMV (lambda bit for bit) and the single-system CG gang.
 
 The result is a text file that ``qdot_load_tune`` reads; ``Qdot()`` loads
 ``tune/<arch>_<cus>cu.txt`` next to this module when it exists.
@@ -37,10 +41,14 @@ BPC = (1, 2, 4, 8, 16)
 UNROLL = (1, 2, 4)
 ACC_FORM = (0, 1)
 HIST_COPIES = (1, 2, 4, 8)
-BATCH_BPC = (2, 4, 8)
+BLOCK_THREADS = (128, 256, 512)
+MARGIN = 0.02  # a non-default form must be this much faster to be kept
+BATCH_BPC = (2, 4)
 BATCH_CHUNK = (65536, 131072, 262144)
 CG_ROWS = (8192, 16384, 32768)
-CG_GANG_MAX = (16, 32, 64)
+CG_GANG_MAX = (8, 16, 32)
+SPMV_BPC = (2, 4, 8, 16)
+CG_BPC = (1, 2)
 
 
 def default_path(arch: str, cus: int) -> str:
@@ -102,31 +110,47 @@ def tune(reps: int = 20, seed: int = 7, tol: float = 1e-6, log=print, buckets=No
         x, y = workloads.log_uniform_pair_torch(n, seed + b, dev)
         ref_cls, ref_hist, ref = h.qdot_classes(x, y, tol)
         d1 = h.get_tune(b)[4:6]
-        # grid and groups in flight of both passes (dense form, 8 copies)
+        # grid and groups in flight of both passes (dense form, 8 copies,
+        # 256 threads per block)
         results = {}
         for bpc in BPC:
             for u in UNROLL:
-                cfg = (bpc, u, bpc, u) + d1 + (0, 8)
+                cfg = (bpc, u, bpc, u) + d1 + (0, 8, 256)
                 results[cfg] = _time_config(h, x, y, tol, out, cfg, reps)
                 _check_same(h, x, y, tol, cfg, ref_cls, ref_hist, ref)
                 checked += 1
         best_scan = min(results, key=lambda c: results[c][0])[:2]
         best_acc = min(results, key=lambda c: results[c][2])[2:4]
-        mixed = best_scan + best_acc + d1 + (0, 8)
+        mixed = best_scan + best_acc + d1 + (0, 8, 256)
         if mixed not in results:
             results[mixed] = _time_config(h, x, y, tol, out, mixed, reps)
             _check_same(h, x, y, tol, mixed, ref_cls, ref_hist, ref)
             checked += 1
         best = min(results, key=lambda c: sum(results[c]))
-        # accumulate form and histogram copies at that shape
+        # accumulate form, histogram copies and threads per block at that
+        # shape; a shape other than the default form (dense, 8 copies, 256
+        # threads) must beat it by MARGIN on a second, interleaved timing,
+        # so that noise does not pick it
+        base = best[:6] + (0, 8, 256)
+        cand = {}
         for af in ACC_FORM:
             for hc in HIST_COPIES:
-                cfg = best[:6] + (af, hc)
-                if cfg not in results:
-                    results[cfg] = _time_config(h, x, y, tol, out, cfg, reps)
-                    _check_same(h, x, y, tol, cfg, ref_cls, ref_hist, ref)
-                    checked += 1
-        best = min(results, key=lambda c: sum(results[c]))
+                for nt in BLOCK_THREADS:
+                    cfg = best[:6] + (af, hc, nt)
+                    if cfg not in results:
+                        results[cfg] = _time_config(h, x, y, tol, out, cfg, reps)
+                        _check_same(h, x, y, tol, cfg, ref_cls, ref_hist, ref)
+                        checked += 1
+                    cand[cfg] = results[cfg]
+        challenger = min(cand, key=lambda c: sum(cand[c]))
+        if challenger != base:
+            tb = tc = 0.0
+            for _ in range(3):
+                tb += sum(_time_config(h, x, y, tol, out, base, reps))
+                tc += sum(_time_config(h, x, y, tol, out, challenger, reps))
+            best = challenger if tc < (1.0 - MARGIN) * tb else base
+        else:
+            best = base
         t = results[best]
         # one-pass scan (accum_mode 1): its value is an exact sum, so every
         # shape must give the same bits
@@ -163,30 +187,38 @@ def _time_batch(h, run, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def tune_batch(h, reps: int = 5, seed: int = 11, log=print):
-    """Batched launch shape: blocks per CU and chunk on 512 ragged instances,
-    then the CG gang sizing on 32 CG systems.  Returns the chosen
-    (blocks_per_cu, chunk, cg_rows_per_block, cg_gang_max)."""
+def tune_batch(h, reps: int = 3, log=print):
+    """Solver and batched launch shapes, each on the workload it serves:
+    blocks per CU and chunk on the 4096 ragged instances of the batched
+    benchmark (n = round(10^U[2,6]), tol from {1e-4, 1e-6, 1e-8}), the CG
+    gang sizing on the 256 Poisson systems (sides round(2^U[5,9])) in the
+    same launch, the SpMV grid on the 3D Laplacian 128^3, the single-system
+    CG gang on Poisson 1024^2, and where the power method takes pass 1.
+    Returns the chosen qdot_solver_tune as a tuple."""
+    import numpy as np
     import torch
 
     import paper_2105_00115_amd as q
     import workloads
 
     dev = "cuda:0"
-    offs, xh, yh, tols = workloads.ragged_batch(512, seed)
-    x, y = torch.from_numpy(xh).to(dev), torch.from_numpy(yh).to(dev)
-    del xh, yh
+    h.set_solver_tune()
+    g = workloads.rng(2025)
+    sizes = np.rint(10.0 ** g.uniform(2, 6, 4096)).astype(np.int64)
+    offs = np.zeros(4097, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    tols = np.array([1e-4, 1e-6, 1e-8])[g.integers(0, 3, 4096)]
+    x, y = workloads.log_uniform_pair_torch(int(offs[-1]), 2025, dev)
     off_d = torch.from_numpy(offs).to(dev)
     tol_d = torch.from_numpy(tols).to(dev)
-    out = torch.zeros(len(tols) * q.RESULT_BYTES, dtype=torch.uint8, device=dev)
-    h.set_batch_tune()
+    out = torch.zeros(4096 * q.RESULT_BYTES, dtype=torch.uint8, device=dev)
     h.batched_async(x, y, off_d, offs, tol_d, out)
     torch.cuda.synchronize()
     ref = q.parse_results(out)
     res = {}
     for bpc in BATCH_BPC:
         for ch in BATCH_CHUNK:
-            h.set_batch_tune(blocks_per_cu=bpc, chunk=ch)
+            h.set_solver_tune(batch_blocks_per_cu=bpc, batch_chunk=ch)
             res[(bpc, ch)] = _time_batch(
                 h, lambda: h.batched_async(x, y, off_d, offs, tol_d, out), reps)
             got = q.parse_results(out)
@@ -194,34 +226,93 @@ def tune_batch(h, reps: int = 5, seed: int = 11, log=print):
                 if a["count"] != r["count"] or a["t"] != r["t"] or a["flags"] != r["flags"]:
                     raise ShapeChanged(f"batch shape {(bpc, ch)} changed instance {j}")
     bpc, ch = min(res, key=res.get)
-    log(f"batch: best blocks/CU {bpc} chunk {ch} ({res[(bpc, ch)]*1e3:.3f} ms)")
-    # CG gang sizing on 2D Poisson systems with sides 2^U[6, 9]
-    sides = workloads.cg_grid_sides(32, seed + 2, 6.0, 9.0)
-    systems, xs = [], []
-    for s_, m in enumerate(sides):
-        rp, ci, va = workloads.poisson2d_csr(int(m))
-        A = q.Csr(rp, ci, va, dev)
-        b = torch.from_numpy(workloads.normal_vector(A.n, 100 + s_)).to(dev)
-        xx = torch.zeros(A.n, dtype=torch.float64, device=dev)
-        xs.append(xx)
-        systems.append((A, b, xx, 1e-10, 1e-8, 20000, 1))
+    log(f"batch: best blocks/CU {bpc} chunk {ch} ({res[(bpc, ch)]*1e3:.3f} ms for 4096 "
+        f"instances)")
+    # CG gang sizing: the 256 systems together with the instances
+    gs = workloads.rng(2026)
+    sides = np.rint(2.0 ** gs.uniform(5, 9, 256)).astype(np.int64)
+    mats, systems = {}, []
+    rows = int((sides ** 2).sum())
+    xall = torch.zeros(rows, dtype=torch.float64, device=dev)
+    ball = torch.empty(rows, dtype=torch.float64, device=dev)
+    ro = 0
+    for k, m in enumerate(sides):
+        m = int(m)
+        if m not in mats:
+            mats[m] = q.Csr(*workloads.poisson2d_csr(m), device=dev)
+        nn = m * m
+        ball[ro:ro + nn] = torch.from_numpy(workloads.normal_vector(nn, 3000 + k)).to(dev)
+        systems.append((mats[m], ball[ro:ro + nn], xall[ro:ro + nn], 1e-10, 1e-8, 20000, 1))
+        ro += nn
+    cgo = torch.zeros(256 * q.CG_RESULT_BYTES, dtype=torch.uint8, device=dev)
     cg_res = {}
-    for rows in CG_ROWS:
+    for rpb in CG_ROWS:
         for gmax in CG_GANG_MAX:
-            h.set_batch_tune(blocks_per_cu=bpc, chunk=ch, cg_rows_per_block=rows,
-                             cg_gang_max=gmax)
-            for xx in xs:
-                xx.zero_()
+            h.set_solver_tune(batch_blocks_per_cu=bpc, batch_chunk=ch, cg_rows_per_block=rpb,
+                              cg_gang_max=gmax)
+            xall.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            rr = h.cg_batched(systems)
-            cg_res[(rows, gmax)] = time.perf_counter() - t0
+            h.batch_run_async(x, y, off_d, offs, tol_d, out, systems, cgo)
+            torch.cuda.synchronize()
+            cg_res[(rpb, gmax)] = time.perf_counter() - t0
+            rr = q.parse_cg_results(cgo)
             if any(r["status"] != q.OK for r in rr):
-                raise RuntimeError(f"CG gang shape {(rows, gmax)} failed: {rr}")
-    rows, gmax = min(cg_res, key=cg_res.get)
-    log(f"batch CG: best rows/block {rows} gang max {gmax} ({cg_res[(rows, gmax)]*1e3:.1f} ms)")
-    h.set_batch_tune(blocks_per_cu=bpc, chunk=ch, cg_rows_per_block=rows, cg_gang_max=gmax)
-    return (bpc, ch, rows, gmax)
+                raise RuntimeError(f"CG gang shape {(rpb, gmax)} failed")
+    rpb, gmax = min(cg_res, key=cg_res.get)
+    log(f"batch CG: best rows/block {rpb} gang max {gmax} ({cg_res[(rpb, gmax)]*1e3:.1f} ms "
+        f"for the launch)")
+    h.set_solver_tune(batch_blocks_per_cu=bpc, batch_chunk=ch, cg_rows_per_block=rpb,
+                      cg_gang_max=gmax)
+    del systems, mats, xall, ball, x, y
+    # SpMV grid on the 3D Laplacian 128^3 (the product bit for bit the same
+    # for every grid), and where the power method takes pass 1
+    A = q.Csr(*workloads.laplacian3d_csr(128), device=dev)
+    v = torch.from_numpy(workloads.normal_vector(A.n, 5)).to(dev)
+    w = torch.empty_like(v)
+    sp_res, ref_w = {}, None
+    for sb in SPMV_BPC:
+        h.set_solver_tune(spmv_blocks_per_cu=sb)
+        sp_res[sb] = _time_batch(h, lambda: h.spmv(A, v, w), 20)
+        if ref_w is None:
+            ref_w = w.clone()
+        elif not torch.equal(w, ref_w):
+            raise ShapeChanged(f"SpMV grid {sb} changed the product")
+    sb = min(sp_res, key=sp_res.get)
+    log(f"SpMV: best blocks/CU {sb} ({sp_res[sb]*1e6:.1f} us)")
+    x0 = workloads.unit_vector(A.n, 4)
+    pm, lam = {}, {}
+    for fused in (0, 1):
+        h.set_solver_tune(spmv_blocks_per_cu=sb, power_scan_in_spmv=fused)
+        xs = torch.from_numpy(x0).to(dev)
+        h.power(A, xs, 5, 1e-6, 1, trace=False)
+        xs = torch.from_numpy(x0).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = h.power(A, xs, 200, 1e-6, 1, trace=False)
+        pm[fused] = (time.perf_counter() - t0) / 200
+        lam[fused] = r["lambda"]
+    if lam[0] != lam[1]:
+        raise ShapeChanged("pass 1 inside the SpMV changed the power method's lambda")
+    ps = min(pm, key=pm.get)
+    log(f"power: pass 1 in the SpMV {ps} ({pm[0]*1e6:.1f} / {pm[1]*1e6:.1f} us per iteration)")
+    del A, v, w
+    A = q.Csr(*workloads.poisson2d_csr(1024), device=dev)
+    b = torch.from_numpy(workloads.normal_vector(A.n, 3)).to(dev)
+    cgs = {}
+    for cb in CG_BPC:
+        h.set_solver_tune(spmv_blocks_per_cu=sb, power_scan_in_spmv=ps, cg_blocks_per_cu=cb)
+        xx = torch.zeros(A.n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = h.cg(A, b, xx, 1e-10, 1e-8, 20000, 1)
+        cgs[cb] = (time.perf_counter() - t0) / max(1, r["iters"])
+        if r["status"] != q.OK:
+            raise RuntimeError(f"CG gang of {cb} blocks per CU failed: {r}")
+    cb = min(cgs, key=cgs.get)
+    log(f"CG: best gang blocks/CU {cb} ({cgs[cb]*1e6:.1f} us per iteration)")
+    h.set_solver_tune(spmv_blocks_per_cu=sb, power_scan_in_spmv=ps, cg_blocks_per_cu=cb)
+    return h.get_solver_tune()
 
 
 def write(path, chosen, arch, cus, batch=None):
@@ -230,15 +321,16 @@ def write(path, chosen, arch, cus, batch=None):
         f.write(f"# qdot launch shapes for {arch} with {cus} CUs, written by "
                 f"python -m paper_2105_00115_amd.autotune on {time.strftime('%Y-%m-%d')}\n")
         f.write("# bucket scan_blocks_per_cu scan_unroll acc_blocks_per_cu acc_unroll"
-                " onepass_blocks_per_cu onepass_unroll acc_form hist_copies"
+                " onepass_blocks_per_cu onepass_unroll acc_form hist_copies block_threads"
                 "   (measured n, scan/cut/acc/fin us, one-pass scan us)\n")
         for b, n, cfg, t in chosen:
             f.write(f"{b} {' '.join(str(c) for c in cfg)}   # n={n} "
                     f"{t[0]*1e3:.1f}/{t[1]*1e3:.1f}/{t[2]*1e3:.1f}/{t[3]*1e3:.1f}, "
                     f"{t[4]*1e3:.1f}\n")
         if batch is not None:
-            f.write("# batch blocks_per_cu chunk cg_rows_per_block cg_gang_max\n")
-            f.write("batch " + " ".join(str(v) for v in batch) + "\n")
+            f.write("# solver batch_blocks_per_cu batch_chunk cg_rows_per_block cg_gang_max"
+                    " spmv_blocks_per_cu cg_blocks_per_cu power_scan_in_spmv\n")
+            f.write("solver " + " ".join(str(v) for v in batch) + "\n")
 
 
 def main(argv=None):

@@ -32,8 +32,8 @@ qdot_tune default_tune(int bucket)
     // on the same block -> chunk mapping so the second pass finds the data
     // in the same XCD's L2
     // in the same XCD's L2; the one-pass scan wants more resident blocks
-    if (bucket < 3) return qdot_tune{2, 1, 2, 1, 4, 1, 0, HIST_COPIES};
-    return qdot_tune{2, 1, 2, 2, 4, 1, 0, HIST_COPIES};
+    if (bucket < 3) return qdot_tune{2, 1, 2, 1, 4, 1, 0, HIST_COPIES, BLOCK};
+    return qdot_tune{2, 1, 2, 2, 4, 1, 0, HIST_COPIES, BLOCK};
 }
 
 bool tune_ok(const qdot_tune &t)
@@ -44,7 +44,8 @@ bool tune_ok(const qdot_tune &t)
     return b_ok(t.scan_blocks_per_cu) && b_ok(t.acc_blocks_per_cu) &&
            b_ok(t.onepass_blocks_per_cu) && u_ok(t.scan_unroll) && u_ok(t.acc_unroll) &&
            u_ok(t.onepass_unroll) && (t.acc_form == 0 || t.acc_form == 1) &&
-           c_ok(t.hist_copies);
+           c_ok(t.hist_copies) &&
+           (t.block_threads == 128 || t.block_threads == BLOCK || t.block_threads == 512);
 }
 
 Launch make_launch_tuned(const qdot_tune &t, int num_cus, Ws *ws, double *partials,
@@ -66,8 +67,12 @@ Launch make_launch_tuned(const qdot_tune &t, int num_cus, Ws *ws, double *partia
     L.s1_blocks = std::min(MAX_GRID, t.onepass_blocks_per_cu * num_cus);
     L.s1_unroll = t.onepass_unroll;
     L.s1tab = s1tab;
-    L.acc_form = t.acc_form;
-    L.hist_copies = t.hist_copies;
+    // the compacting form is tuned on double inputs; float inputs keep the
+    // dense form of their own tuning
+    L.acc_form = single ? 0 : t.acc_form;
+    // single-precision inputs run twice the scan blocks: they keep every copy
+    L.hist_copies = single ? HIST_COPIES : t.hist_copies;
+    L.block_threads = t.block_threads;
     L.ev = nullptr;
     return L;
 }
@@ -260,7 +265,8 @@ int32_t qdot_set_tune(qdot_handle *h, int32_t bucket, const qdot_tune *cfg)
         const qdot_tune t = cfg ? *cfg : default_tune(b);
         if (!tune_ok(t))
             return fail(h, QDOT_E_INVAL, "tune out of range (blocks per CU 1..16, unroll "
-                                         "1/2/4, acc_form 0/1, hist_copies 1/2/4/8)");
+                                         "1/2/4, acc_form 0/1, hist_copies 1/2/4/8, "
+                                         "block_threads 128/256/512)");
         h->tune[b] = t;
     }
     return QDOT_OK;
@@ -280,30 +286,33 @@ int32_t qdot_load_tune(qdot_handle *h, const char *path)
     if (!f) return fail(h, QDOT_E_INVAL, std::string("cannot open tune file ") + path);
     qdot_tune t[QDOT_TUNE_BUCKETS];
     for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) t[b] = h->tune[b];
-    qdot_batch_tune bt;
-    (void)qdot_get_batch_tune(h, &bt);
-    bool have_batch = false;
+    qdot_solver_tune bt;
+    (void)qdot_get_solver_tune(h, &bt);
+    bool have_solver = false;
     char line[256];
     bool ok = true;
     while (ok && std::fgets(line, sizeof line, f)) {
         char *hash = std::strchr(line, '#');
         if (hash) *hash = 0;
-        // "batch blocks_per_cu chunk cg_rows_per_block cg_gang_max"
-        int bv[4];
-        if (std::sscanf(line, " batch %d %d %d %d", &bv[0], &bv[1], &bv[2], &bv[3]) == 4) {
-            bt = qdot_batch_tune{bv[0], bv[1], bv[2], bv[3]};
-            have_batch = true;
+        // "solver batch_bpc batch_chunk cg_rows_per_block cg_gang_max spmv_bpc cg_bpc
+        // power_scan_in_spmv"
+        int bv[7];
+        if (std::sscanf(line, " solver %d %d %d %d %d %d %d", &bv[0], &bv[1], &bv[2], &bv[3],
+                        &bv[4], &bv[5], &bv[6]) == 7) {
+            bt = qdot_solver_tune{bv[0], bv[1], bv[2], bv[3], bv[4], bv[5], bv[6]};
+            have_solver = true;
             continue;
         }
-        if (std::strstr(line, "batch")) {
+        if (std::strstr(line, "solver")) {
             ok = false;
             continue;
         }
-        int b = -1, v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &b, &v[0], &v[1], &v[2],
-                                    &v[3], &v[4], &v[5], &v[6], &v[7]);
+        int b = -1, v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &b, &v[0], &v[1],
+                                    &v[2], &v[3], &v[4], &v[5], &v[6], &v[7], &v[8]);
         if (got <= 0) continue;  // blank or comment
-        if ((got != 5 && got != 7 && got != 9) || b < 0 || b >= QDOT_TUNE_BUCKETS) {
+        if ((got != 5 && got != 7 && got != 9 && got != 10) || b < 0 ||
+            b >= QDOT_TUNE_BUCKETS) {
             ok = false;
             continue;
         }
@@ -316,19 +325,20 @@ int32_t qdot_load_tune(qdot_handle *h, const char *path)
             c.onepass_blocks_per_cu = v[4];
             c.onepass_unroll = v[5];
         }
-        if (got == 9) {
+        if (got >= 9) {
             c.acc_form = v[6];
             c.hist_copies = v[7];
         }
+        if (got == 10) c.block_threads = v[8];
         if (!tune_ok(c)) ok = false;
         else t[b] = c;
     }
     std::fclose(f);
     if (!ok) return fail(h, QDOT_E_INVAL, std::string("malformed tune file ") + path);
-    qdot_batch_tune cur;
-    (void)qdot_get_batch_tune(h, &cur);
-    if (have_batch && std::memcmp(&cur, &bt, sizeof bt) != 0) {
-        const int32_t st = qdot_set_batch_tune(h, &bt);
+    qdot_solver_tune cur;
+    (void)qdot_get_solver_tune(h, &cur);
+    if (have_solver && std::memcmp(&cur, &bt, sizeof bt) != 0) {
+        const int32_t st = qdot_set_solver_tune(h, &bt);
         if (st != QDOT_OK) return st;
     }
     for (int b = 0; b < QDOT_TUNE_BUCKETS; b++) h->tune[b] = t[b];

@@ -77,7 +77,7 @@ struct BatchPlan {
     double *ltab = nullptr;           // one-pass mode: per large instance W x S1_PIECES sums
     CgSys *sys = nullptr;             // S device descriptors
     Gang *gangs = nullptr;            // S gang states
-    double *cgvec = nullptr;          // r, p (two buffers), q of every system
+    double *cgvec = nullptr;          // r, p, q of every system
     qdot_cg_result *cgres = nullptr;  // S results (synchronous CG entry)
     BItem *items = nullptr;
     BLarge *large = nullptr;
@@ -680,7 +680,7 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
               hipMalloc((void **)&p->sys, sizeof(CgSys) * ns) == hipSuccess &&
               hipMalloc((void **)&p->gangs, sizeof(Gang) * ns) == hipSuccess &&
               hipMalloc((void **)&p->cgres, sizeof(qdot_cg_result) * ns) == hipSuccess &&
-              hipMalloc((void **)&p->cgvec, sizeof(double) * std::max<int64_t>(1, 4 * cg_rows)) == hipSuccess &&
+              hipMalloc((void **)&p->cgvec, sizeof(double) * std::max<int64_t>(1, 3 * cg_rows)) == hipSuccess &&
               (accum == 0 ||
                hipMalloc((void **)&p->ltab, sizeof(double) * W * S1_PIECES * nl) == hipSuccess);
     if (!ok) {
@@ -700,9 +700,8 @@ static int32_t build_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B
         d.x = q.x;
         d.r = p->cgvec + vo;
         d.p = p->cgvec + vo + q.A.n;
-        d.pb = p->cgvec + vo + 2 * q.A.n;
-        d.q = p->cgvec + vo + 3 * q.A.n;
-        vo += 4 * q.A.n;
+        d.q = p->cgvec + vo + 2 * q.A.n;
+        vo += 3 * q.A.n;
         d.rtol = q.rtol;
         d.qtol = q.qtol;
         d.maxit = q.maxit;
@@ -863,36 +862,45 @@ using namespace qd;
 
 extern "C" {
 
-int32_t qdot_set_batch_tune(qdot_handle *h, const qdot_batch_tune *cfg)
+int32_t qdot_set_solver_tune(qdot_handle *h, const qdot_solver_tune *cfg)
 {
     if (!h) return QDOT_E_INVAL;
-    qdot_batch_tune t = cfg ? *cfg : qdot_batch_tune{4, 131072, 16384, 16};
-    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16 || t.chunk < (1 << 13) ||
-        t.chunk > (1 << 22) || t.chunk % GROUP != 0 || t.cg_rows_per_block < CHUNK ||
-        t.cg_gang_max < 1 || t.cg_gang_max > MAX_GANG)
-        return fail(h, QDOT_E_INVAL, "batch tune out of range (blocks per CU 1..16, chunk "
+    qdot_solver_tune t = cfg ? *cfg : qdot_solver_tune{4, 131072, 16384, 16, 8, 2, 0};
+    if (t.batch_blocks_per_cu < 1 || t.batch_blocks_per_cu > 16 || t.batch_chunk < (1 << 13) ||
+        t.batch_chunk > (1 << 22) || t.batch_chunk % GROUP != 0 ||
+        t.cg_rows_per_block < CHUNK || t.cg_gang_max < 1 || t.cg_gang_max > MAX_GANG ||
+        t.spmv_blocks_per_cu < 1 || t.spmv_blocks_per_cu > 16 || t.cg_blocks_per_cu < 1 ||
+        t.cg_blocks_per_cu > 2 || (t.power_scan_in_spmv != 0 && t.power_scan_in_spmv != 1))
+        return fail(h, QDOT_E_INVAL, "solver tune out of range (batch blocks per CU 1..16, chunk "
                                      "2^13..2^22 in multiples of 2048, CG rows per block >= "
-                                     "1024, gang 1..512)");
+                                     "1024, gang 1..512, SpMV blocks per CU 1..16, CG blocks "
+                                     "per CU 1..2, power scan in SpMV 0/1)");
     DeviceGuard g(h->device);
     // the cached plans were cut with the old shape
     if (!h->plans.empty()) {
         (void)hipDeviceSynchronize();
         free_plans(h);
     }
-    h->batch_blocks_per_cu = t.blocks_per_cu;
-    h->batch_chunk = t.chunk;
+    h->batch_blocks_per_cu = t.batch_blocks_per_cu;
+    h->batch_chunk = t.batch_chunk;
     h->batch_cg_rows = t.cg_rows_per_block;
     h->batch_cg_gang_max = t.cg_gang_max;
+    h->spmv_blocks_per_cu = t.spmv_blocks_per_cu;
+    h->cg_blocks_per_cu = t.cg_blocks_per_cu;
+    h->power_scan_in_spmv = t.power_scan_in_spmv;
     return QDOT_OK;
 }
 
-int32_t qdot_get_batch_tune(const qdot_handle *h, qdot_batch_tune *cfg)
+int32_t qdot_get_solver_tune(const qdot_handle *h, qdot_solver_tune *cfg)
 {
     if (!h || !cfg) return QDOT_E_INVAL;
-    cfg->blocks_per_cu = h->batch_blocks_per_cu;
-    cfg->chunk = (int32_t)h->batch_chunk;
+    cfg->batch_blocks_per_cu = h->batch_blocks_per_cu;
+    cfg->batch_chunk = (int32_t)h->batch_chunk;
     cfg->cg_rows_per_block = (int32_t)h->batch_cg_rows;
     cfg->cg_gang_max = h->batch_cg_gang_max;
+    cfg->spmv_blocks_per_cu = h->spmv_blocks_per_cu;
+    cfg->cg_blocks_per_cu = h->cg_blocks_per_cu;
+    cfg->power_scan_in_spmv = h->power_scan_in_spmv;
     return QDOT_OK;
 }
 

@@ -49,33 +49,35 @@ __device__ __forceinline__ void load4_tail(const T *__restrict__ p, int lim, T v
     for (int e = 0; e < 4; e++) v[e] = e < lim ? p[e] : T(0);
 }
 
-// One block walks groups of U * CHUNK components of x, y: the groups that
-// start at first, first + stride, first + 2 * stride, ... below n (stride a
-// multiple of U * CHUNK).  Each thread loads EPT consecutive components of
-// each CHUNK, U CHUNKs in flight; the one partial group is bounds-checked.
-template <bool VEC, int U, class T, class Body>
+// One block of NT threads walks groups of U * NT * EPT components of x, y:
+// the groups that start at first, first + stride, first + 2 * stride, ...
+// below n (stride a multiple of the group).  Each thread loads EPT
+// consecutive components of each NT * EPT chunk, U chunks in flight; the one
+// partial group is bounds-checked.
+template <bool VEC, int U, int NT = BLOCK, class T, class Body>
 __device__ __forceinline__ void stream_strided(const T *__restrict__ x, const T *__restrict__ y,
                                                int64_t first, int64_t stride, int64_t n,
                                                Body &&body)
 {
-    const int64_t group = (int64_t)CHUNK * U;
+    constexpr int64_t chunk = (int64_t)NT * EPT;
+    const int64_t group = chunk * U;
     int64_t base = first;
     for (; base + group <= n; base += stride) {
         T xv[U][4], yv[U][4];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            const int64_t i0 = base + (int64_t)u * chunk + threadIdx.x * EPT;
             load4_full<VEC>(x + i0, xv[u]);
             load4_full<VEC>(y + i0, yv[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; u++)
-            body(xv[u], yv[u], base + (int64_t)u * CHUNK + threadIdx.x * EPT, 4);
+            body(xv[u], yv[u], base + (int64_t)u * chunk + threadIdx.x * EPT, 4);
     }
     if (base < n) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int64_t i0 = base + (int64_t)u * CHUNK + threadIdx.x * EPT;
+            const int64_t i0 = base + (int64_t)u * chunk + threadIdx.x * EPT;
             const int64_t left = n - i0;
             const int lim = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
             T xv[4], yv[4];
@@ -92,13 +94,13 @@ __device__ __forceinline__ void stream_strided(const T *__restrict__ x, const T 
 // per-lane limits.  body(xv, yv, i0, lim) sees 4 consecutive components
 // i0..i0+3 of which the first `lim` are real; it is called with every lane
 // of the block active.
-template <bool VEC, int U, class T, class Body>
+template <bool VEC, int U, int NT = BLOCK, class T, class Body>
 __device__ __forceinline__ void stream_groups(const T *__restrict__ x, const T *__restrict__ y,
                                               int64_t n, Body &&body)
 {
-    const int64_t group = (int64_t)CHUNK * U;
-    stream_strided<VEC, U>(x, y, (int64_t)blockIdx.x * group, (int64_t)gridDim.x * group, n,
-                           body);
+    const int64_t group = (int64_t)NT * EPT * U;
+    stream_strided<VEC, U, NT>(x, y, (int64_t)blockIdx.x * group, (int64_t)gridDim.x * group,
+                               n, body);
 }
 
 __device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v)
@@ -144,13 +146,14 @@ __device__ __forceinline__ void block_reduce_range(int &lo, int &hi, unsigned in
 // negative, bit 1 positive) for the cutoff kernel.  nz, bad and sg are the
 // calling thread's own tallies.  Every thread calls it, after a barrier that
 // completes h; it ends with one, so it can be called again.
+template <int NT = BLOCK>
 __device__ __forceinline__ void scan_flush(const unsigned int *h, unsigned int nz,
                                            unsigned int bad, unsigned int sg, Ws *ws, int rec,
                                            int copies = HIST_COPIES)
 {
     unsigned long long *gh = ws->hist[blockIdx.x % copies];
     int lo = W, hi = -1;
-    for (int i = threadIdx.x; i < W; i += BLOCK) {
+    for (int i = threadIdx.x; i < W; i += NT) {
         const unsigned int v = h[i];
         if (v) {
             atomicAdd(&gh[i], (unsigned long long)v);
@@ -166,8 +169,8 @@ __device__ __forceinline__ void scan_flush(const unsigned int *h, unsigned int n
         hi = max(hi, __shfl_xor(hi, m, 64));
         sg |= __shfl_xor(sg, m, 64);
     }
-    __shared__ int2 wr[BLOCK / 64];
-    __shared__ unsigned int wsg[BLOCK / 64];
+    __shared__ int2 wr[NT / 64];
+    __shared__ unsigned int wsg[NT / 64];
     if ((threadIdx.x & 63) == 0) {
         if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
         if (bad) atomicOr(&ws->nonfinite, 1u);
@@ -179,7 +182,7 @@ __device__ __forceinline__ void scan_flush(const unsigned int *h, unsigned int n
         // plain stores, no contention: the cutoff kernel reduces the records
         int2 r = wr[0];
         unsigned int g = wsg[0];
-        for (int w = 1; w < BLOCK / 64; w++) {
+        for (int w = 1; w < NT / 64; w++) {
             r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
             g |= wsg[w];
         }

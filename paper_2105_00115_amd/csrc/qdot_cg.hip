@@ -138,7 +138,7 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
         return fail(h, QDOT_E_INVAL, "accum_mode 1 not admissible for this n and qtol");
     DeviceGuard g(h->device);
     const int64_t n = A->n;
-    int32_t st = ensure_solver_vectors(h, 4 * n);  // r, p (two buffers), q
+    int32_t st = ensure_solver_vectors(h, 3 * n);  // r, p, q
     if (st != QDOT_OK) return st;
     if ((st = ensure_cg_buffers(h, 1, 1)) != QDOT_OK) return st;
     CgDev *d = (CgDev *)h->cg;
@@ -159,8 +159,7 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
                                                            BLOCK, 0);
     if (oe != hipSuccess) return hip_fail(h, oe, "occupancy query");
     if (per_cu < 1) return fail(h, QDOT_E_DEVICE, "the CG kernel cannot be resident");
-    int cap = std::min(MAX_GANG, std::min(per_cu, 2) * h->num_cus);
-    if (const char *e = std::getenv("QDOT_CG_BLOCKS")) cap = std::max(1, std::min(cap, std::atoi(e)));
+    const int cap = std::min(MAX_GANG, std::min(per_cu, h->cg_blocks_per_cu) * h->num_cus);
     const int G = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + CHUNK - 1) / CHUNK));
     CgSys S;
     S.n = n;
@@ -171,8 +170,7 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     S.x = x;
     S.r = h->vec;
     S.p = h->vec + n;
-    S.pb = h->vec + 2 * n;
-    S.q = h->vec + 3 * n;
+    S.q = h->vec + 2 * n;
     S.rtol = rtol;
     S.qtol = qtol;
     S.maxit = maxit;

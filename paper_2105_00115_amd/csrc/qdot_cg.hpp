@@ -4,12 +4,11 @@
 // A gang of G blocks solves one system; block b of the gang owns a
 // contiguous slice of rows and every vector update, SpMV row and qdot pass
 // on that slice.  Gang barriers (an arrival counter and a generation word)
-// separate the steps that need data from other slices: after a qdot's
-// pass 1 (histogram merged) and after its pass 2 (partials written), four
-// per iteration (one more for an inner product that the guaranteed mode
-// sums again; one per inner product in the one-pass mode and with the FP64
-// dot).  The SpMV needs no barrier of its own: it forms p = r + beta p_old
-// from vectors that the inner products' barriers already made complete.  The
+// separate the steps that need data from other slices:
+//   before the SpMV (p complete), after a qdot's pass 1 (histogram merged),
+//   after its pass 2 (partials written),
+// five per iteration (one more for an inner product that the guaranteed
+// mode sums again; one fewer per inner product in the one-pass mode).  The
 // whole-gang reductions (the blocks' pass-1 records and histogram copies at
 // the first barrier of a qdot, its partials at the second) are done once,
 // by the last block to arrive, before it releases the others; that block
@@ -40,9 +39,7 @@ struct CgSys {
     const double *val;
     const double *b;
     double *x;
-    // scratch, n each: r, q, and p in two buffers that alternate between
-    // iterations (p[k & 1] is the p read by iteration k's SpMV)
-    double *r, *p, *pb, *q;
+    double *r, *p, *q;  // scratch, n each
     double rtol, qtol;
     int maxit, use_qdot;
     qdot_result *trace;  // nullable: 2 * maxit + 1 results
@@ -447,39 +444,30 @@ __device__ __forceinline__ DotOut gang_qdot(const double *a, const double *bv, i
 // clears the copies and the table over the live window and publishes the
 // result; the others read it.  No class table or second sweep is needed
 // outside that block, so an inner product costs one gang barrier.
-// With `fed` the caller has already put its rows through s1_group (while it
-// produced a or b, after s1_begin) and passes the window's state and its
-// zero and non-finite counts.
 __device__ __forceinline__ DotOut gang_qdot_s1(const double *a, const double *bv, int64_t n,
                                                int64_t r0, int64_t r1, double tol, int key_mode,
                                                int score_mode, int nonstrict, Gang *gg, int G,
                                                int gb, int k, CgLds &L, S1Lds &S1, double *tab,
-                                               qdot_result *trace_slot,
-                                               const S1Run *fed = nullptr,
-                                               unsigned int nz = 0, unsigned int bad = 0)
+                                               qdot_result *trace_slot)
 {
     DotOut o = {0.0, false, true};
     GangQ &Q = gg->qb[k];
+    const bool vec = ((((uintptr_t)a) | ((uintptr_t)bv)) & 15) == 0;
     // admitted by the host: depth <= S1_WIN
     const int depth = s1_depth_dev(n, tol, score_mode);
-    int top;
-    if (fed) {
-        top = fed->top;
-    } else {
-        const bool vec = ((((uintptr_t)a) | ((uintptr_t)bv)) & 15) == 0;
-        S1Run run = s1_run_start();
-        s1_begin(S1);
-        __syncthreads();
-        if (r1 > r0) {
-            if (vec)
-                s1_stream<true, 2>(a + r0, bv + r0, 0, 2 * CHUNK, r1 - r0, key_mode, depth, L.h,
-                                   S1, run, nz, bad);
-            else
-                s1_stream<false, 2>(a + r0, bv + r0, 0, 2 * CHUNK, r1 - r0, key_mode, depth,
-                                    L.h, S1, run, nz, bad);
-        }
-        top = run.top;
+    unsigned int nz = 0, bad = 0;
+    S1Run run = s1_run_start();
+    s1_begin(S1);
+    __syncthreads();
+    if (r1 > r0) {
+        if (vec)
+            s1_stream<true, 2>(a + r0, bv + r0, 0, 2 * CHUNK, r1 - r0, key_mode, depth, L.h, S1,
+                               run, nz, bad);
+        else
+            s1_stream<false, 2>(a + r0, bv + r0, 0, 2 * CHUNK, r1 - r0, key_mode, depth, L.h,
+                                S1, run, nz, bad);
     }
+    const int top = run.top;
     __syncthreads();
     int lo = W, hi = -1;
     for (int j = threadIdx.x; j < W; j += BLOCK) {
@@ -614,53 +602,18 @@ __device__ __forceinline__ DotOut gang_dot64(const double *a, const double *bv, 
 // A thread takes SR rows at once and issues the column and value loads of
 // their first SNZ entries, then every gather, before it adds: two memory
 // latencies per SR rows instead of two per entry.  Longer rows finish in a
-// plain loop.  Every thread of the block calls it (the row loop is
-// block-uniform).
+// plain loop.
 constexpr int SR = 2;
 constexpr int SNZ = 8;
-
-// The previous CG iteration's update p = r + beta p_old, deferred into the
-// SpMV that reads p: every gathered entry is formed as r[c] + beta *
-// p_old[c] (r[c] alone on the first iteration, p = r), which is bitwise the
-// value the owner of row c forms for its own row and stores in pnew[c] (the
-// same two IEEE operations on the same operands).  r and p_old are complete
-// (written by every block before the barriers of the previous inner
-// products) and nobody writes them during the SpMV; pnew is the other
-// buffer, read by no block until the next SpMV.
-struct SpmvFold {
-    const double *r;  // nullptr: v is gathered as it is
-    double beta;
-    bool first;
-    double *pnew;
-};
-
-// What the SpMV does with each row's pair (v_i, out_i), for the qdot v . out
-// that follows: MODE 1 keys it into the block's LDS histogram (pass 1 of the
-// two-pass qdot), MODE 2 feeds it to the one-pass window (s1_group).
-struct RowScan {
-    int key_mode;
-    CgLds *L;
-    unsigned int nz, bad, sg;
-    S1Lds *S1;  // MODE 2
-    S1Run run;  // MODE 2
-    int depth;  // MODE 2
-};
-
-template <int MODE = 0>
+// With SCAN the row result is also keyed against v's own entry (pass 1 of
+// the qdot v . out that follows, fused here so that v and out are not read
+// again for it).
+template <bool SCAN = false>
 __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, double *out, int64_t r0,
-                                          int64_t r1, const SpmvFold *fold = nullptr,
-                                          RowScan *rs = nullptr)
+                                          int64_t r1, int key_mode = 0, CgLds *L = nullptr,
+                                          unsigned int *nz = nullptr, unsigned int *bad = nullptr,
+                                          unsigned int *sg = nullptr)
 {
-    const bool fd = fold != nullptr && fold->r != nullptr;
-    const bool first = fd && fold->first;
-    const double beta = fd ? fold->beta : 0.0;
-    auto gather = [&](int32_t c) -> double {
-        if (!fd) return ld_dev(&v[c]);
-        const double rc = ld_dev(&fold->r[c]);
-        if (first) return rc;
-        const double bp = beta * ld_dev(&v[c]);
-        return rc + bp;
-    };
     for (int64_t base = r0; base < r1; base += (int64_t)SR * BLOCK) {
         int32_t beg[SR], len[SR];
 #pragma unroll
@@ -690,9 +643,7 @@ __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, doubl
         for (int u = 0; u < SR; u++)
 #pragma unroll
             for (int jj = 0; jj < SNZ; jj++)
-                if (jj < len[u]) pv[u][jj] = pv[u][jj] * gather(ci[u][jj]);
-        double vi[SR], oi[SR];
-        bool ok[SR];
+                if (jj < len[u]) pv[u][jj] = pv[u][jj] * ld_dev(&v[ci[u][jj]]);
 #pragma unroll
         for (int u = 0; u < SR; u++) {
             double s = 0.0;
@@ -700,38 +651,14 @@ __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, doubl
             for (int jj = 0; jj < SNZ; jj++)
                 if (jj < len[u]) s = s + pv[u][jj];
             for (int32_t j = beg[u] + SNZ; j < beg[u] + len[u]; j++) {
-                const double pr = S.val[j] * gather(S.col[j]);
+                const double pr = S.val[j] * ld_dev(&v[S.col[j]]);
                 s = s + pr;
             }
             const int64_t i = base + u * BLOCK + threadIdx.x;
-            ok[u] = i < r1;
-            vi[u] = 0.0;
-            oi[u] = 0.0;
-            if (ok[u]) {
+            if (i < r1) {
                 out[i] = s;
-                oi[u] = s;
-                if (fd) {
-                    // own row: the new p (own rows of r and p_old were
-                    // written by this block)
-                    double pn = fold->r[i];
-                    if (!first) {
-                        const double bp = beta * v[i];
-                        pn = pn + bp;
-                    }
-                    st_dev(&fold->pnew[i], pn);
-                    vi[u] = pn;
-                } else if (MODE != 0) {
-                    vi[u] = v[i];
-                }
+                if (SCAN) scan_pair(v[i], s, key_mode, *L, *nz, *bad, *sg);
             }
-        }
-        if constexpr (MODE == 1) {
-#pragma unroll
-            for (int u = 0; u < SR; u++)
-                if (ok[u]) scan_pair(vi[u], oi[u], rs->key_mode, *rs->L, rs->nz, rs->bad, rs->sg);
-        } else if constexpr (MODE == 2) {
-            s1_group<SR>(vi, oi, ok, rs->key_mode, rs->depth, rs->L->h, *rs->S1, rs->run, rs->nz,
-                         rs->bad);
         }
     }
 }
@@ -740,14 +667,6 @@ __device__ __forceinline__ void spmv_rows(const CgSys &S, const double *v, doubl
 // ACC1: every inner product by the one-pass qdot (gang_qdot_s1, with the
 // caller's LDS window S1 and the gang's table tab, 2 W S1_PIECES doubles);
 // otherwise by the two-pass qdot, guaranteed with GUARD.
-//
-// Per iteration (Alg. 4): q = A p with p = r + beta p_old formed inside the
-// SpMV (SpmvFold), then alpha = c / (p . q), then x += alpha p and r -=
-// alpha q, then c' = r . r and beta = c' / c.  The keys of p . q (two-pass
-// pass 1, or the one-pass window) are taken in the SpMV, those of r . r in
-// the x / r update, so neither qdot reads its vectors for them again.  The
-// gang barriers of an iteration are those of its two inner products: two
-// per two-pass qdot, one per one-pass qdot or FP64 dot.
 template <bool GUARD, bool ACC1 = false>
 __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb, int key_mode,
                                          int score_mode, int nonstrict, CgLds &L,
@@ -760,30 +679,17 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
     const int64_t r0 = min(n, (int64_t)gb * per), r1 = min(n, r0 + per);
     int k = 0;  // qdot buffer / partials parity
     int ntr = 0;
-    // MODE of the rows' pass through the qdot that follows them
-    const int mode = S.use_qdot ? (ACC1 ? 2 : 1) : 0;
-    const int depth = ACC1 && S.use_qdot ? s1_depth_dev(n, S.qtol, score_mode) : 0;
-    auto rows_begin = [&]() {
-        RowScan rs = {key_mode, &L, 0u, 0u, 0u, S1, s1_run_start(), depth};
-        if (ACC1 && S.use_qdot) {
-            s1_begin(*S1);
-            __syncthreads();
-        }
-        return rs;
-    };
-    auto dot = [&](const double *a, const double *bv, RowScan *fed) {
+    auto dot = [&](const double *a, const double *bv, bool scanned = false, unsigned int nz = 0,
+                   unsigned int bad = 0, unsigned int sg = 0) {
         DotOut o;
         if (S.use_qdot) {
             qdot_result *ts = (gb == 0 && S.trace) ? S.trace + ntr : nullptr;
             if constexpr (ACC1)
                 o = gang_qdot_s1(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict, gg,
-                                 G, gb, k, L, *S1, tab + (size_t)k * W * S1_PIECES, ts,
-                                 fed ? &fed->run : nullptr, fed ? fed->nz : 0u,
-                                 fed ? fed->bad : 0u);
+                                 G, gb, k, L, *S1, tab + (size_t)k * W * S1_PIECES, ts);
             else
                 o = gang_qdot<GUARD>(a, bv, n, r0, r1, S.qtol, key_mode, score_mode, nonstrict,
-                                     gg, G, gb, k, L, ts, fed != nullptr, fed ? fed->nz : 0u,
-                                     fed ? fed->bad : 0u, fed ? fed->sg : 0u);
+                                     gg, G, gb, k, L, ts, scanned, nz, bad, sg);
             ntr++;
         } else {
             o = gang_dot64(a, bv, r0, r1, gg, G, gb, k, L);
@@ -793,21 +699,21 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
     };
     int status = QDOT_OK, iters = 0;
     bool healthy = true;
-    // r0 = b - A x0 (p0 = r0 is formed by the first iteration's SpMV)
+    // r0 = b - A x0, p0 = r0
     spmv_rows(S, S.x, S.q, r0, r1);
     for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
         const double v = S.b[i] - S.q[i];
-        st_dev(&S.r[i], v);
+        S.r[i] = v;
+        st_dev(&S.p[i], v);
     }
     __syncthreads();
     DotOut bb = gang_dot64(S.b, S.b, r0, r1, gg, G, gb, k, L);
     k ^= 1;
     const double bnorm = sqrt(bb.value);
     const double thresh = S.rtol * bnorm;
-    DotOut c0 = dot(S.r, S.r, nullptr);
+    DotOut c0 = dot(S.r, S.r);
     healthy = bb.ok && c0.ok;
     double c = c0.value;
-    double beta = 0.0;
     bool done = false;
     if (healthy && c0.all_perf) {
         status = QDOT_E_BREAKDOWN;
@@ -820,18 +726,17 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
             status = QDOT_E_MAXIT;
             break;
         }
-        double *pold = (iters & 1) ? S.pb : S.p;
-        double *p = (iters & 1) ? S.p : S.pb;
-        const SpmvFold fold = {S.r, beta, iters == 0, p};
-        RowScan rq = rows_begin();
-        if (mode == 0)
-            spmv_rows<0>(S, pold, S.q, r0, r1, &fold, nullptr);
-        else if constexpr (ACC1)
-            spmv_rows<2>(S, pold, S.q, r0, r1, &fold, &rq);
+        if (!(healthy = gang_barrier(gg, G, gb))) break;  // p complete
+        // pass 1 of the two-pass qdot(p, q) rides in the SpMV; the one-pass
+        // qdot reads its rows itself
+        const bool scan_q = S.use_qdot != 0 && !ACC1;
+        unsigned int nz1 = 0, bad1 = 0, sg1 = 0;
+        if (scan_q)
+            spmv_rows<true>(S, S.p, S.q, r0, r1, key_mode, &L, &nz1, &bad1, &sg1);
         else
-            spmv_rows<1>(S, pold, S.q, r0, r1, &fold, &rq);
+            spmv_rows(S, S.p, S.q, r0, r1);
         __syncthreads();
-        const DotOut d = dot(p, S.q, mode ? &rq : nullptr);
+        const DotOut d = dot(S.p, S.q, scan_q, nz1, bad1, sg1);
         if (!(healthy = d.ok)) break;
         if (!(d.value > 0.0) || !isfinite(d.value) || d.all_perf) {
             status = QDOT_E_BREAKDOWN;
@@ -839,54 +744,62 @@ __device__ __forceinline__ void cg_solve(const CgSys &S, Gang *gg, int G, int gb
         }
         const double alpha = c / d.value;
         // x += alpha p, r -= alpha q (four rows' loads in flight per thread),
-        // with the keys of the qdot r . r that follows.  r is written with
-        // device-scope stores: the next SpMV gathers it.
-        RowScan rr = rows_begin();
-        for (int64_t base = r0; base < r1; base += 4 * BLOCK) {
-            double pi[4], xi[4], qi[4], ri[4], rn[4];
-            bool ok[4];
+        // with pass 1 of the qdot r . r that follows fused in
+        unsigned int nz2 = 0, bad2 = 0, sg2 = 0;
+        const bool scan_r = S.use_qdot != 0 && !ACC1;
+        auto xr_row = [&](int64_t i, double pi, double xi, double qi, double ri) {
+            const double ap = alpha * pi;
+            st_dev(&S.x[i], xi + ap);
+            const double aq = alpha * qi;
+            const double rn = ri - aq;
+            S.r[i] = rn;
+            if (scan_r) scan_pair(rn, rn, key_mode, L, nz2, bad2, sg2);
+        };
+        {
+            int64_t i = r0 + threadIdx.x;
+            for (; i + 3 * BLOCK < r1; i += 4 * BLOCK) {
+                double pi[4], xi[4], qi[4], ri[4];
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int64_t i = base + u * BLOCK + threadIdx.x;
-                ok[u] = i < r1;
-                pi[u] = xi[u] = qi[u] = ri[u] = 0.0;
-                if (ok[u]) {
-                    pi[u] = p[i];
-                    xi[u] = S.x[i];
-                    qi[u] = S.q[i];
-                    ri[u] = S.r[i];
+                for (int u = 0; u < 4; u++) {
+                    pi[u] = S.p[i + u * BLOCK];
+                    xi[u] = S.x[i + u * BLOCK];
+                    qi[u] = S.q[i + u * BLOCK];
+                    ri[u] = S.r[i + u * BLOCK];
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int64_t i = base + u * BLOCK + threadIdx.x;
-                rn[u] = 0.0;
-                if (ok[u]) {
-                    const double ap = alpha * pi[u];
-                    st_dev(&S.x[i], xi[u] + ap);
-                    const double aq = alpha * qi[u];
-                    rn[u] = ri[u] - aq;
-                    st_dev(&S.r[i], rn[u]);
-                }
+                for (int u = 0; u < 4; u++) xr_row(i + u * BLOCK, pi[u], xi[u], qi[u], ri[u]);
             }
-            if (mode != 0) {
-                if constexpr (ACC1) {
-                    s1_group<4>(rn, rn, ok, key_mode, depth, L.h, *S1, rr.run, rr.nz, rr.bad);
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; u++)
-                        if (ok[u]) scan_pair(rn[u], rn[u], key_mode, L, rr.nz, rr.bad, rr.sg);
-                }
-            }
+            for (; i < r1; i += BLOCK) xr_row(i, S.p[i], S.x[i], S.q[i], S.r[i]);
         }
         __syncthreads();
-        const DotOut cn = dot(S.r, S.r, mode ? &rr : nullptr);
+        const DotOut cn = dot(S.r, S.r, scan_r, nz2, bad2, sg2);
         if (!(healthy = cn.ok)) break;
         if (cn.all_perf) {
             status = QDOT_E_BREAKDOWN;
             break;
         }
-        beta = cn.value / c;
+        const double beta = cn.value / c;
+        // p = r + beta p (four rows' loads in flight per thread)
+        {
+            int64_t i = r0 + threadIdx.x;
+            for (; i + 3 * BLOCK < r1; i += 4 * BLOCK) {
+                double pi[4], ri[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    pi[u] = S.p[i + u * BLOCK];
+                    ri[u] = S.r[i + u * BLOCK];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const double bp = beta * pi[u];
+                    st_dev(&S.p[i + u * BLOCK], ri[u] + bp);
+                }
+            }
+            for (; i < r1; i += BLOCK) {
+                const double bp = beta * S.p[i];
+                st_dev(&S.p[i], S.r[i] + bp);
+            }
+        }
         c = cn.value;
         iters++;
         if (!(sqrt(c) > thresh)) done = true;

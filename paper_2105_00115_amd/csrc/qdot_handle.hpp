@@ -21,7 +21,7 @@ struct qdot_handle {
 
     // solver scratch, grown on demand: the power method keeps w = A x of
     // the current and the previous iteration (2 n doubles), the
-    // single-system CG keeps r, two p buffers and q (4 n doubles)
+    // single-system CG keeps r, p, q (3 n doubles)
     double *vec = nullptr;
     int64_t vec_n = 0;               // doubles held at vec
     void *ctl = nullptr;             // solver control block
@@ -35,6 +35,9 @@ struct qdot_handle {
     int64_t batch_chunk = 131072;    // components per chunk of a large instance
     int64_t batch_cg_rows = 16384;   // CG rows per gang block
     int batch_cg_gang_max = 16;      // CG gang blocks at most
+    int spmv_blocks_per_cu = 8;      // SpMV grid
+    int cg_blocks_per_cu = 2;        // single-system CG gang
+    int power_scan_in_spmv = 0;      // power method: pass 1 inside the SpMV
     void *cg = nullptr;              // persistent CG buffers
 
     // kernel timing (diagnostics)

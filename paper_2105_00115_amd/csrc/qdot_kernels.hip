@@ -22,19 +22,19 @@ namespace qd {
 // global histograms (blockIdx % copies; 8: one per XCD under round-robin
 // dispatch) so that the merge atomics of concurrent blocks spread out.
 // ---------------------------------------------------------------------------
-template <class T, bool VEC, int U>
-__global__ __launch_bounds__(BLOCK) void k_scan(const T *__restrict__ x,
-                                                const T *__restrict__ y,
-                                                int64_t n, int key_mode,
-                                                Ws *__restrict__ ws, int copies)
+template <class T, bool VEC, int U, int NT = BLOCK>
+__global__ __launch_bounds__(NT) void k_scan(const T *__restrict__ x,
+                                             const T *__restrict__ y,
+                                             int64_t n, int key_mode,
+                                             Ws *__restrict__ ws, int copies)
 {
     __shared__ unsigned int h[W + 1];
-    for (int i = threadIdx.x; i < W + 1; i += BLOCK) h[i] = 0;
+    for (int i = threadIdx.x; i < W + 1; i += NT) h[i] = 0;
     __syncthreads();
 
     unsigned int nz = 0, bad = 0, sg = 0;
     // float inputs: the 32-bit decomposition gives the key of the same values
-    stream_groups<VEC, U>(x, y, n, [&](const T *xv, const T *yv, int64_t, int lim) {
+    stream_groups<VEC, U, NT>(x, y, n, [&](const T *xv, const T *yv, int64_t, int lim) {
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const auto c = [&]() {
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const T *__restrict__ x,
         }
     });
     __syncthreads();
-    scan_flush(h, nz, bad, sg, ws, blockIdx.x, copies);
+    scan_flush<NT>(h, nz, bad, sg, ws, blockIdx.x, copies);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,32 +185,32 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut_bins(Ws *__restrict__ ws, d
 // Block `blk` of `nblk` (grid-stride over groups) writes its partials at
 // partials + 6 * blk.
 // Q: the compacting form of the leaf work (acc_group_q), else acc_group.
-template <class T, bool VEC, int U, bool CLS, bool Q = false>
+template <class T, bool VEC, int U, bool CLS, bool Q = false, int NT = BLOCK>
 __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__restrict__ y,
                                          int64_t n, int key_mode, const Ws *__restrict__ ws,
                                          double *__restrict__ partials,
                                          unsigned char *__restrict__ cls_out, int blk, int nblk)
 {
     __shared__ unsigned char lut[W_LUT];
-    __shared__ Acc red[3][BLOCK / 64];
-    __shared__ AccWaveLds wl[Q ? BLOCK / 64 : 1];
+    __shared__ Acc red[3][NT / 64];
+    __shared__ AccWaveLds wl[Q ? NT / 64 : 1];
 
     const int skip = ws->skip;
     if (skip && !CLS) return;
     {
         const unsigned int *src = reinterpret_cast<const unsigned int *>(ws->lut);
         unsigned int *dst = reinterpret_cast<unsigned int *>(lut);
-        for (int i = threadIdx.x; i < W_LUT / 4; i += BLOCK) dst[i] = src[i];
+        for (int i = threadIdx.x; i < W_LUT / 4; i += NT) dst[i] = src[i];
     }
     const int e_max = ws->e_max;
     const int c32 = ws->c32;
-    if (Q) acc_q_begin<BLOCK>(wl);
+    if (Q) acc_q_begin<NT>(wl);
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     Acc aD = {0.0, 0.0}, aS = {0.0, 0.0}, aH = {0.0, 0.0};
-    const int64_t group = (int64_t)CHUNK * U;
-    stream_strided<VEC, U>(x, y, (int64_t)blk * group, (int64_t)nblk * group, n,
+    const int64_t group = (int64_t)NT * EPT * U;
+    stream_strided<VEC, U, NT>(x, y, (int64_t)blk * group, (int64_t)nblk * group, n,
                            [&](const T *xv, const T *yv, int64_t i0, int lim) {
         if constexpr (Q)
             acc_group_q<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
@@ -235,23 +235,23 @@ __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__res
         double *p = partials + (size_t)blk * 6;
         for (int q = 0; q < 3; q++) {
             Acc b = red[q][0];
-            for (int w = 1; w < BLOCK / 64; w++) b = acc_merge(b, red[q][w]);
+            for (int w = 1; w < NT / 64; w++) b = acc_merge(b, red[q][w]);
             p[2 * q] = b.s;
             p[2 * q + 1] = b.c;
         }
     }
 }
 
-template <class T, bool VEC, int U, bool CLS, bool Q>
-__global__ __launch_bounds__(BLOCK) void k_acc(const T *__restrict__ x,
-                                               const T *__restrict__ y,
-                                               int64_t n, int key_mode,
-                                               const Ws *__restrict__ ws,
-                                               double *__restrict__ partials,
-                                               unsigned char *__restrict__ cls_out)
+template <class T, bool VEC, int U, bool CLS, bool Q, int NT = BLOCK>
+__global__ __launch_bounds__(NT) void k_acc(const T *__restrict__ x,
+                                            const T *__restrict__ y,
+                                            int64_t n, int key_mode,
+                                            const Ws *__restrict__ ws,
+                                            double *__restrict__ partials,
+                                            unsigned char *__restrict__ cls_out)
 {
-    acc_body<T, VEC, U, CLS, Q>(x, y, n, key_mode, ws, partials, cls_out, blockIdx.x,
-                                gridDim.x);
+    acc_body<T, VEC, U, CLS, Q, NT>(x, y, n, key_mode, ws, partials, cls_out, blockIdx.x,
+                                    gridDim.x);
 }
 
 // Combine the per-block partials of k_acc in a fixed order (one block).
@@ -539,10 +539,28 @@ __global__ __launch_bounds__(BLOCK) void k_dot_fin(const double *__restrict__ pa
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-static int grid_for(int64_t n, int unroll, int cap)
+static int grid_for(int64_t n, int unroll, int cap, int nt = BLOCK)
 {
-    const int64_t groups = (n + (int64_t)CHUNK * unroll - 1) / ((int64_t)CHUNK * unroll);
+    const int64_t g = (int64_t)nt * EPT * unroll;
+    const int64_t groups = (n + g - 1) / g;
     return (int)std::max<int64_t>(1, std::min<int64_t>(cap, groups));
+}
+
+// Threads per block of the scan and accumulate kernels: the tuned value for
+// aligned double inputs (the hot path), BLOCK otherwise.  The grid caps of
+// the tune entry count blocks of BLOCK threads, so a block of nt threads
+// stands for nt / BLOCK of them.
+template <class T, bool VEC>
+static int block_threads(const Launch &L)
+{
+    return (sizeof(T) == 8 && VEC && (L.block_threads == 128 || L.block_threads == 512))
+               ? L.block_threads
+               : BLOCK;
+}
+
+static int cap_for(int cap_blocks, int nt)
+{
+    return std::max(1, (int)((int64_t)cap_blocks * BLOCK / nt));
 }
 
 // Groups in flight per wave: a group of single-precision inputs is half the
@@ -553,13 +571,26 @@ static int unroll_for(int u)
     return sizeof(T) == 4 ? std::min(4, 2 * u) : u;
 }
 
+template <class T, bool VEC, int U, int NT>
+static int launch_scan_nt(const Launch &L, const T *x, const T *y, int64_t n, int key_mode)
+{
+    const int grid = grid_for(n, U, std::min(MAX_GRID, cap_for(L.scan_blocks, NT)), NT);
+    hipLaunchKernelGGL((k_scan<T, VEC, U, NT>), dim3(grid), dim3(NT), 0, L.stream, x, y, n,
+                       key_mode, L.ws, L.hist_copies);
+    return grid;
+}
+
 template <class T, bool VEC, int U>
 static int launch_scan_u(const Launch &L, const T *x, const T *y, int64_t n, int key_mode)
 {
-    const int grid = grid_for(n, U, L.scan_blocks);
-    hipLaunchKernelGGL((k_scan<T, VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
-                       key_mode, L.ws, L.hist_copies);
-    return grid;
+    if constexpr (sizeof(T) == 8 && VEC) {
+        switch (block_threads<T, VEC>(L)) {
+        case 128: return launch_scan_nt<T, VEC, U, 128>(L, x, y, n, key_mode);
+        case 512: return launch_scan_nt<T, VEC, U, 512>(L, x, y, n, key_mode);
+        default: break;
+        }
+    }
+    return launch_scan_nt<T, VEC, U, BLOCK>(L, x, y, n, key_mode);
 }
 
 template <class T, bool VEC>
@@ -572,18 +603,33 @@ static int launch_scan(const Launch &L, const T *x, const T *y, int64_t n, int k
     }
 }
 
+template <class T, bool VEC, int U, bool CLS, int NT>
+static int launch_acc_nt(const Launch &L, const T *x, const T *y, int64_t n, int key_mode,
+                         unsigned char *cls_out)
+{
+    // the partials hold L.partial_cap blocks of any size
+    const int grid = grid_for(n, U, std::min(L.partial_cap, cap_for(L.acc_blocks, NT)), NT);
+    if (L.acc_form == 1)
+        hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, true, NT>), dim3(grid), dim3(NT), 0, L.stream,
+                           x, y, n, key_mode, L.ws, L.partials, cls_out);
+    else
+        hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, false, NT>), dim3(grid), dim3(NT), 0,
+                           L.stream, x, y, n, key_mode, L.ws, L.partials, cls_out);
+    return grid;
+}
+
 template <class T, bool VEC, int U, bool CLS>
 static int launch_acc_u(const Launch &L, const T *x, const T *y, int64_t n, int key_mode,
                         unsigned char *cls_out)
 {
-    const int grid = grid_for(n, U, L.acc_blocks);
-    if (L.acc_form == 1)
-        hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, true>), dim3(grid), dim3(BLOCK), 0, L.stream,
-                           x, y, n, key_mode, L.ws, L.partials, cls_out);
-    else
-        hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, false>), dim3(grid), dim3(BLOCK), 0, L.stream,
-                           x, y, n, key_mode, L.ws, L.partials, cls_out);
-    return grid;
+    if constexpr (sizeof(T) == 8 && VEC && !CLS) {
+        switch (block_threads<T, VEC>(L)) {
+        case 128: return launch_acc_nt<T, VEC, U, CLS, 128>(L, x, y, n, key_mode, cls_out);
+        case 512: return launch_acc_nt<T, VEC, U, CLS, 512>(L, x, y, n, key_mode, cls_out);
+        default: break;
+        }
+    }
+    return launch_acc_nt<T, VEC, U, CLS, BLOCK>(L, x, y, n, key_mode, cls_out);
 }
 
 template <class T, bool VEC, bool CLS>

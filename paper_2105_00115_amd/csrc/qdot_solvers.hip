@@ -43,7 +43,6 @@ static inline int vgrid(int64_t n) { return (int)std::max<int64_t>(1, (n + VB - 
 // length keep their order.
 constexpr int SP_U = 8;
 constexpr int SP_NZ = SP_U * BLOCK;
-constexpr int SPMV_BLOCKS_PER_CU = 8;
 
 // The SpMV loop over a block's row groups.  gather(c) gives the vector entry
 // of column c; own(i, yi) is called once per row with its result.
@@ -237,8 +236,7 @@ __global__ __launch_bounds__(BLOCK) void k_pm_spmv(
 
 static int spmv_grid(const qdot_handle *h, int64_t n)
 {
-    int bpc = SPMV_BLOCKS_PER_CU;
-    if (const char *e = std::getenv("QDOT_SPMV_BPC")) bpc = std::max(1, std::min(16, std::atoi(e)));
+    const int bpc = h->spmv_blocks_per_cu;
     const int64_t cap = std::min<int64_t>(MAX_GRID, (int64_t)bpc * h->num_cus);
     return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (n + BLOCK - 1) / BLOCK));
 }
@@ -431,7 +429,7 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
         qdot_result *rb = ra + 1;
         // after the first iteration the paired qdot's pass 1 rides in the
         // SpMV (its windows placed by the previous iteration's results)
-        const bool fused = paired && k > 0;
+        const bool fused = paired && k > 0 && h->power_scan_in_spmv;
         const PmScan ps = {{L.ws, L2.ws}, {lr, cr}, o.key_mode, L.hist_copies};
         if (fused)
             hipLaunchKernelGGL(k_pm_spmv<true>, dim3(sg), dim3(BLOCK), 0, s, n, A->rowptr,

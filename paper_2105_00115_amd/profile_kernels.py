@@ -1,0 +1,85 @@
+"""A short run of the hot kernels for profiler counter passes.
+
+Runs, in this order, on cuda:0:
+
+1. a 256 MiB ``torch`` copy (256 MiB read, 256 MiB written), whose
+   FETCH_SIZE / WRITE_SIZE give the scale factors of the byte counters;
+2. the single qdot on the throughput workload (n = 2^27 FP64 components
+   +-10^U[-20,20], tol 1e-6): ``steps`` calls of the two-pass mode, of the
+   one-pass mode and of the FP64 dot;
+3. CG on the 2D Poisson matrix 1024^2 (qdot tol 1e-8, stop at 1e-10) with
+   the two-pass qdot, the FP64 dot and the one-pass qdot, one solve each;
+4. the power method on the 3D Laplacian 128^3, ``power_iters`` iterations
+   with the two-pass qdot.
+
+Each phase prints its name and, for the solvers, the iteration counts, so
+that per-dispatch counters can be divided by iterations.
+
+    python3 paper_2105_00115_amd/profile_kernels.py [--steps 3] [--power-iters 50]
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--power-iters", type=int, default=50)
+    a = ap.parse_args(argv)
+    import torch
+
+    import paper_2105_00115_amd as q
+    import workloads
+
+    dev = "cuda:0"
+    print("[profile] calibration copy 256 MiB", flush=True)
+    src = torch.empty(1 << 25, dtype=torch.float64, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+    n, tol = 1 << 27, 1e-6
+    print(f"[profile] single qdot n={n} tol={tol}", flush=True)
+    x, y = workloads.log_uniform_pair_torch(n, 2027, dev)
+    h = q.Qdot(0)
+    out = torch.zeros(q.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    d_out = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(a.steps):
+        h.qdot_async(x, y, tol, out)
+    for _ in range(a.steps):
+        h.qdot_async(x, y, tol, out, opt=[0, 0, 0, 1])
+    for _ in range(a.steps):
+        h.fp64_dot_async(x, y, d_out)
+    torch.cuda.synchronize()
+    del x, y
+
+    m = 1024
+    print(f"[profile] CG 2D Poisson {m}^2", flush=True)
+    A = q.Csr(*workloads.poisson2d_csr(m), device=dev)
+    b = torch.from_numpy(workloads.normal_vector(m * m, 3)).to(dev)
+    for name, use, opt in (("qdot", 1, None), ("fp64", 0, None), ("qdot_one_pass", 1, [0, 0, 0, 1])):
+        xs = torch.zeros(m * m, dtype=torch.float64, device=dev)
+        r = h.cg(A, b, xs, 1e-10, 1e-8, 20000, use, opt=opt)
+        print(f"[profile] CG {name}: {r['iters']} iterations, status {r['status']}", flush=True)
+    del A, b
+
+    m3 = 128
+    print(f"[profile] power method 3D Laplacian {m3}^3, {a.power_iters} iterations", flush=True)
+    A = q.Csr(*workloads.laplacian3d_csr(m3), device=dev)
+    xs = torch.from_numpy(workloads.unit_vector(m3 ** 3, 4)).to(dev)
+    r = h.power(A, xs, a.power_iters, 1e-6, 1, trace=False)
+    print(f"[profile] power: lambda {r['lambda']!r}, status {r['status']}", flush=True)
+    h.close()
+    print("[profile] done", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,7 +68,7 @@ int main(void) {
   printf("qdot_cg_result %zu\n", sizeof(qdot_cg_result));
   printf("qdot_tune %zu\n", sizeof(qdot_tune));
   printf("qdot_cg_system %zu\n", sizeof(qdot_cg_system));
-  printf("qdot_batch_tune %zu\n", sizeof(qdot_batch_tune));
+  printf("qdot_solver_tune %zu\n", sizeof(qdot_solver_tune));
   P(qdot_result, value); P(qdot_result, count); P(qdot_result, n_zero);
   P(qdot_result, e_min); P(qdot_result, e_max); P(qdot_result, n_bins);
   P(qdot_result, t); P(qdot_result, part); P(qdot_result, bound_rel);
@@ -94,7 +94,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     types = {"qdot_result": q.QdotResult, "qdot_options": q.QdotOptions,
              "qdot_csr": q.QdotCsr, "qdot_cg_result": q.QdotCgResult,
              "qdot_tune": q.QdotTune, "qdot_cg_system": q.QdotCgSystem,
-             "qdot_batch_tune": q.QdotBatchTune}
+             "qdot_solver_tune": q.QdotSolverTune}
     for k, v in got.items():
         if "." in k:
             t, f = k.split(".")

@@ -182,15 +182,17 @@ def test_batched_under_other_batch_shapes(shape):
     # never a tile or a class: every instance still equals the oracle's
     bpc, chunk = shape
     with q.Qdot(0, load_tuned=False) as hh:
-        hh.set_batch_tune(blocks_per_cu=bpc, chunk=chunk)
-        assert hh.get_batch_tune()[:2] == (bpc, chunk)
+        hh.set_solver_tune(batch_blocks_per_cu=bpc, batch_chunk=chunk)
+        assert hh.get_solver_tune()[:2] == (bpc, chunk)
         offsets, x, y, tols = ragged_case(31, EDGE + (300000,), count=40)
         for opt in (None, [0, 0, 0, 1]):
             res = hh.batched(dev(x), dev(y), offsets, tols, opt=opt)
             check_instances(res, offsets, x, y, tols, opt=opt)
-        hh.set_batch_tune()
-        assert hh.get_batch_tune() == (4, 131072, 16384, 16)
+        hh.set_solver_tune()
+        assert hh.get_solver_tune() == (4, 131072, 16384, 16, 8, 2, 0)
         with pytest.raises(q.QdotError):
-            hh.set_batch_tune(chunk=1000)  # not a multiple of 2048
+            hh.set_solver_tune(batch_chunk=1000)  # not a multiple of 2048
         with pytest.raises(q.QdotError):
-            hh.set_batch_tune(cg_gang_max=513)
+            hh.set_solver_tune(cg_gang_max=513)
+        with pytest.raises(q.QdotError):
+            hh.set_solver_tune(cg_blocks_per_cu=3)

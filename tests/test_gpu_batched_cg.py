@@ -240,7 +240,7 @@ def test_cg_batched_gang_sizing(rows, gmax):
     # other gang sizes: every system still takes its FP64 twin's iteration
     # count and stays within one of the oracle's
     with q.Qdot(0, load_tuned=False) as hh:
-        hh.set_batch_tune(cg_rows_per_block=rows, cg_gang_max=gmax)
+        hh.set_solver_tune(cg_rows_per_block=rows, cg_gang_max=gmax)
         sides = (45, 140, 256)
         sq = [poisson_system(m, 300 + m, 1) for m in sides]
         sf = [poisson_system(m, 300 + m, 0) for m in sides]

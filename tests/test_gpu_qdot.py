@@ -202,11 +202,13 @@ def test_repeat_and_tuning_invariance(h):
     assert again["value"] == base["value"]  # same launch configuration: bitwise
     o = oracle.qdot(x, y, 1e-6)
     scale = oracle.abs_dot(x, y)
-    # launch shapes, both forms of the accumulate pass, histogram copies
-    for sb, su, ab, au, af, hc in [(1, 1, 1, 1, 0, 8), (2, 2, 8, 4, 1, 8), (8, 4, 2, 2, 1, 1),
-                                   (16, 1, 16, 2, 0, 2), (4, 2, 1, 4, 1, 4),
-                                   (2, 1, 2, 2, 1, 8)]:
-        h.set_tune(-1, sb, su, ab, au, 4, 1, af, hc)
+    # launch shapes, both forms of the accumulate pass, histogram copies,
+    # threads per block
+    for sb, su, ab, au, af, hc, nt in [(1, 1, 1, 1, 0, 8, 256), (2, 2, 8, 4, 1, 8, 512),
+                                       (8, 4, 2, 2, 1, 1, 128), (16, 1, 16, 2, 0, 2, 512),
+                                       (4, 2, 1, 4, 1, 4, 256), (2, 1, 2, 2, 1, 8, 128),
+                                       (1, 4, 1, 1, 0, 8, 512)]:
+        h.set_tune(-1, sb, su, ab, au, 4, 1, af, hc, nt)
         cls, hist, r = h.qdot_classes(xd, yd, 1e-6)
         assert torch.equal(cls, base_cls) and torch.equal(hist, base_hist)
         assert r["count"] == base["count"]
@@ -225,11 +227,28 @@ def test_tune_file_loading(h, tmp_path):
     # a 5-column line leaves the one-pass shape and the rest as they were
     assert h.get_tune(0) == (1, 1, 2, 2) + d0[4:] and h.get_tune(3)[:4] == (8, 4, 16, 1)
     assert h.get_tune(2) == (1, 2, 4, 4, 8, 2) + d2[6:]
-    assert h.get_tune(1) == (2, 1, 2, 2, 4, 1, 1, 4)
+    assert h.get_tune(1) == (2, 1, 2, 2, 4, 1, 1, 4, 256)
+    wide = tmp_path / "wide.txt"
+    wide.write_text("3 2 1 2 2 4 1 0 8 512\n")
+    h.load_tune(str(wide))
+    assert h.get_tune(3) == (2, 1, 2, 2, 4, 1, 0, 8, 512)
+    # the solver line sets the solver and batched launch shapes
+    solver = tmp_path / "solver.txt"
+    solver.write_text("solver 2 65536 8192 32 4 1 1\n")
+    h.load_tune(str(solver))
+    assert h.get_solver_tune() == (2, 65536, 8192, 32, 4, 1, 1)
+    for line in ("solver 2 65536 8192\n", "solver 2 65536 8192 32 4 3 0\n",
+                 "solver 2 65536 8192 32 4 1 2\n"):
+        solver.write_text(line)
+        with pytest.raises(q.QdotError):
+            h.load_tune(str(solver))
+    assert h.get_solver_tune() == (2, 65536, 8192, 32, 4, 1, 1)
+    h.set_solver_tune()
     for line in ("1 2 3 4 5\n",            # unroll 3 is not allowed
                  "1 2 1 2 2 4 1 2 8\n",    # acc_form 2
                  "1 2 1 2 2 4 1 0 3\n",    # 3 histogram copies
-                 "1 2 1 2 2 4 1 0\n"):     # 8 columns
+                 "1 2 1 2 2 4 1 0\n",      # 8 columns
+                 "1 2 1 2 2 4 1 0 8 384\n"):  # 384 threads per block
         bad = tmp_path / "bad.txt"
         bad.write_text(line)
         with pytest.raises(q.QdotError):
@@ -358,13 +377,16 @@ def test_autotuner_on_small_buckets(tmp_path):
     from paper_2105_00115_amd import autotune
     handle, chosen, checked = autotune.tune(reps=2, buckets=[0, 1], log=lambda m: None)
     path = str(tmp_path / "tune.txt")
-    autotune.write(path, chosen, "gfx950", handle.device_info()[1], batch=(4, 131072, 16384, 16))
+    autotune.write(path, chosen, "gfx950", handle.device_info()[1],
+                   batch=(4, 131072, 16384, 16, 8, 2, 0))
     handle.close()
     assert [c[0] for c in chosen] == [0, 1]
-    # per bucket: 15 grid shapes, up to 1 mixed, 7 form/copies shapes, 1 final
-    assert checked >= 2 * (15 + 7 + 1)
+    # per bucket: 15 grid shapes, up to 1 mixed, 23 form/copies/threads
+    # shapes, 1 final
+    assert checked >= 2 * (15 + 23 + 1)
     for c in chosen:
         assert c[2][6] in autotune.ACC_FORM and c[2][7] in autotune.HIST_COPIES
+        assert c[2][8] in autotune.BLOCK_THREADS
     with q.Qdot(0, load_tuned=False) as tuned, q.Qdot(0, load_tuned=False) as plain:
         tuned.load_tune(path)
         for n in (30000, 500000):

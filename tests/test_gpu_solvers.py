@@ -73,12 +73,13 @@ def ragged_csr(n, seed):
 
 
 @pytest.fixture
-def spmv_blocks(monkeypatch):
-    """Sets the SpMV grid (blocks per CU) for one test."""
+def spmv_blocks(h):
+    """Sets the handle's SpMV grid (blocks per CU) for one test."""
     def put(bpc):
         if bpc is not None:
-            monkeypatch.setenv("QDOT_SPMV_BPC", str(bpc))
-    return put
+            h.set_solver_tune(spmv_blocks_per_cu=bpc)
+    yield put
+    h.set_solver_tune()
 
 
 @pytest.mark.parametrize("bpc", [None, 1])
@@ -453,3 +454,26 @@ def test_full_size_power_laplacian_128(h):
     lam_max = 6.0 + 6.0 * math.cos(math.pi / (m + 1))
     assert abs(lam[1] - lam[0]) <= 1e-9 * lam[0]
     assert lam[0] <= lam_max * (1 + 1e-12) and lam[0] > 0.99 * lam_max
+
+
+@pytest.mark.parametrize("m,opt", [(16, None), (64, None), (40, [1, 1, 1, 0]),
+                                   (32, [0, 0, 0, 0, 1])])
+def test_power_scan_in_spmv_is_the_same_method(h, m, opt):
+    # pass 1 of the paired inner products taken inside the SpMV (after the
+    # first iteration) gives every iteration's results bit for bit as the
+    # separate pass-1 kernel does: lambda trace, qdot results, final x
+    rp, col, val = workloads.laplacian3d_csr(m)
+    A = q.Csr(rp, col, val)
+    x0 = workloads.unit_vector(m ** 3, 21)
+    out = {}
+    for fused in (0, 1):
+        print(f"[gpu-case] power scan in SpMV={fused} m={m} opt={opt}", flush=True)
+        h.set_solver_tune(power_scan_in_spmv=fused)
+        xd = dev(x0)
+        out[fused] = (h.power(A, xd, 40, 1e-6, 1, opt=opt, results=True), xd.cpu().numpy())
+    h.set_solver_tune()
+    (r0, x0d), (r1, x1d) = out[0], out[1]
+    assert r0["status"] == r1["status"] == q.OK
+    np.testing.assert_array_equal(r0["trace"], r1["trace"])
+    assert r0["results"] == r1["results"]
+    np.testing.assert_array_equal(x0d, x1d)
