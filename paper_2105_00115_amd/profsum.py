@@ -15,6 +15,8 @@ kernel's counters (KiB per dispatch, averaged over its first N dispatches)
 are scaled to bytes by what the same counters read for a copy of known
 size (``--calib KERNEL:GRID:BYTES``, bytes read = bytes written) and
 compared with ``--algo`` bytes per launch; ``--json`` writes the table.
+``--each`` lists every dispatch instead, its bytes also divided by
+``--per`` (the iteration count of a persistent solver launch).
 """
 from __future__ import annotations
 
@@ -87,6 +89,18 @@ def pmc_main(a):
     table = OrderedDict()
     print(f"fetch factor {ff:.4f}, write factor {wf:.4f} "
           f"({ck} grid {cgrid}: FETCH {cf[0]:.1f} KiB, WRITE {cw[0]:.1f} KiB)")
+    if a.each:
+        # one row per dispatch, bytes divided by --per (e.g. the iterations
+        # of a persistent solver launch)
+        print(f"| kernel | dispatch | FETCH_SIZE KiB (raw) | WRITE_SIZE KiB (raw) | "
+              f"HBM bytes (scaled) | bytes / {a.per:g} |")
+        print("|---|---|---|---|---|---|")
+        for base in (kernels or fetch.keys()):
+            for i, ((_, fv, name), (_, wv, _)) in enumerate(zip(fetch.get(base, []),
+                                                                write.get(base, []))):
+                hb = (fv * ff + wv * wf) * 1024.0
+                print(f"| {name} | {i} | {fv:.1f} | {wv:.1f} | {hb:.4e} | {hb / a.per:.4e} |")
+        return
     print("| kernel | dispatches | FETCH_SIZE KiB (raw) | WRITE_SIZE KiB (raw) | "
           "HBM bytes / launch (scaled) | / algorithmic |")
     print("|---|---|---|---|---|---|")
@@ -118,6 +132,8 @@ def main(argv=None):
     ap.add_argument("--json", default=None)
     ap.add_argument("--first", type=int, default=None)
     ap.add_argument("--kernels", default=None)
+    ap.add_argument("--each", action="store_true", help="with --pmc: one row per dispatch")
+    ap.add_argument("--per", type=float, default=1.0, help="with --each: divide bytes by this")
     ap.add_argument("--bytes", default="", help="kernel=bytes_per_launch,...")
     a = ap.parse_args(argv)
     if a.pmc:
