@@ -82,6 +82,58 @@ def class_mix(results, n, series):
     return out
 
 
+def tile_skip_report(h, A, n, dev):
+    """Tile skipping (tile_skip 1) on vectors whose index ranges fall into
+    the perforated class: the residuals r = b - A x_k of CG on the 2D
+    Poisson matrix with the smooth right-hand side b = A 1, after k FP64-dot
+    iterations (qdot of r.r at tol 1e-8), and a banded 2^26-component pair
+    (three quarters of its bands 2^-300 below the rest, tol 1e-6).  Per
+    input: the share of 64-component tiles whose components are all
+    perforated (from the classes), the accumulate pass's ms without and with
+    the tile keys (HIP events, 10 calls), and whether the two results agree
+    in every field."""
+    import torch
+
+    import paper_2105_00115_amd as q
+    import workloads
+
+    def one(x, y, tol):
+        nn = x.numel()
+        cls, _, r0 = h.qdot_classes(x, y, tol)
+        full = nn // 64 * 64
+        share = float((cls[:full].view(-1, 64) == q.PERF).all(dim=1).float().mean().item())
+        ms, res = {}, {}
+        for name, opt in (("default", None), ("tile_skip", [0, 0, 0, 0, 0, 0, 0, 1])):
+            res[name] = h.qdot(x, y, tol, opt=opt)
+            h.timing_read()
+            h.timing_enable(True)
+            for _ in range(10):
+                h.qdot(x, y, tol, opt=opt)
+            t = h.timing_read()
+            h.timing_enable(False)
+            ms[name] = round(t["acc_ms"] / t["qdot_calls"], 4)
+        return {"n": nn, "tol": tol, "perforated_tile_share": round(share, 4),
+                "acc_ms": ms, "results_equal": res["default"] == res["tile_skip"]}
+
+    log("tile skipping: CG residuals, a banded pair")
+    out = {}
+    ones = torch.ones(n, dtype=torch.float64, device=dev)
+    b1 = torch.empty_like(ones)
+    h.spmv(A, ones, b1)
+    for k in (20, 200, 1000):
+        xk = torch.zeros_like(b1)
+        h.cg(A, b1, xk, 1e-30, 1e-8, k, 0)
+        ax = torch.empty_like(b1)
+        h.spmv(A, xk, ax)
+        r = b1 - ax
+        out[f"cg_residual_b_A1_iter_{k}"] = one(r, r, 1e-8)
+    x, y = workloads.banded_pair(1 << 26, 81, levels=(0, -300, -300, -300), mean_band=20000.0)
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    del x, y
+    out["banded_2p26"] = one(xd, yd, 1e-6)
+    return out
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -445,6 +497,7 @@ def main():
     xs = torch.zeros(m * m, dtype=torch.float64, device=dev)
     rt = h.cg(A, b, xs, 1e-10, 1e-8, 20000, 1, trace=True)
     cg["class_mix"] = class_mix(rt["trace"], m * m, {"p.Ap": 1, "r.r": 2})
+    tiles = tile_skip_report(h, A, m * m, dev)
     del A, b
 
     # power method on the 3D Laplacian 128^3, 500 iterations, qdot tol 1e-6
@@ -669,6 +722,7 @@ def main():
             "small_qdot_1e5": c1,
             "torch_dot_value": float(tdot.item()),
             "cg_poisson2d_1024": cg,
+            "tile_skip": tiles,
             "batched_ragged_4096": batched,
             "batched_4096_plus_256_cg": batched_cg,
             "power_laplacian3d_128": {**pm, "abs_lambda_diff":

@@ -161,6 +161,23 @@ typedef struct qdot_options {
      * qdot_f32 entry points; QDOT_E_INVAL elsewhere. */
     int32_t bin_mode;
     int32_t bin_param;
+    /* 1: skip perforated tiles in pass 2 (Sec. 4.2 shows whole index ranges
+     * of a solver's vectors falling into the perforated class).  Pass 1
+     * also records, for every 64-component tile of the index order, the
+     * largest key slot of its non-zero products; pass 2 reads neither x nor
+     * y of a tile whose largest key lies below the lowest kept bin, since
+     * every component of it is perforated.  Classes, counts and flags are
+     * those of tile_skip 0, and so is the value, bit for bit, under the
+     * dense accumulate form (qdot_tune acc_form 0; pass 2 with tile keys
+     * always takes it, so a handle tuned to the compacting form gets a
+     * value that may differ by the order of its FP64 additions).  Only the
+     * bytes pass 2 reads change.  The handle keeps 2 bytes per tile (n / 32
+     * bytes), grown at the first call with a larger n (an allocation, so
+     * not while the stream is being captured: QDOT_E_INVAL then).  Needs
+     * accum_mode 0 and guard_mode 0; accepted by qdot_async, qdot,
+     * qdot_classes_async and the qdot_f32 entry points, QDOT_E_INVAL
+     * elsewhere.  0: the default, no tile keys. */
+    int32_t tile_skip;
 } qdot_options;
 
 /* ---- per-call result ------------------------------------------------- */
@@ -306,7 +323,9 @@ QDOT_API int32_t qdot_timing_read(qdot_handle *h, double ms[5], int32_t calls[2]
  * n == 0 or all-zero products give value +0 with QDOT_F_ALL_PERF.
  * Enqueues four kernels (eight with guard_mode 1, whose second pass-2
  * kernels return at once when no reselection is needed); performs no
- * allocation and no host sync, so it may be captured in a HIP graph. */
+ * allocation and no host sync, so it may be captured in a HIP graph
+ * (tile_skip 1: except the first call with a larger n, which grows the
+ * handle's tile keys). */
 QDOT_API int32_t qdot_async(qdot_handle *h, const double *x, const double *y,
                    int64_t n, double tol, const qdot_options *opt,
                    void *stream, qdot_result *dev_out);
@@ -326,8 +345,8 @@ QDOT_API int32_t qdot_async(qdot_handle *h, const double *x, const double *y,
  *   on `stream`.  Every call on one GPU shares its array: calls must be
  *   ordered (one stream, or synchronised); calls that overlap on one GPU
  *   race and give wrong results.
- * Returns QDOT_E_INVAL for the argument errors of qdot_async or a NULL
- * dev_out, QDOT_E_DEVICE when a HIP call fails (no message is kept: there
+ * Returns QDOT_E_INVAL for the argument errors of qdot_async, a NULL
+ * dev_out or tile_skip 1 (the tile keys need memory), QDOT_E_DEVICE when a HIP call fails (no message is kept: there
  * is no handle).  Performs no hipMalloc, hipFree or host sync. */
 QDOT_API int32_t qdot_noalloc_async(const double *x, const double *y, int64_t n,
                            double tol, const qdot_options *opt, void *stream,

@@ -32,7 +32,8 @@ W = KMAX - KMIN + 1
 class QdotOptions(C.Structure):
     _fields_ = [("key_mode", C.c_int32), ("score_mode", C.c_int32),
                 ("boundary_mode", C.c_int32), ("accum_mode", C.c_int32),
-                ("guard_mode", C.c_int32), ("bin_mode", C.c_int32), ("bin_param", C.c_int32)]
+                ("guard_mode", C.c_int32), ("bin_mode", C.c_int32), ("bin_param", C.c_int32),
+                ("tile_skip", C.c_int32)]
 
 
 class QdotResult(C.Structure):

@@ -67,6 +67,7 @@ Launch make_launch_tuned(const qdot_tune &t, int num_cus, Ws *ws, double *partia
     L.s1_blocks = std::min(MAX_GRID, t.onepass_blocks_per_cu * num_cus);
     L.s1_unroll = t.onepass_unroll;
     L.s1tab = s1tab;
+    L.tiles = nullptr;
     // the compacting form is tuned on double inputs; float inputs keep the
     // dense form of their own tuning
     L.acc_form = single ? 0 : t.acc_form;
@@ -112,7 +113,9 @@ bool options_ok(const qdot_options &o)
            (o.boundary_mode == 0 || o.boundary_mode == 1) &&
            (o.accum_mode == 0 || o.accum_mode == 1) &&
            (o.guard_mode == 0 || (o.guard_mode == 1 && o.key_mode == 0 && o.accum_mode == 0)) &&
-           bins_ok;
+           bins_ok &&
+           // tile keys serve the second pass of one selection
+           (o.tile_skip == 0 || (o.tile_skip == 1 && o.accum_mode == 0 && o.guard_mode == 0));
 }
 
 static int ceil_log2_host(int64_t v)
@@ -167,6 +170,34 @@ template int32_t qdot_args<double>(const double *, const double *, int64_t, doub
                                    const qdot_options *, qdot_options &, const char **);
 template int32_t qdot_args<float>(const float *, const float *, int64_t, double,
                                   const qdot_options *, qdot_options &, const char **);
+
+// tile_skip: make the handle's tile keys cover n components and point L at
+// them.  Growing the buffer allocates (after the device has drained, since
+// earlier calls may still read the old one), so it is refused while the
+// stream is being captured.
+static int32_t attach_tiles(qdot_handle *h, hipStream_t s, int64_t n, const qdot_options &o,
+                            Launch &L)
+{
+    if (!o.tile_skip) return QDOT_OK;
+    const int64_t need = std::max<int64_t>(1, (n + TILE - 1) / TILE);
+    if (h->tiles_cap < need) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return fail(h, QDOT_E_INVAL,
+                        "tile_skip: the tile keys must grow (first call with this n) "
+                        "outside graph capture");
+        if (h->tiles) (void)hipFree(h->tiles);
+        h->tiles = nullptr;
+        h->tiles_cap = 0;
+        if (hipMalloc((void **)&h->tiles, sizeof(short) * (size_t)need) != hipSuccess) {
+            h->tiles = nullptr;
+            return fail(h, QDOT_E_NOMEM, "tile key allocation failed");
+        }
+        h->tiles_cap = need;
+    }
+    L.tiles = h->tiles;
+    return QDOT_OK;
+}
 
 template <class T>
 static int32_t check_qdot_args(qdot_handle *h, const T *x, const T *y, int64_t n, double tol,
@@ -235,6 +266,7 @@ int32_t qdot_destroy(qdot_handle *h)
     if (h->dev_res) (void)hipFree(h->dev_res);
     if (h->host_res) (void)hipHostFree(h->host_res);
     if (h->vec) (void)hipFree(h->vec);
+    if (h->tiles) (void)hipFree(h->tiles);
     if (h->ctl) (void)hipFree(h->ctl);
     if (h->res_ring) (void)hipFree(h->res_ring);
     if (h->dres) (void)hipFree(h->dres);
@@ -354,6 +386,7 @@ int32_t qdot_async(qdot_handle *h, const double *x, const double *y, int64_t n, 
     if (!dev_out) return fail(h, QDOT_E_INVAL, "dev_out is NULL");
     DeviceGuard g(h->device);
     Launch L = make_launch(h, (hipStream_t)stream, n);
+    if ((st = attach_tiles(h, (hipStream_t)stream, n, o, L)) != QDOT_OK) return st;
     L.ev = take_events(h, 0);
     hipError_t e = launch_qdot(L, x, y, n, tol, o, dev_out, nullptr, nullptr);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot launch");
@@ -384,6 +417,7 @@ int32_t qdot_f32_async(qdot_handle *h, const float *x, const float *y, int64_t n
     if (!dev_out) return fail(h, QDOT_E_INVAL, "dev_out is NULL");
     DeviceGuard g(h->device);
     Launch L = make_launch(h, (hipStream_t)stream, n, true);
+    if ((st = attach_tiles(h, (hipStream_t)stream, n, o, L)) != QDOT_OK) return st;
     L.ev = take_events(h, 0);
     hipError_t e = launch_qdot_f32(L, x, y, n, tol, o, dev_out, nullptr, nullptr);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot_f32 launch");
@@ -416,8 +450,9 @@ int32_t qdot_f32_classes_async(qdot_handle *h, const float *x, const float *y, i
     if (o.accum_mode != 0)
         return fail(h, QDOT_E_INVAL, "qdot_f32_classes_async needs accum_mode 0");
     DeviceGuard g(h->device);
-    hipError_t e = launch_qdot_f32(make_launch(h, (hipStream_t)stream, n, true), x, y, n, tol, o,
-                                   dev_out, dev_cls, (long long *)dev_hist);
+    Launch L = make_launch(h, (hipStream_t)stream, n, true);
+    if ((st = attach_tiles(h, (hipStream_t)stream, n, o, L)) != QDOT_OK) return st;
+    hipError_t e = launch_qdot_f32(L, x, y, n, tol, o, dev_out, dev_cls, (long long *)dev_hist);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot_f32_classes launch");
 }
 
@@ -457,8 +492,9 @@ int32_t qdot_classes_async(qdot_handle *h, const double *x, const double *y, int
     if (!dev_out || (n > 0 && !dev_cls)) return fail(h, QDOT_E_INVAL, "NULL output");
     if (o.accum_mode != 0) return fail(h, QDOT_E_INVAL, "qdot_classes_async needs accum_mode 0");
     DeviceGuard g(h->device);
-    hipError_t e = launch_qdot(make_launch(h, (hipStream_t)stream, n), x, y, n, tol, o, dev_out,
-                               dev_cls, (long long *)dev_hist);
+    Launch L = make_launch(h, (hipStream_t)stream, n);
+    if ((st = attach_tiles(h, (hipStream_t)stream, n, o, L)) != QDOT_OK) return st;
+    hipError_t e = launch_qdot(L, x, y, n, tol, o, dev_out, dev_cls, (long long *)dev_hist);
     return e == hipSuccess ? QDOT_OK : hip_fail(h, e, "qdot_classes launch");
 }
 

@@ -828,6 +828,8 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
     if (o.bin_mode != 0)
         return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
+    if (o.tile_skip != 0)
+        return fail(h, QDOT_E_INVAL, "tile_skip is for the single-vector qdot entry points");
     if (o.guard_mode != 0) return fail(h, QDOT_E_INVAL, "the batched launch needs guard_mode 0");
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
@@ -922,6 +924,8 @@ int32_t qdot_batch_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
     if (o.bin_mode != 0)
         return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
+    if (o.tile_skip != 0)
+        return fail(h, QDOT_E_INVAL, "tile_skip is for the single-vector qdot entry points");
     if (o.guard_mode != 0) return fail(h, QDOT_E_INVAL, "the batched launch needs guard_mode 0");
     if (B == 0 && S == 0) return QDOT_OK;
     DeviceGuard g(h->device);

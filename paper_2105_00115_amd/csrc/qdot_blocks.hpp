@@ -88,6 +88,100 @@ __device__ __forceinline__ void stream_strided(const T *__restrict__ x, const T 
     }
 }
 
+// stream_strided for tile_skip.  A 64-component tile (the 4 components of
+// 16 consecutive lanes) whose largest key slot tk[i / TILE] lies below
+// keep_lo holds only perforated components: its lanes load nothing and pass
+// zeros, whose products are zero and perforated too, so body() forms the
+// same leaves (zero) and classes (perforated).  A wave none of whose tiles
+// of a group is live skips the group: it calls dead(i0, lim) for each of its
+// chunks instead of body() (the leaves it skips are +0, and adding +0 leaves
+// a compensated sum that starts at +0 unchanged, bit for bit).  The keys of
+// the block's full groups are staged in LDS a batch at a time, one key per
+// thread (KB = 16 / U groups of U chunks of NT / 16 tiles), the next batch
+// loaded while the current one is processed; kl holds 2 x NT keys.  The one
+// partial group reads its keys directly.  Every thread of the block must
+// call it with the same arguments.
+template <bool VEC, int U, int NT = BLOCK, class T, class Body, class Dead>
+__device__ __forceinline__ void stream_strided_ts(const T *__restrict__ x,
+                                                  const T *__restrict__ y, int64_t first,
+                                                  int64_t stride, int64_t n,
+                                                  const short *__restrict__ tk, int keep_lo,
+                                                  short (*kl)[NT], Body &&body, Dead &&dead)
+{
+    constexpr int64_t chunk = (int64_t)NT * EPT;
+    const int64_t group = chunk * U;
+    constexpr int TPC = NT * EPT / TILE;  // tiles per chunk
+    constexpr int KB = 16 / U;            // groups per batch: KB * U * TPC == NT
+    static_assert(KB * U * TPC == NT, "one staged key per thread");
+    const int64_t nfull = n >= first + group ? (n - first - group) / stride + 1 : 0;
+    auto key_of = [&](int64_t g0) -> short {
+        const int t = threadIdx.x;
+        const int64_t gi = g0 + t / (U * TPC);
+        if (gi >= nfull) return (short)-1;
+        const int64_t i = first + gi * stride + (int64_t)((t / TPC) % U) * chunk +
+                          (int64_t)(t % TPC) * TILE;
+        return tk[i / TILE];
+    };
+    int buf = 0;
+    short next = nfull > 0 ? key_of(0) : (short)-1;
+    const int row = threadIdx.x * EPT / TILE;
+    for (int64_t g0 = 0; g0 < nfull; g0 += KB) {
+        kl[buf][threadIdx.x] = next;
+        __syncthreads();
+        if (g0 + KB < nfull) next = key_of(g0 + KB);
+        const int gend = (int)std::min<int64_t>(KB, nfull - g0);
+        for (int gg = 0; gg < gend; gg++) {
+            const int64_t base = first + (g0 + gg) * stride;
+            bool live[U];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                live[u] = kl[buf][(gg * U + u) * TPC + row] >= keep_lo;
+                any |= live[u];
+            }
+            if (__ballot(any) == 0ull) {
+#pragma unroll
+                for (int u = 0; u < U; u++) dead(base + (int64_t)u * chunk + threadIdx.x * EPT, 4);
+                continue;
+            }
+            T xv[U][4], yv[U][4];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int64_t i0 = base + (int64_t)u * chunk + threadIdx.x * EPT;
+                if (live[u]) {
+                    load4_full<VEC>(x + i0, xv[u]);
+                    load4_full<VEC>(y + i0, yv[u]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; e++) xv[u][e] = yv[u][e] = T(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                body(xv[u], yv[u], base + (int64_t)u * chunk + threadIdx.x * EPT, 4);
+        }
+        buf ^= 1;
+    }
+    const int64_t base = first + nfull * stride;
+    if (base < n) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * chunk + threadIdx.x * EPT;
+            const int64_t left = n - i0;
+            const int lim = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
+            T xv[4], yv[4];
+            if (lim > 0 && tk[i0 / TILE] >= keep_lo) {
+                load4_tail(x + i0, lim, xv);
+                load4_tail(y + i0, lim, yv);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; e++) xv[e] = yv[e] = T(0);
+            }
+            body(xv, yv, i0, lim);
+        }
+    }
+}
+
 // Grid-stride walk over groups of CHUNK * U consecutive components: block b
 // takes groups b, b + gridDim.x, ...  Whole groups are loaded without bounds
 // checks; the single partial group (met by one block at most) is loaded with

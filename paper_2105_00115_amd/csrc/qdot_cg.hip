@@ -131,6 +131,8 @@ int32_t qdot_cg(qdot_handle *h, const qdot_csr *A, const double *b, double *x, d
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
     if (o.bin_mode != 0)
         return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
+    if (o.tile_skip != 0)
+        return fail(h, QDOT_E_INVAL, "tile_skip is for the single-vector qdot entry points");
     if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
     const bool acc1 = use_qdot && o.accum_mode == 1;

@@ -54,6 +54,7 @@ struct Ws {
     int flags;                   // result flags known after selection
     int s1_lo, s1_hi;            // live slot range of the last scan
     int mu_single;               // the last selection was for single-precision inputs
+    int keep_lo;                 // tile_skip: lowest slot of a kept class (W: none)
     // per scan block: bit 0 = a negative, bit 1 = a positive non-zero product
     unsigned int block_signs[MAX_GRID];
     // guaranteed mode (guard_mode 1)

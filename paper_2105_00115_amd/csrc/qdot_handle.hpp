@@ -40,6 +40,10 @@ struct qdot_handle {
     int power_scan_in_spmv = 0;      // power method: pass 1 inside the SpMV
     void *cg = nullptr;              // persistent CG buffers
 
+    // tile_skip: largest key slot of every 64-component tile, grown on demand
+    short *tiles = nullptr;
+    int64_t tiles_cap = 0;           // tiles held at `tiles`
+
     // kernel timing (diagnostics)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool; // created events, reused after each read

@@ -21,12 +21,16 @@ namespace qd {
 // a block-private LDS histogram, merged into one of `copies` (<= HIST_COPIES)
 // global histograms (blockIdx % copies; 8: one per XCD under round-robin
 // dispatch) so that the merge atomics of concurrent blocks spread out.
+// TS (tile_skip): also the largest key slot of the non-zero products of
+// every 64-component tile (-1: none) into tk[i / TILE]; a tile is the 4
+// components of each of 16 consecutive lanes, one DPP row.
 // ---------------------------------------------------------------------------
-template <class T, bool VEC, int U, int NT = BLOCK>
+template <class T, bool VEC, int U, int NT = BLOCK, bool TS = false>
 __global__ __launch_bounds__(NT) void k_scan(const T *__restrict__ x,
                                              const T *__restrict__ y,
                                              int64_t n, int key_mode,
-                                             Ws *__restrict__ ws, int copies)
+                                             Ws *__restrict__ ws, int copies,
+                                             short *__restrict__ tk)
 {
     __shared__ unsigned int h[W + 1];
     for (int i = threadIdx.x; i < W + 1; i += NT) h[i] = 0;
@@ -34,7 +38,8 @@ __global__ __launch_bounds__(NT) void k_scan(const T *__restrict__ x,
 
     unsigned int nz = 0, bad = 0, sg = 0;
     // float inputs: the 32-bit decomposition gives the key of the same values
-    stream_groups<VEC, U, NT>(x, y, n, [&](const T *xv, const T *yv, int64_t, int lim) {
+    stream_groups<VEC, U, NT>(x, y, n, [&](const T *xv, const T *yv, int64_t i0, int lim) {
+        int top = -1;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const auto c = [&]() {
@@ -47,6 +52,12 @@ __global__ __launch_bounds__(NT) void k_scan(const T *__restrict__ x,
             sg |= (valid & !c.zero) ? (c.sgn ? 1u : 2u) : 0u;
             // zero and non-finite products land in the spare slot W
             if (valid) atomicAdd(&h[c.slot], 1u);
+            if (TS && valid && c.slot != ZERO_SLOT) top = max(top, c.slot);
+        }
+        if constexpr (TS) {
+#pragma unroll
+            for (int m = 1; m < 16; m <<= 1) top = max(top, __shfl_xor(top, m, 64));
+            if ((threadIdx.x & 15) == 0 && i0 < n) tk[i0 / TILE] = (short)top;
         }
     });
     __syncthreads();
@@ -65,10 +76,11 @@ __device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, i
                                               int nonstrict, int64_t n, int nscan, int guard,
                                               int mu_single, qdot_result *__restrict__ out,
                                               long long *__restrict__ hist_out,
-                                              int bin_mode = 0, int bin_param = 0)
+                                              int bin_mode = 0, int bin_param = 0,
+                                              int want_keep_lo = 0)
 {
     constexpr int NW = CUT_THREADS / 64;
-    __shared__ int s_lo[NW], s_hi[NW];
+    __shared__ int s_lo[NW], s_hi[NW], s_kl[NW];
     __shared__ unsigned int s_sg[NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // only the slot window pass 1 touched holds counts; slots outside it are
@@ -110,7 +122,12 @@ __device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, i
         for (int c = 0; c < HIST_COPIES; c++) v += ws->hist[c][j];
         return v;
     };
-    auto put = [&](int j, int cls) { ws->lut[j] = (unsigned char)cls; };
+    // keep_lo: the lowest slot this thread gave a kept class
+    int keep_lo = W;
+    auto put = [&](int j, int cls) {
+        ws->lut[j] = (unsigned char)cls;
+        if (cls != QDOT_PERF) keep_lo = min(keep_lo, j);
+    };
     auto clear = [&](int j) {
 #pragma unroll
         for (int c = 0; c < HIST_COPIES; c++) ws->hist[c][j] = 0ull;
@@ -130,6 +147,17 @@ __device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, i
                                       put, clear, out, hist_out, 0, mu_single);
     }
     if (tid < W_LUT - W) ws->lut[W + tid] = (unsigned char)QDOT_PERF;
+    if (want_keep_lo) {
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) keep_lo = min(keep_lo, __shfl_xor(keep_lo, m, 64));
+        if (lane == 0) s_kl[wv] = keep_lo;
+        __syncthreads();
+        if (tid == 0) {
+            int kl = W;
+            for (int w = 0; w < NW; w++) kl = min(kl, s_kl[w]);
+            ws->keep_lo = kl;
+        }
+    }
     if (tid == 0) {
         ws->n_zero = 0;
         ws->nonfinite = 0;
@@ -151,9 +179,11 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut(Ws *__restrict__ ws, double
                                                      int64_t n, int nscan, int guard,
                                                      int mu_single,
                                                      qdot_result *__restrict__ out,
-                                                     long long *__restrict__ hist_out)
+                                                     long long *__restrict__ hist_out,
+                                                     int want_keep_lo)
 {
-    cut_body(ws, tol, score_mode, nonstrict, n, nscan, guard, mu_single, out, hist_out);
+    cut_body(ws, tol, score_mode, nonstrict, n, nscan, guard, mu_single, out, hist_out, 0, 0,
+             want_keep_lo);
 }
 
 // k_cut with a binning strategy other than exact bins (Sec. 3.2)
@@ -162,10 +192,11 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut_bins(Ws *__restrict__ ws, d
                                                           int64_t n, int nscan, int mu_single,
                                                           qdot_result *__restrict__ out,
                                                           long long *__restrict__ hist_out,
-                                                          int bin_mode, int bin_param)
+                                                          int bin_mode, int bin_param,
+                                                          int want_keep_lo)
 {
     cut_body<true>(ws, tol, score_mode, nonstrict, n, nscan, 0, mu_single, out, hist_out,
-                   bin_mode, bin_param);
+                   bin_mode, bin_param, want_keep_lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,12 +216,16 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut_bins(Ws *__restrict__ ws, d
 // Block `blk` of `nblk` (grid-stride over groups) writes its partials at
 // partials + 6 * blk.
 // Q: the compacting form of the leaf work (acc_group_q), else acc_group.
-template <class T, bool VEC, int U, bool CLS, bool Q = false, int NT = BLOCK>
+// TS (tile_skip, dense form): tiles whose key in tk lies below the lowest
+// kept slot are not read (stream_strided_ts).
+template <class T, bool VEC, int U, bool CLS, bool Q = false, int NT = BLOCK, bool TS = false>
 __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__restrict__ y,
                                          int64_t n, int key_mode, const Ws *__restrict__ ws,
                                          double *__restrict__ partials,
-                                         unsigned char *__restrict__ cls_out, int blk, int nblk)
+                                         unsigned char *__restrict__ cls_out, int blk, int nblk,
+                                         const short *__restrict__ tk = nullptr)
 {
+    static_assert(!(TS && Q), "tile skipping uses the dense form");
     __shared__ unsigned char lut[W_LUT];
     __shared__ Acc red[3][NT / 64];
     __shared__ AccWaveLds wl[Q ? NT / 64 : 1];
@@ -210,15 +245,25 @@ __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__res
     const int lane = threadIdx.x & 63;
     Acc aD = {0.0, 0.0}, aS = {0.0, 0.0}, aH = {0.0, 0.0};
     const int64_t group = (int64_t)NT * EPT * U;
-    stream_strided<VEC, U, NT>(x, y, (int64_t)blk * group, (int64_t)nblk * group, n,
-                           [&](const T *xv, const T *yv, int64_t i0, int lim) {
+    auto body = [&](const T *xv, const T *yv, int64_t i0, int lim) {
         if constexpr (Q)
             acc_group_q<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
                              CLS ? cls_out + i0 : nullptr, wl[threadIdx.x >> 6]);
         else
             acc_group<CLS>(xv, yv, lim, lut, key_mode, e_max, c32, !skip, aD, aS, aH,
                            CLS ? cls_out + i0 : nullptr);
-    });
+    };
+    if constexpr (TS) {
+        __shared__ short kl[2][NT];
+        // a skipped group's components are all perforated
+        auto dead = [&](int64_t i0, int lim) {
+            if constexpr (CLS)
+                for (int e = 0; e < lim; e++) cls_out[i0 + e] = (unsigned char)QDOT_PERF;
+        };
+        stream_strided_ts<VEC, U, NT>(x, y, (int64_t)blk * group, (int64_t)nblk * group, n, tk,
+                                      ws->keep_lo, kl, body, dead);
+    } else
+        stream_strided<VEC, U, NT>(x, y, (int64_t)blk * group, (int64_t)nblk * group, n, body);
     if (skip) return;
 
     aD = wave_reduce(aD);
@@ -242,16 +287,17 @@ __device__ __forceinline__ void acc_body(const T *__restrict__ x, const T *__res
     }
 }
 
-template <class T, bool VEC, int U, bool CLS, bool Q, int NT = BLOCK>
+template <class T, bool VEC, int U, bool CLS, bool Q, int NT = BLOCK, bool TS = false>
 __global__ __launch_bounds__(NT) void k_acc(const T *__restrict__ x,
                                             const T *__restrict__ y,
                                             int64_t n, int key_mode,
                                             const Ws *__restrict__ ws,
                                             double *__restrict__ partials,
-                                            unsigned char *__restrict__ cls_out)
+                                            unsigned char *__restrict__ cls_out,
+                                            const short *__restrict__ tk)
 {
-    acc_body<T, VEC, U, CLS, Q, NT>(x, y, n, key_mode, ws, partials, cls_out, blockIdx.x,
-                                    gridDim.x);
+    acc_body<T, VEC, U, CLS, Q, NT, TS>(x, y, n, key_mode, ws, partials, cls_out, blockIdx.x,
+                                        gridDim.x, tk);
 }
 
 // Combine the per-block partials of k_acc in a fixed order (one block).
@@ -575,8 +621,12 @@ template <class T, bool VEC, int U, int NT>
 static int launch_scan_nt(const Launch &L, const T *x, const T *y, int64_t n, int key_mode)
 {
     const int grid = grid_for(n, U, std::min(MAX_GRID, cap_for(L.scan_blocks, NT)), NT);
-    hipLaunchKernelGGL((k_scan<T, VEC, U, NT>), dim3(grid), dim3(NT), 0, L.stream, x, y, n,
-                       key_mode, L.ws, L.hist_copies);
+    if (L.tiles)
+        hipLaunchKernelGGL((k_scan<T, VEC, U, NT, true>), dim3(grid), dim3(NT), 0, L.stream, x,
+                           y, n, key_mode, L.ws, L.hist_copies, L.tiles);
+    else
+        hipLaunchKernelGGL((k_scan<T, VEC, U, NT>), dim3(grid), dim3(NT), 0, L.stream, x, y, n,
+                           key_mode, L.ws, L.hist_copies, nullptr);
     return grid;
 }
 
@@ -609,12 +659,17 @@ static int launch_acc_nt(const Launch &L, const T *x, const T *y, int64_t n, int
 {
     // the partials hold L.partial_cap blocks of any size
     const int grid = grid_for(n, U, std::min(L.partial_cap, cap_for(L.acc_blocks, NT)), NT);
-    if (L.acc_form == 1)
+    // tile keys: the dense form (the compacting form's queue holds the
+    // components it reads)
+    if (L.tiles)
+        hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, false, NT, true>), dim3(grid), dim3(NT), 0,
+                           L.stream, x, y, n, key_mode, L.ws, L.partials, cls_out, L.tiles);
+    else if (L.acc_form == 1)
         hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, true, NT>), dim3(grid), dim3(NT), 0, L.stream,
-                           x, y, n, key_mode, L.ws, L.partials, cls_out);
+                           x, y, n, key_mode, L.ws, L.partials, cls_out, nullptr);
     else
         hipLaunchKernelGGL((k_acc<T, VEC, U, CLS, false, NT>), dim3(grid), dim3(NT), 0,
-                           L.stream, x, y, n, key_mode, L.ws, L.partials, cls_out);
+                           L.stream, x, y, n, key_mode, L.ws, L.partials, cls_out, nullptr);
     return grid;
 }
 
@@ -714,10 +769,11 @@ static hipError_t launch_qdot_t(const Launch &L, const T *x, const T *y, int64_t
     if (o.bin_mode != 0)
         hipLaunchKernelGGL(k_cut_bins, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol,
                            o.score_mode, o.boundary_mode, n, nscan, mu_single, out, hs,
-                           o.bin_mode, o.bin_param);
+                           o.bin_mode, o.bin_param, L.tiles ? 1 : 0);
     else
         hipLaunchKernelGGL(k_cut, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
-                           o.boundary_mode, n, nscan, guard, mu_single, out, hs);
+                           o.boundary_mode, n, nscan, guard, mu_single, out, hs,
+                           L.tiles ? 1 : 0);
     if (L.ev) (void)hipEventRecord(L.ev[2], s);
     auto sweep = [&]() {
         int grid;

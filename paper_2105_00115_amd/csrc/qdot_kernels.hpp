@@ -22,6 +22,7 @@ struct Launch {
     int hist_copies;    // global histogram copies the scan blocks spread over (1..8)
     int block_threads;  // threads per block of the scan and accumulate (128, 256, 512)
     double *s1tab;      // one-pass mode: HIST_COPIES x W x S1_PIECES sums (zero between calls)
+    short *tiles;       // tile_skip: ceil(n / TILE) tile keys, else NULL
     hipEvent_t *ev;     // NULL, or events recorded around each kernel
 };
 

@@ -94,7 +94,8 @@ int32_t qdot_noalloc_async(const double *x, const double *y, int64_t n, double t
     const char *msg;
     int32_t st = qdot_args(x, y, n, tol, opt, o, &msg);
     if (st != QDOT_OK) return st;
-    if (!dev_out) return QDOT_E_INVAL;
+    // tile keys would need memory of their own
+    if (!dev_out || o.tile_skip) return QDOT_E_INVAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return QDOT_E_DEVICE;
     hipStream_t s = (hipStream_t)stream;

@@ -386,6 +386,8 @@ int32_t qdot_power(qdot_handle *h, const qdot_csr *A, double *x, int32_t iters, 
     if (!options_ok(o)) return fail(h, QDOT_E_INVAL, "unknown option value");
     if (o.bin_mode != 0)
         return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
+    if (o.tile_skip != 0)
+        return fail(h, QDOT_E_INVAL, "tile_skip is for the single-vector qdot entry points");
     if (use_qdot && (!(qtol > 0.0) || !std::isfinite(qtol)))
         return fail(h, QDOT_E_INVAL, "qtol must be finite and > 0");
     if (use_qdot && o.accum_mode == 1 && !s1_admissible(A->n, qtol, o))

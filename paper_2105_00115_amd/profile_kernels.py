@@ -10,7 +10,11 @@ Runs, in this order, on cuda:0:
 3. CG on the 2D Poisson matrix 1024^2 (qdot tol 1e-8, stop at 1e-10) with
    the two-pass qdot, the FP64 dot and the one-pass qdot, one solve each;
 4. the power method on the 3D Laplacian 128^3, ``power_iters`` iterations
-   with the two-pass qdot.
+   with the two-pass qdot;
+5. tile skipping: a banded pair of 2^26 components (three quarters of its
+   bands 2^-300 below the rest, tol 1e-6), ``steps`` calls without and
+   ``steps`` calls with tile_skip (its k_scan / k_acc instantiations carry
+   the template flag ``true``).
 
 Each phase prints its name and, for the solvers, the iteration counts, so
 that per-dispatch counters can be divided by iterations.
@@ -77,6 +81,16 @@ def main(argv=None):
     xs = torch.from_numpy(workloads.unit_vector(m3 ** 3, 4)).to(dev)
     r = h.power(A, xs, a.power_iters, 1e-6, 1, trace=False)
     print(f"[profile] power: lambda {r['lambda']!r}, status {r['status']}", flush=True)
+    del A, xs
+
+    print("[profile] tile skipping, banded pair 2^26", flush=True)
+    xb, yb = workloads.banded_pair(1 << 26, 81, levels=(0, -300, -300, -300),
+                                   mean_band=20000.0)
+    xb, yb = torch.from_numpy(xb).to(dev), torch.from_numpy(yb).to(dev)
+    for opt in (None, [0, 0, 0, 0, 0, 0, 0, 1]):
+        for _ in range(a.steps):
+            h.qdot_async(xb, yb, 1e-6, out, opt=opt)
+    torch.cuda.synchronize()
     h.close()
     print("[profile] done", flush=True)
 

@@ -24,6 +24,11 @@ value laws follow the workloads the qdot paper studies:
   Laplacians in the power-method study (Sec. 4.3).
 * ``ragged_batch``: many independent qdot instances with log-uniform lengths
   in [1e2, 1e6] and tolerances drawn from {1e-4, 1e-6, 1e-8}.
+* ``banded_pair``: x and y made of contiguous bands of random length, each
+  band at its own magnitude level (normal values times 2**level), so that
+  whole index ranges of products lie far below the largest ones: the banded
+  precision pattern of a solver's vectors (Sec. 4.2), where tiles of the
+  index order fall entirely into the perforated class.
 * ``cancelling_pair``: products of random sign and size whose sum cancels to
   a chosen relative level (the last component is set from the exact sum of
   the others), so that the largest product exponent lies far above the
@@ -48,6 +53,7 @@ __all__ = [
     "cg_grid_sides",
     "log_uniform_pair_torch",
     "cancelling_pair",
+    "banded_pair",
     "paired_cancelling_torch",
     "paper_dist_torch",
 ]
@@ -243,6 +249,24 @@ def log_uniform_pair_torch(n: int, seed: int, device="cuda:0"):
         del s
         out.append(v)
     return out[0], out[1]
+
+
+def banded_pair(n: int, seed: int, levels=(0, -10, -25, -40, -70), mean_band: float = 3000.0):
+    """x, y in FP64 of bands with geometric lengths (mean `mean_band`, not
+    aligned to any tile) whose components are standard normal times
+    2**level, the level drawn per band from `levels` (x and y share the
+    band layout and the level)."""
+    g = rng(seed)
+    x = g.standard_normal(n)
+    y = g.standard_normal(n)
+    i = 0
+    while i < n:
+        length = int(g.geometric(1.0 / mean_band))
+        lv = float(levels[int(g.integers(0, len(levels)))])
+        x[i:i + length] *= 2.0 ** lv
+        y[i:i + length] *= 2.0 ** lv
+        i += length
+    return x, y
 
 
 def cancelling_pair(n: int, seed: int, rel: float):
