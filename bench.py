@@ -82,12 +82,13 @@ def class_mix(results, n, series):
     return out
 
 
-def tile_skip_report(h, A, n, dev):
+def tile_skip_report(h, A, n, dev, x_tp, y_tp, tol_tp):
     """Tile skipping (tile_skip 1) on vectors whose index ranges fall into
     the perforated class: the residuals r = b - A x_k of CG on the 2D
     Poisson matrix with the smooth right-hand side b = A 1, after k FP64-dot
-    iterations (qdot of r.r at tol 1e-8), and a banded 2^26-component pair
-    (three quarters of its bands 2^-300 below the rest, tol 1e-6).  Per
+    iterations (qdot of r.r at tol 1e-8), a banded 2^26-component pair
+    (three quarters of its bands 2^-300 below the rest, tol 1e-6), and the
+    throughput workload itself (no tile is all perforated there).  Per
     input: the share of 64-component tiles whose components are all
     perforated (from the classes), the accumulate pass's ms without and with
     the tile keys (HIP events, 10 calls), and whether the two results agree
@@ -131,6 +132,8 @@ def tile_skip_report(h, A, n, dev):
     xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
     del x, y
     out["banded_2p26"] = one(xd, yd, 1e-6)
+    del xd, yd
+    out["throughput_workload"] = one(x_tp, y_tp, tol_tp)
     return out
 
 
@@ -497,7 +500,7 @@ def main():
     xs = torch.zeros(m * m, dtype=torch.float64, device=dev)
     rt = h.cg(A, b, xs, 1e-10, 1e-8, 20000, 1, trace=True)
     cg["class_mix"] = class_mix(rt["trace"], m * m, {"p.Ap": 1, "r.r": 2})
-    tiles = tile_skip_report(h, A, m * m, dev)
+    tiles = tile_skip_report(h, A, m * m, dev, x, y, tol)
     del A, b
 
     # power method on the 3D Laplacian 128^3, 500 iterations, qdot tol 1e-6
