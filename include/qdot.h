@@ -141,8 +141,8 @@ typedef struct qdot_options {
      *    again (QDOT_F_RESELECTED) and the check is repeated with the
      *    larger of the two lower bounds.  Needs key_mode 0 and accum_mode
      *    0; accepted by qdot_async, qdot, qdot_classes_async, the qdot_f32
-     *    entry points, qdot_power and qdot_cg, QDOT_E_INVAL elsewhere (the
-     *    batched entry points). */
+     *    entry points, qdot_power, qdot_cg and the batched entry points
+     *    (every qdot instance and every CG system of the launch). */
     int32_t guard_mode;
     /* Binning strategy (Sec. 3.2), the partition of [e_min, e_max] into the
      * bins that are scored:
@@ -194,7 +194,8 @@ typedef struct qdot_result {
                             (Thm 3.3 relative bound) */
     double bound_abs;    /* 2^e_max * bound_rel (Thm 3.2 absolute bound) */
     int32_t flags;       /* QDOT_F_* */
-    int32_t status;      /* QDOT_OK or QDOT_E_NONFINITE */
+    int32_t status;      /* QDOT_OK or QDOT_E_NONFINITE (then value is
+                            NaN and every other field 0) */
     double lower;        /* guard_mode 1: certified lower bound L 2^e_max
                             of |x.y| (0 when none is known; rounded to FP64,
                             exact unless subnormal); 0 otherwise */
@@ -428,8 +429,12 @@ QDOT_API int32_t qdot_fp64_dot_async(qdot_handle *h, const double *x, const doub
  * work list, synchronously); later calls with the same layout only launch
  * one kernel: no allocation, no memset, no host sync, graph-capturable.
  * Up to 8 layouts are kept per handle.  Calls on one handle must be ordered
- * on one stream.  Host-side argument errors, and guard_mode 1, return
- * QDOT_E_INVAL.  The pass-2 chunks of a large instance wait for its cutoff
+ * on one stream.  Host-side argument errors return QDOT_E_INVAL.
+ * guard_mode 1 runs the guaranteed mode on every instance (same decisions,
+ * flags, lower bound and passes as qdot_async on it): a small instance is
+ * certified by the block that runs it, a large one by the block that
+ * finishes its last pass-2 chunk, which after a reselection sweeps that
+ * instance again alone.  The pass-2 chunks of a large instance wait for its cutoff
  * with a spin limit; a chunk that waits past it gives that instance status
  * QDOT_E_DEVICE (the work order makes the wait end long before). */
 QDOT_API int32_t qdot_batched_async(qdot_handle *h, const double *x_cat,
@@ -495,7 +500,9 @@ QDOT_API int32_t qdot_batched_plan(qdot_handle *h, const int64_t *host_offsets,
  * launch two kernels (a re-arm pass over the gangs and the batch), allocate
  * nothing and can be captured in a graph.  A gang barrier that does not
  * complete within its spin limit gives that system status QDOT_E_DEVICE.
- * guard_mode 1 is refused (QDOT_E_INVAL). */
+ * guard_mode 1 runs the guaranteed mode on every qdot instance (as
+ * qdot_batched_async) and on every inner product of every CG system (as
+ * qdot_cg). */
 QDOT_API int32_t qdot_batch_run_async(qdot_handle *h, const double *x_cat,
                                       const double *y_cat, const int64_t *offsets,
                                       const int64_t *host_offsets, const double *tols,

@@ -63,6 +63,7 @@ struct BLarge {
     unsigned int bad;
     int first_slot;
     int e_max, c32, skip, flags;
+    unsigned int signs;  // guard_mode 1: OR of the chunks' sign bits
 };
 
 struct BState {
@@ -108,10 +109,11 @@ void free_plan(BatchPlan *p)
 }
 
 // Pass 1 over the groups first, first + stride, ... (below n) of one
-// instance into the LDS histogram h.
+// instance into the LDS histogram h; sg collects bit 0 for a negative and
+// bit 1 for a positive non-zero product (the guaranteed mode's sign test).
 __device__ __forceinline__ void scan_into(const double *xi, const double *yi, int64_t first,
                                           int64_t stride, int64_t n, bool vec, int key_mode, unsigned int *h,
-                                          unsigned int &nz, unsigned int &bad)
+                                          unsigned int &nz, unsigned int &bad, unsigned int &sg)
 {
     auto body = [&](const double *xv, const double *yv, int64_t, int lim) {
 #pragma unroll
@@ -120,6 +122,7 @@ __device__ __forceinline__ void scan_into(const double *xi, const double *yi, in
             const bool valid = k < lim;
             nz += (valid & c.zero) ? 1u : 0u;
             bad |= (valid & c.bad) ? 1u : 0u;
+            sg |= (valid & !c.zero) ? (c.sgn ? 1u : 2u) : 0u;
             if (valid) atomicAdd(&h[c.slot], 1u);
         }
     };
@@ -156,6 +159,88 @@ __device__ __forceinline__ int s1_window_depth(int64_t n, double tol, int score_
     if (!(tol > 0.0) || __builtin_isinf(tol)) return 1;
     const int d = s1_depth_dev(n, tol, score_mode);
     return (n > S1_MAX_N || d > S1_WIN) ? -1 : max(d, 1);
+}
+
+// guard_mode 1 (Thm 3.4) for one instance that one block finishes: the
+// steps and flags of the single-vector guard stages.  R holds the result of
+// the selection and of the first sweep, S that sweep's sum (units of
+// 2^e_max; 0 when nothing was swept), get(j) the instance's counts over
+// [lo, hi], nz its zero count and sg its sign bits.  Certify, or select the
+// classes again against the certified exponent (put() writes them into the
+// block's class table lut) and let resweep(p, flags) sum the instance again
+// with them, returning (in thread 0) the new sum while it writes value,
+// parts and flags into R; then check again with the larger lower bound.
+// Every thread of the block must call it.
+template <class Get, class Put, class Sweep>
+__device__ void batch_guard(int lo, int hi, unsigned long long nz, unsigned int sg, int64_t n,
+                            double tol, int score_mode, int nonstrict, Get get, Put put,
+                            const unsigned char *lut, double S, qdot_result &R, Sweep &&resweep)
+{
+    __shared__ int s_go, s_dref, s_passes;
+    __shared__ double s_low, s_sum;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_go = R.status == QDOT_OK && R.n_bins > 0;
+        // every product zero: +0 is exact
+        if (R.status == QDOT_OK && R.n_bins == 0) R.flags |= QDOT_F_GUARANTEED;
+        s_dref = 0;
+        s_passes = R.passes;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const int e_max = R.e_max;
+    const GuardSums g0 = guard_sums<BLOCK>(get, lut, lo, hi, e_max);
+    if (tid == 0) {
+        const double low = guard_lower(g0, S, n, sg);
+        if (guard_certified(R.bound_rel, low, tol)) {
+            R.flags |= QDOT_F_GUARANTEED;
+            R.lower = ldexp(low, e_max);
+        } else {
+            // L <= 0: every bin double (scores >= 23, one more non-strict)
+            const int ref = low > 0.0 ? e_max + ilogb(low) : R.e_min - R.t - 22 - nonstrict;
+            if (ref < e_max) {
+                s_dref = e_max - ref;
+                s_low = low;
+            } else {
+                R.lower = low > 0.0 ? ldexp(low, e_max) : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    if (!s_dref) return;
+    auto noclear = [](int) {};
+    const CutParams p2 = block_cutoff<BLOCK>(lo, hi, nz, 0u, n, tol, score_mode, nonstrict, get,
+                                             put, noclear, &R, nullptr, s_dref);
+    if (tid == 0) {
+        R.flags |= QDOT_F_RESELECTED;
+        R.passes = s_passes + (p2.skip ? 0 : 1);
+        s_sum = 0.0;
+    }
+    __syncthreads();
+    if (!p2.skip) {
+        const double s2 = resweep(p2, p2.flags | QDOT_F_RESELECTED);
+        if (tid == 0) s_sum = s2;
+    }
+    __syncthreads();
+    const GuardSums g1 = guard_sums<BLOCK>(get, lut, lo, hi, e_max);
+    if (tid == 0) {
+        const double low = fmax(guard_lower(g1, s_sum, n, sg), s_low);
+        R.flags |= QDOT_F_RESELECTED |
+                   (guard_certified(R.bound_rel, low, tol) ? QDOT_F_GUARANTEED : 0);
+        R.lower = low > 0.0 ? ldexp(low, e_max) : 0.0;
+    }
+    __syncthreads();
+}
+
+// Copies a block's result (LDS) to its slot in device memory (every thread
+// calls it).
+__device__ __forceinline__ void put_result(qdot_result *o, const qdot_result &R)
+{
+    constexpr int NWORD = (int)(sizeof(qdot_result) / sizeof(unsigned long long));
+    static_assert(NWORD * sizeof(unsigned long long) == sizeof(qdot_result), "whole words");
+    if (threadIdx.x < NWORD)
+        reinterpret_cast<unsigned long long *>(o)[threadIdx.x] =
+            reinterpret_cast<const unsigned long long *>(&R)[threadIdx.x];
 }
 
 __device__ __forceinline__ void write_invalid(qdot_result *o)
@@ -295,6 +380,8 @@ __global__ __launch_bounds__(BLOCK) void k_gang_rearm(Gang *gangs, int S)
     if (blockIdx.x < (unsigned)S && gangs[blockIdx.x].abort) gang_reset(gangs + blockIdx.x);
 }
 
+// GUARD: guard_mode 1 for the qdot instances (two-pass) and the CG systems.
+template <bool GUARD>
 __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                                                  const double *__restrict__ y,
                                                  const int64_t *__restrict__ offsets,
@@ -338,7 +425,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
         if (I.type == IT_CG) {
             // one block of a CG gang: its other blocks hold the neighbouring
             // tickets, so they are taken by blocks that are running
-            cg_solve<false>(sys[I.inst], gangs + I.inst, I.large, I.slot, key_mode, score_mode,
+            cg_solve<GUARD>(sys[I.inst], gangs + I.inst, I.large, I.slot, key_mode, score_mode,
                             nonstrict, LD, cg_out + I.inst);
             __syncthreads();
             continue;
@@ -352,7 +439,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
             const double *yi = y + off;
             const bool vec = ((((uintptr_t)xi) | ((uintptr_t)yi)) & 15) == 0;
             const double tol = tols[inst];
-            unsigned int nz = 0, bad = 0;
+            unsigned int nz = 0, bad = 0, sg = 0;
             int top = -1, depth = 0;
             if (accum_mode == 1) {
                 depth = s1_window_depth(n, tol, score_mode);
@@ -370,7 +457,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                     s1_stream<false, SU>(xi, yi, 0, GROUP, n, key_mode, depth, h, S1, run, nz, bad);
                 top = run.top;
             } else {
-                scan_into(xi, yi, 0, GROUP, n, vec, key_mode, h, nz, bad);
+                scan_into(xi, yi, 0, GROUP, n, vec, key_mode, h, nz, bad, sg);
             }
             __syncthreads();
             int lo = W, hi = -1;
@@ -379,13 +466,19 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                     lo = min(lo, j);
                     hi = max(hi, j);
                 }
-            block_reduce_range(lo, hi, nz, bad, scratch);
+            unsigned int bs = (bad ? 1u : 0u) | (sg << 1);
+            block_reduce_range(lo, hi, nz, bs, scratch);
+            bad = bs & 1u;
+            sg = bs >> 1;
             auto get = [&](int j) { return (unsigned long long)h[j]; };
             auto put = [&](int j, int c) { lut[j] = (unsigned char)c; };
-            auto clear = [&](int j) { h[j] = 0u; };
+            // the guaranteed mode reads the counts again after the sweep
+            auto clear = [&](int j) {
+                if (!GUARD) h[j] = 0u;
+            };
             const CutParams p = block_cutoff<BLOCK>(lo, hi, nz, bad, n, tol, score_mode,
-                                                    nonstrict, get, put, clear, out + inst,
-                                                    nullptr);
+                                                    nonstrict, get, put, clear,
+                                                    GUARD ? &s_res : out + inst, nullptr);
             if (tid == 0) h[W] = 0u;
             __syncthreads();
             if (accum_mode == 1) {
@@ -394,6 +487,27 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                     s1_pick(p.e_max, max(lo, top - depth + 1), p.flags, lut,
                             [&](int bin, int q) { return S1.win[bin & (S1_WIN - 1)][q]; }, red,
                             out + inst);
+            } else if constexpr (GUARD) {
+                // the whole instance is swept by this block: first sweep,
+                // certification, and a second sweep after a reselection
+                auto sweep = [&](const CutParams &cp, int flags) {
+                    Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+                    accumulate_range(xi, yi, 0, GROUP, n, vec, key_mode, lut, cp.e_max, cp.c32, a);
+                    block_reduce3<BLOCK>(a, red);
+                    return tid == 0 ? combine_value(a, cp.e_max, cp.c32, flags, &s_res) : 0.0;
+                };
+                __shared__ double s_first;
+                if (tid == 0) s_first = 0.0;
+                __syncthreads();
+                if (!p.skip) {
+                    const double s0 = sweep(p, p.flags);
+                    if (tid == 0) s_first = s0;
+                }
+                __syncthreads();
+                batch_guard(lo, hi, nz, sg, n, tol, score_mode, nonstrict, get, put, lut, s_first,
+                            s_res, sweep);
+                put_result(out + inst, s_res);
+                for (int j = lo + tid; j <= hi; j += BLOCK) h[j] = 0u;
             } else if (!p.skip) {
                 Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
                 accumulate_range(xi, yi, 0, GROUP, n, vec, key_mode, lut, p.e_max, p.c32, a);
@@ -417,8 +531,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
         } else if (I.type == IT_P1) {
             BLarge *L = large + I.large;
             unsigned int *gh = ghist + (size_t)I.large * W;
-            unsigned int nz = 0, bad = 0;
-            scan_into(xi, yi, I.first, I.stride, n, vec, key_mode, h, nz, bad);
+            unsigned int nz = 0, bad = 0, sg = 0;
+            scan_into(xi, yi, I.first, I.stride, n, vec, key_mode, h, nz, bad, sg);
             __syncthreads();
             int lo = W, hi = -1;
             for (int j = tid; j < W; j += BLOCK) {
@@ -431,8 +545,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                 }
             }
             if (tid == 0) h[W] = 0u;
-            block_reduce_range(lo, hi, nz, bad, scratch);
+            unsigned int bs = (bad ? 1u : 0u) | (sg << 1);
+            block_reduce_range(lo, hi, nz, bs, scratch);
+            bad = bs & 1u;
+            sg = bs >> 1;
             if (tid == 0) {
+                if (GUARD && sg)
+                    __hip_atomic_fetch_or(&L->signs, sg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (hi >= 0) {
                     __hip_atomic_fetch_min(&L->lo, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_fetch_max(&L->hi, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -462,13 +581,19 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                 unsigned char *gl = glut + (size_t)I.large * W_LUT;
                 auto get = [&](int j) { return (unsigned long long)ld_dev(&gh[j]); };
                 auto put = [&](int j, int c) { st_dev(&gl[j], (unsigned char)c); };
-                auto clear = [&](int j) { st_dev(&gh[j], 0u); };
+                // the guaranteed mode keeps the counts for the block that
+                // finishes the instance
+                auto clear = [&](int j) {
+                    if (!GUARD) st_dev(&gh[j], 0u);
+                };
                 const CutParams p = block_cutoff<BLOCK>(glo, ghi, gnz, gbad, n, tol, score_mode,
                                                         nonstrict, get, put, clear, &s_res,
                                                         nullptr);
-                if (tid == 0) {
+                if (tid == 0 && !GUARD) {
                     // the combining block writes value, part and flags; this
                     // block writes the rest (all of it when nothing is kept)
+                    // (with guard_mode 1 the combining block writes it all:
+                    // two blocks never store the same bytes)
                     qdot_result *o = out + I.inst;
                     for (int q = 0; q < 4; q++) o->count[q] = s_res.count[q];
                     o->n_zero = s_res.n_zero;
@@ -487,14 +612,18 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                         for (int q = 0; q < 3; q++) o->part[q] = s_res.part[q];
                         o->flags = s_res.flags;
                     }
+                }
+                if (tid == 0) {
                     st_dev(&L->e_max, p.e_max);
                     st_dev(&L->c32, p.c32);
                     st_dev(&L->skip, p.skip);
                     st_dev(&L->flags, p.flags);
-                    st_dev(&L->lo, (int)W);
-                    st_dev(&L->hi, -1);
-                    st_dev(&L->n_zero, 0ull);
-                    st_dev(&L->bad, 0u);
+                    if (!GUARD) {
+                        st_dev(&L->lo, (int)W);
+                        st_dev(&L->hi, -1);
+                        st_dev(&L->n_zero, 0ull);
+                        st_dev(&L->bad, 0u);
+                    }
                 }
                 vmem_drain();
                 __syncthreads();
@@ -553,8 +682,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
             __syncthreads();
             if (s_flag) {
                 // last P2 chunk: combine the instance's partials in chunk order
+                Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
                 if (!skip) {
-                    Acc a[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
                     const int nc = (int)L->nchunks;
                     for (int c = tid; c < nc; c += BLOCK) {
                         const double *p = partials + (size_t)(L->first_slot + c) * 6;
@@ -562,7 +691,49 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                             a[q] = acc_merge(a[q], Acc{ld_dev(&p[2 * q]), ld_dev(&p[2 * q + 1])});
                     }
                     block_reduce3<BLOCK>(a, red);
-                    if (tid == 0) combine_value(a, e_max, c32, flags, out + I.inst);
+                    if (!GUARD && tid == 0) combine_value(a, e_max, c32, flags, out + I.inst);
+                }
+                if constexpr (GUARD) {
+                    // the selection again, from the kept counts, into this
+                    // block's result and class table (the same classes as
+                    // the chunks used), the combine, then the certification;
+                    // a reselection sweeps the instance with this block alone
+                    unsigned int *gh = ghist + (size_t)I.large * W;
+                    const int glo = ld_dev(&L->lo), ghi = ld_dev(&L->hi);
+                    const unsigned long long gnz = ld_dev(&L->n_zero);
+                    const unsigned int gbad = ld_dev(&L->bad), gsg = ld_dev(&L->signs);
+                    auto get = [&](int j) { return (unsigned long long)ld_dev(&gh[j]); };
+                    auto put = [&](int j, int c) { lut[j] = (unsigned char)c; };
+                    auto noclear = [](int) {};
+                    const CutParams p = block_cutoff<BLOCK>(glo, ghi, gnz, gbad, n, tol,
+                                                            score_mode, nonstrict, get, put,
+                                                            noclear, &s_res, nullptr);
+                    __shared__ double s_first;
+                    if (tid == 0)
+                        s_first = p.skip ? 0.0 : combine_value(a, p.e_max, p.c32, p.flags, &s_res);
+                    __syncthreads();
+                    auto sweep = [&](const CutParams &cp, int fl) {
+                        Acc b[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+                        accumulate_range(xi, yi, 0, GROUP, n, vec, key_mode, lut, cp.e_max,
+                                         cp.c32, b);
+                        block_reduce3<BLOCK>(b, red);
+                        return tid == 0 ? combine_value(b, cp.e_max, cp.c32, fl, &s_res) : 0.0;
+                    };
+                    batch_guard(glo, ghi, gnz, gsg, n, tol, score_mode, nonstrict, get, put, lut,
+                                s_first, s_res, sweep);
+                    // a chunk that gave up waiting has marked the instance
+                    if (tid == 0 && ld_dev(&out[I.inst].status) == QDOT_E_DEVICE)
+                        s_res.status = QDOT_E_DEVICE;
+                    __syncthreads();
+                    put_result(out + I.inst, s_res);
+                    for (int j = glo + tid; j <= ghi; j += BLOCK) st_dev(&gh[j], 0u);
+                    if (tid == 0) {
+                        st_dev(&L->lo, (int)W);
+                        st_dev(&L->hi, -1);
+                        st_dev(&L->n_zero, 0ull);
+                        st_dev(&L->bad, 0u);
+                        st_dev(&L->signs, 0u);
+                    }
                 }
                 if (tid == 0) {
                     st_dev(&L->p1_done, 0u);
@@ -830,7 +1001,6 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
         return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
     if (o.tile_skip != 0)
         return fail(h, QDOT_E_INVAL, "tile_skip is for the single-vector qdot entry points");
-    if (o.guard_mode != 0) return fail(h, QDOT_E_INVAL, "the batched launch needs guard_mode 0");
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;
     const int accum = B > 0 ? o.accum_mode : 0;  // CG systems always use the default reading
@@ -841,17 +1011,25 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
         // a gang waits for its own blocks only, so it needs that many
         // blocks resident at once
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BLOCK, 0);
+        hipError_t e =
+            o.guard_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<true>, BLOCK, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<false>, BLOCK, 0);
         if (e != hipSuccess) return hip_fail(h, e, "occupancy query");
         if ((int64_t)per_cu * h->num_cus < p->max_gang)
             return fail(h, QDOT_E_DEVICE, "CG gang larger than the resident blocks");
     }
     hipStream_t s = (hipStream_t)stream;
     if (S > 0) hipLaunchKernelGGL(k_gang_rearm, dim3((unsigned)S), dim3(BLOCK), 0, s, p->gangs, S);
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets, tols,
-                       p->items, p->n_items, p->large, p->hist, p->lut, p->partials, p->state,
-                       p->small_list, dev_out, p->sys, p->gangs, dev_cg_out, p->ltab, o.key_mode,
-                       o.score_mode, o.boundary_mode, accum);
+    if (o.guard_mode)
+        hipLaunchKernelGGL(k_batch<true>, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets,
+                           tols, p->items, p->n_items, p->large, p->hist, p->lut, p->partials,
+                           p->state, p->small_list, dev_out, p->sys, p->gangs, dev_cg_out, p->ltab,
+                           o.key_mode, o.score_mode, o.boundary_mode, accum);
+    else
+        hipLaunchKernelGGL(k_batch<false>, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets,
+                           tols, p->items, p->n_items, p->large, p->hist, p->lut, p->partials,
+                           p->state, p->small_list, dev_out, p->sys, p->gangs, dev_cg_out, p->ltab,
+                           o.key_mode, o.score_mode, o.boundary_mode, accum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batched launch");
     if (used) *used = p;
@@ -926,7 +1104,6 @@ int32_t qdot_batch_plan(qdot_handle *h, const int64_t *host_offsets, int32_t B,
         return fail(h, QDOT_E_INVAL, "bin_mode 1 and 2 are for the single-vector qdot entry points");
     if (o.tile_skip != 0)
         return fail(h, QDOT_E_INVAL, "tile_skip is for the single-vector qdot entry points");
-    if (o.guard_mode != 0) return fail(h, QDOT_E_INVAL, "the batched launch needs guard_mode 0");
     if (B == 0 && S == 0) return QDOT_OK;
     DeviceGuard g(h->device);
     BatchPlan *p = nullptr;

@@ -469,9 +469,13 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
         int go = 1, t = 0;
         const bool tol_ok = tol > 0.0 && !__builtin_isinf(tol) && !__builtin_isnan(tol);
         if (bad || !tol_ok) {
+            // an error result: status and a NaN value, every other field 0
             go = 0;
             out->value = __longlong_as_double(0x7ff8000000000000ll);
             for (int q = 0; q < 4; q++) out->count[q] = 0;
+            out->n_zero = 0;
+            out->n_bins = 0;
+            out->e_max = out->e_min = out->e_ref = 0;
             out->status = bad ? QDOT_E_NONFINITE : QDOT_E_INVAL;
             out->flags = 0;
             out->t = 0;
@@ -753,9 +757,13 @@ __device__ CutParams block_cutoff_bins(BinLds &B, int lo, int hi, unsigned long 
         int go = 1, t = 0;
         const bool tol_ok = tol > 0.0 && !__builtin_isinf(tol) && !__builtin_isnan(tol);
         if (bad || !tol_ok) {
+            // an error result: status and a NaN value, every other field 0
             go = 0;
             out->value = __longlong_as_double(0x7ff8000000000000ll);
             for (int q = 0; q < 4; q++) out->count[q] = 0;
+            out->n_zero = 0;
+            out->n_bins = 0;
+            out->e_max = out->e_min = out->e_ref = 0;
             out->status = bad ? QDOT_E_NONFINITE : QDOT_E_INVAL;
             out->flags = 0;
             out->t = 0;

@@ -169,8 +169,8 @@ def test_unsupported_combinations_are_rejected(h):
         with pytest.raises(q.QdotError):
             h.qdot(xd, yd, 1e-6, opt=opt)
     offs = np.array([0, 500, 1000], dtype=np.int64)
-    with pytest.raises(q.QdotError):
-        h.batched(xd, yd, offs, [1e-6, 1e-6], opt=GUARD)
+    with pytest.raises(q.QdotError):  # the batched launch: not with the one-pass mode either
+        h.batched(xd, yd, offs, [1e-6, 1e-6], opt=[0, 0, 0, 1, 1])
     rp, col, val = workloads.poisson2d_csr(8)
     A = q.Csr(rp, col, val)
     b = dev(workloads.normal_vector(64, 85))

@@ -185,6 +185,12 @@ def test_nonfinite_and_bad_arguments(h):
         xb[1234] = bad
         r = h.qdot(dev(xb), dev(y), 1e-6)
         assert r["status"] == q.E_NONFINITE and np.isnan(r["value"])
+        # the oracle's error result field for field: every other field 0
+        o = oracle.qdot(xb, y, 1e-6)
+        for k in ("count", "n_zero", "e_min", "e_max", "n_bins", "t", "flags", "status",
+                  "bound_rel", "bound_abs", "lower", "e_ref", "passes"):
+            assert r[k] == o[k], (k, r[k], o[k])
+        assert r["part"] == [0.0, 0.0, 0.0]
     # the workspace recovers: the next call is normal
     compare(h, x, y, 1e-6)
     for tol in (0.0, -1.0, float("nan"), float("inf")):
