@@ -580,13 +580,28 @@ def main():
     batch1_ms = e0.elapsed_time(e1) / 10
     bres1 = q.parse_results(bout1)
     del graph1
+    # the same launch in the guaranteed mode (Thm 3.4 on every instance)
+    gd = [0, 0, 0, 0, 1]
+    boutg = torch.zeros_like(bout)
+    h.batched_async(bx, by, off_d, offs, tol_d, boutg, opt=gd)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        h.batched_async(bx, by, off_d, offs, tol_d, boutg, opt=gd)
+    e1.record()
+    torch.cuda.synchronize()
+    batchg_ms = e0.elapsed_time(e1) / 5
+    bresg = q.parse_results(boutg)
     batched = {"instances": 4096, "components": total, "ms_per_launch": round(batch_ms, 4),
                "one_pass_ms_per_launch": round(batch1_ms, 4),
                "one_pass_gelem_s": round(total / (batch1_ms * 1e-3) / 1e9, 3),
                "one_pass_counts_equal": all(a["count"] == c["count"] for a, c in zip(bres, bres1)),
                "gelem_s": round(total / (batch_ms * 1e-3) / 1e9, 3),
                "hbm_frac_2pass": round(32.0 * total / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-               "statuses_ok": sum(1 for r in bres if r["status"] == 0)}
+               "statuses_ok": sum(1 for r in bres if r["status"] == 0),
+               "guard_ms_per_launch": round(batchg_ms, 4),
+               "guard_certified": sum(1 for r in bresg if r["flags"] & q.F_GUARANTEED),
+               "guard_reselected": sum(1 for r in bresg if r["flags"] & q.F_RESELECTED)}
 
     # the same 4096 instances plus 256 CG systems (2D Poisson, side
     # round(2^U[5,9]), qdot tol 1e-8, stop at 1e-10) in one launch, captured
