@@ -90,7 +90,9 @@ hipEvent_t *take_events(qdot_handle *h, int kind)
     const size_t k = kind == 0 ? 5 : 2;
     while (h->ev_pool.size() < h->ev_used + k) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        // timing only: no system-scope fence (an L2 writeback and
+        // invalidation) at each record between two kernels
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         h->ev_pool.push_back(e);
     }
     hipEvent_t *ev = h->ev_pool.data() + h->ev_used;

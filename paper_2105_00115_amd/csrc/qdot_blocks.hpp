@@ -1368,6 +1368,169 @@ __device__ __forceinline__ void s1_stream(const T *__restrict__ x, const T *__re
     }
 }
 
+// ---- one-pass mode, one window per wave ----------------------------------
+// The same candidate sums as s1_group, kept by each wave in a window of its
+// own (S1W_WIN bins below the wave's running maximum live slot), so the
+// waves of a block never wait for each other while they stream: a wave
+// agrees on its new maximum with a shuffle, clears the slots of the bins
+// that enter, and drains its in-window components into its window.  The
+// mode needs depth <= S1W_WIN.  Used for single-precision inputs, whose
+// groups are half the bytes of double groups.  At the end of the block the wave windows
+// are added into one block window below the block's maximum (s1w_merge);
+// the sums are exact in any order, so the result is that of s1_group.
+constexpr int S1W_WIN = 64;
+
+struct S1WLds {
+    double win[BLOCK / 64][S1W_WIN][S1_PIECES];
+    double blk[S1W_WIN][S1_PIECES];
+    double2 q[BLOCK / 64][128];
+    int top[BLOCK / 64];
+};
+
+__device__ __forceinline__ void s1w_begin(S1WLds &S)
+{
+    double *w = &S.win[0][0][0];
+    for (int i = threadIdx.x; i < (BLOCK / 64) * S1W_WIN * S1_PIECES; i += BLOCK) w[i] = 0.0;
+    double *b = &S.blk[0][0];
+    for (int i = threadIdx.x; i < S1W_WIN * S1_PIECES; i += BLOCK) b[i] = 0.0;
+}
+
+// One group of K components per thread into the block's LDS histogram h and
+// the calling wave's window; top is the wave's running maximum live slot
+// (wave-uniform, -1: none).  Every lane of the wave must call it.
+template <int K, class T>
+__device__ __forceinline__ void s1w_group(const T (&xv)[K], const T (&yv)[K],
+                                          const bool (&valid)[K], int key_mode, int depth,
+                                          unsigned int *h, S1WLds &S, int &top,
+                                          unsigned int &nz, unsigned int &bad)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int live[K];
+    int wmax = -1;
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const Comp c = component((double)xv[e], (double)yv[e], key_mode);
+        nz += (valid[e] & c.zero) ? 1u : 0u;
+        bad |= (valid[e] & c.bad) ? 1u : 0u;
+        if (valid[e]) atomicAdd(&h[c.slot], 1u);
+        live[e] = (valid[e] && c.slot != ZERO_SLOT) ? c.slot : -1;
+        wmax = max(wmax, live[e]);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) wmax = max(wmax, __shfl_xor(wmax, m, 64));
+    double(*win)[S1_PIECES] = S.win[wv];
+    if (wmax > top) {
+        // bins top+1 .. wmax enter; their slots held bins now below the window
+        const int nclr = min(wmax - top, S1W_WIN);
+        for (int i = lane; i < nclr * S1_PIECES; i += 64)
+            win[(wmax - i / S1_PIECES) & (S1W_WIN - 1)][i % S1_PIECES] = 0.0;
+        __builtin_amdgcn_wave_barrier();
+        top = wmax;
+    }
+    const int wlo = top - depth + 1;
+    double2 *qw = S.q[wv];
+    int qn = 0;  // wave-uniform
+    auto drain = [&](int cnt) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const double2 v = qw[lane];
+            const Comp c = component(v.x, v.y, key_mode);
+            double pc[S1_PIECES];
+            s1_pieces(c, key_mode, pc);
+            double *w = win[c.slot & (S1W_WIN - 1)];
+#pragma unroll
+            for (int q = 0; q < S1_PIECES; q++)
+                if (pc[q] != 0.0) atomicAdd(&w[q], pc[q]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const bool in = live[e] >= wlo && live[e] >= 0;
+        const unsigned long long m = __ballot(in);
+        if (in) {
+            const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                     (unsigned)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            qw[pos] = make_double2((double)xv[e], (double)yv[e]);
+        }
+        qn += __popcll(m);
+        if (qn >= 64) {
+            drain(64);
+            if (lane < qn - 64) qw[lane] = qw[64 + lane];
+            __builtin_amdgcn_wave_barrier();
+            qn -= 64;
+        }
+    }
+    if (qn > 0) drain(qn);
+}
+
+// s1_stream with a window per wave (s1w_group).
+template <bool VEC, int U, class T>
+__device__ __forceinline__ void s1w_stream(const T *__restrict__ x, const T *__restrict__ y,
+                                           int64_t first, int64_t stride, int64_t n,
+                                           int key_mode, int depth, unsigned int *h, S1WLds &S,
+                                           int &top, unsigned int &nz, unsigned int &bad)
+{
+    const int tid = threadIdx.x;
+    const int64_t group = (int64_t)CHUNK * U;
+    for (int64_t base = first; base < n; base += stride) {
+        T xv[U][4], yv[U][4];
+        int lim[U];
+        const bool full = base + group <= n;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i0 = base + (int64_t)u * CHUNK + tid * EPT;
+            if (full) {
+                lim[u] = 4;
+                load4_full<VEC>(x + i0, xv[u]);
+                load4_full<VEC>(y + i0, yv[u]);
+            } else {
+                const int64_t left = n - i0;
+                lim[u] = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
+                load4_tail(x + i0, lim[u], xv[u]);
+                load4_tail(y + i0, lim[u], yv[u]);
+            }
+        }
+        T xf[U * 4], yf[U * 4];
+        bool vf[U * 4];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                xf[u * 4 + e] = xv[u][e];
+                yf[u * 4 + e] = yv[u][e];
+                vf[u * 4 + e] = e < lim[u];
+            }
+        s1w_group<U * 4>(xf, yf, vf, key_mode, depth, h, S, top, nz, bad);
+    }
+}
+
+// The wave windows added into the block window S.blk below the block's
+// maximum live slot, which it returns (-1: none); bins of a wave below the
+// block's window are perforated whatever the rest of the data holds and are
+// left out.  Every thread of the block must call it (top: its wave's).
+__device__ __forceinline__ int s1w_merge(S1WLds &S, int top, int depth)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) S.top[wv] = top;
+    __syncthreads();
+    int T = -1;
+    for (int w = 0; w < BLOCK / 64; w++) T = max(T, S.top[w]);
+    if (top >= 0) {
+        const int lo = max(top, T) - depth + 1;
+        const int cnt = top >= lo ? (top - lo + 1) * S1_PIECES : 0;
+        for (int i = lane; i < cnt; i += 64) {
+            const int bin = top - i / S1_PIECES;
+            if (bin < 0) continue;
+            const double v = S.win[wv][bin & (S1W_WIN - 1)][i % S1_PIECES];
+            if (v != 0.0) atomicAdd(&S.blk[bin & (S1W_WIN - 1)][i % S1_PIECES], v);
+        }
+    }
+    __syncthreads();
+    return T;
+}
+
 // One-pass pick: each kept bin k in [e_max - S1_WIN + 1, e_max] (and >= lo)
 // contributes the candidate sum of its class (get(bin, piece), an exact
 // FP64 number), scaled by 2^(k - e_max); the block sums them with

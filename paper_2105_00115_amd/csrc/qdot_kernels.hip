@@ -503,6 +503,74 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan(const T *__restrict__ x,
     }
 }
 
+// k_s1_scan with a window per wave (s1w_stream; depth <= S1W_WIN): the waves
+// of a block meet only once, at the end, where their windows are added into
+// the block window that goes to the global table.  Same tables, histogram
+// and records as k_s1_scan.
+template <class T, bool VEC, int U>
+__global__ __launch_bounds__(BLOCK) void k_s1_scan_w(const T *__restrict__ x,
+                                                     const T *__restrict__ y,
+                                                     int64_t n, int key_mode, int depth,
+                                                     Ws *__restrict__ ws,
+                                                     double *__restrict__ tab, int copies)
+{
+    __shared__ unsigned int h[W + 1];
+    __shared__ S1WLds S;
+    __shared__ int2 wr[BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int i = tid; i < W + 1; i += BLOCK) h[i] = 0;
+    s1w_begin(S);
+    __syncthreads();
+
+    int wtop = -1;
+    unsigned int nz = 0, bad = 0;
+    const int64_t group = (int64_t)CHUNK * U;
+    s1w_stream<VEC, U>(x, y, (int64_t)blockIdx.x * group, (int64_t)gridDim.x * group, n, key_mode,
+                       depth, h, S, wtop, nz, bad);
+    __syncthreads();
+    const int top = s1w_merge(S, wtop, depth);  // highest live slot of the block (-1: none)
+
+    // histogram merge and live range, as in k_scan
+    unsigned long long *gh = ws->hist[blockIdx.x % copies];
+    int lo = W, hi = -1;
+    for (int i = tid; i < W; i += BLOCK) {
+        const unsigned int v = h[i];
+        if (v) {
+            atomicAdd(&gh[i], (unsigned long long)v);
+            lo = min(lo, i);
+            hi = max(hi, i);
+        }
+    }
+    nz = wave_sum_u32(nz);
+    bad = wave_sum_u32(bad);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo = min(lo, __shfl_xor(lo, m, 64));
+        hi = max(hi, __shfl_xor(hi, m, 64));
+    }
+    if (lane == 0) {
+        if (nz) atomicAdd(&ws->n_zero, (unsigned long long)nz);
+        if (bad) atomicOr(&ws->nonfinite, 1u);
+        wr[tid >> 6] = make_int2(lo, hi);
+    }
+    // block window -> global table (bins top .. top - depth + 1, non-zero sums)
+    if (top >= 0) {
+        double *tb = tab + (size_t)(blockIdx.x % copies) * W * S1_PIECES;
+        for (int i = tid; i < depth * S1_PIECES; i += BLOCK) {
+            const int bin = top - i / S1_PIECES;
+            if (bin < 0) continue;
+            const double v = S.blk[bin & (S1W_WIN - 1)][i % S1_PIECES];
+            if (v != 0.0) atomicAdd(&tb[(size_t)bin * S1_PIECES + i % S1_PIECES], v);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int2 r = wr[0];
+        for (int w = 1; w < BLOCK / 64; w++) r = make_int2(min(r.x, wr[w].x), max(r.y, wr[w].y));
+        ws->block_range[blockIdx.x] = r;
+    }
+}
+
 // One-pass mode, cutoff and pick in one workgroup: the cutoff of k_cut, then
 // (after a barrier, which makes the block's class-table stores visible to
 // all its threads) every kept bin contributes the candidate sum of its
@@ -703,8 +771,16 @@ static int launch_s1_u(const Launch &L, const T *x, const T *y, int64_t n, int k
                        int depth)
 {
     const int grid = grid_for(n, U, L.s1_blocks);
-    hipLaunchKernelGGL((k_s1_scan<T, VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
-                       key_mode, depth, L.ws, L.s1tab, L.hist_copies);
+    // single-precision inputs: a window per wave when every possibly kept
+    // bin fits in S1W_WIN (a group of floats is half the bytes of a group of
+    // doubles, and the block barrier per group costs them 10 %; double
+    // inputs measured the same either way at their best shapes)
+    if (sizeof(T) == 4 && depth <= S1W_WIN)
+        hipLaunchKernelGGL((k_s1_scan_w<T, VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y,
+                           n, key_mode, depth, L.ws, L.s1tab, L.hist_copies);
+    else
+        hipLaunchKernelGGL((k_s1_scan<T, VEC, U>), dim3(grid), dim3(BLOCK), 0, L.stream, x, y, n,
+                           key_mode, depth, L.ws, L.s1tab, L.hist_copies);
     return grid;
 }
 
