@@ -70,16 +70,23 @@ __global__ __launch_bounds__(NT) void k_scan(const T *__restrict__ x,
 // ---------------------------------------------------------------------------
 // BINS: bin_mode / bin_param select the partition (exact bins when 0; the
 // other strategies need the block's BinLds, so only kernels that admit them
-// instantiate this).
-template <bool BINS = false>
+// instantiate this).  pre(lo, hi) runs in every thread once the live slot
+// window is known, before the counts are read (a caller issues loads there
+// that the selection does not need, so that both wait together); a non-null
+// lut_mirror (LDS) receives the class table as well.
+struct NoPre {
+    __device__ void operator()(int, int) const {}
+};
+template <bool BINS = false, int NT = CUT_THREADS, class Pre = NoPre>
 __device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, int score_mode,
                                               int nonstrict, int64_t n, int nscan, int guard,
                                               int mu_single, qdot_result *__restrict__ out,
                                               long long *__restrict__ hist_out,
                                               int bin_mode = 0, int bin_param = 0,
-                                              int want_keep_lo = 0)
+                                              int want_keep_lo = 0, Pre &&pre = Pre(),
+                                              unsigned char *lut_mirror = nullptr)
 {
-    constexpr int NW = CUT_THREADS / 64;
+    constexpr int NW = NT / 64;
     __shared__ int s_lo[NW], s_hi[NW], s_kl[NW];
     __shared__ unsigned int s_sg[NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -87,10 +94,12 @@ __device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, i
     // zero in every copy and their class-table entries are never read
     int lo = W, hi = -1;
     unsigned int sg = 0;
+    const unsigned long long nzero = ws->n_zero;
+    const unsigned int bad = ws->nonfinite;
     {
         int a = W, b = -1;
         unsigned int g = 0;
-        for (int i = tid; i < nscan; i += CUT_THREADS) {
+        for (int i = tid; i < nscan; i += NT) {
             const int2 r = ws->block_range[i];
             a = min(a, r.x);
             b = max(b, r.y);
@@ -114,8 +123,7 @@ __device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, i
             sg |= s_sg[w];
         }
     }
-    const unsigned long long nzero = ws->n_zero;
-    const unsigned int bad = ws->nonfinite;
+    pre(lo, hi);
     auto get = [&](int j) {
         unsigned long long v = 0ull;
 #pragma unroll
@@ -126,6 +134,7 @@ __device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, i
     int keep_lo = W;
     auto put = [&](int j, int cls) {
         ws->lut[j] = (unsigned char)cls;
+        if (lut_mirror) lut_mirror[j] = (unsigned char)cls;
         if (cls != QDOT_PERF) keep_lo = min(keep_lo, j);
     };
     auto clear = [&](int j) {
@@ -136,14 +145,14 @@ __device__ __forceinline__ CutParams cut_body(Ws *__restrict__ ws, double tol, i
     if constexpr (BINS) {
         __shared__ BinLds B;
         if (bin_mode != 0)
-            p = block_cutoff_bins<CUT_THREADS>(B, lo, hi, nzero, bad, n, tol, score_mode,
+            p = block_cutoff_bins<NT>(B, lo, hi, nzero, bad, n, tol, score_mode,
                                                nonstrict, bin_mode, bin_param, get, put, clear,
                                                out, hist_out, mu_single);
         else
-            p = block_cutoff<CUT_THREADS>(lo, hi, nzero, bad, n, tol, score_mode, nonstrict,
+            p = block_cutoff<NT>(lo, hi, nzero, bad, n, tol, score_mode, nonstrict,
                                           get, put, clear, out, hist_out, 0, mu_single);
     } else {
-        p = block_cutoff<CUT_THREADS>(lo, hi, nzero, bad, n, tol, score_mode, nonstrict, get,
+        p = block_cutoff<NT>(lo, hi, nzero, bad, n, tol, score_mode, nonstrict, get,
                                       put, clear, out, hist_out, 0, mu_single);
     }
     if (tid < W_LUT - W) ws->lut[W + tid] = (unsigned char)QDOT_PERF;
@@ -195,8 +204,8 @@ __global__ __launch_bounds__(CUT_THREADS) void k_cut_bins(Ws *__restrict__ ws, d
                                                           int bin_mode, int bin_param,
                                                           int want_keep_lo)
 {
-    cut_body<true>(ws, tol, score_mode, nonstrict, n, nscan, 0, mu_single, out, hist_out,
-                   bin_mode, bin_param, want_keep_lo);
+    cut_body<true, CUT_THREADS>(ws, tol, score_mode, nonstrict, n, nscan, 0, mu_single, out,
+                                hist_out, bin_mode, bin_param, want_keep_lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -572,35 +581,70 @@ __global__ __launch_bounds__(BLOCK) void k_s1_scan_w(const T *__restrict__ x,
 }
 
 // One-pass mode, cutoff and pick in one workgroup: the cutoff of k_cut, then
-// (after a barrier, which makes the block's class-table stores visible to
-// all its threads) every kept bin contributes the candidate sum of its
+// (after a barrier) every kept bin contributes the candidate sum of its
 // class, summed over the table copies (exact), scaled by 2^(k - e_max); the
 // scaled total is summed with compensation and rounded once.  The block then
-// clears the tables over the live range for the next call.
-__global__ __launch_bounds__(CUT_THREADS) void k_s1_cutfin(Ws *__restrict__ ws, double tol,
+// clears the tables over the live range for the next call.  The candidate
+// sums of the only bins that can be kept (the depth bins below the top live
+// slot, which is e_max's) are loaded as soon as the live window is known,
+// so that their loads and the histogram's wait together; the classes come
+// from an LDS copy of the class table.
+constexpr int S1FIN_THREADS = 512;  // 256 VGPRs per lane: the early loads stay in registers
+
+__global__ __launch_bounds__(S1FIN_THREADS) void k_s1_cutfin(Ws *__restrict__ ws, double tol,
                                                            int score_mode, int nonstrict,
                                                            int64_t n, int nscan, int mu_single,
                                                            double *__restrict__ tab,
                                                            qdot_result *__restrict__ out)
 {
-    __shared__ Acc red[3][CUT_THREADS / 64];
-    const CutParams p = cut_body(ws, tol, score_mode, nonstrict, n, nscan, 0, mu_single, out,
-                                 nullptr);
+    __shared__ Acc red[3][S1FIN_THREADS / 64];
+    __shared__ unsigned char cls_l[W_LUT];
+    __shared__ double pv[S1_WIN][S1_PIECES];
+    // admitted by the host: 1 <= depth <= S1_WIN for a valid tolerance
+    const int depth = max(1, min(S1_WIN, s1_depth_dev(n, tol, score_mode)));
+    // one (bin, piece) pair per thread is loaded early (depth <= 85 bins);
+    // the pairs past S1FIN_THREADS (deeper windows) after the cutoff
+    double raw[HIST_COPIES];
+    int cnt = 0, blo = W, top = -1;
+    auto pre = [&](int lo, int hi) {
+        top = hi;
+        blo = hi >= lo ? max(lo, hi - depth + 1) : W;
+        cnt = hi >= lo ? (hi - blo + 1) * S1_PIECES : 0;
+        const int i = (int)threadIdx.x;
+        if (i < cnt) {
+            const int bin = hi - i / S1_PIECES, q = i % S1_PIECES;
+#pragma unroll
+            for (int c = 0; c < HIST_COPIES; c++)
+                raw[c] = tab[((size_t)c * W + bin) * S1_PIECES + q];
+        }
+    };
+    const CutParams p = cut_body<false, S1FIN_THREADS>(ws, tol, score_mode, nonstrict, n, nscan,
+                                                       0, mu_single, out, nullptr, 0, 0, 0, pre,
+                                                       cls_l);
+    for (int i = threadIdx.x; i < cnt; i += S1FIN_THREADS) {
+        double v = 0.0;
+        if (i < S1FIN_THREADS) {
+#pragma unroll
+            for (int c = 0; c < HIST_COPIES; c++) v += raw[c];
+        } else {
+            const int bin = top - i / S1_PIECES, q = i % S1_PIECES;
+            for (int c = 0; c < HIST_COPIES; c++) v += tab[((size_t)c * W + bin) * S1_PIECES + q];
+        }
+        pv[i / S1_PIECES][i % S1_PIECES] = v;
+    }
     __syncthreads();
     const int lo = ws->s1_lo, hi = ws->s1_hi;
     if (!p.skip) {
-        auto get = [&](int bin, int q) {
-            double v = 0.0;
-            for (int c = 0; c < HIST_COPIES; c++) v += tab[((size_t)c * W + bin) * S1_PIECES + q];
-            return v;
-        };
-        s1_pick_nt<CUT_THREADS>(p.e_max, lo, p.flags, ws->lut, get, red, out);
+        // bins below blo are perforated (the mode's admission), so they are
+        // never picked; pv holds bin top - j at row j
+        auto get = [&](int bin, int q) { return bin >= blo ? pv[top - bin][q] : 0.0; };
+        s1_pick_nt<S1FIN_THREADS>(p.e_max, lo, p.flags, cls_l, get, red, out);
     }
     if (hi >= lo) {
         const int64_t cnt = (int64_t)(hi - lo + 1) * S1_PIECES;
         for (int c = 0; c < HIST_COPIES; c++) {
             double *tb = tab + ((size_t)c * W + lo) * S1_PIECES;
-            for (int64_t i = threadIdx.x; i < cnt; i += CUT_THREADS) tb[i] = 0.0;
+            for (int64_t i = threadIdx.x; i < cnt; i += S1FIN_THREADS) tb[i] = 0.0;
         }
     }
 }
@@ -808,7 +852,7 @@ static hipError_t launch_qdot_s1(const Launch &L, const T *x, const T *y, int64_
     const int nscan = vec ? launch_s1<T, true>(L, x, y, n, o.key_mode, depth)
                           : launch_s1<T, false>(L, x, y, n, o.key_mode, depth);
     if (L.ev) (void)hipEventRecord(L.ev[1], s);
-    hipLaunchKernelGGL(k_s1_cutfin, dim3(1), dim3(CUT_THREADS), 0, s, L.ws, tol, o.score_mode,
+    hipLaunchKernelGGL(k_s1_cutfin, dim3(1), dim3(S1FIN_THREADS), 0, s, L.ws, tol, o.score_mode,
                        o.boundary_mode, n, nscan, mu_single, L.s1tab, out);
     if (L.ev) {
         (void)hipEventRecord(L.ev[2], s);
