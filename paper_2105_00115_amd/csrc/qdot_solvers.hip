@@ -46,13 +46,30 @@ constexpr int SP_NZ = SP_U * BLOCK;
 
 // The SpMV loop over a block's row groups.  gather(c) gives the vector entry
 // of column c; own(i, yi) is called once per row with its result.
+// Row groups go to the XCDs in eight contiguous ranges: the hardware deals
+// blocks out to the 8 XCDs in turn (block b to XCD b mod 8), so the blocks
+// of one XCD take the groups of one range, and a row's neighbours a few
+// groups away (a stencil's next grid line) are gathered from that XCD's own
+// L2 instead of being fetched again by another XCD.  Grids that are not a
+// multiple of 8 walk the groups in plain grid-stride order.
 template <class Gather, class Own>
 __device__ __forceinline__ void spmv_lds(int64_t n, const int32_t *__restrict__ rowptr,
                                          const int32_t *__restrict__ col,
                                          const double *__restrict__ val, Gather &&gather,
                                          Own &&own, double *prod)
 {
-    for (int64_t r0 = (int64_t)blockIdx.x * BLOCK; r0 < n; r0 += (int64_t)gridDim.x * BLOCK) {
+    constexpr int XCDS = 8;
+    const int64_t ng = (n + BLOCK - 1) / BLOCK;
+    const int grid = (int)gridDim.x;
+    int64_t g0 = blockIdx.x, gstep = grid, gend = ng;
+    if (grid % XCDS == 0) {
+        const int64_t x = blockIdx.x % XCDS;
+        g0 = ng * x / XCDS + blockIdx.x / XCDS;
+        gstep = grid / XCDS;
+        gend = ng * (x + 1) / XCDS;
+    }
+    for (int64_t g = g0; g < gend; g += gstep) {
+        const int64_t r0 = g * BLOCK;
         const int64_t r1 = min(n, r0 + (int64_t)BLOCK);
         const int64_t i = r0 + threadIdx.x;
         const bool row = i < r1;
