@@ -202,7 +202,7 @@ def test_perforated_tiles_are_not_read(h):
     # three quarters of the bands far below the top ones: pass 2 with the
     # tile keys must take clearly less time than without (it reads about a
     # quarter of the operands)
-    n = 1 << 24
+    n = 1 << 25
     x, y = workloads.banded_pair(n, 81, levels=(0, -300, -300, -300), mean_band=20000.0)
     xd, yd = dev(x), dev(y)
     ms = {}
