@@ -381,8 +381,14 @@ __global__ __launch_bounds__(BLOCK) void k_gang_rearm(Gang *gangs, int S)
 }
 
 // GUARD: guard_mode 1 for the qdot instances (two-pass) and the CG systems.
-template <bool GUARD>
-__global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
+// CG: the work list may hold CG items.  AM: the qdot instances' accum_mode.
+// Each combination is its own kernel, so a launch of qdot instances alone
+// carries neither the CG solver's registers nor (two-pass) the one-pass
+// window's LDS: 128 VGPRs and 22 KB (four blocks per CU) for the two-pass
+// kernel, 168 VGPRs (three per CU) for the one-pass one, against two per CU
+// for the kernel that holds every path.
+template <bool GUARD, bool CG, int AM>
+__global__ __launch_bounds__(BLOCK, (CG || GUARD) ? 1 : (AM ? 3 : 4)) void k_batch(const double *__restrict__ x,
                                                  const double *__restrict__ y,
                                                  const int64_t *__restrict__ offsets,
                                                  const double *__restrict__ tols,
@@ -398,8 +404,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
                                                  Gang *__restrict__ gangs,
                                                  qdot_cg_result *__restrict__ cg_out,
                                                  double *__restrict__ ltab, int key_mode,
-                                                 int score_mode, int nonstrict, int accum_mode)
+                                                 int score_mode, int nonstrict)
 {
+    constexpr int accum_mode = AM;
     __shared__ CgLds LD;
     __shared__ S1Lds S1;
     unsigned int *h = LD.h;
@@ -422,7 +429,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const double *__restrict__ x,
         __syncthreads();
         if (it >= n_items) break;
         const BItem I = items[it];
-        if (I.type == IT_CG) {
+        if (CG && I.type == IT_CG) {
             // one block of a CG gang: its other blocks hold the neighbouring
             // tickets, so they are taken by blocks that are running
             cg_solve<GUARD>(sys[I.inst], gangs + I.inst, I.large, I.slot, key_mode, score_mode,
@@ -973,6 +980,46 @@ static int32_t check_systems(qdot_handle *h, const qdot_cg_system *systems, int3
     return QDOT_OK;
 }
 
+// Arguments of one k_batch launch.
+struct BatchArgs {
+    const double *x, *y;
+    const int64_t *offsets;
+    const double *tols;
+    const BatchPlan *p;
+    qdot_result *out;
+    qdot_cg_result *cg_out;
+    int key_mode, score_mode, nonstrict;
+};
+
+template <bool GUARD, bool CG, int AM>
+static hipError_t batch_kernel_t(const BatchArgs &a, int grid, hipStream_t s, int *per_cu)
+{
+    if (per_cu)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch<GUARD, CG, AM>,
+                                                            BLOCK, 0);
+    const BatchPlan *p = a.p;
+    hipLaunchKernelGGL((k_batch<GUARD, CG, AM>), dim3(grid), dim3(BLOCK), 0, s, a.x, a.y,
+                       a.offsets, a.tols, p->items, p->n_items, p->large, p->hist, p->lut,
+                       p->partials, p->state, p->small_list, a.out, p->sys, p->gangs, a.cg_out,
+                       p->ltab, a.key_mode, a.score_mode, a.nonstrict);
+    return hipGetLastError();
+}
+
+// per_cu != nullptr: the occupancy query of the kernel the launch would use
+// (resident blocks per CU), no launch.
+static hipError_t batch_kernel(bool guard, bool cg, int accum, const BatchArgs &a, int grid,
+                               hipStream_t s, int *per_cu)
+{
+    if (guard)
+        return cg ? batch_kernel_t<true, true, 0>(a, grid, s, per_cu)
+                  : batch_kernel_t<true, false, 0>(a, grid, s, per_cu);
+    if (cg)
+        return accum ? batch_kernel_t<false, true, 1>(a, grid, s, per_cu)
+                     : batch_kernel_t<false, true, 0>(a, grid, s, per_cu);
+    return accum ? batch_kernel_t<false, false, 1>(a, grid, s, per_cu)
+                 : batch_kernel_t<false, false, 0>(a, grid, s, per_cu);
+}
+
 // Plans (when needed) and launches the work of one batch: B qdot instances
 // and S CG systems in one persistent launch.
 static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y_cat,
@@ -1007,29 +1054,22 @@ static int32_t batch_launch(qdot_handle *h, const double *x_cat, const double *y
     if ((st = find_plan(h, host_offsets, B, systems, S, accum, &p)) != QDOT_OK) return st;
     const int bpc = h->batch_blocks_per_cu;
     const int grid = std::max(1, std::min(p->n_items, bpc * h->num_cus));
+    // guard_mode 1 implies accum_mode 0 (options_ok)
+    const BatchArgs a = {x_cat, y_cat, offsets, tols, p, dev_out, dev_cg_out,
+                         o.key_mode, o.score_mode, o.boundary_mode};
+    const bool cg = S > 0;
     if (p->max_gang > 0) {
         // a gang waits for its own blocks only, so it needs that many
         // blocks resident at once
         int per_cu = 0;
-        hipError_t e =
-            o.guard_mode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<true>, BLOCK, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<false>, BLOCK, 0);
+        hipError_t e = batch_kernel(o.guard_mode != 0, cg, accum, a, 0, nullptr, &per_cu);
         if (e != hipSuccess) return hip_fail(h, e, "occupancy query");
         if ((int64_t)per_cu * h->num_cus < p->max_gang)
             return fail(h, QDOT_E_DEVICE, "CG gang larger than the resident blocks");
     }
     hipStream_t s = (hipStream_t)stream;
     if (S > 0) hipLaunchKernelGGL(k_gang_rearm, dim3((unsigned)S), dim3(BLOCK), 0, s, p->gangs, S);
-    if (o.guard_mode)
-        hipLaunchKernelGGL(k_batch<true>, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets,
-                           tols, p->items, p->n_items, p->large, p->hist, p->lut, p->partials,
-                           p->state, p->small_list, dev_out, p->sys, p->gangs, dev_cg_out, p->ltab,
-                           o.key_mode, o.score_mode, o.boundary_mode, accum);
-    else
-        hipLaunchKernelGGL(k_batch<false>, dim3(grid), dim3(BLOCK), 0, s, x_cat, y_cat, offsets,
-                           tols, p->items, p->n_items, p->large, p->hist, p->lut, p->partials,
-                           p->state, p->small_list, dev_out, p->sys, p->gangs, dev_cg_out, p->ltab,
-                           o.key_mode, o.score_mode, o.boundary_mode, accum);
+    (void)batch_kernel(o.guard_mode != 0, cg, accum, a, grid, s, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "batched launch");
     if (used) *used = p;
