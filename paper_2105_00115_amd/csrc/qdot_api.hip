@@ -30,7 +30,6 @@ qdot_tune default_tune(int bucket)
 {
     // measured on MI355X (256 CUs) at n = 2^27; small sizes keep both passes
     // on the same block -> chunk mapping so the second pass finds the data
-    // in the same XCD's L2
     // in the same XCD's L2; the one-pass scan wants more resident blocks
     if (bucket < 3) return qdot_tune{2, 1, 2, 1, 4, 1, 0, HIST_COPIES, BLOCK};
     return qdot_tune{2, 1, 2, 2, 4, 1, 0, HIST_COPIES, BLOCK};

@@ -153,6 +153,42 @@ def test_batch_run_mixes_qdot_instances_and_cg_systems(h):
         assert cg[i]["relres_true"] < 1e-9
 
 
+def test_batch_run_mixes_one_pass_instances_and_cg_systems(h):
+    # qdot instances in the one-pass reading next to CG systems (which keep
+    # the default reading): the launch's own kernel variant for that mix
+    offsets, x, y, tols = ragged(13, 40)
+    sys = [poisson_system(m, 70 + m, u) for m in (20, 64, 150) for u in (1, 0)]
+    tup = [as_tuple(s) for s in sys]
+    xd, yd = dev(x), dev(y)
+    off_d = torch.from_numpy(offsets).to("cuda:0")
+    print(f"[gpu-case] batch_run one-pass instances={len(tols)} systems={len(sys)}", flush=True)
+    cgs = []
+    for opt in ([0, 0, 0, 1], None):
+        for s in sys:
+            s["x"].zero_()
+        out = torch.zeros(len(tols) * q.RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+        cg_out = torch.zeros(len(sys) * q.CG_RESULT_BYTES, dtype=torch.uint8, device="cuda:0")
+        h.batch_run_async(xd, yd, off_d, offsets, dev(tols), out, tup, cg_out, opt=opt)
+        torch.cuda.synchronize()
+        cgs.append(q.parse_cg_results(cg_out))
+        if opt is None:
+            continue
+        res = q.parse_results(out)
+        for j in range(len(tols)):
+            a, b = offsets[j], offsets[j + 1]
+            o = oracle.qdot(x[a:b], y[a:b], tols[j], opt=opt)
+            for k in INT_KEYS:
+                assert res[j][k] == o[k], (j, k)
+            if o["status"] == oracle.OK:
+                assert abs(res[j]["value"] - o["value"]) <= 1e-13 * oracle.abs_dot(x[a:b], y[a:b])
+    # the systems' solves do not depend on the instances' reading
+    for a, b in zip(cgs[0], cgs[1]):
+        assert a["status"] == b["status"] == q.OK
+        assert a["iters"] == b["iters"] and a["relres_true"] == b["relres_true"]
+    for i in range(0, len(sys), 2):
+        assert cgs[0][i]["iters"] == cgs[0][i + 1]["iters"]
+
+
 def test_batch_run_graph_replay(h):
     offsets, x, y, tols = ragged(12, 20)
     sys = [poisson_system(m, 60 + m, 1) for m in (24, 90)]
