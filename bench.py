@@ -612,6 +612,7 @@ def main():
                "one_pass_counts_equal": all(a["count"] == c["count"] for a, c in zip(bres, bres1)),
                "gelem_s": round(total / (batch_ms * 1e-3) / 1e9, 3),
                "hbm_frac_2pass": round(32.0 * total / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "hbm_frac_1pass": round(16.0 * total / (batch1_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "statuses_ok": sum(1 for r in bres if r["status"] == 0),
                "guard_ms_per_launch": round(batchg_ms, 4),
                "guard_certified": sum(1 for r in bresg if r["flags"] & q.F_GUARANTEED),
