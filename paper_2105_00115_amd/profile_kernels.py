@@ -14,7 +14,9 @@ Runs, in this order, on cuda:0:
 5. tile skipping: a banded pair of 2^26 components (three quarters of its
    bands 2^-300 below the rest, tol 1e-6), ``steps`` calls without and
    ``steps`` calls with tile_skip (its k_scan / k_acc instantiations carry
-   the template flag ``true``).
+   the template flag ``true``);
+6. the batched launch on 4096 ragged instances (n = round(10^U[2,6]), tol
+   from {1e-4, 1e-6, 1e-8}): one launch two-pass, then one one-pass.
 
 Each phase prints its name and, for the solvers, the iteration counts, so
 that per-dispatch counters can be divided by iterations.
@@ -90,6 +92,23 @@ def main(argv=None):
     for opt in (None, [0, 0, 0, 0, 0, 0, 0, 1]):
         for _ in range(a.steps):
             h.qdot_async(xb, yb, 1e-6, out, opt=opt)
+    torch.cuda.synchronize()
+    del xb, yb
+
+    import numpy as np
+
+    g = workloads.rng(2025)
+    sizes = np.rint(10.0 ** g.uniform(2, 6, 4096)).astype(np.int64)
+    offs = np.zeros(4097, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    tols = np.array([1e-4, 1e-6, 1e-8])[g.integers(0, 3, 4096)]
+    print(f"[profile] batched 4096 ragged instances, {int(offs[-1])} components", flush=True)
+    bx, by = workloads.log_uniform_pair_torch(int(offs[-1]), 2025, dev)
+    off_d = torch.from_numpy(offs).to(dev)
+    tol_d = torch.from_numpy(tols).to(dev)
+    bout = torch.zeros(4096 * q.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    for opt in (None, [0, 0, 0, 1]):
+        h.batched_async(bx, by, off_d, offs, tol_d, bout, opt=opt)
     torch.cuda.synchronize()
     h.close()
     print("[profile] done", flush=True)
