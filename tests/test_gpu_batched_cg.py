@@ -145,6 +145,12 @@ def test_batch_run_mixes_qdot_instances_and_cg_systems(h):
     h.batch_run_async(xd, yd, off_d, offsets, dev(tols), out, [as_tuple(s) for s in sys], cg_out)
     torch.cuda.synchronize()
     check_qdot(q.parse_results(out), offsets, x, y, tols)
+    # the instances alone (the launch's kernel without CG items): the same
+    # result bytes
+    alone = torch.zeros_like(out)
+    h.batched_async(xd, yd, off_d, offsets, dev(tols), alone)
+    torch.cuda.synchronize()
+    assert torch.equal(alone, out)
     cg = q.parse_cg_results(cg_out)
     for i in range(0, len(sys), 2):
         assert cg[i]["status"] == q.OK and cg[i + 1]["status"] == q.OK
