@@ -423,11 +423,13 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
     __shared__ int s_go;
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // counts are read twice (here and when classifying) rather than kept in
-    // registers: the window is short and the reads hit LDS or L2
+    // the counts of a thread's first RC slots stay in registers for the
+    // classification below (a window of up to RC * NT slots is read once);
+    // slots further up are read again there
+    constexpr int RC = 2;
+    unsigned long long vc[RC];
     int emax = INT_MIN, emin = INT_MAX, nb = 0;
-    for (int j = lo + tid; j <= hi; j += NT) {
-        const unsigned long long v = (unsigned long long)get(j);
+    auto survey = [&](int j, unsigned long long v) {
         if (hist_out) hist_out[j] = (long long)v;
         if (v) {
             const int k = j + KMIN;
@@ -435,7 +437,14 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
             emin = min(emin, k);
             nb++;
         }
+    };
+#pragma unroll
+    for (int r = 0; r < RC; r++) {
+        const int j = lo + tid + r * NT;
+        vc[r] = j <= hi ? (unsigned long long)get(j) : 0ull;
+        if (j <= hi) survey(j, vc[r]);
     }
+    for (int j = lo + tid + RC * NT; j <= hi; j += NT) survey(j, (unsigned long long)get(j));
     if (hist_out)
         for (int j = tid; j < W; j += NT)
             if (j < lo || j > hi) hist_out[j] = 0ll;
@@ -508,8 +517,7 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
     unsigned long long cc[4] = {0, 0, 0, 0};
     double bound = 0.0;
     int unatt = 0;
-    for (int j = lo + tid; j <= hi; j += NT) {
-        const unsigned long long v = (unsigned long long)get(j);
+    auto classify = [&](int j, unsigned long long v) {
         int cls = QDOT_PERF;
         if (go && v) {
             const int k = j + KMIN;
@@ -526,7 +534,13 @@ __device__ CutParams block_cutoff(int lo, int hi, unsigned long long nzero, unsi
         }
         put(j, cls);
         clear(j);
+    };
+#pragma unroll
+    for (int r = 0; r < RC; r++) {
+        const int j = lo + tid + r * NT;
+        if (j <= hi) classify(j, vc[r]);
     }
+    for (int j = lo + tid + RC * NT; j <= hi; j += NT) classify(j, (unsigned long long)get(j));
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
 #pragma unroll
